@@ -1,0 +1,208 @@
+/*
+ * hz.h -- C ABI of the MI355X (gfx950) library for neural-operator-preconditioned
+ * flexible GMRES on the 2-D heterogeneous Helmholtz equation with a PML.
+ *
+ * Method (paper: "Neural operator preconditioning from mixed dataset for the
+ * Helmholtz equations", Sections 2-3): A(c) u = b with A = Laplacian + k^2,
+ * k = omega / c (eq. (1), eq. (3)), a quadratic PML damping profile (eq. (2)),
+ * solved by flexible GMRES (Algorithm 1, eq. (4)) whose preconditioner is a
+ * U-Net neural operator z = N(v, c, sigma) (eq. (7), eq. (9)) trained with the
+ * relative-residual loss (eq. (12)); stopping rule eq. (13).
+ *
+ * Conventions shared by every entry point
+ *   - Grid: nx_t = nx + 2 npml nodes along x, ny_t = ny + 2 npml along y,
+ *     n = nx_t * ny_t. Grid vectors are row-major with x fastest: entry
+ *     (j, i) is at index j * nx_t + i.
+ *   - Complex vectors are interleaved (re, im): HZ_C64 = two floats per entry
+ *     (torch.complex64), HZ_C128 = two doubles (torch.complex128).
+ *   - Every pointer named *_dev is device memory on the current HIP device.
+ *     Host pointers are named *_host. The caller allocates and frees every
+ *     input, output and workspace buffer; the library never frees caller
+ *     memory. Handles own their own (immutable after creation) device data.
+ *   - `stream` is a hipStream_t (NULL = the default stream). All calls are
+ *     asynchronous on `stream` except fgmres_solve / fgmres_solve_batched,
+ *     which synchronise `stream` once per restart cycle and return after
+ *     completion, and the *_create calls, which synchronise once.
+ *   - Return value: HZ_OK (0), HZ_NOT_CONVERGED (1, not an error: the info
+ *     record is filled) or a negative error code. Arguments are validated
+ *     before any launch; on error nothing is launched and hz_last_error()
+ *     (thread-local) describes the failure. No C++ exception crosses the ABI.
+ *   - Handles are read-only after creation: concurrent calls on different
+ *     streams with different workspaces are safe.
+ */
+#ifndef HZ_H
+#define HZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HZ_OK               0
+#define HZ_NOT_CONVERGED    1
+#define HZ_ERR_ARG         -1   /* invalid argument (NULL pointer, bad size, unsupported combination) */
+#define HZ_ERR_HIP         -2   /* a HIP runtime call failed */
+#define HZ_ERR_WORKSPACE   -3   /* workspace smaller than the matching *_workspace_size */
+#define HZ_ERR_BREAKDOWN   -4   /* FGMRES: Z_k lost rank (e.g. zero preconditioner output) */
+#define HZ_ERR_NONFINITE   -5   /* NaN or Inf in the input or an iterate */
+
+/* Complex element type of a vector argument. */
+typedef enum { HZ_C64 = 0, HZ_C128 = 1 } hz_dtype;
+
+/* Arithmetic of the neural operator: BF16 operands with FP32 accumulation on
+ * MFMA, FP32 on MFMA, or FP64 on MFMA. */
+typedef enum { NO_BF16 = 0, NO_FP32 = 1, NO_FP64 = 2 } no_prec;
+
+/* ------------------------------------------------------------------ problem */
+
+/* One discrete Helmholtz system (Section 2.1). Node spacing h, angular
+ * frequency omega, PML of npml cells per side whose damping grows as
+ * sigma_max * (depth / npml)^2 (eq. (2)) and stretches the derivatives by
+ * 1 / (1 + i sigma / omega). Velocities are divided by c_ref (m/s) before use,
+ * so k^2 = (omega * c_ref / c)^2. */
+typedef struct {
+    int32_t nx, ny;       /* interior cells along x and y (>= 1) */
+    int32_t npml;         /* PML cells on each side (>= 0) */
+    double h;             /* grid step (> 0) */
+    double omega;         /* angular frequency (> 0); the paper uses 1 */
+    double sigma_max;     /* damping at the outermost node (>= 0) */
+    double c_ref;         /* reference speed in m/s (> 0) */
+} hz_grid;
+
+typedef struct hz_problem hz_problem;
+
+/* Build the operator data of one system from the velocity field
+ * c_dev (float32, [ny_t][nx_t], m/s, every entry > 0): k^2 in FP32 and FP64, the
+ * per-axis PML coefficients at nodes and half-nodes, and the network's static
+ * channels. Runs the setup kernels on `stream` and synchronises it.
+ * Errors: HZ_ERR_ARG for a bad grid or NULL pointer, HZ_ERR_NONFINITE if some
+ * c is not finite or not positive, HZ_ERR_HIP on allocation failure. */
+int hz_problem_create(const hz_grid* grid, const float* c_dev, void* stream, hz_problem** out);
+int hz_problem_destroy(hz_problem* p);
+/* Number of grid nodes n = nx_t * ny_t and the totals nx_t, ny_t (any may be NULL). */
+int hz_problem_dims(const hz_problem* p, int64_t* n, int32_t* nx_t, int32_t* ny_t);
+
+/* y = A x (adjoint = 0) or y = A^H x (adjoint = 1), eq. (3): the five-point
+ * stretched Laplacian plus k^2 with zero values outside the grid.
+ * x_dev, y_dev: n complex entries of type `dtype` (must not overlap). */
+int hz_op_apply(const hz_problem* p, hz_dtype dtype, int adjoint,
+                const void* x_dev, void* y_dev, void* stream);
+
+/* --------------------------------------------------------- neural operator */
+
+/* U-Net of Section 3.1 with `levels` resolution levels (levels - 1 average
+ * poolings), base channels doubling per level, 3x3 convolutions with ReLU,
+ * 2x2 stride-2 transposed convolutions on the way up, skip connections by
+ * concatenation and a 1x1 head with 2 outputs (Re, Im). in_ch = 2 takes the
+ * (scaled) Re/Im of the field; in_ch = 5 adds c / c_ref, sigma_x, sigma_y. */
+typedef struct {
+    int32_t levels;   /* 1..6 */
+    int32_t base;     /* base channels, a multiple of 8 */
+    int32_t in_ch;    /* 2 or 5 */
+} no_arch;
+
+typedef struct no_net no_net;
+
+/* Number of float32 parameters of the flat parameter vector: per layer, in the
+ * order enc0a, enc0b, enc1a, ..., then up(L-2), dec(L-2)a, dec(L-2)b, ..., up0,
+ * dec0a, dec0b, head, the weight ([out][in][3][3] for 3x3 convolutions,
+ * [in][out][2][2] for transposed convolutions, [out][in][1][1] for the head)
+ * followed by its bias. */
+int64_t no_param_count(const no_arch* arch);
+
+/* Create a network and load theta_dev (float32, no_param_count entries); the
+ * library keeps its own repacked BF16, FP32 and FP64 copies. Synchronises. */
+int no_net_create(const no_arch* arch, const float* theta_dev, void* stream, no_net** out);
+/* Replace the parameters (asynchronous on `stream`). */
+int no_net_set_weights(no_net* net, const float* theta_dev, void* stream);
+int no_net_destroy(no_net* net);
+
+/* Workspace bytes for no_precond_apply on this problem at this precision. */
+size_t no_workspace_size(const no_net* net, const hz_problem* p, no_prec prec);
+
+/* z = N(v, c, sigma), eq. (7): s = ||v|| / sqrt(n); the network runs on the
+ * zero-padded channels [Re v / s, Im v / s (, c / c_ref, sigma_x, sigma_y)] and
+ * z = s (out_0 + i out_1) on the grid (z = 0 when v = 0).
+ * v_dev, z_dev: n complex entries of type `dtype`. ws_dev: ws_bytes bytes. */
+int no_precond_apply(const no_net* net, const hz_problem* p, no_prec prec, hz_dtype dtype,
+                     const void* v_dev, void* z_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for no_loss_backward with `batch` samples on problems of one size. */
+size_t no_train_workspace_size(const no_net* net, const hz_problem* p, int batch, no_prec prec);
+
+/* Physics-informed loss and its gradient (eq. (10)-(12)) for a batch of residuals:
+ * per sample q_b = A_b N(r_b) - r_b and l_b = ||q_b|| / ||r_b|| (squared != 0:
+ * ||q_b||^2 / ||r_b||^2); loss = mean_b l_b. Reverse mode through A^H and the
+ * U-Net. problems: `batch` handles of one grid size; r_dev: [batch][n] complex64;
+ * loss_dev: 1 float (written); per_sample_dev: `batch` floats or NULL;
+ * grad_dev: no_param_count floats (overwritten with d loss / d theta).
+ * prec: NO_BF16 (BF16 operands, FP32 accumulation) or NO_FP32. */
+int no_loss_backward(const no_net* net, int batch, const hz_problem* const* problems,
+                     const void* r_dev, int squared, no_prec prec,
+                     float* loss_dev, float* per_sample_dev, float* grad_dev,
+                     void* ws_dev, size_t ws_bytes, void* stream);
+
+/* One Adam step on the float32 master parameters (Section 3.4), with the gradient
+ * clipped to global L2 norm `clip` when clip > 0; refreshes the network's
+ * working copies. theta/m/v/grad: no_param_count floats on the device; step >= 1. */
+int no_adam_step(no_net* net, float* theta_dev, float* m_dev, float* v_dev, const float* grad_dev,
+                 int step, float lr, float beta1, float beta2, float eps, float clip,
+                 void* ws_dev, size_t ws_bytes, void* stream);
+size_t no_adam_workspace_size(const no_net* net);
+
+/* ------------------------------------------------------------------- solver */
+
+typedef struct {
+    int32_t m;            /* cycle length (restart), >= 1 */
+    int32_t maxit;        /* cap on preconditioner applications, >= 1 */
+    double tol;           /* relative residual target (eq. (13)), > 0 */
+    hz_dtype krylov;      /* HZ_C64: FP32 Krylov basis; HZ_C128: FP64 */
+    no_prec net_prec;     /* arithmetic of the network (ignored when net is NULL) */
+    double* hist_host;    /* optional: |g_{j+1}| / ||b|| after every iteration */
+    int32_t hist_len;     /* entries available in hist_host */
+} hz_opts;
+
+typedef struct {
+    int32_t status;       /* HZ_OK, HZ_NOT_CONVERGED, HZ_ERR_BREAKDOWN or HZ_ERR_NONFINITE */
+    int32_t its;          /* preconditioner applications (Arnoldi steps) */
+    int32_t cycles;       /* restart cycles started */
+    double est_relres;    /* last Givens estimate |g_{j+1}| / ||b|| */
+    double true_relres;   /* FP64 ||b - A x|| / ||b|| of the returned x */
+} hz_info;
+
+/* Workspace bytes for fgmres_solve. */
+size_t fgmres_workspace_size(const hz_problem* p, const no_net* net, const hz_opts* opts);
+
+/* Solve A x = b by restarted flexible GMRES(m), Algorithm 1, right-preconditioned
+ * by the network (net == NULL: identity, i.e. plain GMRES). Each cycle starts
+ * from the FP64 true residual r = b - A x, builds V and Z with Gram-Schmidt
+ * orthogonalisation (CGS with one reorthogonalisation), keeps the Hessenberg
+ * least-squares problem in FP64 with complex Givens rotations, ends early when
+ * |g_{j+1}| / ||b|| <= tol, and adds Z y to x in FP64. Converged means the FP64
+ * true residual <= tol. b_dev: n complex128 (read); x_dev: n complex128, read as
+ * x0 and overwritten with the solution. info_host: filled on return.
+ * Returns HZ_OK, HZ_NOT_CONVERGED or an error (the info record says which). */
+int fgmres_solve(const hz_problem* p, const no_net* net, const hz_opts* opts,
+                 const void* b_dev, void* x_dev, void* ws_dev, size_t ws_bytes,
+                 hz_info* info_host, void* stream);
+
+/* Batched solve of nsys independent systems of (possibly) different grid sizes
+ * that share one network and one set of options: the systems advance together,
+ * one network launch and one set of Krylov launches per step covering every
+ * active system; systems leave the batch as they converge. b_dev[s], x_dev[s]:
+ * complex128 vectors of system s. info_host: nsys records. */
+size_t fgmres_batched_workspace_size(int nsys, const hz_problem* const* problems,
+                                     const no_net* net, const hz_opts* opts);
+int fgmres_solve_batched(int nsys, const hz_problem* const* problems, const no_net* net,
+                         const hz_opts* opts, const void* const* b_dev, void* const* x_dev,
+                         void* ws_dev, size_t ws_bytes, hz_info* info_host, void* stream);
+
+/* Description of the last error on this thread ("" if none). */
+const char* hz_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HZ_H */

@@ -1,0 +1,171 @@
+// Host driver of restarted flexible GMRES (Algorithm 1 with the bookkeeping of Section 4).
+//
+// Everything numerical runs in device kernels; the host only enqueues them. Each
+// restart cycle enqueues its m Arnoldi steps without waiting: every kernel of a
+// step first reads the device flag `stop` (set when the Givens estimate reaches
+// tol, on breakdown or on a non-finite value) and returns at once when it is set,
+// so steps past the end of a cycle cost one empty launch each. The cycle ends
+// with the least-squares update of x and the FP64 true residual that starts the
+// next cycle; the host then reads the device state once (the only
+// synchronisation per cycle).
+#include <algorithm>
+#include <cstring>
+
+#include "krylov.h"
+#include "net.h"
+#include "problem.h"
+
+namespace hz {
+
+struct FgmresLayout {
+    KrylovBufs kb;
+    void* V;          // (m+1) x n Krylov vectors
+    void* Z;          // m x n preconditioned vectors (NULL: Z = V)
+    double2* r64;     // n, FP64 residual
+    double* rpart;    // stencil block partials
+    void* net_ws;
+    size_t net_ws_bytes;
+    size_t total;
+};
+
+static FgmresLayout fgmres_layout(const hz_problem* p, const no_net* net, const hz_opts* o, void* base,
+                                  size_t cap) {
+    FgmresLayout L{};
+    const int64_t n = p->n;
+    const int m = o->m;
+    const bool c128 = o->krylov == HZ_C128;
+    const size_t es = c128 ? sizeof(double2) : sizeof(float2);
+    Split sp = krylov_split(n);
+    Carver c(base, cap);
+    L.kb.st = c.take<SolveState>(1);
+    L.kb.R = c.take<double2>((size_t)(m + 1) * m);
+    L.kb.cs = c.take<double>(m);
+    L.kb.sn = c.take<double2>(m);
+    L.kb.g = c.take<double2>(m + 1);
+    L.kb.y = c.take<double2>(m);
+    L.kb.h1 = c.take<double2>(m + 2);
+    L.kb.h2 = c.take<double2>(m + 2);
+    L.kb.ldp = m + 2;
+    L.kb.part = c.take<double2>((size_t)sp.nblk * L.kb.ldp);
+    L.kb.hist_cap = std::max(o->maxit, 1);
+    L.kb.hist = c.take<double>(L.kb.hist_cap);
+    L.rpart = c.take<double>(stencil_blocks(p));
+    L.r64 = c.take<double2>(n);
+    L.V = c.take<char>(es * n * (m + 1));
+    L.Z = net ? c.take<char>(es * n * m) : nullptr;
+    if (net) {
+        int Hp, Wp;
+        net_padded_dims(net, p, &Hp, &Wp);
+        L.net_ws_bytes = net_fwd_ws_bytes(net, Hp, Wp, 1, o->net_prec);
+        L.net_ws = c.take<char>(L.net_ws_bytes);
+    }
+    L.total = c.off + 256;
+    return L;
+}
+
+static int check_opts(const hz_opts* o, const no_net* net) {
+    HZ_CHECK_ARG(o, "fgmres: NULL options");
+    HZ_CHECK_ARG(o->m >= 1 && o->m <= 4096, "fgmres: m must be in [1, 4096]");
+    HZ_CHECK_ARG(o->maxit >= 1, "fgmres: maxit must be >= 1");
+    HZ_CHECK_ARG(o->tol > 0, "fgmres: tol must be > 0");
+    HZ_CHECK_ARG(o->krylov == HZ_C64 || o->krylov == HZ_C128, "fgmres: krylov must be HZ_C64 or HZ_C128");
+    HZ_CHECK_ARG(!net || o->net_prec == NO_BF16 || o->net_prec == NO_FP32 || o->net_prec == NO_FP64,
+                 "fgmres: bad net_prec");
+    HZ_CHECK_ARG(!o->hist_host || o->hist_len >= 0, "fgmres: bad hist_len");
+    return HZ_OK;
+}
+
+}  // namespace hz
+
+using namespace hz;
+
+extern "C" size_t fgmres_workspace_size(const hz_problem* p, const no_net* net, const hz_opts* o) {
+    clear_error();
+    if (!p || check_opts(o, net) != HZ_OK) return 0;
+    return fgmres_layout(p, net, o, nullptr, 0).total;
+}
+
+extern "C" int fgmres_solve(const hz_problem* p, const no_net* net, const hz_opts* o, const void* b_dev,
+                            void* x_dev, void* ws, size_t ws_bytes, hz_info* info, void* stream) {
+    clear_error();
+    HZ_CHECK_ARG(p && b_dev && x_dev && ws && info, "fgmres_solve: NULL argument");
+    HZ_TRY(check_opts(o, net));
+    FgmresLayout L = fgmres_layout(p, net, o, ws, ws_bytes);
+    if (L.total > ws_bytes) {
+        set_error("fgmres_solve: workspace too small");
+        return HZ_ERR_WORKSPACE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = p->n;
+    const int m = o->m;
+    const bool c128 = o->krylov == HZ_C128;
+    const size_t es = c128 ? sizeof(double2) : sizeof(float2);
+    const double2* b = (const double2*)b_dev;
+    double2* x = (double2*)x_dev;
+    KrylovBufs& kb = L.kb;
+    const int* stop = &kb.st->stop;
+    Split sp = krylov_split(n);
+    const int nres = stencil_blocks(p);
+    auto vcol = [&](int i) { return (void*)((char*)L.V + es * n * i); };
+    auto zcol = [&](int i) { return L.Z ? (void*)((char*)L.Z + es * n * i) : vcol(i); };
+
+    // ||b||, then the first true residual and v_1
+    HZ_TRY(launch_norm_partials(true, b, n, sp, kb.part, kb.ldp, 0, nullptr, s));
+    HZ_TRY(launch_init_state(kb, sp.nblk, o->tol, m, s));
+    HZ_TRY(launch_resid64(p, b, x, L.r64, L.rpart, nullptr, s));
+    HZ_TRY(launch_cycle_start(kb, L.rpart, nres, s));
+    HZ_TRY(launch_cast_scale(c128, L.r64, vcol(0), n, kb.st, s));
+
+    SolveState hs{};
+    HZ_HIP(hipMemcpyAsync(&hs, kb.st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+    HZ_HIP(hipStreamSynchronize(s));
+    if (hs.bnorm == 0.0 && !(hs.flags & FL_NONFINITE)) HZ_HIP(hipMemsetAsync(x, 0, sizeof(double2) * n, s));
+    while (!(hs.flags & (FL_CONVERGED | FL_NONFINITE | FL_BREAKDOWN)) && hs.its < o->maxit) {
+        const int steps = std::min(m, o->maxit - hs.its);
+        for (int j = 0; j < steps; ++j) {
+            if (net) {
+                HZ_TRY(net_precond(net, p, o->net_prec, c128, vcol(j), zcol(j), L.net_ws, L.net_ws_bytes, stop, s));
+            }
+            // w = A z_j, written into the slot of v_{j+1}
+            void* w = vcol(j + 1);
+            HZ_TRY(launch_stencil(p, c128, false, zcol(j), w, s, stop));
+            HZ_TRY(launch_dots(c128, L.V, n, j + 1, w, n, sp, kb.part, kb.ldp, true, stop, s));
+            HZ_TRY(launch_finalize(kb.part, sp.nblk, kb.ldp, j + 2, kb.h1, stop, s));
+            HZ_TRY(launch_update(c128, L.V, n, j + 1, kb.h1, w, n, sp, kb.part, kb.ldp, 1, stop, s));
+            HZ_TRY(launch_finalize(kb.part, sp.nblk, kb.ldp, j + 1, kb.h2, stop, s));
+            HZ_TRY(launch_update(c128, L.V, n, j + 1, kb.h2, w, n, sp, kb.part, kb.ldp, 2, stop, s));
+            HZ_TRY(launch_arnoldi_finish(kb, j, sp.nblk, true, s));
+            HZ_TRY(launch_scale(c128, w, n, &kb.st->inv_h, stop, s));
+        }
+        HZ_TRY(launch_backsolve(kb, s));
+        HZ_TRY(launch_xupdate(c128, zcol(0), n, x, n, kb, s));
+        HZ_TRY(launch_resid64(p, b, x, L.r64, L.rpart, nullptr, s));
+        HZ_TRY(launch_cycle_start(kb, L.rpart, nres, s));
+        HZ_TRY(launch_cast_scale(c128, L.r64, vcol(0), n, kb.st, s));
+        HZ_HIP(hipMemcpyAsync(&hs, kb.st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
+        HZ_HIP(hipStreamSynchronize(s));
+    }
+    if (o->hist_host && o->hist_len > 0) {
+        const int cnt = std::min(std::min(hs.its, o->hist_len), kb.hist_cap);
+        if (cnt > 0) {
+            HZ_HIP(hipMemcpyAsync(o->hist_host, kb.hist, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
+            HZ_HIP(hipStreamSynchronize(s));
+        }
+    }
+    info->its = hs.its;
+    info->cycles = hs.cycles;
+    info->est_relres = hs.est;
+    info->true_relres = hs.true_rel;
+    if (hs.flags & FL_NONFINITE) {
+        info->status = HZ_ERR_NONFINITE;
+        set_error("fgmres_solve: non-finite value in the input or an iterate");
+    } else if (hs.flags & FL_CONVERGED) {
+        info->status = HZ_OK;
+    } else if (hs.flags & FL_BREAKDOWN) {
+        info->status = HZ_ERR_BREAKDOWN;
+        set_error("fgmres_solve: breakdown (preconditioned vectors lost rank)");
+    } else {
+        info->status = HZ_NOT_CONVERGED;
+    }
+    return info->status;
+}

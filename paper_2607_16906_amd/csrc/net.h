@@ -1,0 +1,50 @@
+// Internal view of the neural-operator handle and its forward/backward entry points.
+#pragma once
+
+#include <vector>
+
+#include "common.h"
+#include "problem.h"
+
+namespace hz {
+
+enum LayerKind { L_CONV3 = 0, L_CONVT2 = 1, L_CONV1 = 2 };
+
+struct Layer {
+    int kind;
+    int cin, cout;          // logical channels
+    int cin_p, cout_p;      // channels as stored (padded to a multiple of 8 / 16)
+    int cat_c, cat_cp;      // concatenated input: logical / stored channels of the first part (0: none)
+    int64_t w_off, b_off;   // offsets in the flat FP32 parameter vector
+    int64_t pk_off;         // offset of the repacked weights (elements) in the packed buffers
+    int64_t pk_len;         // repacked weight elements
+    int64_t bias_off;       // offset of the bias in the packed bias buffers
+};
+
+}  // namespace hz
+
+struct no_net {
+    no_arch a;
+    int64_t nparam;
+    std::vector<hz::Layer> layers;   // order of the flat parameter vector
+    int64_t pk_total;                // repacked weight elements
+    int64_t bias_total;              // packed bias elements
+    hz::bf16_t* w_bf;                // repacked weights, BF16
+    float* w_f32;                    // repacked weights, FP32
+    double* w_f64;                   // repacked weights, FP64
+    float* b_f32;                    // biases (FP32; the BF16 path adds them in FP32)
+    double* b_f64;
+    void* block;
+};
+
+namespace hz {
+
+int net_level_count(const no_net* net);
+// Padded grid of the network for a problem (multiple of 2^(levels-1)).
+void net_padded_dims(const no_net* net, const hz_problem* p, int* Hp, int* Wp);
+size_t net_fwd_ws_bytes(const no_net* net, int Hp, int Wp, int batch, no_prec prec);
+// z = N(v) for one field (c128: complex128 vectors, else complex64). skip: optional device flag.
+int net_precond(const no_net* net, const hz_problem* p, no_prec prec, bool c128, const void* v, void* z,
+                void* ws, size_t ws_bytes, const int* skip, hipStream_t s);
+
+}  // namespace hz

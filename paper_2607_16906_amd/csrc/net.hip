@@ -1,0 +1,411 @@
+// U-Net neural operator (Section 3.1, eq. (7), eq. (9)): handle, parameter
+// repacking and the forward pass used as the flexible preconditioner.
+//
+// Architecture (the 3x3 / ReLU / doubling-channel reading of the paper's
+// encoder-decoder): level l = 0..L-1 of the encoder applies two 3x3
+// convolutions with ReLU (C 2^l channels), followed by a 2x2 average pool
+// except at the last level; the decoder, from level L-2 down to 0, upsamples
+// with a 2x2 stride-2 transposed convolution, concatenates the encoder output
+// of the same level (encoder channels first) and applies two 3x3 convolutions
+// with ReLU; a 1x1 head yields (Re, Im). The input field v is scaled by
+// s = ||v|| / sqrt(n) before the network and the output is multiplied by s.
+#include <cmath>
+#include <vector>
+
+#include "krylov.h"
+#include "net.h"
+#include "net_kernels.h"
+
+namespace hz {
+
+static int round16(int c) { return (c + 15) / 16 * 16; }
+
+static bool build_layers(const no_arch* a, std::vector<Layer>& L, int64_t& nparam, int64_t& pk, int64_t& nb) {
+    if (!a || a->levels < 1 || a->levels > 6 || a->base < 8 || a->base % 8 || (a->in_ch != 2 && a->in_ch != 5))
+        return false;
+    L.clear();
+    nparam = pk = nb = 0;
+    auto add = [&](int kind, int cin, int cout, int cin_p, int cout_p, int cat_c = 0, int cat_cp = 0) {
+        Layer y;
+        y.kind = kind;
+        y.cat_c = cat_c;
+        y.cat_cp = cat_cp;
+        y.cin = cin;
+        y.cout = cout;
+        y.cin_p = cin_p;
+        y.cout_p = cout_p;
+        const int taps = kind == L_CONV3 ? 9 : (kind == L_CONVT2 ? 4 : 1);
+        y.w_off = nparam;
+        nparam += (int64_t)taps * cin * cout;
+        y.b_off = nparam;
+        nparam += cout;
+        y.pk_off = pk;
+        y.pk_len = (int64_t)taps * cout_p * cin_p;
+        pk += (y.pk_len + 63) / 64 * 64;
+        y.bias_off = nb;
+        nb += (cout_p + 63) / 64 * 64;
+        L.push_back(y);
+    };
+    const int lv = a->levels;
+    int cin = a->in_ch, cin_p = 8;
+    for (int l = 0; l < lv; ++l) {
+        const int c = a->base << l, cp = round16(c);
+        add(L_CONV3, cin, c, cin_p, cp);
+        add(L_CONV3, c, c, cp, cp);
+        cin = c;
+        cin_p = cp;
+    }
+    for (int l = lv - 2; l >= 0; --l) {
+        const int c = a->base << l, cp = round16(c);
+        const int cu = a->base << (l + 1), cup = round16(cu);
+        add(L_CONVT2, cu, c, cup, cp);
+        add(L_CONV3, 2 * c, c, 2 * cp, cp, c, cp);
+        add(L_CONV3, c, c, cp, cp);
+    }
+    add(L_CONV1, a->base, 2, round16(a->base), 16);
+    return true;
+}
+
+// Repack one layer from the flat FP32 vector into [tap][cout_p][cin_p] (channels
+// padded with zeros) in BF16, FP32 and FP64, and its bias into FP32 and FP64.
+__global__ void k_repack(const float* __restrict__ theta, Layer ly, bf16_t* __restrict__ wb,
+                         float* __restrict__ wf, double* __restrict__ wd, float* __restrict__ bf,
+                         double* __restrict__ bd) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx < ly.pk_len) {
+        const int cis = (int)(idx % ly.cin_p);      // stored input channel
+        const int64_t r = idx / ly.cin_p;
+        const int co = (int)(r % ly.cout_p);
+        const int tap = (int)(r / ly.cout_p);
+        // logical input channel; a concatenated input keeps each part's padding
+        int ci = cis;
+        bool live = cis < ly.cin;
+        if (ly.cat_cp > 0) {
+            if (cis < ly.cat_cp) {
+                live = cis < ly.cat_c;
+            } else {
+                ci = ly.cat_c + (cis - ly.cat_cp);
+                live = ci < ly.cin;
+            }
+        }
+        float v = 0.0f;
+        if (live && co < ly.cout) {
+            if (ly.kind == L_CONV3)        // [cout][cin][3][3]
+                v = theta[ly.w_off + ((int64_t)co * ly.cin + ci) * 9 + tap];
+            else if (ly.kind == L_CONVT2)  // [cin][cout][2][2]
+                v = theta[ly.w_off + ((int64_t)ci * ly.cout + co) * 4 + tap];
+            else                           // [cout][cin][1][1]
+                v = theta[ly.w_off + (int64_t)co * ly.cin + ci];
+        }
+        wb[ly.pk_off + idx] = f2bf(v);
+        wf[ly.pk_off + idx] = v;
+        wd[ly.pk_off + idx] = (double)v;
+    }
+    if (idx < ly.cout_p) {
+        const float b = idx < ly.cout ? theta[ly.b_off + idx] : 0.0f;
+        bf[ly.bias_off + idx] = b;
+        bd[ly.bias_off + idx] = (double)b;
+    }
+}
+
+static int repack_all(no_net* net, const float* theta, hipStream_t s) {
+    for (const Layer& ly : net->layers) {
+        const int64_t n = ly.pk_len > ly.cout_p ? ly.pk_len : ly.cout_p;
+        hipLaunchKernelGGL(k_repack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, theta, ly, net->w_bf,
+                           net->w_f32, net->w_f64, net->b_f32, net->b_f64);
+        HZ_LAUNCH_CHECK();
+    }
+    return HZ_OK;
+}
+
+int net_level_count(const no_net* net) { return net->a.levels; }
+
+void net_padded_dims(const no_net* net, const hz_problem* p, int* Hp, int* Wp) {
+    const int m = 1 << (net->a.levels - 1);
+    *Hp = (p->nyt + m - 1) / m * m;
+    *Wp = (p->nxt + m - 1) / m * m;
+}
+
+// ------------------------------------------------------------------ pack / head
+
+// s = ||v|| / sqrt(n) from norm partials; sc[0] = s, sc[1] = 1 / s (0 when s = 0).
+__global__ void k_scale_factor(const double2* part, int nblk, int64_t n, double* sc, const int* skip) {
+    if (skip && *skip) return;
+    double a = 0;
+    for (int q = threadIdx.x; q < nblk; q += 64) a += part[q].x;
+    a = wave_sum(a);
+    if (threadIdx.x == 0) {
+        const double s = sqrt(a / (double)n);
+        sc[0] = s;
+        sc[1] = s > 0 ? 1.0 / s : 0.0;
+    }
+}
+
+// X[y][x][0..7] = [Re v / s, Im v / s, (c / c_ref, sigma_x, sigma_y), 0...] on the grid, 0 in the padding.
+template <class P, typename C>
+__global__ void k_pack(const C* __restrict__ v, const double* __restrict__ sc, const double* __restrict__ cnd,
+                       const double* __restrict__ sigx, const double* __restrict__ sigy, int nxt, int nyt, int Hp,
+                       int Wp, int in_ch, typename P::T* __restrict__ X, const int* __restrict__ skip) {
+    using T = typename P::T;
+    if (skip && *skip) return;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)Hp * Wp) return;
+    const int yy = (int)(idx / Wp), xx = (int)(idx % Wp);
+    T out[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) out[c] = P::cvt(0);
+    if (yy < nyt && xx < nxt) {
+        const int64_t g = (int64_t)yy * nxt + xx;
+        const double is = sc[1];
+        const C a = v[g];
+        out[0] = P::cvt((typename P::Acc)((double)a.x * is));
+        out[1] = P::cvt((typename P::Acc)((double)a.y * is));
+        if (in_ch == 5) {
+            out[2] = P::cvt((typename P::Acc)cnd[g]);
+            out[3] = P::cvt((typename P::Acc)sigx[xx]);
+            out[4] = P::cvt((typename P::Acc)sigy[yy]);
+        }
+    }
+    T* dst = X + idx * 8;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) dst[c] = out[c];
+}
+
+// z = s (out_0 + i out_1), out_k = sum_c D0[c] Wh[k][c] + bh[k], on the grid only.
+template <class P, typename C>
+__global__ void k_head(const typename P::T* __restrict__ D, int cin_p, const typename P::T* __restrict__ wh,
+                       const typename P::Acc* __restrict__ bh, const double* __restrict__ sc, int nxt, int nyt,
+                       int Wp, C* __restrict__ z, const int* __restrict__ skip) {
+    using Acc = typename P::Acc;
+    if (skip && *skip) return;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)nxt * nyt) return;
+    const int yy = (int)(idx / nxt), xx = (int)(idx % nxt);
+    const typename P::T* d = D + ((int64_t)yy * Wp + xx) * cin_p;
+    Acc o0 = bh[0], o1 = bh[1];
+    for (int c = 0; c < cin_p; ++c) {
+        const Acc dv = P::val(d[c]);
+        o0 += dv * P::val(wh[c]);
+        o1 += dv * P::val(wh[cin_p + c]);
+    }
+    const double s = sc[0];
+    z[idx] = from_d2<C>(double2{s * (double)o0, s * (double)o1});
+}
+
+// ------------------------------------------------------------------ forward
+
+struct FwdBufs {
+    void* X;
+    std::vector<void*> E, T1, P, U, D;
+    double2* part;
+    double* sc;
+    size_t total;
+};
+
+template <class P>
+static FwdBufs fwd_layout(const no_net* net, int Hp, int Wp, int batch, void* base, size_t cap) {
+    using T = typename P::T;
+    FwdBufs b;
+    Carver c(base, cap);
+    const int lv = net->a.levels;
+    b.X = c.take<T>((size_t)batch * Hp * Wp * 8);
+    b.E.resize(lv);
+    b.T1.resize(lv);
+    b.P.resize(lv);
+    b.U.resize(lv);
+    b.D.resize(lv);
+    for (int l = 0; l < lv; ++l) {
+        const size_t px = (size_t)batch * (Hp >> l) * (Wp >> l);
+        const int cs = round16(net->a.base << l);
+        b.E[l] = c.take<T>(px * cs);
+        b.T1[l] = c.take<T>(px * cs);
+        b.P[l] = l > 0 ? c.take<T>(px * round16(net->a.base << (l - 1))) : nullptr;
+        b.U[l] = l < lv - 1 ? c.take<T>(px * cs) : nullptr;
+        b.D[l] = l < lv - 1 ? c.take<T>(px * cs) : nullptr;
+    }
+    b.part = c.take<double2>(1024);
+    b.sc = c.take<double>(2);
+    b.total = c.off + 256;
+    return b;
+}
+
+template <class P>
+static const typename P::T* packed_w(const no_net* net, const Layer& ly) {
+    if constexpr (sizeof(typename P::T) == 2) return net->w_bf + ly.pk_off;
+    else if constexpr (sizeof(typename P::T) == 4) return net->w_f32 + ly.pk_off;
+    else return net->w_f64 + ly.pk_off;
+}
+template <class P>
+static const typename P::Acc* packed_b(const no_net* net, const Layer& ly) {
+    if constexpr (sizeof(typename P::Acc) == 4) return net->b_f32 + ly.bias_off;
+    else return net->b_f64 + ly.bias_off;
+}
+
+// Network body on a packed input X (batch samples), result D0 = decoder level-0 output.
+template <class P>
+static int unet_body(const no_net* net, const FwdBufs& b, int Hp, int Wp, int batch, const int* skip, hipStream_t s) {
+    using T = typename P::T;
+    const int lv = net->a.levels;
+    const std::vector<Layer>& Ls = net->layers;
+    int li = 0;
+    for (int l = 0; l < lv; ++l) {
+        const int H = Hp >> l, W = Wp >> l;
+        const Layer& la = Ls[li++];
+        const Layer& lb = Ls[li++];
+        const T* in = l == 0 ? (const T*)b.X : (const T*)b.P[l];
+        HZ_TRY(launch_conv3<P>(in, la.cin_p, nullptr, 0, packed_w<P>(net, la), packed_b<P>(net, la), (T*)b.T1[l],
+                               la.cout_p, nullptr, H, W, batch, true, skip, s));
+        T* pool = l + 1 < lv ? (T*)b.P[l + 1] : nullptr;
+        HZ_TRY(launch_conv3<P>((const T*)b.T1[l], lb.cin_p, nullptr, 0, packed_w<P>(net, lb), packed_b<P>(net, lb),
+                               (T*)b.E[l], lb.cout_p, pool, H, W, batch, true, skip, s));
+    }
+    const T* Dn = (const T*)b.E[lv - 1];
+    for (int l = lv - 2; l >= 0; --l) {
+        const int H = Hp >> l, W = Wp >> l;
+        const Layer& lu = Ls[li++];
+        const Layer& la = Ls[li++];
+        const Layer& lb = Ls[li++];
+        HZ_TRY(launch_convT2<P>(Dn, lu.cin_p, packed_w<P>(net, lu), packed_b<P>(net, lu), (T*)b.U[l], lu.cout_p,
+                                H / 2, W / 2, batch, skip, s));
+        const int ce = lu.cout_p;
+        HZ_TRY(launch_conv3<P>((const T*)b.E[l], ce, (const T*)b.U[l], ce, packed_w<P>(net, la), packed_b<P>(net, la),
+                               (T*)b.T1[l], la.cout_p, nullptr, H, W, batch, true, skip, s));
+        HZ_TRY(launch_conv3<P>((const T*)b.T1[l], lb.cin_p, nullptr, 0, packed_w<P>(net, lb), packed_b<P>(net, lb),
+                               (T*)b.D[l], lb.cout_p, nullptr, H, W, batch, true, skip, s));
+        Dn = (const T*)b.D[l];
+    }
+    return HZ_OK;
+}
+
+template <class P>
+static int precond_impl(const no_net* net, const hz_problem* p, bool c128, const void* v, void* z, void* ws,
+                        size_t ws_bytes, const int* skip, hipStream_t s) {
+    using T = typename P::T;
+    int Hp, Wp;
+    net_padded_dims(net, p, &Hp, &Wp);
+    FwdBufs b = fwd_layout<P>(net, Hp, Wp, 1, ws, ws_bytes);
+    if (b.total > ws_bytes) {
+        set_error("no_precond_apply: workspace too small");
+        return HZ_ERR_WORKSPACE;
+    }
+    const int64_t n = p->n;
+    Split sp = krylov_split(n);
+    HZ_TRY(launch_norm_partials(c128, v, n, sp, b.part, 1, 0, skip, s));
+    hipLaunchKernelGGL(k_scale_factor, dim3(1), dim3(64), 0, s, b.part, sp.nblk, n, b.sc, skip);
+    HZ_LAUNCH_CHECK();
+    const unsigned gp = (unsigned)(((int64_t)Hp * Wp + 255) / 256);
+    if (c128)
+        hipLaunchKernelGGL((k_pack<P, double2>), dim3(gp), dim3(256), 0, s, (const double2*)v, b.sc, p->cnd, p->sigx,
+                           p->sigy, p->nxt, p->nyt, Hp, Wp, net->a.in_ch, (T*)b.X, skip);
+    else
+        hipLaunchKernelGGL((k_pack<P, float2>), dim3(gp), dim3(256), 0, s, (const float2*)v, b.sc, p->cnd, p->sigx,
+                           p->sigy, p->nxt, p->nyt, Hp, Wp, net->a.in_ch, (T*)b.X, skip);
+    HZ_LAUNCH_CHECK();
+    HZ_TRY(unet_body<P>(net, b, Hp, Wp, 1, skip, s));
+    const Layer& lh = net->layers.back();
+    const T* D0 = net->a.levels > 1 ? (const T*)b.D[0] : (const T*)b.E[0];
+    const unsigned gh = (unsigned)((n + 255) / 256);
+    if (c128)
+        hipLaunchKernelGGL((k_head<P, double2>), dim3(gh), dim3(256), 0, s, D0, lh.cin_p, packed_w<P>(net, lh),
+                           packed_b<P>(net, lh), b.sc, p->nxt, p->nyt, Wp, (double2*)z, skip);
+    else
+        hipLaunchKernelGGL((k_head<P, float2>), dim3(gh), dim3(256), 0, s, D0, lh.cin_p, packed_w<P>(net, lh),
+                           packed_b<P>(net, lh), b.sc, p->nxt, p->nyt, Wp, (float2*)z, skip);
+    HZ_LAUNCH_CHECK();
+    return HZ_OK;
+}
+
+size_t net_fwd_ws_bytes(const no_net* net, int Hp, int Wp, int batch, no_prec prec) {
+    switch (prec) {
+        case NO_BF16: return fwd_layout<PolBF16>(net, Hp, Wp, batch, nullptr, 0).total;
+        case NO_FP32: return fwd_layout<PolF32>(net, Hp, Wp, batch, nullptr, 0).total;
+        default: return fwd_layout<PolF64>(net, Hp, Wp, batch, nullptr, 0).total;
+    }
+}
+
+int net_precond(const no_net* net, const hz_problem* p, no_prec prec, bool c128, const void* v, void* z, void* ws,
+                size_t ws_bytes, const int* skip, hipStream_t s) {
+    switch (prec) {
+        case NO_BF16: return precond_impl<PolBF16>(net, p, c128, v, z, ws, ws_bytes, skip, s);
+        case NO_FP32: return precond_impl<PolF32>(net, p, c128, v, z, ws, ws_bytes, skip, s);
+        case NO_FP64: return precond_impl<PolF64>(net, p, c128, v, z, ws, ws_bytes, skip, s);
+    }
+    set_error("no_precond_apply: bad precision");
+    return HZ_ERR_ARG;
+}
+
+}  // namespace hz
+
+using namespace hz;
+
+extern "C" int64_t no_param_count(const no_arch* a) {
+    std::vector<Layer> L;
+    int64_t np, pk, nb;
+    if (!build_layers(a, L, np, pk, nb)) return -1;
+    return np;
+}
+
+extern "C" int no_net_create(const no_arch* a, const float* theta, void* stream, no_net** out) {
+    clear_error();
+    HZ_CHECK_ARG(a && theta && out, "no_net_create: NULL argument");
+    no_net* net = new no_net();
+    if (!build_layers(a, net->layers, net->nparam, net->pk_total, net->bias_total)) {
+        delete net;
+        set_error("no_net_create: levels must be 1..6, base a multiple of 8, in_ch 2 or 5");
+        return HZ_ERR_ARG;
+    }
+    net->a = *a;
+    const size_t bytes = net->pk_total * (2 + 4 + 8) + net->bias_total * (4 + 8) + 5 * 256;
+    if (hipMalloc(&net->block, bytes) != hipSuccess) {
+        delete net;
+        set_error("no_net_create: hipMalloc failed");
+        return HZ_ERR_HIP;
+    }
+    Carver c(net->block, bytes);
+    net->w_bf = c.take<bf16_t>(net->pk_total);
+    net->w_f32 = c.take<float>(net->pk_total);
+    net->w_f64 = c.take<double>(net->pk_total);
+    net->b_f32 = c.take<float>(net->bias_total);
+    net->b_f64 = c.take<double>(net->bias_total);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = repack_all(net, theta, s);
+    if (rc == HZ_OK && hipStreamSynchronize(s) != hipSuccess) rc = HZ_ERR_HIP;
+    if (rc != HZ_OK) {
+        (void)hipFree(net->block);
+        delete net;
+        return rc;
+    }
+    *out = net;
+    return HZ_OK;
+}
+
+extern "C" int no_net_set_weights(no_net* net, const float* theta, void* stream) {
+    clear_error();
+    HZ_CHECK_ARG(net && theta, "no_net_set_weights: NULL argument");
+    return repack_all(net, theta, (hipStream_t)stream);
+}
+
+extern "C" int no_net_destroy(no_net* net) {
+    clear_error();
+    if (!net) return HZ_OK;
+    HZ_HIP(hipFree(net->block));
+    delete net;
+    return HZ_OK;
+}
+
+extern "C" size_t no_workspace_size(const no_net* net, const hz_problem* p, no_prec prec) {
+    clear_error();
+    if (!net || !p) return 0;
+    int Hp, Wp;
+    net_padded_dims(net, p, &Hp, &Wp);
+    return net_fwd_ws_bytes(net, Hp, Wp, 1, prec);
+}
+
+extern "C" int no_precond_apply(const no_net* net, const hz_problem* p, no_prec prec, hz_dtype dtype, const void* v,
+                                void* z, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    HZ_CHECK_ARG(net && p && v && z && ws, "no_precond_apply: NULL argument");
+    HZ_CHECK_ARG(dtype == HZ_C64 || dtype == HZ_C128, "no_precond_apply: bad dtype");
+    HZ_CHECK_ARG(v != z, "no_precond_apply: v and z must not overlap");
+    return net_precond(net, p, prec, dtype == HZ_C128, v, z, ws, ws_bytes, nullptr, (hipStream_t)stream);
+}

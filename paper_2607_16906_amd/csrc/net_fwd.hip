@@ -1,0 +1,303 @@
+// U-Net layer kernels on the matrix cores (forward): 3x3 convolution as implicit
+// GEMM with fused bias / ReLU / 2x2 average pool, and the 2x2 stride-2 transposed
+// convolution. Templated over the arithmetic policy (BF16, FP32, FP64).
+#include "net_kernels.h"
+
+namespace hz {
+
+constexpr int CT = 256;        // threads per block (4 wavefronts)
+constexpr int TH = 8, TW = 16; // pixel tile of the 3x3 convolution
+
+template <class P>
+constexpr int pix_stride() { return P::CK + 16 / (int)sizeof(typename P::T); }   // +16 B against bank conflicts
+
+template <class P, int TN, bool POOL>
+__global__ __launch_bounds__(CT) void k_conv3(const typename P::T* __restrict__ x0, int c0,
+                                              const typename P::T* __restrict__ x1, int c1,
+                                              const typename P::T* __restrict__ w,
+                                              const typename P::Acc* __restrict__ bias,
+                                              typename P::T* __restrict__ y, int cout_p,
+                                              typename P::T* __restrict__ ypool, int H, int W, int relu, int ck,
+                                              const int* __restrict__ skip) {
+    using T = typename P::T;
+    using Acc = typename P::Acc;
+    using AccV = typename P::AccV;
+    using Frag = typename P::Frag;
+    constexpr int PS = pix_stride<P>();
+    constexpr int VE = 16 / sizeof(T);        // elements per 16-byte vector
+    constexpr int NCB = TN / 16;              // output-channel blocks per block
+    if (skip && *skip) return;
+    __shared__ __attribute__((aligned(16))) T patch[(TH + 2) * (TW + 2) * PS];
+    __shared__ __attribute__((aligned(16))) T wl[9 * TN * PS];
+
+    const int ncb_tot = cout_p / TN;
+    const int bz = blockIdx.z / ncb_tot;                 // sample
+    const int co0 = (blockIdx.z - bz * ncb_tot) * TN;
+    const int ty0 = blockIdx.y * TH, tx0 = blockIdx.x * TW;
+    const int cin_p = c0 + c1;
+    const int64_t plane = (int64_t)H * W;
+    const T* xs0 = x0 + (int64_t)bz * plane * c0;
+    const T* xs1 = x1 ? x1 + (int64_t)bz * plane * c1 : nullptr;
+
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    AccV acc[2][NCB];
+#pragma unroll
+    for (int pb = 0; pb < 2; ++pb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[pb][cb][r] = 0;
+
+    const int vpp = ck / VE;                   // vectors per pixel in this chunk
+    const int cpg = ck / P::GW;                // k-groups per tap
+    const int groups = 9 * cpg;
+    const int steps = (groups + 3) / 4;
+    for (int k0 = 0; k0 < cin_p; k0 += ck) {
+        __syncthreads();
+        // input patch chunk (zero outside the image)
+        for (int v = threadIdx.x; v < (TH + 2) * (TW + 2) * vpp; v += CT) {
+            const int px = v / vpp, part = v - px * vpp;
+            const int py = px / (TW + 2), pxx = px - py * (TW + 2);
+            const int gy = ty0 + py - 1, gx = tx0 + pxx - 1;
+            uint4 val = uint4{0, 0, 0, 0};
+            if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+                const int c = k0 + part * VE;
+                const int64_t pix = (int64_t)gy * W + gx;
+                const T* src = (c < c0) ? xs0 + pix * c0 + c : xs1 + pix * c1 + (c - c0);
+                val = *(const uint4*)src;
+            }
+            *(uint4*)&patch[px * PS + part * VE] = val;
+        }
+        // weights chunk: [tap][TN][ck]
+        for (int v = threadIdx.x; v < 9 * TN * vpp; v += CT) {
+            const int row = v / vpp, part = v - row * vpp;
+            const int tap = row / TN, co = row - tap * TN;
+            const T* src = w + ((int64_t)tap * cout_p + co0 + co) * cin_p + k0 + part * VE;
+            *(uint4*)&wl[row * PS + part * VE] = *(const uint4*)src;
+        }
+        __syncthreads();
+        for (int st = 0; st < steps; ++st) {
+            const int gi = 4 * st + lg;
+            Frag a[NCB], b[2];
+            if (gi < groups) {
+                const int tap = gi / cpg, cg = gi - tap * cpg;
+                const int dy = tap / 3, dx = tap - 3 * (tap / 3);
+#pragma unroll
+                for (int pb = 0; pb < 2; ++pb)
+                    b[pb] = P::load(&patch[((2 * wv + pb + dy) * (TW + 2) + lr + dx) * PS + cg * P::GW]);
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) a[cb] = P::load(&wl[(tap * TN + cb * 16 + lr) * PS + cg * P::GW]);
+            } else {
+#pragma unroll
+                for (int pb = 0; pb < 2; ++pb) b[pb] = P::zero();
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) a[cb] = P::zero();
+            }
+#pragma unroll
+            for (int pb = 0; pb < 2; ++pb)
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) acc[pb][cb] = P::mma(a[cb], b[pb], acc[pb][cb]);
+        }
+    }
+
+    // epilogue: register r of a lane holds output channel co0 + 16 cb + row_of(lg, r) of pixel
+    // (ty0 + 2 wv + pb, tx0 + lr)
+    T* ys = y + (int64_t)bz * plane * cout_p;
+    const int gx = tx0 + lr;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+        const int co = co0 + cb * 16;
+        Acc v[2][4];
+#pragma unroll
+        for (int pb = 0; pb < 2; ++pb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                Acc t = acc[pb][cb][r] + bias[co + P::row_of(lg, r)];
+                if (relu) t = t > Acc(0) ? t : Acc(0);
+                v[pb][r] = t;
+            }
+#pragma unroll
+        for (int pb = 0; pb < 2; ++pb) {
+            const int gy = ty0 + 2 * wv + pb;
+            if (gy < H && gx < W) {
+                T* dst = ys + ((int64_t)gy * W + gx) * cout_p + co;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) dst[P::row_of(lg, r)] = P::cvt(v[pb][r]);
+            }
+        }
+        if (POOL) {
+            T* ps = ypool + (int64_t)bz * (plane / 4) * cout_p;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                Acc s = v[0][r] + v[1][r];
+                s += __shfl_xor(s, 1, 64);
+                v[0][r] = Acc(0.25) * s;
+            }
+            const int gy = ty0 + 2 * wv;
+            if ((lr & 1) == 0 && gy < H && gx < W) {
+                T* dst = ps + ((int64_t)(gy / 2) * (W / 2) + gx / 2) * cout_p + co;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) dst[P::row_of(lg, r)] = P::cvt(v[0][r]);
+            }
+        }
+    }
+}
+
+// 2x2 stride-2 transposed convolution: a GEMM per input pixel with M = 4 x
+// output channels (tap a, b and channel), N = 16 input pixels per wave, K = input
+// channels. Block: 64 input pixels of one row (4 waves x 16) and TN channels.
+template <class P, int TN>
+__global__ __launch_bounds__(CT) void k_convT2(const typename P::T* __restrict__ x, int cin_p,
+                                               const typename P::T* __restrict__ w,
+                                               const typename P::Acc* __restrict__ bias,
+                                               typename P::T* __restrict__ y, int cout_p, int H, int W, int ck,
+                                               const int* __restrict__ skip) {
+    using T = typename P::T;
+    using Acc = typename P::Acc;
+    using AccV = typename P::AccV;
+    using Frag = typename P::Frag;
+    constexpr int PS = pix_stride<P>();
+    constexpr int VE = 16 / sizeof(T);
+    constexpr int NCB = TN / 16;
+    if (skip && *skip) return;
+    __shared__ __attribute__((aligned(16))) T xin[64 * PS];
+    __shared__ __attribute__((aligned(16))) T wl[4 * TN * PS];
+    const int ncb_tot = cout_p / TN;
+    const int bz = blockIdx.z / ncb_tot;
+    const int co0 = (blockIdx.z - bz * ncb_tot) * TN;
+    const int iy = blockIdx.y, ix0 = blockIdx.x * 64;
+    const int64_t plane = (int64_t)H * W;
+    const T* xs = x + (int64_t)bz * plane * cin_p;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    AccV acc[4][NCB];
+#pragma unroll
+    for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[ab][cb][r] = 0;
+    const int vpp = ck / VE;
+    const int groups = ck / P::GW;
+    const int steps = (groups + 3) / 4;
+    for (int k0 = 0; k0 < cin_p; k0 += ck) {
+        __syncthreads();
+        for (int v = threadIdx.x; v < 64 * vpp; v += CT) {
+            const int px = v / vpp, part = v - px * vpp;
+            const int gx = ix0 + px;
+            uint4 val = uint4{0, 0, 0, 0};
+            if (gx < W) val = *(const uint4*)(xs + ((int64_t)iy * W + gx) * cin_p + k0 + part * VE);
+            *(uint4*)&xin[px * PS + part * VE] = val;
+        }
+        for (int v = threadIdx.x; v < 4 * TN * vpp; v += CT) {
+            const int row = v / vpp, part = v - row * vpp;
+            const int ab = row / TN, co = row - ab * TN;
+            const T* src = w + ((int64_t)ab * cout_p + co0 + co) * cin_p + k0 + part * VE;
+            *(uint4*)&wl[row * PS + part * VE] = *(const uint4*)src;
+        }
+        __syncthreads();
+        for (int st = 0; st < steps; ++st) {
+            const int cg = 4 * st + lg;
+            Frag b = cg < groups ? P::load(&xin[(wv * 16 + lr) * PS + cg * P::GW]) : P::zero();
+#pragma unroll
+            for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) {
+                    Frag a = cg < groups ? P::load(&wl[(ab * TN + cb * 16 + lr) * PS + cg * P::GW]) : P::zero();
+                    acc[ab][cb] = P::mma(a, b, acc[ab][cb]);
+                }
+        }
+    }
+    const int gx = ix0 + wv * 16 + lr;
+    if (gx >= W) return;
+    T* ys = y + (int64_t)bz * plane * 4 * cout_p;
+#pragma unroll
+    for (int ab = 0; ab < 4; ++ab) {
+        const int oy = 2 * iy + (ab >> 1), ox = 2 * gx + (ab & 1);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const int co = co0 + cb * 16;
+            T* dst = ys + ((int64_t)oy * (2 * W) + ox) * cout_p + co;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = P::row_of(lg, r);
+                dst[row] = P::cvt(acc[ab][cb][r] + bias[co + row]);
+            }
+        }
+    }
+}
+
+static int pick_tn(int cout_p) { return cout_p % 64 == 0 ? 64 : (cout_p % 32 == 0 ? 32 : 16); }
+
+template <class P>
+static int chunk_for(int cin_p, int c0, int c1) {
+    int ck = P::CK;
+    if (cin_p < ck) ck = cin_p;
+    if (c1 > 0) {
+        if (c0 < ck) ck = c0;
+        if (c1 < ck) ck = c1;
+    }
+    return ck;
+}
+
+template <class P>
+int launch_conv3(const typename P::T* x0, int c0, const typename P::T* x1, int c1, const typename P::T* w,
+                 const typename P::Acc* bias, typename P::T* y, int cout_p, typename P::T* ypool, int H, int W,
+                 int batch, bool relu, const int* skip, hipStream_t s) {
+    const int cin_p = c0 + c1;
+    const int ck = chunk_for<P>(cin_p, c0, c1);
+    constexpr int VE = 16 / sizeof(typename P::T);
+    if (cout_p % 16 || cin_p % ck || c0 % ck || ck % VE || ck % P::GW || (ypool && (H % 2 || W % 2))) {
+        set_error("conv3: unsupported channel / size combination");
+        return HZ_ERR_ARG;
+    }
+    const int tn = pick_tn(cout_p);
+    dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH, (cout_p / tn) * batch);
+#define HZ_C3(TNV, PL)                                                                                  \
+    hipLaunchKernelGGL((k_conv3<P, TNV, PL>), grid, dim3(CT), 0, s, x0, c0, x1, c1, w, bias, y, cout_p, \
+                       ypool, H, W, relu ? 1 : 0, ck, skip)
+    if (ypool) {
+        if (tn == 64) HZ_C3(64, true);
+        else if (tn == 32) HZ_C3(32, true);
+        else HZ_C3(16, true);
+    } else {
+        if (tn == 64) HZ_C3(64, false);
+        else if (tn == 32) HZ_C3(32, false);
+        else HZ_C3(16, false);
+    }
+#undef HZ_C3
+    HZ_LAUNCH_CHECK();
+    return HZ_OK;
+}
+
+template <class P>
+int launch_convT2(const typename P::T* x, int cin_p, const typename P::T* w, const typename P::Acc* bias,
+                  typename P::T* y, int cout_p, int H, int W, int batch, const int* skip, hipStream_t s) {
+    const int ck = chunk_for<P>(cin_p, cin_p, 0);
+    constexpr int VE = 16 / sizeof(typename P::T);
+    if (cout_p % 16 || cin_p % ck || ck % VE) {
+        set_error("convT2: unsupported channel combination");
+        return HZ_ERR_ARG;
+    }
+    const int tn = cout_p % 32 == 0 ? 32 : 16;
+    dim3 grid((W + 63) / 64, H, (cout_p / tn) * batch);
+    if (tn == 32)
+        hipLaunchKernelGGL((k_convT2<P, 32>), grid, dim3(CT), 0, s, x, cin_p, w, bias, y, cout_p, H, W, ck, skip);
+    else
+        hipLaunchKernelGGL((k_convT2<P, 16>), grid, dim3(CT), 0, s, x, cin_p, w, bias, y, cout_p, H, W, ck, skip);
+    HZ_LAUNCH_CHECK();
+    return HZ_OK;
+}
+
+#define HZ_INST(P)                                                                                              \
+    template int launch_conv3<P>(const P::T*, int, const P::T*, int, const P::T*, const P::Acc*, P::T*, int,     \
+                                 P::T*, int, int, int, bool, const int*, hipStream_t);                         \
+    template int launch_convT2<P>(const P::T*, int, const P::T*, const P::Acc*, P::T*, int, int, int, int,       \
+                                  const int*, hipStream_t);
+HZ_INST(PolBF16)
+HZ_INST(PolF32)
+HZ_INST(PolF64)
+#undef HZ_INST
+
+}  // namespace hz

@@ -1,0 +1,85 @@
+// MFMA policies and the U-Net layer kernels (forward), shared by inference and training.
+//
+// Activations are NHWC with channels padded to a multiple of 8; a batch of
+// fields is stored sample after sample. A 3x3 convolution is an implicit GEMM
+// with M = output channels, N = pixels and K = 9 x input channels: each block
+// owns an 8 x 16 pixel tile and TN output channels, stages the (8+2) x (16+2)
+// input patch and the matching weights chunk by chunk in LDS, and feeds the
+// matrix cores with 16 x 16 output blocks (rows = output channels, columns =
+// 16 consecutive pixels of one image row). The epilogue adds the bias, applies
+// ReLU and can also write the 2 x 2 average pool of the result.
+#pragma once
+
+#include "common.h"
+
+namespace hz {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8_t;
+typedef __attribute__((ext_vector_type(4))) float f32x4_t;
+typedef __attribute__((ext_vector_type(4))) double f64x4_t;
+
+// Lane layout of the 16x16 MFMA forms used here (64 lanes, l = lane):
+//   A (16 x K): lane l holds row l % 16, k-group l / 16 (GW consecutive k);
+//   B (K x 16): lane l holds column l % 16, k-group l / 16;
+//   D (16 x 16): lane l holds rows 4 (l / 16) + r, r = 0..3, of column l % 16
+//   for the FP32-accumulating forms, and rows (l / 16) + 4 r for the FP64 form
+//   (row_of gives the row of accumulator register r).
+struct PolBF16 {
+    using T = bf16_t;
+    using Acc = float;
+    using AccV = f32x4_t;
+    using Frag = bf16x8_t;
+    static constexpr int GW = 8;    // k per lane per MFMA
+    static constexpr int CK = 32;   // channels per LDS chunk
+    __device__ static Frag load(const T* p) { return __builtin_bit_cast(Frag, *(const uint4*)p); }
+    __device__ static Frag zero() { return __builtin_bit_cast(Frag, uint4{0, 0, 0, 0}); }
+    __device__ static AccV mma(Frag a, Frag b, AccV c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+    __device__ static T cvt(Acc v) { return f2bf(v); }
+    __device__ static Acc val(T v) { return bf2f(v); }
+    __device__ static int row_of(int lg, int r) { return 4 * lg + r; }
+};
+
+struct PolF32 {
+    using T = float;
+    using Acc = float;
+    using AccV = f32x4_t;
+    using Frag = float;
+    static constexpr int GW = 1;
+    static constexpr int CK = 16;
+    __device__ static Frag load(const T* p) { return *p; }
+    __device__ static Frag zero() { return 0.0f; }
+    __device__ static AccV mma(Frag a, Frag b, AccV c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static T cvt(Acc v) { return v; }
+    __device__ static Acc val(T v) { return v; }
+    __device__ static int row_of(int lg, int r) { return 4 * lg + r; }
+};
+
+struct PolF64 {
+    using T = double;
+    using Acc = double;
+    using AccV = f64x4_t;
+    using Frag = double;
+    static constexpr int GW = 1;
+    static constexpr int CK = 8;
+    __device__ static Frag load(const T* p) { return *p; }
+    __device__ static Frag zero() { return 0.0; }
+    __device__ static AccV mma(Frag a, Frag b, AccV c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static T cvt(Acc v) { return v; }
+    __device__ static Acc val(T v) { return v; }
+    __device__ static int row_of(int lg, int r) { return lg + 4 * r; }
+};
+
+// Host-side launch helpers (defined in net_fwd.hip), one per precision.
+// conv3: y = act(conv3x3(concat[x0, x1]) + b) (+ pooled copy); batch samples along grid z.
+template <class P>
+int launch_conv3(const typename P::T* x0, int c0, const typename P::T* x1, int c1, const typename P::T* w,
+                 const typename P::Acc* bias, typename P::T* y, int cout_p, typename P::T* ypool, int H, int W,
+                 int batch, bool relu, const int* skip, hipStream_t s);
+// convT2: y[2i+a][2j+b] = sum_c x[i][j][c] w[a][b][.][c] + b
+template <class P>
+int launch_convT2(const typename P::T* x, int cin_p, const typename P::T* w, const typename P::Acc* bias,
+                  typename P::T* y, int cout_p, int H, int W, int batch, const int* skip, hipStream_t s);
+
+}  // namespace hz

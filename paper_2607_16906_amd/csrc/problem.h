@@ -1,0 +1,43 @@
+// Internal view of a problem handle and the operator kernels' launchers.
+#pragma once
+
+#include "common.h"
+
+struct hz_problem {
+    hz_grid g;
+    int nxt, nyt;     // totals including the PML
+    int64_t n;        // nxt * nyt
+    // per-node fields
+    float* k2f;       // k^2, FP32 [n]
+    double* k2d;      // k^2, FP64 [n]
+    double* cnd;      // c / c_ref, FP64 [n] (network input channel)
+    // per-axis stencil coefficients: y = E u[i+1] + W u[i-1] + N u[j+1] + S u[j-1] + (k^2 - dx - dy) u
+    // forward (A) and adjoint (A^H) sets, in FP64 and FP32
+    double2 *fE_d, *fW_d, *fN_d, *fS_d, *aE_d, *aW_d, *aN_d, *aS_d, *dx_d, *dy_d;
+    float2 *fE_f, *fW_f, *fN_f, *fS_f, *aE_f, *aW_f, *aN_f, *aS_f, *dx_f, *dy_f;
+    double *sigx, *sigy;  // PML damping at the nodes, [nxt], [nyt] (network input channels)
+    void* block;          // the single device allocation holding all of the above
+};
+
+namespace hz {
+
+// Stencil modes: plain y = A x; residual y = b - A x with ||y||^2 block partials.
+enum StencilMode { ST_PLAIN = 0, ST_RESID = 1 };
+
+struct StencilCoef {
+    const void *E, *W, *N, *S, *dx, *dy;
+    const void* k2;
+    int conj_diag;
+};
+StencilCoef stencil_coef(const hz_problem* p, bool fp64, bool adjoint);
+
+// y = A x (or A^H x) in the precision of the complex type (float2 or double2).
+int launch_stencil(const hz_problem* p, bool fp64, bool adjoint, const void* x, void* y, hipStream_t s,
+                   const int* skip = nullptr);
+// r = b - A x in FP64 (b, x, r: double2 [n]); writes one ||r||^2 partial per block to part
+// (block count = stencil_blocks(p)).
+int launch_resid64(const hz_problem* p, const double2* b, const double2* x, double2* r,
+                   double* part, const int* skip, hipStream_t s);
+int stencil_blocks(const hz_problem* p);
+
+}  // namespace hz

@@ -1,0 +1,241 @@
+"""Thin ctypes binding of the gfx950 library (include/hz.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels. PyTorch supplies device memory (torch tensors on ``cuda``) and the
+current HIP stream. The library is loaded from the package directory; when it
+is missing, or when no GPU is visible, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhzno.so")
+
+HZ_OK, HZ_NOT_CONVERGED = 0, 1
+HZ_ERR_ARG, HZ_ERR_HIP, HZ_ERR_WORKSPACE, HZ_ERR_BREAKDOWN, HZ_ERR_NONFINITE = -1, -2, -3, -4, -5
+HZ_C64, HZ_C128 = 0, 1
+NO_BF16, NO_FP32, NO_FP64 = 0, 1, 2
+PREC = {"bf16": NO_BF16, "fp32": NO_FP32, "fp64": NO_FP64}
+
+
+class HzGrid(ct.Structure):
+    _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("npml", ct.c_int32),
+                ("h", ct.c_double), ("omega", ct.c_double), ("sigma_max", ct.c_double), ("c_ref", ct.c_double)]
+
+
+class NoArch(ct.Structure):
+    _fields_ = [("levels", ct.c_int32), ("base", ct.c_int32), ("in_ch", ct.c_int32)]
+
+
+class HzOpts(ct.Structure):
+    _fields_ = [("m", ct.c_int32), ("maxit", ct.c_int32), ("tol", ct.c_double), ("krylov", ct.c_int),
+                ("net_prec", ct.c_int), ("hist_host", ct.POINTER(ct.c_double)), ("hist_len", ct.c_int32)]
+
+
+class HzInfo(ct.Structure):
+    _fields_ = [("status", ct.c_int32), ("its", ct.c_int32), ("cycles", ct.c_int32),
+                ("est_relres", ct.c_double), ("true_relres", ct.c_double)]
+
+
+_P, _I, _SZ, _F = ct.c_void_p, ct.c_int, ct.c_size_t, ct.c_float
+# name -> (restype, argtypes); the declarations of include/hz.h
+SIGNATURES = {
+    "hz_last_error": (ct.c_char_p, []),
+    "hz_problem_create": (_I, [ct.POINTER(HzGrid), _P, _P, ct.POINTER(_P)]),
+    "hz_problem_destroy": (_I, [_P]),
+    "hz_problem_dims": (_I, [_P, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)]),
+    "hz_op_apply": (_I, [_P, _I, _I, _P, _P, _P]),
+    "no_param_count": (ct.c_int64, [ct.POINTER(NoArch)]),
+    "no_net_create": (_I, [ct.POINTER(NoArch), _P, _P, ct.POINTER(_P)]),
+    "no_net_set_weights": (_I, [_P, _P, _P]),
+    "no_net_destroy": (_I, [_P]),
+    "no_workspace_size": (_SZ, [_P, _P, _I]),
+    "no_precond_apply": (_I, [_P, _P, _I, _I, _P, _P, _P, _SZ, _P]),
+    "no_train_workspace_size": (_SZ, [_P, _P, _I, _I]),
+    "no_loss_backward": (_I, [_P, _I, _P, _P, _I, _I, _P, _P, _P, _P, _SZ, _P]),
+    "no_adam_workspace_size": (_SZ, [_P]),
+    "no_adam_step": (_I, [_P, _P, _P, _P, _P, _I, _F, _F, _F, _F, _F, _P, _SZ, _P]),
+    "fgmres_workspace_size": (_SZ, [_P, _P, ct.POINTER(HzOpts)]),
+    "fgmres_solve": (_I, [_P, _P, ct.POINTER(HzOpts), _P, _P, _P, _SZ, ct.POINTER(HzInfo), _P]),
+    "fgmres_batched_workspace_size": (_SZ, [_I, _P, _P, ct.POINTER(HzOpts)]),
+    "fgmres_solve_batched": (_I, [_I, _P, _P, ct.POINTER(HzOpts), _P, _P, _P, _SZ, ct.POINTER(HzInfo), _P]),
+}
+
+_lib = None
+
+
+class HzError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libhzno.so (no GPU needed to load it). Raises if it was not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: run python -m paper_2607_16906_amd.build")
+        lib = ct.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("the HIP library needs a visible GPU")
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ct.c_void_p(t.data_ptr())
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise HzError(rc, f"{what}: {load_library().hz_last_error().decode()}")
+    return rc
+
+
+def _ws(nbytes):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device="cuda")
+
+
+class Problem:
+    """One discrete Helmholtz system on the GPU (hz_problem_create)."""
+
+    def __init__(self, c, nx: int, ny: int, npml: int, h: float, omega: float = 1.0,
+                 sigma_max: float = 2.0, c_ref: float = 1500.0):
+        torch = _torch()
+        lib = load_library()
+        c = torch.as_tensor(c, dtype=torch.float32).to("cuda").contiguous()
+        nxt, nyt = nx + 2 * npml, ny + 2 * npml
+        if c.numel() != nxt * nyt:
+            raise ValueError(f"velocity has {c.numel()} entries, grid needs {nxt * nyt}")
+        self.grid = HzGrid(nx, ny, npml, h, omega, sigma_max, c_ref)
+        self.c = c
+        self.nx, self.ny, self.npml = nx, ny, npml
+        self.nxt, self.nyt, self.n = nxt, nyt, nxt * nyt
+        h_ = ct.c_void_p()
+        _check(lib.hz_problem_create(ct.byref(self.grid), _ptr(c), _stream(), ct.byref(h_)), "hz_problem_create")
+        self.handle = h_
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.hz_problem_destroy(h)
+            self.handle = None
+
+    def apply(self, x, adjoint: bool = False):
+        """y = A x (or A^H x) for a complex64/complex128 device vector of n entries."""
+        torch = _torch()
+        x = x.contiguous()
+        dt = {torch.complex64: HZ_C64, torch.complex128: HZ_C128}[x.dtype]
+        y = torch.empty_like(x)
+        _check(load_library().hz_op_apply(self.handle, dt, int(adjoint), _ptr(x), _ptr(y), _stream()), "hz_op_apply")
+        return y
+
+
+class Net:
+    """U-Net neural operator (no_net_create) holding its own repacked copies of theta."""
+
+    def __init__(self, levels: int, base: int, in_ch: int, theta):
+        torch = _torch()
+        lib = load_library()
+        self.arch = NoArch(levels, base, in_ch)
+        self.nparam = param_count(levels, base, in_ch)
+        theta = torch.as_tensor(theta, dtype=torch.float32).to("cuda").contiguous()
+        if theta.numel() != self.nparam:
+            raise ValueError(f"theta has {theta.numel()} entries, the network needs {self.nparam}")
+        self.theta = theta
+        h_ = ct.c_void_p()
+        _check(lib.no_net_create(ct.byref(self.arch), _ptr(theta), _stream(), ct.byref(h_)), "no_net_create")
+        self.handle = h_
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.no_net_destroy(h)
+            self.handle = None
+
+    def set_weights(self, theta):
+        torch = _torch()
+        theta = torch.as_tensor(theta, dtype=torch.float32).to("cuda").contiguous()
+        self.theta = theta
+        _check(load_library().no_net_set_weights(self.handle, _ptr(theta), _stream()), "no_net_set_weights")
+
+    def apply(self, problem: Problem, v, prec: str = "bf16"):
+        """z = N(v, c, sigma) (no_precond_apply)."""
+        torch = _torch()
+        lib = load_library()
+        v = v.contiguous()
+        dt = {torch.complex64: HZ_C64, torch.complex128: HZ_C128}[v.dtype]
+        z = torch.empty_like(v)
+        nb = lib.no_workspace_size(self.handle, problem.handle, PREC[prec])
+        ws = _ws(nb)
+        _check(lib.no_precond_apply(self.handle, problem.handle, PREC[prec], dt, _ptr(v), _ptr(z), _ptr(ws),
+                                    ct.c_size_t(ws.numel()), _stream()), "no_precond_apply")
+        return z
+
+
+def param_count(levels: int, base: int, in_ch: int) -> int:
+    n = load_library().no_param_count(ct.byref(NoArch(levels, base, in_ch)))
+    if n < 0:
+        raise ValueError("unsupported architecture")
+    return int(n)
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    its: int
+    cycles: int
+    est_relres: float
+    true_relres: float
+    hist: np.ndarray
+
+
+def fgmres(problem: Problem, b, x0=None, *, net: Net | None = None, m: int = 30, tol: float = 1e-6,
+           maxit: int = 300, krylov: str = "c64", net_prec: str = "bf16", workspace=None):
+    """Solve A x = b (fgmres_solve). b: complex128 device vector; returns (x, SolveInfo)."""
+    torch = _torch()
+    lib = load_library()
+    b = b.to(torch.complex128).contiguous()
+    x = torch.zeros_like(b) if x0 is None else x0.to(torch.complex128).contiguous().clone()
+    hist = np.zeros(maxit, np.float64)
+    opts = HzOpts(m, maxit, tol, HZ_C64 if krylov == "c64" else HZ_C128, PREC[net_prec],
+                  hist.ctypes.data_as(ct.POINTER(ct.c_double)), maxit)
+    nh = net.handle if net is not None else None
+    nb = lib.fgmres_workspace_size(problem.handle, nh, ct.byref(opts))
+    if nb == 0:
+        raise HzError(HZ_ERR_ARG, lib.hz_last_error().decode())
+    ws = workspace if workspace is not None and workspace.numel() >= nb else _ws(nb)
+    info = HzInfo()
+    rc = lib.fgmres_solve(problem.handle, nh, ct.byref(opts), _ptr(b), _ptr(x), _ptr(ws), ct.c_size_t(ws.numel()),
+                          ct.byref(info), _stream())
+    if rc in (HZ_ERR_ARG, HZ_ERR_HIP, HZ_ERR_WORKSPACE):
+        _check(rc, "fgmres_solve")
+    return x, SolveInfo(info.status, info.its, info.cycles, info.est_relres, info.true_relres, hist[:info.its].copy())
+
+
+def fgmres_workspace_bytes(problem: Problem, net: Net | None, m: int, maxit: int, krylov: str = "c64",
+                           net_prec: str = "bf16") -> int:
+    opts = HzOpts(m, maxit, 1e-6, HZ_C64 if krylov == "c64" else HZ_C128, PREC[net_prec], None, 0)
+    return int(load_library().fgmres_workspace_size(problem.handle, net.handle if net else None, ct.byref(opts)))

@@ -1,0 +1,76 @@
+"""GPU parity of the U-Net preconditioner (no_precond_apply) against the FP64 oracle in FP64,
+FP32 and BF16 (the oracle then runs on the BF16-rounded weights)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+from oracle import unet
+from synth import box_smoothed_noise, c1_system, he_uniform, rng_for, skull_ring_velocity
+
+from gpu_util import make_pair, rel, to_dev, to_np
+
+
+def bf16_round(a):
+    """Round-to-nearest-even to bfloat16, returned as float64 (test-side input preparation)."""
+    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def setup(levels, base, in_ch, nx, p, seed=0):
+    from paper_2607_16906_amd import hz
+    nt = nx + 2 * p
+    c = skull_ring_velocity(nt, p, rng_for(12, 0, seed), rings=2)
+    op, gp = make_pair(c, p)
+    specs = unet.layer_specs(levels, base, in_ch)
+    theta = he_uniform(unet.init_shapes(specs), rng_for(12, 2, seed))
+    net = hz.Net(levels, base, in_ch, theta)
+    v = box_smoothed_noise(nt, rng_for(12, 3, seed)) + 0.3 * (
+        np.random.default_rng(seed).standard_normal((nt, nt)))
+    return op, gp, specs, theta, net, v
+
+
+@pytest.mark.parametrize("levels,base,in_ch,nx,p", [(2, 16, 2, 64, 8), (3, 8, 5, 70, 8), (4, 8, 5, 40, 8),
+                                                    (1, 8, 2, 21, 4)])
+def test_net_fp64_matches_oracle(levels, base, in_ch, nx, p):
+    op, gp, specs, theta, net, v = setup(levels, base, in_ch, nx, p)
+    z = to_np(net.apply(gp, to_dev(v, torch.complex128), prec="fp64")).reshape(op.ny, op.nx)
+    ref = unet.precond_apply(theta.astype(np.float64), specs, op, v)
+    assert rel(z, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("levels,base,in_ch,nx,p", [(4, 32, 5, 88, 16), (2, 16, 2, 64, 8)])
+def test_net_fp32_within_1e5(levels, base, in_ch, nx, p):
+    op, gp, specs, theta, net, v = setup(levels, base, in_ch, nx, p, seed=1)
+    z = to_np(net.apply(gp, to_dev(v, torch.complex64), prec="fp32")).reshape(op.ny, op.nx)
+    ref = unet.precond_apply(theta.astype(np.float64), specs, op, v)
+    assert rel(z, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("levels,base,in_ch,nx,p", [(4, 32, 5, 88, 16), (3, 16, 5, 50, 7)])
+def test_net_bf16_normwise(levels, base, in_ch, nx, p):
+    op, gp, specs, theta, net, v = setup(levels, base, in_ch, nx, p, seed=2)
+    z = to_np(net.apply(gp, to_dev(v, torch.complex64), prec="bf16")).reshape(op.ny, op.nx)
+    ref = unet.precond_apply(bf16_round(theta), specs, op, v)
+    err = rel(z, ref)
+    print(f"bf16 normwise error {err:.3e}")
+    assert err <= 3e-2
+
+
+def test_net_zero_input_and_scale():
+    op, gp, specs, theta, net, v = setup(2, 16, 5, 30, 5, seed=3)
+    zero = torch.zeros(gp.n, dtype=torch.complex64, device="cuda")
+    assert torch.count_nonzero(net.apply(gp, zero, prec="fp32")).item() == 0
+    z1 = net.apply(gp, to_dev(v, torch.complex128), prec="fp64")
+    z2 = net.apply(gp, to_dev(3.0 * v, torch.complex128), prec="fp64")
+    assert rel(to_np(z2), 3.0 * to_np(z1)) <= 1e-13
+
+
+def test_net_bad_arch_rejected():
+    from paper_2607_16906_amd import hz
+    with pytest.raises(ValueError):
+        hz.param_count(4, 12, 5)
+    assert hz.param_count(4, 32, 5) == unet.param_count(unet.layer_specs(4, 32, 5))
