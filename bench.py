@@ -1,0 +1,244 @@
+"""Benchmark: solves/s of the BF16-network FGMRES on the single-solve workload (one MI355X).
+
+Workload: 256^2 interior grid + 20-cell PML (296^2 nodes), skull-ring velocity with 1-3 rings
+and 5% noise, 1-4 Gaussian sources, 4-level / 32-channel U-Net (BF16 operands, FP32
+accumulation), FP32 Krylov basis, FGMRES restart 30, tol 1e-6 on the FP64 true residual. A step
+is one full solve from x0 = 0 with every input resident on the GPU. The same solve with the
+network in FP32 (the plain FP32 form) is timed beside it, and the dominant network layer is
+timed alone with HIP events for the roofline. The oracle is timed on the host over a bounded
+sample of iterations.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--roofline-only]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WEIGHTS = os.path.join(ROOT, "paper_2607_16906_amd", "weights", "unet_l4_c32_in5.npz")
+M_RESTART, TOL, MAXIT = 30, 1e-6, 6000
+LEVELS, BASE, IN_CH = 4, 32, 5
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def layer_flops(kind, cin, cout, H, W):
+    """Algorithmic FLOPs of one layer launch on an H x W input (logical channels)."""
+    if kind == 0:
+        return 2.0 * 9 * cin * cout * H * W
+    return 2.0 * cin * cout * 4 * H * W
+
+
+def net_layers(levels, base, in_ch, Hp, Wp):
+    """(index, kind, cin, cout, H, W) of every 3x3 / transposed layer, in parameter order."""
+    out, i = [], 0
+    cin = in_ch
+    for l in range(levels):
+        c = base << l
+        out.append((i, 0, cin, c, Hp >> l, Wp >> l)); i += 1
+        out.append((i, 0, c, c, Hp >> l, Wp >> l)); i += 1
+        cin = c
+    for l in range(levels - 2, -1, -1):
+        c = base << l
+        out.append((i, 1, 2 * c, c, Hp >> (l + 1), Wp >> (l + 1))); i += 1
+        out.append((i, 0, 2 * c, c, Hp >> l, Wp >> l)); i += 1
+        out.append((i, 0, c, c, Hp >> l, Wp >> l)); i += 1
+    return out
+
+
+def time_layers(net, Hp, Wp, reps, prec="bf16", only=-1):
+    """Per-layer average launch time (ms) with HIP events on the current stream."""
+    import torch
+    elem = {"bf16": torch.int16, "fp32": torch.float32}[prec]
+    res = []
+    for (i, kind, cin, cout, H, W) in net_layers(LEVELS, BASE, IN_CH, Hp, Wp):
+        if only >= 0 and i != only:
+            continue
+        _, cin_p, cout_p, cat_cp = net.layer_info(i)
+        c0 = cat_cp if cat_cp else cin_p
+        x0 = torch.zeros(H * W * c0, dtype=elem, device="cuda")
+        x1 = torch.zeros(H * W * (cin_p - c0), dtype=elem, device="cuda") if cat_cp else None
+        Ho, Wo = (H, W) if kind == 0 else (2 * H, 2 * W)
+        y = torch.empty(Ho * Wo * cout_p, dtype=elem, device="cuda")
+        for _ in range(3):
+            net.layer_forward(i, x0, y, H=H, W=W, x1=x1, prec=prec)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            net.layer_forward(i, x0, y, H=H, W=W, x1=x1, prec=prec)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res.append(dict(layer=i, kind=kind, cin=cin, cout=cout, H=H, W=W, ms=ms,
+                        flops=layer_flops(kind, cin, cout, H, W)))
+    return res
+
+
+def time_stencil(hz, torch, nt, reps=50):
+    """Average time (ms) of the FP32 stencil on an nt x nt homogeneous grid, HIP events."""
+    c = np.full(nt * nt, 1500.0, np.float32)
+    p = hz.Problem(c, nt - 32, nt - 32, 16, 2 * np.pi / 10)
+    x = torch.randn(nt * nt, dtype=torch.complex64, device="cuda")
+    for _ in range(3):
+        p.apply(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        y = p.apply(x)
+    e1.record()
+    torch.cuda.synchronize()
+    del y
+    return e0.elapsed_time(e1) / reps
+
+
+def cpu_baseline(system, theta, gpu_its, budget_s=20.0):
+    """The FP64 oracle FGMRES on the same system and weights, timed over a bounded number of
+    iterations and scaled to one solve of gpu_its iterations."""
+    from oracle import fgmres as ofg
+    from oracle import helmholtz as ohz
+    from oracle import unet
+    from synth import C_REF, H_10PPW
+    op = ohz.Problem(system.c.astype(np.float32).astype(np.float64), system.npml, H_10PPW, 1.0, 2.0, C_REF)
+    specs = unet.layer_specs(LEVELS, BASE, IN_CH)
+    th = np.asarray(theta, np.float64)
+    nt = system.nt
+    A = lambda x: ohz.op_apply(op, x.reshape(nt, nt)).ravel()
+    M = lambda v: unet.precond_apply(th, specs, op, v.reshape(nt, nt)).ravel()
+    t0 = time.time()
+    ofg.fgmres(A, M, system.b, m=M_RESTART, tol=TOL, maxit=1)
+    t1 = time.time() - t0
+    its = max(2, min(M_RESTART, int(budget_s / max(t1, 1e-3))))
+    t0 = time.time()
+    r = ofg.fgmres(A, M, system.b, m=M_RESTART, tol=TOL, maxit=its)
+    dt = time.time() - t0
+    per_it = dt / r.its
+    return {"value": 1.0 / (per_it * gpu_its), "unit": "solves/s", "cores": len(os.sched_getaffinity(0)),
+            "kind": "oracle",
+            "sample": f"{r.its} FP64 oracle FGMRES iterations ({dt:.1f} s, {per_it * 1e3:.0f} ms/it) on the same "
+                      f"296^2 system and weights, scaled to the {gpu_its} iterations of the GPU solve"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp32-steps", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--roofline-only", action="store_true", help="only the per-layer roofline timing")
+    ap.add_argument("--roofline-layer", type=int, default=-1,
+                    help="with --roofline-only: time this layer alone (for a profiler run of one kernel)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the single-solve workload is measured on one MI355X; "
+              "--gpus above 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2607_16906_amd import hz
+    from synth import H_10PPW, c2_system
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    w = np.load(WEIGHTS)
+    theta = w["theta"].astype(np.float32)
+    s = c2_system(0)
+    gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW)
+    net = hz.Net(LEVELS, BASE, IN_CH, theta)
+    Hp = Wp = (s.nt + 7) // 8 * 8
+
+    layers = time_layers(net, Hp, Wp, reps=50, only=args.roofline_layer if args.roofline_only else -1)
+    dom = max(layers, key=lambda r: r["ms"])
+    achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
+    net_ms = sum(r["ms"] for r in layers)
+    net_flops = sum(r["flops"] for r in layers)
+    kname = f"k_conv3<PolBF16,{64 if dom['cout'] >= 64 else 32},{'pool' if dom['layer'] in (1, 3, 5) else 'nopool'}>" \
+        if dom["kind"] == 0 else "k_convT2<PolBF16>"
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
+                "kernel": kname, "layer": dom["layer"],
+                "shape": f"{dom['cin']}->{dom['cout']} ch on {dom['H']}x{dom['W']}",
+                "flops_per_launch": dom["flops"], "avg_launch_ms": round(dom["ms"], 5)}
+    if args.roofline_only:
+        print(json.dumps({"roofline": roofline, "layers": layers}))
+        return
+
+    b = torch.from_numpy(s.b.ravel()).cuda()
+    ws = torch.empty(hz.fgmres_workspace_bytes(gp, net, M_RESTART, MAXIT, "c64", "fp32"), dtype=torch.uint8,
+                     device="cuda")
+
+    def solve(prec):
+        return hz.fgmres(gp, b, net=net, m=M_RESTART, tol=TOL, maxit=MAXIT, krylov="c64", net_prec=prec,
+                         workspace=ws)
+
+    for _ in range(args.warmup):
+        x, info = solve("bf16")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        x, info = solve("bf16")
+        infos.append(info)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = elapsed / args.steps * 1e3
+    its = infos[-1].its
+    ok = all(i.status == 0 and i.true_relres <= TOL for i in infos)
+
+    # the plain FP32 form: same solver and weights, network in FP32 on the matrix cores
+    x32, i32 = solve("fp32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.fp32_steps):
+        x32, i32 = solve("fp32")
+    torch.cuda.synchronize()
+    ms32 = (time.perf_counter() - t0) / args.fp32_steps * 1e3
+
+    st_ms = time_stencil(hz, torch, 296)
+    big = 4096
+    st_big = time_stencil(hz, torch, big, reps=20)
+
+    out = {
+        "metric": "solves/s to rel-res 1e-6: BF16-net FGMRES vs plain FP32 FGMRES; HBM GB/s",
+        "value": round(args.steps / elapsed, 4) if ok else 0.0,
+        "unit": "solves/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "single solve, 256^2 interior + 20 PML (296^2), skull-ring velocity, 1-4 Gaussian "
+                               "sources, 4-level/32-ch U-Net BF16, FP32 Krylov, FGMRES(30), tol 1e-6",
+                   "nodes": s.nt * s.nt, "restart": M_RESTART, "tol": TOL,
+                   "weights_step": int(w["step"])},
+        "solve": {"its": its, "cycles": infos[-1].cycles, "true_relres": infos[-1].true_relres,
+                  "converged": ok, "us_per_it": round(ms_step * 1e3 / max(its, 1), 1)},
+        "fp32_form": {"value": round(1e3 / ms32, 4) if i32.status == 0 else 0.0, "unit": "solves/s",
+                      "ms_per_solve": round(ms32, 3), "its": i32.its, "true_relres": i32.true_relres},
+        "speedup_bf16_vs_fp32": round(ms32 / ms_step, 3),
+        "roofline": roofline,
+        "network": {"ms_per_apply_layers": round(net_ms, 4), "tflops_layers": round(net_flops / net_ms * 1e-9, 2),
+                    "gflop_per_apply": round(net_flops * 1e-9, 3)},
+        "stencil": {"fp32_296_us": round(st_ms * 1e3, 2),
+                    "fp32_296_gbs_in_cache": round(20 * 296 * 296 / (st_ms * 1e-3) / 1e9, 1),
+                    f"fp32_{big}_us": round(st_big * 1e3, 2),
+                    f"fp32_{big}_hbm_gbs": round(20 * big * big / (st_big * 1e-3) / 1e9, 1),
+                    "hbm_frac": round(20 * big * big / (st_big * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(s, theta, its)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

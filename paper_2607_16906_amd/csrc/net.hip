@@ -409,3 +409,50 @@ extern "C" int no_precond_apply(const no_net* net, const hz_problem* p, no_prec 
     HZ_CHECK_ARG(v != z, "no_precond_apply: v and z must not overlap");
     return net_precond(net, p, prec, dtype == HZ_C128, v, z, ws, ws_bytes, nullptr, (hipStream_t)stream);
 }
+
+extern "C" int no_layer_info(const no_net* net, int layer, int32_t* kind, int32_t* cin_p, int32_t* cout_p,
+                             int32_t* cat_cp) {
+    clear_error();
+    HZ_CHECK_ARG(net && layer >= 0 && layer < (int)net->layers.size(), "no_layer_info: bad layer");
+    const Layer& ly = net->layers[layer];
+    if (kind) *kind = ly.kind;
+    if (cin_p) *cin_p = ly.cin_p;
+    if (cout_p) *cout_p = ly.cout_p;
+    if (cat_cp) *cat_cp = ly.cat_cp;
+    return HZ_OK;
+}
+
+namespace hz {
+template <class P>
+static int layer_impl(const no_net* net, const Layer& ly, int batch, int H, int W, const void* x0, const void* x1,
+                      void* y, void* pool, hipStream_t s) {
+    using T = typename P::T;
+    if (ly.kind == L_CONV3) {
+        const int c1 = ly.cat_cp ? ly.cin_p - ly.cat_cp : 0;
+        const int c0 = ly.cin_p - c1;
+        return launch_conv3<P>((const T*)x0, c0, (const T*)x1, c1, packed_w<P>(net, ly), packed_b<P>(net, ly),
+                               (T*)y, ly.cout_p, (T*)pool, H, W, batch, true, nullptr, s);
+    }
+    return launch_convT2<P>((const T*)x0, ly.cin_p, packed_w<P>(net, ly), packed_b<P>(net, ly), (T*)y, ly.cout_p,
+                            H, W, batch, nullptr, s);
+}
+}  // namespace hz
+
+extern "C" int no_layer_forward(const no_net* net, int layer, no_prec prec, int batch, int H, int W,
+                                const void* x0, const void* x1, void* y, void* pool, void* stream) {
+    clear_error();
+    HZ_CHECK_ARG(net && layer >= 0 && layer < (int)net->layers.size() && x0 && y, "no_layer_forward: bad argument");
+    const Layer& ly = net->layers[layer];
+    HZ_CHECK_ARG(ly.kind != L_CONV1, "no_layer_forward: the head runs inside no_precond_apply only");
+    HZ_CHECK_ARG(batch >= 1 && H >= 1 && W >= 1, "no_layer_forward: bad sizes");
+    HZ_CHECK_ARG(!ly.cat_cp || x1, "no_layer_forward: concatenated input needs x1");
+    HZ_CHECK_ARG(!pool || (ly.kind == L_CONV3 && H % 2 == 0 && W % 2 == 0), "no_layer_forward: bad pool output");
+    hipStream_t s = (hipStream_t)stream;
+    switch (prec) {
+        case NO_BF16: return layer_impl<PolBF16>(net, ly, batch, H, W, x0, x1, y, pool, s);
+        case NO_FP32: return layer_impl<PolF32>(net, ly, batch, H, W, x0, x1, y, pool, s);
+        case NO_FP64: return layer_impl<PolF64>(net, ly, batch, H, W, x0, x1, y, pool, s);
+    }
+    set_error("no_layer_forward: bad precision");
+    return HZ_ERR_ARG;
+}

@@ -57,6 +57,9 @@ SIGNATURES = {
     "no_net_destroy": (_I, [_P]),
     "no_workspace_size": (_SZ, [_P, _P, _I]),
     "no_precond_apply": (_I, [_P, _P, _I, _I, _P, _P, _P, _SZ, _P]),
+    "no_layer_info": (_I, [_P, _I, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32),
+                           ct.POINTER(ct.c_int32)]),
+    "no_layer_forward": (_I, [_P, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P]),
     "no_train_workspace_size": (_SZ, [_P, _P, _I, _I]),
     "no_loss_backward": (_I, [_P, _I, _P, _P, _I, _I, _P, _P, _P, _P, _SZ, _P]),
     "no_adam_workspace_size": (_SZ, [_P]),
@@ -193,6 +196,21 @@ class Net:
         _check(lib.no_precond_apply(self.handle, problem.handle, PREC[prec], dt, _ptr(v), _ptr(z), _ptr(ws),
                                     ct.c_size_t(ws.numel()), _stream()), "no_precond_apply")
         return z
+
+
+    def layer_info(self, layer: int):
+        """(kind, cin_p, cout_p, cat_cp) of one layer (no_layer_info)."""
+        v = [ct.c_int32() for _ in range(4)]
+        _check(load_library().no_layer_info(self.handle, layer, *[ct.byref(x) for x in v]), "no_layer_info")
+        return tuple(x.value for x in v)
+
+    def layer_forward(self, layer: int, x0, y, *, H: int, W: int, batch: int = 1, x1=None, pool=None,
+                      prec: str = "bf16"):
+        """Run one layer on NHWC device tensors (no_layer_forward); asynchronous on the current stream."""
+        _check(load_library().no_layer_forward(self.handle, layer, PREC[prec], batch, H, W, _ptr(x0),
+                                               _ptr(x1) if x1 is not None else None, _ptr(y),
+                                               _ptr(pool) if pool is not None else None, _stream()),
+               "no_layer_forward")
 
 
 def param_count(levels: int, base: int, in_ch: int) -> int:
