@@ -32,6 +32,9 @@ struct no_net {
     hz::bf16_t* w_bf;                // repacked weights, BF16
     float* w_f32;                    // repacked weights, FP32
     double* w_f64;                   // repacked weights, FP64
+    hz::bf16_t* wt_bf;               // data-gradient packs (flipped / transposed), BF16
+    float* wt_f32;
+    double* wt_f64;
     float* b_f32;                    // biases (FP32; the BF16 path adds them in FP32)
     double* b_f64;
     void* block;

@@ -14,11 +14,10 @@
 
 #include "krylov.h"
 #include "net.h"
+#include "net_impl.h"
 #include "net_kernels.h"
 
 namespace hz {
-
-static int round16(int c) { return (c + 15) / 16 * 16; }
 
 static bool build_layers(const no_arch* a, std::vector<Layer>& L, int64_t& nparam, int64_t& pk, int64_t& nb) {
     if (!a || a->levels < 1 || a->levels > 6 || a->base < 8 || a->base % 8 || (a->in_ch != 2 && a->in_ch != 5))
@@ -68,9 +67,12 @@ static bool build_layers(const no_arch* a, std::vector<Layer>& L, int64_t& npara
 
 // Repack one layer from the flat FP32 vector into [tap][cout_p][cin_p] (channels
 // padded with zeros) in BF16, FP32 and FP64, and its bias into FP32 and FP64.
+// The data-gradient packs hold the same values at [8 - tap][ci][co] (3x3) or [ab][ci][co]
+// (transposed convolutions).
 __global__ void k_repack(const float* __restrict__ theta, Layer ly, bf16_t* __restrict__ wb,
                          float* __restrict__ wf, double* __restrict__ wd, float* __restrict__ bf,
-                         double* __restrict__ bd) {
+                         double* __restrict__ bd, bf16_t* __restrict__ tb, float* __restrict__ tf,
+                         double* __restrict__ td) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx < ly.pk_len) {
         const int cis = (int)(idx % ly.cin_p);      // stored input channel
@@ -100,6 +102,13 @@ __global__ void k_repack(const float* __restrict__ theta, Layer ly, bf16_t* __re
         wb[ly.pk_off + idx] = f2bf(v);
         wf[ly.pk_off + idx] = v;
         wd[ly.pk_off + idx] = (double)v;
+        if (ly.kind != L_CONV1) {
+            const int tt = ly.kind == L_CONV3 ? 8 - tap : tap;
+            const int64_t j = ((int64_t)tt * ly.cin_p + cis) * ly.cout_p + co;
+            tb[ly.pk_off + j] = f2bf(v);
+            tf[ly.pk_off + j] = v;
+            td[ly.pk_off + j] = (double)v;
+        }
     }
     if (idx < ly.cout_p) {
         const float b = idx < ly.cout ? theta[ly.b_off + idx] : 0.0f;
@@ -112,7 +121,7 @@ static int repack_all(no_net* net, const float* theta, hipStream_t s) {
     for (const Layer& ly : net->layers) {
         const int64_t n = ly.pk_len > ly.cout_p ? ly.pk_len : ly.cout_p;
         hipLaunchKernelGGL(k_repack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, theta, ly, net->w_bf,
-                           net->w_f32, net->w_f64, net->b_f32, net->b_f64);
+                           net->w_f32, net->w_f64, net->b_f32, net->b_f64, net->wt_bf, net->wt_f32, net->wt_f64);
         HZ_LAUNCH_CHECK();
     }
     return HZ_OK;
@@ -141,36 +150,6 @@ __global__ void k_scale_factor(const double2* part, int nblk, int64_t n, double*
     }
 }
 
-// X[y][x][0..7] = [Re v / s, Im v / s, (c / c_ref, sigma_x, sigma_y), 0...] on the grid, 0 in the padding.
-template <class P, typename C>
-__global__ void k_pack(const C* __restrict__ v, const double* __restrict__ sc, const double* __restrict__ cnd,
-                       const double* __restrict__ sigx, const double* __restrict__ sigy, int nxt, int nyt, int Hp,
-                       int Wp, int in_ch, typename P::T* __restrict__ X, const int* __restrict__ skip) {
-    using T = typename P::T;
-    if (skip && *skip) return;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)Hp * Wp) return;
-    const int yy = (int)(idx / Wp), xx = (int)(idx % Wp);
-    T out[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) out[c] = P::cvt(0);
-    if (yy < nyt && xx < nxt) {
-        const int64_t g = (int64_t)yy * nxt + xx;
-        const double is = sc[1];
-        const C a = v[g];
-        out[0] = P::cvt((typename P::Acc)((double)a.x * is));
-        out[1] = P::cvt((typename P::Acc)((double)a.y * is));
-        if (in_ch == 5) {
-            out[2] = P::cvt((typename P::Acc)cnd[g]);
-            out[3] = P::cvt((typename P::Acc)sigx[xx]);
-            out[4] = P::cvt((typename P::Acc)sigy[yy]);
-        }
-    }
-    T* dst = X + idx * 8;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) dst[c] = out[c];
-}
-
 // z = s (out_0 + i out_1), out_k = sum_c D0[c] Wh[k][c] + bh[k], on the grid only.
 template <class P, typename C>
 __global__ void k_head(const typename P::T* __restrict__ D, int cin_p, const typename P::T* __restrict__ wh,
@@ -190,91 +169,6 @@ __global__ void k_head(const typename P::T* __restrict__ D, int cin_p, const typ
     }
     const double s = sc[0];
     z[idx] = from_d2<C>(double2{s * (double)o0, s * (double)o1});
-}
-
-// ------------------------------------------------------------------ forward
-
-struct FwdBufs {
-    void* X;
-    std::vector<void*> E, T1, P, U, D;
-    double2* part;
-    double* sc;
-    size_t total;
-};
-
-template <class P>
-static FwdBufs fwd_layout(const no_net* net, int Hp, int Wp, int batch, void* base, size_t cap) {
-    using T = typename P::T;
-    FwdBufs b;
-    Carver c(base, cap);
-    const int lv = net->a.levels;
-    b.X = c.take<T>((size_t)batch * Hp * Wp * 8);
-    b.E.resize(lv);
-    b.T1.resize(lv);
-    b.P.resize(lv);
-    b.U.resize(lv);
-    b.D.resize(lv);
-    for (int l = 0; l < lv; ++l) {
-        const size_t px = (size_t)batch * (Hp >> l) * (Wp >> l);
-        const int cs = round16(net->a.base << l);
-        b.E[l] = c.take<T>(px * cs);
-        b.T1[l] = c.take<T>(px * cs);
-        b.P[l] = l > 0 ? c.take<T>(px * round16(net->a.base << (l - 1))) : nullptr;
-        b.U[l] = l < lv - 1 ? c.take<T>(px * cs) : nullptr;
-        b.D[l] = l < lv - 1 ? c.take<T>(px * cs) : nullptr;
-    }
-    b.part = c.take<double2>(1024);
-    b.sc = c.take<double>(2);
-    b.total = c.off + 256;
-    return b;
-}
-
-template <class P>
-static const typename P::T* packed_w(const no_net* net, const Layer& ly) {
-    if constexpr (sizeof(typename P::T) == 2) return net->w_bf + ly.pk_off;
-    else if constexpr (sizeof(typename P::T) == 4) return net->w_f32 + ly.pk_off;
-    else return net->w_f64 + ly.pk_off;
-}
-template <class P>
-static const typename P::Acc* packed_b(const no_net* net, const Layer& ly) {
-    if constexpr (sizeof(typename P::Acc) == 4) return net->b_f32 + ly.bias_off;
-    else return net->b_f64 + ly.bias_off;
-}
-
-// Network body on a packed input X (batch samples), result D0 = decoder level-0 output.
-template <class P>
-static int unet_body(const no_net* net, const FwdBufs& b, int Hp, int Wp, int batch, const int* skip, hipStream_t s) {
-    using T = typename P::T;
-    const int lv = net->a.levels;
-    const std::vector<Layer>& Ls = net->layers;
-    int li = 0;
-    for (int l = 0; l < lv; ++l) {
-        const int H = Hp >> l, W = Wp >> l;
-        const Layer& la = Ls[li++];
-        const Layer& lb = Ls[li++];
-        const T* in = l == 0 ? (const T*)b.X : (const T*)b.P[l];
-        HZ_TRY(launch_conv3<P>(in, la.cin_p, nullptr, 0, packed_w<P>(net, la), packed_b<P>(net, la), (T*)b.T1[l],
-                               la.cout_p, nullptr, H, W, batch, true, skip, s));
-        T* pool = l + 1 < lv ? (T*)b.P[l + 1] : nullptr;
-        HZ_TRY(launch_conv3<P>((const T*)b.T1[l], lb.cin_p, nullptr, 0, packed_w<P>(net, lb), packed_b<P>(net, lb),
-                               (T*)b.E[l], lb.cout_p, pool, H, W, batch, true, skip, s));
-    }
-    const T* Dn = (const T*)b.E[lv - 1];
-    for (int l = lv - 2; l >= 0; --l) {
-        const int H = Hp >> l, W = Wp >> l;
-        const Layer& lu = Ls[li++];
-        const Layer& la = Ls[li++];
-        const Layer& lb = Ls[li++];
-        HZ_TRY(launch_convT2<P>(Dn, lu.cin_p, packed_w<P>(net, lu), packed_b<P>(net, lu), (T*)b.U[l], lu.cout_p,
-                                H / 2, W / 2, batch, skip, s));
-        const int ce = lu.cout_p;
-        HZ_TRY(launch_conv3<P>((const T*)b.E[l], ce, (const T*)b.U[l], ce, packed_w<P>(net, la), packed_b<P>(net, la),
-                               (T*)b.T1[l], la.cout_p, nullptr, H, W, batch, true, skip, s));
-        HZ_TRY(launch_conv3<P>((const T*)b.T1[l], lb.cin_p, nullptr, 0, packed_w<P>(net, lb), packed_b<P>(net, lb),
-                               (T*)b.D[l], lb.cout_p, nullptr, H, W, batch, true, skip, s));
-        Dn = (const T*)b.D[l];
-    }
-    return HZ_OK;
 }
 
 template <class P>
@@ -355,7 +249,7 @@ extern "C" int no_net_create(const no_arch* a, const float* theta, void* stream,
         return HZ_ERR_ARG;
     }
     net->a = *a;
-    const size_t bytes = net->pk_total * (2 + 4 + 8) + net->bias_total * (4 + 8) + 5 * 256;
+    const size_t bytes = 2 * net->pk_total * (2 + 4 + 8) + net->bias_total * (4 + 8) + 8 * 256;
     if (hipMalloc(&net->block, bytes) != hipSuccess) {
         delete net;
         set_error("no_net_create: hipMalloc failed");
@@ -367,6 +261,9 @@ extern "C" int no_net_create(const no_arch* a, const float* theta, void* stream,
     net->w_f64 = c.take<double>(net->pk_total);
     net->b_f32 = c.take<float>(net->bias_total);
     net->b_f64 = c.take<double>(net->bias_total);
+    net->wt_bf = c.take<bf16_t>(net->pk_total);
+    net->wt_f32 = c.take<float>(net->pk_total);
+    net->wt_f64 = c.take<double>(net->pk_total);
     hipStream_t s = (hipStream_t)stream;
     int rc = repack_all(net, theta, s);
     if (rc == HZ_OK && hipStreamSynchronize(s) != hipSuccess) rc = HZ_ERR_HIP;

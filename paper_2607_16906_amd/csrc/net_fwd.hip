@@ -18,7 +18,7 @@ __global__ __launch_bounds__(CT) void k_conv3(const typename P::T* __restrict__ 
                                               const typename P::Acc* __restrict__ bias,
                                               typename P::T* __restrict__ y, int cout_p,
                                               typename P::T* __restrict__ ypool, int H, int W, int relu, int ck,
-                                              const int* __restrict__ skip) {
+                                              const int* __restrict__ skip, Conv3Out ex) {
     using T = typename P::T;
     using Acc = typename P::Acc;
     using AccV = typename P::AccV;
@@ -102,18 +102,26 @@ __global__ __launch_bounds__(CT) void k_conv3(const typename P::T* __restrict__ 
     }
 
     // epilogue: register r of a lane holds output channel co0 + 16 cb + row_of(lg, r) of pixel
-    // (ty0 + 2 wv + pb, tx0 + lr)
-    T* ys = y + (int64_t)bz * plane * cout_p;
+    // (ty0 + 2 wv + pb, tx0 + lr). Channels below ex.split go to y (ex.split channels per pixel),
+    // the others to ex.y1_; ex.mask0_ / ex.mask1_ (same layouts) zero the entries whose mask is <= 0.
+    const int split = ex.split > 0 ? ex.split : cout_p;
+    const bool second = co0 >= split;
+    const int cst = second ? cout_p - split : split;          // channels per pixel of this output
+    T* ys = (second ? (T*)ex.y1_ : y) + (int64_t)bz * plane * cst;
+    const T* ms = (const T*)(second ? ex.mask1_ : ex.mask0_);
+    if (ms) ms += (int64_t)bz * plane * cst;
+    const int cbase = second ? co0 - split : co0;
     const int gx = tx0 + lr;
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
         const int co = co0 + cb * 16;
+        const int cl = cbase + cb * 16;
         Acc v[2][4];
 #pragma unroll
         for (int pb = 0; pb < 2; ++pb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                Acc t = acc[pb][cb][r] + bias[co + P::row_of(lg, r)];
+                Acc t = acc[pb][cb][r] + (bias ? bias[co + P::row_of(lg, r)] : Acc(0));
                 if (relu) t = t > Acc(0) ? t : Acc(0);
                 v[pb][r] = t;
             }
@@ -121,9 +129,15 @@ __global__ __launch_bounds__(CT) void k_conv3(const typename P::T* __restrict__ 
         for (int pb = 0; pb < 2; ++pb) {
             const int gy = ty0 + 2 * wv + pb;
             if (gy < H && gx < W) {
-                T* dst = ys + ((int64_t)gy * W + gx) * cout_p + co;
+                const int64_t off = ((int64_t)gy * W + gx) * cst + cl;
+                T* dst = ys + off;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) dst[P::row_of(lg, r)] = P::cvt(v[pb][r]);
+                for (int r = 0; r < 4; ++r) {
+                    const int rr = P::row_of(lg, r);
+                    Acc t = v[pb][r];
+                    if (ms && !(P::val(ms[off + rr]) > Acc(0))) t = Acc(0);
+                    dst[rr] = P::cvt(t);
+                }
             }
         }
         if (POOL) {
@@ -244,7 +258,7 @@ static int chunk_for(int cin_p, int c0, int c1) {
 template <class P>
 int launch_conv3(const typename P::T* x0, int c0, const typename P::T* x1, int c1, const typename P::T* w,
                  const typename P::Acc* bias, typename P::T* y, int cout_p, typename P::T* ypool, int H, int W,
-                 int batch, bool relu, const int* skip, hipStream_t s) {
+                 int batch, bool relu, const int* skip, hipStream_t s, Conv3Out ex) {
     const int cin_p = c0 + c1;
     const int ck = chunk_for<P>(cin_p, c0, c1);
     constexpr int VE = 16 / sizeof(typename P::T);
@@ -252,11 +266,21 @@ int launch_conv3(const typename P::T* x0, int c0, const typename P::T* x1, int c
         set_error("conv3: unsupported channel / size combination");
         return HZ_ERR_ARG;
     }
-    const int tn = pick_tn(cout_p);
+    // widest channel tile that still gives the GPU enough blocks (256 CUs)
+    int tn = pick_tn(cout_p);
+    const int64_t tiles = (int64_t)((W + TW - 1) / TW) * ((H + TH - 1) / TH) * batch;
+    while (tn > 16 && tiles * (cout_p / tn) < 512) tn /= 2;
+    if (ex.split > 0) {
+        if (ex.split % 16 || ex.split >= cout_p || (ypool && ex.split)) {
+            set_error("conv3: bad output split");
+            return HZ_ERR_ARG;
+        }
+        while (ex.split % tn || (cout_p - ex.split) % tn) tn /= 2;
+    }
     dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH, (cout_p / tn) * batch);
 #define HZ_C3(TNV, PL)                                                                                  \
     hipLaunchKernelGGL((k_conv3<P, TNV, PL>), grid, dim3(CT), 0, s, x0, c0, x1, c1, w, bias, y, cout_p, \
-                       ypool, H, W, relu ? 1 : 0, ck, skip)
+                       ypool, H, W, relu ? 1 : 0, ck, skip, ex)
     if (ypool) {
         if (tn == 64) HZ_C3(64, true);
         else if (tn == 32) HZ_C3(32, true);
@@ -292,7 +316,7 @@ int launch_convT2(const typename P::T* x, int cin_p, const typename P::T* w, con
 
 #define HZ_INST(P)                                                                                              \
     template int launch_conv3<P>(const P::T*, int, const P::T*, int, const P::T*, const P::Acc*, P::T*, int,     \
-                                 P::T*, int, int, int, bool, const int*, hipStream_t);                         \
+                                 P::T*, int, int, int, bool, const int*, hipStream_t, Conv3Out);               \
     template int launch_convT2<P>(const P::T*, int, const P::T*, const P::Acc*, P::T*, int, int, int, int,       \
                                   const int*, hipStream_t);
 HZ_INST(PolBF16)

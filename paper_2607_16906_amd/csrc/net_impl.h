@@ -1,0 +1,140 @@
+// Forward-pass plumbing shared by inference (net.hip) and training (train.hip).
+#pragma once
+
+#include <vector>
+
+#include "net.h"
+#include "net_kernels.h"
+
+namespace hz {
+
+inline int round16(int c) { return (c + 15) / 16 * 16; }
+
+// X[y][x][0..7] = [Re v / s, Im v / s, (c / c_ref, sigma_x, sigma_y), 0...] on the grid, 0 in the padding.
+template <class P, typename C>
+__global__ void k_pack(const C* __restrict__ v, const double* __restrict__ sc, const double* __restrict__ cnd,
+                       const double* __restrict__ sigx, const double* __restrict__ sigy, int nxt, int nyt, int Hp,
+                       int Wp, int in_ch, typename P::T* __restrict__ X, const int* __restrict__ skip) {
+    using T = typename P::T;
+    if (skip && *skip) return;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)Hp * Wp) return;
+    const int yy = (int)(idx / Wp), xx = (int)(idx % Wp);
+    T out[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) out[c] = P::cvt(0);
+    if (yy < nyt && xx < nxt) {
+        const int64_t g = (int64_t)yy * nxt + xx;
+        const double is = sc[1];
+        const C a = v[g];
+        out[0] = P::cvt((typename P::Acc)((double)a.x * is));
+        out[1] = P::cvt((typename P::Acc)((double)a.y * is));
+        if (in_ch == 5) {
+            out[2] = P::cvt((typename P::Acc)cnd[g]);
+            out[3] = P::cvt((typename P::Acc)sigx[xx]);
+            out[4] = P::cvt((typename P::Acc)sigy[yy]);
+        }
+    }
+    T* dst = X + idx * 8;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) dst[c] = out[c];
+}
+
+
+// ------------------------------------------------------------------ forward
+
+struct FwdBufs {
+    void* X;
+    std::vector<void*> E, T1, T1d, P, U, D;   // T1d: decoder temporaries (alias T1 for inference)
+    double2* part;
+    double* sc;
+    size_t total;
+};
+
+template <class P>
+inline FwdBufs fwd_layout(const no_net* net, int Hp, int Wp, int batch, void* base, size_t cap,
+                          bool keep_all = false) {
+    using T = typename P::T;
+    FwdBufs b;
+    Carver c(base, cap);
+    const int lv = net->a.levels;
+    b.X = c.take<T>((size_t)batch * Hp * Wp * 8);
+    b.E.resize(lv);
+    b.T1.resize(lv);
+    b.T1d.resize(lv);
+    b.P.resize(lv);
+    b.U.resize(lv);
+    b.D.resize(lv);
+    for (int l = 0; l < lv; ++l) {
+        const size_t px = (size_t)batch * (Hp >> l) * (Wp >> l);
+        const int cs = round16(net->a.base << l);
+        b.E[l] = c.take<T>(px * cs);
+        b.T1[l] = c.take<T>(px * cs);
+        b.T1d[l] = keep_all ? c.take<T>(px * cs) : b.T1[l];
+        b.P[l] = l > 0 ? c.take<T>(px * round16(net->a.base << (l - 1))) : nullptr;
+        b.U[l] = l < lv - 1 ? c.take<T>(px * cs) : nullptr;
+        b.D[l] = l < lv - 1 ? c.take<T>(px * cs) : nullptr;
+    }
+    b.part = c.take<double2>(1024);
+    b.sc = c.take<double>(2);
+    b.total = c.off + 256;
+    return b;
+}
+
+template <class P>
+inline const typename P::T* packed_w(const no_net* net, const Layer& ly) {
+    if constexpr (sizeof(typename P::T) == 2) return net->w_bf + ly.pk_off;
+    else if constexpr (sizeof(typename P::T) == 4) return net->w_f32 + ly.pk_off;
+    else return net->w_f64 + ly.pk_off;
+}
+// data-gradient packs: 3x3 layers [tap'][cin_p][cout_p] with tap' = 8 - tap, transposed
+// convolutions [ab][cin_p][cout_p]
+template <class P>
+inline const typename P::T* packed_wt(const no_net* net, const Layer& ly) {
+    if constexpr (sizeof(typename P::T) == 2) return net->wt_bf + ly.pk_off;
+    else if constexpr (sizeof(typename P::T) == 4) return net->wt_f32 + ly.pk_off;
+    else return net->wt_f64 + ly.pk_off;
+}
+template <class P>
+inline const typename P::Acc* packed_b(const no_net* net, const Layer& ly) {
+    if constexpr (sizeof(typename P::Acc) == 4) return net->b_f32 + ly.bias_off;
+    else return net->b_f64 + ly.bias_off;
+}
+
+// Network body on a packed input X (batch samples), result D0 = decoder level-0 output.
+template <class P>
+inline int unet_body(const no_net* net, const FwdBufs& b, int Hp, int Wp, int batch, const int* skip, hipStream_t s) {
+    using T = typename P::T;
+    const int lv = net->a.levels;
+    const std::vector<Layer>& Ls = net->layers;
+    int li = 0;
+    for (int l = 0; l < lv; ++l) {
+        const int H = Hp >> l, W = Wp >> l;
+        const Layer& la = Ls[li++];
+        const Layer& lb = Ls[li++];
+        const T* in = l == 0 ? (const T*)b.X : (const T*)b.P[l];
+        HZ_TRY(launch_conv3<P>(in, la.cin_p, nullptr, 0, packed_w<P>(net, la), packed_b<P>(net, la), (T*)b.T1[l],
+                               la.cout_p, nullptr, H, W, batch, true, skip, s));
+        T* pool = l + 1 < lv ? (T*)b.P[l + 1] : nullptr;
+        HZ_TRY(launch_conv3<P>((const T*)b.T1[l], lb.cin_p, nullptr, 0, packed_w<P>(net, lb), packed_b<P>(net, lb),
+                               (T*)b.E[l], lb.cout_p, pool, H, W, batch, true, skip, s));
+    }
+    const T* Dn = (const T*)b.E[lv - 1];
+    for (int l = lv - 2; l >= 0; --l) {
+        const int H = Hp >> l, W = Wp >> l;
+        const Layer& lu = Ls[li++];
+        const Layer& la = Ls[li++];
+        const Layer& lb = Ls[li++];
+        HZ_TRY(launch_convT2<P>(Dn, lu.cin_p, packed_w<P>(net, lu), packed_b<P>(net, lu), (T*)b.U[l], lu.cout_p,
+                                H / 2, W / 2, batch, skip, s));
+        const int ce = lu.cout_p;
+        HZ_TRY(launch_conv3<P>((const T*)b.E[l], ce, (const T*)b.U[l], ce, packed_w<P>(net, la), packed_b<P>(net, la),
+                               (T*)b.T1d[l], la.cout_p, nullptr, H, W, batch, true, skip, s));
+        HZ_TRY(launch_conv3<P>((const T*)b.T1d[l], lb.cin_p, nullptr, 0, packed_w<P>(net, lb), packed_b<P>(net, lb),
+                               (T*)b.D[l], lb.cout_p, nullptr, H, W, batch, true, skip, s));
+        Dn = (const T*)b.D[l];
+    }
+    return HZ_OK;
+}
+
+}  // namespace hz

@@ -71,12 +71,22 @@ struct PolF64 {
     __device__ static int row_of(int lg, int r) { return lg + 4 * r; }
 };
 
+// Optional extras of a 3x3 convolution launch: a split of the output channels into two
+// tensors (channels [0, split) -> y, [split, cout) -> y1) and ReLU masks for either part
+// (an output entry is zeroed where the mask entry is <= 0). Used by the data gradient.
+struct Conv3Out {
+    int split = 0;
+    void* y1_ = nullptr;
+    const void* mask0_ = nullptr;
+    const void* mask1_ = nullptr;
+};
+
 // Host-side launch helpers (defined in net_fwd.hip), one per precision.
 // conv3: y = act(conv3x3(concat[x0, x1]) + b) (+ pooled copy); batch samples along grid z.
 template <class P>
 int launch_conv3(const typename P::T* x0, int c0, const typename P::T* x1, int c1, const typename P::T* w,
                  const typename P::Acc* bias, typename P::T* y, int cout_p, typename P::T* ypool, int H, int W,
-                 int batch, bool relu, const int* skip, hipStream_t s);
+                 int batch, bool relu, const int* skip, hipStream_t s, Conv3Out ex = Conv3Out());
 // convT2: y[2i+a][2j+b] = sum_c x[i][j][c] w[a][b][.][c] + b
 template <class P>
 int launch_convT2(const typename P::T* x, int cin_p, const typename P::T* w, const typename P::Acc* bias,

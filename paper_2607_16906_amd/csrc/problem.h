@@ -39,5 +39,7 @@ int launch_stencil(const hz_problem* p, bool fp64, bool adjoint, const void* x, 
 int launch_resid64(const hz_problem* p, const double2* b, const double2* x, double2* r,
                    double* part, const int* skip, hipStream_t s);
 int stencil_blocks(const hz_problem* p);
+// y = b - A x in FP32 (float2 [n]) with one ||y||^2 partial (FP64) per block.
+int launch_resid32(const hz_problem* p, const float2* b, const float2* x, float2* y, double* part, hipStream_t s);
 
 }  // namespace hz

@@ -207,6 +207,16 @@ int launch_resid64(const hz_problem* p, const double2* b, const double2* x, doub
     return HZ_OK;
 }
 
+int launch_resid32(const hz_problem* p, const float2* b, const float2* x, float2* y, double* part, hipStream_t s) {
+    StencilCoef c = stencil_coef(p, false, false);
+    hipLaunchKernelGGL((k_stencil<float, ST_RESID>), stencil_grid(p), dim3(ST_THREADS), 0, s, x, y, b,
+                       (const float*)c.k2, (const float2*)c.E, (const float2*)c.W, (const float2*)c.N,
+                       (const float2*)c.S, (const float2*)c.dx, (const float2*)c.dy, 0, p->nxt, p->nyt, part,
+                       (const int*)nullptr);
+    HZ_LAUNCH_CHECK();
+    return HZ_OK;
+}
+
 }  // namespace hz
 
 using namespace hz;

@@ -1,0 +1,785 @@
+// Training step of the neural operator (Sections 3.3-3.4, eq. (10)-(12)): the
+// physics-informed loss mean_b ||A_b N(r_b) - r_b|| / ||r_b|| (or its square), its
+// gradient by reverse mode through the adjoint stencil and the U-Net, and Adam.
+//
+// Reverse mode, with G(layer) = d loss / d(pre-activation of the layer):
+//   head:      g_out = coef_b s_b (A_b^H y_b) with y_b = r_b - A_b z_b and
+//              coef_b = -1 / (B ||y_b|| ||r_b||) (squared: -2 / (B ||r_b||^2));
+//              G(dec0b) = (g_out . W_head) masked by D0 > 0;
+//   3x3 conv:  dW[co][ci][tap] = sum_p G[p][co] x[p + tap][ci], db = sum_p G;
+//              d x = 3x3 convolution of G with the flipped, transposed weights (the forward
+//              MFMA kernel with the data-gradient pack), masked by the producer's ReLU;
+//   concat:    the data gradient splits into the skip part (E_l) and the up part (U_l);
+//   transposed conv: dW[ab][co][ci] = sum_i G[2i + ab][co] x[i][ci]; d x = 2x2 stride-2
+//              gather of G with the transposed weights (MFMA), masked by the input's ReLU;
+//   pool:      G(enc_{l-1}b) = (skip + unpool(d P_l) / 4) masked by E_{l-1} > 0.
+// Weight gradients accumulate in FP32 per pixel chunk and are summed over the chunks in a
+// fixed order (deterministic).
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "krylov.h"
+#include "net_impl.h"
+#include "problem.h"
+
+namespace hz {
+
+constexpr int TT = 256;
+
+// ------------------------------------------------------------------ pack / head (batched)
+
+// s_b = ||r_b|| / sqrt(n) and ||r_b|| from per-sample norm partials (one wavefront per sample).
+__global__ void k_sample_scales(const double2* part, int nblk, int64_t n, double* sc, double* nr) {
+    const int b = blockIdx.x;
+    double a = 0;
+    for (int q = threadIdx.x; q < nblk; q += 64) a += part[(int64_t)b * nblk + q].x;
+    a = wave_sum(a);
+    if (threadIdx.x == 0) {
+        const double s = sqrt(a / (double)n);
+        sc[2 * b] = s;
+        sc[2 * b + 1] = s > 0 ? 1.0 / s : 0.0;
+        nr[b] = sqrt(a);
+    }
+}
+
+// z_b = s_b (out_0 + i out_1) on the grid, out_k = sum_c D0[c] Wh[k][c] + bh[k].
+template <class P>
+__global__ void k_head_batched(const typename P::T* __restrict__ D, int cin_p, const typename P::T* __restrict__ wh,
+                               const typename P::Acc* __restrict__ bh, const double* __restrict__ sc, int nxt,
+                               int nyt, int Hp, int Wp, int B, float2* __restrict__ z) {
+    using Acc = typename P::Acc;
+    const int64_t n = (int64_t)nxt * nyt;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * B) return;
+    const int b = (int)(idx / n);
+    const int64_t g = idx - (int64_t)b * n;
+    const int yy = (int)(g / nxt), xx = (int)(g % nxt);
+    const typename P::T* d = D + (((int64_t)b * Hp + yy) * Wp + xx) * cin_p;
+    Acc o0 = bh[0], o1 = bh[1];
+    for (int c = 0; c < cin_p; ++c) {
+        const Acc dv = P::val(d[c]);
+        o0 += dv * P::val(wh[c]);
+        o1 += dv * P::val(wh[cin_p + c]);
+    }
+    const double s = sc[2 * b];
+    z[idx] = float2{(float)(s * (double)o0), (float)(s * (double)o1)};
+}
+
+// Per-sample loss from the partials of ||y_b||^2 (y_b = r_b - A_b z_b) and ||r_b||; the
+// head-gradient scale coef_b; the batch mean.
+__global__ void k_loss(const double* __restrict__ ypart, int nparts, const double* __restrict__ nr, int B, int squared,
+                       float* __restrict__ coef, float* __restrict__ loss, float* __restrict__ per_sample) {
+    __shared__ double ls[1024];
+    for (int b = threadIdx.x >> 6; b < B; b += blockDim.x >> 6) {
+        double a = 0;
+        for (int q = threadIdx.x & 63; q < nparts; q += 64) a += ypart[(int64_t)b * nparts + q];
+        a = wave_sum(a);
+        if ((threadIdx.x & 63) == 0) {
+            const double nq = sqrt(a), r = nr[b];
+            double l, cf;
+            if (squared) {
+                l = nq * nq / (r * r);
+                cf = -2.0 / ((double)B * r * r);
+            } else {
+                l = nq / r;
+                cf = nq > 0 ? -1.0 / ((double)B * nq * r) : 0.0;
+            }
+            ls[b] = l;
+            coef[b] = (float)cf;
+            if (per_sample) per_sample[b] = (float)l;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int b = 0; b < B; ++b) t += ls[b];
+        *loss = (float)(t / B);
+    }
+}
+
+// g_out at a padded pixel (0 off the grid).
+__device__ inline float2 head_grad(const float2* gz, const float* coef, const double* sc, int b, int yy, int xx,
+                                   int nxt, int nyt) {
+    if (yy >= nyt || xx >= nxt) return float2{0.f, 0.f};
+    const float2 a = gz[(int64_t)b * nxt * nyt + (int64_t)yy * nxt + xx];
+    const float f = coef[b] * (float)sc[2 * b];
+    return float2{f * a.x, f * a.y};
+}
+
+// G(dec0b)[p][c] = (g0 Wh[0][c] + g1 Wh[1][c]) masked by D0[p][c] > 0.
+template <class P>
+__global__ void k_head_dgrad(const float2* __restrict__ gz, const float* __restrict__ coef,
+                             const double* __restrict__ sc, const typename P::T* __restrict__ D0, int cin_p,
+                             const typename P::T* __restrict__ wh, int nxt, int nyt, int Hp, int Wp, int B,
+                             typename P::T* __restrict__ G) {
+    using Acc = typename P::Acc;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t np = (int64_t)Hp * Wp;
+    if (idx >= np * B * cin_p) return;
+    const int c = (int)(idx % cin_p);
+    const int64_t pp = idx / cin_p;
+    const int b = (int)(pp / np);
+    const int64_t q = pp - (int64_t)b * np;
+    const int yy = (int)(q / Wp), xx = (int)(q % Wp);
+    const float2 g = head_grad(gz, coef, sc, b, yy, xx, nxt, nyt);
+    Acc v = (Acc)g.x * P::val(wh[c]) + (Acc)g.y * P::val(wh[cin_p + c]);
+    if (!(P::val(D0[idx]) > Acc(0))) v = Acc(0);
+    G[idx] = P::cvt(v);
+}
+
+// Head weight / bias gradient partials: block z covers a slice of the padded pixels of all
+// samples; part[z][k][c] = sum g_k D0[c] (c < cin_p), part[z][2][k] = sum g_k.
+template <class P>
+__global__ void k_head_wgrad(const float2* __restrict__ gz, const float* __restrict__ coef,
+                             const double* __restrict__ sc, const typename P::T* __restrict__ D0, int cin_p, int nxt,
+                             int nyt, int Hp, int Wp, int B, int64_t per, float* __restrict__ part) {
+    const int64_t np = (int64_t)Hp * Wp * B;
+    const int64_t p0 = (int64_t)blockIdx.x * per, p1 = min(np, p0 + per);
+    const int lanes = TT / cin_p;                       // pixel lanes (cin_p divides 256)
+    const int c = threadIdx.x % cin_p, pl = threadIdx.x / cin_p;
+    float a0 = 0, a1 = 0, s0 = 0, s1 = 0;
+    for (int64_t p = p0 + pl; p < p1; p += lanes) {
+        const int b = (int)(p / ((int64_t)Hp * Wp));
+        const int64_t q = p - (int64_t)b * Hp * Wp;
+        const float2 g = head_grad(gz, coef, sc, b, (int)(q / Wp), (int)(q % Wp), nxt, nyt);
+        const float d = (float)P::val(D0[p * cin_p + c]);
+        a0 += g.x * d;
+        a1 += g.y * d;
+        s0 += g.x;
+        s1 += g.y;
+    }
+    __shared__ float red[TT][4];
+    red[threadIdx.x][0] = a0;
+    red[threadIdx.x][1] = a1;
+    red[threadIdx.x][2] = s0;
+    red[threadIdx.x][3] = s1;
+    __syncthreads();
+    if (threadIdx.x < cin_p) {
+        float t0 = 0, t1 = 0;
+        for (int l = 0; l < lanes; ++l) {
+            t0 += red[l * cin_p + threadIdx.x][0];
+            t1 += red[l * cin_p + threadIdx.x][1];
+        }
+        part[(int64_t)blockIdx.x * (2 * cin_p + 2) + threadIdx.x] = t0;
+        part[(int64_t)blockIdx.x * (2 * cin_p + 2) + cin_p + threadIdx.x] = t1;
+    }
+    if (threadIdx.x == 0) {
+        float t0 = 0, t1 = 0;
+        for (int l = 0; l < lanes; ++l) {   // every pixel lane saw each pixel once per channel 0
+            t0 += red[l * cin_p][2];
+            t1 += red[l * cin_p][3];
+        }
+        part[(int64_t)blockIdx.x * (2 * cin_p + 2) + 2 * cin_p] = t0;
+        part[(int64_t)blockIdx.x * (2 * cin_p + 2) + 2 * cin_p + 1] = t1;
+    }
+}
+
+__global__ void k_head_reduce(const float* __restrict__ part, int nchunk, int cin_p, Layer ly, float* __restrict__ grad) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nw = ly.cout * ly.cin;   // [2][cin]
+    if (t < nw) {
+        const int k = t / ly.cin, c = t % ly.cin;
+        float a = 0;
+        for (int z = 0; z < nchunk; ++z) a += part[(int64_t)z * (2 * cin_p + 2) + k * cin_p + c];
+        grad[ly.w_off + t] = a;
+    } else if (t < nw + 2) {
+        const int k = t - nw;
+        float a = 0;
+        for (int z = 0; z < nchunk; ++z) a += part[(int64_t)z * (2 * cin_p + 2) + 2 * cin_p + k];
+        grad[ly.b_off + k] = a;
+    }
+}
+
+// ------------------------------------------------------------------ weight gradients
+
+// 3x3: block (ci tile of 16, co tile of 16, chunk z) accumulates, over its 8 x 16 pixel tiles,
+// dW[co][ci][tap] into part[z][co][ci][tap] and (ci tile 0) db[co] into partb[z][co].
+template <class P>
+__global__ __launch_bounds__(TT) void k_wgrad3(const typename P::T* __restrict__ G, int cout_p,
+                                               const typename P::T* __restrict__ x0, int c0,
+                                               const typename P::T* __restrict__ x1, int c1, int H, int W,
+                                               int ntiles, int tpc, float* __restrict__ part,
+                                               float* __restrict__ partb) {
+    __shared__ float gs[128][17];
+    __shared__ float xs[180][17];
+    const int cin_p = c0 + c1;
+    const int ci0 = blockIdx.x * 16, co0 = blockIdx.y * 16;
+    const int z = blockIdx.z;
+    const int tco = threadIdx.x >> 4, tci = threadIdx.x & 15;
+    const int tx_n = (W + 15) / 16, ty_n = (H + 7) / 8;
+    const int per_img = tx_n * ty_n;
+    float acc[9], accb = 0;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = 0;
+    const int64_t plane = (int64_t)H * W;
+    const int t_end = min(ntiles, (z + 1) * tpc);
+    for (int tile = z * tpc; tile < t_end; ++tile) {
+        const int b = tile / per_img, r = tile - b * per_img;
+        const int ty0 = (r / tx_n) * 8, tx0 = (r % tx_n) * 16;
+        __syncthreads();
+        for (int v = threadIdx.x; v < 128 * 16; v += TT) {
+            const int px = v >> 4, c = v & 15;
+            const int gy = ty0 + (px >> 4), gx = tx0 + (px & 15);
+            float val = 0.f;
+            if (gy < H && gx < W) val = (float)P::val(G[((int64_t)b * plane + (int64_t)gy * W + gx) * cout_p + co0 + c]);
+            gs[px][c] = val;
+        }
+        for (int v = threadIdx.x; v < 180 * 16; v += TT) {
+            const int px = v >> 4, c = v & 15;
+            const int gy = ty0 + px / 18 - 1, gx = tx0 + px % 18 - 1;
+            const int ci = ci0 + c;
+            float val = 0.f;
+            if (gy >= 0 && gy < H && gx >= 0 && gx < W && ci < cin_p) {
+                const int64_t pix = (int64_t)b * plane + (int64_t)gy * W + gx;
+                val = (float)P::val(ci < c0 ? x0[pix * c0 + ci] : x1[pix * c1 + ci - c0]);
+            }
+            xs[px][c] = val;
+        }
+        __syncthreads();
+        for (int px = 0; px < 128; ++px) {
+            const float g = gs[px][tco];
+            const int py = px >> 4, pxx = px & 15;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) acc[t] += g * xs[(py + t / 3) * 18 + pxx + t % 3][tci];
+            accb += g;
+        }
+    }
+    const int co = co0 + tco, ci = ci0 + tci;
+    if (ci < cin_p) {
+        float* dst = part + (((int64_t)z * cout_p + co) * cin_p + ci) * 9;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) dst[t] = acc[t];
+    }
+    if (blockIdx.x == 0 && tci == 0) partb[(int64_t)z * cout_p + co] = accb;
+}
+
+// Transposed 2x2: dW[ab][co][ci] = sum_i G[2i + ab][co] x[i][ci]; block: ci tile, co tile, chunk of
+// 8 x 8 input tiles.
+template <class P>
+__global__ __launch_bounds__(TT) void k_wgradT(const typename P::T* __restrict__ G, int cout_p,
+                                               const typename P::T* __restrict__ x, int cin_p, int H, int W,
+                                               int ntiles, int tpc, float* __restrict__ part,
+                                               float* __restrict__ partb) {
+    __shared__ float gs[64][4][17];
+    __shared__ float xs[64][17];
+    const int ci0 = blockIdx.x * 16, co0 = blockIdx.y * 16;
+    const int z = blockIdx.z;
+    const int tco = threadIdx.x >> 4, tci = threadIdx.x & 15;
+    const int tx_n = (W + 7) / 8, ty_n = (H + 7) / 8;
+    const int per_img = tx_n * ty_n;
+    float acc[4] = {0, 0, 0, 0}, accb = 0;
+    const int64_t plane = (int64_t)H * W;
+    const int t_end = min(ntiles, (z + 1) * tpc);
+    for (int tile = z * tpc; tile < t_end; ++tile) {
+        const int b = tile / per_img, r = tile - b * per_img;
+        const int ty0 = (r / tx_n) * 8, tx0 = (r % tx_n) * 8;
+        __syncthreads();
+        for (int v = threadIdx.x; v < 64 * 4 * 16; v += TT) {
+            const int c = v & 15, ab = (v >> 4) & 3, px = v >> 6;
+            const int iy = ty0 + (px >> 3), ix = tx0 + (px & 7);
+            float val = 0.f;
+            if (iy < H && ix < W) {
+                const int oy = 2 * iy + (ab >> 1), ox = 2 * ix + (ab & 1);
+                val = (float)P::val(G[((int64_t)b * 4 * plane + (int64_t)oy * 2 * W + ox) * cout_p + co0 + c]);
+            }
+            gs[px][ab][c] = val;
+        }
+        for (int v = threadIdx.x; v < 64 * 16; v += TT) {
+            const int c = v & 15, px = v >> 4;
+            const int iy = ty0 + (px >> 3), ix = tx0 + (px & 7);
+            float val = 0.f;
+            if (iy < H && ix < W) val = (float)P::val(x[((int64_t)b * plane + (int64_t)iy * W + ix) * cin_p + ci0 + c]);
+            xs[px][c] = val;
+        }
+        __syncthreads();
+        for (int px = 0; px < 64; ++px) {
+            const float xv = xs[px][tci];
+#pragma unroll
+            for (int ab = 0; ab < 4; ++ab) acc[ab] += gs[px][ab][tco] * xv;
+            accb += gs[px][0][tco] + gs[px][1][tco] + gs[px][2][tco] + gs[px][3][tco];
+        }
+    }
+    const int co = co0 + tco, ci = ci0 + tci;
+    float* dst = part + (((int64_t)z * cout_p + co) * cin_p + ci) * 4;
+#pragma unroll
+    for (int ab = 0; ab < 4; ++ab) dst[ab] = acc[ab];
+    if (blockIdx.x == 0 && tci == 0) partb[(int64_t)z * cout_p + co] = accb;
+}
+
+// Sum the chunk partials of one layer into the flat FP32 gradient (logical channels).
+__global__ void k_wgrad_reduce(const float* __restrict__ part, const float* __restrict__ partb, int nchunk,
+                               Layer ly, float* __restrict__ grad) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int taps = ly.kind == L_CONV3 ? 9 : 4;
+    const int64_t nw = (int64_t)taps * ly.cin * ly.cout;
+    if (t < nw) {
+        int co, ci, tap;
+        if (ly.kind == L_CONV3) {         // flat [co][ci][tap]
+            tap = (int)(t % 9);
+            ci = (int)((t / 9) % ly.cin);
+            co = (int)(t / (9 * ly.cin));
+        } else {                          // flat [ci][co][ab]
+            tap = (int)(t % 4);
+            co = (int)((t / 4) % ly.cout);
+            ci = (int)(t / (4 * ly.cout));
+        }
+        int cis = ci;                     // stored channel of a concatenated input
+        if (ly.cat_cp > 0 && ci >= ly.cat_c) cis = ly.cat_cp + (ci - ly.cat_c);
+        float a = 0;
+        for (int z = 0; z < nchunk; ++z) a += part[(((int64_t)z * ly.cout_p + co) * ly.cin_p + cis) * taps + tap];
+        grad[ly.w_off + t] = a;
+    } else if (t < nw + ly.cout) {
+        const int co = (int)(t - nw);
+        float a = 0;
+        for (int z = 0; z < nchunk; ++z) a += partb[(int64_t)z * ly.cout_p + co];
+        grad[ly.b_off + co] = a;
+    }
+}
+
+// ------------------------------------------------------------------ data gradients
+
+// Transposed-conv data gradient: gx[i][ci] = sum_{ab, co} G[2i + ab][co] Wt[ab][ci][co], masked by
+// x[i][ci] > 0. Block: 64 input pixels of one row, TN input channels; K = (ab, co) chunks.
+template <class P, int TN>
+__global__ __launch_bounds__(TT) void k_convT2_dgrad(const typename P::T* __restrict__ G, int cout_p,
+                                                     const typename P::T* __restrict__ wt,
+                                                     const typename P::T* __restrict__ xmask,
+                                                     typename P::T* __restrict__ gx, int cin_p, int H, int W, int ck) {
+    using T = typename P::T;
+    using AccV = typename P::AccV;
+    using Frag = typename P::Frag;
+    constexpr int PS = P::CK + 16 / (int)sizeof(T);
+    constexpr int VE = 16 / sizeof(T);
+    constexpr int NCB = TN / 16;
+    __shared__ __attribute__((aligned(16))) T gl[64 * 4 * PS];
+    __shared__ __attribute__((aligned(16))) T wl[4 * TN * PS];
+    const int ncb_tot = cin_p / TN;
+    const int bz = blockIdx.z / ncb_tot;
+    const int ci0 = (blockIdx.z - bz * ncb_tot) * TN;
+    const int iy = blockIdx.y, ix0 = blockIdx.x * 64;
+    const int64_t plane = (int64_t)H * W;
+    const T* gs = G + (int64_t)bz * plane * 4 * cout_p;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    AccV acc[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[cb][r] = 0;
+    const int vpp = ck / VE;
+    const int groups = ck / P::GW;
+    const int steps = (groups + 3) / 4;
+    for (int k0 = 0; k0 < cout_p; k0 += ck) {
+        __syncthreads();
+        for (int v = threadIdx.x; v < 64 * 4 * vpp; v += TT) {
+            const int part = v % vpp, ab = (v / vpp) & 3, px = v / (4 * vpp);
+            const int ix = ix0 + px;
+            uint4 val = uint4{0, 0, 0, 0};
+            if (ix < W) {
+                const int oy = 2 * iy + (ab >> 1), ox = 2 * ix + (ab & 1);
+                val = *(const uint4*)(gs + ((int64_t)oy * 2 * W + ox) * cout_p + k0 + part * VE);
+            }
+            *(uint4*)&gl[(px * 4 + ab) * PS + part * VE] = val;
+        }
+        for (int v = threadIdx.x; v < 4 * TN * vpp; v += TT) {
+            const int part = v % vpp, row = v / vpp;
+            const int ab = row / TN, ci = row - ab * TN;
+            *(uint4*)&wl[row * PS + part * VE] =
+                *(const uint4*)(wt + ((int64_t)ab * cin_p + ci0 + ci) * cout_p + k0 + part * VE);
+        }
+        __syncthreads();
+        for (int st = 0; st < steps; ++st) {
+            const int cg = 4 * st + lg;
+#pragma unroll
+            for (int ab = 0; ab < 4; ++ab) {
+                const Frag b = cg < groups ? P::load(&gl[((wv * 16 + lr) * 4 + ab) * PS + cg * P::GW]) : P::zero();
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) {
+                    const Frag a = cg < groups ? P::load(&wl[(ab * TN + cb * 16 + lr) * PS + cg * P::GW]) : P::zero();
+                    acc[cb] = P::mma(a, b, acc[cb]);
+                }
+            }
+        }
+    }
+    const int ix = ix0 + wv * 16 + lr;
+    if (ix >= W) return;
+    const int64_t pix = (int64_t)bz * plane + (int64_t)iy * W + ix;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int ci = ci0 + cb * 16 + P::row_of(lg, r);
+            typename P::Acc v = acc[cb][r];
+            if (!(P::val(xmask[pix * cin_p + ci]) > typename P::Acc(0))) v = 0;
+            gx[pix * cin_p + ci] = P::cvt(v);
+        }
+}
+
+// G(enc_{l-1}b) = (skip + unpool(dP) / 4) masked by E > 0, in place in skip. E, skip: [B][H][W][c];
+// dP: [B][H/2][W/2][c].
+template <class P>
+__global__ void k_pool_bwd(typename P::T* __restrict__ skip, const typename P::T* __restrict__ dP,
+                           const typename P::T* __restrict__ E, int H, int W, int c, int64_t total) {
+    using Acc = typename P::Acc;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    const int ch = (int)(idx % c);
+    const int64_t pp = idx / c;
+    const int64_t plane = (int64_t)H * W;
+    const int b = (int)(pp / plane);
+    const int64_t q = pp - (int64_t)b * plane;
+    const int yy = (int)(q / W), xx = (int)(q % W);
+    const int64_t pi = ((int64_t)b * (plane / 4) + (int64_t)(yy / 2) * (W / 2) + xx / 2) * c + ch;
+    Acc v = P::val(skip[idx]) + Acc(0.25) * P::val(dP[pi]);
+    if (!(P::val(E[idx]) > Acc(0))) v = Acc(0);
+    skip[idx] = P::cvt(v);
+}
+
+// ------------------------------------------------------------------ workspace
+
+template <class P>
+struct TrainBufs {
+    using T = typename P::T;
+    FwdBufs f;                       // forward activations (kept for the backward)
+    std::vector<T*> gA, gB, gU, gP;  // activation gradients per level
+    float2 *z, *y, *gz;              // [B][n]
+    double2* rpart;                  // [B][nblk] ||r_b||^2 partials
+    double* ypart;                   // [B][stencil blocks] ||y_b||^2 partials
+    double *sc, *nr;                 // [B][2], [B]
+    float* coef;                     // [B]
+    float *wpart, *wpartb;           // weight-gradient chunk partials
+    size_t total;
+};
+
+constexpr int WCHUNKS = 64;
+
+template <class P>
+static TrainBufs<P> train_layout(const no_net* net, const hz_problem* p, int B, void* base, size_t cap) {
+    using T = typename P::T;
+    TrainBufs<P> t;
+    int Hp, Wp;
+    net_padded_dims(net, p, &Hp, &Wp);
+    Carver c(base, cap);
+    // forward activations: carve with the same rules as fwd_layout, then continue after them
+    t.f = fwd_layout<P>(net, Hp, Wp, B, base, cap, true);
+    c.off = t.f.total;
+    const int lv = net->a.levels;
+    t.gA.resize(lv);
+    t.gB.resize(lv);
+    t.gU.resize(lv);
+    t.gP.resize(lv);
+    for (int l = 0; l < lv; ++l) {
+        const size_t px = (size_t)B * (Hp >> l) * (Wp >> l);
+        const int cs = round16(net->a.base << l);
+        t.gA[l] = c.take<T>(px * cs);
+        t.gB[l] = c.take<T>(px * cs);
+        t.gU[l] = l < lv - 1 ? c.take<T>(px * cs) : nullptr;
+        t.gP[l] = l > 0 ? c.take<T>(px * round16(net->a.base << (l - 1))) : nullptr;
+    }
+    const int64_t n = p->n;
+    t.z = c.take<float2>((size_t)B * n);
+    t.y = c.take<float2>((size_t)B * n);
+    t.gz = c.take<float2>((size_t)B * n);
+    Split sp = krylov_split(n);
+    t.rpart = c.take<double2>((size_t)B * sp.nblk);
+    t.ypart = c.take<double>((size_t)B * stencil_blocks(p));
+    t.sc = c.take<double>(2 * (size_t)B);
+    t.nr = c.take<double>(B);
+    t.coef = c.take<float>(B);
+    size_t wmax = 0, bmax = 0;
+    for (const Layer& ly : net->layers) {
+        const int taps = ly.kind == L_CONV3 ? 9 : (ly.kind == L_CONVT2 ? 4 : 1);
+        wmax = std::max(wmax, (size_t)WCHUNKS * taps * ly.cout_p * ly.cin_p);
+        bmax = std::max(bmax, (size_t)WCHUNKS * (ly.cout_p + 2 * ly.cin_p + 2));
+    }
+    t.wpart = c.take<float>(wmax);
+    t.wpartb = c.take<float>(bmax);
+    t.total = c.off + 256;
+    return t;
+}
+
+// ------------------------------------------------------------------ launch helpers
+
+template <class P>
+static int wgrad_conv3(const Layer& ly, const typename P::T* G, const typename P::T* x0, int c0,
+                       const typename P::T* x1, int c1, int H, int W, int B, TrainBufs<P>& t, float* grad,
+                       hipStream_t s) {
+    const int ntiles = ((W + 15) / 16) * ((H + 7) / 8) * B;
+    const int tpc = (ntiles + WCHUNKS - 1) / WCHUNKS;
+    const int nchunk = (ntiles + tpc - 1) / tpc;
+    dim3 grid((ly.cin_p + 15) / 16, ly.cout_p / 16, nchunk);
+    hipLaunchKernelGGL(k_wgrad3<P>, grid, dim3(TT), 0, s, G, ly.cout_p, x0, c0, x1, c1, H, W, ntiles, tpc, t.wpart,
+                       t.wpartb);
+    HZ_LAUNCH_CHECK();
+    const int64_t nout = (int64_t)9 * ly.cin * ly.cout + ly.cout;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, t.wpart, t.wpartb,
+                       nchunk, ly, grad);
+    HZ_LAUNCH_CHECK();
+    return HZ_OK;
+}
+
+template <class P>
+static int wgrad_convT(const Layer& ly, const typename P::T* G, const typename P::T* x, int H, int W, int B,
+                       TrainBufs<P>& t, float* grad, hipStream_t s) {
+    const int ntiles = ((W + 7) / 8) * ((H + 7) / 8) * B;
+    const int tpc = (ntiles + WCHUNKS - 1) / WCHUNKS;
+    const int nchunk = (ntiles + tpc - 1) / tpc;
+    dim3 grid(ly.cin_p / 16, ly.cout_p / 16, nchunk);
+    hipLaunchKernelGGL(k_wgradT<P>, grid, dim3(TT), 0, s, G, ly.cout_p, x, ly.cin_p, H, W, ntiles, tpc, t.wpart,
+                       t.wpartb);
+    HZ_LAUNCH_CHECK();
+    const int64_t nout = (int64_t)4 * ly.cin * ly.cout + ly.cout;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, t.wpart, t.wpartb,
+                       nchunk, ly, grad);
+    HZ_LAUNCH_CHECK();
+    return HZ_OK;
+}
+
+// data gradient of a 3x3 layer: y0 (channels [0, split) or all) and y1 (rest), masks optional
+template <class P>
+static int dgrad_conv3(const no_net* net, const Layer& ly, const typename P::T* G, int H, int W, int B,
+                       typename P::T* y0, typename P::T* y1, const typename P::T* mask0, const typename P::T* mask1,
+                       hipStream_t s) {
+    Conv3Out ex;
+    ex.split = ly.cat_cp;
+    ex.y1_ = y1;
+    ex.mask0_ = mask0;
+    ex.mask1_ = mask1;
+    // output channels of the data gradient = stored input channels of the layer
+    return launch_conv3<P>(G, ly.cout_p, nullptr, 0, packed_wt<P>(net, ly), nullptr, y0, ly.cin_p, nullptr, H, W, B,
+                           false, nullptr, s, ex);
+}
+
+template <class P>
+static int dgrad_convT(const no_net* net, const Layer& ly, const typename P::T* G, const typename P::T* xmask,
+                       typename P::T* gx, int H, int W, int B, hipStream_t s) {
+    const int ck = std::min(P::CK, ly.cout_p);
+    const int tn = ly.cin_p % 32 == 0 ? 32 : 16;
+    dim3 grid((W + 63) / 64, H, (ly.cin_p / tn) * B);
+    if (tn == 32)
+        hipLaunchKernelGGL((k_convT2_dgrad<P, 32>), grid, dim3(TT), 0, s, G, ly.cout_p, packed_wt<P>(net, ly), xmask,
+                           gx, ly.cin_p, H, W, ck);
+    else
+        hipLaunchKernelGGL((k_convT2_dgrad<P, 16>), grid, dim3(TT), 0, s, G, ly.cout_p, packed_wt<P>(net, ly), xmask,
+                           gx, ly.cin_p, H, W, ck);
+    HZ_LAUNCH_CHECK();
+    return HZ_OK;
+}
+
+// ------------------------------------------------------------------ loss + backward
+
+template <class P>
+static int loss_backward_impl(const no_net* net, int B, const hz_problem* const* probs, const float2* r, int squared,
+                              float* loss, float* per_sample, float* grad, void* ws, size_t ws_bytes, hipStream_t s) {
+    using T = typename P::T;
+    const hz_problem* p0 = probs[0];
+    TrainBufs<P> t = train_layout<P>(net, p0, B, ws, ws_bytes);
+    if (t.total > ws_bytes) {
+        set_error("no_loss_backward: workspace too small");
+        return HZ_ERR_WORKSPACE;
+    }
+    int Hp, Wp;
+    net_padded_dims(net, p0, &Hp, &Wp);
+    const int64_t n = p0->n;
+    const int lv = net->a.levels;
+    const std::vector<Layer>& Ls = net->layers;
+    Split sp = krylov_split(n);
+    // scales s_b and ||r_b||
+    for (int b = 0; b < B; ++b)
+        HZ_TRY(launch_norm_partials(false, r + (int64_t)b * n, n, sp, t.rpart + (int64_t)b * sp.nblk, 1, 0, nullptr, s));
+    hipLaunchKernelGGL(k_sample_scales, dim3(B), dim3(64), 0, s, t.rpart, sp.nblk, n, t.sc, t.nr);
+    HZ_LAUNCH_CHECK();
+    // pack every sample with its own velocity channel
+    const unsigned gp = (unsigned)(((int64_t)Hp * Wp + 255) / 256);
+    for (int b = 0; b < B; ++b) {
+        const hz_problem* pb = probs[b];
+        hipLaunchKernelGGL((k_pack<P, float2>), dim3(gp), dim3(256), 0, s, r + (int64_t)b * n, t.sc + 2 * b, pb->cnd,
+                           pb->sigx, pb->sigy, pb->nxt, pb->nyt, Hp, Wp, net->a.in_ch,
+                           (T*)t.f.X + (int64_t)b * Hp * Wp * 8, (const int*)nullptr);
+        HZ_LAUNCH_CHECK();
+    }
+    HZ_TRY(unet_body<P>(net, t.f, Hp, Wp, B, nullptr, s));
+    const Layer& lh = Ls.back();
+    const T* D0 = lv > 1 ? (const T*)t.f.D[0] : (const T*)t.f.E[0];
+    {
+        const int64_t tot = (int64_t)B * n;
+        hipLaunchKernelGGL(k_head_batched<P>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, D0, lh.cin_p,
+                           packed_w<P>(net, lh), packed_b<P>(net, lh), t.sc, p0->nxt, p0->nyt, Hp, Wp, B, t.z);
+        HZ_LAUNCH_CHECK();
+    }
+    // y_b = r_b - A_b z_b with ||y_b||^2 partials, then A_b^H y_b
+    const int nst = stencil_blocks(p0);
+    for (int b = 0; b < B; ++b) {
+        HZ_TRY(launch_resid32(probs[b], r + (int64_t)b * n, t.z + (int64_t)b * n, t.y + (int64_t)b * n,
+                              t.ypart + (int64_t)b * nst, s));
+        HZ_TRY(launch_stencil(probs[b], false, true, t.y + (int64_t)b * n, t.gz + (int64_t)b * n, s));
+    }
+    hipLaunchKernelGGL(k_loss, dim3(1), dim3(1024), 0, s, t.ypart, nst, t.nr, B, squared, t.coef, loss, per_sample);
+    HZ_LAUNCH_CHECK();
+
+    // ---- head
+    {
+        const int cs0 = lh.cin_p;
+        const int64_t tot = (int64_t)B * Hp * Wp * cs0;
+        T* G0 = t.gB[0];
+        hipLaunchKernelGGL(k_head_dgrad<P>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, t.gz, t.coef, t.sc,
+                           D0, cs0, packed_w<P>(net, lh), p0->nxt, p0->nyt, Hp, Wp, B, G0);
+        HZ_LAUNCH_CHECK();
+        const int64_t np = (int64_t)B * Hp * Wp;
+        const int64_t per = (np + WCHUNKS - 1) / WCHUNKS;
+        const int nchunk = (int)((np + per - 1) / per);
+        hipLaunchKernelGGL(k_head_wgrad<P>, dim3(nchunk), dim3(TT), 0, s, t.gz, t.coef, t.sc, D0, cs0, p0->nxt,
+                           p0->nyt, Hp, Wp, B, per, t.wpartb);
+        HZ_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_head_reduce, dim3(1), dim3(256), 0, s, t.wpartb, nchunk, cs0, lh, grad);
+        HZ_LAUNCH_CHECK();
+    }
+    // layer indices in the flat order
+    std::vector<int> enc_a(lv), enc_b(lv), up(lv, -1), dec_a(lv, -1), dec_b(lv, -1);
+    {
+        int li = 0;
+        for (int l = 0; l < lv; ++l) {
+            enc_a[l] = li++;
+            enc_b[l] = li++;
+        }
+        for (int l = lv - 2; l >= 0; --l) {
+            up[l] = li++;
+            dec_a[l] = li++;
+            dec_b[l] = li++;
+        }
+    }
+    // ---- decoder, level 0 upward; G of the current decoder-b layer is in gB[l]
+    for (int l = 0; l <= lv - 2; ++l) {
+        const int H = Hp >> l, W = Wp >> l;
+        const Layer& lb = Ls[dec_b[l]];
+        const Layer& la = Ls[dec_a[l]];
+        const Layer& lu = Ls[up[l]];
+        const T* A1 = (const T*)t.f.T1d[l];
+        HZ_TRY(wgrad_conv3<P>(lb, t.gB[l], A1, lb.cin_p, nullptr, 0, H, W, B, t, grad, s));
+        HZ_TRY(dgrad_conv3<P>(net, lb, t.gB[l], H, W, B, t.gA[l], nullptr, A1, nullptr, s));
+        HZ_TRY(wgrad_conv3<P>(la, t.gA[l], (const T*)t.f.E[l], la.cat_cp, (const T*)t.f.U[l], la.cin_p - la.cat_cp,
+                              H, W, B, t, grad, s));
+        // skip part (unmasked, completed by the pooling path) -> gB[l]; up part -> gU[l]
+        HZ_TRY(dgrad_conv3<P>(net, la, t.gA[l], H, W, B, t.gB[l], t.gU[l], nullptr, nullptr, s));
+        const T* Dn = l + 1 == lv - 1 ? (const T*)t.f.E[l + 1] : (const T*)t.f.D[l + 1];
+        HZ_TRY(wgrad_convT<P>(lu, t.gU[l], Dn, H / 2, W / 2, B, t, grad, s));
+        HZ_TRY(dgrad_convT<P>(net, lu, t.gU[l], Dn, t.gB[l + 1], H / 2, W / 2, B, s));
+    }
+    // ---- encoder, deepest level first; G(enc_lb) is in gB[l]
+    for (int l = lv - 1; l >= 0; --l) {
+        const int H = Hp >> l, W = Wp >> l;
+        const Layer& lb = Ls[enc_b[l]];
+        const Layer& la = Ls[enc_a[l]];
+        const T* A1 = (const T*)t.f.T1[l];
+        const T* in = l == 0 ? (const T*)t.f.X : (const T*)t.f.P[l];
+        HZ_TRY(wgrad_conv3<P>(lb, t.gB[l], A1, lb.cin_p, nullptr, 0, H, W, B, t, grad, s));
+        HZ_TRY(dgrad_conv3<P>(net, lb, t.gB[l], H, W, B, t.gA[l], nullptr, A1, nullptr, s));
+        HZ_TRY(wgrad_conv3<P>(la, t.gA[l], in, la.cin_p, nullptr, 0, H, W, B, t, grad, s));
+        if (l > 0) {
+            HZ_TRY(dgrad_conv3<P>(net, la, t.gA[l], H, W, B, t.gP[l], nullptr, nullptr, nullptr, s));
+            const int Hu = Hp >> (l - 1), Wu = Wp >> (l - 1);
+            const int c = Ls[enc_b[l - 1]].cout_p;
+            const int64_t tot = (int64_t)B * Hu * Wu * c;
+            hipLaunchKernelGGL(k_pool_bwd<P>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, t.gB[l - 1],
+                               (const T*)t.gP[l], (const T*)t.f.E[l - 1], Hu, Wu, c, tot);
+            HZ_LAUNCH_CHECK();
+        }
+    }
+    return HZ_OK;
+}
+
+// ------------------------------------------------------------------ Adam
+
+__global__ void k_sqnorm_part(const float* __restrict__ g, int64_t n, double* __restrict__ part) {
+    double a = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        a += (double)g[i] * g[i];
+    __shared__ double red[4];
+    a = wave_sum(a);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_adam(float* __restrict__ th, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, int64_t n, const double* __restrict__ part, int nparts, int step,
+                       float lr, float b1, float b2, float eps, float clip) {
+    __shared__ double scale;
+    if (threadIdx.x == 0) {
+        double a = 0;
+        for (int q = 0; q < nparts; ++q) a += part[q];
+        const double nrm = sqrt(a);
+        scale = (clip > 0 && nrm > clip) ? clip / nrm : 1.0;
+    }
+    __syncthreads();
+    const float sc = (float)scale;
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i] * sc;
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+constexpr int ADAM_BLOCKS = 512;
+
+}  // namespace hz
+
+using namespace hz;
+
+extern "C" size_t no_train_workspace_size(const no_net* net, const hz_problem* p, int batch, no_prec prec) {
+    clear_error();
+    if (!net || !p || batch < 1) return 0;
+    if (prec == NO_BF16) return train_layout<PolBF16>(net, p, batch, nullptr, 0).total;
+    if (prec == NO_FP32) return train_layout<PolF32>(net, p, batch, nullptr, 0).total;
+    return 0;
+}
+
+extern "C" int no_loss_backward(const no_net* net, int batch, const hz_problem* const* problems, const void* r,
+                                int squared, no_prec prec, float* loss, float* per_sample, float* grad, void* ws,
+                                size_t ws_bytes, void* stream) {
+    clear_error();
+    HZ_CHECK_ARG(net && problems && r && loss && grad && ws, "no_loss_backward: NULL argument");
+    HZ_CHECK_ARG(batch >= 1 && batch <= 1024, "no_loss_backward: batch must be in [1, 1024]");
+    HZ_CHECK_ARG(prec == NO_BF16 || prec == NO_FP32, "no_loss_backward: precision must be NO_BF16 or NO_FP32");
+    for (int b = 0; b < batch; ++b) {
+        HZ_CHECK_ARG(problems[b], "no_loss_backward: NULL problem");
+        HZ_CHECK_ARG(problems[b]->nxt == problems[0]->nxt && problems[b]->nyt == problems[0]->nyt &&
+                         problems[b]->g.npml == problems[0]->g.npml,
+                     "no_loss_backward: every problem of a batch must have the same grid and PML");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == NO_BF16)
+        return loss_backward_impl<PolBF16>(net, batch, problems, (const float2*)r, squared, loss, per_sample, grad, ws,
+                                           ws_bytes, s);
+    return loss_backward_impl<PolF32>(net, batch, problems, (const float2*)r, squared, loss, per_sample, grad, ws,
+                                      ws_bytes, s);
+}
+
+extern "C" size_t no_adam_workspace_size(const no_net* net) {
+    (void)net;
+    return ADAM_BLOCKS * sizeof(double) + 256;
+}
+
+extern "C" int no_adam_step(no_net* net, float* theta, float* m, float* v, const float* grad, int step, float lr,
+                            float b1, float b2, float eps, float clip, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    HZ_CHECK_ARG(net && theta && m && v && grad && ws, "no_adam_step: NULL argument");
+    HZ_CHECK_ARG(step >= 1 && lr > 0 && b1 >= 0 && b1 < 1 && b2 >= 0 && b2 < 1 && eps > 0,
+                 "no_adam_step: bad hyper-parameters");
+    if (ws_bytes < no_adam_workspace_size(net)) {
+        set_error("no_adam_step: workspace too small");
+        return HZ_ERR_WORKSPACE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    double* part = (double*)ws;
+    hipLaunchKernelGGL(k_sqnorm_part, dim3(ADAM_BLOCKS), dim3(256), 0, s, grad, net->nparam, part);
+    hipLaunchKernelGGL(k_adam, dim3(ADAM_BLOCKS), dim3(256), 0, s, theta, m, v, grad, net->nparam, part, ADAM_BLOCKS,
+                       step, lr, b1, b2, eps, clip);
+    HZ_LAUNCH_CHECK();
+    return no_net_set_weights(net, theta, stream);
+}

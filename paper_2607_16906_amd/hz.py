@@ -220,6 +220,69 @@ def param_count(levels: int, base: int, in_ch: int) -> int:
     return int(n)
 
 
+def loss_backward(net: Net, problems, r, *, squared: bool = False, prec: str = "bf16", workspace=None):
+    """Physics-informed loss and its parameter gradient (no_loss_backward).
+
+    problems: list of B Problems of one grid size; r: [B, n] complex64 device tensor.
+    Returns (loss [1] float32, per-sample losses [B] float32, grad [nparam] float32).
+    """
+    torch = _torch()
+    lib = load_library()
+    B = len(problems)
+    r = r.to(torch.complex64).contiguous()
+    if r.numel() != B * problems[0].n:
+        raise ValueError("r must hold batch x n entries")
+    ptrs = (ct.c_void_p * B)(*[p.handle for p in problems])
+    nb = lib.no_train_workspace_size(net.handle, problems[0].handle, B, PREC[prec])
+    ws = workspace if workspace is not None and workspace.numel() >= nb else _ws(nb)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    per = torch.empty(B, dtype=torch.float32, device="cuda")
+    grad = torch.empty(net.nparam, dtype=torch.float32, device="cuda")
+    _check(lib.no_loss_backward(net.handle, B, ptrs, _ptr(r), int(squared), PREC[prec], _ptr(loss), _ptr(per),
+                                _ptr(grad), _ptr(ws), ct.c_size_t(ws.numel()), _stream()), "no_loss_backward")
+    return loss, per, grad
+
+
+def train_workspace_bytes(net: Net, problem: Problem, batch: int, prec: str = "bf16") -> int:
+    return int(load_library().no_train_workspace_size(net.handle, problem.handle, batch, PREC[prec]))
+
+
+def adam_step(net: Net, theta, m, v, grad, step: int, *, lr: float = 1e-3, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8, clip: float = 1.0):
+    """One Adam step on the float32 master parameters in place; refreshes the network (no_adam_step)."""
+    lib = load_library()
+    ws = _ws(lib.no_adam_workspace_size(net.handle))
+    _check(lib.no_adam_step(net.handle, _ptr(theta), _ptr(m), _ptr(v), _ptr(grad), int(step), lr, beta1, beta2, eps,
+                            clip, _ptr(ws), ct.c_size_t(ws.numel()), _stream()), "no_adam_step")
+    net.theta = theta
+
+
+def _loss_function():
+    torch = _torch()
+
+    class NoLoss(torch.autograd.Function):
+        """loss = mean_b ||A_b N_theta(r_b) - r_b|| / ||r_b|| with the library's hand-written reverse mode."""
+
+        @staticmethod
+        def forward(ctx, theta, net, problems, r, squared, prec):
+            net.set_weights(theta.detach())
+            loss, _, grad = loss_backward(net, problems, r, squared=squared, prec=prec)
+            ctx.save_for_backward(grad)
+            return loss[0]
+
+        @staticmethod
+        def backward(ctx, gout):
+            (grad,) = ctx.saved_tensors
+            return gout * grad, None, None, None, None, None
+
+    return NoLoss
+
+
+def physics_loss(theta, net: Net, problems, r, squared: bool = False, prec: str = "bf16"):
+    """Differentiable (w.r.t. theta) physics-informed loss, through torch.autograd."""
+    return _loss_function().apply(theta, net, problems, r, squared, prec)
+
+
 @dataclass
 class SolveInfo:
     status: int
