@@ -1,0 +1,222 @@
+// Device bodies of the FP64-accumulating block reductions used by the Arnoldi kernels
+// (shared by the single-system and the ragged-batch kernels).
+#pragma once
+
+#include "common.h"
+#include "krylov.h"
+
+namespace hz {
+
+constexpr int KT = 256;   // threads per block of the vector kernels
+constexpr int IC = 8;     // inner products accumulated per sweep
+
+// Sum NV pairs over the block and store them as part[slot0 + q] (thread 0 .. writes).
+template <int NV>
+__device__ __forceinline__ void block_store(double (&ar)[NV], double (&ai)[NV], double2* out, int cnt) {
+    __shared__ double red[KT / 64][2 * NV];
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double a = wave_sum(ar[q]), b = wave_sum(ai[q]);
+        if (ln == 0) {
+            red[wv][2 * q] = a;
+            red[wv][2 * q + 1] = b;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < cnt && threadIdx.x < NV) {
+        double a = 0, b = 0;
+#pragma unroll
+        for (int w = 0; w < KT / 64; ++w) {
+            a += red[w][2 * threadIdx.x];
+            b += red[w][2 * threadIdx.x + 1];
+        }
+        out[threadIdx.x] = double2{a, b};
+    }
+    __syncthreads();
+}
+
+template <typename C>
+__device__ __forceinline__ void dots_body(const C* __restrict__ V, int64_t ldv, int nv, const C* __restrict__ w,
+                                 int64_t p0, int64_t p1, double2* __restrict__ part) {
+    for (int i0 = 0; i0 < nv; i0 += IC) {
+        double ar[IC], ai[IC];
+#pragma unroll
+        for (int q = 0; q < IC; ++q) ar[q] = ai[q] = 0.0;
+        for (int64_t p = p0 + threadIdx.x; p < p1; p += KT) {
+            const C wp = w[p];
+#pragma unroll
+            for (int q = 0; q < IC; ++q) {
+                if (i0 + q < nv) {
+                    const C v = V[(int64_t)(i0 + q) * ldv + p];
+                    ar[q] += (double)v.x * wp.x + (double)v.y * wp.y;
+                    ai[q] += (double)v.x * wp.y - (double)v.y * wp.x;
+                }
+            }
+        }
+        block_store<IC>(ar, ai, part + i0, nv - i0);
+    }
+}
+
+template <typename C>
+__device__ __forceinline__ void norm_body(const C* __restrict__ w, int64_t p0, int64_t p1, double2* __restrict__ out) {
+    double a[1] = {0.0}, z[1] = {0.0};
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += KT) {
+        const C wp = w[p];
+        a[0] += (double)wp.x * wp.x + (double)wp.y * wp.y;
+    }
+    block_store<1>(a, z, out, 1);
+}
+
+__device__ inline double sum_parts(const double2* part, int nblk, int ldp, int slot) {
+    const int ln = threadIdx.x & 63;
+    double a = 0;
+    for (int q = ln; q < nblk; q += 64) a += part[(int64_t)q * ldp + slot].x;
+    return wave_sum(a);
+}
+
+__device__ inline void init_state_body(SolveState* st, const double2* part, int nblk, int ldp, double tol, int m,
+                                int hist_cap) {
+    double nb2 = sum_parts(part, nblk, ldp, 0);
+    if (threadIdx.x == 0) {
+        st->bnorm = sqrt(nb2);
+        st->tol = tol;
+        st->m = m;
+        st->stop = 0;
+        st->k = 0;
+        st->its = 0;
+        st->cycles = 0;
+        st->flags = isfinite(nb2) ? 0 : FL_NONFINITE;
+        st->est = 1.0;
+        st->true_rel = 1.0;
+        st->hist_cap = hist_cap;
+    }
+}
+
+// Cycle start: beta = ||r|| from the residual kernel's partials, convergence test
+// on the true residual, g = beta e1.
+__device__ inline void cycle_start_body(SolveState* st, const double* __restrict__ rpart, int nparts, double2* g, int m) {
+    const int ln = threadIdx.x & 63;
+    double a = 0;
+    for (int q = ln; q < nparts; q += 64) a += rpart[q];
+    a = wave_sum(a);
+    for (int i = ln; i <= m; i += 64) g[i] = double2{0.0, 0.0};
+    if (threadIdx.x == 0) {
+        const double beta = sqrt(a);
+        st->beta = beta;
+        st->k = 0;
+        st->true_rel = st->bnorm > 0 ? beta / st->bnorm : 0.0;
+        int stop = 0;
+        if (!isfinite(beta)) {
+            st->flags |= FL_NONFINITE;
+            stop = 1;
+        } else if (st->true_rel <= st->tol || beta == 0.0) {
+            st->flags |= FL_CONVERGED;
+            stop = 1;
+        } else if (st->flags & (FL_NONFINITE | FL_BREAKDOWN)) {
+            stop = 1;
+        }
+        st->stop = stop;
+        st->inv_beta = beta > 0 ? 1.0 / beta : 0.0;
+        g[0] = double2{beta, 0.0};
+    }
+}
+
+// One wavefront: assemble Hessenberg column j, rotate it, form rotation j,
+// update g and the residual estimate, decide whether the cycle ends.
+__device__ inline void arnoldi_finish_body(SolveState* st, double2* R, double* cs, double2* sn, double2* g,
+                                    const double2* h1, const double2* h2, const double2* part, int nblk, int ldp,
+                                    int j, double* hist) {
+    if (st->stop) return;
+    const int m = st->m;
+    const int ln = threadIdx.x & 63;
+    const double hn2 = sum_parts(part, nblk, ldp, 0);     // ||w||^2 after orthogonalisation
+    double2* col = R + (int64_t)j * (m + 1);
+    for (int i = ln; i <= j; i += 64) {
+        double2 a = h1[i];
+        if (h2) a = cadd(a, h2[i]);
+        col[i] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double wn0 = sqrt(h1[j + 1].x);
+    const double hn = sqrt(hn2);
+    bool bad = !isfinite(hn) || !isfinite(wn0);
+    for (int i = 0; i <= j; ++i) bad |= !isfinite(col[i].x) || !isfinite(col[i].y);
+    if (bad) {
+        st->flags |= FL_NONFINITE;
+        st->stop = 1;
+        return;
+    }
+    for (int i = 0; i < j; ++i) {   // previous rotations
+        const double c = cs[i];
+        const double2 s = sn[i];
+        const double2 x0 = col[i], x1 = col[i + 1];
+        col[i] = cadd(double2{c * x0.x, c * x0.y}, cmul(s, x1));
+        col[i + 1] = csub(double2{c * x1.x, c * x1.y}, cmulc(s, x0));   // -conj(s) x0 + c x1
+    }
+    const double2 a = col[j];
+    const double aa = sqrt(a.x * a.x + a.y * a.y);
+    const double rho = sqrt(aa * aa + hn * hn);
+    double c;
+    double2 s, r;
+    if (rho == 0.0) {
+        c = 1.0;
+        s = double2{0.0, 0.0};
+        r = double2{0.0, 0.0};
+    } else if (aa == 0.0) {
+        c = 0.0;
+        s = double2{1.0, 0.0};   // conj(b) / |b| with b = hn real > 0
+        r = double2{hn, 0.0};
+    } else {
+        const double2 ph = double2{a.x / aa, a.y / aa};
+        c = aa / rho;
+        s = double2{ph.x * hn / rho, ph.y * hn / rho};
+        r = double2{ph.x * rho, ph.y * rho};
+    }
+    cs[j] = c;
+    sn[j] = s;
+    col[j] = r;
+    col[j + 1] = double2{0.0, 0.0};
+    const double2 gj = g[j];
+    g[j + 1] = double2{-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x)};   // -conj(s) g_j
+    g[j] = double2{c * gj.x, c * gj.y};
+    const double est = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y) / st->bnorm;
+    st->est = est;
+    if (st->its < st->hist_cap) hist[st->its] = est;
+    st->its += 1;
+    if (j == 0) st->cycles += 1;
+    st->k = j + 1;
+    st->wnorm0 = wn0;
+    if (hn <= 1e-14 * wn0) {
+        st->flags |= FL_BREAKDOWN;
+        st->stop = 1;
+        st->inv_h = 0.0;
+        return;
+    }
+    st->inv_h = 1.0 / hn;
+    if (est <= st->tol || st->its >= st->hist_cap) st->stop = 1;
+}
+
+// y = R^{-1} g over the k completed columns (trailing zero pivots dropped).
+__device__ inline void backsolve_body(SolveState* st, const double2* R, const double2* g, double2* y) {
+    if (threadIdx.x != 0) return;
+    const int m = st->m;
+    int k = st->k;
+    if (st->flags & FL_NONFINITE) k = 0;
+    while (k > 0) {
+        const double2 d = R[(int64_t)(k - 1) * (m + 1) + (k - 1)];
+        if (d.x != 0.0 || d.y != 0.0) break;
+        --k;
+    }
+    for (int i = k - 1; i >= 0; --i) {
+        double2 acc = g[i];
+        for (int l = i + 1; l < k; ++l) acc = csub(acc, cmul(R[(int64_t)l * (m + 1) + i], y[l]));
+        const double2 d = R[(int64_t)i * (m + 1) + i];
+        const double dd = d.x * d.x + d.y * d.y;
+        y[i] = double2{(acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd};
+    }
+    st->k = k;   // columns used by the x update
+}
+
+}  // namespace hz

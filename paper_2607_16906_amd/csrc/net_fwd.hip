@@ -11,14 +11,16 @@ constexpr int TH = 8, TW = 16; // pixel tile of the 3x3 convolution
 template <class P>
 constexpr int pix_stride() { return P::CK + 16 / (int)sizeof(typename P::T); }   // +16 B against bank conflicts
 
+// One block's tile: output channels [co0, co0 + TN) of the 8 x 16 pixel tile at (ty0, tx0) of
+// sample bz.
 template <class P, int TN, bool POOL>
-__global__ __launch_bounds__(CT) void k_conv3(const typename P::T* __restrict__ x0, int c0,
-                                              const typename P::T* __restrict__ x1, int c1,
-                                              const typename P::T* __restrict__ w,
-                                              const typename P::Acc* __restrict__ bias,
-                                              typename P::T* __restrict__ y, int cout_p,
-                                              typename P::T* __restrict__ ypool, int H, int W, int relu, int ck,
-                                              const int* __restrict__ skip, Conv3Out ex) {
+__device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0, int c0,
+                                           const typename P::T* __restrict__ x1, int c1,
+                                           const typename P::T* __restrict__ w,
+                                           const typename P::Acc* __restrict__ bias,
+                                           typename P::T* __restrict__ y, int cout_p,
+                                           typename P::T* __restrict__ ypool, int H, int W, int relu, int ck,
+                                           const Conv3Out& ex, int bz, int co0, int ty0, int tx0) {
     using T = typename P::T;
     using Acc = typename P::Acc;
     using AccV = typename P::AccV;
@@ -26,14 +28,9 @@ __global__ __launch_bounds__(CT) void k_conv3(const typename P::T* __restrict__ 
     constexpr int PS = pix_stride<P>();
     constexpr int VE = 16 / sizeof(T);        // elements per 16-byte vector
     constexpr int NCB = TN / 16;              // output-channel blocks per block
-    if (skip && *skip) return;
     __shared__ __attribute__((aligned(16))) T patch[(TH + 2) * (TW + 2) * PS];
     __shared__ __attribute__((aligned(16))) T wl[9 * TN * PS];
 
-    const int ncb_tot = cout_p / TN;
-    const int bz = blockIdx.z / ncb_tot;                 // sample
-    const int co0 = (blockIdx.z - bz * ncb_tot) * TN;
-    const int ty0 = blockIdx.y * TH, tx0 = blockIdx.x * TW;
     const int cin_p = c0 + c1;
     const int64_t plane = (int64_t)H * W;
     const T* xs0 = x0 + (int64_t)bz * plane * c0;
@@ -158,15 +155,45 @@ __global__ __launch_bounds__(CT) void k_conv3(const typename P::T* __restrict__ 
     }
 }
 
+template <class P, int TN, bool POOL>
+__global__ __launch_bounds__(CT) void k_conv3(const typename P::T* __restrict__ x0, int c0,
+                                              const typename P::T* __restrict__ x1, int c1,
+                                              const typename P::T* __restrict__ w,
+                                              const typename P::Acc* __restrict__ bias,
+                                              typename P::T* __restrict__ y, int cout_p,
+                                              typename P::T* __restrict__ ypool, int H, int W, int relu, int ck,
+                                              const int* __restrict__ skip, Conv3Out ex) {
+    if (skip && *skip) return;
+    const int ncb_tot = cout_p / TN;
+    const int bz = blockIdx.z / ncb_tot;                 // sample
+    const int co0 = (blockIdx.z - bz * ncb_tot) * TN;
+    conv3_tile<P, TN, POOL>(x0, c0, x1, c1, w, bias, y, cout_p, ypool, H, W, relu, ck, ex, bz, co0,
+                            blockIdx.y * TH, blockIdx.x * TW);
+}
+
+// Ragged batch: block b runs job jobs[b] = (system, tile, channel block) with the system's tensors.
+template <class P, int TN, bool POOL>
+__global__ __launch_bounds__(CT) void k_conv3_jobs(const TileJob* __restrict__ jobs, const LayerIO* __restrict__ io,
+                                                   const typename P::T* __restrict__ w,
+                                                   const typename P::Acc* __restrict__ bias, int c0, int c1,
+                                                   int cout_p, int relu, int ck) {
+    const TileJob jb = jobs[blockIdx.x];
+    const LayerIO d = io[jb.sys];
+    if (d.stop && *d.stop) return;
+    conv3_tile<P, TN, POOL>((const typename P::T*)d.x0, c0, (const typename P::T*)d.x1, c1, w, bias,
+                            (typename P::T*)d.y, cout_p, (typename P::T*)d.ypool, d.H, d.W, relu, ck, Conv3Out(), 0,
+                            jb.c0, jb.ty0, jb.tx0);
+}
+
 // 2x2 stride-2 transposed convolution: a GEMM per input pixel with M = 4 x
 // output channels (tap a, b and channel), N = 16 input pixels per wave, K = input
 // channels. Block: 64 input pixels of one row (4 waves x 16) and TN channels.
 template <class P, int TN>
-__global__ __launch_bounds__(CT) void k_convT2(const typename P::T* __restrict__ x, int cin_p,
-                                               const typename P::T* __restrict__ w,
-                                               const typename P::Acc* __restrict__ bias,
-                                               typename P::T* __restrict__ y, int cout_p, int H, int W, int ck,
-                                               const int* __restrict__ skip) {
+__device__ __forceinline__ void convT2_tile(const typename P::T* __restrict__ x, int cin_p,
+                                            const typename P::T* __restrict__ w,
+                                            const typename P::Acc* __restrict__ bias,
+                                            typename P::T* __restrict__ y, int cout_p, int H, int W, int ck, int bz,
+                                            int co0, int iy, int ix0) {
     using T = typename P::T;
     using Acc = typename P::Acc;
     using AccV = typename P::AccV;
@@ -174,13 +201,8 @@ __global__ __launch_bounds__(CT) void k_convT2(const typename P::T* __restrict__
     constexpr int PS = pix_stride<P>();
     constexpr int VE = 16 / sizeof(T);
     constexpr int NCB = TN / 16;
-    if (skip && *skip) return;
     __shared__ __attribute__((aligned(16))) T xin[64 * PS];
     __shared__ __attribute__((aligned(16))) T wl[4 * TN * PS];
-    const int ncb_tot = cout_p / TN;
-    const int bz = blockIdx.z / ncb_tot;
-    const int co0 = (blockIdx.z - bz * ncb_tot) * TN;
-    const int iy = blockIdx.y, ix0 = blockIdx.x * 64;
     const int64_t plane = (int64_t)H * W;
     const T* xs = x + (int64_t)bz * plane * cin_p;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -242,7 +264,39 @@ __global__ __launch_bounds__(CT) void k_convT2(const typename P::T* __restrict__
     }
 }
 
+template <class P, int TN>
+__global__ __launch_bounds__(CT) void k_convT2(const typename P::T* __restrict__ x, int cin_p,
+                                               const typename P::T* __restrict__ w,
+                                               const typename P::Acc* __restrict__ bias,
+                                               typename P::T* __restrict__ y, int cout_p, int H, int W, int ck,
+                                               const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const int ncb_tot = cout_p / TN;
+    const int bz = blockIdx.z / ncb_tot;
+    const int co0 = (blockIdx.z - bz * ncb_tot) * TN;
+    convT2_tile<P, TN>(x, cin_p, w, bias, y, cout_p, H, W, ck, bz, co0, blockIdx.y, blockIdx.x * 64);
+}
+
+template <class P, int TN>
+__global__ __launch_bounds__(CT) void k_convT2_jobs(const TileJob* __restrict__ jobs, const LayerIO* __restrict__ io,
+                                                    const typename P::T* __restrict__ w,
+                                                    const typename P::Acc* __restrict__ bias, int cin_p, int cout_p,
+                                                    int ck) {
+    const TileJob jb = jobs[blockIdx.x];
+    const LayerIO d = io[jb.sys];
+    if (d.stop && *d.stop) return;
+    convT2_tile<P, TN>((const typename P::T*)d.x0, cin_p, w, bias, (typename P::T*)d.y, cout_p, d.H, d.W, ck, 0, jb.c0,
+                       jb.ty0, jb.tx0);
+}
+
 static int pick_tn(int cout_p) { return cout_p % 64 == 0 ? 64 : (cout_p % 32 == 0 ? 32 : 16); }
+
+int conv3_batch_tn(int cout_p, int64_t tiles) {
+    int tn = pick_tn(cout_p);
+    while (tn > 16 && tiles * (cout_p / tn) < 512) tn /= 2;
+    return tn;
+}
+int convT2_batch_tn(int cout_p) { return cout_p % 32 == 0 ? 32 : 16; }
 
 template <class P>
 static int chunk_for(int cin_p, int c0, int c1) {
@@ -314,11 +368,54 @@ int launch_convT2(const typename P::T* x, int cin_p, const typename P::T* w, con
     return HZ_OK;
 }
 
+template <class P>
+int conv_chunk(int cin_p, int c0, int c1) { return chunk_for<P>(cin_p, c0, c1); }
+
+template <class P>
+int launch_conv3_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
+                      const typename P::Acc* bias, int c0, int c1, int cout_p, int tn, bool pool, hipStream_t s) {
+    if (njobs <= 0) return HZ_OK;
+    const int ck = chunk_for<P>(c0 + c1, c0, c1);
+#define HZ_C3J(TNV, PL)                                                                                         \
+    hipLaunchKernelGGL((k_conv3_jobs<P, TNV, PL>), dim3(njobs), dim3(CT), 0, s, jobs, io, w, bias, c0, c1, cout_p, \
+                       1, ck)
+    if (pool) {
+        if (tn == 64) HZ_C3J(64, true);
+        else if (tn == 32) HZ_C3J(32, true);
+        else HZ_C3J(16, true);
+    } else {
+        if (tn == 64) HZ_C3J(64, false);
+        else if (tn == 32) HZ_C3J(32, false);
+        else HZ_C3J(16, false);
+    }
+#undef HZ_C3J
+    HZ_LAUNCH_CHECK();
+    return HZ_OK;
+}
+
+template <class P>
+int launch_convT2_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
+                       const typename P::Acc* bias, int cin_p, int cout_p, int tn, hipStream_t s) {
+    if (njobs <= 0) return HZ_OK;
+    const int ck = chunk_for<P>(cin_p, cin_p, 0);
+    if (tn == 32)
+        hipLaunchKernelGGL((k_convT2_jobs<P, 32>), dim3(njobs), dim3(CT), 0, s, jobs, io, w, bias, cin_p, cout_p, ck);
+    else
+        hipLaunchKernelGGL((k_convT2_jobs<P, 16>), dim3(njobs), dim3(CT), 0, s, jobs, io, w, bias, cin_p, cout_p, ck);
+    HZ_LAUNCH_CHECK();
+    return HZ_OK;
+}
+
 #define HZ_INST(P)                                                                                              \
     template int launch_conv3<P>(const P::T*, int, const P::T*, int, const P::T*, const P::Acc*, P::T*, int,     \
                                  P::T*, int, int, int, bool, const int*, hipStream_t, Conv3Out);               \
     template int launch_convT2<P>(const P::T*, int, const P::T*, const P::Acc*, P::T*, int, int, int, int,       \
-                                  const int*, hipStream_t);
+                                  const int*, hipStream_t);                                                    \
+    template int launch_conv3_jobs<P>(const TileJob*, int, const LayerIO*, const P::T*, const P::Acc*, int, int, \
+                                      int, int, bool, hipStream_t);                                            \
+    template int launch_convT2_jobs<P>(const TileJob*, int, const LayerIO*, const P::T*, const P::Acc*, int, int, \
+                                       int, hipStream_t);                                                      \
+    template int conv_chunk<P>(int, int, int);
 HZ_INST(PolBF16)
 HZ_INST(PolF32)
 HZ_INST(PolF64)

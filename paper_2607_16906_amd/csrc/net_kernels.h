@@ -71,6 +71,21 @@ struct PolF64 {
     __device__ static int row_of(int lg, int r) { return lg + 4 * r; }
 };
 
+// One block of a ragged batch: system index, output-channel block start, tile origin (3x3:
+// pixel row / column of an 8 x 16 tile; transposed conv: input row / first column of 64).
+struct TileJob {
+    int sys, c0, ty0, tx0;
+};
+// Per-system tensors of one layer in a ragged batch.
+struct LayerIO {
+    const void* x0;
+    const void* x1;
+    void* y;
+    void* ypool;
+    int H, W;
+    const int* stop;   // the system's stop flag (the block returns when it is set)
+};
+
 // Optional extras of a 3x3 convolution launch: a split of the output channels into two
 // tensors (channels [0, split) -> y, [split, cout) -> y1) and ReLU masks for either part
 // (an output entry is zeroed where the mask entry is <= 0). Used by the data gradient.
@@ -87,6 +102,18 @@ template <class P>
 int launch_conv3(const typename P::T* x0, int c0, const typename P::T* x1, int c1, const typename P::T* w,
                  const typename P::Acc* bias, typename P::T* y, int cout_p, typename P::T* ypool, int H, int W,
                  int batch, bool relu, const int* skip, hipStream_t s, Conv3Out ex = Conv3Out());
+// Ragged-batch versions: one launch over a job table.
+template <class P>
+int launch_conv3_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
+                      const typename P::Acc* bias, int c0, int c1, int cout_p, int tn, bool pool, hipStream_t s);
+template <class P>
+int launch_convT2_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
+                       const typename P::Acc* bias, int cin_p, int cout_p, int tn, hipStream_t s);
+// channel tile chosen for a ragged batch (so that the job table can be built on the host)
+int conv3_batch_tn(int cout_p, int64_t tiles);
+int convT2_batch_tn(int cout_p);
+template <class P>
+int conv_chunk(int cin_p, int c0, int c1);
 // convT2: y[2i+a][2j+b] = sum_c x[i][j][c] w[a][b][.][c] + b
 template <class P>
 int launch_convT2(const typename P::T* x, int cin_p, const typename P::T* w, const typename P::Acc* bias,

@@ -21,9 +21,6 @@ struct hz_problem {
 
 namespace hz {
 
-// Stencil modes: plain y = A x; residual y = b - A x with ||y||^2 block partials.
-enum StencilMode { ST_PLAIN = 0, ST_RESID = 1 };
-
 struct StencilCoef {
     const void *E, *W, *N, *S, *dx, *dy;
     const void* k2;

@@ -316,6 +316,42 @@ def fgmres(problem: Problem, b, x0=None, *, net: Net | None = None, m: int = 30,
     return x, SolveInfo(info.status, info.its, info.cycles, info.est_relres, info.true_relres, hist[:info.its].copy())
 
 
+def fgmres_batched(problems, bs, x0s=None, *, net: Net | None = None, m: int = 30, tol: float = 1e-6,
+                   maxit: int = 300, krylov: str = "c64", net_prec: str = "bf16", workspace=None):
+    """Solve many systems together (fgmres_solve_batched). bs: list of complex128 device vectors.
+
+    Returns (list of x, list of SolveInfo without histories)."""
+    torch = _torch()
+    lib = load_library()
+    nsys = len(problems)
+    bs = [b.to(torch.complex128).contiguous() for b in bs]
+    xs = [torch.zeros_like(b) if x0s is None else x0s[i].to(torch.complex128).contiguous().clone()
+          for i, b in enumerate(bs)]
+    opts = HzOpts(m, maxit, tol, HZ_C64 if krylov == "c64" else HZ_C128, PREC[net_prec], None, 0)
+    probs = (ct.c_void_p * nsys)(*[p.handle for p in problems])
+    nh = net.handle if net is not None else None
+    nb = lib.fgmres_batched_workspace_size(nsys, probs, nh, ct.byref(opts))
+    if nb == 0:
+        raise HzError(HZ_ERR_ARG, lib.hz_last_error().decode())
+    ws = workspace if workspace is not None and workspace.numel() >= nb else _ws(nb)
+    bp = (ct.c_void_p * nsys)(*[b.data_ptr() for b in bs])
+    xp = (ct.c_void_p * nsys)(*[x.data_ptr() for x in xs])
+    infos = (HzInfo * nsys)()
+    rc = lib.fgmres_solve_batched(nsys, probs, nh, ct.byref(opts), bp, xp, _ptr(ws), ct.c_size_t(ws.numel()), infos,
+                                  _stream())
+    if rc in (HZ_ERR_ARG, HZ_ERR_HIP, HZ_ERR_WORKSPACE):
+        _check(rc, "fgmres_solve_batched")
+    return xs, [SolveInfo(i.status, i.its, i.cycles, i.est_relres, i.true_relres, np.zeros(0)) for i in infos]
+
+
+def fgmres_batched_workspace_bytes(problems, net: Net | None, m: int, maxit: int, krylov: str = "c64",
+                                   net_prec: str = "bf16") -> int:
+    opts = HzOpts(m, maxit, 1e-6, HZ_C64 if krylov == "c64" else HZ_C128, PREC[net_prec], None, 0)
+    probs = (ct.c_void_p * len(problems))(*[p.handle for p in problems])
+    return int(load_library().fgmres_batched_workspace_size(len(problems), probs, net.handle if net else None,
+                                                            ct.byref(opts)))
+
+
 def fgmres_workspace_bytes(problem: Problem, net: Net | None, m: int, maxit: int, krylov: str = "c64",
                            net_prec: str = "bf16") -> int:
     opts = HzOpts(m, maxit, 1e-6, HZ_C64 if krylov == "c64" else HZ_C128, PREC[net_prec], None, 0)

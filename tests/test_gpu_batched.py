@@ -1,0 +1,115 @@
+"""GPU tests of the ragged batched solver (fgmres_solve_batched): systems of different sizes that
+advance together must give what the single-system solver gives, and match the oracle.
+
+The batched kernels inline the same device bodies as the single-system kernels, but the compiler
+may contract multiply-adds differently in the two kernels, so the two agree to rounding, not
+bitwise; across restarts of a nonlinearly preconditioned FGMRES such rounding differences grow
+(as between any two correct runs), so the solutions agree to the accuracy the tolerance fixes and
+the iteration counts to a few steps. A batch run twice is bitwise reproducible."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+from oracle import fgmres as ofg
+from oracle import helmholtz as ohz
+from oracle import unet
+from synth import gaussian_sources, he_uniform, rng_for, skull_ring_velocity
+
+from gpu_util import make_pair, rel, to_dev, to_np
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_2607_16906_amd", "weights", "unet_l4_c32_in5.npz")
+SIZES = [(12, 4), (30, 6), (20, 5), (44, 8)]
+
+
+def systems(sizes, seed=0):
+    out = []
+    for k, (nx, p) in enumerate(sizes):
+        nt = nx + 2 * p
+        c = skull_ring_velocity(nt, p, rng_for(15, 0, 10 * seed + k), rings=1)
+        b = gaussian_sources(nt, p, rng_for(15, 1, 10 * seed + k))
+        op, gp = make_pair(c, p)
+        out.append((op, gp, b))
+    return out
+
+
+def trained_net():
+    from paper_2607_16906_amd import hz
+    theta = np.load(WEIGHTS)["theta"].astype(np.float32)
+    return hz.Net(4, 32, 5, theta), theta
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights missing")
+@pytest.mark.parametrize("krylov,prec", [("c128", "fp64"), ("c64", "bf16"), ("c64", "fp32")])
+def test_batched_equals_single_solves(krylov, prec):
+    from paper_2607_16906_amd import hz
+    sy = systems(SIZES)
+    net, _ = trained_net()
+    bs = [to_dev(b, torch.complex128) for _, _, b in sy]
+    xs, infos = hz.fgmres_batched([gp for _, gp, _ in sy], bs, net=net, m=20, tol=1e-7, maxit=400, krylov=krylov,
+                                  net_prec=prec)
+    for (op, gp, b), x, inf, bd in zip(sy, xs, infos, bs):
+        x1, i1 = hz.fgmres(gp, bd, net=net, m=20, tol=1e-7, maxit=400, krylov=krylov, net_prec=prec)
+        assert inf.status == i1.status == 0
+        if prec == "fp64":
+            assert abs(inf.its - i1.its) <= 2
+            assert rel(to_np(x), to_np(x1)) <= 1e-5
+        else:
+            assert abs(inf.its - i1.its) <= max(2, i1.its // 10)
+            assert rel(to_np(x), to_np(x1)) <= 1e-4
+        r = np.linalg.norm(b.ravel() - ohz.op_apply(op, to_np(x).reshape(op.ny, op.nx)).ravel()) / np.linalg.norm(b)
+        assert r <= 1e-7 and abs(r - inf.true_relres) <= 1e-12
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights missing")
+def test_batched_fp64_matches_oracle():
+    from paper_2607_16906_amd import hz
+    sy = systems(SIZES[:2], seed=1)
+    net, theta = trained_net()
+    specs = unet.layer_specs(4, 32, 5)
+    xs, infos = hz.fgmres_batched([gp for _, gp, _ in sy], [to_dev(b, torch.complex128) for _, _, b in sy],
+                                  net=net, m=60, tol=1e-8, maxit=400, krylov="c128", net_prec="fp64")
+    for (op, gp, b), x, inf in zip(sy, xs, infos):
+        A = lambda v: ohz.op_apply(op, v.reshape(op.ny, op.nx)).ravel()
+        M = lambda v: unet.precond_apply(theta.astype(np.float64), specs, op, v.reshape(op.ny, op.nx)).ravel()
+        ref = ofg.fgmres(A, M, b, m=60, tol=1e-8, maxit=400)
+        assert inf.status == ref.status and inf.its == ref.its
+        assert rel(to_np(x), ref.x) <= 1e-8
+
+
+def test_batched_gmres_isolates_failures():
+    # no network: plain GMRES on every system; one system has b = 0, one a NaN, the others are
+    # unaffected and agree with their single solves
+    from paper_2607_16906_amd import hz
+    sy = systems([(10, 4), (14, 4), (10, 4), (16, 5)], seed=2)
+    bs = [to_dev(b, torch.complex128) for _, _, b in sy]
+    bs[1] = torch.zeros_like(bs[1])
+    bn = sy[2][2].copy()
+    bn[3, 3] = np.nan
+    bs[2] = to_dev(bn, torch.complex128)
+    xs, infos = hz.fgmres_batched([gp for _, gp, _ in sy], bs, m=30, tol=1e-8, maxit=2000, krylov="c128")
+    assert infos[1].status == 0 and infos[1].its == 0 and torch.count_nonzero(xs[1]).item() == 0
+    assert infos[2].status == hz.HZ_ERR_NONFINITE
+    for k in (0, 3):
+        x1, i1 = hz.fgmres(sy[k][1], bs[k], m=30, tol=1e-8, maxit=2000, krylov="c128")
+        assert infos[k].status == 0 and infos[k].its == i1.its
+        assert rel(to_np(xs[k]), to_np(x1)) <= 1e-12
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights missing")
+def test_batched_bitwise_reproducible():
+    # deterministic reductions and no atomics: the same batch twice gives the same bits
+    from paper_2607_16906_amd import hz
+    sy = systems(SIZES, seed=4)
+    net, _ = trained_net()
+    bs = [to_dev(b, torch.complex128) for _, _, b in sy]
+    ps = [gp for _, gp, _ in sy]
+    xa, ia = hz.fgmres_batched(ps, bs, net=net, m=20, tol=1e-6, maxit=300, krylov="c64", net_prec="bf16")
+    xb, ib = hz.fgmres_batched(ps, bs, net=net, m=20, tol=1e-6, maxit=300, krylov="c64", net_prec="bf16")
+    for a, b, i, j in zip(xa, xb, ia, ib):
+        assert i.its == j.its and torch.equal(a, b)
