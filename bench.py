@@ -56,9 +56,11 @@ def net_layers(levels, base, in_ch, Hp, Wp):
 
 
 def time_layers(net, Hp, Wp, reps, prec="bf16", only=-1):
-    """Per-layer average launch time (ms) with HIP events on the current stream."""
+    """Per-layer average launch time (ms) with HIP events on the current stream, each layer with the
+    launch variant the autotuner chose for it (the one the solve uses)."""
     import torch
     elem = {"bf16": torch.int16, "fp32": torch.float32}[prec]
+    ws = torch.empty(4 * Hp * Wp * 32 * 4 + 256, dtype=torch.uint8, device="cuda")
     res = []
     for (i, kind, cin, cout, H, W) in net_layers(LEVELS, BASE, IN_CH, Hp, Wp):
         if only >= 0 and i != only:
@@ -70,11 +72,11 @@ def time_layers(net, Hp, Wp, reps, prec="bf16", only=-1):
         Ho, Wo = (H, W) if kind == 0 else (2 * H, 2 * W)
         y = torch.empty(Ho * Wo * cout_p, dtype=elem, device="cuda")
         for _ in range(3):
-            net.layer_forward(i, x0, y, H=H, W=W, x1=x1, prec=prec)
+            net.layer_forward(i, x0, y, H=H, W=W, x1=x1, prec=prec, workspace=ws)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(reps):
-            net.layer_forward(i, x0, y, H=H, W=W, x1=x1, prec=prec)
+            net.layer_forward(i, x0, y, H=H, W=W, x1=x1, prec=prec, workspace=ws)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
@@ -157,14 +159,15 @@ def main():
     gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW)
     net = hz.Net(LEVELS, BASE, IN_CH, theta)
     Hp = Wp = (s.nt + 7) // 8 * 8
+    net.autotune(gp, "bf16")
+    net.autotune(gp, "fp32")
 
     layers = time_layers(net, Hp, Wp, reps=50, only=args.roofline_layer if args.roofline_only else -1)
     dom = max(layers, key=lambda r: r["ms"])
     achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
     net_ms = sum(r["ms"] for r in layers)
     net_flops = sum(r["flops"] for r in layers)
-    kname = f"k_conv3<PolBF16,{64 if dom['cout'] >= 64 else 32},{'pool' if dom['layer'] in (1, 3, 5) else 'nopool'}>" \
-        if dom["kind"] == 0 else "k_convT2<PolBF16>"
+    kname = "k_conv3<PolBF16, ...> (3x3 layer, autotuned variant)" if dom["kind"] == 0 else "k_convT2<PolBF16>"
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
                 "kernel": kname, "layer": dom["layer"],

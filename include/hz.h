@@ -129,6 +129,14 @@ size_t no_workspace_size(const no_net* net, const hz_problem* p, no_prec prec);
 int no_precond_apply(const no_net* net, const hz_problem* p, no_prec prec, hz_dtype dtype,
                      const void* v_dev, void* z_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
+/* Time every launch variant (channel tile, pixel-tile height, split of the input channels)
+ * of every 3x3 layer at this problem's padded size and precision, on the forward workspace
+ * ws_dev (no_workspace_size bytes), and keep the fastest in the network handle; later
+ * forward passes at that size use it. fgmres_solve calls it on its first use of a size.
+ * Synchronises `stream`; returns at once if the size was tuned before. Thread-safe. */
+int no_autotune(const no_net* net, const hz_problem* p, no_prec prec, void* ws_dev, size_t ws_bytes,
+                void* stream);
+
 /* Shape of layer `layer` (0-based, in the order of the flat parameter vector):
  * kind 0 = 3x3 convolution + ReLU, 1 = 2x2 stride-2 transposed convolution, 2 = 1x1 head;
  * cin_p / cout_p = input / output channels as stored (zero-padded to a multiple of 16, the
@@ -138,14 +146,17 @@ int no_layer_info(const no_net* net, int layer, int32_t* kind, int32_t* cin_p, i
                   int32_t* cat_cp);
 
 /* Run one 3x3 or transposed-convolution layer of the network on caller activations, as the
- * forward pass does. x0_dev: [batch][H][W][c0] with c0 = cat_cp for a concatenated input and
- * c0 = cin_p otherwise; x1_dev: [batch][H][W][cin_p - cat_cp] (second part) or NULL;
- * y_dev: [batch][H'][W'][cout_p] with (H', W') = (H, W) for a 3x3 layer and (2H, 2W) for a
- * transposed one; pool_dev: optional [batch][H/2][W/2][cout_p] average-pooled copy of y
- * (3x3 layers, H and W even). Elements are BF16 (raw 16-bit), float or double per `prec`.
+ * forward pass does (with the launch variant no_autotune chose for this layer and size, if any).
+ * x0_dev: [batch][H][W][c0] with c0 = cat_cp for a concatenated input and c0 = cin_p otherwise;
+ * x1_dev: [batch][H][W][cin_p - cat_cp] (second part) or NULL; y_dev: [batch][H'][W'][cout_p]
+ * with (H', W') = (H, W) for a 3x3 layer and (2H, 2W) for a transposed one; pool_dev: optional
+ * [batch][H/2][W/2][cout_p] average-pooled copy of y (3x3 layers, H and W even). Elements are
+ * BF16 (raw 16-bit), float or double per `prec`. ws_dev / ws_bytes: scratch for a split of the
+ * input channels (4 x batch x H x W x cout_p accumulators; NULL disables the split).
  * Meant for per-layer tests and profiling. */
 int no_layer_forward(const no_net* net, int layer, no_prec prec, int batch, int H, int W,
-                     const void* x0_dev, const void* x1_dev, void* y_dev, void* pool_dev, void* stream);
+                     const void* x0_dev, const void* x1_dev, void* y_dev, void* pool_dev,
+                     void* ws_dev, size_t ws_bytes, void* stream);
 
 /* Workspace bytes for no_loss_backward with `batch` samples on problems of one size. */
 size_t no_train_workspace_size(const no_net* net, const hz_problem* p, int batch, no_prec prec);

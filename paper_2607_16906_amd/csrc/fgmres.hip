@@ -109,6 +109,8 @@ extern "C" int fgmres_solve(const hz_problem* p, const no_net* net, const hz_opt
     auto vcol = [&](int i) { return (void*)((char*)L.V + es * n * i); };
     auto zcol = [&](int i) { return L.Z ? (void*)((char*)L.Z + es * n * i) : vcol(i); };
 
+    // pick the fastest launch variant of every network layer at this size (first call only)
+    if (net) HZ_TRY(net_autotune(net, p, o->net_prec, L.net_ws, L.net_ws_bytes, s));
     // ||b||, then the first true residual and v_1
     HZ_TRY(launch_norm_partials(true, b, n, sp, kb.part, kb.ldp, 0, nullptr, s));
     HZ_TRY(launch_init_state(kb, sp.nblk, o->tol, m, s));

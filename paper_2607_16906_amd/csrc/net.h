@@ -1,9 +1,13 @@
 // Internal view of the neural-operator handle and its forward/backward entry points.
 #pragma once
 
+#include <array>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "common.h"
+#include "net_kernels.h"
 #include "problem.h"
 
 namespace hz {
@@ -38,6 +42,9 @@ struct no_net {
     float* b_f32;                    // biases (FP32; the BF16 path adds them in FP32)
     double* b_f64;
     void* block;
+    // autotuned launch variants of the 3x3 layers, keyed by (layer, H, W, batch, precision)
+    std::map<std::array<int, 5>, hz::ConvCfg> tuned;
+    std::mutex tune_mu;
 };
 
 namespace hz {
@@ -49,5 +56,9 @@ size_t net_fwd_ws_bytes(const no_net* net, int Hp, int Wp, int batch, no_prec pr
 // z = N(v) for one field (c128: complex128 vectors, else complex64). skip: optional device flag.
 int net_precond(const no_net* net, const hz_problem* p, no_prec prec, bool c128, const void* v, void* z,
                 void* ws, size_t ws_bytes, const int* skip, hipStream_t s);
+// Time every launch variant of every 3x3 layer at this problem's size (batch 1) on the forward
+// workspace and remember the fastest; returns HZ_OK at once when already tuned. Synchronises.
+int net_autotune(const no_net* net, const hz_problem* p, no_prec prec, void* ws, size_t ws_bytes, hipStream_t s);
+hz::ConvCfg net_cfg(const no_net* net, int layer, int H, int W, int batch, no_prec prec);
 
 }  // namespace hz

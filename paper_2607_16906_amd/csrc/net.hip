@@ -209,6 +209,112 @@ static int precond_impl(const no_net* net, const hz_problem* p, bool c128, const
     return HZ_OK;
 }
 
+ConvCfg net_cfg(const no_net* net, int layer, int H, int W, int batch, no_prec prec) {
+    no_net* mnet = const_cast<no_net*>(net);
+    std::lock_guard<std::mutex> g(mnet->tune_mu);
+    auto it = mnet->tuned.find({layer, H, W, batch, (int)prec});
+    return it == mnet->tuned.end() ? ConvCfg() : it->second;
+}
+
+// Time the variants of every 3x3 layer on the forward buffers and keep the fastest.
+template <class P>
+static int autotune_impl(const no_net* net, int Hp, int Wp, const FwdBufs& b, hipStream_t s) {
+    using T = typename P::T;
+    using Acc = typename P::Acc;
+    no_net* mnet = const_cast<no_net*>(net);
+    const int lv = net->a.levels;
+    const std::vector<Layer>& Ls = net->layers;
+    hipEvent_t e0, e1;
+    HZ_HIP(hipEventCreate(&e0));
+    HZ_HIP(hipEventCreate(&e1));
+    int rc = HZ_OK;
+    auto tune_layer = [&](int li, const T* x0, int c0, const T* x1, int c1, T* y, T* pool, int H, int W) -> int {
+        const std::array<int, 5> key{li, H, W, 1, (int)prec_of<P>()};
+        {
+            std::lock_guard<std::mutex> g(mnet->tune_mu);
+            if (mnet->tuned.count(key)) return HZ_OK;
+        }
+        const Layer& ly = Ls[li];
+        ConvCfg best;
+        float best_ms = 1e30f;
+        const int chunks = (c0 + c1) / std::max(1, std::min(P::CK, c1 > 0 ? std::min(c0, c1) : c0 + c1));
+        for (int tn : {16, 32, 64}) {
+            if (ly.cout_p % tn) continue;
+            for (int rpw : {2, 4}) {
+                for (int ks : {1, 2, 4}) {
+                    if (ks > 1 && (ks > chunks || (size_t)ks * H * W * ly.cout_p > b.split_elems)) continue;
+                    ConvCfg cfg{tn, rpw, ks};
+                    auto run = [&]() {
+                        return launch_conv3<P>(x0, c0, x1, c1, packed_w<P>(net, ly), packed_b<P>(net, ly), y,
+                                               ly.cout_p, pool, H, W, 1, true, nullptr, s, Conv3Out(), cfg,
+                                               (Acc*)b.splitbuf);
+                    };
+                    HZ_TRY(run());
+                    HZ_HIP(hipEventRecord(e0, s));
+                    for (int r = 0; r < 3; ++r) HZ_TRY(run());
+                    HZ_HIP(hipEventRecord(e1, s));
+                    HZ_HIP(hipEventSynchronize(e1));
+                    float ms = 0;
+                    HZ_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = cfg;
+                    }
+                }
+            }
+        }
+        std::lock_guard<std::mutex> g(mnet->tune_mu);
+        mnet->tuned[key] = best;
+        return HZ_OK;
+    };
+    int li = 0;
+    for (int l = 0; l < lv && rc == HZ_OK; ++l) {
+        const int H = Hp >> l, W = Wp >> l;
+        const Layer& la = Ls[li];
+        const T* in = l == 0 ? (const T*)b.X : (const T*)b.P[l];
+        rc = tune_layer(li, in, la.cin_p, nullptr, 0, (T*)b.T1[l], nullptr, H, W);
+        if (rc == HZ_OK)
+            rc = tune_layer(li + 1, (const T*)b.T1[l], Ls[li + 1].cin_p, nullptr, 0, (T*)b.E[l],
+                            l + 1 < lv ? (T*)b.P[l + 1] : nullptr, H, W);
+        li += 2;
+    }
+    for (int l = lv - 2; l >= 0 && rc == HZ_OK; --l) {
+        const int H = Hp >> l, W = Wp >> l;
+        const int ce = Ls[li].cout_p;
+        rc = tune_layer(li + 1, (const T*)b.E[l], ce, (const T*)b.U[l], ce, (T*)b.T1d[l], nullptr, H, W);
+        if (rc == HZ_OK)
+            rc = tune_layer(li + 2, (const T*)b.T1d[l], Ls[li + 2].cin_p, nullptr, 0, (T*)b.D[l], nullptr, H, W);
+        li += 3;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+int net_autotune(const no_net* net, const hz_problem* p, no_prec prec, void* ws, size_t ws_bytes, hipStream_t s) {
+    int Hp, Wp;
+    net_padded_dims(net, p, &Hp, &Wp);
+    switch (prec) {
+        case NO_BF16: {
+            FwdBufs b = fwd_layout<PolBF16>(net, Hp, Wp, 1, ws, ws_bytes);
+            if (b.total > ws_bytes) break;
+            return autotune_impl<PolBF16>(net, Hp, Wp, b, s);
+        }
+        case NO_FP32: {
+            FwdBufs b = fwd_layout<PolF32>(net, Hp, Wp, 1, ws, ws_bytes);
+            if (b.total > ws_bytes) break;
+            return autotune_impl<PolF32>(net, Hp, Wp, b, s);
+        }
+        case NO_FP64: {
+            FwdBufs b = fwd_layout<PolF64>(net, Hp, Wp, 1, ws, ws_bytes);
+            if (b.total > ws_bytes) break;
+            return autotune_impl<PolF64>(net, Hp, Wp, b, s);
+        }
+    }
+    set_error("autotune: workspace too small or bad precision");
+    return HZ_ERR_WORKSPACE;
+}
+
 size_t net_fwd_ws_bytes(const no_net* net, int Hp, int Wp, int batch, no_prec prec) {
     switch (prec) {
         case NO_BF16: return fwd_layout<PolBF16>(net, Hp, Wp, batch, nullptr, 0).total;
@@ -321,14 +427,19 @@ extern "C" int no_layer_info(const no_net* net, int layer, int32_t* kind, int32_
 
 namespace hz {
 template <class P>
-static int layer_impl(const no_net* net, const Layer& ly, int batch, int H, int W, const void* x0, const void* x1,
-                      void* y, void* pool, hipStream_t s) {
+static int layer_impl(const no_net* net, int layer, int batch, int H, int W, const void* x0, const void* x1,
+                      void* y, void* pool, void* ws, size_t ws_bytes, hipStream_t s) {
     using T = typename P::T;
+    const Layer& ly = net->layers[layer];
     if (ly.kind == L_CONV3) {
         const int c1 = ly.cat_cp ? ly.cin_p - ly.cat_cp : 0;
         const int c0 = ly.cin_p - c1;
+        ConvCfg cfg = net_cfg(net, layer, H, W, batch, prec_of<P>());
+        const size_t need = (size_t)cfg.ksplit * batch * H * W * ly.cout_p * sizeof(typename P::Acc);
+        if (!ws || ws_bytes < need) cfg.ksplit = 1;
         return launch_conv3<P>((const T*)x0, c0, (const T*)x1, c1, packed_w<P>(net, ly), packed_b<P>(net, ly),
-                               (T*)y, ly.cout_p, (T*)pool, H, W, batch, true, nullptr, s);
+                               (T*)y, ly.cout_p, (T*)pool, H, W, batch, true, nullptr, s, Conv3Out(), cfg,
+                               (typename P::Acc*)ws);
     }
     return launch_convT2<P>((const T*)x0, ly.cin_p, packed_w<P>(net, ly), packed_b<P>(net, ly), (T*)y, ly.cout_p,
                             H, W, batch, nullptr, s);
@@ -336,7 +447,8 @@ static int layer_impl(const no_net* net, const Layer& ly, int batch, int H, int 
 }  // namespace hz
 
 extern "C" int no_layer_forward(const no_net* net, int layer, no_prec prec, int batch, int H, int W,
-                                const void* x0, const void* x1, void* y, void* pool, void* stream) {
+                                const void* x0, const void* x1, void* y, void* pool, void* ws, size_t ws_bytes,
+                                void* stream) {
     clear_error();
     HZ_CHECK_ARG(net && layer >= 0 && layer < (int)net->layers.size() && x0 && y, "no_layer_forward: bad argument");
     const Layer& ly = net->layers[layer];
@@ -346,10 +458,18 @@ extern "C" int no_layer_forward(const no_net* net, int layer, no_prec prec, int 
     HZ_CHECK_ARG(!pool || (ly.kind == L_CONV3 && H % 2 == 0 && W % 2 == 0), "no_layer_forward: bad pool output");
     hipStream_t s = (hipStream_t)stream;
     switch (prec) {
-        case NO_BF16: return layer_impl<PolBF16>(net, ly, batch, H, W, x0, x1, y, pool, s);
-        case NO_FP32: return layer_impl<PolF32>(net, ly, batch, H, W, x0, x1, y, pool, s);
-        case NO_FP64: return layer_impl<PolF64>(net, ly, batch, H, W, x0, x1, y, pool, s);
+        case NO_BF16: return layer_impl<PolBF16>(net, layer, batch, H, W, x0, x1, y, pool, ws, ws_bytes, s);
+        case NO_FP32: return layer_impl<PolF32>(net, layer, batch, H, W, x0, x1, y, pool, ws, ws_bytes, s);
+        case NO_FP64: return layer_impl<PolF64>(net, layer, batch, H, W, x0, x1, y, pool, ws, ws_bytes, s);
     }
     set_error("no_layer_forward: bad precision");
     return HZ_ERR_ARG;
+}
+
+extern "C" int no_autotune(const no_net* net, const hz_problem* p, no_prec prec, void* ws, size_t ws_bytes,
+                           void* stream) {
+    clear_error();
+    HZ_CHECK_ARG(net && p && ws, "no_autotune: NULL argument");
+    HZ_CHECK_ARG(prec == NO_BF16 || prec == NO_FP32 || prec == NO_FP64, "no_autotune: bad precision");
+    return net_autotune(net, p, prec, ws, ws_bytes, (hipStream_t)stream);
 }

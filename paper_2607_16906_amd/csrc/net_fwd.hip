@@ -6,29 +6,37 @@
 namespace hz {
 
 constexpr int CT = 256;        // threads per block (4 wavefronts)
-constexpr int TH = 8, TW = 16; // pixel tile of the 3x3 convolution
+constexpr int TW = 16;          // pixel tile width of the 3x3 convolution (rows: 4 per-wave row count)
 
 template <class P>
 constexpr int pix_stride() { return P::CK + 16 / (int)sizeof(typename P::T); }   // +16 B against bank conflicts
 
-// One block's tile: output channels [co0, co0 + TN) of the 8 x 16 pixel tile at (ty0, tx0) of
-// sample bz.
-template <class P, int TN, bool POOL>
+// One block's tile: output channels [co0, co0 + TN) of the (4 RPW) x 16 pixel tile at (ty0, tx0)
+// of sample bz, over the input-channel chunks [kbeg, kend). Each wavefront owns RPW rows of the
+// tile. The next chunk's patch and weights are loaded into registers while the matrix cores work
+// on the current chunk (register double buffering). With splitp set, the raw accumulators are
+// written to splitp[[bz][pixel][channel]] (no bias or activation) for a later split-K reduction.
+template <class P, int TN, bool POOL, int RPW>
 __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0, int c0,
                                            const typename P::T* __restrict__ x1, int c1,
                                            const typename P::T* __restrict__ w,
                                            const typename P::Acc* __restrict__ bias,
                                            typename P::T* __restrict__ y, int cout_p,
                                            typename P::T* __restrict__ ypool, int H, int W, int relu, int ck,
-                                           const Conv3Out& ex, int bz, int co0, int ty0, int tx0) {
+                                           const Conv3Out& ex, int bz, int co0, int ty0, int tx0, int kbeg, int kend,
+                                           typename P::Acc* __restrict__ splitp) {
     using T = typename P::T;
     using Acc = typename P::Acc;
     using AccV = typename P::AccV;
     using Frag = typename P::Frag;
+    constexpr int TH_ = 4 * RPW;
     constexpr int PS = pix_stride<P>();
     constexpr int VE = 16 / sizeof(T);        // elements per 16-byte vector
     constexpr int NCB = TN / 16;              // output-channel blocks per block
-    __shared__ __attribute__((aligned(16))) T patch[(TH + 2) * (TW + 2) * PS];
+    constexpr int VPP_MAX = P::CK / VE;
+    constexpr int NPA = ((TH_ + 2) * (TW + 2) * VPP_MAX + CT - 1) / CT;   // patch vectors per thread
+    constexpr int NPW = (9 * TN * VPP_MAX + CT - 1) / CT;                 // weight vectors per thread
+    __shared__ __attribute__((aligned(16))) T patch[(TH_ + 2) * (TW + 2) * PS];
     __shared__ __attribute__((aligned(16))) T wl[9 * TN * PS];
 
     const int cin_p = c0 + c1;
@@ -38,9 +46,9 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
 
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int lr = lane & 15, lg = lane >> 4;
-    AccV acc[2][NCB];
+    AccV acc[RPW][NCB];
 #pragma unroll
-    for (int pb = 0; pb < 2; ++pb)
+    for (int pb = 0; pb < RPW; ++pb)
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
@@ -50,56 +58,104 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
     const int cpg = ck / P::GW;                // k-groups per tap
     const int groups = 9 * cpg;
     const int steps = (groups + 3) / 4;
-    for (int k0 = 0; k0 < cin_p; k0 += ck) {
-        __syncthreads();
-        // input patch chunk (zero outside the image)
-        for (int v = threadIdx.x; v < (TH + 2) * (TW + 2) * vpp; v += CT) {
-            const int px = v / vpp, part = v - px * vpp;
-            const int py = px / (TW + 2), pxx = px - py * (TW + 2);
-            const int gy = ty0 + py - 1, gx = tx0 + pxx - 1;
+    const int npa = (TH_ + 2) * (TW + 2) * vpp, npw = 9 * TN * vpp;
+    uint4 ra[NPA], rw[NPW];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < NPA; ++i) {
+            const int v = threadIdx.x + i * CT;
             uint4 val = uint4{0, 0, 0, 0};
-            if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-                const int c = k0 + part * VE;
-                const int64_t pix = (int64_t)gy * W + gx;
-                const T* src = (c < c0) ? xs0 + pix * c0 + c : xs1 + pix * c1 + (c - c0);
-                val = *(const uint4*)src;
+            if (v < npa) {
+                const int px = v / vpp, part = v - px * vpp;
+                const int py = px / (TW + 2), pxx = px - py * (TW + 2);
+                const int gy = ty0 + py - 1, gx = tx0 + pxx - 1;
+                if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+                    const int c = k0 + part * VE;
+                    const int64_t pix = (int64_t)gy * W + gx;
+                    const T* src = (c < c0) ? xs0 + pix * c0 + c : xs1 + pix * c1 + (c - c0);
+                    val = *(const uint4*)src;
+                }
             }
-            *(uint4*)&patch[px * PS + part * VE] = val;
+            ra[i] = val;
         }
-        // weights chunk: [tap][TN][ck]
-        for (int v = threadIdx.x; v < 9 * TN * vpp; v += CT) {
-            const int row = v / vpp, part = v - row * vpp;
-            const int tap = row / TN, co = row - tap * TN;
-            const T* src = w + ((int64_t)tap * cout_p + co0 + co) * cin_p + k0 + part * VE;
-            *(uint4*)&wl[row * PS + part * VE] = *(const uint4*)src;
+#pragma unroll
+        for (int i = 0; i < NPW; ++i) {
+            const int v = threadIdx.x + i * CT;
+            uint4 val = uint4{0, 0, 0, 0};
+            if (v < npw) {
+                const int row = v / vpp, part = v - row * vpp;
+                const int tap = row / TN, co = row - tap * TN;
+                val = *(const uint4*)(w + ((int64_t)tap * cout_p + co0 + co) * cin_p + k0 + part * VE);
+            }
+            rw[i] = val;
         }
+    };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int i = 0; i < NPA; ++i) {
+            const int v = threadIdx.x + i * CT;
+            if (v < npa) {
+                const int px = v / vpp, part = v - px * vpp;
+                *(uint4*)&patch[px * PS + part * VE] = ra[i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NPW; ++i) {
+            const int v = threadIdx.x + i * CT;
+            if (v < npw) {
+                const int row = v / vpp, part = v - row * vpp;
+                *(uint4*)&wl[row * PS + part * VE] = rw[i];
+            }
+        }
+    };
+    gload(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += ck) {
         __syncthreads();
+        lstore();
+        __syncthreads();
+        if (k0 + ck < kend) gload(k0 + ck);
         for (int st = 0; st < steps; ++st) {
             const int gi = 4 * st + lg;
-            Frag a[NCB], b[2];
+            Frag a[NCB], b[RPW];
             if (gi < groups) {
                 const int tap = gi / cpg, cg = gi - tap * cpg;
                 const int dy = tap / 3, dx = tap - 3 * (tap / 3);
 #pragma unroll
-                for (int pb = 0; pb < 2; ++pb)
-                    b[pb] = P::load(&patch[((2 * wv + pb + dy) * (TW + 2) + lr + dx) * PS + cg * P::GW]);
+                for (int pb = 0; pb < RPW; ++pb)
+                    b[pb] = P::load(&patch[((RPW * wv + pb + dy) * (TW + 2) + lr + dx) * PS + cg * P::GW]);
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb) a[cb] = P::load(&wl[(tap * TN + cb * 16 + lr) * PS + cg * P::GW]);
             } else {
 #pragma unroll
-                for (int pb = 0; pb < 2; ++pb) b[pb] = P::zero();
+                for (int pb = 0; pb < RPW; ++pb) b[pb] = P::zero();
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb) a[cb] = P::zero();
             }
 #pragma unroll
-            for (int pb = 0; pb < 2; ++pb)
+            for (int pb = 0; pb < RPW; ++pb)
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb) acc[pb][cb] = P::mma(a[cb], b[pb], acc[pb][cb]);
         }
     }
 
+    const int gx = tx0 + lr;
+    if (splitp) {
+        Acc* sp = splitp + (int64_t)bz * plane * cout_p;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int pb = 0; pb < RPW; ++pb) {
+                const int gy = ty0 + RPW * wv + pb;
+                if (gy < H && gx < W) {
+                    Acc* dst = sp + ((int64_t)gy * W + gx) * cout_p + co0 + cb * 16;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) dst[P::row_of(lg, r)] = acc[pb][cb][r];
+                }
+            }
+        return;
+    }
     // epilogue: register r of a lane holds output channel co0 + 16 cb + row_of(lg, r) of pixel
-    // (ty0 + 2 wv + pb, tx0 + lr). Channels below ex.split go to y (ex.split channels per pixel),
+    // (ty0 + RPW wv + pb, tx0 + lr). Channels below ex.split go to y (ex.split channels per pixel),
     // the others to ex.y1_; ex.mask0_ / ex.mask1_ (same layouts) zero the entries whose mask is <= 0.
     const int split = ex.split > 0 ? ex.split : cout_p;
     const bool second = co0 >= split;
@@ -108,14 +164,13 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
     const T* ms = (const T*)(second ? ex.mask1_ : ex.mask0_);
     if (ms) ms += (int64_t)bz * plane * cst;
     const int cbase = second ? co0 - split : co0;
-    const int gx = tx0 + lr;
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
         const int co = co0 + cb * 16;
         const int cl = cbase + cb * 16;
-        Acc v[2][4];
+        Acc v[RPW][4];
 #pragma unroll
-        for (int pb = 0; pb < 2; ++pb)
+        for (int pb = 0; pb < RPW; ++pb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 Acc t = acc[pb][cb][r] + (bias ? bias[co + P::row_of(lg, r)] : Acc(0));
@@ -123,8 +178,8 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
                 v[pb][r] = t;
             }
 #pragma unroll
-        for (int pb = 0; pb < 2; ++pb) {
-            const int gy = ty0 + 2 * wv + pb;
+        for (int pb = 0; pb < RPW; ++pb) {
+            const int gy = ty0 + RPW * wv + pb;
             if (gy < H && gx < W) {
                 const int64_t off = ((int64_t)gy * W + gx) * cst + cl;
                 T* dst = ys + off;
@@ -140,35 +195,85 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
         if (POOL) {
             T* ps = ypool + (int64_t)bz * (plane / 4) * cout_p;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                Acc s = v[0][r] + v[1][r];
-                s += __shfl_xor(s, 1, 64);
-                v[0][r] = Acc(0.25) * s;
-            }
-            const int gy = ty0 + 2 * wv;
-            if ((lr & 1) == 0 && gy < H && gx < W) {
-                T* dst = ps + ((int64_t)(gy / 2) * (W / 2) + gx / 2) * cout_p + co;
+            for (int pp = 0; pp < RPW; pp += 2) {
+                Acc q[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) dst[P::row_of(lg, r)] = P::cvt(v[0][r]);
+                for (int r = 0; r < 4; ++r) {
+                    Acc s = v[pp][r] + v[pp + 1][r];
+                    s += __shfl_xor(s, 1, 64);
+                    q[r] = Acc(0.25) * s;
+                }
+                const int gy = ty0 + RPW * wv + pp;
+                if ((lr & 1) == 0 && gy < H && gx < W) {
+                    T* dst = ps + ((int64_t)(gy / 2) * (W / 2) + gx / 2) * cout_p + co;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) dst[P::row_of(lg, r)] = P::cvt(q[r]);
+                }
             }
         }
     }
 }
 
-template <class P, int TN, bool POOL>
+// Split-K reduction and epilogue: y = act(sum_s part[s] + b) (+ pooled copy). One thread per
+// output channel of one pixel (or of one 2 x 2 block when pooling).
+template <class P, bool POOL>
+__global__ void k_splitk_epilogue(const typename P::Acc* __restrict__ part, int nsplit, int64_t sstride,
+                                  const typename P::Acc* __restrict__ bias, typename P::T* __restrict__ y,
+                                  typename P::T* __restrict__ ypool, int H, int W, int cout_p, int batch, int relu,
+                                  const int* __restrict__ skip) {
+    using Acc = typename P::Acc;
+    if (skip && *skip) return;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = (int)(idx % cout_p);
+    const int64_t q = idx / cout_p;
+    if (!POOL) {
+        if (q >= (int64_t)batch * H * W) return;
+        Acc s = bias[c];
+        for (int k = 0; k < nsplit; ++k) s += part[k * sstride + q * cout_p + c];
+        if (relu) s = s > Acc(0) ? s : Acc(0);
+        y[q * cout_p + c] = P::cvt(s);
+    } else {
+        const int Hh = H / 2, Wh = W / 2;
+        if (q >= (int64_t)batch * Hh * Wh) return;
+        const int b = (int)(q / ((int64_t)Hh * Wh));
+        const int64_t r = q - (int64_t)b * Hh * Wh;
+        const int py = (int)(r / Wh), px = (int)(r % Wh);
+        Acc pool = 0;
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const int64_t pix = (int64_t)b * H * W + (int64_t)(2 * py + dy) * W + 2 * px + dx;
+                Acc s = bias[c];
+                for (int k = 0; k < nsplit; ++k) s += part[k * sstride + pix * cout_p + c];
+                if (relu) s = s > Acc(0) ? s : Acc(0);
+                y[pix * cout_p + c] = P::cvt(s);
+                pool += s;
+            }
+        ypool[q * cout_p + c] = P::cvt(Acc(0.25) * pool);
+    }
+}
+
+// grid: x = column tiles, y = row tiles, z = (sample, channel block, K split)
+template <class P, int TN, bool POOL, int RPW>
 __global__ __launch_bounds__(CT) void k_conv3(const typename P::T* __restrict__ x0, int c0,
                                               const typename P::T* __restrict__ x1, int c1,
                                               const typename P::T* __restrict__ w,
                                               const typename P::Acc* __restrict__ bias,
                                               typename P::T* __restrict__ y, int cout_p,
                                               typename P::T* __restrict__ ypool, int H, int W, int relu, int ck,
-                                              const int* __restrict__ skip, Conv3Out ex) {
+                                              const int* __restrict__ skip, Conv3Out ex, int nsplit,
+                                              typename P::Acc* __restrict__ splitp, int64_t sstride) {
     if (skip && *skip) return;
     const int ncb_tot = cout_p / TN;
-    const int bz = blockIdx.z / ncb_tot;                 // sample
-    const int co0 = (blockIdx.z - bz * ncb_tot) * TN;
-    conv3_tile<P, TN, POOL>(x0, c0, x1, c1, w, bias, y, cout_p, ypool, H, W, relu, ck, ex, bz, co0,
-                            blockIdx.y * TH, blockIdx.x * TW);
+    const int zs = blockIdx.z % nsplit;
+    const int zz = blockIdx.z / nsplit;
+    const int bz = zz / ncb_tot;                 // sample
+    const int co0 = (zz - bz * ncb_tot) * TN;
+    const int cin_p = c0 + c1;
+    const int nch = cin_p / ck;
+    const int kb = (nch * zs / nsplit) * ck, ke = (nch * (zs + 1) / nsplit) * ck;
+    conv3_tile<P, TN, POOL, RPW>(x0, c0, x1, c1, w, bias, y, cout_p, ypool, H, W, relu, ck, ex, bz, co0,
+                                 blockIdx.y * 4 * RPW, blockIdx.x * TW, kb, ke,
+                                 splitp ? splitp + zs * sstride : nullptr);
 }
 
 // Ragged batch: block b runs job jobs[b] = (system, tile, channel block) with the system's tensors.
@@ -180,9 +285,9 @@ __global__ __launch_bounds__(CT) void k_conv3_jobs(const TileJob* __restrict__ j
     const TileJob jb = jobs[blockIdx.x];
     const LayerIO d = io[jb.sys];
     if (d.stop && *d.stop) return;
-    conv3_tile<P, TN, POOL>((const typename P::T*)d.x0, c0, (const typename P::T*)d.x1, c1, w, bias,
-                            (typename P::T*)d.y, cout_p, (typename P::T*)d.ypool, d.H, d.W, relu, ck, Conv3Out(), 0,
-                            jb.c0, jb.ty0, jb.tx0);
+    conv3_tile<P, TN, POOL, 2>((const typename P::T*)d.x0, c0, (const typename P::T*)d.x1, c1, w, bias,
+                               (typename P::T*)d.y, cout_p, (typename P::T*)d.ypool, d.H, d.W, relu, ck, Conv3Out(),
+                               0, jb.c0, jb.ty0, jb.tx0, 0, c0 + c1, nullptr);
 }
 
 // 2x2 stride-2 transposed convolution: a GEMM per input pixel with M = 4 x
@@ -292,7 +397,7 @@ __global__ __launch_bounds__(CT) void k_convT2_jobs(const TileJob* __restrict__ 
 static int pick_tn(int cout_p) { return cout_p % 64 == 0 ? 64 : (cout_p % 32 == 0 ? 32 : 16); }
 
 int conv3_batch_tn(int cout_p, int64_t tiles) {
-    int tn = pick_tn(cout_p);
+    int tn = cout_p % 64 == 0 ? 64 : (cout_p % 32 == 0 ? 32 : 16);
     while (tn > 16 && tiles * (cout_p / tn) < 512) tn /= 2;
     return tn;
 }
@@ -312,7 +417,8 @@ static int chunk_for(int cin_p, int c0, int c1) {
 template <class P>
 int launch_conv3(const typename P::T* x0, int c0, const typename P::T* x1, int c1, const typename P::T* w,
                  const typename P::Acc* bias, typename P::T* y, int cout_p, typename P::T* ypool, int H, int W,
-                 int batch, bool relu, const int* skip, hipStream_t s, Conv3Out ex) {
+                 int batch, bool relu, const int* skip, hipStream_t s, Conv3Out ex, ConvCfg cfg,
+                 typename P::Acc* splitbuf) {
     const int cin_p = c0 + c1;
     const int ck = chunk_for<P>(cin_p, c0, c1);
     constexpr int VE = 16 / sizeof(typename P::T);
@@ -320,10 +426,19 @@ int launch_conv3(const typename P::T* x0, int c0, const typename P::T* x1, int c
         set_error("conv3: unsupported channel / size combination");
         return HZ_ERR_ARG;
     }
-    // widest channel tile that still gives the GPU enough blocks (256 CUs)
-    int tn = pick_tn(cout_p);
-    const int64_t tiles = (int64_t)((W + TW - 1) / TW) * ((H + TH - 1) / TH) * batch;
-    while (tn > 16 && tiles * (cout_p / tn) < 512) tn /= 2;
+    const int rpw = cfg.rpw == 4 ? 4 : 2;
+    int ksplit = cfg.ksplit < 1 ? 1 : cfg.ksplit;
+    if (ksplit > cin_p / ck) ksplit = cin_p / ck;
+    if (ksplit > 1 && (!splitbuf || ex.split || ex.mask0_ || ex.mask1_)) ksplit = 1;
+    const int th = 4 * rpw;
+    int tn = cfg.tn;
+    if (tn != 16 && tn != 32 && tn != 64) {
+        // widest channel tile that still gives the GPU enough blocks (256 CUs)
+        tn = pick_tn(cout_p);
+        const int64_t tiles = (int64_t)((W + TW - 1) / TW) * ((H + th - 1) / th) * batch;
+        while (tn > 16 && tiles * (cout_p / tn) < 512) tn /= 2;
+    }
+    while (cout_p % tn) tn /= 2;
     if (ex.split > 0) {
         if (ex.split % 16 || ex.split >= cout_p || (ypool && ex.split)) {
             set_error("conv3: bad output split");
@@ -331,21 +446,36 @@ int launch_conv3(const typename P::T* x0, int c0, const typename P::T* x1, int c
         }
         while (ex.split % tn || (cout_p - ex.split) % tn) tn /= 2;
     }
-    dim3 grid((W + TW - 1) / TW, (H + TH - 1) / TH, (cout_p / tn) * batch);
-#define HZ_C3(TNV, PL)                                                                                  \
-    hipLaunchKernelGGL((k_conv3<P, TNV, PL>), grid, dim3(CT), 0, s, x0, c0, x1, c1, w, bias, y, cout_p, \
-                       ypool, H, W, relu ? 1 : 0, ck, skip, ex)
-    if (ypool) {
-        if (tn == 64) HZ_C3(64, true);
-        else if (tn == 32) HZ_C3(32, true);
-        else HZ_C3(16, true);
+    dim3 grid((W + TW - 1) / TW, (H + th - 1) / th, (cout_p / tn) * batch * ksplit);
+    const int64_t sstride = (int64_t)batch * H * W * cout_p;
+    typename P::Acc* sp = ksplit > 1 ? splitbuf : nullptr;
+    const bool kpool = ypool && ksplit == 1;
+#define HZ_C3(TNV, PL, R)                                                                                  \
+    hipLaunchKernelGGL((k_conv3<P, TNV, PL, R>), grid, dim3(CT), 0, s, x0, c0, x1, c1, w, bias, y, cout_p, \
+                       kpool ? ypool : nullptr, H, W, relu ? 1 : 0, ck, skip, ex, ksplit, sp, sstride)
+#define HZ_C3T(PL, R)                       \
+    if (tn == 64) HZ_C3(64, PL, R);         \
+    else if (tn == 32) HZ_C3(32, PL, R);    \
+    else HZ_C3(16, PL, R);
+    if (kpool) {
+        if (rpw == 4) { HZ_C3T(true, 4) } else { HZ_C3T(true, 2) }
     } else {
-        if (tn == 64) HZ_C3(64, false);
-        else if (tn == 32) HZ_C3(32, false);
-        else HZ_C3(16, false);
+        if (rpw == 4) { HZ_C3T(false, 4) } else { HZ_C3T(false, 2) }
     }
+#undef HZ_C3T
 #undef HZ_C3
     HZ_LAUNCH_CHECK();
+    if (ksplit > 1) {
+        const int64_t items = ypool ? (int64_t)batch * (H / 2) * (W / 2) * cout_p : (int64_t)batch * H * W * cout_p;
+        const unsigned g = (unsigned)((items + 255) / 256);
+        if (ypool)
+            hipLaunchKernelGGL((k_splitk_epilogue<P, true>), dim3(g), dim3(256), 0, s, splitbuf, ksplit, sstride, bias,
+                               y, ypool, H, W, cout_p, batch, relu ? 1 : 0, skip);
+        else
+            hipLaunchKernelGGL((k_splitk_epilogue<P, false>), dim3(g), dim3(256), 0, s, splitbuf, ksplit, sstride,
+                               bias, y, ypool, H, W, cout_p, batch, relu ? 1 : 0, skip);
+        HZ_LAUNCH_CHECK();
+    }
     return HZ_OK;
 }
 
@@ -408,7 +538,8 @@ int launch_convT2_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const 
 
 #define HZ_INST(P)                                                                                              \
     template int launch_conv3<P>(const P::T*, int, const P::T*, int, const P::T*, const P::Acc*, P::T*, int,     \
-                                 P::T*, int, int, int, bool, const int*, hipStream_t, Conv3Out);               \
+                                 P::T*, int, int, int, bool, const int*, hipStream_t, Conv3Out, ConvCfg,       \
+                                 P::Acc*);                                                                     \
     template int launch_convT2<P>(const P::T*, int, const P::T*, const P::Acc*, P::T*, int, int, int, int,       \
                                   const int*, hipStream_t);                                                    \
     template int launch_conv3_jobs<P>(const TileJob*, int, const LayerIO*, const P::T*, const P::Acc*, int, int, \

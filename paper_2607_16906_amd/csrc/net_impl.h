@@ -1,6 +1,7 @@
 // Forward-pass plumbing shared by inference (net.hip) and training (train.hip).
 #pragma once
 
+#include <algorithm>
 #include <vector>
 
 #include "net.h"
@@ -48,8 +49,12 @@ struct FwdBufs {
     std::vector<void*> E, T1, T1d, P, U, D;   // T1d: decoder temporaries (alias T1 for inference)
     double2* part;
     double* sc;
+    void* splitbuf;      // split-K partial sums (accumulator type)
+    size_t split_elems;
     size_t total;
 };
+
+constexpr int KSPLIT_MAX = 4;
 
 template <class P>
 inline FwdBufs fwd_layout(const no_net* net, int Hp, int Wp, int batch, void* base, size_t cap,
@@ -77,6 +82,11 @@ inline FwdBufs fwd_layout(const no_net* net, int Hp, int Wp, int batch, void* ba
     }
     b.part = c.take<double2>(1024);
     b.sc = c.take<double>(2);
+    // split-K partials: the largest 3x3 layer output times the split count
+    size_t mx = 0;
+    for (int l = 0; l < lv; ++l) mx = std::max(mx, (size_t)batch * (Hp >> l) * (Wp >> l) * round16(net->a.base << l));
+    b.split_elems = mx * KSPLIT_MAX;
+    b.splitbuf = c.take<typename P::Acc>(b.split_elems);
     b.total = c.off + 256;
     return b;
 }
@@ -103,7 +113,14 @@ inline const typename P::Acc* packed_b(const no_net* net, const Layer& ly) {
 
 // Network body on a packed input X (batch samples), result D0 = decoder level-0 output.
 template <class P>
+constexpr no_prec prec_of() {
+    return sizeof(typename P::T) == 2 ? NO_BF16 : (sizeof(typename P::T) == 4 ? NO_FP32 : NO_FP64);
+}
+
+template <class P>
 inline int unet_body(const no_net* net, const FwdBufs& b, int Hp, int Wp, int batch, const int* skip, hipStream_t s) {
+    using Acc = typename P::Acc;
+    Acc* sb = (Acc*)b.splitbuf;
     using T = typename P::T;
     const int lv = net->a.levels;
     const std::vector<Layer>& Ls = net->layers;
@@ -114,10 +131,12 @@ inline int unet_body(const no_net* net, const FwdBufs& b, int Hp, int Wp, int ba
         const Layer& lb = Ls[li++];
         const T* in = l == 0 ? (const T*)b.X : (const T*)b.P[l];
         HZ_TRY(launch_conv3<P>(in, la.cin_p, nullptr, 0, packed_w<P>(net, la), packed_b<P>(net, la), (T*)b.T1[l],
-                               la.cout_p, nullptr, H, W, batch, true, skip, s));
+                               la.cout_p, nullptr, H, W, batch, true, skip, s, Conv3Out(),
+                               net_cfg(net, li - 2, H, W, batch, prec_of<P>()), sb));
         T* pool = l + 1 < lv ? (T*)b.P[l + 1] : nullptr;
         HZ_TRY(launch_conv3<P>((const T*)b.T1[l], lb.cin_p, nullptr, 0, packed_w<P>(net, lb), packed_b<P>(net, lb),
-                               (T*)b.E[l], lb.cout_p, pool, H, W, batch, true, skip, s));
+                               (T*)b.E[l], lb.cout_p, pool, H, W, batch, true, skip, s, Conv3Out(),
+                               net_cfg(net, li - 1, H, W, batch, prec_of<P>()), sb));
     }
     const T* Dn = (const T*)b.E[lv - 1];
     for (int l = lv - 2; l >= 0; --l) {
@@ -129,9 +148,11 @@ inline int unet_body(const no_net* net, const FwdBufs& b, int Hp, int Wp, int ba
                                 H / 2, W / 2, batch, skip, s));
         const int ce = lu.cout_p;
         HZ_TRY(launch_conv3<P>((const T*)b.E[l], ce, (const T*)b.U[l], ce, packed_w<P>(net, la), packed_b<P>(net, la),
-                               (T*)b.T1d[l], la.cout_p, nullptr, H, W, batch, true, skip, s));
+                               (T*)b.T1d[l], la.cout_p, nullptr, H, W, batch, true, skip, s, Conv3Out(),
+                               net_cfg(net, li - 2, H, W, batch, prec_of<P>()), sb));
         HZ_TRY(launch_conv3<P>((const T*)b.T1d[l], lb.cin_p, nullptr, 0, packed_w<P>(net, lb), packed_b<P>(net, lb),
-                               (T*)b.D[l], lb.cout_p, nullptr, H, W, batch, true, skip, s));
+                               (T*)b.D[l], lb.cout_p, nullptr, H, W, batch, true, skip, s, Conv3Out(),
+                               net_cfg(net, li - 1, H, W, batch, prec_of<P>()), sb));
         Dn = (const T*)b.D[l];
     }
     return HZ_OK;

@@ -96,12 +96,22 @@ struct Conv3Out {
     const void* mask1_ = nullptr;
 };
 
+// Variant of a 3x3 convolution launch: channel tile (16 / 32 / 64; 0 = heuristic), rows per
+// wavefront (2 or 4: 8- or 16-row pixel tiles) and the number of input-channel splits (split-K
+// writes FP32/FP64 partial sums to a workspace and reduces them in a separate epilogue kernel).
+struct ConvCfg {
+    int tn = 0;
+    int rpw = 2;
+    int ksplit = 1;
+};
+
 // Host-side launch helpers (defined in net_fwd.hip), one per precision.
 // conv3: y = act(conv3x3(concat[x0, x1]) + b) (+ pooled copy); batch samples along grid z.
 template <class P>
 int launch_conv3(const typename P::T* x0, int c0, const typename P::T* x1, int c1, const typename P::T* w,
                  const typename P::Acc* bias, typename P::T* y, int cout_p, typename P::T* ypool, int H, int W,
-                 int batch, bool relu, const int* skip, hipStream_t s, Conv3Out ex = Conv3Out());
+                 int batch, bool relu, const int* skip, hipStream_t s, Conv3Out ex = Conv3Out(),
+                 ConvCfg cfg = ConvCfg(), typename P::Acc* splitbuf = nullptr);
 // Ragged-batch versions: one launch over a job table.
 template <class P>
 int launch_conv3_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,

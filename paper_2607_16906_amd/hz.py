@@ -57,9 +57,10 @@ SIGNATURES = {
     "no_net_destroy": (_I, [_P]),
     "no_workspace_size": (_SZ, [_P, _P, _I]),
     "no_precond_apply": (_I, [_P, _P, _I, _I, _P, _P, _P, _SZ, _P]),
+    "no_autotune": (_I, [_P, _P, _I, _P, _SZ, _P]),
     "no_layer_info": (_I, [_P, _I, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32),
                            ct.POINTER(ct.c_int32)]),
-    "no_layer_forward": (_I, [_P, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P]),
+    "no_layer_forward": (_I, [_P, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P, _SZ, _P]),
     "no_train_workspace_size": (_SZ, [_P, _P, _I, _I]),
     "no_loss_backward": (_I, [_P, _I, _P, _P, _I, _I, _P, _P, _P, _P, _SZ, _P]),
     "no_adam_workspace_size": (_SZ, [_P]),
@@ -198,6 +199,13 @@ class Net:
         return z
 
 
+    def autotune(self, problem: Problem, prec: str = "bf16"):
+        """Pick the fastest launch variant of every 3x3 layer at this problem's size (no_autotune)."""
+        lib = load_library()
+        ws = _ws(lib.no_workspace_size(self.handle, problem.handle, PREC[prec]))
+        _check(lib.no_autotune(self.handle, problem.handle, PREC[prec], _ptr(ws), ct.c_size_t(ws.numel()), _stream()),
+               "no_autotune")
+
     def layer_info(self, layer: int):
         """(kind, cin_p, cout_p, cat_cp) of one layer (no_layer_info)."""
         v = [ct.c_int32() for _ in range(4)]
@@ -205,11 +213,13 @@ class Net:
         return tuple(x.value for x in v)
 
     def layer_forward(self, layer: int, x0, y, *, H: int, W: int, batch: int = 1, x1=None, pool=None,
-                      prec: str = "bf16"):
+                      prec: str = "bf16", workspace=None):
         """Run one layer on NHWC device tensors (no_layer_forward); asynchronous on the current stream."""
+        ws = _ptr(workspace) if workspace is not None else None
+        nb = ct.c_size_t(workspace.numel() if workspace is not None else 0)
         _check(load_library().no_layer_forward(self.handle, layer, PREC[prec], batch, H, W, _ptr(x0),
                                                _ptr(x1) if x1 is not None else None, _ptr(y),
-                                               _ptr(pool) if pool is not None else None, _stream()),
+                                               _ptr(pool) if pool is not None else None, ws, nb, _stream()),
                "no_layer_forward")
 
 

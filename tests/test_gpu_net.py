@@ -74,3 +74,19 @@ def test_net_bad_arch_rejected():
     with pytest.raises(ValueError):
         hz.param_count(4, 12, 5)
     assert hz.param_count(4, 32, 5) == unet.param_count(unet.layer_specs(4, 32, 5))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("bf16", 3e-2)])
+def test_autotuned_variants_keep_parity(prec, tol):
+    # the autotuner may pick other channel tiles, taller pixel tiles or a split of the input
+    # channels (split-K with a separate reduction): the forward pass keeps its parity
+    op, gp, specs, theta, net, v = setup(4, 32, 5, 120, 20, seed=5)
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    vd = to_dev(v, dt)
+    z0 = to_np(net.apply(gp, vd, prec=prec))
+    net.autotune(gp, prec)
+    z1 = to_np(net.apply(gp, vd, prec=prec)).reshape(op.ny, op.nx)
+    th = bf16_round(theta) if prec == "bf16" else theta.astype(np.float64)
+    ref = unet.precond_apply(th, specs, op, v)
+    assert rel(z1, ref) <= tol
+    assert rel(z1, z0.reshape(op.ny, op.nx)) <= (1e-13 if prec == "fp64" else tol)
