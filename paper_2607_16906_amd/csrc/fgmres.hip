@@ -1,13 +1,13 @@
 // Host driver of restarted flexible GMRES (Algorithm 1 with the bookkeeping of Section 4).
 //
-// Everything numerical runs in device kernels; the host only enqueues them. Each
-// restart cycle enqueues its m Arnoldi steps without waiting: every kernel of a
-// step first reads the device flag `stop` (set when the Givens estimate reaches
-// tol, on breakdown or on a non-finite value) and returns at once when it is set,
-// so steps past the end of a cycle cost one empty launch each. The cycle ends
-// with the least-squares update of x and the FP64 true residual that starts the
-// next cycle; the host then reads the device state once (the only
-// synchronisation per cycle).
+// Everything numerical runs in device kernels; the host only enqueues them. A restart
+// cycle is captured once into a HIP graph (its m Arnoldi steps and the cycle end) and
+// replayed for every cycle of the same length: every kernel of a step first reads the
+// device flag `stop` (set when the Givens estimate reaches tol, on breakdown or on a
+// non-finite value) and returns at once when it is set, so steps past the end of a cycle
+// cost one empty launch each. The cycle ends with the least-squares update of x and the
+// FP64 true residual that starts the next cycle; the host then reads the device state
+// once (the only synchronisation per cycle).
 #include <algorithm>
 #include <cstring>
 
@@ -75,39 +75,46 @@ static int check_opts(const hz_opts* o, const no_net* net) {
     return HZ_OK;
 }
 
-}  // namespace hz
-
-using namespace hz;
-
-extern "C" size_t fgmres_workspace_size(const hz_problem* p, const no_net* net, const hz_opts* o) {
-    clear_error();
-    if (!p || check_opts(o, net) != HZ_OK) return 0;
-    return fgmres_layout(p, net, o, nullptr, 0).total;
-}
-
-extern "C" int fgmres_solve(const hz_problem* p, const no_net* net, const hz_opts* o, const void* b_dev,
-                            void* x_dev, void* ws, size_t ws_bytes, hz_info* info, void* stream) {
-    clear_error();
-    HZ_CHECK_ARG(p && b_dev && x_dev && ws && info, "fgmres_solve: NULL argument");
-    HZ_TRY(check_opts(o, net));
-    FgmresLayout L = fgmres_layout(p, net, o, ws, ws_bytes);
-    if (L.total > ws_bytes) {
-        set_error("fgmres_solve: workspace too small");
-        return HZ_ERR_WORKSPACE;
-    }
-    hipStream_t s = (hipStream_t)stream;
+// The launches of one restart cycle (steps Arnoldi steps, then the cycle end).
+static int cycle_launches(const hz_problem* p, const no_net* net, const hz_opts* o, const FgmresLayout& L,
+                          KrylovBufs& kb, const double2* b, double2* x, int steps, hipStream_t s) {
     const int64_t n = p->n;
-    const int m = o->m;
     const bool c128 = o->krylov == HZ_C128;
     const size_t es = c128 ? sizeof(double2) : sizeof(float2);
-    const double2* b = (const double2*)b_dev;
-    double2* x = (double2*)x_dev;
-    KrylovBufs& kb = L.kb;
     const int* stop = &kb.st->stop;
     Split sp = krylov_split(n);
     const int nres = stencil_blocks(p);
     auto vcol = [&](int i) { return (void*)((char*)L.V + es * n * i); };
     auto zcol = [&](int i) { return L.Z ? (void*)((char*)L.Z + es * n * i) : vcol(i); };
+    for (int j = 0; j < steps; ++j) {
+        if (net) HZ_TRY(net_precond(net, p, o->net_prec, c128, vcol(j), zcol(j), L.net_ws, L.net_ws_bytes, stop, s, true));
+        // w = A z_j, written into the slot of v_{j+1}
+        void* w = vcol(j + 1);
+        HZ_TRY(launch_stencil(p, c128, false, zcol(j), w, s, stop));
+        HZ_TRY(launch_dots(c128, L.V, n, j + 1, w, n, sp, kb.part, kb.ldp, true, stop, s));
+        HZ_TRY(launch_finalize(kb.part, sp.nblk, kb.ldp, j + 2, kb.h1, stop, s));
+        HZ_TRY(launch_update(c128, L.V, n, j + 1, kb.h1, w, n, sp, kb.part, kb.ldp, 1, stop, s));
+        HZ_TRY(launch_finalize(kb.part, sp.nblk, kb.ldp, j + 1, kb.h2, stop, s));
+        HZ_TRY(launch_update(c128, L.V, n, j + 1, kb.h2, w, n, sp, kb.part, kb.ldp, 2, stop, s));
+        HZ_TRY(launch_arnoldi_finish(kb, j, sp.nblk, true, s));
+        HZ_TRY(launch_scale(c128, w, n, &kb.st->inv_h, stop, s));
+    }
+    HZ_TRY(launch_backsolve(kb, s));
+    HZ_TRY(launch_xupdate(c128, zcol(0), n, x, n, kb, s));
+    HZ_TRY(launch_resid64(p, b, x, L.r64, L.rpart, nullptr, s));
+    HZ_TRY(launch_cycle_start(kb, L.rpart, nres, s));
+    HZ_TRY(launch_cast_scale(c128, L.r64, vcol(0), n, kb.st, s));
+    return HZ_OK;
+}
+
+static int solve_on(const hz_problem* p, const no_net* net, const hz_opts* o, const double2* b, double2* x,
+                    FgmresLayout& L, hz_info* info, hipStream_t s, hipGraph_t& graph, hipGraphExec_t& exec) {
+    const int64_t n = p->n;
+    const int m = o->m;
+    const bool c128 = o->krylov == HZ_C128;
+    KrylovBufs& kb = L.kb;
+    Split sp = krylov_split(n);
+    const int nres = stencil_blocks(p);
 
     // pick the fastest launch variant of every network layer at this size (first call only)
     if (net) HZ_TRY(net_autotune(net, p, o->net_prec, L.net_ws, L.net_ws_bytes, s));
@@ -116,34 +123,30 @@ extern "C" int fgmres_solve(const hz_problem* p, const no_net* net, const hz_opt
     HZ_TRY(launch_init_state(kb, sp.nblk, o->tol, m, s));
     HZ_TRY(launch_resid64(p, b, x, L.r64, L.rpart, nullptr, s));
     HZ_TRY(launch_cycle_start(kb, L.rpart, nres, s));
-    HZ_TRY(launch_cast_scale(c128, L.r64, vcol(0), n, kb.st, s));
+    HZ_TRY(launch_cast_scale(c128, L.r64, L.V, n, kb.st, s));
 
     SolveState hs{};
     HZ_HIP(hipMemcpyAsync(&hs, kb.st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
     HZ_HIP(hipStreamSynchronize(s));
     if (hs.bnorm == 0.0 && !(hs.flags & FL_NONFINITE)) HZ_HIP(hipMemsetAsync(x, 0, sizeof(double2) * n, s));
+    int graph_steps = -1;
     while (!(hs.flags & (FL_CONVERGED | FL_NONFINITE | FL_BREAKDOWN)) && hs.its < o->maxit) {
         const int steps = std::min(m, o->maxit - hs.its);
-        for (int j = 0; j < steps; ++j) {
-            if (net) {
-                HZ_TRY(net_precond(net, p, o->net_prec, c128, vcol(j), zcol(j), L.net_ws, L.net_ws_bytes, stop, s));
-            }
-            // w = A z_j, written into the slot of v_{j+1}
-            void* w = vcol(j + 1);
-            HZ_TRY(launch_stencil(p, c128, false, zcol(j), w, s, stop));
-            HZ_TRY(launch_dots(c128, L.V, n, j + 1, w, n, sp, kb.part, kb.ldp, true, stop, s));
-            HZ_TRY(launch_finalize(kb.part, sp.nblk, kb.ldp, j + 2, kb.h1, stop, s));
-            HZ_TRY(launch_update(c128, L.V, n, j + 1, kb.h1, w, n, sp, kb.part, kb.ldp, 1, stop, s));
-            HZ_TRY(launch_finalize(kb.part, sp.nblk, kb.ldp, j + 1, kb.h2, stop, s));
-            HZ_TRY(launch_update(c128, L.V, n, j + 1, kb.h2, w, n, sp, kb.part, kb.ldp, 2, stop, s));
-            HZ_TRY(launch_arnoldi_finish(kb, j, sp.nblk, true, s));
-            HZ_TRY(launch_scale(c128, w, n, &kb.st->inv_h, stop, s));
+        // one cycle = one graph launch; the graph is captured once per cycle length
+        if (steps != graph_steps) {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+            exec = nullptr;
+            graph = nullptr;
+            HZ_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            const int crc = cycle_launches(p, net, o, L, kb, b, x, steps, s);
+            const hipError_t e = hipStreamEndCapture(s, &graph);
+            if (crc != HZ_OK) return crc;
+            HZ_HIP(e);
+            HZ_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+            graph_steps = steps;
         }
-        HZ_TRY(launch_backsolve(kb, s));
-        HZ_TRY(launch_xupdate(c128, zcol(0), n, x, n, kb, s));
-        HZ_TRY(launch_resid64(p, b, x, L.r64, L.rpart, nullptr, s));
-        HZ_TRY(launch_cycle_start(kb, L.rpart, nres, s));
-        HZ_TRY(launch_cast_scale(c128, L.r64, vcol(0), n, kb.st, s));
+        HZ_HIP(hipGraphLaunch(exec, s));
         HZ_HIP(hipMemcpyAsync(&hs, kb.st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
         HZ_HIP(hipStreamSynchronize(s));
     }
@@ -171,3 +174,50 @@ extern "C" int fgmres_solve(const hz_problem* p, const no_net* net, const hz_opt
     }
     return info->status;
 }
+
+}  // namespace hz
+
+using namespace hz;
+
+extern "C" size_t fgmres_workspace_size(const hz_problem* p, const no_net* net, const hz_opts* o) {
+    clear_error();
+    if (!p || check_opts(o, net) != HZ_OK) return 0;
+    return fgmres_layout(p, net, o, nullptr, 0).total;
+}
+
+// The solve runs on a stream owned by the call (graph capture needs a non-default stream),
+// ordered after the caller's pending work and before anything the caller enqueues later.
+extern "C" int fgmres_solve(const hz_problem* p, const no_net* net, const hz_opts* o, const void* b_dev,
+                            void* x_dev, void* ws, size_t ws_bytes, hz_info* info, void* stream) {
+    clear_error();
+    HZ_CHECK_ARG(p && b_dev && x_dev && ws && info, "fgmres_solve: NULL argument");
+    HZ_TRY(check_opts(o, net));
+    FgmresLayout L = fgmres_layout(p, net, o, ws, ws_bytes);
+    if (L.total > ws_bytes) {
+        set_error("fgmres_solve: workspace too small");
+        return HZ_ERR_WORKSPACE;
+    }
+    hipStream_t user = (hipStream_t)stream, s;
+    hipEvent_t ev;
+    HZ_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        set_error("fgmres_solve: hipEventCreate failed");
+        return HZ_ERR_HIP;
+    }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int rc = HZ_ERR_HIP;
+    if (hipEventRecord(ev, user) == hipSuccess && hipStreamWaitEvent(s, ev, 0) == hipSuccess)
+        rc = solve_on(p, net, o, (const double2*)b_dev, (double2*)x_dev, L, info, s, graph, exec);
+    else
+        set_error("fgmres_solve: stream ordering failed");
+    if (hipEventRecord(ev, s) != hipSuccess || hipStreamWaitEvent(user, ev, 0) != hipSuccess) rc = HZ_ERR_HIP;
+    (void)hipStreamSynchronize(s);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipEventDestroy(ev);
+    (void)hipStreamDestroy(s);
+    return rc;
+}
+

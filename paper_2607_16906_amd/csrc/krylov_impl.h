@@ -10,30 +10,53 @@ namespace hz {
 constexpr int KT = 256;   // threads per block of the vector kernels
 constexpr int IC = 8;     // inner products accumulated per sweep
 
-// Sum NV pairs over the block and store them as part[slot0 + q] (thread 0 .. writes).
+// Sum NV pairs over the block and store the first cnt of them as out[q]. For NV >= 2 the
+// 2 NV values are transposed through LDS: 256 / (2 NV) consecutive lanes own one value, each
+// sums a strided slice of the 256 thread contributions, and the lanes combine with
+// in-wavefront shuffles (fixed order, so the result is deterministic).
 template <int NV>
 __device__ __forceinline__ void block_store(double (&ar)[NV], double (&ai)[NV], double2* out, int cnt) {
-    __shared__ double red[KT / 64][2 * NV];
-    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    if constexpr (NV >= 2) {
+        constexpr int NVAL = 2 * NV;
+        constexpr int PER = KT / NVAL;          // lanes per value (<= 64)
+        __shared__ double red[NVAL][KT];
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        double a = wave_sum(ar[q]), b = wave_sum(ai[q]);
-        if (ln == 0) {
-            red[wv][2 * q] = a;
-            red[wv][2 * q + 1] = b;
+        for (int q = 0; q < NV; ++q) {
+            red[2 * q][threadIdx.x] = ar[q];
+            red[2 * q + 1][threadIdx.x] = ai[q];
         }
-    }
-    __syncthreads();
-    if (threadIdx.x < cnt && threadIdx.x < NV) {
-        double a = 0, b = 0;
+        __syncthreads();
+        const int v = threadIdx.x / PER, g = threadIdx.x % PER;
+        double s = 0;
 #pragma unroll
-        for (int w = 0; w < KT / 64; ++w) {
-            a += red[w][2 * threadIdx.x];
-            b += red[w][2 * threadIdx.x + 1];
+        for (int k = 0; k < KT / PER; ++k) s += red[v][g + PER * k];
+#pragma unroll
+        for (int o = PER / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+        if (g == 0 && (v >> 1) < cnt) ((double*)out)[v] = s;
+        __syncthreads();
+    } else {
+        __shared__ double red[KT / 64][2 * NV];
+        const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double a = wave_sum(ar[q]), b = wave_sum(ai[q]);
+            if (ln == 0) {
+                red[wv][2 * q] = a;
+                red[wv][2 * q + 1] = b;
+            }
         }
-        out[threadIdx.x] = double2{a, b};
+        __syncthreads();
+        if (threadIdx.x < cnt && threadIdx.x < NV) {
+            double a = 0, b = 0;
+#pragma unroll
+            for (int w = 0; w < KT / 64; ++w) {
+                a += red[w][2 * threadIdx.x];
+                b += red[w][2 * threadIdx.x + 1];
+            }
+            out[threadIdx.x] = double2{a, b};
+        }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 template <typename C>

@@ -54,8 +54,9 @@ int net_level_count(const no_net* net);
 void net_padded_dims(const no_net* net, const hz_problem* p, int* Hp, int* Wp);
 size_t net_fwd_ws_bytes(const no_net* net, int Hp, int Wp, int batch, no_prec prec);
 // z = N(v) for one field (c128: complex128 vectors, else complex64). skip: optional device flag.
+// unit_norm: v is a Krylov vector of norm 1, so s = 1 / sqrt(n) without a reduction.
 int net_precond(const no_net* net, const hz_problem* p, no_prec prec, bool c128, const void* v, void* z,
-                void* ws, size_t ws_bytes, const int* skip, hipStream_t s);
+                void* ws, size_t ws_bytes, const int* skip, hipStream_t s, bool unit_norm = false);
 // Time every launch variant of every 3x3 layer at this problem's size (batch 1) on the forward
 // workspace and remember the fastest; returns HZ_OK at once when already tuned. Synchronises.
 int net_autotune(const no_net* net, const hz_problem* p, no_prec prec, void* ws, size_t ws_bytes, hipStream_t s);

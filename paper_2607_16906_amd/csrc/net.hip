@@ -154,7 +154,7 @@ __global__ void k_scale_factor(const double2* part, int nblk, int64_t n, double*
 template <class P, typename C>
 __global__ void k_head(const typename P::T* __restrict__ D, int cin_p, const typename P::T* __restrict__ wh,
                        const typename P::Acc* __restrict__ bh, const double* __restrict__ sc, int nxt, int nyt,
-                       int Wp, C* __restrict__ z, const int* __restrict__ skip) {
+                       int Wp, C* __restrict__ z, const int* __restrict__ skip, double fixed_s) {
     using Acc = typename P::Acc;
     if (skip && *skip) return;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -167,13 +167,13 @@ __global__ void k_head(const typename P::T* __restrict__ D, int cin_p, const typ
         o0 += dv * P::val(wh[c]);
         o1 += dv * P::val(wh[cin_p + c]);
     }
-    const double s = sc[0];
+    const double s = fixed_s > 0 ? fixed_s : sc[0];
     z[idx] = from_d2<C>(double2{s * (double)o0, s * (double)o1});
 }
 
 template <class P>
 static int precond_impl(const no_net* net, const hz_problem* p, bool c128, const void* v, void* z, void* ws,
-                        size_t ws_bytes, const int* skip, hipStream_t s) {
+                        size_t ws_bytes, const int* skip, hipStream_t s, bool unit_norm) {
     using T = typename P::T;
     int Hp, Wp;
     net_padded_dims(net, p, &Hp, &Wp);
@@ -184,16 +184,20 @@ static int precond_impl(const no_net* net, const hz_problem* p, bool c128, const
     }
     const int64_t n = p->n;
     Split sp = krylov_split(n);
-    HZ_TRY(launch_norm_partials(c128, v, n, sp, b.part, 1, 0, skip, s));
-    hipLaunchKernelGGL(k_scale_factor, dim3(1), dim3(64), 0, s, b.part, sp.nblk, n, b.sc, skip);
-    HZ_LAUNCH_CHECK();
+    // s = ||v|| / sqrt(n); a unit-norm Krylov vector has s = 1 / sqrt(n) without a reduction
+    const double fixed_s = unit_norm ? 1.0 / sqrt((double)n) : 0.0;
+    if (!unit_norm) {
+        HZ_TRY(launch_norm_partials(c128, v, n, sp, b.part, 1, 0, skip, s));
+        hipLaunchKernelGGL(k_scale_factor, dim3(1), dim3(64), 0, s, b.part, sp.nblk, n, b.sc, skip);
+        HZ_LAUNCH_CHECK();
+    }
     const unsigned gp = (unsigned)(((int64_t)Hp * Wp + 255) / 256);
     if (c128)
         hipLaunchKernelGGL((k_pack<P, double2>), dim3(gp), dim3(256), 0, s, (const double2*)v, b.sc, p->cnd, p->sigx,
-                           p->sigy, p->nxt, p->nyt, Hp, Wp, net->a.in_ch, (T*)b.X, skip);
+                           p->sigy, p->nxt, p->nyt, Hp, Wp, net->a.in_ch, (T*)b.X, skip, fixed_s);
     else
         hipLaunchKernelGGL((k_pack<P, float2>), dim3(gp), dim3(256), 0, s, (const float2*)v, b.sc, p->cnd, p->sigx,
-                           p->sigy, p->nxt, p->nyt, Hp, Wp, net->a.in_ch, (T*)b.X, skip);
+                           p->sigy, p->nxt, p->nyt, Hp, Wp, net->a.in_ch, (T*)b.X, skip, fixed_s);
     HZ_LAUNCH_CHECK();
     HZ_TRY(unet_body<P>(net, b, Hp, Wp, 1, skip, s));
     const Layer& lh = net->layers.back();
@@ -201,10 +205,10 @@ static int precond_impl(const no_net* net, const hz_problem* p, bool c128, const
     const unsigned gh = (unsigned)((n + 255) / 256);
     if (c128)
         hipLaunchKernelGGL((k_head<P, double2>), dim3(gh), dim3(256), 0, s, D0, lh.cin_p, packed_w<P>(net, lh),
-                           packed_b<P>(net, lh), b.sc, p->nxt, p->nyt, Wp, (double2*)z, skip);
+                           packed_b<P>(net, lh), b.sc, p->nxt, p->nyt, Wp, (double2*)z, skip, fixed_s);
     else
         hipLaunchKernelGGL((k_head<P, float2>), dim3(gh), dim3(256), 0, s, D0, lh.cin_p, packed_w<P>(net, lh),
-                           packed_b<P>(net, lh), b.sc, p->nxt, p->nyt, Wp, (float2*)z, skip);
+                           packed_b<P>(net, lh), b.sc, p->nxt, p->nyt, Wp, (float2*)z, skip, fixed_s);
     HZ_LAUNCH_CHECK();
     return HZ_OK;
 }
@@ -324,11 +328,11 @@ size_t net_fwd_ws_bytes(const no_net* net, int Hp, int Wp, int batch, no_prec pr
 }
 
 int net_precond(const no_net* net, const hz_problem* p, no_prec prec, bool c128, const void* v, void* z, void* ws,
-                size_t ws_bytes, const int* skip, hipStream_t s) {
+                size_t ws_bytes, const int* skip, hipStream_t s, bool unit_norm) {
     switch (prec) {
-        case NO_BF16: return precond_impl<PolBF16>(net, p, c128, v, z, ws, ws_bytes, skip, s);
-        case NO_FP32: return precond_impl<PolF32>(net, p, c128, v, z, ws, ws_bytes, skip, s);
-        case NO_FP64: return precond_impl<PolF64>(net, p, c128, v, z, ws, ws_bytes, skip, s);
+        case NO_BF16: return precond_impl<PolBF16>(net, p, c128, v, z, ws, ws_bytes, skip, s, unit_norm);
+        case NO_FP32: return precond_impl<PolF32>(net, p, c128, v, z, ws, ws_bytes, skip, s, unit_norm);
+        case NO_FP64: return precond_impl<PolF64>(net, p, c128, v, z, ws, ws_bytes, skip, s, unit_norm);
     }
     set_error("no_precond_apply: bad precision");
     return HZ_ERR_ARG;

@@ -12,10 +12,12 @@ namespace hz {
 inline int round16(int c) { return (c + 15) / 16 * 16; }
 
 // X[y][x][0..7] = [Re v / s, Im v / s, (c / c_ref, sigma_x, sigma_y), 0...] on the grid, 0 in the padding.
+// fixed_s > 0: the caller knows ||v|| / sqrt(n) (a unit-norm Krylov vector) and sc is not read.
 template <class P, typename C>
 __global__ void k_pack(const C* __restrict__ v, const double* __restrict__ sc, const double* __restrict__ cnd,
                        const double* __restrict__ sigx, const double* __restrict__ sigy, int nxt, int nyt, int Hp,
-                       int Wp, int in_ch, typename P::T* __restrict__ X, const int* __restrict__ skip) {
+                       int Wp, int in_ch, typename P::T* __restrict__ X, const int* __restrict__ skip,
+                       double fixed_s = 0.0) {
     using T = typename P::T;
     if (skip && *skip) return;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -26,7 +28,7 @@ __global__ void k_pack(const C* __restrict__ v, const double* __restrict__ sc, c
     for (int c = 0; c < 8; ++c) out[c] = P::cvt(0);
     if (yy < nyt && xx < nxt) {
         const int64_t g = (int64_t)yy * nxt + xx;
-        const double is = sc[1];
+        const double is = fixed_s > 0 ? 1.0 / fixed_s : sc[1];
         const C a = v[g];
         out[0] = P::cvt((typename P::Acc)((double)a.x * is));
         out[1] = P::cvt((typename P::Acc)((double)a.y * is));
