@@ -31,6 +31,37 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "conv3_dominant_layer_296_bf16_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2607_16906_amd", "csrc", f) for f in ("net_fwd.hip", "net_kernels.h")]
+
+
+def kernel_fingerprint():
+    import hashlib
+    h = hashlib.md5()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(layer):
+    """HBM bytes per launch of the dominant layer from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy of known size), or None when the summary is missing, is for
+    another layer, or the kernel sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        if kv.get("source_md5") != kernel_fingerprint() or int(kv.get("layer", -1)) != layer:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def layer_flops(kind, cin, cout, H, W):
     """Algorithmic FLOPs of one layer launch on an H x W input (logical channels)."""
     if kind == 0:
@@ -102,6 +133,70 @@ def time_stencil(hz, torch, nt, reps=50):
     return e0.elapsed_time(e1) / reps
 
 
+def train_flops(levels, base, in_ch, Hp, Wp, batch):
+    """Algorithmic FLOPs of one training step: forward, data gradients (all layers but the first)
+    and weight gradients of every layer (the head and stencils are negligible)."""
+    fwd = sum(layer_flops(k, ci, co, H, W) for (_, k, ci, co, H, W) in net_layers(levels, base, in_ch, Hp, Wp))
+    first = layer_flops(0, in_ch, base, Hp, Wp)
+    return batch * (3 * fwd - first)
+
+
+def bench_training(hz, torch, steps=3, batch=64):
+    """Training step of the physics-informed loss on 64 samples at 128^2 + 16 PML (BF16), from the
+    seeded initial weights with Adam at lr 1e-3."""
+    from synth import CFG_C3, COMP_WEIGHTS, H_10PPW, c3_batch, he_uniform, rng_for
+    theta = he_uniform(hz.init_shapes(LEVELS, BASE, IN_CH), rng_for(CFG_C3, COMP_WEIGHTS, 0))
+    cs, rs = c3_batch(batch=batch, step=0)
+    probs = [hz.Problem(c.astype(np.float32).ravel(), 128, 128, 16, H_10PPW) for c in cs]
+    net = hz.Net(LEVELS, BASE, IN_CH, theta)
+    r = torch.from_numpy(rs.astype(np.complex64).reshape(batch, -1)).cuda()
+    th = torch.from_numpy(theta.copy()).cuda()
+    m, v = torch.zeros_like(th), torch.zeros_like(th)
+    ws = torch.empty(hz.train_workspace_bytes(net, probs[0], batch, "bf16"), dtype=torch.uint8, device="cuda")
+    losses = []
+    for step in range(1, steps + 2):
+        if step == 2:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        loss, _, g = hz.loss_backward(net, probs, r, prec="bf16", workspace=ws)
+        hz.adam_step(net, th, m, v, g, step, lr=1e-3, clip=1.0)
+        losses.append(loss)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    fl = train_flops(LEVELS, BASE, IN_CH, 160, 160, batch)
+    return {"workload": "training step, 64 x (128^2 + 16 PML), 4-level/32-ch U-Net, BF16 fwd/bwd, FP32 master, Adam",
+            "ms_per_step": round(dt * 1e3, 2), "samples_per_s": round(batch / dt, 1),
+            "tflops": round(fl / dt * 1e-12, 2), "loss_first": float(losses[0].item()),
+            "loss_last": float(losses[-1].item())}
+
+
+def bench_batched(hz, torch, net, nsys=32, maxit=60):
+    """Ragged batch: nsys systems with the batched-serving size mix (128..512 interior + 16..32 PML),
+    BF16 network, FGMRES(30), advanced together for maxit iterations (bounded run)."""
+    from synth import H_10PPW, c4_sizes, c4_system
+    sizes = c4_sizes(128)[:nsys]
+    probs, bs = [], []
+    for k, (nx, p) in enumerate(sizes):
+        sy = c4_system(k, nx, p)
+        probs.append(hz.Problem(sy.c.astype(np.float32).ravel(), nx, nx, p, H_10PPW))
+        bs.append(torch.from_numpy(sy.b.ravel()).cuda())
+    ws = torch.empty(hz.fgmres_batched_workspace_bytes(probs, net, M_RESTART, maxit, "c64", "bf16"),
+                     dtype=torch.uint8, device="cuda")
+    hz.fgmres_batched(probs, bs, net=net, m=M_RESTART, tol=TOL, maxit=M_RESTART, workspace=ws)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, infos = hz.fgmres_batched(probs, bs, net=net, m=M_RESTART, tol=TOL, maxit=maxit, workspace=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    node_its = sum(i.its * p.n for i, p in zip(infos, probs))
+    steps = max(i.its for i in infos)
+    return {"workload": f"{nsys} systems of the batched-serving mix, BF16 U-Net, FGMRES(30), {maxit} iterations",
+            "nodes_total": int(sum(p.n for p in probs)), "seconds": round(dt, 3),
+            "ms_per_step": round(dt / steps * 1e3, 2),
+            "node_iterations_per_s": round(node_its / dt, 1),
+            "min_relres": min(i.true_relres for i in infos), "max_relres": max(i.true_relres for i in infos)}
+
+
 def cpu_baseline(system, theta, gpu_its, budget_s=20.0):
     """The FP64 oracle FGMRES on the same system and weights, timed over a bounded number of
     iterations and scaled to one solve of gpu_its iterations."""
@@ -136,9 +231,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp32-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the training and batched sections")
     ap.add_argument("--roofline-only", action="store_true", help="only the per-layer roofline timing")
     ap.add_argument("--roofline-layer", type=int, default=-1,
                     help="with --roofline-only: time this layer alone (for a profiler run of one kernel)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="with --roofline-only: also copy 512 MiB with a plain device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the single-solve workload is measured on one MI355X; "
@@ -169,11 +267,17 @@ def main():
     net_flops = sum(r["flops"] for r in layers)
     kname = "k_conv3<PolBF16, ...> (3x3 layer, autotuned variant)" if dom["kind"] == 0 else "k_convT2<PolBF16>"
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": measured_traffic(dom["layer"]),
                 "kernel": kname, "layer": dom["layer"],
                 "shape": f"{dom['cin']}->{dom['cout']} ch on {dom['H']}x{dom['W']}",
                 "flops_per_launch": dom["flops"], "avg_launch_ms": round(dom["ms"], 5)}
     if args.roofline_only:
+        if args.copy_calibration:
+            src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
         print(json.dumps({"roofline": roofline, "layers": layers}))
         return
 
@@ -238,6 +342,9 @@ def main():
                     f"fp32_{big}_hbm_gbs": round(20 * big * big / (st_big * 1e-3) / 1e9, 1),
                     "hbm_frac": round(20 * big * big / (st_big * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
     }
+    if not args.no_extra:
+        out["training"] = bench_training(hz, torch)
+        out["batched"] = bench_batched(hz, torch, net)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, theta, its)
     print(json.dumps(out))

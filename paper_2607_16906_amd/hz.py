@@ -223,6 +223,24 @@ class Net:
                "no_layer_forward")
 
 
+def init_shapes(levels: int, base: int, in_ch: int):
+    """(weight shape, fan-in, bias length) of every layer in the flat parameter order of hz.h
+    (input for a seeded initialiser)."""
+    out, cin = [], in_ch
+    for l in range(levels):
+        c = base << l
+        out.append(((c, cin, 3, 3), 9 * cin, c))
+        out.append(((c, c, 3, 3), 9 * c, c))
+        cin = c
+    for l in range(levels - 2, -1, -1):
+        c = base << l
+        out.append(((2 * c, c, 2, 2), 2 * c, c))
+        out.append(((c, 2 * c, 3, 3), 18 * c, c))
+        out.append(((c, c, 3, 3), 9 * c, c))
+    out.append(((2, base, 1, 1), base, 2))
+    return out
+
+
 def param_count(levels: int, base: int, in_ch: int) -> int:
     n = load_library().no_param_count(ct.byref(NoArch(levels, base, in_ch)))
     if n < 0:
