@@ -492,16 +492,18 @@ static void build_tables(const BatchPlan<P>& B, const no_net* net, const std::ve
                 case 4: io.x0 = fb.T1d[l]; io.y = fb.D[l]; break;
             }
         }
+        // channel blocks of one tile are neighbours in the job order (the kernel maps each XCD
+        // to a contiguous range of jobs, so they share the tile's input in one L2)
         for (int s : active) {
             const int H = B.S[s].Hp >> l, W = B.S[s].Wp >> l;
-            for (int co = 0; co < ly.cout_p; co += tn) {
-                if (convT) {
-                    for (int iy = 0; iy < H; ++iy)
-                        for (int ix = 0; ix < W; ix += 64) h.cjobs[li].push_back(TileJob{s, co, iy, ix});
-                } else {
-                    for (int ty = 0; ty < H; ty += 8)
-                        for (int tx = 0; tx < W; tx += 16) h.cjobs[li].push_back(TileJob{s, co, ty, tx});
-                }
+            if (convT) {
+                for (int iy = 0; iy < H; ++iy)
+                    for (int ix = 0; ix < W; ix += 64)
+                        for (int co = 0; co < ly.cout_p; co += tn) h.cjobs[li].push_back(TileJob{s, co, iy, ix});
+            } else {
+                for (int ty = 0; ty < H; ty += 8)
+                    for (int tx = 0; tx < W; tx += 16)
+                        for (int co = 0; co < ly.cout_p; co += tn) h.cjobs[li].push_back(TileJob{s, co, ty, tx});
             }
         }
     }

@@ -8,6 +8,15 @@ namespace hz {
 constexpr int CT = 256;        // threads per block (4 wavefronts)
 constexpr int TW = 16;          // pixel tile width of the 3x3 convolution (rows: 4 per-wave row count)
 
+// Consecutive workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Renumber the physical block id so that the blocks one XCD runs form one contiguous range of
+// the logical order (in which blocks that read the same input tile are neighbours).
+__device__ __forceinline__ int xcd_linear(int p, int n) {
+    const int q = n / 8, r = n % 8;
+    const int k = p % 8, i = p / 8;
+    return k * q + (k < r ? k : r) + i;
+}
+
 template <class P>
 constexpr int pix_stride() { return P::CK + 16 / (int)sizeof(typename P::T); }   // +16 B against bank conflicts
 
@@ -263,17 +272,24 @@ __global__ __launch_bounds__(CT) void k_conv3(const typename P::T* __restrict__ 
                                               const int* __restrict__ skip, Conv3Out ex, int nsplit,
                                               typename P::Acc* __restrict__ splitp, int64_t sstride) {
     if (skip && *skip) return;
+    // logical order: channel block fastest, then K split, column tile, row tile, sample
     const int ncb_tot = cout_p / TN;
-    const int zs = blockIdx.z % nsplit;
-    const int zz = blockIdx.z / nsplit;
-    const int bz = zz / ncb_tot;                 // sample
-    const int co0 = (zz - bz * ncb_tot) * TN;
+    const int nblk = gridDim.x * gridDim.y * gridDim.z;
+    int v = xcd_linear(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nblk);
+    const int cbi = v % ncb_tot;
+    v /= ncb_tot;
+    const int zs = v % nsplit;
+    v /= nsplit;
+    const int txi = v % gridDim.x;
+    v /= gridDim.x;
+    const int tyi = v % gridDim.y;
+    const int bz = v / gridDim.y;                // sample
+    const int co0 = cbi * TN;
     const int cin_p = c0 + c1;
     const int nch = cin_p / ck;
     const int kb = (nch * zs / nsplit) * ck, ke = (nch * (zs + 1) / nsplit) * ck;
     conv3_tile<P, TN, POOL, RPW>(x0, c0, x1, c1, w, bias, y, cout_p, ypool, H, W, relu, ck, ex, bz, co0,
-                                 blockIdx.y * 4 * RPW, blockIdx.x * TW, kb, ke,
-                                 splitp ? splitp + zs * sstride : nullptr);
+                                 tyi * 4 * RPW, txi * TW, kb, ke, splitp ? splitp + zs * sstride : nullptr);
 }
 
 // Ragged batch: block b runs job jobs[b] = (system, tile, channel block) with the system's tensors.
@@ -282,7 +298,7 @@ __global__ __launch_bounds__(CT) void k_conv3_jobs(const TileJob* __restrict__ j
                                                    const typename P::T* __restrict__ w,
                                                    const typename P::Acc* __restrict__ bias, int c0, int c1,
                                                    int cout_p, int relu, int ck) {
-    const TileJob jb = jobs[blockIdx.x];
+    const TileJob jb = jobs[xcd_linear(blockIdx.x, gridDim.x)];
     const LayerIO d = io[jb.sys];
     if (d.stop && *d.stop) return;
     conv3_tile<P, TN, POOL, 2>((const typename P::T*)d.x0, c0, (const typename P::T*)d.x1, c1, w, bias,
@@ -377,9 +393,15 @@ __global__ __launch_bounds__(CT) void k_convT2(const typename P::T* __restrict__
                                                const int* __restrict__ skip) {
     if (skip && *skip) return;
     const int ncb_tot = cout_p / TN;
-    const int bz = blockIdx.z / ncb_tot;
-    const int co0 = (blockIdx.z - bz * ncb_tot) * TN;
-    convT2_tile<P, TN>(x, cin_p, w, bias, y, cout_p, H, W, ck, bz, co0, blockIdx.y, blockIdx.x * 64);
+    const int nblk = gridDim.x * gridDim.y * gridDim.z;
+    int v = xcd_linear(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nblk);
+    const int cbi = v % ncb_tot;
+    v /= ncb_tot;
+    const int txi = v % gridDim.x;
+    v /= gridDim.x;
+    const int tyi = v % gridDim.y;
+    const int bz = v / gridDim.y;
+    convT2_tile<P, TN>(x, cin_p, w, bias, y, cout_p, H, W, ck, bz, cbi * TN, tyi, txi * 64);
 }
 
 template <class P, int TN>
@@ -387,7 +409,7 @@ __global__ __launch_bounds__(CT) void k_convT2_jobs(const TileJob* __restrict__ 
                                                     const typename P::T* __restrict__ w,
                                                     const typename P::Acc* __restrict__ bias, int cin_p, int cout_p,
                                                     int ck) {
-    const TileJob jb = jobs[blockIdx.x];
+    const TileJob jb = jobs[xcd_linear(blockIdx.x, gridDim.x)];
     const LayerIO d = io[jb.sys];
     if (d.stop && *d.stop) return;
     convT2_tile<P, TN>((const typename P::T*)d.x0, cin_p, w, bias, (typename P::T*)d.y, cout_p, d.H, d.W, ck, 0, jb.c0,
