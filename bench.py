@@ -335,7 +335,9 @@ def main():
         "speedup_bf16_vs_fp32": round(ms32 / ms_step, 3),
         "roofline": roofline,
         "network": {"ms_per_apply_layers": round(net_ms, 4), "tflops_layers": round(net_flops / net_ms * 1e-9, 2),
-                    "gflop_per_apply": round(net_flops * 1e-9, 3)},
+                    "gflop_per_apply": round(net_flops * 1e-9, 3),
+                    "layer_us": [[r["layer"], "conv3" if r["kind"] == 0 else "convT2", r["cin"], r["cout"], r["H"],
+                                  round(r["ms"] * 1e3, 2)] for r in layers]},
         "stencil": {"fp32_296_us": round(st_ms * 1e3, 2),
                     "fp32_296_gbs_in_cache": round(20 * 296 * 296 / (st_ms * 1e-3) / 1e9, 1),
                     f"fp32_{big}_us": round(st_big * 1e3, 2),

@@ -87,7 +87,10 @@ static int cycle_launches(const hz_problem* p, const no_net* net, const hz_opts*
     auto vcol = [&](int i) { return (void*)((char*)L.V + es * n * i); };
     auto zcol = [&](int i) { return L.Z ? (void*)((char*)L.Z + es * n * i) : vcol(i); };
     for (int j = 0; j < steps; ++j) {
-        if (net) HZ_TRY(net_precond(net, p, o->net_prec, c128, vcol(j), zcol(j), L.net_ws, L.net_ws_bytes, stop, s, true));
+        // z_j = N(v_j); for j >= 1 the network's input pass first completes v_j = w / h_{j,j-1}
+        if (net)
+            HZ_TRY(net_precond(net, p, o->net_prec, c128, vcol(j), zcol(j), L.net_ws, L.net_ws_bytes, stop, s, true,
+                               j > 0 ? &kb.st->inv_h : nullptr));
         // w = A z_j, written into the slot of v_{j+1}
         void* w = vcol(j + 1);
         HZ_TRY(launch_stencil(p, c128, false, zcol(j), w, s, stop));
@@ -97,7 +100,8 @@ static int cycle_launches(const hz_problem* p, const no_net* net, const hz_opts*
         HZ_TRY(launch_finalize(kb.part, sp.nblk, kb.ldp, j + 1, kb.h2, stop, s));
         HZ_TRY(launch_update(c128, L.V, n, j + 1, kb.h2, w, n, sp, kb.part, kb.ldp, 2, stop, s));
         HZ_TRY(launch_arnoldi_finish(kb, j, sp.nblk, true, s));
-        HZ_TRY(launch_scale(c128, w, n, &kb.st->inv_h, stop, s));
+        // without a network the next step's matvec reads v_{j+1} directly
+        if (!net) HZ_TRY(launch_scale(c128, w, n, &kb.st->inv_h, stop, s));
     }
     HZ_TRY(launch_backsolve(kb, s));
     HZ_TRY(launch_xupdate(c128, zcol(0), n, x, n, kb, s));

@@ -55,8 +55,11 @@ void net_padded_dims(const no_net* net, const hz_problem* p, int* Hp, int* Wp);
 size_t net_fwd_ws_bytes(const no_net* net, int Hp, int Wp, int batch, no_prec prec);
 // z = N(v) for one field (c128: complex128 vectors, else complex64). skip: optional device flag.
 // unit_norm: v is a Krylov vector of norm 1, so s = 1 / sqrt(n) without a reduction.
+// vscale (device scalar, with unit_norm only): v is first scaled in place by *vscale, which
+// makes it of norm 1 (the Arnoldi normalisation v_{j+1} = w / h_{j+1,j} done here).
 int net_precond(const no_net* net, const hz_problem* p, no_prec prec, bool c128, const void* v, void* z,
-                void* ws, size_t ws_bytes, const int* skip, hipStream_t s, bool unit_norm = false);
+                void* ws, size_t ws_bytes, const int* skip, hipStream_t s, bool unit_norm = false,
+                const double* vscale = nullptr);
 // Time every launch variant of every 3x3 layer at this problem's size (batch 1) on the forward
 // workspace and remember the fastest; returns HZ_OK at once when already tuned. Synchronises.
 int net_autotune(const no_net* net, const hz_problem* p, no_prec prec, void* ws, size_t ws_bytes, hipStream_t s);

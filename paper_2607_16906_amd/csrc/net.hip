@@ -173,8 +173,13 @@ __global__ void k_head(const typename P::T* __restrict__ D, int cin_p, const typ
 
 template <class P>
 static int precond_impl(const no_net* net, const hz_problem* p, bool c128, const void* v, void* z, void* ws,
-                        size_t ws_bytes, const int* skip, hipStream_t s, bool unit_norm) {
+                        size_t ws_bytes, const int* skip, hipStream_t s, bool unit_norm,
+                        const double* vscale) {
     using T = typename P::T;
+    if (vscale && !unit_norm) {
+        set_error("no_precond_apply: in-place scaling needs a unit-norm result");
+        return HZ_ERR_ARG;
+    }
     int Hp, Wp;
     net_padded_dims(net, p, &Hp, &Wp);
     FwdBufs b = fwd_layout<P>(net, Hp, Wp, 1, ws, ws_bytes);
@@ -194,10 +199,12 @@ static int precond_impl(const no_net* net, const hz_problem* p, bool c128, const
     const unsigned gp = (unsigned)(((int64_t)Hp * Wp + 255) / 256);
     if (c128)
         hipLaunchKernelGGL((k_pack<P, double2>), dim3(gp), dim3(256), 0, s, (const double2*)v, b.sc, p->cnd, p->sigx,
-                           p->sigy, p->nxt, p->nyt, Hp, Wp, net->a.in_ch, (T*)b.X, skip, fixed_s);
+                           p->sigy, p->nxt, p->nyt, Hp, Wp, net->a.in_ch, (T*)b.X, skip, fixed_s, vscale,
+                           vscale ? (double2*)v : nullptr);
     else
         hipLaunchKernelGGL((k_pack<P, float2>), dim3(gp), dim3(256), 0, s, (const float2*)v, b.sc, p->cnd, p->sigx,
-                           p->sigy, p->nxt, p->nyt, Hp, Wp, net->a.in_ch, (T*)b.X, skip, fixed_s);
+                           p->sigy, p->nxt, p->nyt, Hp, Wp, net->a.in_ch, (T*)b.X, skip, fixed_s, vscale,
+                           vscale ? (float2*)v : nullptr);
     HZ_LAUNCH_CHECK();
     HZ_TRY(unet_body<P>(net, b, Hp, Wp, 1, skip, s));
     const Layer& lh = net->layers.back();
@@ -328,11 +335,11 @@ size_t net_fwd_ws_bytes(const no_net* net, int Hp, int Wp, int batch, no_prec pr
 }
 
 int net_precond(const no_net* net, const hz_problem* p, no_prec prec, bool c128, const void* v, void* z, void* ws,
-                size_t ws_bytes, const int* skip, hipStream_t s, bool unit_norm) {
+                size_t ws_bytes, const int* skip, hipStream_t s, bool unit_norm, const double* vscale) {
     switch (prec) {
-        case NO_BF16: return precond_impl<PolBF16>(net, p, c128, v, z, ws, ws_bytes, skip, s, unit_norm);
-        case NO_FP32: return precond_impl<PolF32>(net, p, c128, v, z, ws, ws_bytes, skip, s, unit_norm);
-        case NO_FP64: return precond_impl<PolF64>(net, p, c128, v, z, ws, ws_bytes, skip, s, unit_norm);
+        case NO_BF16: return precond_impl<PolBF16>(net, p, c128, v, z, ws, ws_bytes, skip, s, unit_norm, vscale);
+        case NO_FP32: return precond_impl<PolF32>(net, p, c128, v, z, ws, ws_bytes, skip, s, unit_norm, vscale);
+        case NO_FP64: return precond_impl<PolF64>(net, p, c128, v, z, ws, ws_bytes, skip, s, unit_norm, vscale);
     }
     set_error("no_precond_apply: bad precision");
     return HZ_ERR_ARG;

@@ -17,7 +17,7 @@ template <class P, typename C>
 __global__ void k_pack(const C* __restrict__ v, const double* __restrict__ sc, const double* __restrict__ cnd,
                        const double* __restrict__ sigx, const double* __restrict__ sigy, int nxt, int nyt, int Hp,
                        int Wp, int in_ch, typename P::T* __restrict__ X, const int* __restrict__ skip,
-                       double fixed_s = 0.0) {
+                       double fixed_s = 0.0, const double* __restrict__ vscale = nullptr, C* vout = nullptr) {
     using T = typename P::T;
     if (skip && *skip) return;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -29,7 +29,12 @@ __global__ void k_pack(const C* __restrict__ v, const double* __restrict__ sc, c
     if (yy < nyt && xx < nxt) {
         const int64_t g = (int64_t)yy * nxt + xx;
         const double is = fixed_s > 0 ? 1.0 / fixed_s : sc[1];
-        const C a = v[g];
+        C a = v[g];
+        if (vscale) {   // v <- vscale v first (rounded to the vector precision, stored back)
+            const double f = *vscale;
+            a = from_d2<C>(double2{a.x * f, a.y * f});
+            vout[g] = a;
+        }
         out[0] = P::cvt((typename P::Acc)((double)a.x * is));
         out[1] = P::cvt((typename P::Acc)((double)a.y * is));
         if (in_ch == 5) {

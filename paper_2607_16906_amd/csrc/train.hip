@@ -17,6 +17,7 @@
 // fixed order (deterministic).
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "krylov.h"
@@ -175,19 +176,20 @@ __global__ void k_head_wgrad(const float2* __restrict__ gz, const float* __restr
     }
 }
 
+// One wavefront per output (2 cin weights, then 2 biases): lanes sum strided chunks, then a
+// fixed-order wavefront sum.
 __global__ void k_head_reduce(const float* __restrict__ part, int nchunk, int cin_p, Layer ly, float* __restrict__ grad) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int ln = threadIdx.x & 63;
     const int nw = ly.cout * ly.cin;   // [2][cin]
-    if (t < nw) {
-        const int k = t / ly.cin, c = t % ly.cin;
-        float a = 0;
-        for (int z = 0; z < nchunk; ++z) a += part[(int64_t)z * (2 * cin_p + 2) + k * cin_p + c];
-        grad[ly.w_off + t] = a;
-    } else if (t < nw + 2) {
-        const int k = t - nw;
-        float a = 0;
-        for (int z = 0; z < nchunk; ++z) a += part[(int64_t)z * (2 * cin_p + 2) + 2 * cin_p + k];
-        grad[ly.b_off + k] = a;
+    if (t >= nw + 2) return;
+    const int slot = t < nw ? (t / ly.cin) * cin_p + t % ly.cin : 2 * cin_p + (t - nw);
+    float a = 0;
+    for (int z = ln; z < nchunk; z += 64) a += part[(int64_t)z * (2 * cin_p + 2) + slot];
+    a = wave_sum(a);
+    if (ln == 0) {
+        if (t < nw) grad[ly.w_off + t] = a;
+        else grad[ly.b_off + (t - nw)] = a;
     }
 }
 
@@ -254,6 +256,118 @@ __global__ __launch_bounds__(TT) void k_wgrad3(const typename P::T* __restrict__
     if (blockIdx.x == 0 && tci == 0) partb[(int64_t)z * cout_p + co] = accb;
 }
 
+// 3x3 on the matrix cores (BF16 operands, FP32 accumulation): for every tap (dy, dx),
+// dW[co][ci][tap] = sum_p G[p][co] X[p + (dy - 1, dx - 1)][ci] is a product with the pixels as
+// the reduction index. Block: 32 output x 32 input channels over its chunk of 8 x 16 pixel
+// tiles. Each tile is staged in LDS transposed (pixels contiguous per channel) so that a lane's
+// 8 consecutive reduction elements are one 16-byte read; the input patch is stored three times,
+// shifted by dx, to keep those reads aligned. Wavefront w owns the 16 x 16 channel pair
+// (w / 2, w % 2) for all 9 taps. Partials and bias sums as in k_wgrad3.
+constexpr int WG_CO = 32, WG_CI = 32;
+constexpr int WG_GS = 128 + 8;              // LDS row of Gt: 128 pixels (+16 B)
+constexpr int WG_XS = 10 * 16 + 8;          // LDS plane of one channel of Xt: 10 rows x 16 (+16 B)
+
+__global__ __launch_bounds__(TT) void k_wgrad3_mfma(const bf16_t* __restrict__ G, int cout_p,
+                                                    const bf16_t* __restrict__ x0, int c0,
+                                                    const bf16_t* __restrict__ x1, int c1, int H, int W,
+                                                    int ntiles, int tpc, float* __restrict__ part,
+                                                    float* __restrict__ partb) {
+    __shared__ __attribute__((aligned(16))) bf16_t gt[WG_CO * WG_GS];
+    __shared__ __attribute__((aligned(16))) bf16_t xt[3 * WG_CI * WG_XS];
+    const int cin_p = c0 + c1;
+    const int ci0 = blockIdx.x * WG_CI, co0 = blockIdx.y * WG_CO;
+    const int z = blockIdx.z;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lr = lane & 15, kg = lane >> 4;
+    const int cob = wv >> 1, cib = wv & 1;
+    const int tx_n = (W + 15) / 16, ty_n = (H + 7) / 8;
+    const int per_img = tx_n * ty_n;
+    const int64_t plane = (int64_t)H * W;
+    f32x4_t acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[t][r] = 0.f;
+    float accb = 0.f;                            // bias: thread sums 16 pixels of channel threadIdx.x / 8
+    const int t_end = min(ntiles, (z + 1) * tpc);
+    for (int tile = z * tpc; tile < t_end; ++tile) {
+        const int b = tile / per_img, r = tile - b * per_img;
+        const int ty0 = (r / tx_n) * 8, tx0 = (r % tx_n) * 16;
+        __syncthreads();
+        // G tile: 128 pixels x 32 channels, 4 vectors of 8 channels per pixel
+        for (int v = threadIdx.x; v < 128 * 4; v += TT) {
+            const int px = v >> 2, part8 = v & 3;
+            const int gy = ty0 + (px >> 4), gx = tx0 + (px & 15);
+            const int co = co0 + part8 * 8;
+            uint4 val = uint4{0, 0, 0, 0};
+            if (gy < H && gx < W && co < cout_p)
+                val = *(const uint4*)(G + ((int64_t)b * plane + (int64_t)gy * W + gx) * cout_p + co);
+            const bf16_t* e = (const bf16_t*)&val;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) gt[(part8 * 8 + k) * WG_GS + px] = e[k];
+        }
+        // input patch: 10 x 18 pixels x 32 channels; copy dx holds column c + dx at column c
+        for (int v = threadIdx.x; v < 180 * 4; v += TT) {
+            const int px = v >> 2, part8 = v & 3;
+            const int py = px / 18, pc = px - py * 18;
+            const int gy = ty0 + py - 1, gx = tx0 + pc - 1;
+            const int ci = ci0 + part8 * 8;
+            uint4 val = uint4{0, 0, 0, 0};
+            if (gy >= 0 && gy < H && gx >= 0 && gx < W && ci < cin_p) {
+                const int64_t pix = (int64_t)b * plane + (int64_t)gy * W + gx;
+                val = *(const uint4*)(ci < c0 ? x0 + pix * c0 + ci : x1 + pix * c1 + (ci - c0));
+            }
+            const bf16_t* e = (const bf16_t*)&val;
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int c = pc - dx;
+                if (c >= 0 && c < 16) {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) xt[(dx * WG_CI + part8 * 8 + k) * WG_XS + py * 16 + c] = e[k];
+                }
+            }
+        }
+        __syncthreads();
+        if (blockIdx.x == 0) {
+            const int co = threadIdx.x >> 3, seg = threadIdx.x & 7;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) accb += bf2f(gt[co * WG_GS + seg * 16 + k]);
+        }
+        // 4 reduction steps of 32 pixels (tile rows 2s, 2s + 1)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int row = 2 * s + (kg >> 1), col = 8 * (kg & 1);
+            const bf16x8_t a = PolBF16::load(&gt[(cob * 16 + lr) * WG_GS + 32 * s + 8 * kg]);
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int dy = t / 3, dx = t % 3;
+                const bf16x8_t bb = PolBF16::load(&xt[(dx * WG_CI + cib * 16 + lr) * WG_XS + (row + dy) * 16 + col]);
+                acc[t] = PolBF16::mma(a, bb, acc[t]);
+            }
+        }
+    }
+    // lane holds D[co = co0 + 16 cob + 4 kg + r][ci = ci0 + 16 cib + lr] of every tap
+    const int ci = ci0 + cib * 16 + lr;
+    if (ci < cin_p) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int co = co0 + cob * 16 + 4 * kg + r;
+            if (co < cout_p) {
+                float* dst = part + (((int64_t)z * cout_p + co) * cin_p + ci) * 9;
+#pragma unroll
+                for (int t = 0; t < 9; ++t) dst[t] = acc[t][r];
+            }
+        }
+    }
+    if (blockIdx.x == 0) {
+        accb += __shfl_xor(accb, 1, 64);
+        accb += __shfl_xor(accb, 2, 64);
+        accb += __shfl_xor(accb, 4, 64);
+        const int co = co0 + (threadIdx.x >> 3);
+        if ((threadIdx.x & 7) == 0 && co < cout_p) partb[(int64_t)z * cout_p + co] = accb;
+    }
+}
+
 // Transposed 2x2: dW[ab][co][ci] = sum_i G[2i + ab][co] x[i][ci]; block: ci tile, co tile, chunk of
 // 8 x 8 input tiles.
 template <class P>
@@ -307,12 +421,113 @@ __global__ __launch_bounds__(TT) void k_wgradT(const typename P::T* __restrict__
     if (blockIdx.x == 0 && tci == 0) partb[(int64_t)z * cout_p + co] = accb;
 }
 
+// Transposed 2x2 on the matrix cores: for every output parity ab, dW[ab][co][ci] =
+// sum_i G[2i + ab][co] x[i][ci] with the coarse pixels i as the reduction index. Block: 32 x 32
+// channels over its chunk of 8 x 16 coarse tiles, staged transposed in LDS as in k_wgrad3_mfma;
+// wavefront w owns the channel pair (w / 2, w % 2) for the 4 parities.
+__global__ __launch_bounds__(TT) void k_wgradT_mfma(const bf16_t* __restrict__ G, int cout_p,
+                                                    const bf16_t* __restrict__ x, int cin_p, int H, int W,
+                                                    int ntiles, int tpc, float* __restrict__ part,
+                                                    float* __restrict__ partb) {
+    __shared__ __attribute__((aligned(16))) bf16_t gt[4 * WG_CO * WG_GS];
+    __shared__ __attribute__((aligned(16))) bf16_t xt[WG_CI * WG_GS];
+    const int ci0 = blockIdx.x * WG_CI, co0 = blockIdx.y * WG_CO;
+    const int z = blockIdx.z;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lr = lane & 15, kg = lane >> 4;
+    const int cob = wv >> 1, cib = wv & 1;
+    const int tx_n = (W + 15) / 16, ty_n = (H + 7) / 8;
+    const int per_img = tx_n * ty_n;
+    const int64_t plane = (int64_t)H * W;
+    f32x4_t acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[t][r] = 0.f;
+    float accb = 0.f;
+    const int t_end = min(ntiles, (z + 1) * tpc);
+    for (int tile = z * tpc; tile < t_end; ++tile) {
+        const int b = tile / per_img, r = tile - b * per_img;
+        const int ty0 = (r / tx_n) * 8, tx0 = (r % tx_n) * 16;
+        __syncthreads();
+        // G at the 4 fine pixels of each of the 128 coarse pixels, 4 vectors of 8 channels each
+        for (int v = threadIdx.x; v < 128 * 4 * 4; v += TT) {
+            const int part8 = v & 3, ab = (v >> 2) & 3, px = v >> 4;
+            const int iy = ty0 + (px >> 4), ix = tx0 + (px & 15);
+            const int co = co0 + part8 * 8;
+            uint4 val = uint4{0, 0, 0, 0};
+            if (iy < H && ix < W && co < cout_p) {
+                const int oy = 2 * iy + (ab >> 1), ox = 2 * ix + (ab & 1);
+                val = *(const uint4*)(G + ((int64_t)b * 4 * plane + (int64_t)oy * 2 * W + ox) * cout_p + co);
+            }
+            const bf16_t* e = (const bf16_t*)&val;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) gt[(ab * WG_CO + part8 * 8 + k) * WG_GS + px] = e[k];
+        }
+        for (int v = threadIdx.x; v < 128 * 4; v += TT) {
+            const int part8 = v & 3, px = v >> 2;
+            const int iy = ty0 + (px >> 4), ix = tx0 + (px & 15);
+            const int ci = ci0 + part8 * 8;
+            uint4 val = uint4{0, 0, 0, 0};
+            if (iy < H && ix < W && ci < cin_p)
+                val = *(const uint4*)(x + ((int64_t)b * plane + (int64_t)iy * W + ix) * cin_p + ci);
+            const bf16_t* e = (const bf16_t*)&val;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) xt[(part8 * 8 + k) * WG_GS + px] = e[k];
+        }
+        __syncthreads();
+        if (blockIdx.x == 0) {
+            const int co = threadIdx.x >> 3, seg = threadIdx.x & 7;
+#pragma unroll
+            for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+                for (int k = 0; k < 16; ++k) accb += bf2f(gt[(ab * WG_CO + co) * WG_GS + seg * 16 + k]);
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const bf16x8_t bb = PolBF16::load(&xt[(cib * 16 + lr) * WG_GS + 32 * s + 8 * kg]);
+#pragma unroll
+            for (int ab = 0; ab < 4; ++ab) {
+                const bf16x8_t a = PolBF16::load(&gt[(ab * WG_CO + cob * 16 + lr) * WG_GS + 32 * s + 8 * kg]);
+                acc[ab] = PolBF16::mma(a, bb, acc[ab]);
+            }
+        }
+    }
+    const int ci = ci0 + cib * 16 + lr;
+    if (ci < cin_p) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int co = co0 + cob * 16 + 4 * kg + r;
+            if (co < cout_p) {
+                float* dst = part + (((int64_t)z * cout_p + co) * cin_p + ci) * 4;
+#pragma unroll
+                for (int ab = 0; ab < 4; ++ab) dst[ab] = acc[ab][r];
+            }
+        }
+    }
+    if (blockIdx.x == 0) {
+        accb += __shfl_xor(accb, 1, 64);
+        accb += __shfl_xor(accb, 2, 64);
+        accb += __shfl_xor(accb, 4, 64);
+        const int co = co0 + (threadIdx.x >> 3);
+        if ((threadIdx.x & 7) == 0 && co < cout_p) partb[(int64_t)z * cout_p + co] = accb;
+    }
+}
+
 // Sum the chunk partials of one layer into the flat FP32 gradient (logical channels).
-__global__ void k_wgrad_reduce(const float* __restrict__ part, const float* __restrict__ partb, int nchunk,
-                               Layer ly, float* __restrict__ grad) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// grad[...] = sum over the nchunk partials, in a fixed order: a block covers 32 consecutive
+// outputs; thread group g (of 8) sums the chunks z = g mod 8, and the 8 group sums are added
+// in order g = 0..7.
+constexpr int WR_OUT = 32, WR_GRP = 8;
+__global__ __launch_bounds__(WR_OUT * WR_GRP) void k_wgrad_reduce(const float* __restrict__ part,
+                                                                 const float* __restrict__ partb, int nchunk,
+                                                                 Layer ly, float* __restrict__ grad) {
+    __shared__ float red[WR_GRP][WR_OUT];
+    const int o = threadIdx.x % WR_OUT, g = threadIdx.x / WR_OUT;
+    const int64_t t = (int64_t)blockIdx.x * WR_OUT + o;
     const int taps = ly.kind == L_CONV3 ? 9 : 4;
     const int64_t nw = (int64_t)taps * ly.cin * ly.cout;
+    float a = 0;
     if (t < nw) {
         int co, ci, tap;
         if (ly.kind == L_CONV3) {         // flat [co][ci][tap]
@@ -326,14 +541,20 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, const float* __re
         }
         int cis = ci;                     // stored channel of a concatenated input
         if (ly.cat_cp > 0 && ci >= ly.cat_c) cis = ly.cat_cp + (ci - ly.cat_c);
-        float a = 0;
-        for (int z = 0; z < nchunk; ++z) a += part[(((int64_t)z * ly.cout_p + co) * ly.cin_p + cis) * taps + tap];
-        grad[ly.w_off + t] = a;
+        for (int z = g; z < nchunk; z += WR_GRP)
+            a += part[(((int64_t)z * ly.cout_p + co) * ly.cin_p + cis) * taps + tap];
     } else if (t < nw + ly.cout) {
         const int co = (int)(t - nw);
-        float a = 0;
-        for (int z = 0; z < nchunk; ++z) a += partb[(int64_t)z * ly.cout_p + co];
-        grad[ly.b_off + co] = a;
+        for (int z = g; z < nchunk; z += WR_GRP) a += partb[(int64_t)z * ly.cout_p + co];
+    }
+    red[g][o] = a;
+    __syncthreads();
+    if (g == 0 && t < nw + ly.cout) {
+        float sum = 0;
+#pragma unroll
+        for (int k = 0; k < WR_GRP; ++k) sum += red[k][o];
+        if (t < nw) grad[ly.w_off + t] = sum;
+        else grad[ly.b_off + (t - nw)] = sum;
     }
 }
 
@@ -449,10 +670,12 @@ struct TrainBufs {
     double *sc, *nr;                 // [B][2], [B]
     float* coef;                     // [B]
     float *wpart, *wpartb;           // weight-gradient chunk partials
+    size_t wcap, bcap;               // their capacities (floats)
     size_t total;
 };
 
-constexpr int WCHUNKS = 64;
+constexpr int WCHUNKS = 64;          // pixel chunks of the scalar weight-gradient kernels
+constexpr int WCHUNKS_MAX = 1024;    // upper bound of the matrix-core and head chunk counts
 
 template <class P>
 static TrainBufs<P> train_layout(const no_net* net, const hz_problem* p, int B, void* base, size_t cap) {
@@ -493,8 +716,13 @@ static TrainBufs<P> train_layout(const no_net* net, const hz_problem* p, int B, 
         wmax = std::max(wmax, (size_t)WCHUNKS * taps * ly.cout_p * ly.cin_p);
         bmax = std::max(bmax, (size_t)WCHUNKS * (ly.cout_p + 2 * ly.cin_p + 2));
     }
+    // the head's partials: one row of 2 cin_p + 2 per chunk
+    const Layer& lh = net->layers.back();
+    bmax = std::max(bmax, (size_t)WCHUNKS_MAX * (2 * lh.cin_p + 2));
     t.wpart = c.take<float>(wmax);
     t.wpartb = c.take<float>(bmax);
+    t.wcap = wmax;
+    t.bcap = bmax;
     t.total = c.off + 256;
     return t;
 }
@@ -506,15 +734,30 @@ static int wgrad_conv3(const Layer& ly, const typename P::T* G, const typename P
                        const typename P::T* x1, int c1, int H, int W, int B, TrainBufs<P>& t, float* grad,
                        hipStream_t s) {
     const int ntiles = ((W + 15) / 16) * ((H + 7) / 8) * B;
-    const int tpc = (ntiles + WCHUNKS - 1) / WCHUNKS;
-    const int nchunk = (ntiles + tpc - 1) / tpc;
-    dim3 grid((ly.cin_p + 15) / 16, ly.cout_p / 16, nchunk);
-    hipLaunchKernelGGL(k_wgrad3<P>, grid, dim3(TT), 0, s, G, ly.cout_p, x0, c0, x1, c1, H, W, ntiles, tpc, t.wpart,
-                       t.wpartb);
+    int nchunk;
+    if constexpr (std::is_same<P, PolBF16>::value) {
+        // matrix-core form: about 1024 blocks, as many chunks as the partial buffer holds
+        const int ctiles = ((ly.cin_p + WG_CI - 1) / WG_CI) * ((ly.cout_p + WG_CO - 1) / WG_CO);
+        const size_t per_chunk = (size_t)9 * ly.cout_p * ly.cin_p;
+        int want = std::min(512, std::max(1, (1024 + ctiles - 1) / ctiles));
+        want = (int)std::min<size_t>((size_t)want, t.wcap / per_chunk);
+        want = std::min(want, (int)std::min<size_t>((size_t)WCHUNKS_MAX, t.bcap / (size_t)ly.cout_p));
+        const int tpc = (ntiles + want - 1) / want;
+        nchunk = (ntiles + tpc - 1) / tpc;
+        dim3 grid((ly.cin_p + WG_CI - 1) / WG_CI, (ly.cout_p + WG_CO - 1) / WG_CO, nchunk);
+        hipLaunchKernelGGL(k_wgrad3_mfma, grid, dim3(TT), 0, s, G, ly.cout_p, x0, c0, x1, c1, H, W, ntiles, tpc,
+                           t.wpart, t.wpartb);
+    } else {
+        const int tpc = (ntiles + WCHUNKS - 1) / WCHUNKS;
+        nchunk = (ntiles + tpc - 1) / tpc;
+        dim3 grid((ly.cin_p + 15) / 16, ly.cout_p / 16, nchunk);
+        hipLaunchKernelGGL(k_wgrad3<P>, grid, dim3(TT), 0, s, G, ly.cout_p, x0, c0, x1, c1, H, W, ntiles, tpc,
+                           t.wpart, t.wpartb);
+    }
     HZ_LAUNCH_CHECK();
     const int64_t nout = (int64_t)9 * ly.cin * ly.cout + ly.cout;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, t.wpart, t.wpartb,
-                       nchunk, ly, grad);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nout + WR_OUT - 1) / WR_OUT)), dim3(WR_OUT * WR_GRP), 0, s,
+                       t.wpart, t.wpartb, nchunk, ly, grad);
     HZ_LAUNCH_CHECK();
     return HZ_OK;
 }
@@ -522,16 +765,31 @@ static int wgrad_conv3(const Layer& ly, const typename P::T* G, const typename P
 template <class P>
 static int wgrad_convT(const Layer& ly, const typename P::T* G, const typename P::T* x, int H, int W, int B,
                        TrainBufs<P>& t, float* grad, hipStream_t s) {
-    const int ntiles = ((W + 7) / 8) * ((H + 7) / 8) * B;
-    const int tpc = (ntiles + WCHUNKS - 1) / WCHUNKS;
-    const int nchunk = (ntiles + tpc - 1) / tpc;
-    dim3 grid(ly.cin_p / 16, ly.cout_p / 16, nchunk);
-    hipLaunchKernelGGL(k_wgradT<P>, grid, dim3(TT), 0, s, G, ly.cout_p, x, ly.cin_p, H, W, ntiles, tpc, t.wpart,
-                       t.wpartb);
+    int nchunk;
+    if constexpr (std::is_same<P, PolBF16>::value) {
+        const int ntiles = ((W + 15) / 16) * ((H + 7) / 8) * B;
+        const int ctiles = ((ly.cin_p + WG_CI - 1) / WG_CI) * ((ly.cout_p + WG_CO - 1) / WG_CO);
+        const size_t per_chunk = (size_t)4 * ly.cout_p * ly.cin_p;
+        int want = std::min(512, std::max(1, (1024 + ctiles - 1) / ctiles));
+        want = (int)std::min<size_t>((size_t)want, t.wcap / per_chunk);
+        want = std::min(want, (int)std::min<size_t>((size_t)WCHUNKS_MAX, t.bcap / (size_t)ly.cout_p));
+        const int tpc = (ntiles + want - 1) / want;
+        nchunk = (ntiles + tpc - 1) / tpc;
+        dim3 grid((ly.cin_p + WG_CI - 1) / WG_CI, (ly.cout_p + WG_CO - 1) / WG_CO, nchunk);
+        hipLaunchKernelGGL(k_wgradT_mfma, grid, dim3(TT), 0, s, G, ly.cout_p, x, ly.cin_p, H, W, ntiles, tpc,
+                           t.wpart, t.wpartb);
+    } else {
+        const int ntiles = ((W + 7) / 8) * ((H + 7) / 8) * B;
+        const int tpc = (ntiles + WCHUNKS - 1) / WCHUNKS;
+        nchunk = (ntiles + tpc - 1) / tpc;
+        dim3 grid(ly.cin_p / 16, ly.cout_p / 16, nchunk);
+        hipLaunchKernelGGL(k_wgradT<P>, grid, dim3(TT), 0, s, G, ly.cout_p, x, ly.cin_p, H, W, ntiles, tpc,
+                           t.wpart, t.wpartb);
+    }
     HZ_LAUNCH_CHECK();
     const int64_t nout = (int64_t)4 * ly.cin * ly.cout + ly.cout;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, t.wpart, t.wpartb,
-                       nchunk, ly, grad);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nout + WR_OUT - 1) / WR_OUT)), dim3(WR_OUT * WR_GRP), 0, s,
+                       t.wpart, t.wpartb, nchunk, ly, grad);
     HZ_LAUNCH_CHECK();
     return HZ_OK;
 }
@@ -627,12 +885,13 @@ static int loss_backward_impl(const no_net* net, int B, const hz_problem* const*
                            D0, cs0, packed_w<P>(net, lh), p0->nxt, p0->nyt, Hp, Wp, B, G0);
         HZ_LAUNCH_CHECK();
         const int64_t np = (int64_t)B * Hp * Wp;
-        const int64_t per = (np + WCHUNKS - 1) / WCHUNKS;
+        const int64_t per = (np + WCHUNKS_MAX - 1) / WCHUNKS_MAX;
         const int nchunk = (int)((np + per - 1) / per);
         hipLaunchKernelGGL(k_head_wgrad<P>, dim3(nchunk), dim3(TT), 0, s, t.gz, t.coef, t.sc, D0, cs0, p0->nxt,
                            p0->nyt, Hp, Wp, B, per, t.wpartb);
         HZ_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_head_reduce, dim3(1), dim3(256), 0, s, t.wpartb, nchunk, cs0, lh, grad);
+        hipLaunchKernelGGL(k_head_reduce, dim3((unsigned)((lh.cout * lh.cin + 2 + 3) / 4)), dim3(256), 0, s, t.wpartb,
+                           nchunk, cs0, lh, grad);
         HZ_LAUNCH_CHECK();
     }
     // layer indices in the flat order
