@@ -134,23 +134,14 @@ __global__ __launch_bounds__(KT) void kb_update(const TileJob* __restrict__ jobs
 }
 
 // per-system reductions: one block of 256 threads per active system
-__global__ __launch_bounds__(KT) void kb_finalize(const KDesc* __restrict__ kd, const int* __restrict__ act, int cnt,
+// block (system, value)
+__global__ __launch_bounds__(KT) void kb_finalize(const KDesc* __restrict__ kd, const int* __restrict__ act,
                                                   int which) {
     const KDesc& d = kd[act[blockIdx.x]];
     if (d.st->stop) return;
     double2* out = which == 1 ? d.h1 : d.h2;
-    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-    for (int i = wv; i < cnt; i += KT / 64) {
-        double a = 0, b = 0;
-        for (int q = ln; q < d.nblk; q += 64) {
-            const double2 v = d.part[(int64_t)q * d.ldp + i];
-            a += v.x;
-            b += v.y;
-        }
-        a = wave_sum(a);
-        b = wave_sum(b);
-        if (ln == 0) out[i] = double2{a, b};
-    }
+    const double2 v = block_sum_slot(d.part, d.nblk, d.ldp, blockIdx.y);
+    if (threadIdx.x == 0) out[blockIdx.y] = v;
 }
 
 __global__ void kb_arnoldi_finish(const KDesc* __restrict__ kd, const int* __restrict__ act, int j) {
@@ -572,9 +563,9 @@ static int cycle_launches(const BatchPlan<P>& B, const HostTables<P>& h, const n
         if (net) HZ_TRY((net_step<P, C>(B, h, net, j, s)));
         hipLaunchKernelGGL((kb_stencil<T>), dim3(nst), dim3(256), 0, s, t.stjobs, t.kd, j, j + 1, net ? 1 : 0);
         hipLaunchKernelGGL((kb_dots<C>), dim3(nv), dim3(KT), 0, s, t.vjobs, t.kd, j + 1);
-        hipLaunchKernelGGL(kb_finalize, dim3(nact), dim3(KT), 0, s, t.kd, t.act, j + 2, 1);
+        hipLaunchKernelGGL(kb_finalize, dim3(nact, j + 2), dim3(KT), 0, s, t.kd, t.act, 1);
         hipLaunchKernelGGL((kb_update<C, 1>), dim3(nv), dim3(KT), 0, s, t.vjobs, t.kd, j + 1);
-        hipLaunchKernelGGL(kb_finalize, dim3(nact), dim3(KT), 0, s, t.kd, t.act, j + 1, 2);
+        hipLaunchKernelGGL(kb_finalize, dim3(nact, j + 1), dim3(KT), 0, s, t.kd, t.act, 2);
         hipLaunchKernelGGL((kb_update<C, 2>), dim3(nv), dim3(KT), 0, s, t.vjobs, t.kd, j + 1);
         hipLaunchKernelGGL(kb_arnoldi_finish, dim3(nact), dim3(64), 0, s, t.kd, t.act, j);
         hipLaunchKernelGGL((kb_scale<C>), dim3(nv), dim3(KT), 0, s, t.vjobs, t.kd, j + 1);

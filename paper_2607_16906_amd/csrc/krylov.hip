@@ -74,21 +74,12 @@ __global__ __launch_bounds__(KT) void k_update(const C* __restrict__ V, int64_t 
     if (MODE == 2) norm_body(w, p0, p1, mine);
 }
 
-__global__ __launch_bounds__(KT) void k_finalize(const double2* __restrict__ part, int nblk, int ldp, int cnt,
+// one block per output value
+__global__ __launch_bounds__(KT) void k_finalize(const double2* __restrict__ part, int nblk, int ldp,
                                                  double2* __restrict__ out, const int* __restrict__ skip) {
     if (skip && *skip) return;
-    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
-    for (int i = wv; i < cnt; i += KT / 64) {
-        double a = 0, b = 0;
-        for (int q = ln; q < nblk; q += 64) {
-            const double2 v = part[(int64_t)q * ldp + i];
-            a += v.x;
-            b += v.y;
-        }
-        a = wave_sum(a);
-        b = wave_sum(b);
-        if (ln == 0) out[i] = double2{a, b};
-    }
+    const double2 v = block_sum_slot(part, nblk, ldp, blockIdx.x);
+    if (threadIdx.x == 0) out[blockIdx.x] = v;
 }
 
 
@@ -177,7 +168,7 @@ int launch_norm_partials(bool c128, const void* x, int64_t n, Split sp, double2*
 }
 
 int launch_finalize(const double2* part, int nblk, int ldp, int cnt, double2* out, const int* skip, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(KT), 0, s, part, nblk, ldp, cnt, out, skip);
+    hipLaunchKernelGGL(k_finalize, dim3(cnt), dim3(KT), 0, s, part, nblk, ldp, out, skip);
     HZ_LAUNCH_CHECK();
     return HZ_OK;
 }

@@ -91,6 +91,32 @@ __device__ __forceinline__ void norm_body(const C* __restrict__ w, int64_t p0, i
     block_store<1>(a, z, out, 1);
 }
 
+// sum_b part[b * ldp + i] by one block of KT threads: thread t takes b = t mod KT, then the
+// wavefront sums and the KT / 64 wavefront totals are added in order (deterministic).
+__device__ inline double2 block_sum_slot(const double2* __restrict__ part, int nblk, int ldp, int i) {
+    __shared__ double red[KT / 64][2];
+    double a = 0, b = 0;
+    for (int q = threadIdx.x; q < nblk; q += KT) {
+        const double2 v = part[(int64_t)q * ldp + i];
+        a += v.x;
+        b += v.y;
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6][0] = a;
+        red[threadIdx.x >> 6][1] = b;
+    }
+    __syncthreads();
+    double2 r{0.0, 0.0};
+#pragma unroll
+    for (int w = 0; w < KT / 64; ++w) {
+        r.x += red[w][0];
+        r.y += red[w][1];
+    }
+    return r;
+}
+
 __device__ inline double sum_parts(const double2* part, int nblk, int ldp, int slot) {
     const int ln = threadIdx.x & 63;
     double a = 0;
@@ -145,40 +171,44 @@ __device__ inline void cycle_start_body(SolveState* st, const double* __restrict
     }
 }
 
-// One wavefront: assemble Hessenberg column j, rotate it, form rotation j,
-// update g and the residual estimate, decide whether the cycle ends.
-__device__ inline void arnoldi_finish_body(SolveState* st, double2* R, double* cs, double2* sn, double2* g,
-                                    const double2* h1, const double2* h2, const double2* part, int nblk, int ldp,
-                                    int j, double* hist) {
+// One wavefront: assemble Hessenberg column j (h1 + h2), apply the previous rotations to it,
+// form rotation j, update g and the residual estimate, decide whether the cycle ends. The
+// rotations run as one chain in registers on lane 0; the column entries and rotations it reads
+// do not depend on its stores, so their loads can be issued ahead of the chain.
+__device__ inline void arnoldi_finish_body(SolveState* st, double2* __restrict__ R, double* __restrict__ cs,
+                                           double2* __restrict__ sn, double2* __restrict__ g,
+                                           const double2* __restrict__ h1, const double2* __restrict__ h2,
+                                           const double2* __restrict__ part, int nblk, int ldp, int j,
+                                           double* __restrict__ hist) {
     if (st->stop) return;
     const int m = st->m;
-    const int ln = threadIdx.x & 63;
     const double hn2 = sum_parts(part, nblk, ldp, 0);     // ||w||^2 after orthogonalisation
-    double2* col = R + (int64_t)j * (m + 1);
-    for (int i = ln; i <= j; i += 64) {
-        double2 a = h1[i];
-        if (h2) a = cadd(a, h2[i]);
-        col[i] = a;
-    }
-    __syncthreads();
     if (threadIdx.x != 0) return;
+    double2* col = R + (int64_t)j * (m + 1);
     const double wn0 = sqrt(h1[j + 1].x);
     const double hn = sqrt(hn2);
-    bool bad = !isfinite(hn) || !isfinite(wn0);
-    for (int i = 0; i <= j; ++i) bad |= !isfinite(col[i].x) || !isfinite(col[i].y);
+    auto hcol = [&](int i) {
+        double2 a = h1[i];
+        if (h2) a = cadd(a, h2[i]);
+        return a;
+    };
+    double2 cur = hcol(0);
+    bool bad = !isfinite(hn) || !isfinite(wn0) || !isfinite(cur.x) || !isfinite(cur.y);
+#pragma unroll 4
+    for (int i = 0; i < j; ++i) {   // previous rotations: (x0, x1) -> (c x0 + s x1, -conj(s) x0 + c x1)
+        const double2 x1 = hcol(i + 1);
+        const double c = cs[i];
+        const double2 s = sn[i];
+        bad |= !isfinite(x1.x) || !isfinite(x1.y);
+        col[i] = cadd(double2{c * cur.x, c * cur.y}, cmul(s, x1));
+        cur = csub(double2{c * x1.x, c * x1.y}, cmulc(s, cur));
+    }
     if (bad) {
         st->flags |= FL_NONFINITE;
         st->stop = 1;
         return;
     }
-    for (int i = 0; i < j; ++i) {   // previous rotations
-        const double c = cs[i];
-        const double2 s = sn[i];
-        const double2 x0 = col[i], x1 = col[i + 1];
-        col[i] = cadd(double2{c * x0.x, c * x0.y}, cmul(s, x1));
-        col[i + 1] = csub(double2{c * x1.x, c * x1.y}, cmulc(s, x0));   // -conj(s) x0 + c x1
-    }
-    const double2 a = col[j];
+    const double2 a = cur;
     const double aa = sqrt(a.x * a.x + a.y * a.y);
     const double rho = sqrt(aa * aa + hn * hn);
     double c;

@@ -206,8 +206,21 @@ static int precond_impl(const no_net* net, const hz_problem* p, bool c128, const
                            p->sigy, p->nxt, p->nyt, Hp, Wp, net->a.in_ch, (T*)b.X, skip, fixed_s, vscale,
                            vscale ? (float2*)v : nullptr);
     HZ_LAUNCH_CHECK();
-    HZ_TRY(unet_body<P>(net, b, Hp, Wp, 1, skip, s));
     const Layer& lh = net->layers.back();
+    if (lh.cin_p == 16 || lh.cin_p == 32 || lh.cin_p == 64) {
+        // the head runs in the epilogue of the last 3x3 layer
+        Conv3Out hd;
+        hd.head_w = packed_w<P>(net, lh);
+        hd.head_b = packed_b<P>(net, lh);
+        hd.head_z = z;
+        hd.head_c128 = c128 ? 1 : 0;
+        hd.head_nxt = p->nxt;
+        hd.head_nyt = p->nyt;
+        hd.head_sc = b.sc;
+        hd.head_fixed_s = fixed_s;
+        return unet_body<P>(net, b, Hp, Wp, 1, skip, s, &hd);
+    }
+    HZ_TRY(unet_body<P>(net, b, Hp, Wp, 1, skip, s));
     const T* D0 = net->a.levels > 1 ? (const T*)b.D[0] : (const T*)b.E[0];
     const unsigned gh = (unsigned)((n + 255) / 256);
     if (c128)

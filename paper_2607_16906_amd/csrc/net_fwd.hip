@@ -163,6 +163,45 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
             }
         return;
     }
+    if (ex.head_w) {   // fused 1x1 head over all cout_p = TN channels of the pixel
+        const T* wh = (const T*)ex.head_w;
+        const Acc* bh = (const Acc*)ex.head_b;
+        Acc o0[RPW], o1[RPW];
+#pragma unroll
+        for (int pb = 0; pb < RPW; ++pb) o0[pb] = o1[pb] = Acc(0);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = co0 + cb * 16 + P::row_of(lg, r);
+                const Acc w0 = P::val(wh[co]), w1 = P::val(wh[cout_p + co]), bc = bias ? bias[co] : Acc(0);
+#pragma unroll
+                for (int pb = 0; pb < RPW; ++pb) {
+                    Acc t = acc[pb][cb][r] + bc;
+                    if (relu) t = t > Acc(0) ? t : Acc(0);
+                    t = P::val(P::cvt(t));
+                    o0[pb] += t * w0;
+                    o1[pb] += t * w1;
+                }
+            }
+        const double sfac = ex.head_fixed_s > 0 ? ex.head_fixed_s : ex.head_sc[0];
+#pragma unroll
+        for (int pb = 0; pb < RPW; ++pb) {
+            Acc a0 = o0[pb], a1 = o1[pb];
+            a0 += __shfl_xor(a0, 16, 64);
+            a1 += __shfl_xor(a1, 16, 64);
+            a0 += __shfl_xor(a0, 32, 64);
+            a1 += __shfl_xor(a1, 32, 64);
+            const int gy = ty0 + RPW * wv + pb;
+            if (lg == 0 && gy < ex.head_nyt && gx < ex.head_nxt) {
+                const double2 zv{sfac * (double)(bh[0] + a0), sfac * (double)(bh[1] + a1)};
+                const int64_t zi = (int64_t)gy * ex.head_nxt + gx;
+                if (ex.head_c128) ((double2*)ex.head_z)[zi] = zv;
+                else ((float2*)ex.head_z)[zi] = from_d2<float2>(zv);
+            }
+        }
+        return;
+    }
     // epilogue: register r of a lane holds output channel co0 + 16 cb + row_of(lg, r) of pixel
     // (ty0 + RPW wv + pb, tx0 + lr). Channels below ex.split go to y (ex.split channels per pixel),
     // the others to ex.y1_; ex.mask0_ / ex.mask1_ (same layouts) zero the entries whose mask is <= 0.
@@ -461,6 +500,15 @@ int launch_conv3(const typename P::T* x0, int c0, const typename P::T* x1, int c
         while (tn > 16 && tiles * (cout_p / tn) < 512) tn /= 2;
     }
     while (cout_p % tn) tn /= 2;
+    if (ex.head_w) {
+        if ((cout_p != 16 && cout_p != 32 && cout_p != 64) || ypool || ex.split || batch != 1 || !ex.head_z ||
+            (!ex.head_sc && !(ex.head_fixed_s > 0))) {
+            set_error("conv3: fused head needs 16, 32 or 64 channels, one sample and no pooling");
+            return HZ_ERR_ARG;
+        }
+        tn = cout_p;
+        ksplit = 1;
+    }
     if (ex.split > 0) {
         if (ex.split % 16 || ex.split >= cout_p || (ypool && ex.split)) {
             set_error("conv3: bad output split");

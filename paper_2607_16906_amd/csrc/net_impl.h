@@ -125,7 +125,8 @@ constexpr no_prec prec_of() {
 }
 
 template <class P>
-inline int unet_body(const no_net* net, const FwdBufs& b, int Hp, int Wp, int batch, const int* skip, hipStream_t s) {
+inline int unet_body(const no_net* net, const FwdBufs& b, int Hp, int Wp, int batch, const int* skip, hipStream_t s,
+                     const Conv3Out* head = nullptr) {
     using Acc = typename P::Acc;
     Acc* sb = (Acc*)b.splitbuf;
     using T = typename P::T;
@@ -141,8 +142,9 @@ inline int unet_body(const no_net* net, const FwdBufs& b, int Hp, int Wp, int ba
                                la.cout_p, nullptr, H, W, batch, true, skip, s, Conv3Out(),
                                net_cfg(net, li - 2, H, W, batch, prec_of<P>()), sb));
         T* pool = l + 1 < lv ? (T*)b.P[l + 1] : nullptr;
+        const bool last = lv == 1 && head;   // a one-level net ends here
         HZ_TRY(launch_conv3<P>((const T*)b.T1[l], lb.cin_p, nullptr, 0, packed_w<P>(net, lb), packed_b<P>(net, lb),
-                               (T*)b.E[l], lb.cout_p, pool, H, W, batch, true, skip, s, Conv3Out(),
+                               (T*)b.E[l], lb.cout_p, pool, H, W, batch, true, skip, s, last ? *head : Conv3Out(),
                                net_cfg(net, li - 1, H, W, batch, prec_of<P>()), sb));
     }
     const T* Dn = (const T*)b.E[lv - 1];
@@ -157,8 +159,9 @@ inline int unet_body(const no_net* net, const FwdBufs& b, int Hp, int Wp, int ba
         HZ_TRY(launch_conv3<P>((const T*)b.E[l], ce, (const T*)b.U[l], ce, packed_w<P>(net, la), packed_b<P>(net, la),
                                (T*)b.T1d[l], la.cout_p, nullptr, H, W, batch, true, skip, s, Conv3Out(),
                                net_cfg(net, li - 2, H, W, batch, prec_of<P>()), sb));
+        const bool last = l == 0 && head;
         HZ_TRY(launch_conv3<P>((const T*)b.T1d[l], lb.cin_p, nullptr, 0, packed_w<P>(net, lb), packed_b<P>(net, lb),
-                               (T*)b.D[l], lb.cout_p, nullptr, H, W, batch, true, skip, s, Conv3Out(),
+                               (T*)b.D[l], lb.cout_p, nullptr, H, W, batch, true, skip, s, last ? *head : Conv3Out(),
                                net_cfg(net, li - 1, H, W, batch, prec_of<P>()), sb));
         Dn = (const T*)b.D[l];
     }

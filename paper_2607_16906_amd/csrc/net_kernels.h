@@ -94,6 +94,17 @@ struct Conv3Out {
     void* y1_ = nullptr;
     const void* mask0_ = nullptr;
     const void* mask1_ = nullptr;
+    // 1x1 output head fused into the epilogue (one block then covers every output channel and
+    // y is not stored): z[yy * head_nxt + xx] = s (head_b + head_w ReLU(y)) as a complex number
+    // (real, imaginary = head outputs 0, 1) for yy < head_nyt, xx < head_nxt, with y rounded to
+    // the activation type first; s = head_fixed_s if > 0, else head_sc[0].
+    const void* head_w = nullptr;   // activation type, [2][cout_p]
+    const void* head_b = nullptr;   // accumulator type, [2]
+    void* head_z = nullptr;         // float2 (head_c128 = 0) or double2
+    int head_c128 = 0;
+    int head_nxt = 0, head_nyt = 0;
+    const double* head_sc = nullptr;
+    double head_fixed_s = 0.0;
 };
 
 // Variant of a 3x3 convolution launch: channel tile (16 / 32 / 64; 0 = heuristic), rows per
