@@ -91,10 +91,9 @@ static int cycle_launches(const hz_problem* p, const no_net* net, const hz_opts*
         if (net)
             HZ_TRY(net_precond(net, p, o->net_prec, c128, vcol(j), zcol(j), L.net_ws, L.net_ws_bytes, stop, s, true,
                                j > 0 ? &kb.st->inv_h : nullptr));
-        // w = A z_j, written into the slot of v_{j+1}
+        // w = A z_j, written into the slot of v_{j+1}, with the first Gram-Schmidt sums
         void* w = vcol(j + 1);
-        HZ_TRY(launch_stencil(p, c128, false, zcol(j), w, s, stop));
-        HZ_TRY(launch_dots(c128, L.V, n, j + 1, w, n, sp, kb.part, kb.ldp, true, stop, s));
+        HZ_TRY(launch_stencil_dots(p, c128, zcol(j), L.V, n, j + 1, w, sp, kb.part, kb.ldp, stop, s));
         HZ_TRY(launch_finalize(kb.part, sp.nblk, kb.ldp, j + 2, kb.h1, stop, s));
         HZ_TRY(launch_update(c128, L.V, n, j + 1, kb.h1, w, n, sp, kb.part, kb.ldp, 1, stop, s));
         HZ_TRY(launch_finalize(kb.part, sp.nblk, kb.ldp, j + 1, kb.h2, stop, s));

@@ -56,6 +56,10 @@ int launch_finalize(const double2* part, int nblk, int ldp, int cnt, double2* ou
 // part[b][i] = sum over block b of conj(V_i) w (i < nv), plus ||w||^2 in slot nv when with_norm
 int launch_dots(bool c128, const void* V, int64_t ldv, int nv, const void* w, int64_t n, Split sp,
                 double2* part, int ldp, bool with_norm, const int* skip, hipStream_t s);
+
+// w = A z (the problem's operator) fused with launch_dots(..., with_norm = true) on w
+int launch_stencil_dots(const hz_problem* p, bool c128, const void* z, const void* V, int64_t ldv, int nv,
+                        void* w, Split sp, double2* part, int ldp, const int* skip, hipStream_t s);
 // w -= sum_i V_i h_i; mode 1 then also writes dots conj(V_i) w (slots 0..nv-1);
 // mode 2 writes ||w||^2 into slot 0
 int launch_update(bool c128, const void* V, int64_t ldv, int nv, const double2* h, void* w, int64_t n,

@@ -15,6 +15,7 @@
 
 #include "krylov.h"
 #include "krylov_impl.h"
+#include "problem.h"
 
 namespace hz {
 
@@ -48,6 +49,44 @@ __global__ __launch_bounds__(KT) void k_dots(const C* __restrict__ V, int64_t ld
     double2* mine = part + (int64_t)blockIdx.x * ldp;
     dots_body(V, ldv, nv, w, p0, p1, mine);
     if (with_norm) norm_body(w, p0, p1, mine + nv);
+}
+
+// w = A z evaluated pointwise over the block's index range (neighbours read through the cache,
+// zero outside the grid; same term order as the tiled stencil), then the pass-1 sums of k_dots
+// with the norm: part[b][i] = block sum of conj(V_i) w, part[b][nv] = ||w||^2.
+template <typename C>
+__global__ __launch_bounds__(KT) void k_stencil_dots(const C* __restrict__ z, StencilCoef sc, int nx, int ny,
+                                                     const C* __restrict__ V, int64_t ldv, int nv,
+                                                     C* __restrict__ w, int64_t n, int64_t per,
+                                                     double2* __restrict__ part, int ldp,
+                                                     const int* __restrict__ skip) {
+    using T = decltype(C{}.x);
+    if (skip && *skip) return;
+    const C* __restrict__ cE = (const C*)sc.E;
+    const C* __restrict__ cW = (const C*)sc.W;
+    const C* __restrict__ cN = (const C*)sc.N;
+    const C* __restrict__ cS = (const C*)sc.S;
+    const C* __restrict__ dxv = (const C*)sc.dx;
+    const C* __restrict__ dyv = (const C*)sc.dy;
+    const T* __restrict__ k2 = (const T*)sc.k2;
+    const int64_t p0 = blockIdx.x * per, p1 = min(n, p0 + per);
+    const C zero{0, 0};
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += KT) {
+        const int gj = (int)(p / nx), gi = (int)(p - (int64_t)gj * nx);
+        const C dxi = dxv[gi], dyj = dyv[gj];
+        C d = C{k2[p] - dxi.x - dyj.x, -dxi.y - dyj.y};
+        if (sc.conj_diag) d.y = -d.y;
+        C acc = cmul(d, z[p]);
+        acc = cadd(acc, cmul(cE[gi], gi + 1 < nx ? z[p + 1] : zero));
+        acc = cadd(acc, cmul(cW[gi], gi > 0 ? z[p - 1] : zero));
+        acc = cadd(acc, cmul(cN[gj], gj + 1 < ny ? z[p + nx] : zero));
+        acc = cadd(acc, cmul(cS[gj], gj > 0 ? z[p - nx] : zero));
+        w[p] = acc;
+    }
+    // each thread reads back only the points it wrote
+    double2* mine = part + (int64_t)blockIdx.x * ldp;
+    dots_body(V, ldv, nv, (const C*)w, p0, p1, mine);
+    norm_body((const C*)w, p0, p1, mine + nv);
 }
 
 template <typename C, int MODE>
@@ -181,6 +220,19 @@ int launch_dots(bool c128, const void* V, int64_t ldv, int nv, const void* w, in
     else
         hipLaunchKernelGGL(k_dots<float2>, dim3(sp.nblk), dim3(KT), 0, s, (const float2*)V, ldv, nv,
                            (const float2*)w, n, sp.per_block, part, ldp, with_norm ? 1 : 0, skip);
+    HZ_LAUNCH_CHECK();
+    return HZ_OK;
+}
+
+int launch_stencil_dots(const hz_problem* p, bool c128, const void* z, const void* V, int64_t ldv, int nv,
+                        void* w, Split sp, double2* part, int ldp, const int* skip, hipStream_t s) {
+    const StencilCoef sc = stencil_coef(p, c128, false);
+    if (c128)
+        hipLaunchKernelGGL(k_stencil_dots<double2>, dim3(sp.nblk), dim3(KT), 0, s, (const double2*)z, sc, p->nxt,
+                           p->nyt, (const double2*)V, ldv, nv, (double2*)w, p->n, sp.per_block, part, ldp, skip);
+    else
+        hipLaunchKernelGGL(k_stencil_dots<float2>, dim3(sp.nblk), dim3(KT), 0, s, (const float2*)z, sc, p->nxt,
+                           p->nyt, (const float2*)V, ldv, nv, (float2*)w, p->n, sp.per_block, part, ldp, skip);
     HZ_LAUNCH_CHECK();
     return HZ_OK;
 }

@@ -171,7 +171,7 @@ __device__ inline void cycle_start_body(SolveState* st, const double* __restrict
     }
 }
 
-// One wavefront: assemble Hessenberg column j (h1 + h2), apply the previous rotations to it,
+// One block (every thread calls it): assemble Hessenberg column j (h1 + h2), apply the previous rotations to it,
 // form rotation j, update g and the residual estimate, decide whether the cycle ends. The
 // rotations run as one chain in registers on lane 0; the column entries and rotations it reads
 // do not depend on its stores, so their loads can be issued ahead of the chain.
@@ -183,11 +183,26 @@ __device__ inline void arnoldi_finish_body(SolveState* st, double2* __restrict__
     if (st->stop) return;
     const int m = st->m;
     const double hn2 = sum_parts(part, nblk, ldp, 0);     // ||w||^2 after orthogonalisation
+    // stage the column and the first AF_WIN rotations in LDS with one parallel pass
+    constexpr int AF_WIN = 128;
+    __shared__ double2 hl[AF_WIN + 1], snl[AF_WIN];
+    __shared__ double csl[AF_WIN];
+    for (int i = threadIdx.x; i <= j && i <= AF_WIN; i += blockDim.x) {
+        double2 a = h1[i];
+        if (h2) a = cadd(a, h2[i]);
+        hl[i] = a;
+        if (i < j && i < AF_WIN) {
+            csl[i] = cs[i];
+            snl[i] = sn[i];
+        }
+    }
+    __syncthreads();
     if (threadIdx.x != 0) return;
     double2* col = R + (int64_t)j * (m + 1);
     const double wn0 = sqrt(h1[j + 1].x);
     const double hn = sqrt(hn2);
     auto hcol = [&](int i) {
+        if (i <= AF_WIN) return hl[i];
         double2 a = h1[i];
         if (h2) a = cadd(a, h2[i]);
         return a;
@@ -197,8 +212,8 @@ __device__ inline void arnoldi_finish_body(SolveState* st, double2* __restrict__
 #pragma unroll 4
     for (int i = 0; i < j; ++i) {   // previous rotations: (x0, x1) -> (c x0 + s x1, -conj(s) x0 + c x1)
         const double2 x1 = hcol(i + 1);
-        const double c = cs[i];
-        const double2 s = sn[i];
+        const double c = i < AF_WIN ? csl[i] : cs[i];
+        const double2 s = i < AF_WIN ? snl[i] : sn[i];
         bad |= !isfinite(x1.x) || !isfinite(x1.y);
         col[i] = cadd(double2{c * cur.x, c * cur.y}, cmul(s, x1));
         cur = csub(double2{c * x1.x, c * x1.y}, cmulc(s, cur));

@@ -123,6 +123,29 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
         lstore();
         __syncthreads();
         if (k0 + ck < kend) gload(k0 + ck);
+        if (ck == P::CK) {
+            // full chunk: step st covers tap st / SPT and k-groups 4 (st mod SPT) + lg of it, all
+            // offsets are compile-time after unrolling (the reads of the next steps can be issued
+            // while the matrix cores work)
+            constexpr int SPT = P::CK / P::GW / 4;
+            const T* pbase = &patch[((RPW * wv) * (TW + 2) + lr) * PS + lg * P::GW];
+            const T* wbase = &wl[lr * PS + lg * P::GW];
+#pragma unroll
+            for (int st = 0; st < 9 * SPT; ++st) {
+                const int tap = st / SPT, cgo = 4 * (st % SPT) * P::GW;
+                const int dy = tap / 3, dx = tap % 3;
+                Frag a[NCB], b[RPW];
+#pragma unroll
+                for (int pb = 0; pb < RPW; ++pb) b[pb] = P::load(pbase + ((pb + dy) * (TW + 2) + dx) * PS + cgo);
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) a[cb] = P::load(wbase + (tap * TN + cb * 16) * PS + cgo);
+#pragma unroll
+                for (int pb = 0; pb < RPW; ++pb)
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) acc[pb][cb] = P::mma(a[cb], b[pb], acc[pb][cb]);
+            }
+            continue;
+        }
         for (int st = 0; st < steps; ++st) {
             const int gi = 4 * st + lg;
             Frag a[NCB], b[RPW];
