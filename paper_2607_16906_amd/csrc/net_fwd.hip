@@ -253,14 +253,13 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
             const int gy = ty0 + RPW * wv + pb;
             if (gy < H && gx < W) {
                 const int64_t off = ((int64_t)gy * W + gx) * cst + cl;
-                T* dst = ys + off;
+                Acc t[4];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int rr = P::row_of(lg, r);
-                    Acc t = v[pb][r];
-                    if (ms && !(P::val(ms[off + rr]) > Acc(0))) t = Acc(0);
-                    dst[rr] = P::cvt(t);
+                    t[r] = v[pb][r];
+                    if (ms && !(P::val(ms[off + P::row_of(lg, r)]) > Acc(0))) t[r] = Acc(0);
                 }
+                store_rows<P>(ys + off + P::row_of(lg, 0), t);
             }
         }
         if (POOL) {
@@ -275,11 +274,8 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
                     q[r] = Acc(0.25) * s;
                 }
                 const int gy = ty0 + RPW * wv + pp;
-                if ((lr & 1) == 0 && gy < H && gx < W) {
-                    T* dst = ps + ((int64_t)(gy / 2) * (W / 2) + gx / 2) * cout_p + co;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) dst[P::row_of(lg, r)] = P::cvt(q[r]);
-                }
+                if ((lr & 1) == 0 && gy < H && gx < W)
+                    store_rows<P>(ps + ((int64_t)(gy / 2) * (W / 2) + gx / 2) * cout_p + co + P::row_of(lg, 0), q);
             }
         }
     }
@@ -371,19 +367,29 @@ __global__ __launch_bounds__(CT) void k_conv3_jobs(const TileJob* __restrict__ j
 // 2x2 stride-2 transposed convolution: a GEMM per input pixel with M = 4 x
 // output channels (tap a, b and channel), N = 16 input pixels per wave, K = input
 // channels. Block: 64 input pixels of one row (4 waves x 16) and TN channels.
+template <class P>
+constexpr int convT2_ksmax() { return 4 * P::CK; }   // input channels per LDS stage (at most)
+
+// One block: output channels [co0, co0 + TN) of the 4 parities for the 64 input pixels
+// (iy, ix0 .. ix0 + 63) of sample bz. Input channels go in stages of ks (<= 4 CK); the next
+// stage is loaded into registers while the matrix cores work on the current one, and a stage of
+// whole steps runs an unrolled step schedule.
 template <class P, int TN>
 __device__ __forceinline__ void convT2_tile(const typename P::T* __restrict__ x, int cin_p,
                                             const typename P::T* __restrict__ w,
                                             const typename P::Acc* __restrict__ bias,
-                                            typename P::T* __restrict__ y, int cout_p, int H, int W, int ck, int bz,
+                                            typename P::T* __restrict__ y, int cout_p, int H, int W, int ks, int bz,
                                             int co0, int iy, int ix0) {
     using T = typename P::T;
     using Acc = typename P::Acc;
     using AccV = typename P::AccV;
     using Frag = typename P::Frag;
-    constexpr int PS = pix_stride<P>();
+    constexpr int KSM = convT2_ksmax<P>();
+    constexpr int PS = KSM + 16 / (int)sizeof(T);
     constexpr int VE = 16 / sizeof(T);
     constexpr int NCB = TN / 16;
+    constexpr int NXV = (64 * KSM / VE + CT - 1) / CT;
+    constexpr int NWV = (4 * TN * KSM / VE + CT - 1) / CT;
     __shared__ __attribute__((aligned(16))) T xin[64 * PS];
     __shared__ __attribute__((aligned(16))) T wl[4 * TN * PS];
     const int64_t plane = (int64_t)H * W;
@@ -397,35 +403,83 @@ __device__ __forceinline__ void convT2_tile(const typename P::T* __restrict__ x,
         for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[ab][cb][r] = 0;
-    const int vpp = ck / VE;
-    const int groups = ck / P::GW;
-    const int steps = (groups + 3) / 4;
-    for (int k0 = 0; k0 < cin_p; k0 += ck) {
-        __syncthreads();
-        for (int v = threadIdx.x; v < 64 * vpp; v += CT) {
-            const int px = v / vpp, part = v - px * vpp;
-            const int gx = ix0 + px;
+    const int vpp = ks / VE;
+    const int nxv = 64 * vpp, nwv = 4 * TN * vpp;
+    uint4 rx[NXV], rw[NWV];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < NXV; ++i) {
+            const int v = threadIdx.x + i * CT;
             uint4 val = uint4{0, 0, 0, 0};
-            if (gx < W) val = *(const uint4*)(xs + ((int64_t)iy * W + gx) * cin_p + k0 + part * VE);
-            *(uint4*)&xin[px * PS + part * VE] = val;
+            if (v < nxv) {
+                const int px = v / vpp, part = v - px * vpp;
+                const int gx = ix0 + px;
+                if (gx < W) val = *(const uint4*)(xs + ((int64_t)iy * W + gx) * cin_p + k0 + part * VE);
+            }
+            rx[i] = val;
         }
-        for (int v = threadIdx.x; v < 4 * TN * vpp; v += CT) {
-            const int row = v / vpp, part = v - row * vpp;
-            const int ab = row / TN, co = row - ab * TN;
-            const T* src = w + ((int64_t)ab * cout_p + co0 + co) * cin_p + k0 + part * VE;
-            *(uint4*)&wl[row * PS + part * VE] = *(const uint4*)src;
+#pragma unroll
+        for (int i = 0; i < NWV; ++i) {
+            const int v = threadIdx.x + i * CT;
+            uint4 val = uint4{0, 0, 0, 0};
+            if (v < nwv) {
+                const int row = v / vpp, part = v - row * vpp;
+                const int ab = row / TN, co = row - ab * TN;
+                val = *(const uint4*)(w + ((int64_t)ab * cout_p + co0 + co) * cin_p + k0 + part * VE);
+            }
+            rw[i] = val;
         }
+    };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int i = 0; i < NXV; ++i) {
+            const int v = threadIdx.x + i * CT;
+            if (v < nxv) {
+                const int px = v / vpp, part = v - px * vpp;
+                *(uint4*)&xin[px * PS + part * VE] = rx[i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NWV; ++i) {
+            const int v = threadIdx.x + i * CT;
+            if (v < nwv) {
+                const int row = v / vpp, part = v - row * vpp;
+                *(uint4*)&wl[row * PS + part * VE] = rw[i];
+            }
+        }
+    };
+    gload(0);
+    for (int k0 = 0; k0 < cin_p; k0 += ks) {
         __syncthreads();
-        for (int st = 0; st < steps; ++st) {
-            const int cg = 4 * st + lg;
-            Frag b = cg < groups ? P::load(&xin[(wv * 16 + lr) * PS + cg * P::GW]) : P::zero();
+        lstore();
+        __syncthreads();
+        if (k0 + ks < cin_p) gload(k0 + ks);
+        const T* xb = &xin[(wv * 16 + lr) * PS + lg * P::GW];
+        const T* wb = &wl[lr * PS + lg * P::GW];
+        if (ks % (4 * P::GW) == 0) {   // whole steps: unrolled, stops after ks channels
 #pragma unroll
-            for (int ab = 0; ab < 4; ++ab)
+            for (int st = 0; st < KSM / P::GW / 4; ++st) {
+                if (4 * st * P::GW >= ks) break;
+                const Frag b = P::load(xb + 4 * st * P::GW);
 #pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) {
-                    Frag a = cg < groups ? P::load(&wl[(ab * TN + cb * 16 + lr) * PS + cg * P::GW]) : P::zero();
-                    acc[ab][cb] = P::mma(a, b, acc[ab][cb]);
-                }
+                for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb)
+                        acc[ab][cb] = P::mma(P::load(wb + (ab * TN + cb * 16) * PS + 4 * st * P::GW), b, acc[ab][cb]);
+            }
+        } else {
+            const int groups = ks / P::GW;
+            for (int st = 0; st < (groups + 3) / 4; ++st) {
+                const int cg = 4 * st + lg;
+                const Frag b = cg < groups ? P::load(xb + 4 * st * P::GW) : P::zero();
+#pragma unroll
+                for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) {
+                        const Frag a = cg < groups ? P::load(wb + (ab * TN + cb * 16) * PS + 4 * st * P::GW) : P::zero();
+                        acc[ab][cb] = P::mma(a, b, acc[ab][cb]);
+                    }
+            }
         }
     }
     const int gx = ix0 + wv * 16 + lr;
@@ -438,11 +492,10 @@ __device__ __forceinline__ void convT2_tile(const typename P::T* __restrict__ x,
         for (int cb = 0; cb < NCB; ++cb) {
             const int co = co0 + cb * 16;
             T* dst = ys + ((int64_t)oy * (2 * W) + ox) * cout_p + co;
+            Acc t[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = P::row_of(lg, r);
-                dst[row] = P::cvt(acc[ab][cb][r] + bias[co + row]);
-            }
+            for (int r = 0; r < 4; ++r) t[r] = acc[ab][cb][r] + bias[co + P::row_of(lg, r)];
+            store_rows<P>(dst + P::row_of(lg, 0), t);
         }
     }
 }
@@ -486,6 +539,13 @@ int conv3_batch_tn(int cout_p, int64_t tiles) {
     return tn;
 }
 int convT2_batch_tn(int cout_p) { return cout_p % 32 == 0 ? 32 : 16; }
+
+template <class P>
+static int convT2_stage(int cin_p) {
+    int ks = convT2_ksmax<P>();
+    while (ks > 1 && cin_p % ks) ks /= 2;
+    return ks;
+}
 
 template <class P>
 static int chunk_for(int cin_p, int c0, int c1) {
@@ -575,9 +635,9 @@ int launch_conv3(const typename P::T* x0, int c0, const typename P::T* x1, int c
 template <class P>
 int launch_convT2(const typename P::T* x, int cin_p, const typename P::T* w, const typename P::Acc* bias,
                   typename P::T* y, int cout_p, int H, int W, int batch, const int* skip, hipStream_t s) {
-    const int ck = chunk_for<P>(cin_p, cin_p, 0);
+    const int ck = convT2_stage<P>(cin_p);
     constexpr int VE = 16 / sizeof(typename P::T);
-    if (cout_p % 16 || cin_p % ck || ck % VE) {
+    if (cout_p % 16 || ck < VE || cin_p % ck || ck % VE) {
         set_error("convT2: unsupported channel combination");
         return HZ_ERR_ARG;
     }
@@ -620,7 +680,11 @@ template <class P>
 int launch_convT2_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
                        const typename P::Acc* bias, int cin_p, int cout_p, int tn, hipStream_t s) {
     if (njobs <= 0) return HZ_OK;
-    const int ck = chunk_for<P>(cin_p, cin_p, 0);
+    const int ck = convT2_stage<P>(cin_p);
+    if (ck < 16 / (int)sizeof(typename P::T) || cin_p % ck) {
+        set_error("convT2: unsupported channel combination");
+        return HZ_ERR_ARG;
+    }
     if (tn == 32)
         hipLaunchKernelGGL((k_convT2_jobs<P, 32>), dim3(njobs), dim3(CT), 0, s, jobs, io, w, bias, cin_p, cout_p, ck);
     else

@@ -39,6 +39,14 @@ struct PolBF16 {
     __device__ static T cvt(Acc v) { return f2bf(v); }
     __device__ static Acc val(T v) { return bf2f(v); }
     __device__ static int row_of(int lg, int r) { return 4 * lg + r; }
+    // the 4 registers of a lane are 4 consecutive channels: one 8-byte store at p = &row_of(lg, 0)
+    static constexpr bool CONTIG = true;
+    __device__ static void store4(T* p, const Acc (&v)[4]) {
+        uint2 u;
+        u.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+        u.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+        *(uint2*)p = u;
+    }
 };
 
 struct PolF32 {
@@ -54,6 +62,8 @@ struct PolF32 {
     __device__ static T cvt(Acc v) { return v; }
     __device__ static Acc val(T v) { return v; }
     __device__ static int row_of(int lg, int r) { return 4 * lg + r; }
+    static constexpr bool CONTIG = true;   // one 16-byte store
+    __device__ static void store4(T* p, const Acc (&v)[4]) { *(float4*)p = float4{v[0], v[1], v[2], v[3]}; }
 };
 
 struct PolF64 {
@@ -69,7 +79,15 @@ struct PolF64 {
     __device__ static T cvt(Acc v) { return v; }
     __device__ static Acc val(T v) { return v; }
     __device__ static int row_of(int lg, int r) { return lg + 4 * r; }
+    static constexpr bool CONTIG = false;  // channels lg, lg + 4, ...: element stores
+    __device__ static void store4(T* p, const Acc (&v)[4]) {
+        for (int r = 0; r < 4; ++r) p[4 * r] = v[r];
+    }
 };
+
+// y[row_of(lg, r)] = cvt(v[r]) for r < 4, with y = p - row_of(lg, 0)
+template <class P>
+__device__ __forceinline__ void store_rows(typename P::T* p, const typename P::Acc (&v)[4]) { P::store4(p, v); }
 
 // One block of a ragged batch: system index, output-channel block start, tile origin (3x3:
 // pixel row / column of an 8 x 16 tile; transposed conv: input row / first column of 64).
