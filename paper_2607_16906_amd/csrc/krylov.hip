@@ -89,6 +89,8 @@ __global__ __launch_bounds__(KT) void k_stencil_dots(const C* __restrict__ z, St
     norm_body((const C*)w, p0, p1, mine + nv);
 }
 
+constexpr int UPD_REG = 32;   // vectors held in registers by the one-point-per-thread update
+
 template <typename C, int MODE>
 __global__ __launch_bounds__(KT) void k_update(const C* __restrict__ V, int64_t ldv, int nv,
                                                const double2* __restrict__ h, C* __restrict__ w, int64_t n,
@@ -96,6 +98,48 @@ __global__ __launch_bounds__(KT) void k_update(const C* __restrict__ V, int64_t 
                                                const int* __restrict__ skip) {
     if (skip && *skip) return;
     const int64_t p0 = blockIdx.x * per, p1 = min(n, p0 + per);
+    if (MODE == 1 && nv <= UPD_REG && per == KT) {
+        // one point per thread: the vectors read for the update stay in registers for the sums
+        // conj(V_i) w of the second pass (V is read once)
+        const int64_t p = p0 + threadIdx.x;
+        C vr[UPD_REG];
+        double ar[UPD_REG], ai[UPD_REG];
+        C wp = C{0, 0};
+        if (p < p1) {
+            wp = w[p];
+#pragma unroll
+            for (int i = 0; i < UPD_REG; ++i)
+                if (i < nv) vr[i] = V[(int64_t)i * ldv + p];
+            double ax = wp.x, ay = wp.y;
+#pragma unroll
+            for (int i = 0; i < UPD_REG; ++i)
+                if (i < nv) {
+                    const double2 hi = h[i];
+                    ax -= (double)vr[i].x * hi.x - (double)vr[i].y * hi.y;
+                    ay -= (double)vr[i].x * hi.y + (double)vr[i].y * hi.x;
+                }
+            wp = from_d2<C>(double2{ax, ay});
+            w[p] = wp;
+        }
+        double2* mine = part + (int64_t)blockIdx.x * ldp;
+#pragma unroll
+        for (int i0 = 0; i0 < UPD_REG; i0 += IC) {
+            if (i0 >= nv) break;
+#pragma unroll
+            for (int q = 0; q < IC; ++q) {
+                ar[i0 + q] = ai[i0 + q] = 0.0;
+                if (p < p1 && i0 + q < nv) {
+                    const C v = vr[i0 + q];
+                    ar[i0 + q] = (double)v.x * wp.x + (double)v.y * wp.y;
+                    ai[i0 + q] = (double)v.x * wp.y - (double)v.y * wp.x;
+                }
+            }
+            double (&sr)[IC] = *reinterpret_cast<double (*)[IC]>(&ar[i0]);
+            double (&si)[IC] = *reinterpret_cast<double (*)[IC]>(&ai[i0]);
+            block_store<IC>(sr, si, mine + i0, nv - i0);
+        }
+        return;
+    }
     for (int64_t p = p0 + threadIdx.x; p < p1; p += KT) {
         const C wp = w[p];
         double ax = wp.x, ay = wp.y;

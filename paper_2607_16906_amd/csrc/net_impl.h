@@ -23,7 +23,7 @@ __global__ void k_pack(const C* __restrict__ v, const double* __restrict__ sc, c
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)Hp * Wp) return;
     const int yy = (int)(idx / Wp), xx = (int)(idx % Wp);
-    T out[8];
+    __attribute__((aligned(16))) T out[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) out[c] = P::cvt(0);
     if (yy < nyt && xx < nxt) {
@@ -43,9 +43,10 @@ __global__ void k_pack(const C* __restrict__ v, const double* __restrict__ sc, c
             out[4] = P::cvt((typename P::Acc)sigy[yy]);
         }
     }
-    T* dst = X + idx * 8;
+    T* dst = X + idx * 8;   // 8 channels per pixel: 16 B (BF16) or whole 16-byte vectors
+    static_assert((8 * sizeof(T)) % 16 == 0, "pack: 8 channels must be whole 16-byte vectors");
 #pragma unroll
-    for (int c = 0; c < 8; ++c) dst[c] = out[c];
+    for (int c = 0; c < 8; c += 16 / (int)sizeof(T)) *(uint4*)(dst + c) = *(const uint4*)(out + c);
 }
 
 
