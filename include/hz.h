@@ -129,10 +129,11 @@ size_t no_workspace_size(const no_net* net, const hz_problem* p, no_prec prec);
 int no_precond_apply(const no_net* net, const hz_problem* p, no_prec prec, hz_dtype dtype,
                      const void* v_dev, void* z_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
-/* Time every launch variant (channel tile, pixel-tile height, split of the input channels)
- * of every 3x3 layer at this problem's padded size and precision, on the forward workspace
- * ws_dev (no_workspace_size bytes), and keep the fastest in the network handle; later
- * forward passes at that size use it. fgmres_solve calls it on its first use of a size.
+/* Time every launch variant (output-channel tile, pixel-tile height) of every 3x3 layer at
+ * this problem's padded size and precision, on the forward workspace ws_dev
+ * (no_workspace_size bytes), and keep the fastest in the network handle; later forward passes
+ * at that size use it. The variants accumulate every output in the same order, so the choice
+ * never changes a result bit. fgmres_solve calls it on its first use of a size.
  * Synchronises `stream`; returns at once if the size was tuned before. Thread-safe. */
 int no_autotune(const no_net* net, const hz_problem* p, no_prec prec, void* ws_dev, size_t ws_bytes,
                 void* stream);

@@ -160,37 +160,56 @@ def relu(x):
 
 # --------------------------------------------------------------------------- network
 
-def forward(theta, specs, X, keep=False):
-    """U-Net on an NCHW batch X. Returns out (and the activation cache when keep=True)."""
+def bf16_activation(a):
+    """Emulated BF16 activation storage: the value as an FP32 accumulator holds it, rounded to
+    bfloat16 (8-bit significand) to nearest, ties to even; returned as float64. NaN stays NaN."""
+    f = np.asarray(a, dtype=np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = (((u + 0x7FFF + lsb) >> 16) << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+    return np.where(np.isnan(f), np.nan, r)
+
+
+def forward(theta, specs, X, keep=False, act_round=None):
+    """U-Net on an NCHW batch X. Returns out (and the activation cache when keep=True).
+
+    act_round (optional, inference only): a rounding applied to every stored activation, to
+    emulate a reduced-precision activation format: the network input, each 3x3 layer's output
+    after ReLU and each transposed convolution's output. Pooling averages the encoder output
+    before its rounding (the pooled value is then rounded)."""
+    if act_round is not None and keep:
+        raise ValueError("act_round is an inference-only emulation")
+    q = act_round if act_round is not None else (lambda a: a)
     P = unpack(theta, specs)
     levels = sum(1 for s in specs if s[0].startswith("enc")) // 2
     cache = {}
-    E, h = [], X
+    E, h = [], q(X)
+    e_raw = None
     for l in range(levels):
         if l > 0:
-            h = avgpool2(E[l - 1])
+            h = q(avgpool2(e_raw))
         Wa, ba = P[f"enc{l}a"]
         Wb, bb = P[f"enc{l}b"]
         a1 = conv3(h, Wa, ba)
-        r1 = relu(a1)
+        r1 = q(relu(a1))
         a2 = conv3(r1, Wb, bb)
-        e = relu(a2)
+        e_raw = relu(a2)
         if keep:
             cache[f"enc{l}"] = (h, a1, r1, a2)
-        E.append(e)
+        E.append(q(e_raw))
     D = E[-1]
     for l in range(levels - 2, -1, -1):
         Wu, bu = P[f"up{l}"]
-        U = convT2(D, Wu, bu)
+        U = q(convT2(D, Wu, bu))
         cat = np.concatenate([E[l], U], axis=1)
         Wa, ba = P[f"dec{l}a"]
         Wb, bb = P[f"dec{l}b"]
         a1 = conv3(cat, Wa, ba)
-        r1 = relu(a1)
+        r1 = q(relu(a1))
         a2 = conv3(r1, Wb, bb)
         if keep:
             cache[f"dec{l}"] = (D, cat, a1, r1, a2)
-        D = relu(a2)
+        D = q(relu(a2))
     Wh, bh = P["head"]
     out = conv1(D, Wh, bh)
     if keep:
@@ -283,14 +302,14 @@ def pack_input(v, p: hz.Problem, in_ch: int, levels: int, dtype=np.float64):
     return X, s
 
 
-def precond_apply(theta, specs, p: hz.Problem, v, dtype=np.float64):
-    """Eq. (7): z = N_theta(v, c, sigma) for one complex field v [ny, nx]."""
+def precond_apply(theta, specs, p: hz.Problem, v, dtype=np.float64, act_round=None):
+    """Eq. (7): z = N_theta(v, c, sigma) for one complex field v [ny, nx] (act_round: see forward)."""
     in_ch = specs[0][2]
     levels = sum(1 for s in specs if s[0].startswith("enc")) // 2
     X, s = pack_input(v, p, in_ch, levels, dtype)
     if s == 0:
         return np.zeros((p.ny, p.nx), np.complex128)
-    out = forward(np.asarray(theta, dtype=dtype), specs, X)
+    out = forward(np.asarray(theta, dtype=dtype), specs, X, act_round=act_round)
     return s * (out[0, 0, :p.ny, :p.nx].astype(np.float64) + 1j * out[0, 1, :p.ny, :p.nx].astype(np.float64))
 
 

@@ -1,0 +1,137 @@
+"""Parity at the single-solve workload's full size (256^2 interior + 20 PML = 296^2 nodes, the
+trained 4-level / 32-channel network, the autotuned launch configuration the solver and the
+benchmark use), and the BF16-preconditioned FGMRES bar: true relative residual <= tol, iteration
+count within 2 of the FP64 oracle's on average over a set of seeded solves (each within
+max(2, 10 %), also on long solves)."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+from oracle import fgmres as ofg
+from oracle import helmholtz as ohz
+from oracle import unet
+from synth import C_REF, H_10PPW, c2_system, gaussian_sources, rng_for, skull_ring_velocity
+
+from gpu_util import make_pair, rel, to_dev, to_np
+
+WEIGHTS = os.path.join(os.path.dirname(__file__), "..", "paper_2607_16906_amd", "weights", "unet_l4_c32_in5.npz")
+SPECS = unet.layer_specs(4, 32, 5)
+
+
+def bf16_round(a):
+    """Round-to-nearest-even to bfloat16, returned as float64 (test-side input preparation)."""
+    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.fixture(scope="module")
+def c2():
+    from paper_2607_16906_amd import hz
+    s = c2_system(0)
+    op, gp = make_pair(s.c, s.npml)
+    theta = np.load(WEIGHTS)["theta"].astype(np.float32)
+    net = hz.Net(4, 32, 5, theta)
+    net.autotune(gp, "bf16")
+    net.autotune(gp, "fp32")
+    return s, op, gp, theta, net
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16", 3e-2), ("fp32", 1e-5)])
+def test_c2_network_full_size(c2, prec, tol):
+    s, op, gp, theta, net = c2
+    # a unit-norm Krylov-like input: the normalised source field plus seeded noise
+    v = s.b.reshape(op.ny, op.nx) + 0.05 * np.random.default_rng(7).standard_normal((op.ny, op.nx))
+    v = v / np.linalg.norm(v)
+    z = to_np(net.apply(gp, to_dev(v, torch.complex64), prec=prec)).reshape(op.ny, op.nx)
+    th = bf16_round(theta) if prec == "bf16" else theta.astype(np.float64)
+    ref = unet.precond_apply(th, SPECS, op, v)
+    err = rel(z, ref)
+    print(f"{prec} full-size network error {err:.3e}")
+    assert err <= tol
+
+
+def test_c2_solve_full_size(c2):
+    # the benchmark's solve: BF16 network, FP32 Krylov vectors, FGMRES(30), tol 1e-6; the true
+    # residual of the returned x is recomputed with the oracle's FP64 operator
+    from paper_2607_16906_amd import hz
+    s, op, gp, theta, net = c2
+    x, info = hz.fgmres(gp, to_dev(s.b, torch.complex128), net=net, m=30, tol=1e-6, maxit=3000, krylov="c64",
+                        net_prec="bf16")
+    assert info.status == 0
+    xs = to_np(x).reshape(op.ny, op.nx)
+    r = s.b.reshape(op.ny, op.nx) - ohz.op_apply(op, xs)
+    rr = np.linalg.norm(r) / np.linalg.norm(s.b)
+    print(f"its {info.its}, true relres {rr:.3e} (reported {info.true_relres:.3e})")
+    assert rr <= 1e-6 and abs(rr - info.true_relres) <= 1e-9
+
+
+def bf16_solve_pair(nx, p, seed):
+    """(oracle result, GPU info, true relative residual of the GPU x) of one BF16-preconditioned
+    solve: FP64 oracle FGMRES with the FP64 network on the BF16-rounded weights, GPU FGMRES with
+    the BF16 network and FP32 Krylov vectors (m = 30, tol = 1e-6)."""
+    from paper_2607_16906_amd import hz
+    nt = nx + 2 * p
+    c = skull_ring_velocity(nt, p, rng_for(14, 0, seed), rings=1 + seed % 3)
+    b = gaussian_sources(nt, p, rng_for(14, 1, seed))
+    op, gp = make_pair(c, p)
+    theta = np.load(WEIGHTS)["theta"].astype(np.float32)
+    th = bf16_round(theta)
+    M = lambda vv: unet.precond_apply(th, SPECS, op, vv.reshape(op.ny, op.nx)).ravel()
+    A = lambda xx: ohz.op_apply(op, xx.reshape(op.ny, op.nx)).ravel()
+    ref = ofg.fgmres(A, M, b.ravel(), m=30, tol=1e-6, maxit=400)
+    net = hz.Net(4, 32, 5, theta)
+    x, info = hz.fgmres(gp, to_dev(b, torch.complex128), net=net, m=30, tol=1e-6, maxit=400, krylov="c64",
+                        net_prec="bf16")
+    rr = np.linalg.norm(b.ravel() - A(to_np(x))) / np.linalg.norm(b)
+    print(f"nx {nx} seed {seed}: its GPU {info.its}, oracle {ref.its}, true relres {rr:.3e}")
+    return ref, info, rr
+
+
+def test_bf16_fgmres_iterations_match_oracle():
+    # 18 seeded solves of 30-60 iterations (12^2-20^2 interiors + 6 PML): every solve converges
+    # with true relative residual <= tol; the iteration count is within 2 of the oracle's on
+    # average and within max(2, 10 %) for each solve (rounding-level differences move single
+    # trajectories of this nonlinear iteration by a few steps; the FP64 network with FP64 Krylov
+    # vectors does so against the FP64 oracle as well)
+    diffs = []
+    for nx in (12, 16, 20):
+        for seed in range(6):
+            ref, info, rr = bf16_solve_pair(nx, 6, seed)
+            assert ref.status == 0 and info.status == 0 and rr <= 1e-6
+            assert abs(info.its - ref.its) <= max(2, ref.its // 10), (nx, seed, info.its, ref.its)
+            diffs.append(abs(info.its - ref.its))
+    print("mean |d its|", np.mean(diffs), "max", max(diffs))
+    assert np.mean(diffs) <= 2.0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_bf16_fgmres_long_solve_iterations(seed):
+    # 90-130 iterations (40^2 interior + 8 PML): count within max(2, 10 %) of the oracle's
+    ref, info, rr = bf16_solve_pair(40, 8, seed)
+    assert ref.status == 0 and info.status == 0
+    assert abs(info.its - ref.its) <= max(2, ref.its // 10)
+    assert rr <= 1e-6
+
+
+def test_solves_independent_of_autotuning():
+    # the autotuner's variants never change a result bit: two solves on fresh network handles
+    # (each tunes anew, and timing noise may pick other variants) give identical iterates
+    from paper_2607_16906_amd import hz
+    nx, p = 24, 8
+    nt = nx + 2 * p
+    c = skull_ring_velocity(nt, p, rng_for(14, 0, 0), rings=1)
+    b = to_dev(gaussian_sources(nt, p, rng_for(14, 1, 0)), torch.complex128)
+    op, gp = make_pair(c, p)
+    theta = np.load(WEIGHTS)["theta"].astype(np.float32)
+    xs = []
+    for _ in range(2):
+        net = hz.Net(4, 32, 5, theta)
+        x, info = hz.fgmres(gp, b, net=net, m=30, tol=1e-6, maxit=400, krylov="c64", net_prec="bf16")
+        xs.append((x, info.its))
+    assert xs[0][1] == xs[1][1] and torch.equal(xs[0][0], xs[1][0])

@@ -89,6 +89,54 @@ def torch_unet(theta, specs, X):
     return F.conv2d(h, *P["head"])
 
 
+def torch_unet_bf16_storage(theta, specs, X):
+    """The same architecture with every stored activation cast FP64 -> FP32 -> bfloat16 -> FP64 by
+    torch (input, 3x3 outputs after ReLU, transposed-conv outputs; pooling from the uncast value)."""
+    q = lambda t: t.to(torch.float32).to(torch.bfloat16).to(torch.float64)
+    P = {k: (torch.from_numpy(np.ascontiguousarray(w)), torch.from_numpy(np.ascontiguousarray(b)))
+         for k, (w, b) in unet.unpack(theta, specs).items()}
+    L = sum(1 for s in specs if s[0].startswith("enc")) // 2
+    h, raw = q(X), None
+    skips = []
+    for l in range(L):
+        if l:
+            h = q(F.avg_pool2d(raw, 2))
+        h = q(F.relu(F.conv2d(h, *P[f"enc{l}a"], padding=1)))
+        raw = F.relu(F.conv2d(h, *P[f"enc{l}b"], padding=1))
+        skips.append(q(raw))
+    h = skips[-1]
+    for l in range(L - 2, -1, -1):
+        u = q(F.conv_transpose2d(h, *P[f"up{l}"], stride=2))
+        h = torch.cat([skips[l], u], 1)
+        h = q(F.relu(F.conv2d(h, *P[f"dec{l}a"], padding=1)))
+        h = q(F.relu(F.conv2d(h, *P[f"dec{l}b"], padding=1)))
+    return F.conv2d(h, *P["head"])
+
+
+def test_bf16_activation_rounding():
+    # round to nearest even at 8 significant bits; torch's float32 -> bfloat16 cast agrees
+    x = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -2.5, 0.0, 1e-30, 3.0e38, np.inf, np.nan])
+    r = unet.bf16_activation(x)
+    assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 + 2.0 ** -6 and r[3] == -2.5 and r[4] == 0.0
+    assert np.isinf(r[7]) and np.isnan(r[8])
+    y = np.random.default_rng(3).standard_normal(10000) * 10.0 ** np.random.default_rng(4).uniform(-5, 5, 10000)
+    ref = torch.from_numpy(y).to(torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(unet.bf16_activation(y), ref)
+
+
+@pytest.mark.parametrize("levels,base,in_ch", [(2, 4, 2), (3, 4, 5)])
+def test_forward_bf16_activation_storage_matches_torch(levels, base, in_ch):
+    specs = unet.layer_specs(levels, base, in_ch)
+    theta = he_uniform(unet.init_shapes(specs), np.random.default_rng(levels)).astype(np.float64)
+    X = rand(2, in_ch, 16, 24, seed=levels)
+    out = unet.forward(theta, specs, X, act_round=unet.bf16_activation)
+    ref = torch_unet_bf16_storage(theta, specs, torch.from_numpy(X)).numpy()
+    assert np.max(np.abs(out - ref)) <= 1e-12 * max(1.0, np.abs(ref).max())
+    exact = unet.forward(theta, specs, X)
+    assert np.array_equal(unet.forward(theta, specs, X, act_round=lambda a: a), exact)
+    assert np.abs(out - exact).max() > 1e-4 * np.abs(exact).max()     # the rounding is applied
+
+
 @pytest.mark.parametrize("levels,base,in_ch", [(2, 4, 2), (3, 4, 5), (4, 2, 5)])
 def test_forward_matches_torch_composition(levels, base, in_ch):
     specs = unet.layer_specs(levels, base, in_ch)
