@@ -197,6 +197,48 @@ def bench_batched(hz, torch, net, nsys=32, maxit=60):
             "min_relres": min(i.true_relres for i in infos), "max_relres": max(i.true_relres for i in infos)}
 
 
+def bench_large(hz, torch, net, maxit=100, m=50):
+    """Large single solve: 1024^2 interior + 32 PML (1088^2 nodes), FGMRES(50), BF16 network (the
+    trained 4-level network stands in for a 5-level one), FP32 Krylov vectors, bounded to maxit
+    iterations. Reports the network's rate at this size and the HBM rate of the Krylov phase
+    (stencil + Gram-Schmidt passes + Givens), whose basis (m + 1 vectors of 9.5 MB) no longer fits
+    in the caches."""
+    from synth import H_10PPW, c5_system
+    s = c5_system(0)
+    gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW)
+    n = s.nt * s.nt
+    Hp = (s.nt + 7) // 8 * 8
+    net.autotune(gp, "bf16")
+    layers = time_layers(net, Hp, Hp, reps=5)
+    net_ms = sum(r["ms"] for r in layers)
+    net_flops = sum(r["flops"] for r in layers)
+    dom = max(layers, key=lambda r: r["ms"])
+    b = torch.from_numpy(s.b.ravel()).cuda()
+    ws = torch.empty(hz.fgmres_workspace_bytes(gp, net, m, maxit, "c64", "bf16"), dtype=torch.uint8, device="cuda")
+    hz.fgmres(gp, b, net=net, m=m, tol=1e-6, maxit=m, workspace=ws)   # warm-up (one cycle)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info = hz.fgmres(gp, b, net=net, m=m, tol=1e-6, maxit=maxit, workspace=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_it = dt / max(info.its, 1) * 1e3
+    # Krylov-phase bytes of Arnoldi step j (j + 1 basis vectors, FP32 complex): matvec fused with
+    # the first Gram-Schmidt pass 20n + 8n (j + 1); two update passes 2 (8n (j + 1) + 16n)
+    steps = [k % m for k in range(info.its)]
+    kbytes = sum(52 * n + 24 * n * (j + 1) for j in steps)
+    kry_s = max(dt - info.its * net_ms * 1e-3, 1e-9)
+    return {"workload": "single solve, 1024^2 interior + 32 PML (1088^2), FGMRES(50), BF16 4-level/32-ch U-Net, "
+                        f"FP32 Krylov, bounded to {maxit} iterations",
+            "nodes": n, "its": info.its, "true_relres": info.true_relres, "ms_per_it": round(ms_it, 3),
+            "network_ms_per_apply": round(net_ms, 3), "network_tflops": round(net_flops / net_ms * 1e-9, 1),
+            "network_mfma_frac": round(net_flops / net_ms * 1e-9 / PEAK_BF16_TFLOPS, 4),
+            "dominant_layer": {"layer": dom["layer"], "shape": f"{dom['cin']}->{dom['cout']} ch on {dom['H']}x{dom['W']}",
+                               "ms": round(dom["ms"], 4), "tflops": round(dom["flops"] / dom["ms"] * 1e-9, 1)},
+            "krylov_ms_per_it": round(kry_s / max(info.its, 1) * 1e3, 3),
+            "krylov_hbm_gbs": round(kbytes / kry_s / 1e9, 1),
+            "krylov_hbm_frac": round(kbytes / kry_s / 1e9 / PEAK_HBM_GBS, 4)}
+
+
 def cpu_baseline(system, theta, gpu_its, budget_s=20.0):
     """The FP64 oracle FGMRES on the same system and weights, timed over a bounded number of
     iterations and scaled to one solve of gpu_its iterations."""
@@ -347,6 +389,7 @@ def main():
     if not args.no_extra:
         out["training"] = bench_training(hz, torch)
         out["batched"] = bench_batched(hz, torch, net)
+        out["large"] = bench_large(hz, torch, net)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, theta, its)
     print(json.dumps(out))

@@ -128,6 +128,7 @@ __global__ __launch_bounds__(KT) void kb_update(const TileJob* __restrict__ jobs
         }
         w[p] = from_d2<C>(double2{ax, ay});
     }
+    __syncthreads();   // the sweeps below may read points written by other threads of the block
     double2* mine = d.part + (int64_t)jb.c0 * d.ldp;
     if (MODE == 1) dots_body(V, d.n, nv, (const C*)w, p0, p1, mine);
     if (MODE == 2) norm_body((const C*)w, p0, p1, mine);

@@ -16,6 +16,7 @@
 #include "krylov.h"
 #include "krylov_impl.h"
 #include "problem.h"
+#include "stencil_impl.h"
 
 namespace hz {
 
@@ -59,7 +60,7 @@ __global__ __launch_bounds__(KT) void k_stencil_dots(const C* __restrict__ z, St
                                                      const C* __restrict__ V, int64_t ldv, int nv,
                                                      C* __restrict__ w, int64_t n, int64_t per,
                                                      double2* __restrict__ part, int ldp,
-                                                     const int* __restrict__ skip) {
+                                                     const int* __restrict__ skip, int pairs) {
     using T = decltype(C{}.x);
     if (skip && *skip) return;
     const C* __restrict__ cE = (const C*)sc.E;
@@ -70,6 +71,17 @@ __global__ __launch_bounds__(KT) void k_stencil_dots(const C* __restrict__ z, St
     const C* __restrict__ dyv = (const C*)sc.dy;
     const T* __restrict__ k2 = (const T*)sc.k2;
     const int64_t p0 = blockIdx.x * per, p1 = min(n, p0 + per);
+    if constexpr (std::is_same<C, float2>::value) {
+        if (pairs) {   // two points per lane (nx even, aligned vectors, even block start)
+            for (int64_t p = p0 + 2 * threadIdx.x; p < p1; p += 2 * KT)
+                stencil_pair(z, w, k2, cE, cW, cN, cS, dxv, dyv, sc.conj_diag, nx, ny, p);
+            __syncthreads();
+            double2* mine = part + (int64_t)blockIdx.x * ldp;
+            dots_body(V, ldv, nv, (const C*)w, p0, p1, mine);
+            norm_body((const C*)w, p0, p1, mine + nv);
+            return;
+        }
+    }
     const C zero{0, 0};
     for (int64_t p = p0 + threadIdx.x; p < p1; p += KT) {
         const int gj = (int)(p / nx), gi = (int)(p - (int64_t)gj * nx);
@@ -83,13 +95,13 @@ __global__ __launch_bounds__(KT) void k_stencil_dots(const C* __restrict__ z, St
         acc = cadd(acc, cmul(cS[gj], gj > 0 ? z[p - nx] : zero));
         w[p] = acc;
     }
-    // each thread reads back only the points it wrote
+    __syncthreads();   // the sweeps below may read points written by other threads of the block
     double2* mine = part + (int64_t)blockIdx.x * ldp;
     dots_body(V, ldv, nv, (const C*)w, p0, p1, mine);
     norm_body((const C*)w, p0, p1, mine + nv);
 }
 
-constexpr int UPD_REG = 32;   // vectors held in registers by the one-point-per-thread update
+constexpr int UPD_REG = 32;   // vectors held in registers by the single-pass first update
 
 template <typename C, int MODE>
 __global__ __launch_bounds__(KT) void k_update(const C* __restrict__ V, int64_t ldv, int nv,
@@ -98,19 +110,19 @@ __global__ __launch_bounds__(KT) void k_update(const C* __restrict__ V, int64_t 
                                                const int* __restrict__ skip) {
     if (skip && *skip) return;
     const int64_t p0 = blockIdx.x * per, p1 = min(n, p0 + per);
-    if (MODE == 1 && nv <= UPD_REG && per == KT) {
-        // one point per thread: the vectors read for the update stay in registers for the sums
-        // conj(V_i) w of the second pass (V is read once)
-        const int64_t p = p0 + threadIdx.x;
-        C vr[UPD_REG];
+    if (MODE == 1 && nv <= UPD_REG) {
+        // single pass: the vectors read for the update of a point stay in registers for the sums
+        // conj(V_i) w of the second Gram-Schmidt pass (V is read once)
         double ar[UPD_REG], ai[UPD_REG];
-        C wp = C{0, 0};
-        if (p < p1) {
-            wp = w[p];
+#pragma unroll
+        for (int i = 0; i < UPD_REG; ++i) ar[i] = ai[i] = 0.0;
+        for (int64_t p = p0 + threadIdx.x; p < p1; p += KT) {
+            C vr[UPD_REG];
 #pragma unroll
             for (int i = 0; i < UPD_REG; ++i)
                 if (i < nv) vr[i] = V[(int64_t)i * ldv + p];
-            double ax = wp.x, ay = wp.y;
+            const C w0 = w[p];
+            double ax = w0.x, ay = w0.y;
 #pragma unroll
             for (int i = 0; i < UPD_REG; ++i)
                 if (i < nv) {
@@ -118,40 +130,68 @@ __global__ __launch_bounds__(KT) void k_update(const C* __restrict__ V, int64_t 
                     ax -= (double)vr[i].x * hi.x - (double)vr[i].y * hi.y;
                     ay -= (double)vr[i].x * hi.y + (double)vr[i].y * hi.x;
                 }
-            wp = from_d2<C>(double2{ax, ay});
+            const C wp = from_d2<C>(double2{ax, ay});
             w[p] = wp;
+#pragma unroll
+            for (int i = 0; i < UPD_REG; ++i)
+                if (i < nv) {
+                    ar[i] += (double)vr[i].x * wp.x + (double)vr[i].y * wp.y;
+                    ai[i] += (double)vr[i].x * wp.y - (double)vr[i].y * wp.x;
+                }
         }
         double2* mine = part + (int64_t)blockIdx.x * ldp;
 #pragma unroll
         for (int i0 = 0; i0 < UPD_REG; i0 += IC) {
             if (i0 >= nv) break;
-#pragma unroll
-            for (int q = 0; q < IC; ++q) {
-                ar[i0 + q] = ai[i0 + q] = 0.0;
-                if (p < p1 && i0 + q < nv) {
-                    const C v = vr[i0 + q];
-                    ar[i0 + q] = (double)v.x * wp.x + (double)v.y * wp.y;
-                    ai[i0 + q] = (double)v.x * wp.y - (double)v.y * wp.x;
-                }
-            }
             double (&sr)[IC] = *reinterpret_cast<double (*)[IC]>(&ar[i0]);
             double (&si)[IC] = *reinterpret_cast<double (*)[IC]>(&ai[i0]);
             block_store<IC>(sr, si, mine + i0, nv - i0);
         }
         return;
     }
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += KT) {
-        const C wp = w[p];
-        double ax = wp.x, ay = wp.y;
-        for (int i = 0; i < nv; ++i) {
-            const C v = V[(int64_t)i * ldv + p];
-            const double2 hi = h[i];
-            ax -= (double)v.x * hi.x - (double)v.y * hi.y;
-            ay -= (double)v.x * hi.y + (double)v.y * hi.x;
+    if (pair_ok<C>(V, w, ldv, p0)) {
+        // two points per lane, 16-byte loads and stores
+        float4* __restrict__ w4 = (float4*)(w + p0);
+        const int64_t npair = (p1 - p0) >> 1;
+        for (int64_t k = threadIdx.x; k < npair; k += KT) {
+            const float4 a = w4[k];
+            double ax = a.x, ay = a.y, bx = a.z, by = a.w;
+            for (int i = 0; i < nv; ++i) {
+                const float4 v = ((const float4*)(V + (int64_t)i * ldv + p0))[k];
+                const double2 hi = h[i];
+                ax -= (double)v.x * hi.x - (double)v.y * hi.y;
+                ay -= (double)v.x * hi.y + (double)v.y * hi.x;
+                bx -= (double)v.z * hi.x - (double)v.w * hi.y;
+                by -= (double)v.z * hi.y + (double)v.w * hi.x;
+            }
+            w4[k] = float4{(float)ax, (float)ay, (float)bx, (float)by};
         }
-        w[p] = from_d2<C>(double2{ax, ay});
+        if (((p1 - p0) & 1) && threadIdx.x == KT - 1) {
+            const int64_t p = p1 - 1;
+            const C wp = w[p];
+            double ax = wp.x, ay = wp.y;
+            for (int i = 0; i < nv; ++i) {
+                const C v = V[(int64_t)i * ldv + p];
+                const double2 hi = h[i];
+                ax -= (double)v.x * hi.x - (double)v.y * hi.y;
+                ay -= (double)v.x * hi.y + (double)v.y * hi.x;
+            }
+            w[p] = from_d2<C>(double2{ax, ay});
+        }
+    } else {
+        for (int64_t p = p0 + threadIdx.x; p < p1; p += KT) {
+            const C wp = w[p];
+            double ax = wp.x, ay = wp.y;
+            for (int i = 0; i < nv; ++i) {
+                const C v = V[(int64_t)i * ldv + p];
+                const double2 hi = h[i];
+                ax -= (double)v.x * hi.x - (double)v.y * hi.y;
+                ay -= (double)v.x * hi.y + (double)v.y * hi.x;
+            }
+            w[p] = from_d2<C>(double2{ax, ay});
+        }
     }
-    // each thread reads back only the points it wrote: no barrier needed before the sweeps
+    __syncthreads();   // the sweeps below may read points written by other threads of the block
     double2* mine = part + (int64_t)blockIdx.x * ldp;
     if (MODE == 1) dots_body(V, ldv, nv, w, p0, p1, mine);
     if (MODE == 2) norm_body(w, p0, p1, mine);
@@ -271,12 +311,16 @@ int launch_dots(bool c128, const void* V, int64_t ldv, int nv, const void* w, in
 int launch_stencil_dots(const hz_problem* p, bool c128, const void* z, const void* V, int64_t ldv, int nv,
                         void* w, Split sp, double2* part, int ldp, const int* skip, hipStream_t s) {
     const StencilCoef sc = stencil_coef(p, c128, false);
+    // the pair form needs even block starts (per_block is a multiple of the block size) and an
+    // even row length
+    const int pairs = !c128 && stencil_pairs_ok(p, z, w) && (sp.per_block & 1) == 0 ? 1 : 0;
     if (c128)
         hipLaunchKernelGGL(k_stencil_dots<double2>, dim3(sp.nblk), dim3(KT), 0, s, (const double2*)z, sc, p->nxt,
-                           p->nyt, (const double2*)V, ldv, nv, (double2*)w, p->n, sp.per_block, part, ldp, skip);
+                           p->nyt, (const double2*)V, ldv, nv, (double2*)w, p->n, sp.per_block, part, ldp, skip, 0);
     else
         hipLaunchKernelGGL(k_stencil_dots<float2>, dim3(sp.nblk), dim3(KT), 0, s, (const float2*)z, sc, p->nxt,
-                           p->nyt, (const float2*)V, ldv, nv, (float2*)w, p->n, sp.per_block, part, ldp, skip);
+                           p->nyt, (const float2*)V, ldv, nv, (float2*)w, p->n, sp.per_block, part, ldp, skip,
+                           pairs);
     HZ_LAUNCH_CHECK();
     return HZ_OK;
 }

@@ -2,6 +2,8 @@
 // (shared by the single-system and the ragged-batch kernels).
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 #include "krylov.h"
 
@@ -59,9 +61,59 @@ __device__ __forceinline__ void block_store(double (&ar)[NV], double (&ai)[NV], 
     }
 }
 
+// FP32 complex vectors with an even stride and 16-byte aligned bases are read two points per
+// lane (one 16-byte load per vector): the pair path of the sweeps below.
+template <typename C>
+__device__ __forceinline__ bool pair_ok(const void* a, const void* b, int64_t ldv, int64_t p0) {
+    if constexpr (std::is_same<C, float2>::value)
+        return ((ldv | p0) & 1) == 0 && ((((uintptr_t)a) | ((uintptr_t)b)) & 15) == 0;
+    return false;
+}
+
+// part[i] = sum over [p0, p1) of conj(V_i) w, i < nv, two points per lane
+__device__ __forceinline__ void dots_body_pairs(const float2* __restrict__ V, int64_t ldv, int nv,
+                                                const float2* __restrict__ w, int64_t p0, int64_t p1,
+                                                double2* __restrict__ part) {
+    const int64_t npair = (p1 - p0) >> 1;
+    const float4* __restrict__ w4 = (const float4*)(w + p0);
+    for (int i0 = 0; i0 < nv; i0 += IC) {
+        double ar[IC], ai[IC];
+#pragma unroll
+        for (int q = 0; q < IC; ++q) ar[q] = ai[q] = 0.0;
+        for (int64_t k = threadIdx.x; k < npair; k += KT) {
+            const float4 a = w4[k];
+#pragma unroll
+            for (int q = 0; q < IC; ++q) {
+                if (i0 + q < nv) {
+                    const float4 v = ((const float4*)(V + (int64_t)(i0 + q) * ldv + p0))[k];
+                    ar[q] += (double)v.x * a.x + (double)v.y * a.y + (double)v.z * a.z + (double)v.w * a.w;
+                    ai[q] += (double)v.x * a.y - (double)v.y * a.x + (double)v.z * a.w - (double)v.w * a.z;
+                }
+            }
+        }
+        if (((p1 - p0) & 1) && threadIdx.x == KT - 1) {   // odd tail point
+            const float2 a = w[p1 - 1];
+#pragma unroll
+            for (int q = 0; q < IC; ++q)
+                if (i0 + q < nv) {
+                    const float2 v = V[(int64_t)(i0 + q) * ldv + p1 - 1];
+                    ar[q] += (double)v.x * a.x + (double)v.y * a.y;
+                    ai[q] += (double)v.x * a.y - (double)v.y * a.x;
+                }
+        }
+        block_store<IC>(ar, ai, part + i0, nv - i0);
+    }
+}
+
 template <typename C>
 __device__ __forceinline__ void dots_body(const C* __restrict__ V, int64_t ldv, int nv, const C* __restrict__ w,
                                  int64_t p0, int64_t p1, double2* __restrict__ part) {
+    if constexpr (std::is_same<C, float2>::value) {
+        if (pair_ok<C>(V, w, ldv, p0)) {
+            dots_body_pairs(V, ldv, nv, w, p0, p1, part);
+            return;
+        }
+    }
     for (int i0 = 0; i0 < nv; i0 += IC) {
         double ar[IC], ai[IC];
 #pragma unroll
@@ -84,9 +136,22 @@ __device__ __forceinline__ void dots_body(const C* __restrict__ V, int64_t ldv, 
 template <typename C>
 __device__ __forceinline__ void norm_body(const C* __restrict__ w, int64_t p0, int64_t p1, double2* __restrict__ out) {
     double a[1] = {0.0}, z[1] = {0.0};
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += KT) {
-        const C wp = w[p];
-        a[0] += (double)wp.x * wp.x + (double)wp.y * wp.y;
+    if (pair_ok<C>(w, w, 0, p0)) {
+        const float4* __restrict__ w4 = (const float4*)(w + p0);
+        const int64_t npair = (p1 - p0) >> 1;
+        for (int64_t k = threadIdx.x; k < npair; k += KT) {
+            const float4 v = w4[k];
+            a[0] += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
+        }
+        if (((p1 - p0) & 1) && threadIdx.x == KT - 1) {
+            const C v = w[p1 - 1];
+            a[0] += (double)v.x * v.x + (double)v.y * v.y;
+        }
+    } else {
+        for (int64_t p = p0 + threadIdx.x; p < p1; p += KT) {
+            const C wp = w[p];
+            a[0] += (double)wp.x * wp.x + (double)wp.y * wp.y;
+        }
     }
     block_store<1>(a, z, out, 1);
 }

@@ -27,6 +27,9 @@ struct StencilCoef {
     int conj_diag;
 };
 StencilCoef stencil_coef(const hz_problem* p, bool fp64, bool adjoint);
+// true when the FP32 operator can run two points per lane on x -> y (even row length, 16-byte
+// aligned vectors)
+bool stencil_pairs_ok(const hz_problem* p, const void* x, const void* y);
 
 // y = A x (or A^H x) in the precision of the complex type (float2 or double2).
 int launch_stencil(const hz_problem* p, bool fp64, bool adjoint, const void* x, void* y, hipStream_t s,

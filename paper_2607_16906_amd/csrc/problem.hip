@@ -98,6 +98,10 @@ __global__ __launch_bounds__(ST_THREADS) void k_stencil(
                           blockIdx.y * ST_TY);
 }
 
+bool stencil_pairs_ok(const hz_problem* p, const void* x, const void* y) {
+    return (p->nxt & 1) == 0 && ((((uintptr_t)x) | ((uintptr_t)y)) & 15) == 0;
+}
+
 StencilCoef stencil_coef(const hz_problem* p, bool fp64, bool adjoint) {
     StencilCoef c;
     if (fp64) {

@@ -67,4 +67,46 @@ __device__ __forceinline__ void stencil_tile(
     }
 }
 
+// The same operator for the two adjacent points (p, p + 1) = (gi, gi + 1) of one row, gi even,
+// nx even, u / y 16-byte aligned: the centre, north and south pairs are 16-byte loads, the west
+// and east neighbours 8-byte loads (zero outside the grid), the result one 16-byte store. Same
+// term order as stencil_tile.
+__device__ __forceinline__ void stencil_pair(const float2* __restrict__ u, float2* __restrict__ y,
+                                             const float* __restrict__ k2, const float2* __restrict__ cE,
+                                             const float2* __restrict__ cW, const float2* __restrict__ cN,
+                                             const float2* __restrict__ cS, const float2* __restrict__ dx,
+                                             const float2* __restrict__ dy, int conj_diag, int nx, int ny,
+                                             int64_t p) {
+    using C = float2;
+    const int gj = (int)(p / nx), gi = (int)(p - (int64_t)gj * nx);
+    const int64_t q = p >> 1, hq = nx >> 1;
+    const float4* __restrict__ u4 = (const float4*)u;
+    const float4 c = u4[q];
+    const float4 zero4{0.f, 0.f, 0.f, 0.f};
+    const float4 nn = gj + 1 < ny ? u4[q + hq] : zero4;
+    const float4 ss = gj > 0 ? u4[q - hq] : zero4;
+    const C uw = gi > 0 ? u[p - 1] : C{0.f, 0.f};
+    const C ue = gi + 2 < nx ? u[p + 2] : C{0.f, 0.f};
+    const float2 kk = ((const float2*)k2)[q];
+    const C dyj = dy[gj], nj = cN[gj], sj = cS[gj];
+    const C u0{c.x, c.y}, u1{c.z, c.w};
+    C d0 = C{kk.x - dx[gi].x - dyj.x, -dx[gi].y - dyj.y};
+    C d1 = C{kk.y - dx[gi + 1].x - dyj.x, -dx[gi + 1].y - dyj.y};
+    if (conj_diag) {
+        d0.y = -d0.y;
+        d1.y = -d1.y;
+    }
+    C a0 = cmul(d0, u0);
+    a0 = cadd(a0, cmul(cE[gi], u1));
+    a0 = cadd(a0, cmul(cW[gi], uw));
+    a0 = cadd(a0, cmul(nj, C{nn.x, nn.y}));
+    a0 = cadd(a0, cmul(sj, C{ss.x, ss.y}));
+    C a1 = cmul(d1, u1);
+    a1 = cadd(a1, cmul(cE[gi + 1], ue));
+    a1 = cadd(a1, cmul(cW[gi + 1], u0));
+    a1 = cadd(a1, cmul(nj, C{nn.z, nn.w}));
+    a1 = cadd(a1, cmul(sj, C{ss.z, ss.w}));
+    ((float4*)y)[q] = float4{a0.x, a0.y, a1.x, a1.y};
+}
+
 }  // namespace hz
