@@ -102,6 +102,16 @@ bool stencil_pairs_ok(const hz_problem* p, const void* x, const void* y) {
     return (p->nxt & 1) == 0 && ((((uintptr_t)x) | ((uintptr_t)y)) & 15) == 0;
 }
 
+__global__ __launch_bounds__(256) void k_stencil_wide(const float2* __restrict__ u, float2* __restrict__ y,
+                                                      const float* __restrict__ k2, const float2* __restrict__ cE,
+                                                      const float2* __restrict__ cW, const float2* __restrict__ cN,
+                                                      const float2* __restrict__ cS, const float2* __restrict__ dx,
+                                                      const float2* __restrict__ dy, int conj_diag, int nx, int ny,
+                                                      const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    stencil_tile_wide(u, y, k2, cE, cW, cN, cS, dx, dy, conj_diag, nx, ny, blockIdx.x * SW_TX, blockIdx.y * SW_TY);
+}
+
 StencilCoef stencil_coef(const hz_problem* p, bool fp64, bool adjoint) {
     StencilCoef c;
     if (fp64) {
@@ -143,6 +153,11 @@ int launch_stencil(const hz_problem* p, bool fp64, bool adjoint, const void* x, 
                            (const double2*)c.E, (const double2*)c.W, (const double2*)c.N, (const double2*)c.S,
                            (const double2*)c.dx, (const double2*)c.dy, c.conj_diag, p->nxt, p->nyt,
                            nullptr, skip);
+    } else if (stencil_pairs_ok(p, x, y)) {
+        const dim3 gw((p->nxt + SW_TX - 1) / SW_TX, (p->nyt + SW_TY - 1) / SW_TY);
+        hipLaunchKernelGGL(k_stencil_wide, gw, dim3(256), 0, s, (const float2*)x, (float2*)y, (const float*)c.k2,
+                           (const float2*)c.E, (const float2*)c.W, (const float2*)c.N, (const float2*)c.S,
+                           (const float2*)c.dx, (const float2*)c.dy, c.conj_diag, p->nxt, p->nyt, skip);
     } else {
         hipLaunchKernelGGL((k_stencil<float, ST_PLAIN>), grid, dim3(ST_THREADS), 0, s,
                            (const float2*)x, (float2*)y, nullptr, (const float*)c.k2,

@@ -67,6 +67,72 @@ __device__ __forceinline__ void stencil_tile(
     }
 }
 
+// FP32 operator on a 64 x 32 output tile (nx even, 16-byte aligned u and y): the (32 + 2) x 64
+// interior of the input tile is staged in LDS with 16-byte loads (two points each), the two halo
+// columns with 8-byte loads; thread (c, r) computes the point pair (2c, 2c + 1) of rows r, r + 8,
+// r + 16, r + 24 and stores each pair with one 16-byte store. Same term order as stencil_tile.
+constexpr int SW_TX = 64, SW_TY = 32;
+__device__ __forceinline__ void stencil_tile_wide(const float2* __restrict__ u, float2* __restrict__ y,
+                                                  const float* __restrict__ k2, const float2* __restrict__ cE,
+                                                  const float2* __restrict__ cW, const float2* __restrict__ cN,
+                                                  const float2* __restrict__ cS, const float2* __restrict__ dx,
+                                                  const float2* __restrict__ dy, int conj_diag, int nx, int ny,
+                                                  int i0, int j0) {
+    using C = float2;
+    __shared__ __attribute__((aligned(16))) float4 mid[SW_TY + 2][SW_TX / 2];   // columns i0 .. i0 + 63
+    __shared__ C hal[SW_TY + 2][2];                                              // columns i0 - 1, i0 + 64
+    const int hq = nx >> 1;
+    const float4* __restrict__ u4 = (const float4*)u;
+    for (int t = threadIdx.x; t < (SW_TY + 2) * (SW_TX / 2); t += 256) {
+        const int ly = t / (SW_TX / 2), lc = t - ly * (SW_TX / 2);
+        const int gj = j0 + ly - 1, gi = i0 + 2 * lc;
+        float4 v{0.f, 0.f, 0.f, 0.f};
+        if (gj >= 0 && gj < ny && gi < nx) v = u4[(int64_t)gj * hq + (gi >> 1)];
+        mid[ly][lc] = v;
+    }
+    for (int t = threadIdx.x; t < (SW_TY + 2) * 2; t += 256) {
+        const int ly = t >> 1, side = t & 1;
+        const int gj = j0 + ly - 1, gi = side ? i0 + SW_TX : i0 - 1;
+        C v{0.f, 0.f};
+        if (gj >= 0 && gj < ny && gi >= 0 && gi < nx) v = u[(int64_t)gj * nx + gi];
+        hal[ly][side] = v;
+    }
+    __syncthreads();
+    const int c = threadIdx.x & 31, r0 = threadIdx.x >> 5;
+    const int gi = i0 + 2 * c;
+    if (gi >= nx) return;
+    const C e0 = cE[gi], e1 = cE[gi + 1], w0 = cW[gi], w1 = cW[gi + 1], x0 = dx[gi], x1 = dx[gi + 1];
+#pragma unroll
+    for (int k = 0; k < SW_TY / 8; ++k) {
+        const int r = r0 + 8 * k, gj = j0 + r;
+        if (gj >= ny) break;
+        const float4 cc = mid[r + 1][c], nn = mid[r + 2][c], ss = mid[r][c];
+        const C uw = c > 0 ? C{mid[r + 1][c - 1].z, mid[r + 1][c - 1].w} : hal[r + 1][0];
+        const C ue = c < SW_TX / 2 - 1 ? C{mid[r + 1][c + 1].x, mid[r + 1][c + 1].y} : hal[r + 1][1];
+        const int64_t p = (int64_t)gj * nx + gi;
+        const float2 kk = *(const float2*)(k2 + p);
+        const C dyj = dy[gj], nj = cN[gj], sj = cS[gj];
+        const C u0{cc.x, cc.y}, u1{cc.z, cc.w};
+        C d0 = C{kk.x - x0.x - dyj.x, -x0.y - dyj.y};
+        C d1 = C{kk.y - x1.x - dyj.x, -x1.y - dyj.y};
+        if (conj_diag) {
+            d0.y = -d0.y;
+            d1.y = -d1.y;
+        }
+        C a0 = cmul(d0, u0);
+        a0 = cadd(a0, cmul(e0, u1));
+        a0 = cadd(a0, cmul(w0, uw));
+        a0 = cadd(a0, cmul(nj, C{nn.x, nn.y}));
+        a0 = cadd(a0, cmul(sj, C{ss.x, ss.y}));
+        C a1 = cmul(d1, u1);
+        a1 = cadd(a1, cmul(e1, ue));
+        a1 = cadd(a1, cmul(w1, u0));
+        a1 = cadd(a1, cmul(nj, C{nn.z, nn.w}));
+        a1 = cadd(a1, cmul(sj, C{ss.z, ss.w}));
+        *(float4*)(y + p) = float4{a0.x, a0.y, a1.x, a1.y};
+    }
+}
+
 // The same operator for the two adjacent points (p, p + 1) = (gi, gi + 1) of one row, gi even,
 // nx even, u / y 16-byte aligned: the centre, north and south pairs are 16-byte loads, the west
 // and east neighbours 8-byte loads (zero outside the grid), the result one 16-byte store. Same
