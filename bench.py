@@ -8,7 +8,7 @@ network in FP32 (the plain FP32 form) is timed beside it, and the dominant netwo
 timed alone with HIP events for the roofline. The oracle is timed on the host over a bounded
 sample of iterations.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--roofline-only]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extra] [--roofline-only] [--only SECTION]
 """
 from __future__ import annotations
 
@@ -43,10 +43,10 @@ def kernel_fingerprint():
     return h.hexdigest()
 
 
-def measured_traffic(layer):
+def measured_traffic(layer, variant):
     """HBM bytes per launch of the dominant layer from the committed counter summary (FETCH_SIZE +
     WRITE_SIZE, scaled by a plain copy of known size), or None when the summary is missing, is for
-    another layer, or the kernel sources changed since the counters were taken."""
+    another layer or launch variant, or the kernel sources changed since the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -55,7 +55,8 @@ def measured_traffic(layer):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
     try:
-        if kv.get("source_md5") != kernel_fingerprint() or int(kv.get("layer", -1)) != layer:
+        if (kv.get("source_md5") != kernel_fingerprint() or int(kv.get("layer", -1)) != layer
+                or kv.get("variant") != variant):
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -274,11 +275,14 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the training and batched sections")
+    ap.add_argument("--roofline-variant", default="", help="with --roofline-only: pin the layer's launch variant 'tn,rows'")
     ap.add_argument("--roofline-only", action="store_true", help="only the per-layer roofline timing")
     ap.add_argument("--roofline-layer", type=int, default=-1,
                     help="with --roofline-only: time this layer alone (for a profiler run of one kernel)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="with --roofline-only: also copy 512 MiB with a plain device copy (counter calibration)")
+    ap.add_argument("--only", choices=["training", "batched", "large"], default=None,
+                    help="run one extra section alone and print its JSON (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the single-solve workload is measured on one MI355X; "
@@ -295,6 +299,14 @@ def main():
     torch.cuda.set_device(0)
     w = np.load(WEIGHTS)
     theta = w["theta"].astype(np.float32)
+    if args.only:
+        if args.only == "training":
+            res = bench_training(hz, torch, steps=2)
+        else:
+            net1 = hz.Net(LEVELS, BASE, IN_CH, theta)
+            res = bench_batched(hz, torch, net1) if args.only == "batched" else bench_large(hz, torch, net1)
+        print(json.dumps({args.only: res}))
+        return
     s = c2_system(0)
     gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW)
     net = hz.Net(LEVELS, BASE, IN_CH, theta)
@@ -302,15 +314,22 @@ def main():
     net.autotune(gp, "bf16")
     net.autotune(gp, "fp32")
 
+    if args.roofline_only and args.roofline_variant:
+        # pin the launch variant (the profiler runs must time the launch the solve uses)
+        tn, rows = (int(t) for t in args.roofline_variant.split(","))
+        lay = [r for r in net_layers(LEVELS, BASE, IN_CH, Hp, Wp) if r[0] == args.roofline_layer][0]
+        net.set_layer_variant(args.roofline_layer, lay[4], lay[5], tn, rows)
     layers = time_layers(net, Hp, Wp, reps=50, only=args.roofline_layer if args.roofline_only else -1)
     dom = max(layers, key=lambda r: r["ms"])
+    tn, rows = net.layer_variant(dom["layer"], dom["H"], dom["W"]) if dom["kind"] == 0 else (0, 0)
+    variant = f"tn{tn} rows{rows}"
     achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
     net_ms = sum(r["ms"] for r in layers)
     net_flops = sum(r["flops"] for r in layers)
     kname = "k_conv3<PolBF16, ...> (3x3 layer, autotuned variant)" if dom["kind"] == 0 else "k_convT2<PolBF16>"
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": measured_traffic(dom["layer"]),
-                "kernel": kname, "layer": dom["layer"],
+                "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": measured_traffic(dom["layer"], variant),
+                "kernel": kname, "variant": variant, "layer": dom["layer"],
                 "shape": f"{dom['cin']}->{dom['cout']} ch on {dom['H']}x{dom['W']}",
                 "flops_per_launch": dom["flops"], "avg_launch_ms": round(dom["ms"], 5)}
     if args.roofline_only:

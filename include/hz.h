@@ -138,6 +138,19 @@ int no_precond_apply(const no_net* net, const hz_problem* p, no_prec prec, hz_dt
 int no_autotune(const no_net* net, const hz_problem* p, no_prec prec, void* ws_dev, size_t ws_bytes,
                 void* stream);
 
+/* Launch variant used for 3x3 layer `layer` at (batch, H, W, prec): output-channel tile *tn
+ * (16, 32 or 64; 0 = the built-in choice) and pixel-tile height *rows (8 or 16), as no_autotune
+ * chose it or no_set_layer_variant pinned it. Errors: NULL pointer, not a 3x3 layer. */
+int no_layer_variant(const no_net* net, int layer, no_prec prec, int batch, int H, int W, int32_t* tn,
+                     int32_t* rows);
+
+/* Pin the launch variant of 3x3 layer `layer` at (batch, H, W, prec) to (tn, rows), as if
+ * no_autotune had chosen it (a later no_autotune of that size keeps it). Every variant gives
+ * the same result bits; this fixes the launch for profiling and measurement. Errors: not a 3x3
+ * layer, tn not in {16, 32, 64} or not dividing the stored output channels, rows not 8 or 16.
+ * Thread-safe. */
+int no_set_layer_variant(const no_net* net, int layer, no_prec prec, int batch, int H, int W, int tn, int rows);
+
 /* Shape of layer `layer` (0-based, in the order of the flat parameter vector):
  * kind 0 = 3x3 convolution + ReLU, 1 = 2x2 stride-2 transposed convolution, 2 = 1x1 head;
  * cin_p / cout_p = input / output channels as stored (zero-padded to a multiple of 16, the

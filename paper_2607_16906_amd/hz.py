@@ -58,6 +58,8 @@ SIGNATURES = {
     "no_workspace_size": (_SZ, [_P, _P, _I]),
     "no_precond_apply": (_I, [_P, _P, _I, _I, _P, _P, _P, _SZ, _P]),
     "no_autotune": (_I, [_P, _P, _I, _P, _SZ, _P]),
+    "no_layer_variant": (_I, [_P, _I, _I, _I, _I, _I, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)]),
+    "no_set_layer_variant": (_I, [_P, _I, _I, _I, _I, _I, _I, _I]),
     "no_layer_info": (_I, [_P, _I, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32),
                            ct.POINTER(ct.c_int32)]),
     "no_layer_forward": (_I, [_P, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P, _SZ, _P]),
@@ -205,6 +207,18 @@ class Net:
         ws = _ws(lib.no_workspace_size(self.handle, problem.handle, PREC[prec]))
         _check(lib.no_autotune(self.handle, problem.handle, PREC[prec], _ptr(ws), ct.c_size_t(ws.numel()), _stream()),
                "no_autotune")
+
+    def layer_variant(self, layer: int, H: int, W: int, prec: str = "bf16", batch: int = 1):
+        """(tn, rows) launch variant of a 3x3 layer at this size (no_layer_variant)."""
+        tn, rows = ct.c_int32(), ct.c_int32()
+        _check(load_library().no_layer_variant(self.handle, layer, PREC[prec], batch, H, W, ct.byref(tn),
+                                               ct.byref(rows)), "no_layer_variant")
+        return tn.value, rows.value
+
+    def set_layer_variant(self, layer: int, H: int, W: int, tn: int, rows: int, prec: str = "bf16", batch: int = 1):
+        """Pin the launch variant of a 3x3 layer at this size (no_set_layer_variant)."""
+        _check(load_library().no_set_layer_variant(self.handle, layer, PREC[prec], batch, H, W, tn, rows),
+               "no_set_layer_variant")
 
     def layer_info(self, layer: int):
         """(kind, cin_p, cout_p, cat_cp) of one layer (no_layer_info)."""

@@ -90,3 +90,33 @@ def test_autotuned_variants_keep_parity(prec, tol):
     ref = unet.precond_apply(th, specs, op, v)
     assert rel(z1, ref) <= tol
     assert rel(z1, z0.reshape(op.ny, op.nx)) <= (1e-13 if prec == "fp64" else tol)
+
+
+def test_pinned_layer_variants_identical_bits():
+    # every launch variant accumulates each output in the same order: pinning other channel tiles
+    # and tile heights leaves the BF16 and FP32 outputs bit-identical
+    from paper_2607_16906_amd import hz
+    op, gp, specs, theta, net, v = setup(3, 16, 5, 60, 10, seed=6)
+    Hp = (op.ny + 3) // 4 * 4
+    convs = [i for i, s in enumerate(specs) if s[1] == "conv3"]
+    level = {}
+    for i, s in enumerate(specs):
+        if s[0].startswith("enc"):
+            level[i] = int(s[0][3])
+        elif s[0].startswith("dec"):
+            level[i] = int(s[0][3])
+    for prec, dt in (("bf16", torch.complex64), ("fp32", torch.complex64)):
+        vd = to_dev(v, dt)
+        outs = []
+        for tn0, rows in ((16, 8), (16, 16), (32, 8)):
+            for i in convs:
+                H = Hp >> level[i]
+                tn = tn0 if specs[i][3] % tn0 == 0 else 16
+                net.set_layer_variant(i, H, H, tn, rows, prec=prec)
+                assert net.layer_variant(i, H, H, prec=prec) == (tn, rows)
+            outs.append(net.apply(gp, vd, prec=prec))
+        assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+    with pytest.raises(hz.HzError):
+        net.set_layer_variant(convs[0], Hp, Hp, 24, 8)
+    with pytest.raises(hz.HzError):
+        net.set_layer_variant(len(specs) - 1, Hp, Hp, 16, 8)   # the head is not a 3x3 layer
