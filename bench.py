@@ -171,9 +171,10 @@ def bench_training(hz, torch, steps=3, batch=64):
             "loss_last": float(losses[-1].item())}
 
 
-def bench_batched(hz, torch, net, nsys=32, maxit=60):
-    """Ragged batch: nsys systems with the batched-serving size mix (128..512 interior + 16..32 PML),
-    BF16 network, FGMRES(30), advanced together for maxit iterations (bounded run)."""
+def bench_batched(hz, torch, net, nsys=128, maxit=30):
+    """Ragged batch: the 128 systems of the batched-serving mix (128..512 interior + 16..32 PML, each
+    with its own velocity and sources), BF16 network, FGMRES(30), advanced together for one cycle
+    of maxit iterations (bounded run)."""
     from synth import H_10PPW, c4_sizes, c4_system
     sizes = c4_sizes(128)[:nsys]
     probs, bs = [], []
