@@ -11,26 +11,23 @@ namespace hz {
 
 inline int round16(int c) { return (c + 15) / 16 * 16; }
 
-// X[y][x][0..7] = [Re v / s, Im v / s, (c / c_ref, sigma_x, sigma_y), 0...] on the grid, 0 in the padding.
-// fixed_s > 0: the caller knows ||v|| / sqrt(n) (a unit-norm Krylov vector) and sc is not read.
+// X[y][x][0..7] = [Re v / s, Im v / s, (c / c_ref, sigma_x, sigma_y), 0...] on the grid, 0 in the
+// padding, for padded pixel idx; is = 1 / s. vscale: v <- vscale v first (rounded to the vector
+// precision, stored back through vout).
 template <class P, typename C>
-__global__ void k_pack(const C* __restrict__ v, const double* __restrict__ sc, const double* __restrict__ cnd,
-                       const double* __restrict__ sigx, const double* __restrict__ sigy, int nxt, int nyt, int Hp,
-                       int Wp, int in_ch, typename P::T* __restrict__ X, const int* __restrict__ skip,
-                       double fixed_s = 0.0, const double* __restrict__ vscale = nullptr, C* vout = nullptr) {
+__device__ __forceinline__ void pack_pixel(const C* __restrict__ v, double is, const double* __restrict__ cnd,
+                                           const double* __restrict__ sigx, const double* __restrict__ sigy, int nxt,
+                                           int nyt, int Wp, int in_ch, typename P::T* __restrict__ X, int64_t idx,
+                                           const double* __restrict__ vscale, C* vout) {
     using T = typename P::T;
-    if (skip && *skip) return;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)Hp * Wp) return;
     const int yy = (int)(idx / Wp), xx = (int)(idx % Wp);
     __attribute__((aligned(16))) T out[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) out[c] = P::cvt(0);
     if (yy < nyt && xx < nxt) {
         const int64_t g = (int64_t)yy * nxt + xx;
-        const double is = fixed_s > 0 ? 1.0 / fixed_s : sc[1];
         C a = v[g];
-        if (vscale) {   // v <- vscale v first (rounded to the vector precision, stored back)
+        if (vscale) {
             const double f = *vscale;
             a = from_d2<C>(double2{a.x * f, a.y * f});
             vout[g] = a;
@@ -47,6 +44,20 @@ __global__ void k_pack(const C* __restrict__ v, const double* __restrict__ sc, c
     static_assert((8 * sizeof(T)) % 16 == 0, "pack: 8 channels must be whole 16-byte vectors");
 #pragma unroll
     for (int c = 0; c < 8; c += 16 / (int)sizeof(T)) *(uint4*)(dst + c) = *(const uint4*)(out + c);
+}
+
+// One padded pixel per thread. fixed_s > 0: the caller knows ||v|| / sqrt(n) (a unit-norm Krylov
+// vector) and sc is not read; otherwise s = 1 / sc[1].
+template <class P, typename C>
+__global__ void k_pack(const C* __restrict__ v, const double* __restrict__ sc, const double* __restrict__ cnd,
+                       const double* __restrict__ sigx, const double* __restrict__ sigy, int nxt, int nyt, int Hp,
+                       int Wp, int in_ch, typename P::T* __restrict__ X, const int* __restrict__ skip,
+                       double fixed_s = 0.0, const double* __restrict__ vscale = nullptr, C* vout = nullptr) {
+    if (skip && *skip) return;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)Hp * Wp) return;
+    const double is = fixed_s > 0 ? 1.0 / fixed_s : sc[1];
+    pack_pixel<P, C>(v, is, cnd, sigx, sigy, nxt, nyt, Wp, in_ch, X, idx, vscale, vout);
 }
 
 

@@ -21,8 +21,10 @@
 #include <vector>
 
 #include "krylov.h"
+#include "krylov_impl.h"
 #include "net_impl.h"
 #include "problem.h"
+#include "stencil_impl.h"
 
 namespace hz {
 
@@ -659,6 +661,13 @@ __global__ void k_pool_bwd(typename P::T* __restrict__ skip, const typename P::T
 
 // ------------------------------------------------------------------ workspace
 
+// The per-sample problem data a batched launch reads (every sample of a batch has the same grid).
+struct SampleProb {
+    const float* k2;
+    const double *cnd, *sigx, *sigy;
+    const float2 *fE, *fW, *fN, *fS, *aE, *aW, *aN, *aS, *dx, *dy;
+};
+
 template <class P>
 struct TrainBufs {
     using T = typename P::T;
@@ -669,6 +678,7 @@ struct TrainBufs {
     double* ypart;                   // [B][stencil blocks] ||y_b||^2 partials
     double *sc, *nr;                 // [B][2], [B]
     float* coef;                     // [B]
+    SampleProb* sprob;               // [B] per-sample problem pointers
     float *wpart, *wpartb;           // weight-gradient chunk partials
     size_t wcap, bcap;               // their capacities (floats)
     size_t total;
@@ -710,6 +720,7 @@ static TrainBufs<P> train_layout(const no_net* net, const hz_problem* p, int B, 
     t.sc = c.take<double>(2 * (size_t)B);
     t.nr = c.take<double>(B);
     t.coef = c.take<float>(B);
+    t.sprob = c.take<SampleProb>(B);
     size_t wmax = 0, bmax = 0;
     for (const Layer& ly : net->layers) {
         const int taps = ly.kind == L_CONV3 ? 9 : (ly.kind == L_CONVT2 ? 4 : 1);
@@ -825,6 +836,54 @@ static int dgrad_convT(const no_net* net, const Layer& ly, const typename P::T* 
     return HZ_OK;
 }
 
+// ------------------------------------------------------------------ per-sample batches
+
+// ||r_b||^2 partials of every sample: block (q, b) covers [q per, (q + 1) per) of sample b.
+__global__ __launch_bounds__(KT) void k_norm_batched(const float2* __restrict__ r, int64_t n, int64_t per,
+                                                     double2* __restrict__ part, int nblk) {
+    const int b = blockIdx.y;
+    const int64_t p0 = (int64_t)blockIdx.x * per, p1 = min(n, p0 + per);
+    norm_body(r + (int64_t)b * n, p0, p1, part + (int64_t)b * nblk + blockIdx.x);
+}
+
+// network input of every sample (sample b on grid row blockIdx.y), scale 1 / s_b = sc[2 b + 1]
+template <class P>
+__global__ void k_pack_batched(const float2* __restrict__ r, int64_t n, const double* __restrict__ sc,
+                               const SampleProb* __restrict__ sp, int nxt, int nyt, int Hp, int Wp, int in_ch,
+                               typename P::T* __restrict__ X) {
+    const int b = blockIdx.y;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)Hp * Wp) return;
+    const SampleProb& q = sp[b];
+    pack_pixel<P, float2>(r + (int64_t)b * n, sc[2 * b + 1], q.cnd, q.sigx, q.sigy, nxt, nyt, Wp, in_ch,
+                          X + (int64_t)b * Hp * Wp * 8, idx, nullptr, (float2*)nullptr);
+}
+
+// y_b = r_b - A_b z_b with one ||y_b||^2 partial per tile (sample b = blockIdx.z)
+__global__ __launch_bounds__(ST_THREADS) void k_resid_batched(const float2* __restrict__ z, const float2* __restrict__ r,
+                                                              float2* __restrict__ y, int64_t n,
+                                                              const SampleProb* __restrict__ sp, int nxt, int nyt,
+                                                              double* __restrict__ part) {
+    const int b = blockIdx.z;
+    const SampleProb& q = sp[b];
+    const int64_t o = (int64_t)b * n;
+    const int nst = gridDim.x * gridDim.y;
+    stencil_tile<float, ST_RESID>(z + o, y + o, r + o, q.k2, q.fE, q.fW, q.fN, q.fS, q.dx, q.dy, 0, nxt, nyt,
+                                  part + (int64_t)b * nst + blockIdx.y * gridDim.x + blockIdx.x, blockIdx.x * ST_TX,
+                                  blockIdx.y * ST_TY);
+}
+
+// g_b = A_b^H y_b (sample b = blockIdx.z)
+__global__ __launch_bounds__(ST_THREADS) void k_adjoint_batched(const float2* __restrict__ y, float2* __restrict__ g,
+                                                                int64_t n, const SampleProb* __restrict__ sp, int nxt,
+                                                                int nyt) {
+    const int b = blockIdx.z;
+    const SampleProb& q = sp[b];
+    const int64_t o = (int64_t)b * n;
+    stencil_tile<float, ST_PLAIN>(y + o, g + o, nullptr, q.k2, q.aE, q.aW, q.aN, q.aS, q.dx, q.dy, 1, nxt, nyt, nullptr,
+                                  blockIdx.x * ST_TX, blockIdx.y * ST_TY);
+}
+
 // ------------------------------------------------------------------ loss + backward
 
 template <class P>
@@ -843,20 +902,26 @@ static int loss_backward_impl(const no_net* net, int B, const hz_problem* const*
     const int lv = net->a.levels;
     const std::vector<Layer>& Ls = net->layers;
     Split sp = krylov_split(n);
+    // the samples' problem pointers (one table, uploaded with the batch)
+    {
+        std::vector<SampleProb> hp(B);
+        for (int b = 0; b < B; ++b) {
+            const hz_problem* q = probs[b];
+            hp[b] = SampleProb{q->k2f, q->cnd, q->sigx, q->sigy, q->fE_f, q->fW_f, q->fN_f, q->fS_f,
+                               q->aE_f, q->aW_f, q->aN_f, q->aS_f, q->dx_f, q->dy_f};
+        }
+        HZ_HIP(hipMemcpyAsync(t.sprob, hp.data(), sizeof(SampleProb) * B, hipMemcpyHostToDevice, s));
+    }
     // scales s_b and ||r_b||
-    for (int b = 0; b < B; ++b)
-        HZ_TRY(launch_norm_partials(false, r + (int64_t)b * n, n, sp, t.rpart + (int64_t)b * sp.nblk, 1, 0, nullptr, s));
+    hipLaunchKernelGGL(k_norm_batched, dim3(sp.nblk, B), dim3(KT), 0, s, r, n, sp.per_block, t.rpart, sp.nblk);
+    HZ_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_sample_scales, dim3(B), dim3(64), 0, s, t.rpart, sp.nblk, n, t.sc, t.nr);
     HZ_LAUNCH_CHECK();
     // pack every sample with its own velocity channel
     const unsigned gp = (unsigned)(((int64_t)Hp * Wp + 255) / 256);
-    for (int b = 0; b < B; ++b) {
-        const hz_problem* pb = probs[b];
-        hipLaunchKernelGGL((k_pack<P, float2>), dim3(gp), dim3(256), 0, s, r + (int64_t)b * n, t.sc + 2 * b, pb->cnd,
-                           pb->sigx, pb->sigy, pb->nxt, pb->nyt, Hp, Wp, net->a.in_ch,
-                           (T*)t.f.X + (int64_t)b * Hp * Wp * 8, (const int*)nullptr);
-        HZ_LAUNCH_CHECK();
-    }
+    hipLaunchKernelGGL((k_pack_batched<P>), dim3(gp, B), dim3(256), 0, s, r, n, t.sc, t.sprob, p0->nxt, p0->nyt, Hp, Wp,
+                       net->a.in_ch, (T*)t.f.X);
+    HZ_LAUNCH_CHECK();
     HZ_TRY(unet_body<P>(net, t.f, Hp, Wp, B, nullptr, s));
     const Layer& lh = Ls.back();
     const T* D0 = lv > 1 ? (const T*)t.f.D[0] : (const T*)t.f.E[0];
@@ -868,10 +933,13 @@ static int loss_backward_impl(const no_net* net, int B, const hz_problem* const*
     }
     // y_b = r_b - A_b z_b with ||y_b||^2 partials, then A_b^H y_b
     const int nst = stencil_blocks(p0);
-    for (int b = 0; b < B; ++b) {
-        HZ_TRY(launch_resid32(probs[b], r + (int64_t)b * n, t.z + (int64_t)b * n, t.y + (int64_t)b * n,
-                              t.ypart + (int64_t)b * nst, s));
-        HZ_TRY(launch_stencil(probs[b], false, true, t.y + (int64_t)b * n, t.gz + (int64_t)b * n, s));
+    {
+        const dim3 g((p0->nxt + ST_TX - 1) / ST_TX, (p0->nyt + ST_TY - 1) / ST_TY, B);
+        hipLaunchKernelGGL(k_resid_batched, g, dim3(ST_THREADS), 0, s, t.z, r, t.y, n, t.sprob, p0->nxt, p0->nyt,
+                           t.ypart);
+        HZ_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_adjoint_batched, g, dim3(ST_THREADS), 0, s, t.y, t.gz, n, t.sprob, p0->nxt, p0->nyt);
+        HZ_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_loss, dim3(1), dim3(1024), 0, s, t.ypart, nst, t.nr, B, squared, t.coef, loss, per_sample);
     HZ_LAUNCH_CHECK();
