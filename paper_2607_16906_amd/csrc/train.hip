@@ -58,12 +58,19 @@ __global__ void k_head_batched(const typename P::T* __restrict__ D, int cin_p, c
     const int b = (int)(idx / n);
     const int64_t g = idx - (int64_t)b * n;
     const int yy = (int)(g / nxt), xx = (int)(g % nxt);
-    const typename P::T* d = D + (((int64_t)b * Hp + yy) * Wp + xx) * cin_p;
+    using T = typename P::T;
+    constexpr int VE = 16 / sizeof(T);
+    const T* d = D + (((int64_t)b * Hp + yy) * Wp + xx) * cin_p;
     Acc o0 = bh[0], o1 = bh[1];
-    for (int c = 0; c < cin_p; ++c) {
-        const Acc dv = P::val(d[c]);
-        o0 += dv * P::val(wh[c]);
-        o1 += dv * P::val(wh[cin_p + c]);
+    for (int c0 = 0; c0 < cin_p; c0 += VE) {   // 16-byte loads, channels summed in order
+        const uint4 dv = *(const uint4*)(d + c0);
+        const T* dd = (const T*)&dv;
+#pragma unroll
+        for (int k = 0; k < VE; ++k) {
+            const Acc x = P::val(dd[k]);
+            o0 += x * P::val(wh[c0 + k]);
+            o1 += x * P::val(wh[cin_p + c0 + k]);
+        }
     }
     const double s = sc[2 * b];
     z[idx] = float2{(float)(s * (double)o0), (float)(s * (double)o1)};
@@ -116,62 +123,87 @@ __global__ void k_head_dgrad(const float2* __restrict__ gz, const float* __restr
                              const double* __restrict__ sc, const typename P::T* __restrict__ D0, int cin_p,
                              const typename P::T* __restrict__ wh, int nxt, int nyt, int Hp, int Wp, int B,
                              typename P::T* __restrict__ G) {
+    // one 16-byte vector of VE channels of one padded pixel per thread
+    using T = typename P::T;
     using Acc = typename P::Acc;
+    constexpr int VE = 16 / sizeof(T);
+    const int nvec = cin_p / VE;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t np = (int64_t)Hp * Wp;
-    if (idx >= np * B * cin_p) return;
-    const int c = (int)(idx % cin_p);
-    const int64_t pp = idx / cin_p;
+    if (idx >= np * B * nvec) return;
+    const int c0 = (int)(idx % nvec) * VE;
+    const int64_t pp = idx / nvec;
     const int b = (int)(pp / np);
     const int64_t q = pp - (int64_t)b * np;
-    const int yy = (int)(q / Wp), xx = (int)(q % Wp);
-    const float2 g = head_grad(gz, coef, sc, b, yy, xx, nxt, nyt);
-    Acc v = (Acc)g.x * P::val(wh[c]) + (Acc)g.y * P::val(wh[cin_p + c]);
-    if (!(P::val(D0[idx]) > Acc(0))) v = Acc(0);
-    G[idx] = P::cvt(v);
+    const float2 g = head_grad(gz, coef, sc, b, (int)(q / Wp), (int)(q % Wp), nxt, nyt);
+    const uint4 dv = *(const uint4*)(D0 + pp * cin_p + c0);
+    const T* d = (const T*)&dv;
+    __attribute__((aligned(16))) T out[VE];
+#pragma unroll
+    for (int k = 0; k < VE; ++k) {
+        Acc v = (Acc)g.x * P::val(wh[c0 + k]) + (Acc)g.y * P::val(wh[cin_p + c0 + k]);
+        if (!(P::val(d[k]) > Acc(0))) v = Acc(0);
+        out[k] = P::cvt(v);
+    }
+    *(uint4*)(G + pp * cin_p + c0) = *(const uint4*)out;
 }
 
 // Head weight / bias gradient partials: block z covers a slice of the padded pixels of all
-// samples; part[z][k][c] = sum g_k D0[c] (c < cin_p), part[z][2][k] = sum g_k.
+// samples; part[z][k][c] = sum g_k D0[c] (c < cin_p), part[z][2][k] = sum g_k. A thread holds one
+// 16-byte vector of VE channels of a pixel; the pixel lanes are summed in a fixed order.
 template <class P>
 __global__ void k_head_wgrad(const float2* __restrict__ gz, const float* __restrict__ coef,
                              const double* __restrict__ sc, const typename P::T* __restrict__ D0, int cin_p, int nxt,
                              int nyt, int Hp, int Wp, int B, int64_t per, float* __restrict__ part) {
+    using T = typename P::T;
+    constexpr int VE = 16 / sizeof(T);
+    const int nvec = cin_p / VE;                        // vectors per pixel (divides 256)
     const int64_t np = (int64_t)Hp * Wp * B;
     const int64_t p0 = (int64_t)blockIdx.x * per, p1 = min(np, p0 + per);
-    const int lanes = TT / cin_p;                       // pixel lanes (cin_p divides 256)
-    const int c = threadIdx.x % cin_p, pl = threadIdx.x / cin_p;
-    float a0 = 0, a1 = 0, s0 = 0, s1 = 0;
+    const int lanes = TT / nvec;                        // pixel lanes
+    const int cv = threadIdx.x % nvec, pl = threadIdx.x / nvec;
+    float a0[VE], a1[VE], s0 = 0, s1 = 0;
+#pragma unroll
+    for (int k = 0; k < VE; ++k) a0[k] = a1[k] = 0;
     for (int64_t p = p0 + pl; p < p1; p += lanes) {
         const int b = (int)(p / ((int64_t)Hp * Wp));
         const int64_t q = p - (int64_t)b * Hp * Wp;
         const float2 g = head_grad(gz, coef, sc, b, (int)(q / Wp), (int)(q % Wp), nxt, nyt);
-        const float d = (float)P::val(D0[p * cin_p + c]);
-        a0 += g.x * d;
-        a1 += g.y * d;
+        const uint4 dv = *(const uint4*)(D0 + p * cin_p + cv * VE);
+        const T* d = (const T*)&dv;
+#pragma unroll
+        for (int k = 0; k < VE; ++k) {
+            const float x = (float)P::val(d[k]);
+            a0[k] += g.x * x;
+            a1[k] += g.y * x;
+        }
         s0 += g.x;
         s1 += g.y;
     }
-    __shared__ float red[TT][4];
-    red[threadIdx.x][0] = a0;
-    red[threadIdx.x][1] = a1;
-    red[threadIdx.x][2] = s0;
-    red[threadIdx.x][3] = s1;
+    __shared__ float red[TT][2 * 8 + 2];
+#pragma unroll
+    for (int k = 0; k < VE; ++k) {
+        red[threadIdx.x][k] = a0[k];
+        red[threadIdx.x][8 + k] = a1[k];
+    }
+    red[threadIdx.x][16] = s0;
+    red[threadIdx.x][17] = s1;
     __syncthreads();
     if (threadIdx.x < cin_p) {
+        const int c = threadIdx.x, v = c / VE, k = c % VE;
         float t0 = 0, t1 = 0;
         for (int l = 0; l < lanes; ++l) {
-            t0 += red[l * cin_p + threadIdx.x][0];
-            t1 += red[l * cin_p + threadIdx.x][1];
+            t0 += red[l * nvec + v][k];
+            t1 += red[l * nvec + v][8 + k];
         }
-        part[(int64_t)blockIdx.x * (2 * cin_p + 2) + threadIdx.x] = t0;
-        part[(int64_t)blockIdx.x * (2 * cin_p + 2) + cin_p + threadIdx.x] = t1;
+        part[(int64_t)blockIdx.x * (2 * cin_p + 2) + c] = t0;
+        part[(int64_t)blockIdx.x * (2 * cin_p + 2) + cin_p + c] = t1;
     }
     if (threadIdx.x == 0) {
         float t0 = 0, t1 = 0;
-        for (int l = 0; l < lanes; ++l) {   // every pixel lane saw each pixel once per channel 0
-            t0 += red[l * cin_p][2];
-            t1 += red[l * cin_p][3];
+        for (int l = 0; l < lanes; ++l) {   // the vector-0 thread of every pixel lane saw each pixel once
+            t0 += red[l * nvec][16];
+            t1 += red[l * nvec][17];
         }
         part[(int64_t)blockIdx.x * (2 * cin_p + 2) + 2 * cin_p] = t0;
         part[(int64_t)blockIdx.x * (2 * cin_p + 2) + 2 * cin_p + 1] = t1;
@@ -644,9 +676,13 @@ __global__ __launch_bounds__(TT) void k_convT2_dgrad(const typename P::T* __rest
 template <class P>
 __global__ void k_pool_bwd(typename P::T* __restrict__ skip, const typename P::T* __restrict__ dP,
                            const typename P::T* __restrict__ E, int H, int W, int c, int64_t total) {
+    // one 16-byte vector of VE channels per thread (c is a multiple of 16)
+    using T = typename P::T;
     using Acc = typename P::Acc;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= total) return;
+    constexpr int VE = 16 / sizeof(T);
+    const int64_t iv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (iv * VE >= total) return;
+    const int64_t idx = iv * VE;
     const int ch = (int)(idx % c);
     const int64_t pp = idx / c;
     const int64_t plane = (int64_t)H * W;
@@ -654,9 +690,16 @@ __global__ void k_pool_bwd(typename P::T* __restrict__ skip, const typename P::T
     const int64_t q = pp - (int64_t)b * plane;
     const int yy = (int)(q / W), xx = (int)(q % W);
     const int64_t pi = ((int64_t)b * (plane / 4) + (int64_t)(yy / 2) * (W / 2) + xx / 2) * c + ch;
-    Acc v = P::val(skip[idx]) + Acc(0.25) * P::val(dP[pi]);
-    if (!(P::val(E[idx]) > Acc(0))) v = Acc(0);
-    skip[idx] = P::cvt(v);
+    const uint4 sv = *(const uint4*)(skip + idx), pv = *(const uint4*)(dP + pi), ev = *(const uint4*)(E + idx);
+    const T *sk = (const T*)&sv, *pd = (const T*)&pv, *e = (const T*)&ev;
+    __attribute__((aligned(16))) T out[VE];
+#pragma unroll
+    for (int k = 0; k < VE; ++k) {
+        Acc v = P::val(sk[k]) + Acc(0.25) * P::val(pd[k]);
+        if (!(P::val(e[k]) > Acc(0))) v = Acc(0);
+        out[k] = P::cvt(v);
+    }
+    *(uint4*)(skip + idx) = *(const uint4*)out;
 }
 
 // ------------------------------------------------------------------ workspace
@@ -947,7 +990,7 @@ static int loss_backward_impl(const no_net* net, int B, const hz_problem* const*
     // ---- head
     {
         const int cs0 = lh.cin_p;
-        const int64_t tot = (int64_t)B * Hp * Wp * cs0;
+        const int64_t tot = (int64_t)B * Hp * Wp * (cs0 / (16 / (int)sizeof(T)));
         T* G0 = t.gB[0];
         hipLaunchKernelGGL(k_head_dgrad<P>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, t.gz, t.coef, t.sc,
                            D0, cs0, packed_w<P>(net, lh), p0->nxt, p0->nyt, Hp, Wp, B, G0);
@@ -1008,7 +1051,8 @@ static int loss_backward_impl(const no_net* net, int B, const hz_problem* const*
             const int Hu = Hp >> (l - 1), Wu = Wp >> (l - 1);
             const int c = Ls[enc_b[l - 1]].cout_p;
             const int64_t tot = (int64_t)B * Hu * Wu * c;
-            hipLaunchKernelGGL(k_pool_bwd<P>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, t.gB[l - 1],
+            const int64_t nv = tot / (16 / (int)sizeof(T));
+            hipLaunchKernelGGL(k_pool_bwd<P>, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, t.gB[l - 1],
                                (const T*)t.gP[l], (const T*)t.f.E[l - 1], Hu, Wu, c, tot);
             HZ_LAUNCH_CHECK();
         }
