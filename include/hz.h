@@ -181,7 +181,9 @@ size_t no_train_workspace_size(const no_net* net, const hz_problem* p, int batch
  * U-Net. problems: `batch` handles of one grid size; r_dev: [batch][n] complex64;
  * loss_dev: 1 float (written); per_sample_dev: `batch` floats or NULL;
  * grad_dev: no_param_count floats (overwritten with d loss / d theta).
- * prec: NO_BF16 (BF16 operands, FP32 accumulation) or NO_FP32. */
+ * prec: NO_BF16 (BF16 operands, FP32 accumulation) or NO_FP32. Asynchronous on `stream`,
+ * except that the first call at a (grid size, batch) autotunes the forward layers as
+ * no_autotune does (which synchronises the stream once). */
 int no_loss_backward(const no_net* net, int batch, const hz_problem* const* problems,
                      const void* r_dev, int squared, no_prec prec,
                      float* loss_dev, float* per_sample_dev, float* grad_dev,

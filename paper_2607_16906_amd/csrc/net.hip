@@ -245,7 +245,7 @@ ConvCfg net_cfg(const no_net* net, int layer, int H, int W, int batch, no_prec p
 // so the choice changes speed only, never a result bit; split-K (a different summation order)
 // is not a candidate, which keeps solves reproducible whatever the timings were.
 template <class P>
-static int autotune_impl(const no_net* net, int Hp, int Wp, const FwdBufs& b, hipStream_t s) {
+static int autotune_impl(const no_net* net, int Hp, int Wp, int batch, const FwdBufs& b, hipStream_t s) {
     using T = typename P::T;
     using Acc = typename P::Acc;
     no_net* mnet = const_cast<no_net*>(net);
@@ -256,7 +256,7 @@ static int autotune_impl(const no_net* net, int Hp, int Wp, const FwdBufs& b, hi
     HZ_HIP(hipEventCreate(&e1));
     int rc = HZ_OK;
     auto tune_layer = [&](int li, const T* x0, int c0, const T* x1, int c1, T* y, T* pool, int H, int W) -> int {
-        const std::array<int, 5> key{li, H, W, 1, (int)prec_of<P>()};
+        const std::array<int, 5> key{li, H, W, batch, (int)prec_of<P>()};
         {
             std::lock_guard<std::mutex> g(mnet->tune_mu);
             if (mnet->tuned.count(key)) return HZ_OK;
@@ -273,7 +273,7 @@ static int autotune_impl(const no_net* net, int Hp, int Wp, const FwdBufs& b, hi
                     ConvCfg cfg{tn, rpw, ks};
                     auto run = [&]() {
                         return launch_conv3<P>(x0, c0, x1, c1, packed_w<P>(net, ly), packed_b<P>(net, ly), y,
-                                               ly.cout_p, pool, H, W, 1, true, nullptr, s, Conv3Out(), cfg,
+                                               ly.cout_p, pool, H, W, batch, true, nullptr, s, Conv3Out(), cfg,
                                                (Acc*)b.splitbuf);
                     };
                     HZ_TRY(run());
@@ -327,21 +327,31 @@ int net_autotune(const no_net* net, const hz_problem* p, no_prec prec, void* ws,
         case NO_BF16: {
             FwdBufs b = fwd_layout<PolBF16>(net, Hp, Wp, 1, ws, ws_bytes);
             if (b.total > ws_bytes) break;
-            return autotune_impl<PolBF16>(net, Hp, Wp, b, s);
+            return autotune_impl<PolBF16>(net, Hp, Wp, 1, b, s);
         }
         case NO_FP32: {
             FwdBufs b = fwd_layout<PolF32>(net, Hp, Wp, 1, ws, ws_bytes);
             if (b.total > ws_bytes) break;
-            return autotune_impl<PolF32>(net, Hp, Wp, b, s);
+            return autotune_impl<PolF32>(net, Hp, Wp, 1, b, s);
         }
         case NO_FP64: {
             FwdBufs b = fwd_layout<PolF64>(net, Hp, Wp, 1, ws, ws_bytes);
             if (b.total > ws_bytes) break;
-            return autotune_impl<PolF64>(net, Hp, Wp, b, s);
+            return autotune_impl<PolF64>(net, Hp, Wp, 1, b, s);
         }
     }
     set_error("autotune: workspace too small or bad precision");
     return HZ_ERR_WORKSPACE;
+}
+
+int net_autotune_bufs(const no_net* net, int Hp, int Wp, int batch, const FwdBufs& b, no_prec prec, hipStream_t s) {
+    switch (prec) {
+        case NO_BF16: return autotune_impl<PolBF16>(net, Hp, Wp, batch, b, s);
+        case NO_FP32: return autotune_impl<PolF32>(net, Hp, Wp, batch, b, s);
+        case NO_FP64: return autotune_impl<PolF64>(net, Hp, Wp, batch, b, s);
+    }
+    set_error("autotune: bad precision");
+    return HZ_ERR_ARG;
 }
 
 size_t net_fwd_ws_bytes(const no_net* net, int Hp, int Wp, int batch, no_prec prec) {

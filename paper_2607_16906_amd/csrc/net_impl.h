@@ -73,6 +73,10 @@ struct FwdBufs {
     size_t total;
 };
 
+// Autotune the 3x3 layers for `batch` samples on the forward buffers b (see no_autotune); layers
+// already tuned at that size return at once. Synchronises the stream on the first call of a size.
+int net_autotune_bufs(const no_net* net, int Hp, int Wp, int batch, const FwdBufs& b, no_prec prec, hipStream_t s);
+
 constexpr int KSPLIT_MAX = 4;
 
 template <class P>

@@ -965,6 +965,8 @@ static int loss_backward_impl(const no_net* net, int B, const hz_problem* const*
     hipLaunchKernelGGL((k_pack_batched<P>), dim3(gp, B), dim3(256), 0, s, r, n, t.sc, t.sprob, p0->nxt, p0->nyt, Hp, Wp,
                        net->a.in_ch, (T*)t.f.X);
     HZ_LAUNCH_CHECK();
+    // launch variants of the 3x3 layers at this batch (tuned on the first call of a size)
+    HZ_TRY(net_autotune_bufs(net, Hp, Wp, B, t.f, prec_of<P>(), s));
     HZ_TRY(unet_body<P>(net, t.f, Hp, Wp, B, nullptr, s));
     const Layer& lh = Ls.back();
     const T* D0 = lv > 1 ? (const T*)t.f.D[0] : (const T*)t.f.E[0];
