@@ -13,7 +13,7 @@ rings standing in for the idealized skulls. Grids are small (the network is
 fully convolutional and is applied to larger grids later, Section 4.2).
 
 Usage: python -m oracle.train_weights --out FILE [--steps N] [--batch B] [--levels L]
-       [--base C] [--resume CKPT] [--ckpt CKPT]
+       [--base C] [--resume CKPT] [--ckpt CKPT] [--lr0 LR] [--restart STEP]
 """
 from __future__ import annotations
 
@@ -42,9 +42,12 @@ def sample_batch(step: int, batch: int, nint: int):
     return problems, np.stack(rs)
 
 
-def lr_at(step: int, total: int, lr0: float = 1e-3, lr_min: float = 1e-5) -> float:
-    """Cosine decay from lr0 to lr_min over the run."""
-    return lr_min + 0.5 * (lr0 - lr_min) * (1.0 + math.cos(math.pi * min(step, total) / total))
+def lr_at(step: int, total: int, lr0: float = 1e-3, lr_min: float = 1e-5, restart: int = 0) -> float:
+    """Cosine decay from lr0 to lr_min over [restart, total) (restart > 0: a warm restart of the
+    schedule for a continued run)."""
+    span = max(total - restart, 1)
+    k = min(max(step - restart, 0), span)
+    return lr_min + 0.5 * (lr0 - lr_min) * (1.0 + math.cos(math.pi * k / span))
 
 
 def save(path, theta, specs, levels, base, in_ch, step, loss_hist, m=None, v=None):
@@ -67,6 +70,8 @@ def main():
     ap.add_argument("--base", type=int, default=32)
     ap.add_argument("--in-ch", type=int, default=5)
     ap.add_argument("--save-every", type=int, default=100)
+    ap.add_argument("--lr0", type=float, default=1e-3, help="peak learning rate of the cosine schedule")
+    ap.add_argument("--restart", type=int, default=0, help="step at which the cosine schedule restarts")
     args = ap.parse_args()
 
     specs = unet.layer_specs(args.levels, args.base, args.in_ch)
@@ -85,10 +90,11 @@ def main():
         problems, rs = sample_batch(step, args.batch, args.nint)
         loss, _, g = unet.loss_and_grad(theta.astype(np.float32), specs, problems, rs, dtype=np.float32)
         theta, m, v = adam.adam_step(theta, g.astype(np.float64), m, v, step + 1,
-                                     lr=lr_at(step, args.steps), clip=1.0)
+                                     lr=lr_at(step, args.steps, args.lr0, restart=args.restart), clip=1.0)
         hist.append(loss)
         if (step + 1) % 10 == 0:
-            print(f"step {step + 1} loss {np.mean(hist[-10:]):.4f} lr {lr_at(step, args.steps):.2e} "
+            print(f"step {step + 1} loss {np.mean(hist[-10:]):.4f} "
+                  f"lr {lr_at(step, args.steps, args.lr0, restart=args.restart):.2e} "
                   f"{(time.time() - t0) / (step + 1 - start):.2f} s/step", flush=True)
         if (step + 1) % args.save_every == 0 or step + 1 == args.steps:
             save(args.out, theta, specs, args.levels, args.base, args.in_ch, step + 1, hist)
