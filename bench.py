@@ -45,22 +45,28 @@ def kernel_fingerprint():
 
 def measured_traffic(layer, variant):
     """HBM bytes per launch of the dominant layer from the committed counter summary (FETCH_SIZE +
-    WRITE_SIZE, scaled by a plain copy of known size), or None when the summary is missing, is for
-    another layer or launch variant, or the kernel sources changed since the counters were taken."""
+    WRITE_SIZE, scaled by a plain copy of known size; one record per launch variant, records
+    separated by blank lines), or None when no record matches the layer and variant or the kernel
+    sources changed since the counters were taken."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
-    kv = {}
-    for line in open(TRAFFIC_FILE):
-        if ":" in line:
+    recs, kv = [], {}
+    for line in list(open(TRAFFIC_FILE)) + [""]:
+        if not line.strip():
+            if kv:
+                recs.append(kv)
+            kv = {}
+        elif ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    try:
-        if (kv.get("source_md5") != kernel_fingerprint() or int(kv.get("layer", -1)) != layer
-                or kv.get("variant") != variant):
-            return None
-        return float(kv["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    fp = kernel_fingerprint()
+    for kv in recs:
+        try:
+            if kv.get("source_md5") == fp and int(kv.get("layer", -1)) == layer and kv.get("variant") == variant:
+                return float(kv["traffic_bytes_per_launch"])
+        except (KeyError, ValueError):
+            continue
+    return None
 
 
 def layer_flops(kind, cin, cout, H, W):
