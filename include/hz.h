@@ -172,8 +172,10 @@ int no_layer_forward(const no_net* net, int layer, no_prec prec, int batch, int 
                      const void* x0_dev, const void* x1_dev, void* y_dev, void* pool_dev,
                      void* ws_dev, size_t ws_bytes, void* stream);
 
-/* Workspace bytes for no_loss_backward with `batch` samples on problems of one size. */
-size_t no_train_workspace_size(const no_net* net, const hz_problem* p, int batch, no_prec prec);
+/* Workspace bytes for no_loss_backward with `batch` samples on problems of one size and the
+ * same `recompute` setting. */
+size_t no_train_workspace_size(const no_net* net, const hz_problem* p, int batch, no_prec prec,
+                               int recompute);
 
 /* Physics-informed loss and its gradient (eq. (10)-(12)) for a batch of residuals:
  * per sample q_b = A_b N(r_b) - r_b and l_b = ||q_b|| / ||r_b|| (squared != 0:
@@ -181,11 +183,15 @@ size_t no_train_workspace_size(const no_net* net, const hz_problem* p, int batch
  * U-Net. problems: `batch` handles of one grid size; r_dev: [batch][n] complex64;
  * loss_dev: 1 float (written); per_sample_dev: `batch` floats or NULL;
  * grad_dev: no_param_count floats (overwritten with d loss / d theta).
- * prec: NO_BF16 (BF16 operands, FP32 accumulation) or NO_FP32. Asynchronous on `stream`,
- * except that the first call at a (grid size, batch) autotunes the forward layers as
- * no_autotune does (which synchronises the stream once). */
+ * prec: NO_BF16 (BF16 operands, FP32 accumulation) or NO_FP32. recompute != 0 checkpoints
+ * activations for large grids: the forward pass keeps only each level's outputs (and pooled
+ * inputs), and the first-convolution and upsampled tensors of a level are recomputed with the
+ * same kernels just before that level's backward step, so loss and gradient are bit-identical
+ * to recompute = 0 with a smaller workspace. Asynchronous on `stream`, except that the first
+ * call at a (grid size, batch) autotunes the forward layers as no_autotune does (which
+ * synchronises the stream once). */
 int no_loss_backward(const no_net* net, int batch, const hz_problem* const* problems,
-                     const void* r_dev, int squared, no_prec prec,
+                     const void* r_dev, int squared, int recompute, no_prec prec,
                      float* loss_dev, float* per_sample_dev, float* grad_dev,
                      void* ws_dev, size_t ws_bytes, void* stream);
 

@@ -81,7 +81,7 @@ constexpr int KSPLIT_MAX = 4;
 
 template <class P>
 inline FwdBufs fwd_layout(const no_net* net, int Hp, int Wp, int batch, void* base, size_t cap,
-                          bool keep_all = false) {
+                          bool keep_all = false, bool recompute = false) {
     using T = typename P::T;
     FwdBufs b;
     Carver c(base, cap);
@@ -93,14 +93,26 @@ inline FwdBufs fwd_layout(const no_net* net, int Hp, int Wp, int batch, void* ba
     b.P.resize(lv);
     b.U.resize(lv);
     b.D.resize(lv);
+    // recompute (training with activation checkpointing): the first-convolution outputs (T1, T1d)
+    // and the upsampled tensors (U) of every level share one scratch of the largest level's size
+    // each; the backward pass recomputes them level by level
+    T* t1s = nullptr;
+    T* us = nullptr;
+    if (recompute) {
+        const size_t px0 = (size_t)batch * Hp * Wp;
+        size_t mx = 0;
+        for (int l = 0; l < lv; ++l) mx = std::max(mx, (px0 >> (2 * l)) * round16(net->a.base << l));
+        t1s = c.take<T>(mx);
+        us = c.take<T>(mx);
+    }
     for (int l = 0; l < lv; ++l) {
         const size_t px = (size_t)batch * (Hp >> l) * (Wp >> l);
         const int cs = round16(net->a.base << l);
         b.E[l] = c.take<T>(px * cs);
-        b.T1[l] = c.take<T>(px * cs);
-        b.T1d[l] = keep_all ? c.take<T>(px * cs) : b.T1[l];
+        b.T1[l] = recompute ? t1s : c.take<T>(px * cs);
+        b.T1d[l] = recompute ? t1s : (keep_all ? c.take<T>(px * cs) : b.T1[l]);
         b.P[l] = l > 0 ? c.take<T>(px * round16(net->a.base << (l - 1))) : nullptr;
-        b.U[l] = l < lv - 1 ? c.take<T>(px * cs) : nullptr;
+        b.U[l] = l < lv - 1 ? (recompute ? us : c.take<T>(px * cs)) : nullptr;
         b.D[l] = l < lv - 1 ? c.take<T>(px * cs) : nullptr;
     }
     b.part = c.take<double2>(1024);

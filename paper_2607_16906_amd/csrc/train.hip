@@ -731,14 +731,15 @@ constexpr int WCHUNKS = 64;          // pixel chunks of the scalar weight-gradie
 constexpr int WCHUNKS_MAX = 1024;    // upper bound of the matrix-core and head chunk counts
 
 template <class P>
-static TrainBufs<P> train_layout(const no_net* net, const hz_problem* p, int B, void* base, size_t cap) {
+static TrainBufs<P> train_layout(const no_net* net, const hz_problem* p, int B, void* base, size_t cap,
+                                 bool recompute) {
     using T = typename P::T;
     TrainBufs<P> t;
     int Hp, Wp;
     net_padded_dims(net, p, &Hp, &Wp);
     Carver c(base, cap);
     // forward activations: carve with the same rules as fwd_layout, then continue after them
-    t.f = fwd_layout<P>(net, Hp, Wp, B, base, cap, true);
+    t.f = fwd_layout<P>(net, Hp, Wp, B, base, cap, true, recompute);
     c.off = t.f.total;
     const int lv = net->a.levels;
     t.gA.resize(lv);
@@ -931,10 +932,12 @@ __global__ __launch_bounds__(ST_THREADS) void k_adjoint_batched(const float2* __
 
 template <class P>
 static int loss_backward_impl(const no_net* net, int B, const hz_problem* const* probs, const float2* r, int squared,
-                              float* loss, float* per_sample, float* grad, void* ws, size_t ws_bytes, hipStream_t s) {
+                              bool recompute, float* loss, float* per_sample, float* grad, void* ws, size_t ws_bytes,
+                              hipStream_t s) {
     using T = typename P::T;
+    using Acc = typename P::Acc;
     const hz_problem* p0 = probs[0];
-    TrainBufs<P> t = train_layout<P>(net, p0, B, ws, ws_bytes);
+    TrainBufs<P> t = train_layout<P>(net, p0, B, ws, ws_bytes, recompute);
     if (t.total > ws_bytes) {
         set_error("no_loss_backward: workspace too small");
         return HZ_ERR_WORKSPACE;
@@ -1027,6 +1030,16 @@ static int loss_backward_impl(const no_net* net, int B, const hz_problem* const*
         const Layer& lb = Ls[dec_b[l]];
         const Layer& la = Ls[dec_a[l]];
         const Layer& lu = Ls[up[l]];
+        if (recompute) {
+            // the level's upsampled tensor and first-convolution output, as the forward pass made them
+            const T* Dn0 = l + 1 == lv - 1 ? (const T*)t.f.E[l + 1] : (const T*)t.f.D[l + 1];
+            HZ_TRY(launch_convT2<P>(Dn0, lu.cin_p, packed_w<P>(net, lu), packed_b<P>(net, lu), (T*)t.f.U[l],
+                                    lu.cout_p, H / 2, W / 2, B, nullptr, s));
+            HZ_TRY(launch_conv3<P>((const T*)t.f.E[l], lu.cout_p, (const T*)t.f.U[l], lu.cout_p, packed_w<P>(net, la),
+                                   packed_b<P>(net, la), (T*)t.f.T1d[l], la.cout_p, nullptr, H, W, B, true, nullptr,
+                                   s, Conv3Out(), net_cfg(net, dec_a[l], H, W, B, prec_of<P>()),
+                                   (Acc*)t.f.splitbuf));
+        }
         const T* A1 = (const T*)t.f.T1d[l];
         HZ_TRY(wgrad_conv3<P>(lb, t.gB[l], A1, lb.cin_p, nullptr, 0, H, W, B, t, grad, s));
         HZ_TRY(dgrad_conv3<P>(net, lb, t.gB[l], H, W, B, t.gA[l], nullptr, A1, nullptr, s));
@@ -1043,8 +1056,12 @@ static int loss_backward_impl(const no_net* net, int B, const hz_problem* const*
         const int H = Hp >> l, W = Wp >> l;
         const Layer& lb = Ls[enc_b[l]];
         const Layer& la = Ls[enc_a[l]];
-        const T* A1 = (const T*)t.f.T1[l];
         const T* in = l == 0 ? (const T*)t.f.X : (const T*)t.f.P[l];
+        if (recompute)   // the level's first-convolution output, as the forward pass made it
+            HZ_TRY(launch_conv3<P>(in, la.cin_p, nullptr, 0, packed_w<P>(net, la), packed_b<P>(net, la),
+                                   (T*)t.f.T1[l], la.cout_p, nullptr, H, W, B, true, nullptr, s, Conv3Out(),
+                                   net_cfg(net, enc_a[l], H, W, B, prec_of<P>()), (Acc*)t.f.splitbuf));
+        const T* A1 = (const T*)t.f.T1[l];
         HZ_TRY(wgrad_conv3<P>(lb, t.gB[l], A1, lb.cin_p, nullptr, 0, H, W, B, t, grad, s));
         HZ_TRY(dgrad_conv3<P>(net, lb, t.gB[l], H, W, B, t.gA[l], nullptr, A1, nullptr, s));
         HZ_TRY(wgrad_conv3<P>(la, t.gA[l], in, la.cin_p, nullptr, 0, H, W, B, t, grad, s));
@@ -1104,17 +1121,18 @@ constexpr int ADAM_BLOCKS = 512;
 
 using namespace hz;
 
-extern "C" size_t no_train_workspace_size(const no_net* net, const hz_problem* p, int batch, no_prec prec) {
+extern "C" size_t no_train_workspace_size(const no_net* net, const hz_problem* p, int batch, no_prec prec,
+                                          int recompute) {
     clear_error();
     if (!net || !p || batch < 1) return 0;
-    if (prec == NO_BF16) return train_layout<PolBF16>(net, p, batch, nullptr, 0).total;
-    if (prec == NO_FP32) return train_layout<PolF32>(net, p, batch, nullptr, 0).total;
+    if (prec == NO_BF16) return train_layout<PolBF16>(net, p, batch, nullptr, 0, recompute != 0).total;
+    if (prec == NO_FP32) return train_layout<PolF32>(net, p, batch, nullptr, 0, recompute != 0).total;
     return 0;
 }
 
 extern "C" int no_loss_backward(const no_net* net, int batch, const hz_problem* const* problems, const void* r,
-                                int squared, no_prec prec, float* loss, float* per_sample, float* grad, void* ws,
-                                size_t ws_bytes, void* stream) {
+                                int squared, int recompute, no_prec prec, float* loss, float* per_sample, float* grad,
+                                void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     HZ_CHECK_ARG(net && problems && r && loss && grad && ws, "no_loss_backward: NULL argument");
     HZ_CHECK_ARG(batch >= 1 && batch <= 1024, "no_loss_backward: batch must be in [1, 1024]");
@@ -1127,10 +1145,10 @@ extern "C" int no_loss_backward(const no_net* net, int batch, const hz_problem* 
     }
     hipStream_t s = (hipStream_t)stream;
     if (prec == NO_BF16)
-        return loss_backward_impl<PolBF16>(net, batch, problems, (const float2*)r, squared, loss, per_sample, grad, ws,
-                                           ws_bytes, s);
-    return loss_backward_impl<PolF32>(net, batch, problems, (const float2*)r, squared, loss, per_sample, grad, ws,
-                                      ws_bytes, s);
+        return loss_backward_impl<PolBF16>(net, batch, problems, (const float2*)r, squared, recompute != 0, loss,
+                                           per_sample, grad, ws, ws_bytes, s);
+    return loss_backward_impl<PolF32>(net, batch, problems, (const float2*)r, squared, recompute != 0, loss,
+                                      per_sample, grad, ws, ws_bytes, s);
 }
 
 extern "C" size_t no_adam_workspace_size(const no_net* net) {

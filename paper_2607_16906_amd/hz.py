@@ -63,8 +63,8 @@ SIGNATURES = {
     "no_layer_info": (_I, [_P, _I, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32),
                            ct.POINTER(ct.c_int32)]),
     "no_layer_forward": (_I, [_P, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P, _SZ, _P]),
-    "no_train_workspace_size": (_SZ, [_P, _P, _I, _I]),
-    "no_loss_backward": (_I, [_P, _I, _P, _P, _I, _I, _P, _P, _P, _P, _SZ, _P]),
+    "no_train_workspace_size": (_SZ, [_P, _P, _I, _I, _I]),
+    "no_loss_backward": (_I, [_P, _I, _P, _P, _I, _I, _I, _P, _P, _P, _P, _SZ, _P]),
     "no_adam_workspace_size": (_SZ, [_P]),
     "no_adam_step": (_I, [_P, _P, _P, _P, _P, _I, _F, _F, _F, _F, _F, _P, _SZ, _P]),
     "fgmres_workspace_size": (_SZ, [_P, _P, ct.POINTER(HzOpts)]),
@@ -262,10 +262,12 @@ def param_count(levels: int, base: int, in_ch: int) -> int:
     return int(n)
 
 
-def loss_backward(net: Net, problems, r, *, squared: bool = False, prec: str = "bf16", workspace=None):
+def loss_backward(net: Net, problems, r, *, squared: bool = False, prec: str = "bf16", workspace=None,
+                  recompute: bool = False):
     """Physics-informed loss and its parameter gradient (no_loss_backward).
 
     problems: list of B Problems of one grid size; r: [B, n] complex64 device tensor.
+    recompute: checkpoint activations (smaller workspace, bit-identical results).
     Returns (loss [1] float32, per-sample losses [B] float32, grad [nparam] float32).
     """
     torch = _torch()
@@ -275,18 +277,21 @@ def loss_backward(net: Net, problems, r, *, squared: bool = False, prec: str = "
     if r.numel() != B * problems[0].n:
         raise ValueError("r must hold batch x n entries")
     ptrs = (ct.c_void_p * B)(*[p.handle for p in problems])
-    nb = lib.no_train_workspace_size(net.handle, problems[0].handle, B, PREC[prec])
+    nb = lib.no_train_workspace_size(net.handle, problems[0].handle, B, PREC[prec], int(recompute))
     ws = workspace if workspace is not None and workspace.numel() >= nb else _ws(nb)
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
     per = torch.empty(B, dtype=torch.float32, device="cuda")
     grad = torch.empty(net.nparam, dtype=torch.float32, device="cuda")
-    _check(lib.no_loss_backward(net.handle, B, ptrs, _ptr(r), int(squared), PREC[prec], _ptr(loss), _ptr(per),
-                                _ptr(grad), _ptr(ws), ct.c_size_t(ws.numel()), _stream()), "no_loss_backward")
+    _check(lib.no_loss_backward(net.handle, B, ptrs, _ptr(r), int(squared), int(recompute), PREC[prec],
+                                _ptr(loss), _ptr(per), _ptr(grad), _ptr(ws), ct.c_size_t(ws.numel()), _stream()),
+           "no_loss_backward")
     return loss, per, grad
 
 
-def train_workspace_bytes(net: Net, problem: Problem, batch: int, prec: str = "bf16") -> int:
-    return int(load_library().no_train_workspace_size(net.handle, problem.handle, batch, PREC[prec]))
+def train_workspace_bytes(net: Net, problem: Problem, batch: int, prec: str = "bf16",
+                          recompute: bool = False) -> int:
+    return int(load_library().no_train_workspace_size(net.handle, problem.handle, batch, PREC[prec],
+                                                      int(recompute)))
 
 
 def adam_step(net: Net, theta, m, v, grad, step: int, *, lr: float = 1e-3, beta1: float = 0.9,
@@ -306,23 +311,23 @@ def _loss_function():
         """loss = mean_b ||A_b N_theta(r_b) - r_b|| / ||r_b|| with the library's hand-written reverse mode."""
 
         @staticmethod
-        def forward(ctx, theta, net, problems, r, squared, prec):
+        def forward(ctx, theta, net, problems, r, squared, prec, recompute):
             net.set_weights(theta.detach())
-            loss, _, grad = loss_backward(net, problems, r, squared=squared, prec=prec)
+            loss, _, grad = loss_backward(net, problems, r, squared=squared, prec=prec, recompute=recompute)
             ctx.save_for_backward(grad)
             return loss[0]
 
         @staticmethod
         def backward(ctx, gout):
             (grad,) = ctx.saved_tensors
-            return gout * grad, None, None, None, None, None
+            return gout * grad, None, None, None, None, None, None
 
     return NoLoss
 
 
-def physics_loss(theta, net: Net, problems, r, squared: bool = False, prec: str = "bf16"):
+def physics_loss(theta, net: Net, problems, r, squared: bool = False, prec: str = "bf16", recompute: bool = False):
     """Differentiable (w.r.t. theta) physics-informed loss, through torch.autograd."""
-    return _loss_function().apply(theta, net, problems, r, squared, prec)
+    return _loss_function().apply(theta, net, problems, r, squared, prec, recompute)
 
 
 @dataclass

@@ -131,3 +131,27 @@ def test_training_batch_full_grid_sampled():
     rl, rp, rg = unet.loss_and_grad(theta.astype(np.float64), specs, ops, rs.astype(np.complex64).astype(np.complex128))
     assert abs(to_np(loss)[0] - rl) <= 1e-5 * rl
     assert np.linalg.norm(to_np(g) - rg) / np.linalg.norm(rg) <= 1e-4
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp32"])
+def test_recompute_bit_identical(prec):
+    # activation checkpointing: the same loss and gradient bits as keeping every activation,
+    # with a smaller workspace (4 levels, 32 channels, a ragged 44 x 44 padded grid, batch 3)
+    from paper_2607_16906_amd import hz
+    ops, gps, rs = batch(30, 6, 3, seed=4)
+    specs = unet.layer_specs(4, 32, 5)
+    theta = he_uniform(unet.init_shapes(specs), rng_for(14, 2, 4))
+    net = hz.Net(4, 32, 5, theta)
+    r = to_dev(rs.astype(np.complex64), torch.complex64)
+    full = hz.train_workspace_bytes(net, gps[0], 3, prec)
+    ckpt = hz.train_workspace_bytes(net, gps[0], 3, prec, recompute=True)
+    print(f"{prec} workspace {full} -> {ckpt} bytes")
+    assert ckpt < full
+    a = hz.loss_backward(net, gps, r, prec=prec)
+    b = hz.loss_backward(net, gps, r, prec=prec, recompute=True)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    if prec == "fp32":
+        rl, _, rg = unet.loss_and_grad(theta.astype(np.float64), specs, ops, rs.astype(np.complex64).astype(np.complex128))
+        assert abs(to_np(b[0])[0] - rl) <= 1e-5 * rl
+        assert np.linalg.norm(to_np(b[2]) - rg) / np.linalg.norm(rg) <= 5e-4
