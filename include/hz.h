@@ -151,6 +151,15 @@ int no_layer_variant(const no_net* net, int layer, no_prec prec, int batch, int 
  * Thread-safe. */
 int no_set_layer_variant(const no_net* net, int layer, no_prec prec, int batch, int H, int W, int tn, int rows);
 
+/* Choose how no_precond_apply and fgmres_solve run a decoder level with BF16 activations
+ * whose coarser tensor has at most 128 channels: the fused form computes the 2x2 stride-2
+ * transposed convolution (the decoder's upsampling, Section 3.1) inside the blocks of the
+ * level's first 3x3 convolution instead of storing it. mode 0: never; 1: always where it
+ * applies; 2 (the default): where no_autotune measured it faster than the two separate layers
+ * (untuned sizes run them separately). Every choice gives the same result bits. Not
+ * thread-safe against concurrent solves on the handle. Errors: NULL network, mode not 0-2. */
+int no_set_fused_upsampling(no_net* net, int mode);
+
 /* Shape of layer `layer` (0-based, in the order of the flat parameter vector):
  * kind 0 = 3x3 convolution + ReLU, 1 = 2x2 stride-2 transposed convolution, 2 = 1x1 head;
  * cin_p / cout_p = input / output channels as stored (zero-padded to a multiple of 16, the

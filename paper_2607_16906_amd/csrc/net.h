@@ -45,6 +45,7 @@ struct no_net {
     // autotuned launch variants of the 3x3 layers, keyed by (layer, H, W, batch, precision)
     std::map<std::array<int, 5>, hz::ConvCfg> tuned;
     std::mutex tune_mu;
+    int fuse_up = 2;   // fused decoder convolution: 0 never, 1 where it applies, 2 where autotuned faster
 };
 
 namespace hz {
@@ -64,5 +65,7 @@ int net_precond(const no_net* net, const hz_problem* p, no_prec prec, bool c128,
 // workspace and remember the fastest; returns HZ_OK at once when already tuned. Synchronises.
 int net_autotune(const no_net* net, const hz_problem* p, no_prec prec, void* ws, size_t ws_bytes, hipStream_t s);
 hz::ConvCfg net_cfg(const no_net* net, int layer, int H, int W, int batch, no_prec prec);
+// launch variant of the fused form (transposed convolution inside) of decoder 3x3 layer `layer`
+hz::ConvCfg net_cfg_up(const no_net* net, int layer, int H, int W, int batch, no_prec prec);
 
 }  // namespace hz

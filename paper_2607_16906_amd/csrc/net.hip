@@ -187,6 +187,7 @@ static int precond_impl(const no_net* net, const hz_problem* p, bool c128, const
         set_error("no_precond_apply: workspace too small");
         return HZ_ERR_WORKSPACE;
     }
+    b.fuse_up = net->fuse_up;
     const int64_t n = p->n;
     Split sp = krylov_split(n);
     // s = ||v|| / sqrt(n); a unit-norm Krylov vector has s = 1 / sqrt(n) without a reduction
@@ -240,6 +241,20 @@ ConvCfg net_cfg(const no_net* net, int layer, int H, int W, int batch, no_prec p
     return it == mnet->tuned.end() ? ConvCfg() : it->second;
 }
 
+constexpr int FUSED_KEY = 16;   // offset of the precision field in the keys of fused-form variants
+
+ConvCfg net_cfg_up(const no_net* net, int layer, int H, int W, int batch, no_prec prec) {
+    return net_cfg(net, layer, H, W, batch, (no_prec)((int)prec + FUSED_KEY));
+}
+
+// Holds the stream for `ticks` of the constant-rate wall clock (always returns), so that the
+// launches queued behind it meanwhile run back to back: the autotuner then times the GPU, not the
+// host's launch rate.
+__global__ void k_hold(int64_t ticks) {
+    const int64_t t0 = wall_clock64();
+    while (wall_clock64() - t0 < ticks) __builtin_amdgcn_s_sleep(8);
+}
+
 // Time the variants of every 3x3 layer on the forward buffers and keep the fastest. The
 // candidates (channel tile, rows per wavefront) all accumulate every output in the same order,
 // so the choice changes speed only, never a result bit; split-K (a different summation order)
@@ -255,11 +270,23 @@ static int autotune_impl(const no_net* net, int Hp, int Wp, int batch, const Fwd
     HZ_HIP(hipEventCreate(&e0));
     HZ_HIP(hipEventCreate(&e1));
     int rc = HZ_OK;
-    auto tune_layer = [&](int li, const T* x0, int c0, const T* x1, int c1, T* y, T* pool, int H, int W) -> int {
-        const std::array<int, 5> key{li, H, W, batch, (int)prec_of<P>()};
+    // 0.5 ms hold before each timed batch (the wall clock rate is reported in kHz)
+    int dev = 0, wrate = 0;
+    HZ_HIP(hipGetDevice(&dev));
+    if (hipDeviceGetAttribute(&wrate, hipDeviceAttributeWallClockRate, dev) != hipSuccess || wrate <= 0) wrate = 100000;
+    const int64_t hold_ticks = (int64_t)wrate / 2;
+    auto hold = [&]() {
+        hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, s, hold_ticks);
+        return hipGetLastError() == hipSuccess ? HZ_OK : HZ_ERR_HIP;
+    };
+    // up (fused form): x1 is unused and U = convT2(up) is computed inside the layer
+    // best_out (optional): average time of the chosen variant, ms per launch
+    auto tune_layer = [&](int li, const T* x0, int c0, const T* x1, int c1, T* y, T* pool, int H, int W,
+                          const UpIn* up = nullptr, float* best_out = nullptr) -> int {
+        const std::array<int, 5> key{li, H, W, batch, (int)prec_of<P>() + (up ? FUSED_KEY : 0)};
         {
             std::lock_guard<std::mutex> g(mnet->tune_mu);
-            if (mnet->tuned.count(key)) return HZ_OK;
+            if (mnet->tuned.count(key) && !best_out) return HZ_OK;
         }
         const Layer& ly = Ls[li];
         ConvCfg best;
@@ -272,11 +299,15 @@ static int autotune_impl(const no_net* net, int Hp, int Wp, int batch, const Fwd
                     if (ks > 1 && (ks > chunks || (size_t)ks * H * W * ly.cout_p > b.split_elems)) continue;
                     ConvCfg cfg{tn, rpw, ks};
                     auto run = [&]() {
+                        if (up)
+                            return launch_conv3_up<P>(x0, c0, *up, c1, packed_w<P>(net, ly), packed_b<P>(net, ly),
+                                                      y, ly.cout_p, H, W, batch, nullptr, s, cfg);
                         return launch_conv3<P>(x0, c0, x1, c1, packed_w<P>(net, ly), packed_b<P>(net, ly), y,
                                                ly.cout_p, pool, H, W, batch, true, nullptr, s, Conv3Out(), cfg,
                                                (Acc*)b.splitbuf);
                     };
                     HZ_TRY(run());
+                    HZ_TRY(hold());
                     HZ_HIP(hipEventRecord(e0, s));
                     for (int r = 0; r < 10; ++r) HZ_TRY(run());
                     HZ_HIP(hipEventRecord(e1, s));
@@ -292,8 +323,26 @@ static int autotune_impl(const no_net* net, int Hp, int Wp, int batch, const Fwd
                 }
             }
         }
+        if (best_out) *best_out = best_ms / 10;
         std::lock_guard<std::mutex> g(mnet->tune_mu);
-        mnet->tuned[key] = best;
+        if (!mnet->tuned.count(key)) mnet->tuned[key] = best;
+        return HZ_OK;
+    };
+    // average time of the stand-alone transposed convolution, ms per launch
+    auto time_convT2 = [&](const Layer& lu, const T* x, T* y, int H, int W, float* ms_out) -> int {
+        auto run = [&]() {
+            return launch_convT2<P>(x, lu.cin_p, packed_w<P>(net, lu), packed_b<P>(net, lu), y, lu.cout_p, H, W,
+                                    batch, nullptr, s);
+        };
+        HZ_TRY(run());
+        HZ_TRY(hold());
+        HZ_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < 10; ++r) HZ_TRY(run());
+        HZ_HIP(hipEventRecord(e1, s));
+        HZ_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        HZ_HIP(hipEventElapsedTime(&ms, e0, e1));
+        *ms_out = ms / 10;
         return HZ_OK;
     };
     int li = 0;
@@ -309,8 +358,36 @@ static int autotune_impl(const no_net* net, int Hp, int Wp, int batch, const Fwd
     }
     for (int l = lv - 2; l >= 0 && rc == HZ_OK; --l) {
         const int H = Hp >> l, W = Wp >> l;
-        const int ce = Ls[li].cout_p;
-        rc = tune_layer(li + 1, (const T*)b.E[l], ce, (const T*)b.U[l], ce, (T*)b.T1d[l], nullptr, H, W);
+        const Layer& lu = Ls[li];
+        const int ce = lu.cout_p;
+        const std::array<int, 5> ukey{li + 1, H, W, batch, (int)prec_of<P>() + FUSED_KEY};
+        bool have_u;
+        {
+            std::lock_guard<std::mutex> g(mnet->tune_mu);
+            have_u = mnet->tuned.count(ukey) > 0;
+        }
+        if (b.fuse_up && conv3_up_ok<P>(ce, ce, lu.cin_p, H, W) && !have_u) {
+            // the fused form against the two separate layers (the same result bits): keep the
+            // faster, by a clear margin for the fused form
+            const T* dn = (const T*)(l + 1 == lv - 1 ? b.E[l + 1] : b.D[l + 1]);
+            UpIn up;
+            up.d = dn;
+            up.cd = lu.cin_p;
+            up.wt = packed_w<P>(net, lu);
+            up.bt = packed_b<P>(net, lu);
+            float t_fused = 0, t_conv = 0, t_up = 0;
+            rc = tune_layer(li + 1, (const T*)b.E[l], ce, nullptr, ce, (T*)b.T1d[l], nullptr, H, W, &up, &t_fused);
+            if (rc == HZ_OK)
+                rc = tune_layer(li + 1, (const T*)b.E[l], ce, (const T*)b.U[l], ce, (T*)b.T1d[l], nullptr, H, W,
+                                nullptr, &t_conv);
+            if (rc == HZ_OK) rc = time_convT2(lu, dn, (T*)b.U[l], H / 2, W / 2, &t_up);
+            if (rc == HZ_OK) {
+                std::lock_guard<std::mutex> g(mnet->tune_mu);
+                mnet->tuned[ukey].fuse = t_fused < 0.97f * (t_conv + t_up) ? 1 : 0;
+            }
+        } else {
+            rc = tune_layer(li + 1, (const T*)b.E[l], ce, (const T*)b.U[l], ce, (T*)b.T1d[l], nullptr, H, W);
+        }
         if (rc == HZ_OK)
             rc = tune_layer(li + 2, (const T*)b.T1d[l], Ls[li + 2].cin_p, nullptr, 0, (T*)b.D[l], nullptr, H, W);
         li += 3;
@@ -327,16 +404,19 @@ int net_autotune(const no_net* net, const hz_problem* p, no_prec prec, void* ws,
         case NO_BF16: {
             FwdBufs b = fwd_layout<PolBF16>(net, Hp, Wp, 1, ws, ws_bytes);
             if (b.total > ws_bytes) break;
+            b.fuse_up = net->fuse_up;
             return autotune_impl<PolBF16>(net, Hp, Wp, 1, b, s);
         }
         case NO_FP32: {
             FwdBufs b = fwd_layout<PolF32>(net, Hp, Wp, 1, ws, ws_bytes);
             if (b.total > ws_bytes) break;
+            b.fuse_up = net->fuse_up;
             return autotune_impl<PolF32>(net, Hp, Wp, 1, b, s);
         }
         case NO_FP64: {
             FwdBufs b = fwd_layout<PolF64>(net, Hp, Wp, 1, ws, ws_bytes);
             if (b.total > ws_bytes) break;
+            b.fuse_up = net->fuse_up;
             return autotune_impl<PolF64>(net, Hp, Wp, 1, b, s);
         }
     }
@@ -530,6 +610,14 @@ extern "C" int no_set_layer_variant(const no_net* net, int layer, no_prec prec, 
     no_net* mnet = const_cast<no_net*>(net);
     std::lock_guard<std::mutex> g(mnet->tune_mu);
     mnet->tuned[{layer, H, W, batch, (int)prec}] = ConvCfg{tn, rows / 4, 1};
+    return HZ_OK;
+}
+
+extern "C" int no_set_fused_upsampling(no_net* net, int mode) {
+    clear_error();
+    HZ_CHECK_ARG(net, "no_set_fused_upsampling: NULL network");
+    HZ_CHECK_ARG(mode >= 0 && mode <= 2, "no_set_fused_upsampling: mode must be 0, 1 or 2");
+    net->fuse_up = mode;
     return HZ_OK;
 }
 

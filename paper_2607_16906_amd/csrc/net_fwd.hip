@@ -1,6 +1,8 @@
 // U-Net layer kernels on the matrix cores (forward): 3x3 convolution as implicit
 // GEMM with fused bias / ReLU / 2x2 average pool, and the 2x2 stride-2 transposed
 // convolution. Templated over the arithmetic policy (BF16, FP32, FP64).
+#include <type_traits>
+
 #include "net_kernels.h"
 
 namespace hz {
@@ -25,7 +27,14 @@ constexpr int pix_stride() { return P::CK + 16 / (int)sizeof(typename P::T); }  
 // tile. The next chunk's patch and weights are loaded into registers while the matrix cores work
 // on the current chunk (register double buffering). With splitp set, the raw accumulators are
 // written to splitp[[bz][pixel][channel]] (no bias or activation) for a later split-K reduction.
-template <class P, int TN, bool POOL, int RPW>
+//
+// UPCD > 0 (fused upsampling, see UpIn): the channels from c0 on are U, computed per chunk from the
+// coarse patch d[ty0/2 - 1 .. ty0/2 + 2 RPW][tx0/2 - 1 .. tx0/2 + 8] (staged once in LDS, all
+// up.cd <= UPCD channels): wavefront a' computes parity a' = 2a + b of the chunk's channels for
+// every coarse pixel of the patch, with the same MFMA steps (input channels in groups of 4 GW, in
+// order) as the stand-alone transposed convolution, adds the bias, rounds to the activation type
+// and writes the values that land in the (4 RPW + 2) x 18 patch (zero outside the image).
+template <class P, int TN, bool POOL, int RPW, int UPCD = 0>
 __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0, int c0,
                                            const typename P::T* __restrict__ x1, int c1,
                                            const typename P::T* __restrict__ w,
@@ -33,7 +42,7 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
                                            typename P::T* __restrict__ y, int cout_p,
                                            typename P::T* __restrict__ ypool, int H, int W, int relu, int ck,
                                            const Conv3Out& ex, int bz, int co0, int ty0, int tx0, int kbeg, int kend,
-                                           typename P::Acc* __restrict__ splitp) {
+                                           typename P::Acc* __restrict__ splitp, UpIn up = UpIn()) {
     using T = typename P::T;
     using Acc = typename P::Acc;
     using AccV = typename P::AccV;
@@ -47,6 +56,17 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
     constexpr int NPW = (9 * TN * VPP_MAX + CT - 1) / CT;                 // weight vectors per thread
     __shared__ __attribute__((aligned(16))) T patch[(TH_ + 2) * (TW + 2) * PS];
     __shared__ __attribute__((aligned(16))) T wl[9 * TN * PS];
+    // fused upsampling: coarse patch geometry, LDS and per-lane fragments
+    constexpr int DR = TH_ / 2 + 2, DC = TW / 2 + 2, NDP = DR * DC;   // coarse patch pixels
+    constexpr int NDB = (NDP + 15) / 16;                               // their 16-pixel MFMA blocks
+    constexpr int PSD = (UPCD > 0 ? UPCD : 0) + VE;                    // coarse pixel stride
+    constexpr int NDV = UPCD > 0 ? (NDP * (UPCD / VE) + CT - 1) / CT : 1;
+    constexpr int UMB = P::CK >= 16 ? P::CK / 16 : 1;                  // 16-channel blocks per chunk
+    constexpr int UKS = UPCD > 0 ? UPCD / (4 * P::GW) : 1;             // MFMA steps over up.cd (max)
+    __shared__ __attribute__((aligned(16))) T dpatch[UPCD > 0 ? NDB * 16 * PSD : 1];
+    typename P::Frag rwt[UMB * UKS];
+    typename P::Acc rbt[UMB][4];   // the chunk's transposed-convolution bias, per accumulator row
+    uint4 rd[NDV];
 
     const int cin_p = c0 + c1;
     const int64_t plane = (int64_t)H * W;
@@ -69,19 +89,41 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
     const int steps = (groups + 3) / 4;
     const int npa = (TH_ + 2) * (TW + 2) * vpp, npw = 9 * TN * vpp;
     uint4 ra[NPA], rw[NPW];
+    const int ukn = UPCD > 0 ? up.cd / (4 * P::GW) : 0;   // MFMA steps of the transposed convolution
     auto gload = [&](int k0) {
+        const bool uchunk = UPCD > 0 && k0 >= c0;
+        if constexpr (UPCD > 0) {
+            if (uchunk) {
+                // a U chunk: this wavefront's fragments of the transposed weights (parity wv,
+                // channels k0 - c0 + 16 mb + lane % 16, input channels 4 GW ks + GW (lane / 16) ...)
+                // and the bias of its accumulator rows
+                const T* wt = (const T*)up.wt;
+#pragma unroll
+                for (int mb = 0; mb < UMB; ++mb)
+#pragma unroll
+                    for (int ks = 0; ks < UKS; ++ks)
+                        if (ks < ukn)
+                            rwt[mb * UKS + ks] = P::load(wt + ((int64_t)wv * c1 + (k0 - c0) + mb * 16 + lr) * up.cd +
+                                                         ks * 4 * P::GW + lg * P::GW);
+#pragma unroll
+                for (int mb = 0; mb < UMB; ++mb)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) rbt[mb][r] = ((const Acc*)up.bt)[k0 - c0 + mb * 16 + P::row_of(lg, r)];
+            }
+        }
 #pragma unroll
         for (int i = 0; i < NPA; ++i) {
             const int v = threadIdx.x + i * CT;
             uint4 val = uint4{0, 0, 0, 0};
-            if (v < npa) {
+            if (v < npa && !uchunk) {
                 const int px = v / vpp, part = v - px * vpp;
                 const int py = px / (TW + 2), pxx = px - py * (TW + 2);
                 const int gy = ty0 + py - 1, gx = tx0 + pxx - 1;
                 if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
                     const int c = k0 + part * VE;
                     const int64_t pix = (int64_t)gy * W + gx;
-                    const T* src = (c < c0) ? xs0 + pix * c0 + c : xs1 + pix * c1 + (c - c0);
+                    // (the fused form stages only the first part from memory)
+                    const T* src = (UPCD > 0 || c < c0) ? xs0 + pix * c0 + c : xs1 + pix * c1 + (c - c0);
                     val = *(const uint4*)src;
                 }
             }
@@ -99,11 +141,11 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
             rw[i] = val;
         }
     };
-    auto lstore = [&]() {
+    auto lstore = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < NPA; ++i) {
             const int v = threadIdx.x + i * CT;
-            if (v < npa) {
+            if (v < npa && !(UPCD > 0 && k0 >= c0)) {
                 const int px = v / vpp, part = v - px * vpp;
                 *(uint4*)&patch[px * PS + part * VE] = ra[i];
             }
@@ -117,11 +159,81 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
             }
         }
     };
+    const int hd = H / 2, wd = W / 2, dr0 = ty0 / 2 - 1, dc0 = tx0 / 2 - 1;
+    if constexpr (UPCD > 0) {
+        // the coarse patch, every channel (zero outside the coarse grid)
+        const int vpd = up.cd / VE;
+        const T* ds = (const T*)up.d + (int64_t)bz * hd * wd * up.cd;
+#pragma unroll
+        for (int i = 0; i < NDV; ++i) {
+            const int v = threadIdx.x + i * CT;
+            uint4 val = uint4{0, 0, 0, 0};
+            if (v < NDP * vpd) {
+                const int px = v / vpd, part = v - px * vpd;
+                const int gy = dr0 + px / DC, gx = dc0 + px % DC;
+                if (gy >= 0 && gy < hd && gx >= 0 && gx < wd)
+                    val = *(const uint4*)(ds + ((int64_t)gy * wd + gx) * up.cd + part * VE);
+            }
+            rd[i] = val;
+        }
+    }
     gload(kbeg);
     for (int k0 = kbeg; k0 < kend; k0 += ck) {
         __syncthreads();
-        lstore();
+        lstore(k0);
+        if constexpr (UPCD > 0) {
+            if (k0 == kbeg) {
+                const int vpd = up.cd / VE;
+#pragma unroll
+                for (int i = 0; i < NDV; ++i) {
+                    const int v = threadIdx.x + i * CT;
+                    if (v < NDP * vpd) {
+                        const int px = v / vpd, part = v - px * vpd;
+                        *(uint4*)&dpatch[px * PSD + part * VE] = rd[i];
+                    }
+                }
+            }
+        }
         __syncthreads();
+        if constexpr (UPCD > 0) {
+            if (k0 >= c0) {
+                // U chunk: wavefront wv computes parity (a, b) = (wv / 2, wv % 2) of channels
+                // k0 - c0 .. + CK for every coarse pixel, then writes them into the patch
+                const int pa = wv >> 1, pb2 = wv & 1;
+                // one block of 16 coarse pixels at a time (few live accumulators)
+#pragma unroll 1
+                for (int nb = 0; nb < NDB; ++nb) {
+                    AccV au[UMB];
+#pragma unroll
+                    for (int mb = 0; mb < UMB; ++mb)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) au[mb][r] = 0;
+#pragma unroll
+                    for (int ks = 0; ks < UKS; ++ks) {
+                        if (ks < ukn) {
+                            const Frag bf = P::load(&dpatch[(nb * 16 + lr) * PSD + ks * 4 * P::GW + lg * P::GW]);
+#pragma unroll
+                            for (int mb = 0; mb < UMB; ++mb) au[mb] = P::mma(rwt[mb * UKS + ks], bf, au[mb]);
+                        }
+                    }
+                    const int n = nb * 16 + lr;
+                    const int py = 2 * (n / DC) + pa - 1, pxx = 2 * (n % DC) + pb2 - 1;
+                    if (n < NDP && py >= 0 && py < TH_ + 2 && pxx >= 0 && pxx < TW + 2) {
+                        const int gy = ty0 - 1 + py, gx = tx0 - 1 + pxx;
+                        const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+#pragma unroll
+                        for (int mb = 0; mb < UMB; ++mb) {
+                            Acc t[4];
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                t[r] = in ? au[mb][r] + rbt[mb][r] : Acc(0);
+                            store_rows<P>(&patch[(py * (TW + 2) + pxx) * PS + mb * 16 + P::row_of(lg, 0)], t);
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
         if (k0 + ck < kend) gload(k0 + ck);
         if (ck == P::CK) {
             // full chunk: step st covers tap st / SPT and k-groups 4 (st mod SPT) + lg of it, all
@@ -348,6 +460,28 @@ __global__ __launch_bounds__(CT) void k_conv3(const typename P::T* __restrict__ 
     const int kb = (nch * zs / nsplit) * ck, ke = (nch * (zs + 1) / nsplit) * ck;
     conv3_tile<P, TN, POOL, RPW>(x0, c0, x1, c1, w, bias, y, cout_p, ypool, H, W, relu, ck, ex, bz, co0,
                                  tyi * 4 * RPW, txi * TW, kb, ke, splitp ? splitp + zs * sstride : nullptr);
+}
+
+// Decoder 3x3 convolution with the transposed convolution of the coarser level fused in (UpIn).
+// grid: x = column tiles, y = row tiles, z = (sample, channel block)
+template <class P, int TN, int RPW, int UPCD>
+__global__ __launch_bounds__(CT) void k_conv3_up(const typename P::T* __restrict__ x0, int c0, UpIn up, int c1,
+                                                 const typename P::T* __restrict__ w,
+                                                 const typename P::Acc* __restrict__ bias,
+                                                 typename P::T* __restrict__ y, int cout_p, int H, int W,
+                                                 const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const int ncb_tot = cout_p / TN;
+    const int nblk = gridDim.x * gridDim.y * gridDim.z;
+    int v = xcd_linear(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nblk);
+    const int cbi = v % ncb_tot;
+    v /= ncb_tot;
+    const int txi = v % gridDim.x;
+    v /= gridDim.x;
+    const int tyi = v % gridDim.y;
+    const int bz = v / gridDim.y;
+    conv3_tile<P, TN, false, RPW, UPCD>(x0, c0, nullptr, c1, w, bias, y, cout_p, nullptr, H, W, 1, P::CK, Conv3Out(),
+                                        bz, cbi * TN, tyi * 4 * RPW, txi * TW, 0, c0 + c1, nullptr, up);
 }
 
 // Ragged batch: block b runs job jobs[b] = (system, tile, channel block) with the system's tensors.
@@ -633,6 +767,58 @@ int launch_conv3(const typename P::T* x0, int c0, const typename P::T* x1, int c
 }
 
 template <class P>
+bool conv3_up_ok(int c0, int c1, int cd, int H, int W) {
+    if constexpr (!std::is_same<P, PolBF16>::value) {
+        return false;
+    } else {
+        return c0 > 0 && c1 > 0 && c0 % P::CK == 0 && c1 % P::CK == 0 && cd > 0 && cd <= UP_CDMAX &&
+               cd % (4 * P::GW) == 0 && H % 2 == 0 && W % 2 == 0;
+    }
+}
+
+template <class P>
+int launch_conv3_up(const typename P::T* x0, int c0, UpIn up, int c1, const typename P::T* w,
+                    const typename P::Acc* bias, typename P::T* y, int cout_p, int H, int W, int batch,
+                    const int* skip, hipStream_t s, ConvCfg cfg) {
+    if (!conv3_up_ok<P>(c0, c1, up.cd, H, W) || cout_p % 16 || !up.d || !up.wt || !up.bt) {
+        set_error("conv3_up: unsupported channel / size combination");
+        return HZ_ERR_ARG;
+    }
+    if constexpr (std::is_same<P, PolBF16>::value) {
+        const int rpw = cfg.rpw == 4 ? 4 : 2;
+        const int th = 4 * rpw;
+        int tn = cfg.tn;
+        if (tn != 16 && tn != 32 && tn != 64) {
+            tn = pick_tn(cout_p);
+            const int64_t tiles = (int64_t)((W + TW - 1) / TW) * ((H + th - 1) / th) * batch;
+            while (tn > 16 && tiles * (cout_p / tn) < 512) tn /= 2;
+        }
+        while (cout_p % tn) tn /= 2;
+        dim3 grid((W + TW - 1) / TW, (H + th - 1) / th, (cout_p / tn) * batch);
+        // LDS and fragment registers sized for the coarse channel count (64 or 128)
+#define HZ_CU(TNV, R)                                                                                             \
+    if (up.cd <= 64)                                                                                             \
+        hipLaunchKernelGGL((k_conv3_up<P, TNV, R, 64>), grid, dim3(CT), 0, s, x0, c0, up, c1, w, bias, y, cout_p, \
+                           H, W, skip);                                                                          \
+    else                                                                                                         \
+        hipLaunchKernelGGL((k_conv3_up<P, TNV, R, UP_CDMAX>), grid, dim3(CT), 0, s, x0, c0, up, c1, w, bias, y,    \
+                           cout_p, H, W, skip)
+        if (rpw == 4) {
+            if (tn == 64) HZ_CU(64, 4);
+            else if (tn == 32) HZ_CU(32, 4);
+            else HZ_CU(16, 4);
+        } else {
+            if (tn == 64) HZ_CU(64, 2);
+            else if (tn == 32) HZ_CU(32, 2);
+            else HZ_CU(16, 2);
+        }
+#undef HZ_CU
+        HZ_LAUNCH_CHECK();
+    }
+    return HZ_OK;
+}
+
+template <class P>
 int launch_convT2(const typename P::T* x, int cin_p, const typename P::T* w, const typename P::Acc* bias,
                   typename P::T* y, int cout_p, int H, int W, int batch, const int* skip, hipStream_t s) {
     const int ck = convT2_stage<P>(cin_p);
@@ -703,7 +889,10 @@ int launch_convT2_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const 
                                       int, int, bool, hipStream_t);                                            \
     template int launch_convT2_jobs<P>(const TileJob*, int, const LayerIO*, const P::T*, const P::Acc*, int, int, \
                                        int, hipStream_t);                                                      \
-    template int conv_chunk<P>(int, int, int);
+    template int conv_chunk<P>(int, int, int);                                                                 \
+    template bool conv3_up_ok<P>(int, int, int, int, int);                                                     \
+    template int launch_conv3_up<P>(const P::T*, int, UpIn, int, const P::T*, const P::Acc*, P::T*, int, int, int, \
+                                    int, const int*, hipStream_t, ConvCfg);
 HZ_INST(PolBF16)
 HZ_INST(PolF32)
 HZ_INST(PolF64)

@@ -71,13 +71,15 @@ struct FwdBufs {
     void* splitbuf;      // split-K partial sums (accumulator type)
     size_t split_elems;
     size_t total;
+    // inference: decoder levels may take the transposed convolution inside their first 3x3
+    // convolution where that form applies (U is then not written): 0 never, 1 always, 2 where
+    // the autotuner found it faster
+    int fuse_up = 0;
 };
 
 // Autotune the 3x3 layers for `batch` samples on the forward buffers b (see no_autotune); layers
 // already tuned at that size return at once. Synchronises the stream on the first call of a size.
 int net_autotune_bufs(const no_net* net, int Hp, int Wp, int batch, const FwdBufs& b, no_prec prec, hipStream_t s);
-
-constexpr int KSPLIT_MAX = 4;
 
 template <class P>
 inline FwdBufs fwd_layout(const no_net* net, int Hp, int Wp, int batch, void* base, size_t cap,
@@ -117,11 +119,10 @@ inline FwdBufs fwd_layout(const no_net* net, int Hp, int Wp, int batch, void* ba
     }
     b.part = c.take<double2>(1024);
     b.sc = c.take<double>(2);
-    // split-K partials: the largest 3x3 layer output times the split count
-    size_t mx = 0;
-    for (int l = 0; l < lv; ++l) mx = std::max(mx, (size_t)batch * (Hp >> l) * (Wp >> l) * round16(net->a.base << l));
-    b.split_elems = mx * KSPLIT_MAX;
-    b.splitbuf = c.take<typename P::Acc>(b.split_elems);
+    // no split-K partials: the network's launches accumulate each output in one block (a split
+    // would change the summation order with the launch variant)
+    b.split_elems = 0;
+    b.splitbuf = nullptr;
     b.total = c.off + 256;
     return b;
 }
@@ -181,12 +182,23 @@ inline int unet_body(const no_net* net, const FwdBufs& b, int Hp, int Wp, int ba
         const Layer& lu = Ls[li++];
         const Layer& la = Ls[li++];
         const Layer& lb = Ls[li++];
-        HZ_TRY(launch_convT2<P>(Dn, lu.cin_p, packed_w<P>(net, lu), packed_b<P>(net, lu), (T*)b.U[l], lu.cout_p,
-                                H / 2, W / 2, batch, skip, s));
         const int ce = lu.cout_p;
-        HZ_TRY(launch_conv3<P>((const T*)b.E[l], ce, (const T*)b.U[l], ce, packed_w<P>(net, la), packed_b<P>(net, la),
-                               (T*)b.T1d[l], la.cout_p, nullptr, H, W, batch, true, skip, s, Conv3Out(),
-                               net_cfg(net, li - 2, H, W, batch, prec_of<P>()), sb));
+        const ConvCfg ucfg = net_cfg_up(net, li - 2, H, W, batch, prec_of<P>());
+        if (conv3_up_ok<P>(ce, ce, lu.cin_p, H, W) && (b.fuse_up == 1 || (b.fuse_up == 2 && ucfg.fuse))) {
+            UpIn up;
+            up.d = Dn;
+            up.cd = lu.cin_p;
+            up.wt = packed_w<P>(net, lu);
+            up.bt = packed_b<P>(net, lu);
+            HZ_TRY(launch_conv3_up<P>((const T*)b.E[l], ce, up, ce, packed_w<P>(net, la), packed_b<P>(net, la),
+                                      (T*)b.T1d[l], la.cout_p, H, W, batch, skip, s, ucfg));
+        } else {
+            HZ_TRY(launch_convT2<P>(Dn, lu.cin_p, packed_w<P>(net, lu), packed_b<P>(net, lu), (T*)b.U[l],
+                                    lu.cout_p, H / 2, W / 2, batch, skip, s));
+            HZ_TRY(launch_conv3<P>((const T*)b.E[l], ce, (const T*)b.U[l], ce, packed_w<P>(net, la),
+                                   packed_b<P>(net, la), (T*)b.T1d[l], la.cout_p, nullptr, H, W, batch, true, skip,
+                                   s, Conv3Out(), net_cfg(net, li - 2, H, W, batch, prec_of<P>()), sb));
+        }
         const bool last = l == 0 && head;
         HZ_TRY(launch_conv3<P>((const T*)b.T1d[l], lb.cin_p, nullptr, 0, packed_w<P>(net, lb), packed_b<P>(net, lb),
                                (T*)b.D[l], lb.cout_p, nullptr, H, W, batch, true, skip, s, last ? *head : Conv3Out(),

@@ -126,13 +126,26 @@ struct Conv3Out {
 };
 
 // Variant of a 3x3 convolution launch: channel tile (16 / 32 / 64; 0 = heuristic), rows per
-// wavefront (2 or 4: 8- or 16-row pixel tiles) and the number of input-channel splits (split-K
-// writes FP32/FP64 partial sums to a workspace and reduces them in a separate epilogue kernel).
+// wavefront (2 or 4: 8- or 16-row pixel tiles), the number of input-channel splits (split-K
+// writes FP32/FP64 partial sums to a workspace and reduces them in a separate epilogue kernel)
+// and, for a decoder's first layer, whether the fused form is faster.
 struct ConvCfg {
     int tn = 0;
     int rpw = 2;
     int ksplit = 1;
+    int fuse = 0;   // decoder layer: take the fused form (transposed convolution inside, UpIn)
 };
+
+// Second input part of a decoder 3x3 convolution given as the 2x2 stride-2 transposed
+// convolution of a coarser tensor, computed inside each block and never stored:
+// U[2i+a][2j+b][c] = bt[c] + sum_k d[i][j][k] wt[2a+b][c][k], d: [H/2][W/2][cd] per sample.
+struct UpIn {
+    const void* d = nullptr;
+    int cd = 0;
+    const void* wt = nullptr;   // activation type, [4][c1][cd] (the transposed layer's pack)
+    const void* bt = nullptr;   // accumulator type, [c1]
+};
+constexpr int UP_CDMAX = 128;   // largest coarse channel count of the fused form
 
 // Host-side launch helpers (defined in net_fwd.hip), one per precision.
 // conv3: y = act(conv3x3(concat[x0, x1]) + b) (+ pooled copy); batch samples along grid z.
@@ -153,6 +166,15 @@ int conv3_batch_tn(int cout_p, int64_t tiles);
 int convT2_batch_tn(int cout_p);
 template <class P>
 int conv_chunk(int cin_p, int c0, int c1);
+// Fused decoder convolution y = ReLU(conv3x3(concat[x0, U]) + b) with U = convT2(up) (see UpIn):
+// the same result bits as launch_convT2 followed by launch_conv3. BF16 only; conv3_up_ok tells
+// whether a layer qualifies.
+template <class P>
+bool conv3_up_ok(int c0, int c1, int cd, int H, int W);
+template <class P>
+int launch_conv3_up(const typename P::T* x0, int c0, UpIn up, int c1, const typename P::T* w,
+                    const typename P::Acc* bias, typename P::T* y, int cout_p, int H, int W, int batch,
+                    const int* skip, hipStream_t s, ConvCfg cfg);
 // convT2: y[2i+a][2j+b] = sum_c x[i][j][c] w[a][b][.][c] + b
 template <class P>
 int launch_convT2(const typename P::T* x, int cin_p, const typename P::T* w, const typename P::Acc* bias,

@@ -746,13 +746,24 @@ static TrainBufs<P> train_layout(const no_net* net, const hz_problem* p, int B, 
     t.gB.resize(lv);
     t.gU.resize(lv);
     t.gP.resize(lv);
+    // gA, gU and gP live within one level's backward step (written in full, then read): one
+    // scratch each for all levels; gB carries gradients from level to level
+    size_t ga = 0, gp = 0;
+    for (int l = 0; l < lv; ++l) {
+        const size_t px = (size_t)B * (Hp >> l) * (Wp >> l);
+        ga = std::max(ga, px * round16(net->a.base << l));
+        if (l > 0) gp = std::max(gp, px * round16(net->a.base << (l - 1)));
+    }
+    T* gas = c.take<T>(ga);
+    T* gus = lv > 1 ? c.take<T>(ga) : nullptr;
+    T* gps = lv > 1 ? c.take<T>(gp) : nullptr;
     for (int l = 0; l < lv; ++l) {
         const size_t px = (size_t)B * (Hp >> l) * (Wp >> l);
         const int cs = round16(net->a.base << l);
-        t.gA[l] = c.take<T>(px * cs);
+        t.gA[l] = gas;
         t.gB[l] = c.take<T>(px * cs);
-        t.gU[l] = l < lv - 1 ? c.take<T>(px * cs) : nullptr;
-        t.gP[l] = l > 0 ? c.take<T>(px * round16(net->a.base << (l - 1))) : nullptr;
+        t.gU[l] = l < lv - 1 ? gus : nullptr;
+        t.gP[l] = l > 0 ? gps : nullptr;
     }
     const int64_t n = p->n;
     t.z = c.take<float2>((size_t)B * n);

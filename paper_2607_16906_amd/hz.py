@@ -60,6 +60,7 @@ SIGNATURES = {
     "no_autotune": (_I, [_P, _P, _I, _P, _SZ, _P]),
     "no_layer_variant": (_I, [_P, _I, _I, _I, _I, _I, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)]),
     "no_set_layer_variant": (_I, [_P, _I, _I, _I, _I, _I, _I, _I]),
+    "no_set_fused_upsampling": (_I, [_P, _I]),
     "no_layer_info": (_I, [_P, _I, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32),
                            ct.POINTER(ct.c_int32)]),
     "no_layer_forward": (_I, [_P, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P, _SZ, _P]),
@@ -219,6 +220,11 @@ class Net:
         """Pin the launch variant of a 3x3 layer at this size (no_set_layer_variant)."""
         _check(load_library().no_set_layer_variant(self.handle, layer, PREC[prec], batch, H, W, tn, rows),
                "no_set_layer_variant")
+
+    def set_fused_upsampling(self, mode: int):
+        """BF16 decoder: transposed convolution inside the next 3x3 layer: 0 never, 1 always,
+        2 where autotuned faster (the default); the same result bits (no_set_fused_upsampling)."""
+        _check(load_library().no_set_fused_upsampling(self.handle, int(mode)), "no_set_fused_upsampling")
 
     def layer_info(self, layer: int):
         """(kind, cin_p, cout_p, cat_cp) of one layer (no_layer_info)."""

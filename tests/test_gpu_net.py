@@ -120,3 +120,29 @@ def test_pinned_layer_variants_identical_bits():
         net.set_layer_variant(convs[0], Hp, Hp, 24, 8)
     with pytest.raises(hz.HzError):
         net.set_layer_variant(len(specs) - 1, Hp, Hp, 16, 8)   # the head is not a 3x3 layer
+
+
+@pytest.mark.parametrize("levels,base,nx,p", [(4, 32, 256, 20), (4, 32, 30, 6), (3, 64, 44, 10), (4, 32, 100, 14)])
+def test_fused_upsampling_identical_bits(levels, base, nx, p):
+    # the BF16 decoder with the transposed convolution computed inside the next 3x3 layer gives
+    # the bits of the two separate layers (ragged tiles, both parities at the tile borders, the
+    # image border, untuned and autotuned launch variants)
+    from paper_2607_16906_amd import hz
+    op, gp, specs, theta, net, v = setup(levels, base, 5, nx, p, seed=8)
+    vd = to_dev(v, torch.complex64)
+    for tune in (False, True):
+        if tune:
+            net.set_fused_upsampling(2)
+            net.autotune(gp, "bf16")
+        outs = []
+        for mode in (1, 0, 2):   # always fused, never, the autotuner's choice
+            net.set_fused_upsampling(mode)
+            outs.append(net.apply(gp, vd, prec="bf16"))
+        fused = outs[0]
+        for o in outs[1:]:
+            assert torch.equal(fused, o), (tune, rel(to_np(fused), to_np(o)))
+    with pytest.raises(hz.HzError):
+        net.set_fused_upsampling(3)
+    # the oracle on the BF16-rounded weights, as for the unfused network
+    ref = unet.precond_apply(bf16_round(theta), specs, op, v)
+    assert rel(to_np(fused), ref) <= 3e-2
