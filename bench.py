@@ -205,6 +205,31 @@ def bench_batched(hz, torch, net, nsys=128, maxit=30):
             "min_relres": min(i.true_relres for i in infos), "max_relres": max(i.true_relres for i in infos)}
 
 
+def bench_restart(hz, torch, net, ms=(10, 30, 50, 100, 200, 512)):
+    """Restart-length study on the single-solve workload (296^2, BF16 network, FP32 Krylov,
+    tol 1e-6), up to the paper's long-cycle regime (m = 512): iterations, solve time and time per
+    iteration (the orthogonalisation grows with the basis)."""
+    from synth import H_10PPW, c2_system
+    s = c2_system(0)
+    gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW)
+    b = torch.from_numpy(s.b.ravel()).cuda()
+    rows = []
+    for m in ms:
+        ws = torch.empty(hz.fgmres_workspace_bytes(gp, net, m, 3000, "c64", "bf16"), dtype=torch.uint8, device="cuda")
+        hz.fgmres(gp, b, net=net, m=m, tol=TOL, maxit=3000, workspace=ws)   # warm-up (graphs, tuning)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = hz.fgmres(gp, b, net=net, m=m, tol=TOL, maxit=3000, workspace=ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rows.append({"m": m, "its": info.its, "cycles": info.cycles, "converged": info.status == 0,
+                     "true_relres": info.true_relres, "ms_per_solve": round(dt * 1e3, 2),
+                     "us_per_it": round(dt * 1e6 / max(info.its, 1), 1)})
+        del ws
+    return {"workload": "single solve, 256^2 interior + 20 PML, BF16 U-Net, FP32 Krylov, tol 1e-6, FGMRES(m)",
+            "runs": rows}
+
+
 def bench_large(hz, torch, net, maxit=100, m=50):
     """Large single solve: 1024^2 interior + 32 PML (1088^2 nodes), FGMRES(50), BF16 network (the
     trained 4-level network stands in for a 5-level one), FP32 Krylov vectors, bounded to maxit
@@ -297,7 +322,7 @@ def main():
                     help="with --roofline-only: time this layer alone (for a profiler run of one kernel)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="with --roofline-only: also copy 512 MiB with a plain device copy (counter calibration)")
-    ap.add_argument("--only", choices=["training", "batched", "large"], default=None,
+    ap.add_argument("--only", choices=["training", "batched", "large", "restart"], default=None,
                     help="run one extra section alone and print its JSON (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -320,7 +345,7 @@ def main():
             res = bench_training(hz, torch, steps=2)
         else:
             net1 = hz.Net(LEVELS, BASE, IN_CH, theta)
-            res = bench_batched(hz, torch, net1) if args.only == "batched" else bench_large(hz, torch, net1)
+            res = {"batched": bench_batched, "large": bench_large, "restart": bench_restart}[args.only](hz, torch, net1)
         print(json.dumps({args.only: res}))
         return
     s = c2_system(0)
@@ -425,6 +450,7 @@ def main():
         out["training"] = bench_training(hz, torch)
         out["batched"] = bench_batched(hz, torch, net)
         out["large"] = bench_large(hz, torch, net)
+        out["restart"] = bench_restart(hz, torch, net)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, theta, its)
     print(json.dumps(out))

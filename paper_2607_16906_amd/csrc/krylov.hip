@@ -139,13 +139,25 @@ __global__ __launch_bounds__(KT) void k_update(const C* __restrict__ V, int64_t 
                     ai[i] += (double)vr[i].x * wp.y - (double)vr[i].y * wp.x;
                 }
         }
+        // each wavefront reduces its lanes group by group, the 4 wavefront totals meet in LDS
         double2* mine = part + (int64_t)blockIdx.x * ldp;
+        __shared__ double red[KT / 64][2 * UPD_REG];
+        const int wv = threadIdx.x >> 6;
 #pragma unroll
         for (int i0 = 0; i0 < UPD_REG; i0 += IC) {
             if (i0 >= nv) break;
             double (&sr)[IC] = *reinterpret_cast<double (*)[IC]>(&ar[i0]);
             double (&si)[IC] = *reinterpret_cast<double (*)[IC]>(&ai[i0]);
-            block_store<IC>(sr, si, mine + i0, nv - i0);
+            int idx;
+            const double v = wave_reduce8(sr, si, &idx);
+            if ((threadIdx.x & 3) == 0) red[wv][2 * i0 + idx] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < 2 * nv) {
+            double t = 0;
+#pragma unroll
+            for (int k = 0; k < KT / 64; ++k) t += red[k][threadIdx.x];
+            ((double*)mine)[threadIdx.x] = t;
         }
         return;
     }

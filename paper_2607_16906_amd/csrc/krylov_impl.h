@@ -61,6 +61,43 @@ __device__ __forceinline__ void block_store(double (&ar)[NV], double (&ai)[NV], 
     }
 }
 
+// Sum IC = 8 complex values (16 doubles) over the 64 lanes of a wavefront with a transposing
+// butterfly (each exchange halves what a lane carries: 8 + 4 + 2 + 1 + 1 + 1 shuffles instead of
+// 16 x 6), fixed order. Afterwards lane l holds double number 8 b5 + 4 b4 + 2 b3 + b2 (bits of l)
+// of the 16 (re, im, re, im, ...); returns it and its index.
+__device__ __forceinline__ double wave_reduce8(const double (&ar)[IC], const double (&ai)[IC], int* idx) {
+    static_assert(IC == 8, "wave_reduce8 reduces 8 complex values");
+    const int ln = threadIdx.x & 63;
+    const int b5 = (ln >> 5) & 1, b4 = (ln >> 4) & 1, b3 = (ln >> 3) & 1, b2 = (ln >> 2) & 1;
+    double x[16];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        x[2 * q] = ar[q];
+        x[2 * q + 1] = ai[q];
+    }
+    double y[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) y[k] = (b5 ? x[k + 8] : x[k]) + __shfl_xor(b5 ? x[k] : x[k + 8], 32, 64);
+    double z[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) z[k] = (b4 ? y[k + 4] : y[k]) + __shfl_xor(b4 ? y[k] : y[k + 4], 16, 64);
+    double u[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) u[k] = (b3 ? z[k + 2] : z[k]) + __shfl_xor(b3 ? z[k] : z[k + 2], 8, 64);
+    double v = (b2 ? u[1] : u[0]) + __shfl_xor(b2 ? u[0] : u[1], 4, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 1, 64);
+    *idx = 8 * b5 + 4 * b4 + 2 * b3 + b2;
+    return v;
+}
+
+// part[q] = wavefront sum of (ar[q], ai[q]) for q < cnt (no LDS, no barrier)
+__device__ __forceinline__ void wave_store8(const double (&ar)[IC], const double (&ai)[IC], double2* out, int cnt) {
+    int idx;
+    const double v = wave_reduce8(ar, ai, &idx);
+    if ((threadIdx.x & 3) == 0 && (idx >> 1) < cnt) ((double*)out)[idx] = v;
+}
+
 // FP32 complex vectors with an even stride and 16-byte aligned bases are read two points per
 // lane (one 16-byte load per vector): the pair path of the sweeps below.
 template <typename C>
@@ -105,9 +142,70 @@ __device__ __forceinline__ void dots_body_pairs(const float2* __restrict__ V, in
     }
 }
 
+// Long bases (more than 2 IC vectors): wavefront wv takes the groups of IC vectors i0 = IC wv,
+// IC (wv + 4), ... over all of the block's points and reduces each group within the wavefront,
+// so the groups' loads and reductions overlap across the 4 wavefronts (no block barrier).
+template <typename C>
+__device__ __forceinline__ void dots_body_waves(const C* __restrict__ V, int64_t ldv, int nv,
+                                                const C* __restrict__ w, int64_t p0, int64_t p1,
+                                                double2* __restrict__ part) {
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const bool pairs = pair_ok<C>(V, w, ldv, p0);
+    for (int i0 = wv * IC; i0 < nv; i0 += (KT / 64) * IC) {
+        double ar[IC], ai[IC];
+#pragma unroll
+        for (int q = 0; q < IC; ++q) ar[q] = ai[q] = 0.0;
+        if constexpr (std::is_same<C, float2>::value) {
+            if (pairs) {
+                const int64_t npair = (p1 - p0) >> 1;
+                const float4* __restrict__ w4 = (const float4*)(w + p0);
+                for (int64_t k = ln; k < npair; k += 64) {
+                    const float4 a = w4[k];
+#pragma unroll
+                    for (int q = 0; q < IC; ++q) {
+                        if (i0 + q < nv) {
+                            const float4 v = ((const float4*)(V + (int64_t)(i0 + q) * ldv + p0))[k];
+                            ar[q] += (double)v.x * a.x + (double)v.y * a.y + (double)v.z * a.z + (double)v.w * a.w;
+                            ai[q] += (double)v.x * a.y - (double)v.y * a.x + (double)v.z * a.w - (double)v.w * a.z;
+                        }
+                    }
+                }
+                if (((p1 - p0) & 1) && ln == 63) {   // odd tail point
+                    const float2 a = w[p1 - 1];
+#pragma unroll
+                    for (int q = 0; q < IC; ++q)
+                        if (i0 + q < nv) {
+                            const float2 v = V[(int64_t)(i0 + q) * ldv + p1 - 1];
+                            ar[q] += (double)v.x * a.x + (double)v.y * a.y;
+                            ai[q] += (double)v.x * a.y - (double)v.y * a.x;
+                        }
+                }
+                wave_store8(ar, ai, part + i0, nv - i0);
+                continue;
+            }
+        }
+        for (int64_t p = p0 + ln; p < p1; p += 64) {
+            const C wp = w[p];
+#pragma unroll
+            for (int q = 0; q < IC; ++q) {
+                if (i0 + q < nv) {
+                    const C v = V[(int64_t)(i0 + q) * ldv + p];
+                    ar[q] += (double)v.x * wp.x + (double)v.y * wp.y;
+                    ai[q] += (double)v.x * wp.y - (double)v.y * wp.x;
+                }
+            }
+        }
+        wave_store8(ar, ai, part + i0, nv - i0);
+    }
+}
+
 template <typename C>
 __device__ __forceinline__ void dots_body(const C* __restrict__ V, int64_t ldv, int nv, const C* __restrict__ w,
                                  int64_t p0, int64_t p1, double2* __restrict__ part) {
+    if (nv > 2 * IC) {
+        dots_body_waves(V, ldv, nv, w, p0, p1, part);
+        return;
+    }
     if constexpr (std::is_same<C, float2>::value) {
         if (pair_ok<C>(V, w, ldv, p0)) {
             dots_body_pairs(V, ldv, nv, w, p0, p1, part);

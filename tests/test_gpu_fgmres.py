@@ -47,6 +47,22 @@ def test_gmres_fp64_matches_oracle_history(nx, p, m, maxit, conv):
     assert rel(to_np(x), ref.x) <= 1e-10
 
 
+def test_gmres_fp64_long_cycle_matches_oracle():
+    # one cycle of 300 Arnoldi steps (the long-cycle regime: basis blocks beyond the kernels'
+    # register and LDS windows of 32 and 128 vectors): FP64 history, count, status and solution
+    from paper_2607_16906_amd import hz
+    c, b, p = small_system(nx=24, p=6, seed=4)
+    op, gp = make_pair(c, p)
+    ref = ofg.fgmres(oracle_A(op), lambda v: v, b, m=300, tol=1e-10, maxit=300)
+    x, info = hz.fgmres(gp, to_dev(b, torch.complex128), m=300, tol=1e-10, maxit=300, krylov="c128")
+    print(f"its {info.its} (oracle {ref.its}), status {info.status}, final estimate {info.hist[-1]:.3e}")
+    assert info.status == ref.status and info.its == ref.its and info.its > 128
+    h = np.array(ref.est_history)
+    d = np.abs(info.hist - h)
+    assert np.all(d <= 1e-10 * h + 1e-14), float(np.max(d / (1e-10 * h + 1e-14)))
+    assert rel(to_np(x), ref.x) <= 1e-9
+
+
 def test_gmres_fp32_krylov_reaches_tol():
     # FP32 Krylov basis with the FP64 true residual and FP64 update of x: the solve still reaches
     # 1e-6 in the FP64 residual, in about as many steps as the FP64 oracle
