@@ -222,6 +222,11 @@ typedef struct {
     no_prec net_prec;     /* arithmetic of the network (ignored when net is NULL) */
     double* hist_host;    /* optional: |g_{j+1}| / ||b|| after every iteration */
     int32_t hist_len;     /* entries available in hist_host */
+    int32_t ortho;        /* 0: CGS with one reorthogonalisation (three reductions per step);
+                             1: delayed reorthogonalisation (one reduction per step: the step's
+                             reduction also reorthogonalises and normalises the previous vector,
+                             whose network input scale comes from the Pythagorean norm); needs a
+                             network and fgmres_solve; same iterates in exact arithmetic */
 } hz_opts;
 
 typedef struct {

@@ -717,6 +717,7 @@ static int check_batch(int nsys, const hz_problem* const* probs, const no_net* n
     HZ_CHECK_ARG(o->krylov == HZ_C64 || o->krylov == HZ_C128, "fgmres_solve_batched: bad krylov precision");
     HZ_CHECK_ARG(!net || o->net_prec == NO_BF16 || o->net_prec == NO_FP32 || o->net_prec == NO_FP64,
                  "fgmres_solve_batched: bad net_prec");
+    HZ_CHECK_ARG(o->ortho == 0, "fgmres_solve_batched: only ortho = 0 (CGS with one reorthogonalisation)");
     for (int s = 0; s < nsys; ++s) HZ_CHECK_ARG(probs[s], "fgmres_solve_batched: NULL problem");
     return HZ_OK;
 }

@@ -43,9 +43,16 @@ static FgmresLayout fgmres_layout(const hz_problem* p, const no_net* net, const 
     L.kb.sn = c.take<double2>(m);
     L.kb.g = c.take<double2>(m + 1);
     L.kb.y = c.take<double2>(m);
-    L.kb.h1 = c.take<double2>(m + 2);
+    const bool lag = o->ortho == 1;
+    L.kb.h1 = c.take<double2>(lag ? 2 * m + 4 : m + 2);
     L.kb.h2 = c.take<double2>(m + 2);
-    L.kb.ldp = m + 2;
+    L.kb.ldp = lag ? 2 * m + 4 : m + 2;
+    if (lag) {
+        L.kb.pend = c.take<double2>(m + 1);
+        L.kb.colb = c.take<double2>(m + 1);
+        L.kb.coef = c.take<double2>(2 * m + 2);
+        L.kb.lag_sc = c.take<double>(4);
+    }
     L.kb.part = c.take<double2>((size_t)sp.nblk * L.kb.ldp);
     L.kb.hist_cap = std::max(o->maxit, 1);
     L.kb.hist = c.take<double>(L.kb.hist_cap);
@@ -72,6 +79,7 @@ static int check_opts(const hz_opts* o, const no_net* net) {
     HZ_CHECK_ARG(!net || o->net_prec == NO_BF16 || o->net_prec == NO_FP32 || o->net_prec == NO_FP64,
                  "fgmres: bad net_prec");
     HZ_CHECK_ARG(!o->hist_host || o->hist_len >= 0, "fgmres: bad hist_len");
+    HZ_CHECK_ARG(o->ortho == 0 || (o->ortho == 1 && net), "fgmres: ortho must be 0, or 1 with a network");
     return HZ_OK;
 }
 
@@ -102,6 +110,43 @@ static int cycle_launches(const hz_problem* p, const no_net* net, const hz_opts*
         // without a network the next step's matvec reads v_{j+1} directly
         if (!net) HZ_TRY(launch_scale(c128, w, n, &kb.st->inv_h, stop, s));
     }
+    HZ_TRY(launch_backsolve(kb, s));
+    HZ_TRY(launch_xupdate(c128, zcol(0), n, x, n, kb, s));
+    HZ_TRY(launch_resid64(p, b, x, L.r64, L.rpart, nullptr, s));
+    HZ_TRY(launch_cycle_start(kb, L.rpart, nres, s));
+    HZ_TRY(launch_cast_scale(c128, L.r64, vcol(0), n, kb.st, s));
+    return HZ_OK;
+}
+
+// One restart cycle with delayed reorthogonalisation (ortho = 1): per step the network on the
+// once-projected vector v~_j (slot j; v_0 is normalised), w = A z_j into slot j + 1 with the
+// sums [Q, v~]^H [v~, w] and ||w||^2 in one reduction, the Hessenberg step (completes column
+// j - 1, forms column j's first pass) and one update pass (q_j into slot j, the next v~ into slot
+// j + 1); after the last step one more reduction completes the last column.
+static int cycle_launches_lag(const hz_problem* p, const no_net* net, const hz_opts* o, const FgmresLayout& L,
+                              KrylovBufs& kb, const double2* b, double2* x, int steps, hipStream_t s) {
+    const int64_t n = p->n;
+    const bool c128 = o->krylov == HZ_C128;
+    const size_t es = c128 ? sizeof(double2) : sizeof(float2);
+    const int* stop = &kb.st->stop;
+    Split sp = krylov_split(n);
+    const int nres = stencil_blocks(p);
+    auto vcol = [&](int i) { return (void*)((char*)L.V + es * n * i); };
+    auto zcol = [&](int i) { return (void*)((char*)L.Z + es * n * i); };
+    // the previous step's update pass leaves ||v~_j||^2 as block partials in slot 0 of part
+    const NormParts np{kb.part, sp.nblk, kb.ldp, kb.lag_sc};
+    for (int j = 0; j < steps; ++j) {
+        HZ_TRY(net_precond(net, p, o->net_prec, c128, vcol(j), zcol(j), L.net_ws, L.net_ws_bytes, stop, s, j == 0,
+                           nullptr, j > 0 ? &np : nullptr));
+        HZ_TRY(launch_stencil_dots(p, c128, zcol(j), L.V, n, j + 1, vcol(j + 1), sp, kb.part, kb.ldp, stop, s, true));
+        HZ_TRY(launch_finalize(kb.part, sp.nblk, kb.ldp, 2 * j + 3, kb.h1, stop, s));
+        HZ_TRY(launch_arnoldi_lag(kb, j, false, s));
+        HZ_TRY(launch_update_lag(c128, L.V, n, j, kb.coef, n, sp, kb.part, kb.ldp, stop, s));
+    }
+    // complete the last column: [Q, v~]^H v~ with v~ in slot steps
+    HZ_TRY(launch_dots(c128, L.V, n, steps + 1, vcol(steps), n, sp, kb.part, kb.ldp, false, stop, s));
+    HZ_TRY(launch_finalize(kb.part, sp.nblk, kb.ldp, steps + 1, kb.h1, stop, s));
+    HZ_TRY(launch_arnoldi_lag(kb, steps, true, s));
     HZ_TRY(launch_backsolve(kb, s));
     HZ_TRY(launch_xupdate(c128, zcol(0), n, x, n, kb, s));
     HZ_TRY(launch_resid64(p, b, x, L.r64, L.rpart, nullptr, s));
@@ -142,7 +187,8 @@ static int solve_on(const hz_problem* p, const no_net* net, const hz_opts* o, co
             exec = nullptr;
             graph = nullptr;
             HZ_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            const int crc = cycle_launches(p, net, o, L, kb, b, x, steps, s);
+            const int crc = o->ortho == 1 ? cycle_launches_lag(p, net, o, L, kb, b, x, steps, s)
+                                          : cycle_launches(p, net, o, L, kb, b, x, steps, s);
             const hipError_t e = hipStreamEndCapture(s, &graph);
             if (crc != HZ_OK) return crc;
             HZ_HIP(e);

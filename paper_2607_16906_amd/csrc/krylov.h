@@ -40,6 +40,11 @@ struct KrylovBufs {
     int ldp;           // m + 2
     double* hist;      // hist_cap entries
     int hist_cap;
+    // delayed reorthogonalisation (one reduction per step)
+    double2* pend;     // m+1: first-pass entries of the column completed at the next step
+    double2* colb;     // m+1: the column being completed
+    double2* coef;     // 2m+2: coefficients of the update pass
+    double* lag_sc;    // 4: network input scale s, 1/s; ||w|| of this and of the previous step
 };
 
 struct Split {
@@ -57,9 +62,15 @@ int launch_finalize(const double2* part, int nblk, int ldp, int cnt, double2* ou
 int launch_dots(bool c128, const void* V, int64_t ldv, int nv, const void* w, int64_t n, Split sp,
                 double2* part, int ldp, bool with_norm, const int* skip, hipStream_t s);
 
-// w = A z (the problem's operator) fused with launch_dots(..., with_norm = true) on w
+// w = A z (the problem's operator) fused with launch_dots(..., with_norm = true) on w; two: the
+// sums are taken against both V_{nv-1} and w (slots 0..nv-1 and nv..2nv-1, ||w||^2 in slot 2nv)
 int launch_stencil_dots(const hz_problem* p, bool c128, const void* z, const void* V, int64_t ldv, int nv,
-                        void* w, Split sp, double2* part, int ldp, const int* skip, hipStream_t s);
+                        void* w, Split sp, double2* part, int ldp, const int* skip, hipStream_t s,
+                        bool two = false);
+// delayed reorthogonalisation: the Hessenberg step (one block) and the one-pass update of step j
+int launch_arnoldi_lag(KrylovBufs& kb, int j, bool tail, hipStream_t s);
+int launch_update_lag(bool c128, void* V, int64_t ldv, int j, const double2* coef, int64_t n, Split sp,
+                      double2* part, int ldp, const int* skip, hipStream_t s);
 // w -= sum_i V_i h_i; mode 1 then also writes dots conj(V_i) w (slots 0..nv-1);
 // mode 2 writes ||w||^2 into slot 0
 int launch_update(bool c128, const void* V, int64_t ldv, int nv, const double2* h, void* w, int64_t n,

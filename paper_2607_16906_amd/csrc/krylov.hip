@@ -11,6 +11,7 @@
 // rotations: for (a, b) = (h_jj, h_{j+1,j}), rho = sqrt(|a|^2 + |b|^2),
 // c = |a| / rho, s = (a / |a|) conj(b) / rho (s = 1 when a = 0), and the pair
 // (x, y) maps to (c x + s y, -conj(s) x + c y); the residual norm is |g_{j+1}|.
+#include <algorithm>
 #include <cmath>
 
 #include "krylov.h"
@@ -55,7 +56,9 @@ __global__ __launch_bounds__(KT) void k_dots(const C* __restrict__ V, int64_t ld
 // w = A z evaluated pointwise over the block's index range (neighbours read through the cache,
 // zero outside the grid; same term order as the tiled stencil), then the pass-1 sums of k_dots
 // with the norm: part[b][i] = block sum of conj(V_i) w, part[b][nv] = ||w||^2.
-template <typename C>
+// TWO (delayed reorthogonalisation): the sums are taken against both v~ = V_{nv-1} and w,
+// part[b][i] = conj(V_i) v~, part[b][nv + i] = conj(V_i) w (i < nv), part[b][2 nv] = ||w||^2.
+template <typename C, bool TWO>
 __global__ __launch_bounds__(KT) void k_stencil_dots(const C* __restrict__ z, StencilCoef sc, int nx, int ny,
                                                      const C* __restrict__ V, int64_t ldv, int nv,
                                                      C* __restrict__ w, int64_t n, int64_t per,
@@ -77,8 +80,13 @@ __global__ __launch_bounds__(KT) void k_stencil_dots(const C* __restrict__ z, St
                 stencil_pair(z, w, k2, cE, cW, cN, cS, dxv, dyv, sc.conj_diag, nx, ny, p);
             __syncthreads();
             double2* mine = part + (int64_t)blockIdx.x * ldp;
-            dots_body(V, ldv, nv, (const C*)w, p0, p1, mine);
-            norm_body((const C*)w, p0, p1, mine + nv);
+            if constexpr (TWO) {
+                dots2_body(V, ldv, nv, V + (int64_t)(nv - 1) * ldv, (const C*)w, p0, p1, mine, nv);
+                norm_body((const C*)w, p0, p1, mine + 2 * nv);
+            } else {
+                dots_body(V, ldv, nv, (const C*)w, p0, p1, mine);
+                norm_body((const C*)w, p0, p1, mine + nv);
+            }
             return;
         }
     }
@@ -97,6 +105,11 @@ __global__ __launch_bounds__(KT) void k_stencil_dots(const C* __restrict__ z, St
     }
     __syncthreads();   // the sweeps below may read points written by other threads of the block
     double2* mine = part + (int64_t)blockIdx.x * ldp;
+    if constexpr (TWO) {
+        dots2_body(V, ldv, nv, V + (int64_t)(nv - 1) * ldv, (const C*)w, p0, p1, mine, nv);
+        norm_body((const C*)w, p0, p1, mine + 2 * nv);
+        return;
+    }
     dots_body(V, ldv, nv, (const C*)w, p0, p1, mine);
     norm_body((const C*)w, p0, p1, mine + nv);
 }
@@ -321,18 +334,147 @@ int launch_dots(bool c128, const void* V, int64_t ldv, int nv, const void* w, in
 }
 
 int launch_stencil_dots(const hz_problem* p, bool c128, const void* z, const void* V, int64_t ldv, int nv,
-                        void* w, Split sp, double2* part, int ldp, const int* skip, hipStream_t s) {
+                        void* w, Split sp, double2* part, int ldp, const int* skip, hipStream_t s, bool two) {
     const StencilCoef sc = stencil_coef(p, c128, false);
     // the pair form needs even block starts (per_block is a multiple of the block size) and an
     // even row length
     const int pairs = !c128 && stencil_pairs_ok(p, z, w) && (sp.per_block & 1) == 0 ? 1 : 0;
+#define HZ_SD(C, TW, PR)                                                                                       \
+    hipLaunchKernelGGL((k_stencil_dots<C, TW>), dim3(sp.nblk), dim3(KT), 0, s, (const C*)z, sc, p->nxt, p->nyt, \
+                       (const C*)V, ldv, nv, (C*)w, p->n, sp.per_block, part, ldp, skip, PR)
+    if (c128) {
+        if (two) HZ_SD(double2, true, 0);
+        else HZ_SD(double2, false, 0);
+    } else {
+        if (two) HZ_SD(float2, true, pairs);
+        else HZ_SD(float2, false, pairs);
+    }
+#undef HZ_SD
+    HZ_LAUNCH_CHECK();
+    return HZ_OK;
+}
+
+// Delayed-reorthogonalisation update of step j (one pass over q_0 .. q_{j-1}): slot j (v~)
+// becomes q_j = (v~ - sum_i a_i q_i) / nu and slot j + 1 (w) becomes w - sum_i b_i q_i - h_jj q_j,
+// with q_j as stored; coef = [a_0 .. a_{j-1}, b_0 .. b_{j-1}, h_jj, (1 / nu, 0)]. Each block writes
+// the squared norm of its part of the new slot j + 1 (as stored) to part[b * ldp].x: the next
+// network input's scale.
+template <typename C>
+__global__ __launch_bounds__(KT) void k_update_lag(C* __restrict__ V, int64_t ldv, int j,
+                                                   const double2* __restrict__ coef, int64_t n, int64_t per,
+                                                   double2* __restrict__ part, int ldp,
+                                                   const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const int64_t p0 = blockIdx.x * per, p1 = min(n, p0 + per);
+    C* __restrict__ vt = V + (int64_t)j * ldv;
+    C* __restrict__ w = V + (int64_t)(j + 1) * ldv;
+    const double inv_nu = coef[2 * j + 1].x;
+    const double2 h = coef[2 * j];
+    double nw[1] = {0.0}, zz[1] = {0.0};
+    bool done = false;
+    if constexpr (std::is_same<C, float2>::value) {
+        if (pair_ok<C>(V, V, ldv, p0)) {
+            float4* __restrict__ v4 = (float4*)(vt + p0);
+            float4* __restrict__ w4 = (float4*)(w + p0);
+            const int64_t npair = (p1 - p0) >> 1;
+            for (int64_t k = threadIdx.x; k < npair; k += KT) {
+                const float4 a0 = v4[k], b0 = w4[k];
+                double vx = a0.x, vy = a0.y, vz = a0.z, vw = a0.w;
+                double wx = b0.x, wy = b0.y, wz = b0.z, ww = b0.w;
+                for (int i = 0; i < j; ++i) {
+                    const float4 q = ((const float4*)(V + (int64_t)i * ldv + p0))[k];
+                    const double2 a = coef[i], b = coef[j + i];
+                    vx -= (double)q.x * a.x - (double)q.y * a.y;
+                    vy -= (double)q.x * a.y + (double)q.y * a.x;
+                    vz -= (double)q.z * a.x - (double)q.w * a.y;
+                    vw -= (double)q.z * a.y + (double)q.w * a.x;
+                    wx -= (double)q.x * b.x - (double)q.y * b.y;
+                    wy -= (double)q.x * b.y + (double)q.y * b.x;
+                    wz -= (double)q.z * b.x - (double)q.w * b.y;
+                    ww -= (double)q.z * b.y + (double)q.w * b.x;
+                }
+                const float4 qj{(float)(vx * inv_nu), (float)(vy * inv_nu), (float)(vz * inv_nu), (float)(vw * inv_nu)};
+                wx -= (double)qj.x * h.x - (double)qj.y * h.y;
+                wy -= (double)qj.x * h.y + (double)qj.y * h.x;
+                wz -= (double)qj.z * h.x - (double)qj.w * h.y;
+                ww -= (double)qj.z * h.y + (double)qj.w * h.x;
+                const float4 wn{(float)wx, (float)wy, (float)wz, (float)ww};
+                v4[k] = qj;
+                w4[k] = wn;
+                nw[0] += (double)wn.x * wn.x + (double)wn.y * wn.y + (double)wn.z * wn.z + (double)wn.w * wn.w;
+            }
+            done = ((p1 - p0) & 1) == 0;
+            if (!done) {
+                // the odd last point of the range, by one thread
+                if (threadIdx.x == KT - 1) {
+                    const int64_t p = p1 - 1;
+                    const C a0 = vt[p], b0 = w[p];
+                    double vx = a0.x, vy = a0.y, wx = b0.x, wy = b0.y;
+                    for (int i = 0; i < j; ++i) {
+                        const C q = V[(int64_t)i * ldv + p];
+                        const double2 a = coef[i], b = coef[j + i];
+                        vx -= (double)q.x * a.x - (double)q.y * a.y;
+                        vy -= (double)q.x * a.y + (double)q.y * a.x;
+                        wx -= (double)q.x * b.x - (double)q.y * b.y;
+                        wy -= (double)q.x * b.y + (double)q.y * b.x;
+                    }
+                    const C qj = from_d2<C>(double2{vx * inv_nu, vy * inv_nu});
+                    wx -= (double)qj.x * h.x - (double)qj.y * h.y;
+                    wy -= (double)qj.x * h.y + (double)qj.y * h.x;
+                    const C wn = from_d2<C>(double2{wx, wy});
+                    vt[p] = qj;
+                    w[p] = wn;
+                    nw[0] += (double)wn.x * wn.x + (double)wn.y * wn.y;
+                }
+                done = true;
+            }
+        }
+    }
+    if (!done) {
+        for (int64_t p = p0 + threadIdx.x; p < p1; p += KT) {
+            const C a0 = vt[p], b0 = w[p];
+            double vx = a0.x, vy = a0.y, wx = b0.x, wy = b0.y;
+            for (int i = 0; i < j; ++i) {
+                const C q = V[(int64_t)i * ldv + p];
+                const double2 a = coef[i], b = coef[j + i];
+                vx -= (double)q.x * a.x - (double)q.y * a.y;
+                vy -= (double)q.x * a.y + (double)q.y * a.x;
+                wx -= (double)q.x * b.x - (double)q.y * b.y;
+                wy -= (double)q.x * b.y + (double)q.y * b.x;
+            }
+            const C qj = from_d2<C>(double2{vx * inv_nu, vy * inv_nu});
+            wx -= (double)qj.x * h.x - (double)qj.y * h.y;
+            wy -= (double)qj.x * h.y + (double)qj.y * h.x;
+            const C wn = from_d2<C>(double2{wx, wy});
+            vt[p] = qj;
+            w[p] = wn;
+            nw[0] += (double)wn.x * wn.x + (double)wn.y * wn.y;
+        }
+    }
+    block_store<1>(nw, zz, part + (int64_t)blockIdx.x * ldp, 1);
+}
+
+__global__ void k_arnoldi_lag(SolveState* st, double2* R, double* cs, double2* sn, double2* g, double2* pend,
+                              double2* colb, double2* coef, double* sc, const double2* red, int j, int tail,
+                              double* hist) {
+    arnoldi_lag_body(st, R, cs, sn, g, pend, colb, coef, sc, red, j, tail, hist);
+}
+
+int launch_update_lag(bool c128, void* V, int64_t ldv, int j, const double2* coef, int64_t n, Split sp,
+                      double2* part, int ldp, const int* skip, hipStream_t s) {
     if (c128)
-        hipLaunchKernelGGL(k_stencil_dots<double2>, dim3(sp.nblk), dim3(KT), 0, s, (const double2*)z, sc, p->nxt,
-                           p->nyt, (const double2*)V, ldv, nv, (double2*)w, p->n, sp.per_block, part, ldp, skip, 0);
+        hipLaunchKernelGGL(k_update_lag<double2>, dim3(sp.nblk), dim3(KT), 0, s, (double2*)V, ldv, j, coef, n,
+                           sp.per_block, part, ldp, skip);
     else
-        hipLaunchKernelGGL(k_stencil_dots<float2>, dim3(sp.nblk), dim3(KT), 0, s, (const float2*)z, sc, p->nxt,
-                           p->nyt, (const float2*)V, ldv, nv, (float2*)w, p->n, sp.per_block, part, ldp, skip,
-                           pairs);
+        hipLaunchKernelGGL(k_update_lag<float2>, dim3(sp.nblk), dim3(KT), 0, s, (float2*)V, ldv, j, coef, n,
+                           sp.per_block, part, ldp, skip);
+    HZ_LAUNCH_CHECK();
+    return HZ_OK;
+}
+
+int launch_arnoldi_lag(KrylovBufs& kb, int j, bool tail, hipStream_t s) {
+    hipLaunchKernelGGL(k_arnoldi_lag, dim3(1), dim3(64), 0, s, kb.st, kb.R, kb.cs, kb.sn, kb.g, kb.pend, kb.colb,
+                       kb.coef, kb.lag_sc, kb.h1, j, tail ? 1 : 0, kb.hist);
     HZ_LAUNCH_CHECK();
     return HZ_OK;
 }

@@ -231,6 +231,73 @@ __device__ __forceinline__ void dots_body(const C* __restrict__ V, int64_t ldv, 
     }
 }
 
+// part[i] = sum conj(V_i) r0 and part[off1 + i] = sum conj(V_i) r1 over the block's points
+// [p0, p1), i < nv, reading V once: wavefront wv takes the groups of IC vectors IC wv,
+// IC (wv + 4), ... and reduces each within the wavefront.
+template <typename C>
+__device__ __forceinline__ void dots2_body(const C* __restrict__ V, int64_t ldv, int nv, const C* __restrict__ r0,
+                                           const C* __restrict__ r1, int64_t p0, int64_t p1,
+                                           double2* __restrict__ part, int off1) {
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    const bool pairs = pair_ok<C>(V, r0, ldv, p0) && pair_ok<C>(r1, r1, 0, p0);
+    for (int i0 = wv * IC; i0 < nv; i0 += (KT / 64) * IC) {
+        double xr[IC], xi[IC], yr[IC], yi[IC];
+#pragma unroll
+        for (int q = 0; q < IC; ++q) xr[q] = xi[q] = yr[q] = yi[q] = 0.0;
+        bool done = false;
+        if constexpr (std::is_same<C, float2>::value) {
+            if (pairs) {
+                const int64_t npair = (p1 - p0) >> 1;
+                const float4* __restrict__ a4 = (const float4*)(r0 + p0);
+                const float4* __restrict__ b4 = (const float4*)(r1 + p0);
+                for (int64_t k = ln; k < npair; k += 64) {
+                    const float4 a = a4[k], b = b4[k];
+#pragma unroll
+                    for (int q = 0; q < IC; ++q) {
+                        if (i0 + q < nv) {
+                            const float4 v = ((const float4*)(V + (int64_t)(i0 + q) * ldv + p0))[k];
+                            xr[q] += (double)v.x * a.x + (double)v.y * a.y + (double)v.z * a.z + (double)v.w * a.w;
+                            xi[q] += (double)v.x * a.y - (double)v.y * a.x + (double)v.z * a.w - (double)v.w * a.z;
+                            yr[q] += (double)v.x * b.x + (double)v.y * b.y + (double)v.z * b.z + (double)v.w * b.w;
+                            yi[q] += (double)v.x * b.y - (double)v.y * b.x + (double)v.z * b.w - (double)v.w * b.z;
+                        }
+                    }
+                }
+                if (((p1 - p0) & 1) && ln == 63) {   // odd tail point
+                    const float2 a = r0[p1 - 1], b = r1[p1 - 1];
+#pragma unroll
+                    for (int q = 0; q < IC; ++q)
+                        if (i0 + q < nv) {
+                            const float2 v = V[(int64_t)(i0 + q) * ldv + p1 - 1];
+                            xr[q] += (double)v.x * a.x + (double)v.y * a.y;
+                            xi[q] += (double)v.x * a.y - (double)v.y * a.x;
+                            yr[q] += (double)v.x * b.x + (double)v.y * b.y;
+                            yi[q] += (double)v.x * b.y - (double)v.y * b.x;
+                        }
+                }
+                done = true;
+            }
+        }
+        if (!done) {
+            for (int64_t p = p0 + ln; p < p1; p += 64) {
+                const C a = r0[p], b = r1[p];
+#pragma unroll
+                for (int q = 0; q < IC; ++q) {
+                    if (i0 + q < nv) {
+                        const C v = V[(int64_t)(i0 + q) * ldv + p];
+                        xr[q] += (double)v.x * a.x + (double)v.y * a.y;
+                        xi[q] += (double)v.x * a.y - (double)v.y * a.x;
+                        yr[q] += (double)v.x * b.x + (double)v.y * b.y;
+                        yi[q] += (double)v.x * b.y - (double)v.y * b.x;
+                    }
+                }
+            }
+        }
+        wave_store8(xr, xi, part + i0, nv - i0);
+        wave_store8(yr, yi, part + off1 + i0, nv - i0);
+    }
+}
+
 template <typename C>
 __device__ __forceinline__ void norm_body(const C* __restrict__ w, int64_t p0, int64_t p1, double2* __restrict__ out) {
     double a[1] = {0.0}, z[1] = {0.0};
@@ -334,46 +401,22 @@ __device__ inline void cycle_start_body(SolveState* st, const double* __restrict
     }
 }
 
-// One block (every thread calls it): assemble Hessenberg column j (h1 + h2), apply the previous rotations to it,
-// form rotation j, update g and the residual estimate, decide whether the cycle ends. The
-// rotations run as one chain in registers on lane 0; the column entries and rotations it reads
-// do not depend on its stores, so their loads can be issued ahead of the chain.
-__device__ inline void arnoldi_finish_body(SolveState* st, double2* __restrict__ R, double* __restrict__ cs,
-                                           double2* __restrict__ sn, double2* __restrict__ g,
-                                           const double2* __restrict__ h1, const double2* __restrict__ h2,
-                                           const double2* __restrict__ part, int nblk, int ldp, int j,
-                                           double* __restrict__ hist) {
-    if (st->stop) return;
+constexpr int AF_WIN = 128;   // rotations staged in LDS by the Hessenberg kernels
+
+// Lane 0: apply the previous rotations to Hessenberg column jc (entries col(i), i <= jc), form
+// rotation jc from the rotated diagonal entry and the subdiagonal hn, update g and the residual
+// estimate, and decide whether the cycle ends (converged, breakdown against wn0 = ||w|| before
+// orthogonalisation, non-finite values, history full). csl / snl hold the first AF_WIN rotations.
+template <class Col>
+__device__ inline void givens_tail(SolveState* st, double2* __restrict__ R, double* __restrict__ cs,
+                                   double2* __restrict__ sn, double2* __restrict__ g, double* __restrict__ hist,
+                                   int jc, double hn, double wn0, Col hcol, const double* csl, const double2* snl) {
     const int m = st->m;
-    const double hn2 = sum_parts(part, nblk, ldp, 0);     // ||w||^2 after orthogonalisation
-    // stage the column and the first AF_WIN rotations in LDS with one parallel pass
-    constexpr int AF_WIN = 128;
-    __shared__ double2 hl[AF_WIN + 1], snl[AF_WIN];
-    __shared__ double csl[AF_WIN];
-    for (int i = threadIdx.x; i <= j && i <= AF_WIN; i += blockDim.x) {
-        double2 a = h1[i];
-        if (h2) a = cadd(a, h2[i]);
-        hl[i] = a;
-        if (i < j && i < AF_WIN) {
-            csl[i] = cs[i];
-            snl[i] = sn[i];
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    double2* col = R + (int64_t)j * (m + 1);
-    const double wn0 = sqrt(h1[j + 1].x);
-    const double hn = sqrt(hn2);
-    auto hcol = [&](int i) {
-        if (i <= AF_WIN) return hl[i];
-        double2 a = h1[i];
-        if (h2) a = cadd(a, h2[i]);
-        return a;
-    };
+    double2* col = R + (int64_t)jc * (m + 1);
     double2 cur = hcol(0);
     bool bad = !isfinite(hn) || !isfinite(wn0) || !isfinite(cur.x) || !isfinite(cur.y);
 #pragma unroll 4
-    for (int i = 0; i < j; ++i) {   // previous rotations: (x0, x1) -> (c x0 + s x1, -conj(s) x0 + c x1)
+    for (int i = 0; i < jc; ++i) {   // previous rotations: (x0, x1) -> (c x0 + s x1, -conj(s) x0 + c x1)
         const double2 x1 = hcol(i + 1);
         const double c = i < AF_WIN ? csl[i] : cs[i];
         const double2 s = i < AF_WIN ? snl[i] : sn[i];
@@ -405,19 +448,19 @@ __device__ inline void arnoldi_finish_body(SolveState* st, double2* __restrict__
         s = double2{ph.x * hn / rho, ph.y * hn / rho};
         r = double2{ph.x * rho, ph.y * rho};
     }
-    cs[j] = c;
-    sn[j] = s;
-    col[j] = r;
-    col[j + 1] = double2{0.0, 0.0};
-    const double2 gj = g[j];
-    g[j + 1] = double2{-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x)};   // -conj(s) g_j
-    g[j] = double2{c * gj.x, c * gj.y};
-    const double est = sqrt(g[j + 1].x * g[j + 1].x + g[j + 1].y * g[j + 1].y) / st->bnorm;
+    cs[jc] = c;
+    sn[jc] = s;
+    col[jc] = r;
+    col[jc + 1] = double2{0.0, 0.0};
+    const double2 gj = g[jc];
+    g[jc + 1] = double2{-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x)};   // -conj(s) g_j
+    g[jc] = double2{c * gj.x, c * gj.y};
+    const double est = sqrt(g[jc + 1].x * g[jc + 1].x + g[jc + 1].y * g[jc + 1].y) / st->bnorm;
     st->est = est;
     if (st->its < st->hist_cap) hist[st->its] = est;
     st->its += 1;
-    if (j == 0) st->cycles += 1;
-    st->k = j + 1;
+    if (jc == 0) st->cycles += 1;
+    st->k = jc + 1;
     st->wnorm0 = wn0;
     if (hn <= 1e-14 * wn0) {
         st->flags |= FL_BREAKDOWN;
@@ -427,6 +470,122 @@ __device__ inline void arnoldi_finish_body(SolveState* st, double2* __restrict__
     }
     st->inv_h = 1.0 / hn;
     if (est <= st->tol || st->its >= st->hist_cap) st->stop = 1;
+}
+
+// One block (every thread calls it): assemble Hessenberg column j (h1 + h2), apply the previous rotations to it,
+// form rotation j, update g and the residual estimate, decide whether the cycle ends. The
+// rotations run as one chain in registers on lane 0; the column entries and rotations it reads
+// do not depend on its stores, so their loads can be issued ahead of the chain.
+__device__ inline void arnoldi_finish_body(SolveState* st, double2* __restrict__ R, double* __restrict__ cs,
+                                           double2* __restrict__ sn, double2* __restrict__ g,
+                                           const double2* __restrict__ h1, const double2* __restrict__ h2,
+                                           const double2* __restrict__ part, int nblk, int ldp, int j,
+                                           double* __restrict__ hist) {
+    if (st->stop) return;
+    const double hn2 = sum_parts(part, nblk, ldp, 0);     // ||w||^2 after orthogonalisation
+    // stage the column and the first AF_WIN rotations in LDS with one parallel pass
+    __shared__ double2 hl[AF_WIN + 1], snl[AF_WIN];
+    __shared__ double csl[AF_WIN];
+    for (int i = threadIdx.x; i <= j && i <= AF_WIN; i += blockDim.x) {
+        double2 a = h1[i];
+        if (h2) a = cadd(a, h2[i]);
+        hl[i] = a;
+        if (i < j && i < AF_WIN) {
+            csl[i] = cs[i];
+            snl[i] = sn[i];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double wn0 = sqrt(h1[j + 1].x);
+    const double hn = sqrt(hn2);
+    auto hcol = [&](int i) {
+        if (i <= AF_WIN) return hl[i];
+        double2 a = h1[i];
+        if (h2) a = cadd(a, h2[i]);
+        return a;
+    };
+    givens_tail(st, R, cs, sn, g, hist, j, hn, wn0, hcol, csl, snl);
+}
+
+// Delayed reorthogonalisation (one reduction per step), one block of 64 threads. At step j the
+// reduction gave red[i] = conj(q_i) v~ (i < j; red[j] = ||v~||^2) and red[j + 1 + i] =
+// conj(q_i) w (i < j; red[2j + 1] = conj(v~) w), red[2j + 2].x = ||w||^2, where v~ (slot j) is the
+// previous step's once-projected vector and w = A z_j with z_j the network applied to v~.
+// With a = red[0..j), nu = sqrt(||v~||^2 - ||a||^2) (Pythagoras):
+//  * column j - 1 is complete: its pending first-pass entries plus a, subdiagonal nu (Givens
+//    step, estimate, stop decisions as for the one-step form);
+//  * q_j = (v~ - Q a) / nu, and the first pass of column j against [Q, q_j]: b = red[j+1 ..),
+//    h_jj = (conj(v~) w - a^H b) / nu (pending entries of column j; coefficients for the update);
+//  * the update pass then forms the next network input v~_{j+1} = w - Q b - h_jj q_j (its norm,
+//    which sets the network's input scale, comes from that pass's partial sums: a Pythagorean
+//    estimate ||w||^2 - ||b||^2 - |h_jj|^2 loses all accuracy with FP32 vectors once
+//    ||v~_{j+1}|| / ||w|| falls below about 1e-3, as happens late in long cycles).
+// sc[2] = ||w|| of this step, sc[3] = that of the previous step (breakdown test of column j - 1).
+// tail: the cycle's last call (no new column: only column j - 1 is completed).
+__device__ inline void arnoldi_lag_body(SolveState* st, double2* __restrict__ R, double* __restrict__ cs,
+                                        double2* __restrict__ sn, double2* __restrict__ g,
+                                        double2* __restrict__ pend, double2* __restrict__ colb,
+                                        double2* __restrict__ coef, double* __restrict__ sc,
+                                        const double2* __restrict__ red, int j, int tail,
+                                        double* __restrict__ hist) {
+    if (st->stop) return;
+    const int ln = threadIdx.x & 63;
+    // ||a||^2, a^H b (fixed-order wavefront sums)
+    double na = 0, abr = 0, abi = 0;
+    for (int i = ln; i < j; i += 64) {
+        const double2 a = red[i];
+        na += a.x * a.x + a.y * a.y;
+        if (!tail) {
+            const double2 b = red[j + 1 + i];
+            abr += a.x * b.x + a.y * b.y;
+            abi += a.x * b.y - a.y * b.x;
+        }
+    }
+    na = wave_sum(na);
+    abr = wave_sum(abr);
+    abi = wave_sum(abi);
+    // v_0 comes normalised from the cycle start (g = beta e_1 relies on it): nu = 1 there
+    const double nu2 = red[j].x - na;
+    const double nu = j == 0 ? 1.0 : sqrt(nu2 > 0 ? nu2 : 0.0);
+    // column j - 1 = pending entries + a (entry j - 1 + 1 = nu is the subdiagonal)
+    __shared__ double2 snl[AF_WIN];
+    __shared__ double csl[AF_WIN];
+    if (j > 0) {
+        for (int i = ln; i < j; i += 64) {
+            colb[i] = cadd(pend[i], red[i]);
+            if (i < j - 1 && i < AF_WIN) {
+                csl[i] = cs[i];
+                snl[i] = sn[i];
+            }
+        }
+    }
+    __syncthreads();
+    if (!tail) {
+        // first pass of column j, the update's coefficients and the next input scale
+        const double inv_nu = nu > 0 ? 1.0 / nu : 0.0;
+        const double2 hjj{(red[2 * j + 1].x - abr) * inv_nu, (red[2 * j + 1].y - abi) * inv_nu};
+        for (int i = ln; i < j; i += 64) {
+            pend[i] = red[j + 1 + i];
+            coef[i] = red[i];                 // q_j = (v~ - sum a_i q_i) / nu
+            coef[j + i] = red[j + 1 + i];     // w' = w - sum b_i q_i - h_jj q_j
+        }
+        if (ln == 0) {
+            pend[j] = hjj;
+            coef[2 * j] = hjj;
+            coef[2 * j + 1] = double2{inv_nu, 0.0};
+            sc[2] = sqrt(red[2 * j + 2].x);     // ||w|| before orthogonalisation: breakdown test of column j
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    if (j > 0) {
+        // the breakdown test of column j - 1 compares nu with ||w_{j-1}|| (kept from the previous step)
+        const double wn0 = sc[3];
+        auto hcol = [&](int i) { return colb[i]; };
+        givens_tail(st, R, cs, sn, g, hist, j - 1, nu, wn0, hcol, csl, snl);
+    }
+    if (!tail) sc[3] = sc[2];
 }
 
 // y = R^{-1} g over the k completed columns (trailing zero pivots dropped).

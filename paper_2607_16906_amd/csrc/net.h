@@ -58,9 +58,18 @@ size_t net_fwd_ws_bytes(const no_net* net, int Hp, int Wp, int batch, no_prec pr
 // unit_norm: v is a Krylov vector of norm 1, so s = 1 / sqrt(n) without a reduction.
 // vscale (device scalar, with unit_norm only): v is first scaled in place by *vscale, which
 // makes it of norm 1 (the Arnoldi normalisation v_{j+1} = w / h_{j+1,j} done here).
+// ||v||^2 given as partial sums by the caller's last pass over v: part[q * ldp].x, q < count;
+// sc (device, 2 doubles) receives [s, 1/s].
+struct NormParts {
+    const double2* part;
+    int count, ldp;
+    double* sc;
+};
+// nparts (without unit_norm and vscale): the input scale comes from the caller's partial sums
+// and no separate reduction runs.
 int net_precond(const no_net* net, const hz_problem* p, no_prec prec, bool c128, const void* v, void* z,
                 void* ws, size_t ws_bytes, const int* skip, hipStream_t s, bool unit_norm = false,
-                const double* vscale = nullptr);
+                const double* vscale = nullptr, const NormParts* nparts = nullptr);
 // Time every launch variant of every 3x3 layer at this problem's size (batch 1) on the forward
 // workspace and remember the fastest; returns HZ_OK at once when already tuned. Synchronises.
 int net_autotune(const no_net* net, const hz_problem* p, no_prec prec, void* ws, size_t ws_bytes, hipStream_t s);

@@ -174,10 +174,10 @@ __global__ void k_head(const typename P::T* __restrict__ D, int cin_p, const typ
 template <class P>
 static int precond_impl(const no_net* net, const hz_problem* p, bool c128, const void* v, void* z, void* ws,
                         size_t ws_bytes, const int* skip, hipStream_t s, bool unit_norm,
-                        const double* vscale) {
+                        const double* vscale, const NormParts* nparts) {
     using T = typename P::T;
-    if (vscale && !unit_norm) {
-        set_error("no_precond_apply: in-place scaling needs a unit-norm result");
+    if ((vscale && !unit_norm) || (nparts && (unit_norm || vscale))) {
+        set_error("no_precond_apply: in-place scaling needs a unit-norm result, a given scale neither");
         return HZ_ERR_ARG;
     }
     int Hp, Wp;
@@ -192,20 +192,23 @@ static int precond_impl(const no_net* net, const hz_problem* p, bool c128, const
     Split sp = krylov_split(n);
     // s = ||v|| / sqrt(n); a unit-norm Krylov vector has s = 1 / sqrt(n) without a reduction
     const double fixed_s = unit_norm ? 1.0 / sqrt((double)n) : 0.0;
-    if (!unit_norm) {
+    double* scp = nparts ? nparts->sc : b.sc;   // [s, 1/s]
+    if (!unit_norm && !nparts) {
         HZ_TRY(launch_norm_partials(c128, v, n, sp, b.part, 1, 0, skip, s));
         hipLaunchKernelGGL(k_scale_factor, dim3(1), dim3(64), 0, s, b.part, sp.nblk, n, b.sc, skip);
         HZ_LAUNCH_CHECK();
     }
     const unsigned gp = (unsigned)(((int64_t)Hp * Wp + 255) / 256);
     if (c128)
-        hipLaunchKernelGGL((k_pack<P, double2>), dim3(gp), dim3(256), 0, s, (const double2*)v, b.sc, p->cnd, p->sigx,
+        hipLaunchKernelGGL((k_pack<P, double2>), dim3(gp), dim3(256), 0, s, (const double2*)v, scp, p->cnd, p->sigx,
                            p->sigy, p->nxt, p->nyt, Hp, Wp, net->a.in_ch, (T*)b.X, skip, fixed_s, vscale,
-                           vscale ? (double2*)v : nullptr);
+                           vscale ? (double2*)v : nullptr, nparts ? nparts->part : nullptr, nparts ? nparts->count : 0,
+                           nparts ? nparts->ldp : 0);
     else
-        hipLaunchKernelGGL((k_pack<P, float2>), dim3(gp), dim3(256), 0, s, (const float2*)v, b.sc, p->cnd, p->sigx,
+        hipLaunchKernelGGL((k_pack<P, float2>), dim3(gp), dim3(256), 0, s, (const float2*)v, scp, p->cnd, p->sigx,
                            p->sigy, p->nxt, p->nyt, Hp, Wp, net->a.in_ch, (T*)b.X, skip, fixed_s, vscale,
-                           vscale ? (float2*)v : nullptr);
+                           vscale ? (float2*)v : nullptr, nparts ? nparts->part : nullptr, nparts ? nparts->count : 0,
+                           nparts ? nparts->ldp : 0);
     HZ_LAUNCH_CHECK();
     const Layer& lh = net->layers.back();
     if (lh.cin_p == 16 || lh.cin_p == 32 || lh.cin_p == 64) {
@@ -217,7 +220,7 @@ static int precond_impl(const no_net* net, const hz_problem* p, bool c128, const
         hd.head_c128 = c128 ? 1 : 0;
         hd.head_nxt = p->nxt;
         hd.head_nyt = p->nyt;
-        hd.head_sc = b.sc;
+        hd.head_sc = scp;
         hd.head_fixed_s = fixed_s;
         return unet_body<P>(net, b, Hp, Wp, 1, skip, s, &hd);
     }
@@ -226,10 +229,10 @@ static int precond_impl(const no_net* net, const hz_problem* p, bool c128, const
     const unsigned gh = (unsigned)((n + 255) / 256);
     if (c128)
         hipLaunchKernelGGL((k_head<P, double2>), dim3(gh), dim3(256), 0, s, D0, lh.cin_p, packed_w<P>(net, lh),
-                           packed_b<P>(net, lh), b.sc, p->nxt, p->nyt, Wp, (double2*)z, skip, fixed_s);
+                           packed_b<P>(net, lh), scp, p->nxt, p->nyt, Wp, (double2*)z, skip, fixed_s);
     else
         hipLaunchKernelGGL((k_head<P, float2>), dim3(gh), dim3(256), 0, s, D0, lh.cin_p, packed_w<P>(net, lh),
-                           packed_b<P>(net, lh), b.sc, p->nxt, p->nyt, Wp, (float2*)z, skip, fixed_s);
+                           packed_b<P>(net, lh), scp, p->nxt, p->nyt, Wp, (float2*)z, skip, fixed_s);
     HZ_LAUNCH_CHECK();
     return HZ_OK;
 }
@@ -443,11 +446,15 @@ size_t net_fwd_ws_bytes(const no_net* net, int Hp, int Wp, int batch, no_prec pr
 }
 
 int net_precond(const no_net* net, const hz_problem* p, no_prec prec, bool c128, const void* v, void* z, void* ws,
-                size_t ws_bytes, const int* skip, hipStream_t s, bool unit_norm, const double* vscale) {
+                size_t ws_bytes, const int* skip, hipStream_t s, bool unit_norm, const double* vscale,
+                const NormParts* nparts) {
     switch (prec) {
-        case NO_BF16: return precond_impl<PolBF16>(net, p, c128, v, z, ws, ws_bytes, skip, s, unit_norm, vscale);
-        case NO_FP32: return precond_impl<PolF32>(net, p, c128, v, z, ws, ws_bytes, skip, s, unit_norm, vscale);
-        case NO_FP64: return precond_impl<PolF64>(net, p, c128, v, z, ws, ws_bytes, skip, s, unit_norm, vscale);
+        case NO_BF16:
+            return precond_impl<PolBF16>(net, p, c128, v, z, ws, ws_bytes, skip, s, unit_norm, vscale, nparts);
+        case NO_FP32:
+            return precond_impl<PolF32>(net, p, c128, v, z, ws, ws_bytes, skip, s, unit_norm, vscale, nparts);
+        case NO_FP64:
+            return precond_impl<PolF64>(net, p, c128, v, z, ws, ws_bytes, skip, s, unit_norm, vscale, nparts);
     }
     set_error("no_precond_apply: bad precision");
     return HZ_ERR_ARG;

@@ -49,14 +49,36 @@ __device__ __forceinline__ void pack_pixel(const C* __restrict__ v, double is, c
 // One padded pixel per thread. fixed_s > 0: the caller knows ||v|| / sqrt(n) (a unit-norm Krylov
 // vector) and sc is not read; otherwise s = 1 / sc[1].
 template <class P, typename C>
-__global__ void k_pack(const C* __restrict__ v, const double* __restrict__ sc, const double* __restrict__ cnd,
+//
+// npart (with nnp, ldp): ||v||^2 is given as nnp partial sums npart[q * ldp].x (the caller's last
+// pass over v wrote them); every block adds them in the same fixed order, and block 0 stores
+// sc[0] = s, sc[1] = 1 / s for the later output scaling.
+__global__ void k_pack(const C* __restrict__ v, double* __restrict__ sc, const double* __restrict__ cnd,
                        const double* __restrict__ sigx, const double* __restrict__ sigy, int nxt, int nyt, int Hp,
                        int Wp, int in_ch, typename P::T* __restrict__ X, const int* __restrict__ skip,
-                       double fixed_s = 0.0, const double* __restrict__ vscale = nullptr, C* vout = nullptr) {
+                       double fixed_s = 0.0, const double* __restrict__ vscale = nullptr, C* vout = nullptr,
+                       const double2* __restrict__ npart = nullptr, int nnp = 0, int ldp = 0) {
     if (skip && *skip) return;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double is;
+    if (npart) {
+        __shared__ double red[4];
+        double a = 0;
+        for (int q = threadIdx.x; q < nnp; q += blockDim.x) a += npart[(int64_t)q * ldp].x;
+        a = wave_sum(a);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+        __syncthreads();
+        const double nv2 = red[0] + red[1] + red[2] + red[3];
+        const double s = sqrt(nv2 / ((double)nxt * nyt));
+        is = s > 0 ? 1.0 / s : 0.0;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc[0] = s;
+            sc[1] = is;
+        }
+    } else {
+        is = fixed_s > 0 ? 1.0 / fixed_s : sc[1];
+    }
     if (idx >= (int64_t)Hp * Wp) return;
-    const double is = fixed_s > 0 ? 1.0 / fixed_s : sc[1];
     pack_pixel<P, C>(v, is, cnd, sigx, sigy, nxt, nyt, Wp, in_ch, X, idx, vscale, vout);
 }
 

@@ -35,7 +35,8 @@ class NoArch(ct.Structure):
 
 class HzOpts(ct.Structure):
     _fields_ = [("m", ct.c_int32), ("maxit", ct.c_int32), ("tol", ct.c_double), ("krylov", ct.c_int),
-                ("net_prec", ct.c_int), ("hist_host", ct.POINTER(ct.c_double)), ("hist_len", ct.c_int32)]
+                ("net_prec", ct.c_int), ("hist_host", ct.POINTER(ct.c_double)), ("hist_len", ct.c_int32),
+                ("ortho", ct.c_int32)]
 
 
 class HzInfo(ct.Structure):
@@ -346,16 +347,22 @@ class SolveInfo:
     hist: np.ndarray
 
 
+ORTHO = {"cgs2": 0, "dcgs2": 1}
+
+
 def fgmres(problem: Problem, b, x0=None, *, net: Net | None = None, m: int = 30, tol: float = 1e-6,
-           maxit: int = 300, krylov: str = "c64", net_prec: str = "bf16", workspace=None):
-    """Solve A x = b (fgmres_solve). b: complex128 device vector; returns (x, SolveInfo)."""
+           maxit: int = 300, krylov: str = "c64", net_prec: str = "bf16", workspace=None, ortho: str = "cgs2"):
+    """Solve A x = b (fgmres_solve). b: complex128 device vector; returns (x, SolveInfo).
+
+    ortho: "cgs2" (classical Gram-Schmidt with one reorthogonalisation) or "dcgs2" (delayed
+    reorthogonalisation, one reduction per step; needs a network)."""
     torch = _torch()
     lib = load_library()
     b = b.to(torch.complex128).contiguous()
     x = torch.zeros_like(b) if x0 is None else x0.to(torch.complex128).contiguous().clone()
     hist = np.zeros(maxit, np.float64)
     opts = HzOpts(m, maxit, tol, HZ_C64 if krylov == "c64" else HZ_C128, PREC[net_prec],
-                  hist.ctypes.data_as(ct.POINTER(ct.c_double)), maxit)
+                  hist.ctypes.data_as(ct.POINTER(ct.c_double)), maxit, ORTHO[ortho])
     nh = net.handle if net is not None else None
     nb = lib.fgmres_workspace_size(problem.handle, nh, ct.byref(opts))
     if nb == 0:

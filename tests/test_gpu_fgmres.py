@@ -78,7 +78,8 @@ def test_gmres_fp32_krylov_reaches_tol():
     assert r <= 1e-6 and abs(r - info.true_relres) <= 1e-9
 
 
-def test_c1_fgmres_fp64_net_matches_oracle():
+@pytest.mark.parametrize("ortho", ["cgs2", "dcgs2"])
+def test_c1_fgmres_fp64_net_matches_oracle(ortho):
     # the plain-FP64 configuration: 64^2 + 8 PML, 2-level / 16-channel U-Net with seeded (untrained)
     # weights, m = 30, tol 1e-6, <= 300 its. The untrained network barely reduces the residual, and in
     # that stagnating regime rounding differences between two correct FP64 runs grow from cycle to
@@ -92,7 +93,7 @@ def test_c1_fgmres_fp64_net_matches_oracle():
     M = lambda v: unet.precond_apply(theta.astype(np.float64), specs, op, v.reshape(op.ny, op.nx)).ravel()
     ref = ofg.fgmres(oracle_A(op), M, s.b, m=30, tol=1e-6, maxit=300)
     x, info = hz.fgmres(gp, to_dev(s.b, torch.complex128), net=net, m=30, tol=1e-6, maxit=300,
-                        krylov="c128", net_prec="fp64")
+                        krylov="c128", net_prec="fp64", ortho=ortho)
     assert info.its == ref.its and info.status == ref.status and info.cycles == ref.cycles
     h = np.array(ref.est_history)
     d = np.abs(info.hist[:30] - h[:30])
@@ -111,7 +112,8 @@ WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 
 
 @pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights missing")
-def test_fgmres_fp64_net_converging_matches_oracle():
+@pytest.mark.parametrize("ortho", ["cgs2", "dcgs2"])
+def test_fgmres_fp64_net_converging_matches_oracle(ortho):
     # a small grid where FGMRES preconditioned by the trained 4-level / 32-channel network converges
     # in one cycle: FP64 parity of the whole residual history, the iteration count and the solution
     from paper_2607_16906_amd import hz
@@ -123,13 +125,43 @@ def test_fgmres_fp64_net_converging_matches_oracle():
     M = lambda v: unet.precond_apply(theta.astype(np.float64), specs, op, v.reshape(op.ny, op.nx)).ravel()
     ref = ofg.fgmres(oracle_A(op), M, b, m=60, tol=1e-8, maxit=400)
     x, info = hz.fgmres(gp, to_dev(b, torch.complex128), net=net, m=60, tol=1e-8, maxit=400,
-                        krylov="c128", net_prec="fp64")
+                        krylov="c128", net_prec="fp64", ortho=ortho)
     assert ref.status == 0 and info.status == 0
     assert info.its == ref.its
     h = np.array(ref.est_history)
     d = np.abs(info.hist - h)
     assert np.all(d <= 1e-10 * h + 1e-14), float(np.max(d / (1e-10 * h + 1e-14)))
     assert rel(to_np(x), ref.x) <= 1e-8
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights missing")
+@pytest.mark.parametrize("m,maxit", [(5, 23), (1, 6), (8, 8)])
+def test_dcgs2_cycle_boundaries_match_oracle(m, maxit):
+    # delayed reorthogonalisation completes each column one step late: short cycles, cycles of one
+    # step, a maxit cap inside a cycle and a cap at a cycle end give the oracle's FP64 history
+    from paper_2607_16906_amd import hz
+    c, b, p = small_system(nx=12, p=4, seed=5)
+    op, gp = make_pair(c, p)
+    specs = unet.layer_specs(4, 32, 5)
+    theta = np.load(WEIGHTS)["theta"].astype(np.float32)
+    net = hz.Net(4, 32, 5, theta)
+    M = lambda v: unet.precond_apply(theta.astype(np.float64), specs, op, v.reshape(op.ny, op.nx)).ravel()
+    ref = ofg.fgmres(oracle_A(op), M, b, m=m, tol=1e-12, maxit=maxit)
+    x, info = hz.fgmres(gp, to_dev(b, torch.complex128), net=net, m=m, tol=1e-12, maxit=maxit,
+                        krylov="c128", net_prec="fp64", ortho="dcgs2")
+    assert info.its == ref.its and info.status == ref.status and info.cycles == ref.cycles
+    h = np.array(ref.est_history)
+    d = np.abs(info.hist - h)
+    assert np.all(d <= 1e-10 * h + 1e-14), float(np.max(d / (1e-10 * h + 1e-14)))
+    assert rel(to_np(x), ref.x) <= 1e-9
+
+
+def test_dcgs2_needs_a_network():
+    from paper_2607_16906_amd import hz
+    c, b, p = small_system(nx=12, p=4, seed=5)
+    op, gp = make_pair(c, p)
+    with pytest.raises(hz.HzError):
+        hz.fgmres(gp, to_dev(b, torch.complex128), m=5, tol=1e-6, maxit=10, ortho="dcgs2")
 
 
 def test_degenerate_solves():

@@ -56,13 +56,14 @@ def test_c2_network_full_size(c2, prec, tol):
     assert err <= tol
 
 
-def test_c2_solve_full_size(c2):
+@pytest.mark.parametrize("ortho", ["cgs2", "dcgs2"])
+def test_c2_solve_full_size(c2, ortho):
     # the benchmark's solve: BF16 network, FP32 Krylov vectors, FGMRES(30), tol 1e-6; the true
     # residual of the returned x is recomputed with the oracle's FP64 operator
     from paper_2607_16906_amd import hz
     s, op, gp, theta, net = c2
     x, info = hz.fgmres(gp, to_dev(s.b, torch.complex128), net=net, m=30, tol=1e-6, maxit=3000, krylov="c64",
-                        net_prec="bf16")
+                        net_prec="bf16", ortho=ortho)
     assert info.status == 0
     xs = to_np(x).reshape(op.ny, op.nx)
     r = s.b.reshape(op.ny, op.nx) - ohz.op_apply(op, xs)
@@ -71,7 +72,7 @@ def test_c2_solve_full_size(c2):
     assert rr <= 1e-6 and abs(rr - info.true_relres) <= 1e-9
 
 
-def bf16_solve_pair(nx, p, seed):
+def bf16_solve_pair(nx, p, seed, ortho="cgs2"):
     """(oracle result, GPU info, true relative residual of the GPU x) of one BF16-preconditioned
     solve: FP64 oracle FGMRES with the FP64 network on the BF16-rounded weights, GPU FGMRES with
     the BF16 network and FP32 Krylov vectors (m = 30, tol = 1e-6)."""
@@ -87,13 +88,14 @@ def bf16_solve_pair(nx, p, seed):
     ref = ofg.fgmres(A, M, b.ravel(), m=30, tol=1e-6, maxit=400)
     net = hz.Net(4, 32, 5, theta)
     x, info = hz.fgmres(gp, to_dev(b, torch.complex128), net=net, m=30, tol=1e-6, maxit=400, krylov="c64",
-                        net_prec="bf16")
+                        net_prec="bf16", ortho=ortho)
     rr = np.linalg.norm(b.ravel() - A(to_np(x))) / np.linalg.norm(b)
     print(f"nx {nx} seed {seed}: its GPU {info.its}, oracle {ref.its}, true relres {rr:.3e}")
     return ref, info, rr
 
 
-def test_bf16_fgmres_iterations_match_oracle():
+@pytest.mark.parametrize("ortho", ["cgs2", "dcgs2"])
+def test_bf16_fgmres_iterations_match_oracle(ortho):
     # 18 seeded solves of 30-60 iterations (12^2-20^2 interiors + 6 PML): every solve converges
     # with true relative residual <= tol; the iteration count is within 2 of the oracle's on
     # average and within max(2, 10 %) for each solve (rounding-level differences move single
@@ -102,7 +104,7 @@ def test_bf16_fgmres_iterations_match_oracle():
     diffs = []
     for nx in (12, 16, 20):
         for seed in range(6):
-            ref, info, rr = bf16_solve_pair(nx, 6, seed)
+            ref, info, rr = bf16_solve_pair(nx, 6, seed, ortho)
             assert ref.status == 0 and info.status == 0 and rr <= 1e-6
             assert abs(info.its - ref.its) <= max(2, ref.its // 10), (nx, seed, info.its, ref.its)
             diffs.append(abs(info.its - ref.its))
