@@ -205,29 +205,37 @@ def bench_batched(hz, torch, net, nsys=128, maxit=30):
             "min_relres": min(i.true_relres for i in infos), "max_relres": max(i.true_relres for i in infos)}
 
 
-def bench_restart(hz, torch, net, ms=(10, 30, 50, 100, 200, 512)):
-    """Restart-length study on the single-solve workload (296^2, BF16 network, FP32 Krylov,
-    tol 1e-6), up to the paper's long-cycle regime (m = 512): iterations, solve time and time per
-    iteration (the orthogonalisation grows with the basis)."""
+RESTART_RUNS = [(m, "c64", "cgs2") for m in (10, 30, 50, 100, 200, 512)] + [
+    (30, "c64", "dcgs2"), (100, "c64", "dcgs2"), (100, "c128", "cgs2"), (100, "c128", "dcgs2"),
+    (512, "c128", "cgs2"), (512, "c128", "dcgs2")]
+
+
+def bench_restart(hz, torch, net, runs=RESTART_RUNS):
+    """Restart-length study on the single-solve workload (296^2, BF16 network, tol 1e-6), up to
+    the paper's long-cycle regime (m = 512): iterations, solve time and time per iteration (the
+    orthogonalisation grows with the basis), for CGS with one reorthogonalisation and the delayed
+    (one-reduction) form, with FP32 or FP64 Krylov vectors. The one-reduction form is not run with
+    FP32 vectors at m = 512: it loses orthogonality there and stalls near 4e-4."""
     from synth import H_10PPW, c2_system
     s = c2_system(0)
     gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW)
     b = torch.from_numpy(s.b.ravel()).cuda()
     rows = []
-    for m in ms:
-        ws = torch.empty(hz.fgmres_workspace_bytes(gp, net, m, 3000, "c64", "bf16"), dtype=torch.uint8, device="cuda")
-        hz.fgmres(gp, b, net=net, m=m, tol=TOL, maxit=3000, workspace=ws)   # warm-up (graphs, tuning)
+    for m, kr, ortho in runs:
+        ws = torch.empty(hz.fgmres_workspace_bytes(gp, net, m, 3000, kr, "bf16", ortho), dtype=torch.uint8,
+                         device="cuda")
+        kw = dict(net=net, m=m, tol=TOL, maxit=3000, krylov=kr, workspace=ws, ortho=ortho)
+        hz.fgmres(gp, b, **kw)   # warm-up (graphs, tuning)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, info = hz.fgmres(gp, b, net=net, m=m, tol=TOL, maxit=3000, workspace=ws)
+        x, info = hz.fgmres(gp, b, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        rows.append({"m": m, "its": info.its, "cycles": info.cycles, "converged": info.status == 0,
-                     "true_relres": info.true_relres, "ms_per_solve": round(dt * 1e3, 2),
-                     "us_per_it": round(dt * 1e6 / max(info.its, 1), 1)})
+        rows.append({"m": m, "krylov": kr, "ortho": ortho, "its": info.its, "cycles": info.cycles,
+                     "converged": info.status == 0, "true_relres": info.true_relres,
+                     "ms_per_solve": round(dt * 1e3, 2), "us_per_it": round(dt * 1e6 / max(info.its, 1), 1)})
         del ws
-    return {"workload": "single solve, 256^2 interior + 20 PML, BF16 U-Net, FP32 Krylov, tol 1e-6, FGMRES(m)",
-            "runs": rows}
+    return {"workload": "single solve, 256^2 interior + 20 PML, BF16 U-Net, tol 1e-6, FGMRES(m)", "runs": rows}
 
 
 def bench_large(hz, torch, net, maxit=100, m=50):

@@ -413,6 +413,6 @@ def fgmres_batched_workspace_bytes(problems, net: Net | None, m: int, maxit: int
 
 
 def fgmres_workspace_bytes(problem: Problem, net: Net | None, m: int, maxit: int, krylov: str = "c64",
-                           net_prec: str = "bf16") -> int:
-    opts = HzOpts(m, maxit, 1e-6, HZ_C64 if krylov == "c64" else HZ_C128, PREC[net_prec], None, 0)
+                           net_prec: str = "bf16", ortho: str = "cgs2") -> int:
+    opts = HzOpts(m, maxit, 1e-6, HZ_C64 if krylov == "c64" else HZ_C128, PREC[net_prec], None, 0, ORTHO[ortho])
     return int(load_library().fgmres_workspace_size(problem.handle, net.handle if net else None, ct.byref(opts)))
