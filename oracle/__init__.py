@@ -7,6 +7,7 @@ dependency is the seeded input generator module ``synth``.
 
 Modules:
   helmholtz -- the discrete operator A = Laplacian + k^2 with PML, its adjoint, dense assembly
+  spectral  -- the Fourier-differentiation form of the same operator (the paper's discretization)
   unet      -- the U-Net neural operator, its reverse mode and the physics-informed loss
   fgmres    -- flexible GMRES with MGS Arnoldi and Givens least squares
   adam      -- the Adam update
