@@ -69,7 +69,13 @@ typedef struct {
     double omega;         /* angular frequency (> 0); the paper uses 1 */
     double sigma_max;     /* damping at the outermost node (>= 0) */
     double c_ref;         /* reference speed in m/s (> 0) */
+    int32_t disc;         /* HZ_DISC_FD (0, five-point finite differences, zero outside the grid)
+                             or HZ_DISC_SPECTRAL (1, Fourier differentiation over the periodic
+                             grid, the paper's discretization) */
 } hz_grid;
+
+#define HZ_DISC_FD       0
+#define HZ_DISC_SPECTRAL 1
 
 typedef struct hz_problem hz_problem;
 
@@ -84,8 +90,12 @@ int hz_problem_destroy(hz_problem* p);
 /* Number of grid nodes n = nx_t * ny_t and the totals nx_t, ny_t (any may be NULL). */
 int hz_problem_dims(const hz_problem* p, int64_t* n, int32_t* nx_t, int32_t* ny_t);
 
-/* y = A x (adjoint = 0) or y = A^H x (adjoint = 1), eq. (3): the five-point
- * stretched Laplacian plus k^2 with zero values outside the grid.
+/* y = A x (adjoint = 0) or y = A^H x (adjoint = 1), eq. (3). HZ_DISC_FD: the five-point
+ * stretched Laplacian plus k^2 with zero values outside the grid. HZ_DISC_SPECTRAL (Section
+ * 2.1, Table 1): A u = (1/gx) Dx((1/gx) Dx u) + (1/gy) Dy((1/gy) Dy u) + k^2 u with the periodic
+ * spectral derivatives D (Nyquist mode zeroed for an even axis) and gamma = 1 + i sigma / omega
+ * at the nodes; its setup forms the per-axis matrices (1/g) D (1/g) D once (O(N^3) work and
+ * N^2 complex entries per axis, FP64 and FP32, at problem creation).
  * x_dev, y_dev: n complex entries of type `dtype` (must not overlap). */
 int hz_op_apply(const hz_problem* p, hz_dtype dtype, int adjoint,
                 const void* x_dev, void* y_dev, void* stream);

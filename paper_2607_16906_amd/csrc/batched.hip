@@ -719,6 +719,8 @@ static int check_batch(int nsys, const hz_problem* const* probs, const no_net* n
                  "fgmres_solve_batched: bad net_prec");
     HZ_CHECK_ARG(o->ortho == 0, "fgmres_solve_batched: only ortho = 0 (CGS with one reorthogonalisation)");
     for (int s = 0; s < nsys; ++s) HZ_CHECK_ARG(probs[s], "fgmres_solve_batched: NULL problem");
+    for (int s = 0; s < nsys; ++s)
+        HZ_CHECK_ARG(!is_spectral(probs[s]), "fgmres_solve_batched: finite-difference problems only");
     return HZ_OK;
 }
 

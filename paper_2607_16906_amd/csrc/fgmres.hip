@@ -70,7 +70,7 @@ static FgmresLayout fgmres_layout(const hz_problem* p, const no_net* net, const 
     return L;
 }
 
-static int check_opts(const hz_opts* o, const no_net* net) {
+static int check_opts(const hz_opts* o, const no_net* net, const hz_problem* p) {
     HZ_CHECK_ARG(o, "fgmres: NULL options");
     HZ_CHECK_ARG(o->m >= 1 && o->m <= 4096, "fgmres: m must be in [1, 4096]");
     HZ_CHECK_ARG(o->maxit >= 1, "fgmres: maxit must be >= 1");
@@ -80,6 +80,7 @@ static int check_opts(const hz_opts* o, const no_net* net) {
                  "fgmres: bad net_prec");
     HZ_CHECK_ARG(!o->hist_host || o->hist_len >= 0, "fgmres: bad hist_len");
     HZ_CHECK_ARG(o->ortho == 0 || (o->ortho == 1 && net), "fgmres: ortho must be 0, or 1 with a network");
+    HZ_CHECK_ARG(!(o->ortho == 1 && p && is_spectral(p)), "fgmres: the spectral operator runs with ortho = 0");
     return HZ_OK;
 }
 
@@ -230,7 +231,7 @@ using namespace hz;
 
 extern "C" size_t fgmres_workspace_size(const hz_problem* p, const no_net* net, const hz_opts* o) {
     clear_error();
-    if (!p || check_opts(o, net) != HZ_OK) return 0;
+    if (!p || check_opts(o, net, p) != HZ_OK) return 0;
     return fgmres_layout(p, net, o, nullptr, 0).total;
 }
 
@@ -240,7 +241,7 @@ extern "C" int fgmres_solve(const hz_problem* p, const no_net* net, const hz_opt
                             void* x_dev, void* ws, size_t ws_bytes, hz_info* info, void* stream) {
     clear_error();
     HZ_CHECK_ARG(p && b_dev && x_dev && ws && info, "fgmres_solve: NULL argument");
-    HZ_TRY(check_opts(o, net));
+    HZ_TRY(check_opts(o, net, p));
     FgmresLayout L = fgmres_layout(p, net, o, ws, ws_bytes);
     if (L.total > ws_bytes) {
         set_error("fgmres_solve: workspace too small");

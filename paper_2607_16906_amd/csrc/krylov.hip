@@ -335,6 +335,15 @@ int launch_dots(bool c128, const void* V, int64_t ldv, int nv, const void* w, in
 
 int launch_stencil_dots(const hz_problem* p, bool c128, const void* z, const void* V, int64_t ldv, int nv,
                         void* w, Split sp, double2* part, int ldp, const int* skip, hipStream_t s, bool two) {
+    if (is_spectral(p)) {
+        // the Fourier-differentiation operator, then the Gram-Schmidt sums as a separate pass
+        if (two) {
+            set_error("fgmres: the spectral operator runs with ortho = 0");
+            return HZ_ERR_ARG;
+        }
+        HZ_TRY(launch_spectral(p, c128, false, z, w, s, skip));
+        return launch_dots(c128, V, ldv, nv, w, p->n, sp, part, ldp, true, skip, s);
+    }
     const StencilCoef sc = stencil_coef(p, c128, false);
     // the pair form needs even block starts (per_block is a multiple of the block size) and an
     // even row length

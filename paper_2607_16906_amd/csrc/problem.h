@@ -16,6 +16,11 @@ struct hz_problem {
     double2 *fE_d, *fW_d, *fN_d, *fS_d, *aE_d, *aW_d, *aN_d, *aS_d, *dx_d, *dy_d;
     float2 *fE_f, *fW_f, *fN_f, *fS_f, *aE_f, *aW_f, *aN_f, *aS_f, *dx_f, *dy_f;
     double *sigx, *sigy;  // PML damping at the nodes, [nxt], [nyt] (network input channels)
+    // HZ_DISC_SPECTRAL: per-axis derivative tables d [nxt], [nyt] and M = G D G D [nxt][nxt],
+    // [nyt][nyt] in FP64 and FP32 (NULL for finite differences)
+    double *dtx, *dty;
+    double2 *Mx_d, *My_d;
+    float2 *Mx_f, *My_f;
     void* block;          // the single device allocation holding all of the above
 };
 
@@ -39,6 +44,15 @@ int launch_stencil(const hz_problem* p, bool fp64, bool adjoint, const void* x, 
 int launch_resid64(const hz_problem* p, const double2* b, const double2* x, double2* r,
                    double* part, const int* skip, hipStream_t s);
 int stencil_blocks(const hz_problem* p);
+inline bool is_spectral(const hz_problem* p) { return p->g.disc == HZ_DISC_SPECTRAL; }
+// Fourier-differentiation operator (spectral.hip): setup at creation, y = A x / A^H x, and the FP64
+// residual r = b - A x with one ||r||^2 partial per tile (spectral_blocks of them)
+int spectral_setup(hz_problem* p, hipStream_t s);
+int spectral_blocks(const hz_problem* p);
+int launch_spectral(const hz_problem* p, bool fp64, bool adjoint, const void* x, void* y, hipStream_t s,
+                    const int* skip = nullptr);
+int launch_spectral_resid64(const hz_problem* p, const double2* b, const double2* x, double2* r, double* part,
+                            const int* skip, hipStream_t s);
 // y = b - A x in FP32 (float2 [n]) with one ||y||^2 partial (FP64) per block.
 int launch_resid32(const hz_problem* p, const float2* b, const float2* x, float2* y, double* part, hipStream_t s);
 

@@ -139,12 +139,14 @@ static dim3 stencil_grid(const hz_problem* p) {
     return dim3((p->nxt + ST_TX - 1) / ST_TX, (p->nyt + ST_TY - 1) / ST_TY);
 }
 int stencil_blocks(const hz_problem* p) {
+    if (is_spectral(p)) return spectral_blocks(p);
     dim3 g = stencil_grid(p);
     return (int)(g.x * g.y);
 }
 
 int launch_stencil(const hz_problem* p, bool fp64, bool adjoint, const void* x, void* y, hipStream_t s,
                    const int* skip) {
+    if (is_spectral(p)) return launch_spectral(p, fp64, adjoint, x, y, s, skip);
     StencilCoef c = stencil_coef(p, fp64, adjoint);
     dim3 grid = stencil_grid(p);
     if (fp64) {
@@ -171,6 +173,7 @@ int launch_stencil(const hz_problem* p, bool fp64, bool adjoint, const void* x, 
 
 int launch_resid64(const hz_problem* p, const double2* b, const double2* x, double2* r,
                    double* part, const int* skip, hipStream_t s) {
+    if (is_spectral(p)) return launch_spectral_resid64(p, b, x, r, part, skip, s);
     StencilCoef c = stencil_coef(p, true, false);
     hipLaunchKernelGGL((k_stencil<double, ST_RESID>), stencil_grid(p), dim3(ST_THREADS), 0, s,
                        x, r, b, (const double*)c.k2, (const double2*)c.E, (const double2*)c.W,
@@ -181,6 +184,10 @@ int launch_resid64(const hz_problem* p, const double2* b, const double2* x, doub
 }
 
 int launch_resid32(const hz_problem* p, const float2* b, const float2* x, float2* y, double* part, hipStream_t s) {
+    if (is_spectral(p)) {
+        set_error("the FP32 residual kernel takes the finite-difference operator only");
+        return HZ_ERR_ARG;
+    }
     StencilCoef c = stencil_coef(p, false, false);
     hipLaunchKernelGGL((k_stencil<float, ST_RESID>), stencil_grid(p), dim3(ST_THREADS), 0, s, x, y, b,
                        (const float*)c.k2, (const float2*)c.E, (const float2*)c.W, (const float2*)c.N,
@@ -202,8 +209,11 @@ extern "C" int hz_problem_create(const hz_grid* g, const float* c_dev, void* str
     HZ_CHECK_ARG(g->nx >= 1 && g->ny >= 1 && g->npml >= 0, "hz_problem_create: bad grid sizes");
     HZ_CHECK_ARG(g->h > 0 && g->omega > 0 && g->sigma_max >= 0 && g->c_ref > 0,
                  "hz_problem_create: h, omega, c_ref must be > 0 and sigma_max >= 0");
+    HZ_CHECK_ARG(g->disc == HZ_DISC_FD || g->disc == HZ_DISC_SPECTRAL, "hz_problem_create: bad disc");
     const int nxt = g->nx + 2 * g->npml, nyt = g->ny + 2 * g->npml;
     HZ_CHECK_ARG((int64_t)nxt * nyt < (int64_t)1 << 31, "hz_problem_create: grid too large");
+    HZ_CHECK_ARG(g->disc != HZ_DISC_SPECTRAL || (nxt <= 8192 && nyt <= 8192),
+                 "hz_problem_create: the spectral operator takes at most 8192 nodes per axis");
     hipStream_t s = (hipStream_t)stream;
     hz_problem* p = new hz_problem();
     p->g = *g;
@@ -226,6 +236,14 @@ extern "C" int hz_problem_create(const hz_grid* g, const float* c_dev, void* str
         for (auto q : f2) *q = c.take<float2>(nyt);
         p->sigx = c.take<double>(nxt);
         p->sigy = c.take<double>(nyt);
+        if (g->disc == HZ_DISC_SPECTRAL) {
+            p->dtx = c.take<double>(nxt);
+            p->dty = c.take<double>(nyt);
+            p->Mx_d = c.take<double2>((size_t)nxt * nxt);
+            p->My_d = c.take<double2>((size_t)nyt * nyt);
+            p->Mx_f = c.take<float2>((size_t)nxt * nxt);
+            p->My_f = c.take<float2>((size_t)nyt * nyt);
+        }
         return c.take<int>(1);
     };
     layout(cv);
@@ -250,6 +268,7 @@ extern "C" int hz_problem_create(const hz_grid* g, const float* c_dev, void* str
         hipLaunchKernelGGL(k_setup_field, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, c_dev, n,
                            g->omega, g->c_ref, p->k2f, p->k2d, p->cnd, bad);
         if (hipGetLastError() != hipSuccess) { rc = HZ_ERR_HIP; break; }
+        if (g->disc == HZ_DISC_SPECTRAL && spectral_setup(p, s) != HZ_OK) { rc = HZ_ERR_HIP; break; }
         if (hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess) { rc = HZ_ERR_HIP; break; }
         if (hipStreamSynchronize(s) != hipSuccess) { rc = HZ_ERR_HIP; break; }
     } while (0);

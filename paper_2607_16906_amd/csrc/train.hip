@@ -1153,6 +1153,7 @@ extern "C" int no_loss_backward(const no_net* net, int batch, const hz_problem* 
         HZ_CHECK_ARG(problems[b]->nxt == problems[0]->nxt && problems[b]->nyt == problems[0]->nyt &&
                          problems[b]->g.npml == problems[0]->g.npml,
                      "no_loss_backward: every problem of a batch must have the same grid and PML");
+        HZ_CHECK_ARG(!is_spectral(problems[b]), "no_loss_backward: finite-difference problems only");
     }
     hipStream_t s = (hipStream_t)stream;
     if (prec == NO_BF16)

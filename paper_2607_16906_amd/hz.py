@@ -26,7 +26,8 @@ PREC = {"bf16": NO_BF16, "fp32": NO_FP32, "fp64": NO_FP64}
 
 class HzGrid(ct.Structure):
     _fields_ = [("nx", ct.c_int32), ("ny", ct.c_int32), ("npml", ct.c_int32),
-                ("h", ct.c_double), ("omega", ct.c_double), ("sigma_max", ct.c_double), ("c_ref", ct.c_double)]
+                ("h", ct.c_double), ("omega", ct.c_double), ("sigma_max", ct.c_double), ("c_ref", ct.c_double),
+                ("disc", ct.c_int32)]
 
 
 class NoArch(ct.Structure):
@@ -129,15 +130,18 @@ def _ws(nbytes):
 class Problem:
     """One discrete Helmholtz system on the GPU (hz_problem_create)."""
 
+    DISC = {"fd": 0, "spectral": 1}
+
     def __init__(self, c, nx: int, ny: int, npml: int, h: float, omega: float = 1.0,
-                 sigma_max: float = 2.0, c_ref: float = 1500.0):
+                 sigma_max: float = 2.0, c_ref: float = 1500.0, disc: str = "fd"):
+        """disc: "fd" (five-point finite differences) or "spectral" (Fourier differentiation)."""
         torch = _torch()
         lib = load_library()
         c = torch.as_tensor(c, dtype=torch.float32).to("cuda").contiguous()
         nxt, nyt = nx + 2 * npml, ny + 2 * npml
         if c.numel() != nxt * nyt:
             raise ValueError(f"velocity has {c.numel()} entries, grid needs {nxt * nyt}")
-        self.grid = HzGrid(nx, ny, npml, h, omega, sigma_max, c_ref)
+        self.grid = HzGrid(nx, ny, npml, h, omega, sigma_max, c_ref, self.DISC[disc])
         self.c = c
         self.nx, self.ny, self.npml = nx, ny, npml
         self.nxt, self.nyt, self.n = nxt, nyt, nxt * nyt
