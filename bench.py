@@ -205,6 +205,51 @@ def bench_batched(hz, torch, net, nsys=128, maxit=30):
             "min_relres": min(i.true_relres for i in infos), "max_relres": max(i.true_relres for i in infos)}
 
 
+def bench_spectral(hz, torch, net):
+    """The paper's Fourier-differentiation operator (hz_grid.disc = spectral): one apply of A on
+    the single-solve grid (296^2) and the large grid (1088^2) in FP32 and FP64 (HIP events; the
+    kernel contracts each node's row and column with the per-axis matrices, 8 (nx + ny) FLOP per
+    node), and the BF16-network FGMRES(30) solve of the single-solve system with that operator,
+    bounded to 1000 iterations (the network was trained with the finite-difference operator and
+    does not precondition this one well)."""
+    from synth import H_10PPW, c2_system, c5_system
+    out = {"workload": "Fourier-differentiation operator: apply at 296^2 and 1088^2; FGMRES(30), BF16 U-Net, "
+                       "FP32 Krylov, tol 1e-6 on the 256^2 + 20 PML system"}
+    for name, sysf in (("296", c2_system), ("1088", c5_system)):
+        s = sysf(0)
+        gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW, disc="spectral")
+        n = s.nt * s.nt
+        flops = 8.0 * (2 * s.nt) * n
+        for dt, tag in ((torch.complex64, "fp32"), (torch.complex128, "fp64")):
+            x = torch.randn(n, dtype=dt, device="cuda")
+            for _ in range(3):
+                gp.apply(x)
+            reps = 20 if name == "296" else 5
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                y = gp.apply(x)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            out[f"apply_{name}_{tag}_us"] = round(ms * 1e3, 2)
+            out[f"apply_{name}_{tag}_tflops"] = round(flops / ms * 1e-9, 2)
+            del x, y
+        if name == "296":
+            b = torch.from_numpy(s.b.ravel()).cuda()
+            hz.fgmres(gp, b, net=net, m=M_RESTART, tol=TOL, maxit=M_RESTART)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = hz.fgmres(gp, b, net=net, m=M_RESTART, tol=TOL, maxit=1000)
+            torch.cuda.synchronize()
+            dtm = time.perf_counter() - t0
+            out["solve_296"] = {"its": info.its, "converged": info.status == 0, "true_relres": info.true_relres,
+                                "ms_per_solve": round(dtm * 1e3, 2), "solves_per_s": round(1.0 / dtm, 3),
+                                "us_per_it": round(dtm * 1e6 / max(info.its, 1), 1)}
+        del gp
+    return out
+
+
 RESTART_RUNS = [(m, "c64", "cgs2") for m in (10, 30, 50, 100, 200, 512)] + [
     (30, "c64", "dcgs2"), (100, "c64", "dcgs2"), (100, "c128", "cgs2"), (100, "c128", "dcgs2"),
     (512, "c128", "cgs2"), (512, "c128", "dcgs2")]
@@ -330,7 +375,7 @@ def main():
                     help="with --roofline-only: time this layer alone (for a profiler run of one kernel)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="with --roofline-only: also copy 512 MiB with a plain device copy (counter calibration)")
-    ap.add_argument("--only", choices=["training", "batched", "large", "restart"], default=None,
+    ap.add_argument("--only", choices=["training", "batched", "large", "restart", "spectral"], default=None,
                     help="run one extra section alone and print its JSON (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -353,7 +398,8 @@ def main():
             res = bench_training(hz, torch, steps=2)
         else:
             net1 = hz.Net(LEVELS, BASE, IN_CH, theta)
-            res = {"batched": bench_batched, "large": bench_large, "restart": bench_restart}[args.only](hz, torch, net1)
+            res = {"batched": bench_batched, "large": bench_large, "restart": bench_restart,
+                   "spectral": bench_spectral}[args.only](hz, torch, net1)
         print(json.dumps({args.only: res}))
         return
     s = c2_system(0)
@@ -459,6 +505,7 @@ def main():
         out["batched"] = bench_batched(hz, torch, net)
         out["large"] = bench_large(hz, torch, net)
         out["restart"] = bench_restart(hz, torch, net)
+        out["spectral"] = bench_spectral(hz, torch, net)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, theta, its)
     print(json.dumps(out))

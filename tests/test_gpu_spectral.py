@@ -36,7 +36,7 @@ def rand_field(shape, seed):
     return g.standard_normal(shape) + 1j * g.standard_normal(shape)
 
 
-@pytest.mark.parametrize("nt,p", [(37, 6), (48, 8), (70, 10), (33, 0)])
+@pytest.mark.parametrize("nt,p", [(37, 6), (48, 8), (70, 10), (33, 0), (520, 20)])   # 520: the 32 x 32 tiles
 @pytest.mark.parametrize("adjoint", [False, True])
 def test_spectral_apply_fp64_and_fp32(nt, p, adjoint):
     c = skull_ring_velocity(nt, p, rng_for(31, 0, nt), rings=1 + nt % 2)
