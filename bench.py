@@ -250,6 +250,37 @@ def bench_spectral(hz, torch, net):
     return out
 
 
+def bench_appendix_b(hz, torch, net, nsys=5, nx=64, npml=16):
+    """The paper's second synthetic workload at its solver settings (eta_b = 1e-12, maxit = 512
+    without restart): constant speed with one or two +-1 point sources, four aligned or faulted
+    layers with a smoothed source, at the paper's scale (64^2 interior, here with 16 PML cells
+    outside it); nsys systems per kind, FGMRES with the BF16 network and plain GMRES, FP64 Krylov
+    vectors (1e-12 is below FP32 resolution)."""
+    from synth import APPB_KINDS, H_10PPW, appendix_b_system
+    res = {"workload": f"{nsys} systems per kind, {nx}^2 + {npml} PML, m = 512 (no restart), maxit 512, "
+                       "tol 1e-12, FP64 Krylov; FGMRES with the BF16 U-Net and GMRES", "kinds": {}}
+    for kind in APPB_KINDS:
+        rows = {"fgmres_its": [], "fgmres_ms": [], "fgmres_converged": 0, "fgmres_final_relres": [],
+                "gmres_its": [], "gmres_ms": [], "gmres_converged": 0, "gmres_final_relres": []}
+        for sid in range(nsys):
+            s = appendix_b_system(kind, sid, nx=nx, npml=npml)
+            gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW)
+            b = torch.from_numpy(s.b.ravel()).cuda()
+            for tag, nn in (("fgmres", net), ("gmres", None)):
+                hz.fgmres(gp, b, net=nn, m=512, tol=1e-12, maxit=8, krylov="c128")   # graphs, tuning
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, info = hz.fgmres(gp, b, net=nn, m=512, tol=1e-12, maxit=512, krylov="c128")
+                torch.cuda.synchronize()
+                rows[f"{tag}_its"].append(info.its)
+                rows[f"{tag}_ms"].append(round((time.perf_counter() - t0) * 1e3, 1))
+                rows[f"{tag}_converged"] += int(info.status == 0)
+                rows[f"{tag}_final_relres"].append(float(f"{info.true_relres:.3e}"))
+            del gp
+        res["kinds"][kind] = rows
+    return res
+
+
 RESTART_RUNS = [(m, "c64", "cgs2") for m in (10, 30, 50, 100, 200, 512)] + [
     (30, "c64", "dcgs2"), (100, "c64", "dcgs2"), (100, "c128", "cgs2"), (100, "c128", "dcgs2"),
     (512, "c128", "cgs2"), (512, "c128", "dcgs2")]
@@ -375,7 +406,8 @@ def main():
                     help="with --roofline-only: time this layer alone (for a profiler run of one kernel)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="with --roofline-only: also copy 512 MiB with a plain device copy (counter calibration)")
-    ap.add_argument("--only", choices=["training", "batched", "large", "restart", "spectral"], default=None,
+    ap.add_argument("--only", choices=["training", "batched", "large", "restart", "spectral", "appendix_b"],
+                    default=None,
                     help="run one extra section alone and print its JSON (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -399,7 +431,7 @@ def main():
         else:
             net1 = hz.Net(LEVELS, BASE, IN_CH, theta)
             res = {"batched": bench_batched, "large": bench_large, "restart": bench_restart,
-                   "spectral": bench_spectral}[args.only](hz, torch, net1)
+                   "spectral": bench_spectral, "appendix_b": bench_appendix_b}[args.only](hz, torch, net1)
         print(json.dumps({args.only: res}))
         return
     s = c2_system(0)
@@ -506,6 +538,7 @@ def main():
         out["large"] = bench_large(hz, torch, net)
         out["restart"] = bench_restart(hz, torch, net)
         out["spectral"] = bench_spectral(hz, torch, net)
+        out["appendix_b"] = bench_appendix_b(hz, torch, net)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, theta, its)
     print(json.dumps(out))

@@ -34,6 +34,7 @@ COMP_RESIDUAL = 3
 COMP_SIZES = 4
 
 CFG_C1, CFG_C2, CFG_C3, CFG_C4, CFG_C5 = 1, 2, 3, 4, 5
+CFG_APPB = 8            # the second synthetic workload (simplified spherical-wave and seismic settings)
 
 
 def rng_for(cfg: int, comp: int, sys: int = 0) -> np.random.Generator:
@@ -101,6 +102,34 @@ def square_velocity(nt: int) -> np.ndarray:
     return c
 
 
+def layered_velocity(nt: int, rng: np.random.Generator, *, layers: int = 4, faulted: bool = False,
+                     lo: float = 1.0, hi: float = 2.0) -> np.ndarray:
+    """Aligned horizontal layers over the whole grid, each at one nondimensional speed U[lo, hi]
+    (the 4layered class of the paper's second synthetic workload); m/s.
+
+    The layer boundaries are depths j drawn without repetition from [nt/8, 7 nt/8), at least
+    nt/(4 layers) apart. faulted (4faulted): a vertical fault at column xf ~ U{nt/4 .. 3nt/4}; to
+    its right every boundary is shifted down by s ~ U{nt/16 .. nt/8} rows (clipped to the grid)."""
+    gap = max(1, nt // (4 * layers))
+    while True:
+        cuts = np.sort(rng.choice(np.arange(nt // 8, nt - nt // 8), size=layers - 1, replace=False))
+        if np.all(np.diff(np.concatenate([[0], cuts, [nt]])) >= gap):
+            break
+    vals = C_REF * rng.uniform(lo, hi, layers)
+    jj = np.arange(nt)[:, None]
+    c = np.empty((nt, nt))
+    if faulted:
+        xf = int(rng.integers(nt // 4, 3 * nt // 4 + 1))
+        sh = int(rng.integers(max(1, nt // 16), max(2, nt // 8) + 1))
+        left = np.searchsorted(cuts, np.arange(nt), side="right")
+        right = np.searchsorted(np.minimum(cuts + sh, nt), np.arange(nt), side="right")
+        c[:, :xf] = vals[left][:, None]
+        c[:, xf:] = vals[right][:, None]
+    else:
+        c[:] = vals[np.searchsorted(cuts, jj[:, 0], side="right")][:, None]
+    return c
+
+
 # --------------------------------------------------------------------------- sources
 
 def _interior_node(nt: int, npml: int, rng: np.random.Generator, margin: int = 4):
@@ -129,6 +158,20 @@ def gaussian_sources(nt: int, npml: int, rng: np.random.Generator, *, nsrc=None,
         i, j = _interior_node(nt, npml, rng)
         amp = rng.uniform(0.5, 1.5) * np.exp(1j * rng.uniform(0.0, 2 * math.pi))
         b += amp * np.exp(-((ii - i) ** 2 + (jj - j) ** 2) / (2.0 * width * width))
+    return b
+
+
+def m_dirac_source(nt: int, npml: int, rng: np.random.Generator, m: int) -> np.ndarray:
+    """m entries set to +1 or -1 (equally likely) at distinct random interior nodes at least 4
+    cells from the PML, zero elsewhere (the paper's m-dirac class). complex128 [nt, nt]."""
+    b = np.zeros((nt, nt), np.complex128)
+    placed = 0
+    while placed < m:
+        i, j = _interior_node(nt, npml, rng)
+        if b[j, i] != 0:
+            continue
+        b[j, i] = 1.0 if rng.uniform() < 0.5 else -1.0
+        placed += 1
     return b
 
 
@@ -241,6 +284,29 @@ def c5_system(sys: int = 0) -> System:
     c = skull_ring_velocity(nx + 2 * p, p, rv, rings=rings)
     b = gaussian_sources(nx + 2 * p, p, rng_for(CFG_C5, COMP_SOURCE, sys))
     return System(nx, p, c, b)
+
+
+APPB_KINDS = ("gamma_dirac", "gamma_2dirac", "4layered", "4faulted")
+
+
+def appendix_b_system(kind: str, sys: int = 0, nx: int = 256, npml: int = 20) -> System:
+    """The paper's second synthetic workload (simplified spherical-wave and seismic settings):
+    gamma_dirac / gamma_2dirac: one constant speed U[1, 2] (nondimensional) with 1 or 2 entries
+    of +-1; 4layered / 4faulted: four aligned (or faulted) constant layers U[1, 2] with one
+    smoothed unit point source (Gaussian, width 1.5 cells)."""
+    nt = nx + 2 * npml
+    k = APPB_KINDS.index(kind)
+    rv = rng_for(CFG_APPB, COMP_VELOCITY, 100 * k + sys)
+    rs = rng_for(CFG_APPB, COMP_SOURCE, 100 * k + sys)
+    if kind in ("gamma_dirac", "gamma_2dirac"):
+        c = rand_constant_velocity(nt, rv)
+        b = m_dirac_source(nt, npml, rs, 1 if kind == "gamma_dirac" else 2)
+    else:
+        c = layered_velocity(nt, rv, layers=4, faulted=kind == "4faulted")
+        i, j = _interior_node(nt, npml, rs)
+        jj, ii = np.meshgrid(np.arange(nt, dtype=np.float64), np.arange(nt, dtype=np.float64), indexing="ij")
+        b = np.exp(-((ii - i) ** 2 + (jj - j) ** 2) / (2.0 * 1.5 * 1.5)).astype(np.complex128)
+    return System(nx, npml, c, b)
 
 
 def c3_batch(batch: int = 64, nx: int = 128, npml: int = 16, step: int = 0):

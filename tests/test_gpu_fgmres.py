@@ -156,6 +156,31 @@ def test_dcgs2_cycle_boundaries_match_oracle(m, maxit):
     assert rel(to_np(x), ref.x) <= 1e-9
 
 
+@pytest.mark.skipif(not os.path.exists(WEIGHTS), reason="trained weights missing")
+@pytest.mark.parametrize("kind", ["gamma_dirac", "gamma_2dirac", "4layered", "4faulted"])
+def test_appendix_b_workload_fp64_matches_oracle(kind):
+    # the second synthetic workload (constant speed with +-1 point sources, aligned and faulted
+    # layers with a smoothed source): FP64 FGMRES with the trained network, one long cycle, against
+    # the oracle's history
+    from paper_2607_16906_amd import hz
+    from synth import appendix_b_system
+    s = appendix_b_system(kind, 0, nx=20, npml=5)
+    op, gp = make_pair(s.c, s.npml)
+    specs = unet.layer_specs(4, 32, 5)
+    theta = np.load(WEIGHTS)["theta"].astype(np.float32)
+    net = hz.Net(4, 32, 5, theta)
+    M = lambda v: unet.precond_apply(theta.astype(np.float64), specs, op, v.reshape(op.ny, op.nx)).ravel()
+    b = s.b.ravel()
+    ref = ofg.fgmres(oracle_A(op), M, b, m=200, tol=1e-10, maxit=200)
+    x, info = hz.fgmres(gp, to_dev(b, torch.complex128), net=net, m=200, tol=1e-10, maxit=200,
+                        krylov="c128", net_prec="fp64")
+    assert info.its == ref.its and info.status == ref.status
+    h = np.array(ref.est_history)
+    d = np.abs(info.hist - h)
+    assert np.all(d <= 1e-10 * h + 1e-14), float(np.max(d / (1e-10 * h + 1e-14)))
+    assert rel(to_np(x), ref.x) <= 1e-8
+
+
 def test_dcgs2_needs_a_network():
     from paper_2607_16906_amd import hz
     c, b, p = small_system(nx=12, p=4, seed=5)
