@@ -177,6 +177,40 @@ def bench_training(hz, torch, steps=3, batch=64):
             "loss_last": float(losses[-1].item())}
 
 
+def bench_training_loop(hz, torch, S=1024, V=128, batch=32, epochs=2, nint=64, npml=16):
+    """Epoch-based training (Section 3.4): a fixed D0-like set of S samples and V validation
+    samples on the paper's training grid (64^2, here with 16 PML cells outside it), batch 32, Adam
+    with clipping at 1, cosine schedule 1e-3 -> 1e-5 over the epochs, validation and best-epoch
+    selection after each epoch; from the seeded initial weights. One untimed epoch first (it
+    tunes the launch variants at this batch), then `epochs` timed epochs per precision."""
+    from synth import CFG_C3, COMP_WEIGHTS, H_10PPW, VAL_FIRST, epoch_order, he_uniform, rng_for, training_set
+    from paper_2607_16906_amd.train import Trainer, resident_set
+    nt = nint + 2 * npml
+    theta = he_uniform(hz.init_shapes(LEVELS, BASE, IN_CH), rng_for(CFG_C3, COMP_WEIGHTS, 0))
+    c, b = training_set(S, nt, npml)
+    vc, vb = training_set(V, nt, npml, first=VAL_FIRST)
+    probs, r = resident_set(c, b, nint, npml, H_10PPW)
+    vprobs, vr = resident_set(vc, vb, nint, npml, H_10PPW)
+    out = {"workload": f"{S} training + {V} validation samples of the D0-like mixture, {nint}^2 + {npml} PML, "
+                       f"batch {batch}, 4-level/32-ch U-Net, Adam, clip 1, cosine 1e-3 -> 1e-5, "
+                       f"{epochs} timed epochs"}
+    for prec in ("bf16", "fp32"):
+        net = hz.Net(LEVELS, BASE, IN_CH, theta)
+        tr = Trainer(net, probs, r, vprobs, vr, batch=batch, prec=prec)
+        tr.fit(theta, [epoch_order(S, 0)])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = tr.fit(theta, [epoch_order(S, e) for e in range(epochs)])
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / epochs
+        out[prec] = {"s_per_epoch": round(wall, 3), "train_samples_per_s": round(S / (res.step_ms * 1e-3 *
+                                                                                     ((S + batch - 1) // batch)), 1),
+                     "ms_per_step": round(res.step_ms, 2), "ms_validation": round(res.val_ms, 2),
+                     "val_loss": [round(x, 5) for x in res.val_loss], "best_epoch": res.best_epoch}
+        del tr, net
+    return out
+
+
 def bench_batched(hz, torch, net, nsys=128, maxit=30):
     """Ragged batch: the 128 systems of the batched-serving mix (128..512 interior + 16..32 PML, each
     with its own velocity and sources), BF16 network, FGMRES(30), advanced together for one cycle
@@ -406,7 +440,8 @@ def main():
                     help="with --roofline-only: time this layer alone (for a profiler run of one kernel)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="with --roofline-only: also copy 512 MiB with a plain device copy (counter calibration)")
-    ap.add_argument("--only", choices=["training", "batched", "large", "restart", "spectral", "appendix_b"],
+    ap.add_argument("--only", choices=["training", "training_loop", "batched", "large", "restart", "spectral",
+                                       "appendix_b"],
                     default=None,
                     help="run one extra section alone and print its JSON (for profiler runs)")
     args = ap.parse_args()
@@ -428,6 +463,8 @@ def main():
     if args.only:
         if args.only == "training":
             res = bench_training(hz, torch, steps=2)
+        elif args.only == "training_loop":
+            res = bench_training_loop(hz, torch)
         else:
             net1 = hz.Net(LEVELS, BASE, IN_CH, theta)
             res = {"batched": bench_batched, "large": bench_large, "restart": bench_restart,
@@ -534,6 +571,7 @@ def main():
     }
     if not args.no_extra:
         out["training"] = bench_training(hz, torch)
+        out["training_loop"] = bench_training_loop(hz, torch)
         out["batched"] = bench_batched(hz, torch, net)
         out["large"] = bench_large(hz, torch, net)
         out["restart"] = bench_restart(hz, torch, net)

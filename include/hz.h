@@ -201,7 +201,8 @@ size_t no_train_workspace_size(const no_net* net, const hz_problem* p, int batch
  * ||q_b||^2 / ||r_b||^2); loss = mean_b l_b. Reverse mode through A^H and the
  * U-Net. problems: `batch` handles of one grid size; r_dev: [batch][n] complex64;
  * loss_dev: 1 float (written); per_sample_dev: `batch` floats or NULL;
- * grad_dev: no_param_count floats (overwritten with d loss / d theta).
+ * grad_dev: no_param_count floats (overwritten with d loss / d theta), or NULL to evaluate the
+ * loss alone (a validation pass: the forward pass and the residuals, no reverse pass).
  * prec: NO_BF16 (BF16 operands, FP32 accumulation) or NO_FP32. recompute != 0 checkpoints
  * activations for large grids: the forward pass keeps only each level's outputs (and pooled
  * inputs), and the first-convolution and upsampled tensors of a level are recomputed with the

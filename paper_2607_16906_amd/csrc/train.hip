@@ -997,11 +997,15 @@ static int loss_backward_impl(const no_net* net, int B, const hz_problem* const*
         hipLaunchKernelGGL(k_resid_batched, g, dim3(ST_THREADS), 0, s, t.z, r, t.y, n, t.sprob, p0->nxt, p0->nyt,
                            t.ypart);
         HZ_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_adjoint_batched, g, dim3(ST_THREADS), 0, s, t.y, t.gz, n, t.sprob, p0->nxt, p0->nyt);
-        HZ_LAUNCH_CHECK();
+        if (grad) {
+            hipLaunchKernelGGL(k_adjoint_batched, g, dim3(ST_THREADS), 0, s, t.y, t.gz, n, t.sprob, p0->nxt,
+                               p0->nyt);
+            HZ_LAUNCH_CHECK();
+        }
     }
     hipLaunchKernelGGL(k_loss, dim3(1), dim3(1024), 0, s, t.ypart, nst, t.nr, B, squared, t.coef, loss, per_sample);
     HZ_LAUNCH_CHECK();
+    if (!grad) return HZ_OK;  // loss only (validation): no reverse pass
 
     // ---- head
     {
@@ -1145,7 +1149,7 @@ extern "C" int no_loss_backward(const no_net* net, int batch, const hz_problem* 
                                 int squared, int recompute, no_prec prec, float* loss, float* per_sample, float* grad,
                                 void* ws, size_t ws_bytes, void* stream) {
     clear_error();
-    HZ_CHECK_ARG(net && problems && r && loss && grad && ws, "no_loss_backward: NULL argument");
+    HZ_CHECK_ARG(net && problems && r && loss && ws, "no_loss_backward: NULL argument");
     HZ_CHECK_ARG(batch >= 1 && batch <= 1024, "no_loss_backward: batch must be in [1, 1024]");
     HZ_CHECK_ARG(prec == NO_BF16 || prec == NO_FP32, "no_loss_backward: precision must be NO_BF16 or NO_FP32");
     for (int b = 0; b < batch; ++b) {

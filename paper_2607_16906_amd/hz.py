@@ -274,11 +274,12 @@ def param_count(levels: int, base: int, in_ch: int) -> int:
 
 
 def loss_backward(net: Net, problems, r, *, squared: bool = False, prec: str = "bf16", workspace=None,
-                  recompute: bool = False):
+                  recompute: bool = False, need_grad: bool = True):
     """Physics-informed loss and its parameter gradient (no_loss_backward).
 
     problems: list of B Problems of one grid size; r: [B, n] complex64 device tensor.
     recompute: checkpoint activations (smaller workspace, bit-identical results).
+    need_grad: False evaluates the loss alone (no reverse pass; grad is None).
     Returns (loss [1] float32, per-sample losses [B] float32, grad [nparam] float32).
     """
     torch = _torch()
@@ -292,9 +293,10 @@ def loss_backward(net: Net, problems, r, *, squared: bool = False, prec: str = "
     ws = workspace if workspace is not None and workspace.numel() >= nb else _ws(nb)
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
     per = torch.empty(B, dtype=torch.float32, device="cuda")
-    grad = torch.empty(net.nparam, dtype=torch.float32, device="cuda")
+    grad = torch.empty(net.nparam, dtype=torch.float32, device="cuda") if need_grad else None
     _check(lib.no_loss_backward(net.handle, B, ptrs, _ptr(r), int(squared), int(recompute), PREC[prec],
-                                _ptr(loss), _ptr(per), _ptr(grad), _ptr(ws), ct.c_size_t(ws.numel()), _stream()),
+                                _ptr(loss), _ptr(per), _ptr(grad) if need_grad else None, _ptr(ws),
+                                ct.c_size_t(ws.numel()), _stream()),
            "no_loss_backward")
     return loss, per, grad
 

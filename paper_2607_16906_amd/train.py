@@ -1,0 +1,167 @@
+"""Epoch-based training of the neural operator on the GPU (Section 3.4, Tables 3 and 5).
+
+Host orchestration over the library's entry points: every step of a batch runs in the library
+(no_loss_backward for the loss of eq. (12) and its gradient, no_adam_step for the clipped Adam
+update); this module only chooses the batches, the learning rate of each epoch and the saved
+epoch. The data set stays resident on the device for the whole run: one problem handle per
+sample and the residuals as one [S, n] complex64 tensor, gathered per batch in the epoch's order.
+
+Schedule and selection (the paper gives the end points and the saved-epoch rule only):
+* the learning rate is constant within an epoch and follows a cosine in the epoch index from
+  lr0 (first epoch) to lr_min (last epoch), 1e-3 and 1e-5 by default (Table 3);
+* each epoch visits the training set once, in the order given for it, in batches of ``batch``
+  samples (the last batch is shorter when ``batch`` does not divide the set);
+* Adam's step counter runs over all batches; the gradient is clipped to global L2 norm ``clip``;
+* after each epoch the validation loss (the mean per-sample loss over the validation set, a
+  forward-only pass) is computed, and the parameters of the first epoch with the lowest
+  validation loss are kept (Table 5 lists the saved epoch and its validation loss).
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import hz
+
+
+def cosine_lr(epoch: int, epochs: int, lr0: float = 1e-3, lr_min: float = 1e-5) -> float:
+    """Learning rate of epoch ``epoch`` (0-based) of ``epochs``."""
+    if epochs <= 1:
+        return lr0
+    return lr_min + 0.5 * (lr0 - lr_min) * (1.0 + math.cos(math.pi * epoch / (epochs - 1)))
+
+
+@dataclass
+class FitResult:
+    theta_best: object                               # device float32 [nparam]
+    best_epoch: int
+    best_val: float
+    theta_last: object                               # device float32 [nparam]
+    train_loss: np.ndarray = None                    # batch-mean loss of every step
+    val_loss: list = field(default_factory=list)     # validation loss after every epoch
+    lr: list = field(default_factory=list)           # learning rate of every epoch
+    step_ms: float = 0.0                             # mean wall time of a training step
+    val_ms: float = 0.0                              # mean wall time of a validation pass
+
+
+class Trainer:
+    """Runs epochs of training for one network on one resident data set.
+
+    net: hz.Net; problems / val_problems: hz.Problem lists of one grid size;
+    r / val_r: [S, n] / [V, n] complex64 device tensors (the sources, used as residuals).
+    """
+
+    def __init__(self, net: hz.Net, problems, r, val_problems, val_r, *, batch: int = 32,
+                 prec: str = "bf16", squared: bool = False, recompute: bool = False):
+        torch = hz._torch()
+        self.lib = hz.load_library()
+        self.net, self.batch, self.prec = net, int(batch), prec
+        self.squared, self.recompute = int(squared), int(recompute)
+        self.problems, self.val_problems = list(problems), list(val_problems)
+        S, V = len(self.problems), len(self.val_problems)
+        if S < 1 or V < 1 or self.batch < 1:
+            raise ValueError("need at least one training sample, one validation sample and batch >= 1")
+        p0 = self.problems[0]
+        for p in self.problems + self.val_problems:
+            if (p.nxt, p.nyt, p.npml) != (p0.nxt, p0.nyt, p0.npml):
+                raise ValueError("every sample must have the same grid and PML")
+        self.n = p0.n
+        if tuple(r.shape) != (S, self.n) or tuple(val_r.shape) != (V, self.n):
+            raise ValueError("r must be [S, n] and val_r [V, n]")
+        if r.dtype != torch.complex64 or val_r.dtype != torch.complex64 or not r.is_cuda or not val_r.is_cuda:
+            raise ValueError("r and val_r must be complex64 device tensors")
+        self.r, self.val_r = r.contiguous(), val_r.contiguous()
+        self.handles = np.array([p.handle.value for p in self.problems], dtype=np.uint64)
+        self.val_handles = np.array([p.handle.value for p in self.val_problems], dtype=np.uint64)
+        # workspace for the largest batch (the training workspace grows with the batch)
+        nb = max(self.lib.no_train_workspace_size(net.handle, p0.handle, b, hz.PREC[prec], self.recompute)
+                 for b in {min(self.batch, S), min(self.batch, V)})
+        self.ws = hz._ws(nb)
+        self.aws = hz._ws(self.lib.no_adam_workspace_size(net.handle))
+        self.grad = torch.empty(net.nparam, dtype=torch.float32, device="cuda")
+        self.rb = torch.empty((min(self.batch, S), self.n), dtype=torch.complex64, device="cuda")
+        self.per = torch.empty(max(min(self.batch, S), V), dtype=torch.float32, device="cuda")
+        self.vloss = torch.empty(1, dtype=torch.float32, device="cuda")
+
+    def _loss(self, handles, rptr, bsz, loss_ptr, per_ptr, grad):
+        ptrs = (ct.c_void_p * bsz)(*[int(h) for h in handles])
+        hz._check(self.lib.no_loss_backward(self.net.handle, bsz, ptrs, ct.c_void_p(rptr), self.squared,
+                                            self.recompute, hz.PREC[self.prec], ct.c_void_p(loss_ptr),
+                                            ct.c_void_p(per_ptr), hz._ptr(grad) if grad is not None else None,
+                                            hz._ptr(self.ws), ct.c_size_t(self.ws.numel()), hz._stream()),
+                  "no_loss_backward")
+
+    def validation_loss(self) -> float:
+        """Mean per-sample loss over the validation set at the network's current weights."""
+        V = len(self.val_problems)
+        for i in range(0, V, self.batch):
+            bsz = min(self.batch, V - i)
+            self._loss(self.val_handles[i:i + bsz], self.val_r.data_ptr() + 8 * self.n * i, bsz,
+                       self.vloss.data_ptr(), self.per.data_ptr() + 4 * i, None)
+        per = self.per[:V].cpu().numpy().astype(np.float64)    # synchronises the stream
+        return float(per.sum() / V)
+
+    def fit(self, theta0, orders, *, lr0: float = 1e-3, lr_min: float = 1e-5, clip: float = 1.0,
+            beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, log=None) -> FitResult:
+        """Train for len(orders) epochs from theta0 (orders[e]: the visiting order of epoch e)."""
+        import time
+        torch = hz._torch()
+        S, E = len(self.problems), len(orders)
+        theta = torch.as_tensor(theta0, dtype=torch.float32).to("cuda").clone().contiguous()
+        if theta.numel() != self.net.nparam:
+            raise ValueError("theta0 does not match the network")
+        m = torch.zeros_like(theta)
+        v = torch.zeros_like(theta)
+        self.net.set_weights(theta)
+        steps_per_epoch = (S + self.batch - 1) // self.batch
+        losses = torch.empty(E * steps_per_epoch, dtype=torch.float32, device="cuda")
+        res = FitResult(theta.clone(), -1, math.inf, theta)
+        t, tstep, tval = 0, 0.0, 0.0
+        for e in range(E):
+            order = np.asarray(orders[e], dtype=np.int64)
+            if order.shape != (S,) or not np.array_equal(np.sort(order), np.arange(S)):
+                raise ValueError(f"orders[{e}] is not a permutation of the training set")
+            lr = cosine_lr(e, E, lr0, lr_min)
+            res.lr.append(lr)
+            idx = torch.from_numpy(order).to("cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(0, S, self.batch):
+                bsz = min(self.batch, S - i)
+                torch.index_select(self.r, 0, idx[i:i + bsz], out=self.rb[:bsz])
+                self._loss(self.handles[order[i:i + bsz]], self.rb.data_ptr(), bsz,
+                           losses.data_ptr() + 4 * t, self.per.data_ptr(), self.grad)
+                t += 1
+                hz._check(self.lib.no_adam_step(self.net.handle, hz._ptr(theta), hz._ptr(m), hz._ptr(v),
+                                                hz._ptr(self.grad), t, lr, beta1, beta2, eps, clip,
+                                                hz._ptr(self.aws), ct.c_size_t(self.aws.numel()), hz._stream()),
+                          "no_adam_step")
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            vl = self.validation_loss()
+            tval += time.perf_counter() - t1
+            tstep += t1 - t0
+            res.val_loss.append(vl)
+            if vl < res.best_val:
+                res.best_val, res.best_epoch = vl, e
+                res.theta_best.copy_(theta)
+            if log:
+                tl = losses[t - steps_per_epoch:t].cpu().numpy().astype(np.float64).mean()
+                log(f"epoch {e} lr {lr:.2e} train {tl:.4f} val {vl:.4f}")
+        res.theta_last = theta
+        res.train_loss = losses[:t].cpu().numpy().astype(np.float64)
+        res.step_ms = 1e3 * tstep / max(t, 1)
+        res.val_ms = 1e3 * tval / max(E, 1)
+        return res
+
+
+def resident_set(c, b, nint: int, npml: int, h: float):
+    """Upload a data set: velocities c [S, nt, nt] (m/s) and sources b [S, nt, nt] (complex) to one
+    hz.Problem per sample and one [S, n] complex64 device tensor."""
+    torch = hz._torch()
+    probs = [hz.Problem(ci.astype(np.float32).ravel(), nint, nint, npml, h) for ci in c]
+    r = torch.from_numpy(np.ascontiguousarray(b.reshape(len(b), -1)).astype(np.complex64)).to("cuda")
+    return probs, r

@@ -32,9 +32,12 @@ COMP_SOURCE = 1
 COMP_WEIGHTS = 2
 COMP_RESIDUAL = 3
 COMP_SIZES = 4
+COMP_ORDER = 7          # the per-epoch visiting order of a fixed training set
 
 CFG_C1, CFG_C2, CFG_C3, CFG_C4, CFG_C5 = 1, 2, 3, 4, 5
 CFG_APPB = 8            # the second synthetic workload (simplified spherical-wave and seismic settings)
+CFG_TRAIN = 9           # epoch-based training on a fixed data set (Section 3.4)
+VAL_FIRST = 10_000_000  # first stream index of validation samples (disjoint from training ones)
 
 
 def rng_for(cfg: int, comp: int, sys: int = 0) -> np.random.Generator:
@@ -347,3 +350,21 @@ def mixed_training_sample(nt: int, npml: int, rng: np.random.Generator):
     else:
         b = gaussian_sources(nt, npml, rng)
     return c, b
+
+
+def training_set(count: int, nt: int, npml: int, *, first: int = 0):
+    """A fixed data set of ``count`` (velocity, source) pairs from the D0-like mixture on one
+    nt x nt grid (Section 3.4 trains on a fixed set of random samples per data set); sample i draws
+    from stream ``first + i``. Validation sets use ``first = VAL_FIRST``.
+    Returns (c [count, nt, nt] float64 in m/s, b [count, nt, nt] complex128)."""
+    cs = np.empty((count, nt, nt), np.float64)
+    bs = np.empty((count, nt, nt), np.complex128)
+    for i in range(count):
+        cs[i], bs[i] = mixed_training_sample(nt, npml, rng_for(CFG_TRAIN, COMP_SOURCE, first + i))
+    return cs, bs
+
+
+def epoch_order(count: int, epoch: int) -> np.ndarray:
+    """The order in which epoch ``epoch`` visits a training set of ``count`` samples (a seeded
+    permutation, drawn here so that the oracle and the GPU loop visit the same batches)."""
+    return rng_for(CFG_TRAIN, COMP_ORDER, epoch).permutation(count)
