@@ -102,15 +102,25 @@ int hz_op_apply(const hz_problem* p, hz_dtype dtype, int adjoint,
 
 /* --------------------------------------------------------- neural operator */
 
-/* U-Net of Section 3.1 with `levels` resolution levels (levels - 1 average
- * poolings), base channels doubling per level, 3x3 convolutions with ReLU,
- * 2x2 stride-2 transposed convolutions on the way up, skip connections by
- * concatenation and a 1x1 head with 2 outputs (Re, Im). in_ch = 2 takes the
- * (scaled) Re/Im of the field; in_ch = 5 adds c / c_ref, sigma_x, sigma_y. */
+/* Two U-Net layer sets (Section 3.1), chosen by `kind`:
+ * NO_ARCH_UNET3 (0): `levels` resolution levels (levels - 1 average poolings),
+ *   base channels doubling per level, 3x3 convolutions with ReLU, 2x2 stride-2
+ *   transposed convolutions on the way up, skip connections by concatenation.
+ * NO_ARCH_PAPER8 (1): Table 2's layers: `levels` = depth 8x8 stride-2 padding-3
+ *   convolutions down and as many transposed ones up, `base` channels in every
+ *   layer, PReLU (one slope per layer), batch normalisation folded into the
+ *   convolutions; the decoder concatenates the encoder output of its input size
+ *   (encoder part first). Inference only (no_loss_backward, the batched solver,
+ *   no_layer_forward and the launch-variant calls reject it).
+ * Both end in a 1x1 head with 2 outputs (Re, Im). in_ch = 2 takes the (scaled)
+ * Re/Im of the field; in_ch = 5 adds c / c_ref, sigma_x, sigma_y. */
+#define NO_ARCH_UNET3  0
+#define NO_ARCH_PAPER8 1
 typedef struct {
-    int32_t levels;   /* 1..6 */
-    int32_t base;     /* base channels, a multiple of 8 */
+    int32_t levels;   /* UNET3: 1..6; PAPER8: depth 1..5 */
+    int32_t base;     /* UNET3: base channels, a multiple of 8; PAPER8: 32 */
     int32_t in_ch;    /* 2 or 5 */
+    int32_t kind;     /* NO_ARCH_UNET3 (0, also what a zero-initialised struct gives) or NO_ARCH_PAPER8 */
 } no_arch;
 
 typedef struct no_net no_net;
@@ -119,7 +129,9 @@ typedef struct no_net no_net;
  * order enc0a, enc0b, enc1a, ..., then up(L-2), dec(L-2)a, dec(L-2)b, ..., up0,
  * dec0a, dec0b, head, the weight ([out][in][3][3] for 3x3 convolutions,
  * [in][out][2][2] for transposed convolutions, [out][in][1][1] for the head)
- * followed by its bias. */
+ * followed by its bias. PAPER8: down1..down(L), up(L-1), up(L-2), ..., up0, head,
+ * each as its weight ([out][in][8][8] down, [in][out][8][8] up, [out][in][1][1]
+ * head), its bias and (down, up) its PReLU slope; -1 for an unsupported arch. */
 int64_t no_param_count(const no_arch* arch);
 
 /* Create a network and load theta_dev (float32, no_param_count entries); the

@@ -718,6 +718,7 @@ static int check_batch(int nsys, const hz_problem* const* probs, const no_net* n
     HZ_CHECK_ARG(!net || o->net_prec == NO_BF16 || o->net_prec == NO_FP32 || o->net_prec == NO_FP64,
                  "fgmres_solve_batched: bad net_prec");
     HZ_CHECK_ARG(o->ortho == 0, "fgmres_solve_batched: only ortho = 0 (CGS with one reorthogonalisation)");
+    HZ_CHECK_ARG(!net || net->a.kind == NO_ARCH_UNET3, "fgmres_solve_batched: the UNET3 network only");
     for (int s = 0; s < nsys; ++s) HZ_CHECK_ARG(probs[s], "fgmres_solve_batched: NULL problem");
     for (int s = 0; s < nsys; ++s)
         HZ_CHECK_ARG(!is_spectral(probs[s]), "fgmres_solve_batched: finite-difference problems only");

@@ -12,7 +12,8 @@
 
 namespace hz {
 
-enum LayerKind { L_CONV3 = 0, L_CONVT2 = 1, L_CONV1 = 2 };
+// L_DOWN8 / L_UP8: the 8x8 stride-2 layers of the paper's own network (NO_ARCH_PAPER8)
+enum LayerKind { L_CONV3 = 0, L_CONVT2 = 1, L_CONV1 = 2, L_DOWN8 = 3, L_UP8 = 4 };
 
 struct Layer {
     int kind;
@@ -23,6 +24,7 @@ struct Layer {
     int64_t pk_off;         // offset of the repacked weights (elements) in the packed buffers
     int64_t pk_len;         // repacked weight elements
     int64_t bias_off;       // offset of the bias in the packed bias buffers
+    int64_t a_off = -1;     // PReLU slope in the flat vector (L_DOWN8 / L_UP8; stored at bias[cout_p])
 };
 
 }  // namespace hz

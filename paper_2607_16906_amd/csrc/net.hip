@@ -20,8 +20,14 @@
 namespace hz {
 
 static bool build_layers(const no_arch* a, std::vector<Layer>& L, int64_t& nparam, int64_t& pk, int64_t& nb) {
-    if (!a || a->levels < 1 || a->levels > 6 || a->base < 8 || a->base % 8 || (a->in_ch != 2 && a->in_ch != 5))
+    if (!a || (a->in_ch != 2 && a->in_ch != 5)) return false;
+    if (a->kind == NO_ARCH_UNET3) {
+        if (a->levels < 1 || a->levels > 6 || a->base < 8 || a->base % 8) return false;
+    } else if (a->kind == NO_ARCH_PAPER8) {
+        if (a->levels < 1 || a->levels > 5 || a->base != 32) return false;
+    } else {
         return false;
+    }
     L.clear();
     nparam = pk = nb = 0;
     auto add = [&](int kind, int cin, int cout, int cin_p, int cout_p, int cat_c = 0, int cat_cp = 0) {
@@ -33,19 +39,32 @@ static bool build_layers(const no_arch* a, std::vector<Layer>& L, int64_t& npara
         y.cout = cout;
         y.cin_p = cin_p;
         y.cout_p = cout_p;
-        const int taps = kind == L_CONV3 ? 9 : (kind == L_CONVT2 ? 4 : 1);
+        const bool k8 = kind == L_DOWN8 || kind == L_UP8;
+        const int taps = kind == L_CONV3 ? 9 : (kind == L_CONVT2 ? 4 : (k8 ? 64 : 1));
         y.w_off = nparam;
         nparam += (int64_t)taps * cin * cout;
         y.b_off = nparam;
         nparam += cout;
+        if (k8) y.a_off = nparam++;   // PReLU slope
         y.pk_off = pk;
         y.pk_len = (int64_t)taps * cout_p * cin_p;
         pk += (y.pk_len + 63) / 64 * 64;
         y.bias_off = nb;
-        nb += (cout_p + 63) / 64 * 64;
+        nb += (cout_p + (k8 ? 1 : 0) + 63) / 64 * 64;
         L.push_back(y);
     };
     const int lv = a->levels;
+    if (a->kind == NO_ARCH_PAPER8) {
+        // Table 2's layers: lv stride-2 8x8 convolutions down, lv transposed ones up (the decoder
+        // input concatenates the encoder output of that size, encoder part first), 1x1 head
+        const int c = a->base;
+        add(L_DOWN8, a->in_ch, c, 8, c);
+        for (int l = 1; l < lv; ++l) add(L_DOWN8, c, c, c, c);
+        add(L_UP8, c, c, c, c);
+        for (int l = lv - 2; l >= 0; --l) add(L_UP8, 2 * c, c, 2 * c, c, c, c);
+        add(L_CONV1, c, 2, c, 16);
+        return true;
+    }
     int cin = a->in_ch, cin_p = 8;
     for (int l = 0; l < lv; ++l) {
         const int c = a->base << l, cp = round16(c);
@@ -96,13 +115,17 @@ __global__ void k_repack(const float* __restrict__ theta, Layer ly, bf16_t* __re
                 v = theta[ly.w_off + ((int64_t)co * ly.cin + ci) * 9 + tap];
             else if (ly.kind == L_CONVT2)  // [cin][cout][2][2]
                 v = theta[ly.w_off + ((int64_t)ci * ly.cout + co) * 4 + tap];
+            else if (ly.kind == L_DOWN8)   // [cout][cin][8][8]
+                v = theta[ly.w_off + ((int64_t)co * ly.cin + ci) * 64 + tap];
+            else if (ly.kind == L_UP8)     // [cin][cout][8][8]
+                v = theta[ly.w_off + ((int64_t)ci * ly.cout + co) * 64 + tap];
             else                           // [cout][cin][1][1]
                 v = theta[ly.w_off + (int64_t)co * ly.cin + ci];
         }
         wb[ly.pk_off + idx] = f2bf(v);
         wf[ly.pk_off + idx] = v;
         wd[ly.pk_off + idx] = (double)v;
-        if (ly.kind != L_CONV1) {
+        if (ly.kind == L_CONV3 || ly.kind == L_CONVT2) {
             const int tt = ly.kind == L_CONV3 ? 8 - tap : tap;
             const int64_t j = ((int64_t)tt * ly.cin_p + cis) * ly.cout_p + co;
             tb[ly.pk_off + j] = f2bf(v);
@@ -114,6 +137,10 @@ __global__ void k_repack(const float* __restrict__ theta, Layer ly, bf16_t* __re
         const float b = idx < ly.cout ? theta[ly.b_off + idx] : 0.0f;
         bf[ly.bias_off + idx] = b;
         bd[ly.bias_off + idx] = (double)b;
+    }
+    if (idx == 0 && ly.a_off >= 0) {   // PReLU slope after the bias
+        bf[ly.bias_off + ly.cout_p] = theta[ly.a_off];
+        bd[ly.bias_off + ly.cout_p] = (double)theta[ly.a_off];
     }
 }
 
@@ -130,7 +157,8 @@ static int repack_all(no_net* net, const float* theta, hipStream_t s) {
 int net_level_count(const no_net* net) { return net->a.levels; }
 
 void net_padded_dims(const no_net* net, const hz_problem* p, int* Hp, int* Wp) {
-    const int m = 1 << (net->a.levels - 1);
+    // UNET3: levels - 1 halvings; PAPER8: levels halvings
+    const int m = 1 << (net->a.kind == NO_ARCH_PAPER8 ? net->a.levels : net->a.levels - 1);
     *Hp = (p->nyt + m - 1) / m * m;
     *Wp = (p->nxt + m - 1) / m * m;
 }
@@ -211,6 +239,20 @@ static int precond_impl(const no_net* net, const hz_problem* p, bool c128, const
                            nparts ? nparts->ldp : 0);
     HZ_LAUNCH_CHECK();
     const Layer& lh = net->layers.back();
+    if (net->a.kind == NO_ARCH_PAPER8) {
+        HZ_TRY(paper8_body<P>(net, b, Hp, Wp, 1, skip, s));
+        const unsigned gh = (unsigned)((n + 255) / 256);
+        if (c128)
+            hipLaunchKernelGGL((k_head<P, double2>), dim3(gh), dim3(256), 0, s, (const T*)b.U[0], lh.cin_p,
+                               packed_w<P>(net, lh), packed_b<P>(net, lh), scp, p->nxt, p->nyt, Wp, (double2*)z, skip,
+                               fixed_s);
+        else
+            hipLaunchKernelGGL((k_head<P, float2>), dim3(gh), dim3(256), 0, s, (const T*)b.U[0], lh.cin_p,
+                               packed_w<P>(net, lh), packed_b<P>(net, lh), scp, p->nxt, p->nyt, Wp, (float2*)z, skip,
+                               fixed_s);
+        HZ_LAUNCH_CHECK();
+        return HZ_OK;
+    }
     if (lh.cin_p == 16 || lh.cin_p == 32 || lh.cin_p == 64) {
         // the head runs in the epilogue of the last 3x3 layer
         Conv3Out hd;
@@ -401,6 +443,7 @@ static int autotune_impl(const no_net* net, int Hp, int Wp, int batch, const Fwd
 }
 
 int net_autotune(const no_net* net, const hz_problem* p, no_prec prec, void* ws, size_t ws_bytes, hipStream_t s) {
+    if (net->a.kind == NO_ARCH_PAPER8) return HZ_OK;   // one launch form per layer: nothing to tune
     int Hp, Wp;
     net_padded_dims(net, p, &Hp, &Wp);
     switch (prec) {
@@ -428,6 +471,7 @@ int net_autotune(const no_net* net, const hz_problem* p, no_prec prec, void* ws,
 }
 
 int net_autotune_bufs(const no_net* net, int Hp, int Wp, int batch, const FwdBufs& b, no_prec prec, hipStream_t s) {
+    if (net->a.kind == NO_ARCH_PAPER8) return HZ_OK;
     switch (prec) {
         case NO_BF16: return autotune_impl<PolBF16>(net, Hp, Wp, batch, b, s);
         case NO_FP32: return autotune_impl<PolF32>(net, Hp, Wp, batch, b, s);
@@ -477,7 +521,8 @@ extern "C" int no_net_create(const no_arch* a, const float* theta, void* stream,
     no_net* net = new no_net();
     if (!build_layers(a, net->layers, net->nparam, net->pk_total, net->bias_total)) {
         delete net;
-        set_error("no_net_create: levels must be 1..6, base a multiple of 8, in_ch 2 or 5");
+        set_error("no_net_create: UNET3 needs levels 1..6 and base a multiple of 8, PAPER8 depth 1..5 and 32 "
+                  "channels; in_ch 2 or 5");
         return HZ_ERR_ARG;
     }
     net->a = *a;
@@ -557,6 +602,9 @@ static int layer_impl(const no_net* net, int layer, int batch, int H, int W, con
                       void* y, void* pool, void* ws, size_t ws_bytes, hipStream_t s) {
     using T = typename P::T;
     const Layer& ly = net->layers[layer];
+    if (ly.kind == L_DOWN8 || ly.kind == L_UP8)   // H, W: the input's size
+        return launch_conv8<P>(ly.kind == L_UP8, (const T*)x0, (const T*)x1, ly.cin_p, ly.cat_cp,
+                               packed_w<P>(net, ly), packed_b<P>(net, ly), (T*)y, ly.cout_p, H, W, batch, nullptr, s);
     if (ly.kind == L_CONV3) {
         const int c1 = ly.cat_cp ? ly.cin_p - ly.cat_cp : 0;
         const int c0 = ly.cin_p - c1;

@@ -111,6 +111,20 @@ inline FwdBufs fwd_layout(const no_net* net, int Hp, int Wp, int batch, void* ba
     Carver c(base, cap);
     const int lv = net->a.levels;
     b.X = c.take<T>((size_t)batch * Hp * Wp * 8);
+    if (net->a.kind == NO_ARCH_PAPER8) {
+        // E[l], l = 1..lv: encoder outputs at 1 / 2^l; U[l], l = 0..lv-1: decoder outputs at 1 / 2^l
+        const int ch = net->a.base;
+        b.E.assign(lv + 1, nullptr);
+        b.U.assign(lv, nullptr);
+        for (int l = 1; l <= lv; ++l) b.E[l] = c.take<T>((size_t)batch * (Hp >> l) * (Wp >> l) * ch);
+        for (int l = 0; l < lv; ++l) b.U[l] = c.take<T>((size_t)batch * (Hp >> l) * (Wp >> l) * ch);
+        b.part = c.take<double2>(1024);
+        b.sc = c.take<double>(2);
+        b.split_elems = 0;
+        b.splitbuf = nullptr;
+        b.total = c.off + 256;
+        return b;
+    }
     b.E.resize(lv);
     b.T1.resize(lv);
     b.T1d.resize(lv);
@@ -173,6 +187,36 @@ inline const typename P::Acc* packed_b(const no_net* net, const Layer& ly) {
 template <class P>
 constexpr no_prec prec_of() {
     return sizeof(typename P::T) == 2 ? NO_BF16 : (sizeof(typename P::T) == 4 ? NO_FP32 : NO_FP64);
+}
+
+// Body of the paper's own network (NO_ARCH_PAPER8) on a packed input X: encoder E[1..lv], decoder
+// U[lv-1..0]; the 1x1 head reads U[0].
+template <class P>
+inline int paper8_body(const no_net* net, const FwdBufs& b, int Hp, int Wp, int batch, const int* skip,
+                       hipStream_t s) {
+    using T = typename P::T;
+    const int lv = net->a.levels;
+    const std::vector<Layer>& Ls = net->layers;
+    int li = 0;
+    const T* in = (const T*)b.X;
+    for (int l = 1; l <= lv; ++l) {
+        const Layer& ly = Ls[li++];
+        HZ_TRY(launch_conv8<P>(false, in, nullptr, ly.cin_p, 0, packed_w<P>(net, ly), packed_b<P>(net, ly),
+                               (T*)b.E[l], ly.cout_p, Hp >> (l - 1), Wp >> (l - 1), batch, skip, s));
+        in = (const T*)b.E[l];
+    }
+    {
+        const Layer& ly = Ls[li++];
+        HZ_TRY(launch_conv8<P>(true, (const T*)b.E[lv], nullptr, ly.cin_p, 0, packed_w<P>(net, ly),
+                               packed_b<P>(net, ly), (T*)b.U[lv - 1], ly.cout_p, Hp >> lv, Wp >> lv, batch, skip, s));
+    }
+    for (int l = lv - 2; l >= 0; --l) {
+        const Layer& ly = Ls[li++];
+        HZ_TRY(launch_conv8<P>(true, (const T*)b.E[l + 1], (const T*)b.U[l + 1], ly.cin_p, ly.cat_cp,
+                               packed_w<P>(net, ly), packed_b<P>(net, ly), (T*)b.U[l], ly.cout_p, Hp >> (l + 1),
+                               Wp >> (l + 1), batch, skip, s));
+    }
+    return HZ_OK;
 }
 
 template <class P>

@@ -1139,7 +1139,7 @@ using namespace hz;
 extern "C" size_t no_train_workspace_size(const no_net* net, const hz_problem* p, int batch, no_prec prec,
                                           int recompute) {
     clear_error();
-    if (!net || !p || batch < 1) return 0;
+    if (!net || !p || batch < 1 || net->a.kind != NO_ARCH_UNET3) return 0;
     if (prec == NO_BF16) return train_layout<PolBF16>(net, p, batch, nullptr, 0, recompute != 0).total;
     if (prec == NO_FP32) return train_layout<PolF32>(net, p, batch, nullptr, 0, recompute != 0).total;
     return 0;
@@ -1150,6 +1150,7 @@ extern "C" int no_loss_backward(const no_net* net, int batch, const hz_problem* 
                                 void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     HZ_CHECK_ARG(net && problems && r && loss && ws, "no_loss_backward: NULL argument");
+    HZ_CHECK_ARG(net->a.kind == NO_ARCH_UNET3, "no_loss_backward: training needs the UNET3 network");
     HZ_CHECK_ARG(batch >= 1 && batch <= 1024, "no_loss_backward: batch must be in [1, 1024]");
     HZ_CHECK_ARG(prec == NO_BF16 || prec == NO_FP32, "no_loss_backward: precision must be NO_BF16 or NO_FP32");
     for (int b = 0; b < batch; ++b) {

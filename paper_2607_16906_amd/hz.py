@@ -31,7 +31,7 @@ class HzGrid(ct.Structure):
 
 
 class NoArch(ct.Structure):
-    _fields_ = [("levels", ct.c_int32), ("base", ct.c_int32), ("in_ch", ct.c_int32)]
+    _fields_ = [("levels", ct.c_int32), ("base", ct.c_int32), ("in_ch", ct.c_int32), ("kind", ct.c_int32)]
 
 
 class HzOpts(ct.Structure):
@@ -168,11 +168,16 @@ class Problem:
 class Net:
     """U-Net neural operator (no_net_create) holding its own repacked copies of theta."""
 
-    def __init__(self, levels: int, base: int, in_ch: int, theta):
+    KIND = {"unet3": 0, "paper8": 1}
+
+    def __init__(self, levels: int, base: int, in_ch: int, theta, kind: str = "unet3"):
+        """kind: "unet3" (3x3 / ReLU / doubling channels) or "paper8" (Table 2's 8x8 stride-2
+        layers with PReLU; levels = depth, base = 32)."""
         torch = _torch()
         lib = load_library()
-        self.arch = NoArch(levels, base, in_ch)
-        self.nparam = param_count(levels, base, in_ch)
+        self.arch = NoArch(levels, base, in_ch, self.KIND[kind])
+        self.kind = kind
+        self.nparam = param_count(levels, base, in_ch, kind)
         theta = torch.as_tensor(theta, dtype=torch.float32).to("cuda").contiguous()
         if theta.numel() != self.nparam:
             raise ValueError(f"theta has {theta.numel()} entries, the network needs {self.nparam}")
@@ -266,8 +271,8 @@ def init_shapes(levels: int, base: int, in_ch: int):
     return out
 
 
-def param_count(levels: int, base: int, in_ch: int) -> int:
-    n = load_library().no_param_count(ct.byref(NoArch(levels, base, in_ch)))
+def param_count(levels: int, base: int, in_ch: int, kind: str = "unet3") -> int:
+    n = load_library().no_param_count(ct.byref(NoArch(levels, base, in_ch, Net.KIND[kind])))
     if n < 0:
         raise ValueError("unsupported architecture")
     return int(n)
