@@ -211,6 +211,63 @@ def bench_training_loop(hz, torch, S=1024, V=128, batch=32, epochs=2, nint=64, n
     return out
 
 
+def paper8_flops(depth, ch, in_ch, Hp, Wp):
+    """Algorithmic FLOPs of one forward of the paper's 8x8 stride-2 network on an Hp x Wp grid
+    (logical channels; 64 taps down, 16 taps per output pixel up, the 1x1 head)."""
+    fl = 0
+    for l in range(1, depth + 1):
+        fl += 2 * (Hp >> l) * (Wp >> l) * ch * (in_ch if l == 1 else ch) * 64
+    for l in range(depth - 1, -1, -1):
+        fl += 2 * (Hp >> l) * (Wp >> l) * ch * (ch if l == depth - 1 else 2 * ch) * 16
+    return fl + 2 * Hp * Wp * 2 * ch
+
+
+def bench_paper8(hz, torch, net3, reps=50):
+    """The paper's own layer set (Table 2: depth 4, 32 channels, 8x8 stride-2, PReLU) as the
+    preconditioner on the single-solve system (296^2), seeded He-uniform weights with slopes 0.25
+    (no trained weights of this network exist here): one application in BF16 and FP32 against the
+    3x3 network's, and FGMRES time per iteration with it (m = 30)."""
+    from synth import H_10PPW, c2_system, he_uniform, rng_for
+    rng = rng_for(21, 2, 0)
+    parts = []
+    for i, shp in enumerate(hz.init_shapes_paper8(4, 32, 5)):
+        parts.append(he_uniform([shp], rng))
+        if i < 8:
+            parts.append(np.array([0.25], np.float32))
+    theta8 = np.concatenate(parts).astype(np.float32)
+    net8 = hz.Net(4, 32, 5, theta8, kind="paper8")
+    s = c2_system(0)
+    gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW)
+    v = torch.from_numpy(s.b.ravel().astype(np.complex64)).cuda()
+    Hp = (s.nt + 15) // 16 * 16
+    out = {"workload": "one application on 296^2 (padded to 304^2), seeded weights; FGMRES m = 30, 60 iterations",
+           "params": net8.nparam, "gflop_per_apply": round(paper8_flops(4, 32, 5, Hp, Hp) * 1e-9, 3)}
+    for tag, net in (("paper8", net8), ("unet3", net3)):
+        for prec in ("bf16", "fp32"):
+            net.autotune(gp, prec)
+            for _ in range(3):
+                net.apply(gp, v, prec=prec)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                net.apply(gp, v, prec=prec)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            out[f"{tag}_{prec}_apply_us"] = round(ms * 1e3, 1)
+            if tag == "paper8":
+                out[f"{tag}_{prec}_tflops"] = round(paper8_flops(4, 32, 5, Hp, Hp) / (ms * 1e-3) * 1e-12, 1)
+    b = torch.from_numpy(s.b.ravel()).cuda()
+    hz.fgmres(gp, b, net=net8, m=30, tol=1e-6, maxit=8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = hz.fgmres(gp, b, net=net8, m=30, tol=1e-6, maxit=60)
+    torch.cuda.synchronize()
+    out["fgmres_ms_per_it"] = round((time.perf_counter() - t0) * 1e3 / max(info.its, 1), 3)
+    out["fgmres_relres_after_60"] = float(f"{info.true_relres:.3e}")
+    return out
+
+
 def bench_batched(hz, torch, net, nsys=128, maxit=30):
     """Ragged batch: the 128 systems of the batched-serving mix (128..512 interior + 16..32 PML, each
     with its own velocity and sources), BF16 network, FGMRES(30), advanced together for one cycle
@@ -441,7 +498,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="with --roofline-only: also copy 512 MiB with a plain device copy (counter calibration)")
     ap.add_argument("--only", choices=["training", "training_loop", "batched", "large", "restart", "spectral",
-                                       "appendix_b"],
+                                       "appendix_b", "paper8"],
                     default=None,
                     help="run one extra section alone and print its JSON (for profiler runs)")
     args = ap.parse_args()
@@ -468,7 +525,8 @@ def main():
         else:
             net1 = hz.Net(LEVELS, BASE, IN_CH, theta)
             res = {"batched": bench_batched, "large": bench_large, "restart": bench_restart,
-                   "spectral": bench_spectral, "appendix_b": bench_appendix_b}[args.only](hz, torch, net1)
+                   "spectral": bench_spectral, "appendix_b": bench_appendix_b,
+                   "paper8": bench_paper8}[args.only](hz, torch, net1)
         print(json.dumps({args.only: res}))
         return
     s = c2_system(0)
@@ -577,6 +635,7 @@ def main():
         out["restart"] = bench_restart(hz, torch, net)
         out["spectral"] = bench_spectral(hz, torch, net)
         out["appendix_b"] = bench_appendix_b(hz, torch, net)
+        out["paper8"] = bench_paper8(hz, torch, net)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, theta, its)
     print(json.dumps(out))

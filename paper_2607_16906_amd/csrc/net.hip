@@ -188,12 +188,20 @@ __global__ void k_head(const typename P::T* __restrict__ D, int cin_p, const typ
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)nxt * nyt) return;
     const int yy = (int)(idx / nxt), xx = (int)(idx % nxt);
-    const typename P::T* d = D + ((int64_t)yy * Wp + xx) * cin_p;
+    using T = typename P::T;
+    const T* d = D + ((int64_t)yy * Wp + xx) * cin_p;
     Acc o0 = bh[0], o1 = bh[1];
-    for (int c = 0; c < cin_p; ++c) {
-        const Acc dv = P::val(d[c]);
-        o0 += dv * P::val(wh[c]);
-        o1 += dv * P::val(wh[cin_p + c]);
+    // the pixel's channels in 16-byte loads (cin_p is a multiple of 8); same order of sums
+    constexpr int V = 16 / (int)sizeof(T);
+    for (int c = 0; c < cin_p; c += V) {
+        const uint4 raw = *(const uint4*)(d + c);
+        const T* e = (const T*)&raw;
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const Acc dv = P::val(e[j]);
+            o0 += dv * P::val(wh[c + j]);
+            o1 += dv * P::val(wh[cin_p + c + j]);
+        }
     }
     const double s = fixed_s > 0 ? fixed_s : sc[0];
     z[idx] = from_d2<C>(double2{s * (double)o0, s * (double)o1});

@@ -12,36 +12,43 @@
 // pixels of one parity class, which share their weights, and K = 16 x input channels.
 //
 // Activations are NHWC (channels padded to a multiple of 8, the first layer's input has 8); the
-// packed weights are [tap = 8 a + e][cout_p][cin_p]; bias[cout_p] holds the PReLU slope. A
-// wavefront owns 2 tiles of 16 pixels and all output channels (2 tiles of 16): each K step loads
-// one B fragment per pixel tile straight from the (cache-resident) input and one A fragment per
-// channel tile, and issues 4 matrix instructions.
+// packed weights are [tap = 8 a + e][cout_p][cin_p]; bias[cout_p] holds the PReLU slope. An item
+// is 2 tiles of 16 pixels and all output channels (2 tiles of 16): each K step loads one B
+// fragment per pixel tile straight from the (cache-resident) input and one A fragment per channel
+// tile, and issues 4 matrix instructions. Small layers split an item's K steps over several
+// wavefronts so that the grid still fills the chip.
 #include "net.h"
 #include "net_kernels.h"
 
 namespace hz {
 
-constexpr int C8_WAVES = 4;   // wavefronts per block
 constexpr int C8_PX = 32;     // output pixels per wavefront
 
+// ks wavefronts of a block share one item (2 x 16 pixels, all 32 output channels) and split its K
+// steps into ks consecutive ranges; the partial sums meet in LDS (dynamic, nw x 16 x 64
+// accumulators) and the first wavefront of the group finishes the item. A block has nw = 4 or 8
+// wavefronts and holds nw / ks items.
 template <class P, bool UP>
-__global__ __launch_bounds__(64 * C8_WAVES) void k_conv8(
+__global__ __launch_bounds__(512) void k_conv8(
     const typename P::T* __restrict__ x0, const typename P::T* __restrict__ x1, int cin_p, int cat_cp,
     const typename P::T* __restrict__ w, const typename P::Acc* __restrict__ bias, typename P::T* __restrict__ y,
-    int Hin, int Win, int batch, int tiles, const int* __restrict__ skip) {
+    int Hin, int Win, int batch, int tiles, int ks, const int* __restrict__ skip) {
     using T = typename P::T;
     using Acc = typename P::Acc;
     using Frag = typename P::Frag;
     using AccV = typename P::AccV;
     constexpr int COUT = 32;
     constexpr int KSTEP = 4 * P::GW;
-    if (skip && *skip) return;
-    const int lane = threadIdx.x & 63;
-    const int64_t item = (int64_t)blockIdx.x * C8_WAVES + (threadIdx.x >> 6);
+    extern __shared__ __align__(16) unsigned char c8_smem[];
+    if (skip && *skip) return;   // uniform over the block
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+    const int kw = wv % ks;
+    const int64_t item = (int64_t)blockIdx.x * (nw / ks) + wv / ks;
     constexpr int NCLS = UP ? 4 : 1;
-    if (item >= (int64_t)batch * NCLS * tiles) return;   // whole wavefronts; no block barrier follows
-    const int tile = (int)(item % tiles);
-    const int bc = (int)(item / tiles);
+    const bool live = item < (int64_t)batch * NCLS * tiles;   // dead wavefronts still meet the barrier
+    const int tile = live ? (int)(item % tiles) : 0;
+    const int bc = live ? (int)(item / tiles) : 0;
     const int cls = bc % NCLS;
     const int b = bc / NCLS;
     const int py = cls >> 1, px = cls & 1;
@@ -53,7 +60,7 @@ __global__ __launch_bounds__(64 * C8_WAVES) void k_conv8(
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         const int q = tile * C8_PX + t * 16 + col;
-        qv[t] = q < Hq * Wq;
+        qv[t] = live && q < Hq * Wq;
         qy[t] = qv[t] ? q / Wq : 0;
         qx[t] = qv[t] ? q % Wq : 0;
     }
@@ -68,9 +75,13 @@ __global__ __launch_bounds__(64 * C8_WAVES) void k_conv8(
         for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[m][t][r] = 0;
-    const int K = (UP ? 16 : 64) * cin_p;
-    for (int k0 = 0; k0 < K; k0 += KSTEP) {
-        const int k = k0 + g * P::GW;
+    const int nsteps = (UP ? 16 : 64) * cin_p / KSTEP;
+    const int per = nsteps / ks;
+    const int s0 = kw * per;
+    const int s1 = live ? (kw + 1) * per : s0;
+    // fragments of K step st: B (input) per pixel tile, A (weights) per channel tile
+    auto load_step = [&](int st, Frag (&bf)[2], Frag (&af)[2]) {
+        const int k = st * KSTEP + g * P::GW;
         const int tap = k / cin_p, ci = k - tap * cin_p;
         int a, e, dy, dx;
         if (UP) {
@@ -88,7 +99,6 @@ __global__ __launch_bounds__(64 * C8_WAVES) void k_conv8(
         const T* src = second ? xb1 : xb0;
         const int cstr = second ? cs1 : cs0;
         const int cc = second ? ci - cat_cp : ci;
-        Frag bf[2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             const int iy = UP ? qy[t] + dy : 2 * qy[t] + dy;
@@ -98,11 +108,46 @@ __global__ __launch_bounds__(64 * C8_WAVES) void k_conv8(
         }
         const T* wt = w + ((int64_t)(a * 8 + e) * COUT + col) * cin_p + ci;
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            const Frag af = P::load(wt + (int64_t)m * 16 * cin_p);
+        for (int m = 0; m < 2; ++m) af[m] = P::load(wt + (int64_t)m * 16 * cin_p);
+    };
+    // one step of look-ahead: the next step's loads are in flight during this step's products
+    Frag bcur[2], acur[2];
+    if (s0 < s1) load_step(s0, bcur, acur);
+    for (int st = s0; st < s1; ++st) {
+        // the last step reloads its own fragments (unused): no branch around the loads, so the
+        // wait for them can sit just before their first use
+        Frag bnxt[2], anxt[2];
+        load_step(st + 1 < s1 ? st + 1 : st, bnxt, anxt);
 #pragma unroll
-            for (int t = 0; t < 2; ++t) acc[m][t] = P::mma(af, bf[t], acc[m][t]);
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int t = 0; t < 2; ++t) acc[m][t] = P::mma(acur[m], bcur[t], acc[m][t]);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            bcur[t] = bnxt[t];
+            acur[t] = anxt[t];
         }
+    }
+    if (ks > 1) {
+        // red[wave][16 values][64 lanes]: lane-fastest, conflict-free
+        Acc* red = (Acc*)c8_smem;
+        if (kw > 0) {
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) red[(wv * 16 + (m * 2 + t) * 4 + r) * 64 + lane] = acc[m][t][r];
+        }
+        __syncthreads();
+        if (kw > 0) return;
+        for (int j = 1; j < ks; ++j)
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[m][t][r] += red[((wv + j) * 16 + (m * 2 + t) * 4 + r) * 64 + lane];
     }
     const Acc slope = bias[COUT];
 #pragma unroll
@@ -139,13 +184,21 @@ int launch_conv8(bool up, const typename P::T* x0, const typename P::T* x1, int 
     const int64_t px = up ? (int64_t)Hin * Win : (int64_t)(Hin / 2) * (Win / 2);
     const int tiles = (int)((px + C8_PX - 1) / C8_PX);
     const int64_t items = (int64_t)batch * (up ? 4 : 1) * tiles;
-    const unsigned grid = (unsigned)((items + C8_WAVES - 1) / C8_WAVES);
+    // split K over up to 8 wavefronts while the grid holds fewer than 2048 wavefronts (about 8 per
+    // compute unit); the split depends on the sizes only, so results are reproducible
+    const int nsteps = (up ? 16 : 64) * cin_p / (4 * P::GW);
+    int ks = 1;
+    while (ks < 8 && items * ks < 2048 && nsteps % (2 * ks) == 0) ks *= 2;
+    const int nw = ks <= 4 ? 4 : 8;
+    const int64_t per_block = nw / ks;
+    const unsigned grid = (unsigned)((items + per_block - 1) / per_block);
+    const size_t shm = ks > 1 ? (size_t)nw * 16 * 64 * sizeof(typename P::Acc) : 0;
     if (up)
-        hipLaunchKernelGGL((k_conv8<P, true>), dim3(grid), dim3(64 * C8_WAVES), 0, s, x0, x1, cin_p, cat_cp, w, bias,
-                           y, Hin, Win, batch, tiles, skip);
+        hipLaunchKernelGGL((k_conv8<P, true>), dim3(grid), dim3(64 * nw), shm, s, x0, x1, cin_p, cat_cp, w, bias, y,
+                           Hin, Win, batch, tiles, ks, skip);
     else
-        hipLaunchKernelGGL((k_conv8<P, false>), dim3(grid), dim3(64 * C8_WAVES), 0, s, x0, x1, cin_p, cat_cp, w,
-                           bias, y, Hin, Win, batch, tiles, skip);
+        hipLaunchKernelGGL((k_conv8<P, false>), dim3(grid), dim3(64 * nw), shm, s, x0, x1, cin_p, cat_cp, w, bias, y,
+                           Hin, Win, batch, tiles, ks, skip);
     HZ_LAUNCH_CHECK();
     return HZ_OK;
 }

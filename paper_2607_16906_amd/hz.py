@@ -253,6 +253,14 @@ class Net:
                "no_layer_forward")
 
 
+def init_shapes_paper8(depth: int, ch: int, in_ch: int):
+    """(weight shape, fan-in, bias length) of every layer of the NO_ARCH_PAPER8 network in the flat
+    parameter order of hz.h; each layer but the head is followed by one PReLU slope."""
+    out = [((ch, in_ch, 8, 8), 64 * in_ch, ch)] + [((ch, ch, 8, 8), 64 * ch, ch)] * (depth - 1)
+    out += [((ch, ch, 8, 8), 16 * ch, ch)] + [((2 * ch, ch, 8, 8), 32 * ch, ch)] * (depth - 1)
+    return out + [((2, ch, 1, 1), ch, 2)]
+
+
 def init_shapes(levels: int, base: int, in_ch: int):
     """(weight shape, fan-in, bias length) of every layer in the flat parameter order of hz.h
     (input for a seeded initialiser)."""
