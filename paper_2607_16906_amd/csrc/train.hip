@@ -402,6 +402,110 @@ __global__ __launch_bounds__(TT) void k_wgrad3_mfma(const bf16_t* __restrict__ G
     }
 }
 
+// The same product in FP32 on the matrix cores (v_mfma_f32_16x16x4_f32: one reduction element
+// per lane, 4 pixels per instruction). Block, tiles, partials and bias sums as in k_wgrad3_mfma;
+// the transposed LDS copies hold FP32 values, and a single copy of the 10 x 18 input patch serves
+// every dx since a lane reads one value. Row pitches of 130 and 194 floats (2 mod 32) make the 32
+// lanes of a half-wavefront hit 32 distinct banks.
+constexpr int WF_GS = 128 + 2;
+constexpr int WF_XS = 10 * 18 + 14;
+
+__global__ __launch_bounds__(TT) void k_wgrad3_mfma_f32(const float* __restrict__ G, int cout_p,
+                                                        const float* __restrict__ x0, int c0,
+                                                        const float* __restrict__ x1, int c1, int H, int W,
+                                                        int ntiles, int tpc, float* __restrict__ part,
+                                                        float* __restrict__ partb) {
+    __shared__ float gt[WG_CO * WF_GS];
+    __shared__ float xt[WG_CI * WF_XS];
+    const int cin_p = c0 + c1;
+    const int ci0 = blockIdx.x * WG_CI, co0 = blockIdx.y * WG_CO;
+    const int z = blockIdx.z;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lr = lane & 15, kg = lane >> 4;
+    const int cob = wv >> 1, cib = wv & 1;
+    const int tx_n = (W + 15) / 16, ty_n = (H + 7) / 8;
+    const int per_img = tx_n * ty_n;
+    const int64_t plane = (int64_t)H * W;
+    f32x4_t acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[t][r] = 0.f;
+    float accb = 0.f;
+    const int t_end = min(ntiles, (z + 1) * tpc);
+    for (int tile = z * tpc; tile < t_end; ++tile) {
+        const int b = tile / per_img, r = tile - b * per_img;
+        const int ty0 = (r / tx_n) * 8, tx0 = (r % tx_n) * 16;
+        __syncthreads();
+        // G tile: 128 pixels x 32 channels, 8 vectors of 4 channels per pixel
+        for (int v = threadIdx.x; v < 128 * 8; v += TT) {
+            const int px = v >> 3, part4 = v & 7;
+            const int gy = ty0 + (px >> 4), gx = tx0 + (px & 15);
+            const int co = co0 + part4 * 4;
+            float4 val = float4{0.f, 0.f, 0.f, 0.f};
+            if (gy < H && gx < W && co < cout_p)
+                val = *(const float4*)(G + ((int64_t)b * plane + (int64_t)gy * W + gx) * cout_p + co);
+            gt[(part4 * 4 + 0) * WF_GS + px] = val.x;
+            gt[(part4 * 4 + 1) * WF_GS + px] = val.y;
+            gt[(part4 * 4 + 2) * WF_GS + px] = val.z;
+            gt[(part4 * 4 + 3) * WF_GS + px] = val.w;
+        }
+        // input patch: 10 x 18 pixels x 32 channels
+        for (int v = threadIdx.x; v < 180 * 8; v += TT) {
+            const int px = v >> 3, part4 = v & 7;
+            const int py = px / 18, pc = px - py * 18;
+            const int gy = ty0 + py - 1, gx = tx0 + pc - 1;
+            const int ci = ci0 + part4 * 4;
+            float4 val = float4{0.f, 0.f, 0.f, 0.f};
+            if (gy >= 0 && gy < H && gx >= 0 && gx < W && ci < cin_p) {
+                const int64_t pix = (int64_t)b * plane + (int64_t)gy * W + gx;
+                val = *(const float4*)(ci < c0 ? x0 + pix * c0 + ci : x1 + pix * c1 + (ci - c0));
+            }
+            xt[(part4 * 4 + 0) * WF_XS + px] = val.x;
+            xt[(part4 * 4 + 1) * WF_XS + px] = val.y;
+            xt[(part4 * 4 + 2) * WF_XS + px] = val.z;
+            xt[(part4 * 4 + 3) * WF_XS + px] = val.w;
+        }
+        __syncthreads();
+        if (blockIdx.x == 0) {
+            const int co = threadIdx.x >> 3, seg = threadIdx.x & 7;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) accb += gt[co * WF_GS + seg * 16 + k];
+        }
+        // 32 reduction steps of 4 pixels: lane group kg takes pixel 4 q + kg
+#pragma unroll 4
+        for (int q = 0; q < 32; ++q) {
+            const int p = 4 * q + kg;
+            const int row = p >> 4, col = p & 15;
+            const float a = gt[(cob * 16 + lr) * WF_GS + p];
+            const float* xb = &xt[(cib * 16 + lr) * WF_XS + row * 18 + col];
+#pragma unroll
+            for (int t = 0; t < 9; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, xb[(t / 3) * 18 + t % 3], acc[t], 0, 0, 0);
+        }
+    }
+    // lane holds D[co = co0 + 16 cob + 4 kg + r][ci = ci0 + 16 cib + lr] of every tap
+    const int ci = ci0 + cib * 16 + lr;
+    if (ci < cin_p) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int co = co0 + cob * 16 + 4 * kg + r;
+            if (co < cout_p) {
+                float* dst = part + (((int64_t)z * cout_p + co) * cin_p + ci) * 9;
+#pragma unroll
+                for (int t = 0; t < 9; ++t) dst[t] = acc[t][r];
+            }
+        }
+    }
+    if (blockIdx.x == 0) {
+        accb += __shfl_xor(accb, 1, 64);
+        accb += __shfl_xor(accb, 2, 64);
+        accb += __shfl_xor(accb, 4, 64);
+        const int co = co0 + (threadIdx.x >> 3);
+        if ((threadIdx.x & 7) == 0 && co < cout_p) partb[(int64_t)z * cout_p + co] = accb;
+    }
+}
+
 // Transposed 2x2: dW[ab][co][ci] = sum_i G[2i + ab][co] x[i][ci]; block: ci tile, co tile, chunk of
 // 8 x 8 input tiles.
 template <class P>
@@ -801,7 +905,7 @@ static int wgrad_conv3(const Layer& ly, const typename P::T* G, const typename P
                        hipStream_t s) {
     const int ntiles = ((W + 15) / 16) * ((H + 7) / 8) * B;
     int nchunk;
-    if constexpr (std::is_same<P, PolBF16>::value) {
+    if constexpr (std::is_same<P, PolBF16>::value || std::is_same<P, PolF32>::value) {
         // matrix-core form: about 1024 blocks, as many chunks as the partial buffer holds
         const int ctiles = ((ly.cin_p + WG_CI - 1) / WG_CI) * ((ly.cout_p + WG_CO - 1) / WG_CO);
         const size_t per_chunk = (size_t)9 * ly.cout_p * ly.cin_p;
@@ -811,8 +915,12 @@ static int wgrad_conv3(const Layer& ly, const typename P::T* G, const typename P
         const int tpc = (ntiles + want - 1) / want;
         nchunk = (ntiles + tpc - 1) / tpc;
         dim3 grid((ly.cin_p + WG_CI - 1) / WG_CI, (ly.cout_p + WG_CO - 1) / WG_CO, nchunk);
-        hipLaunchKernelGGL(k_wgrad3_mfma, grid, dim3(TT), 0, s, G, ly.cout_p, x0, c0, x1, c1, H, W, ntiles, tpc,
-                           t.wpart, t.wpartb);
+        if constexpr (std::is_same<P, PolBF16>::value)
+            hipLaunchKernelGGL(k_wgrad3_mfma, grid, dim3(TT), 0, s, G, ly.cout_p, x0, c0, x1, c1, H, W, ntiles, tpc,
+                               t.wpart, t.wpartb);
+        else
+            hipLaunchKernelGGL(k_wgrad3_mfma_f32, grid, dim3(TT), 0, s, G, ly.cout_p, x0, c0, x1, c1, H, W, ntiles,
+                               tpc, t.wpart, t.wpartb);
     } else {
         const int tpc = (ntiles + WCHUNKS - 1) / WCHUNKS;
         nchunk = (ntiles + tpc - 1) / tpc;
