@@ -110,8 +110,8 @@ int hz_op_apply(const hz_problem* p, hz_dtype dtype, int adjoint,
  *   convolutions down and as many transposed ones up, `base` channels in every
  *   layer, PReLU (one slope per layer), batch normalisation folded into the
  *   convolutions; the decoder concatenates the encoder output of its input size
- *   (encoder part first). Inference only (no_loss_backward, the batched solver,
- *   no_layer_forward and the launch-variant calls reject it).
+ *   (encoder part first). Inference only: no_loss_backward, the batched solver
+ *   and the launch-variant calls reject it.
  * Both end in a 1x1 head with 2 outputs (Re, Im). in_ch = 2 takes the (scaled)
  * Re/Im of the field; in_ch = 5 adds c / c_ref, sigma_x, sigma_y. */
 #define NO_ARCH_UNET3  0
@@ -183,18 +183,20 @@ int no_set_layer_variant(const no_net* net, int layer, no_prec prec, int batch, 
 int no_set_fused_upsampling(no_net* net, int mode);
 
 /* Shape of layer `layer` (0-based, in the order of the flat parameter vector):
- * kind 0 = 3x3 convolution + ReLU, 1 = 2x2 stride-2 transposed convolution, 2 = 1x1 head;
+ * kind 0 = 3x3 convolution + ReLU, 1 = 2x2 stride-2 transposed convolution, 2 = 1x1 head,
+ * 3 = 8x8 stride-2 convolution + PReLU, 4 = 8x8 stride-2 transposed convolution + PReLU;
  * cin_p / cout_p = input / output channels as stored (zero-padded to a multiple of 16, the
  * network input to 8); cat_cp = stored channels of the first part of a concatenated input
  * (0 if the input is not a concatenation). Any output pointer may be NULL. */
 int no_layer_info(const no_net* net, int layer, int32_t* kind, int32_t* cin_p, int32_t* cout_p,
                   int32_t* cat_cp);
 
-/* Run one 3x3 or transposed-convolution layer of the network on caller activations, as the
+/* Run one 3x3, transposed-convolution or 8x8 layer of the network on caller activations, as the
  * forward pass does (with the launch variant no_autotune chose for this layer and size, if any).
  * x0_dev: [batch][H][W][c0] with c0 = cat_cp for a concatenated input and c0 = cin_p otherwise;
  * x1_dev: [batch][H][W][cin_p - cat_cp] (second part) or NULL; y_dev: [batch][H'][W'][cout_p]
- * with (H', W') = (H, W) for a 3x3 layer and (2H, 2W) for a transposed one; pool_dev: optional
+ * with (H', W') = (H, W) for a 3x3 layer, (2H, 2W) for a transposed one (2x2 or 8x8) and
+ * (H/2, W/2) for an 8x8 stride-2 convolution (H, W even); pool_dev: optional
  * [batch][H/2][W/2][cout_p] average-pooled copy of y (3x3 layers, H and W even). Elements are
  * BF16 (raw 16-bit), float or double per `prec`. ws_dev / ws_bytes: scratch for a split of the
  * input channels (4 x batch x H x W x cout_p accumulators; NULL disables the split).
