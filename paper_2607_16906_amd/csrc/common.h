@@ -50,6 +50,12 @@ void clear_error();
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Process-wide identity of problem and network handles (never reused, unlike addresses).
+uint64_t next_handle_uid();
+// Drop the solver's kept graphs that refer to the handle with this identity (called when a
+// problem or a network is destroyed; defined in fgmres.hip).
+void fgmres_graph_cache_evict(uint64_t uid);
+
 // Bump allocator over a caller workspace; every carve is 256-byte aligned.
 struct Carver {
     char* base;

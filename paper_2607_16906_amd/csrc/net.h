@@ -57,6 +57,7 @@ struct no_net {
     std::map<std::array<int, 5>, hz::ConvCfg> tuned;
     std::mutex tune_mu;
     int fuse_up = 2;   // fused decoder convolution: 0 never, 1 where it applies, 2 where autotuned faster
+    uint64_t uid = 0;  // handle identity (next_handle_uid)
 };
 
 namespace hz {

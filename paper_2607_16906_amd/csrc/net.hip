@@ -527,6 +527,7 @@ extern "C" int no_net_create(const no_arch* a, const float* theta, void* stream,
     clear_error();
     HZ_CHECK_ARG(a && theta && out, "no_net_create: NULL argument");
     no_net* net = new no_net();
+    net->uid = next_handle_uid();
     if (!build_layers(a, net->layers, net->nparam, net->pk_total, net->bias_total)) {
         delete net;
         set_error("no_net_create: UNET3 needs levels 1..6 and base a multiple of 8, PAPER8 depth 1..5 and 32 "
@@ -570,6 +571,7 @@ extern "C" int no_net_set_weights(no_net* net, const float* theta, void* stream)
 extern "C" int no_net_destroy(no_net* net) {
     clear_error();
     if (!net) return HZ_OK;
+    fgmres_graph_cache_evict(net->uid);
     HZ_HIP(hipFree(net->block));
     delete net;
     return HZ_OK;

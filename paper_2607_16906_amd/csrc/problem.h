@@ -22,6 +22,7 @@ struct hz_problem {
     double2 *Mx_d, *My_d;
     float2 *Mx_f, *My_f;
     void* block;          // the single device allocation holding all of the above
+    uint64_t uid = 0;     // handle identity (next_handle_uid)
 };
 
 namespace hz {

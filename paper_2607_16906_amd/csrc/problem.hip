@@ -216,6 +216,7 @@ extern "C" int hz_problem_create(const hz_grid* g, const float* c_dev, void* str
                  "hz_problem_create: the spectral operator takes at most 8192 nodes per axis");
     hipStream_t s = (hipStream_t)stream;
     hz_problem* p = new hz_problem();
+    p->uid = next_handle_uid();
     p->g = *g;
     p->nxt = nxt;
     p->nyt = nyt;
@@ -290,6 +291,7 @@ extern "C" int hz_problem_create(const hz_grid* g, const float* c_dev, void* str
 extern "C" int hz_problem_destroy(hz_problem* p) {
     clear_error();
     if (!p) return HZ_OK;
+    fgmres_graph_cache_evict(p->uid);
     HZ_HIP(hipFree(p->block));
     delete p;
     return HZ_OK;

@@ -370,15 +370,28 @@ ORTHO = {"cgs2": 0, "dcgs2": 1}
 
 
 def fgmres(problem: Problem, b, x0=None, *, net: Net | None = None, m: int = 30, tol: float = 1e-6,
-           maxit: int = 300, krylov: str = "c64", net_prec: str = "bf16", workspace=None, ortho: str = "cgs2"):
+           maxit: int = 300, krylov: str = "c64", net_prec: str = "bf16", workspace=None, ortho: str = "cgs2",
+           out=None):
     """Solve A x = b (fgmres_solve). b: complex128 device vector; returns (x, SolveInfo).
 
     ortho: "cgs2" (classical Gram-Schmidt with one reorthogonalisation) or "dcgs2" (delayed
-    reorthogonalisation, one reduction per step; needs a network)."""
+    reorthogonalisation, one reduction per step; needs a network).
+    out: optional complex128 device vector of n entries that receives x (x0, or 0, is written into
+    it first); repeated solves with the same b, out and workspace replay the library's kept cycle
+    graphs."""
     torch = _torch()
     lib = load_library()
     b = b.to(torch.complex128).contiguous()
-    x = torch.zeros_like(b) if x0 is None else x0.to(torch.complex128).contiguous().clone()
+    if out is not None:
+        if out.dtype != torch.complex128 or out.numel() != b.numel() or not out.is_contiguous() or not out.is_cuda:
+            raise ValueError("out must be a contiguous complex128 device vector of n entries")
+        x = out
+        if x0 is None:
+            x.zero_()
+        else:
+            x.copy_(x0.reshape(x.shape))
+    else:
+        x = torch.zeros_like(b) if x0 is None else x0.to(torch.complex128).contiguous().clone()
     hist = np.zeros(maxit, np.float64)
     opts = HzOpts(m, maxit, tol, HZ_C64 if krylov == "c64" else HZ_C128, PREC[net_prec],
                   hist.ctypes.data_as(ct.POINTER(ct.c_double)), maxit, ORTHO[ortho])

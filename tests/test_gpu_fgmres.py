@@ -212,3 +212,40 @@ def test_degenerate_solves():
     # bad options are rejected before any launch
     with pytest.raises(hz.HzError):
         hz.fgmres(gp, to_dev(b, torch.complex128), m=0, tol=1e-6, maxit=10)
+
+
+def test_kept_cycle_graphs_replay_exactly():
+    # a second solve with the same problem, options, vectors and workspace replays the kept cycle
+    # graphs (full cycles and the shorter last one): the same bits, history and counts; new values
+    # in the same b buffer are seen; a destroyed problem's graphs are dropped
+    import gc
+    from paper_2607_16906_amd import hz
+    c, b, p = small_system(nx=30, p=6, seed=4)
+    _, gp = make_pair(c, p)
+    theta = he_uniform(unet.init_shapes(unet.layer_specs(2, 8, 5)), rng_for(13, 2, 4))
+    net = hz.Net(2, 8, 5, theta)
+    bd = to_dev(b, torch.complex128)
+    out = torch.empty_like(bd)
+    for nn, prec, kr in ((None, "fp32", "c128"), (net, "bf16", "c64"), (net, "fp64", "c128")):
+        kw = dict(net=nn, m=10, tol=1e-9, maxit=45, krylov=kr, net_prec=prec)
+        ws = torch.empty(hz.fgmres_workspace_bytes(gp, nn, 10, 45, kr, prec), dtype=torch.uint8, device="cuda")
+        bd.copy_(to_dev(b, torch.complex128))
+        x1, i1 = hz.fgmres(gp, bd, workspace=ws, out=out, **kw)
+        x1 = x1.clone()
+        x2, i2 = hz.fgmres(gp, bd, workspace=ws, out=out, **kw)
+        assert torch.equal(x1, x2) and (i1.its, i1.cycles, i1.status) == (i2.its, i2.cycles, i2.status)
+        assert np.array_equal(i1.hist, i2.hist)
+        # new right-hand side in the same buffer: as a solve on fresh buffers
+        bd.copy_(to_dev(b * (0.5 - 2j), torch.complex128))
+        x3, i3 = hz.fgmres(gp, bd, workspace=ws, out=out, **kw)
+        x3 = x3.clone()
+        xf, i_f = hz.fgmres(gp, bd.clone(), **kw)
+        assert torch.equal(x3, xf) and i3.its == i_f.its
+    # a new problem after the old one is destroyed (its kept graphs go with it)
+    del gp
+    gc.collect()
+    _, gp2 = make_pair(c, p)
+    ws = torch.empty(hz.fgmres_workspace_bytes(gp2, net, 10, 45, "c128", "fp64"), dtype=torch.uint8, device="cuda")
+    x4, i4 = hz.fgmres(gp2, bd, workspace=ws, out=out, net=net, m=10, tol=1e-9, maxit=45, krylov="c128",
+                       net_prec="fp64")
+    assert torch.equal(x4, xf) and i4.its == i_f.its
