@@ -29,7 +29,10 @@ def data(S, V, nint, p):
     return ([o for o, _ in tr], [g for _, g in tr], b, dev(b), [o for o, _ in va], [g for _, g in va], vb, dev(vb))
 
 
-def test_loop_matches_oracle_loop_fp32():
+@pytest.mark.parametrize("squared,recompute", [(False, False), (True, True)])
+def test_loop_matches_oracle_loop_fp32(squared, recompute):
+    # the unsquared loss with full activations, and the paper's squared loss with activation
+    # checkpointing
     from paper_2607_16906_amd import hz
     from paper_2607_16906_amd.train import Trainer
     levels, base, nint, p = 3, 8, 24, 4
@@ -39,10 +42,11 @@ def test_loop_matches_oracle_loop_fp32():
     theta0 = he_uniform(unet.init_shapes(specs), rng_for(42, 2, 0))
     orders = [epoch_order(S, e) for e in range(epochs)]
     net = hz.Net(levels, base, 5, theta0)
-    tr = Trainer(net, gtr, bd, gva, vbd, batch=batch, prec="fp32")
+    tr = Trainer(net, gtr, bd, gva, vbd, batch=batch, prec="fp32", squared=squared, recompute=recompute)
     res = tr.fit(theta0, orders, lr0=1e-2, lr_min=1e-3, clip=1.0)
     ref = otl.train(theta0.astype(np.float64), specs, otr, b.astype(np.complex128), ova,
-                    vb.astype(np.complex128), orders, batch=batch, lr0=1e-2, lr_min=1e-3, clip=1.0)
+                    vb.astype(np.complex128), orders, batch=batch, lr0=1e-2, lr_min=1e-3, clip=1.0,
+                    squared=squared)
     tl_err = np.max(np.abs(res.train_loss - ref.train_loss) / np.asarray(ref.train_loss))
     vl_err = np.max(np.abs(np.asarray(res.val_loss) - ref.val_loss) / np.asarray(ref.val_loss))
     moved = np.linalg.norm(ref.theta_last - theta0)
