@@ -42,3 +42,31 @@ def test_binding_loads_and_covers_the_header():
     # a pure host query needs no GPU
     assert hz.param_count(4, 32, 5) == 1_926_210
     assert lib.hz_last_error() == b""
+
+
+def test_param_counts_of_both_network_kinds_on_the_cpu():
+    # no_param_count is host logic: it needs no GPU
+    from paper_2607_16906_amd import hz
+    from oracle import unet, unet8
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    assert hz.param_count(4, 32, 5) == unet.param_count(unet.layer_specs(4, 32, 5))
+    assert hz.param_count(4, 32, 5, "paper8") == unet8.param_count(unet8.layer_specs(4, 32, 5))
+    assert hz.param_count(3, 32, 2, "paper8") == unet8.param_count(unet8.layer_specs(3, 32, 2))
+    for bad in ((4, 16, 5, "paper8"), (6, 32, 5, "paper8"), (7, 32, 5, "unet3"), (4, 12, 5, "unet3")):
+        with pytest.raises(ValueError):
+            hz.param_count(*bad)
+
+
+def test_training_loop_schedule_matches_torch_scheduler():
+    # the GPU loop's host-side schedule: torch's CosineAnnealingLR stepped once per epoch
+    import torch
+    from paper_2607_16906_amd.train import cosine_lr
+    for epochs in (1, 2, 7, 500):
+        p = torch.nn.Parameter(torch.zeros(1))
+        opt = torch.optim.SGD([p], lr=1e-3)
+        sch = torch.optim.lr_scheduler.CosineAnnealingLR(opt, T_max=max(epochs - 1, 1), eta_min=1e-5)
+        for e in range(epochs):
+            assert abs(opt.param_groups[0]["lr"] - cosine_lr(e, epochs)) <= 1e-15
+            opt.step()
+            sch.step()
