@@ -70,12 +70,14 @@ def test_layers_fp64_match_oracle():
         assert rel(to_np(y).transpose(0, 3, 1, 2), unet8.prelu(unet8.up(x, Wu, bu), au)) <= 1e-13
 
 
-@pytest.mark.parametrize("nt,p,depth", [(74, 10, 4), (45, 6, 3), (16, 4, 4), (296, 20, 4)])
-def test_precond_matches_oracle(nt, p, depth):
+@pytest.mark.parametrize("nt,p,depth,in_ch", [(74, 10, 4, 5), (45, 6, 3, 5), (16, 4, 4, 5), (296, 20, 4, 5),
+                                               (30, 4, 1, 2), (70, 5, 5, 2)])
+def test_precond_matches_oracle(nt, p, depth, in_ch):
     # grids padded to a multiple of 2^depth: 74 -> 80, 45 -> 48, 16 exact, 296 -> 304 (the
-    # single-solve grid)
+    # single-solve grid), 30 -> 30 (depth 1), 70 -> 96 (depth 5); two input channels (the field
+    # alone) in the last two
     from paper_2607_16906_amd import hz
-    specs, theta, net = net8(depth=depth, seed=depth)
+    specs, theta, net = net8(depth=depth, seed=depth, in_ch=in_ch)
     c = skull_ring_velocity(nt, p, rng_for(21, 0, nt), rings=2)
     op, gp = make_pair(c, p)
     v = box_smoothed_noise(nt, rng_for(21, 3, nt))
@@ -94,7 +96,8 @@ def test_precond_matches_oracle(nt, p, depth):
     assert torch.count_nonzero(z0).item() == 0
 
 
-def test_fgmres_fp64_with_paper_network_matches_oracle():
+@pytest.mark.parametrize("ortho", ["cgs2", "dcgs2"])
+def test_fgmres_fp64_with_paper_network_matches_oracle(ortho):
     from paper_2607_16906_amd import hz
     specs, theta, net = net8(seed=5)
     nt, p = 40, 6
@@ -105,7 +108,7 @@ def test_fgmres_fp64_with_paper_network_matches_oracle():
     A = lambda x: ohz.op_apply(op, x.reshape(nt, nt)).ravel()
     ref = ofg.fgmres(A, M, b, m=20, tol=1e-9, maxit=60)
     x, info = hz.fgmres(gp, to_dev(b, torch.complex128), net=net, m=20, tol=1e-9, maxit=60, krylov="c128",
-                        net_prec="fp64")
+                        net_prec="fp64", ortho=ortho)
     assert info.its == ref.its and info.status == ref.status
     h = np.array(ref.est_history)
     d = np.abs(info.hist - h)
