@@ -53,6 +53,9 @@ struct no_net {
     float* b_f32;                    // biases (FP32; the BF16 path adds them in FP32)
     double* b_f64;
     void* block;
+    hz::Layer* layers_dev;           // device copy of `layers` (for the one-launch repack)
+    int64_t* repack_start;           // device: first repack block of each layer, then the total
+    int64_t repack_blocks;           // repack blocks over all layers
     // autotuned launch variants of the 3x3 layers, keyed by (layer, H, W, batch, precision)
     std::map<std::array<int, 5>, hz::ConvCfg> tuned;
     std::mutex tune_mu;

@@ -88,11 +88,16 @@ static bool build_layers(const no_arch* a, std::vector<Layer>& L, int64_t& npara
 // padded with zeros) in BF16, FP32 and FP64, and its bias into FP32 and FP64.
 // The data-gradient packs hold the same values at [8 - tap][ci][co] (3x3) or [ab][ci][co]
 // (transposed convolutions).
-__global__ void k_repack(const float* __restrict__ theta, Layer ly, bf16_t* __restrict__ wb,
+// One launch covers every layer: the blocks of layer l are [start[l], start[l + 1]).
+__global__ void k_repack(const float* __restrict__ theta, const Layer* __restrict__ layers,
+                         const int64_t* __restrict__ start, int nl, bf16_t* __restrict__ wb,
                          float* __restrict__ wf, double* __restrict__ wd, float* __restrict__ bf,
                          double* __restrict__ bd, bf16_t* __restrict__ tb, float* __restrict__ tf,
                          double* __restrict__ td) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int l = 0;
+    while (l + 1 < nl && (int64_t)blockIdx.x >= start[l + 1]) ++l;
+    const Layer ly = layers[l];
+    const int64_t idx = ((int64_t)blockIdx.x - start[l]) * blockDim.x + threadIdx.x;
     if (idx < ly.pk_len) {
         const int cis = (int)(idx % ly.cin_p);      // stored input channel
         const int64_t r = idx / ly.cin_p;
@@ -145,12 +150,10 @@ __global__ void k_repack(const float* __restrict__ theta, Layer ly, bf16_t* __re
 }
 
 static int repack_all(no_net* net, const float* theta, hipStream_t s) {
-    for (const Layer& ly : net->layers) {
-        const int64_t n = ly.pk_len > ly.cout_p ? ly.pk_len : ly.cout_p;
-        hipLaunchKernelGGL(k_repack, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, theta, ly, net->w_bf,
-                           net->w_f32, net->w_f64, net->b_f32, net->b_f64, net->wt_bf, net->wt_f32, net->wt_f64);
-        HZ_LAUNCH_CHECK();
-    }
+    hipLaunchKernelGGL(k_repack, dim3((unsigned)net->repack_blocks), dim3(256), 0, s, theta, net->layers_dev,
+                       net->repack_start, (int)net->layers.size(), net->w_bf, net->w_f32, net->w_f64, net->b_f32,
+                       net->b_f64, net->wt_bf, net->wt_f32, net->wt_f64);
+    HZ_LAUNCH_CHECK();
     return HZ_OK;
 }
 
@@ -535,7 +538,9 @@ extern "C" int no_net_create(const no_arch* a, const float* theta, void* stream,
         return HZ_ERR_ARG;
     }
     net->a = *a;
-    const size_t bytes = 2 * net->pk_total * (2 + 4 + 8) + net->bias_total * (4 + 8) + 8 * 256;
+    const size_t nl = net->layers.size();
+    const size_t bytes = 2 * net->pk_total * (2 + 4 + 8) + net->bias_total * (4 + 8) + nl * sizeof(Layer) +
+                         (nl + 1) * sizeof(int64_t) + 10 * 256;
     if (hipMalloc(&net->block, bytes) != hipSuccess) {
         delete net;
         set_error("no_net_create: hipMalloc failed");
@@ -550,8 +555,23 @@ extern "C" int no_net_create(const no_arch* a, const float* theta, void* stream,
     net->wt_bf = c.take<bf16_t>(net->pk_total);
     net->wt_f32 = c.take<float>(net->pk_total);
     net->wt_f64 = c.take<double>(net->pk_total);
+    net->layers_dev = c.take<Layer>(nl);
+    net->repack_start = c.take<int64_t>(nl + 1);
+    std::vector<int64_t> start(nl + 1, 0);
+    for (size_t l = 0; l < nl; ++l) {
+        const Layer& ly = net->layers[l];
+        const int64_t n = std::max<int64_t>(ly.pk_len, ly.cout_p);
+        start[l + 1] = start[l] + (n + 255) / 256;
+    }
+    net->repack_blocks = start[nl];
     hipStream_t s = (hipStream_t)stream;
-    int rc = repack_all(net, theta, s);
+    int rc = HZ_OK;
+    if (hipMemcpy(net->layers_dev, net->layers.data(), nl * sizeof(Layer), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(net->repack_start, start.data(), (nl + 1) * sizeof(int64_t), hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("no_net_create: copying the layer table failed");
+        rc = HZ_ERR_HIP;
+    }
+    if (rc == HZ_OK) rc = repack_all(net, theta, s);
     if (rc == HZ_OK && hipStreamSynchronize(s) != hipSuccess) rc = HZ_ERR_HIP;
     if (rc != HZ_OK) {
         (void)hipFree(net->block);
