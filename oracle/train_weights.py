@@ -12,8 +12,11 @@ mixture of velocity and source classes like dataset D0 (Table 4) with skull
 rings standing in for the idealized skulls. Grids are small (the network is
 fully convolutional and is applied to larger grids later, Section 4.2).
 
+With --arch paper8 it trains Table 2's own layer set (oracle/unet8.py: --levels is the depth and
+--base the channels per layer) instead of the 3x3 network.
+
 Usage: python -m oracle.train_weights --out FILE [--steps N] [--batch B] [--levels L]
-       [--base C] [--resume CKPT] [--ckpt CKPT] [--lr0 LR] [--restart STEP]
+       [--base C] [--resume CKPT] [--ckpt CKPT] [--lr0 LR] [--restart STEP] [--arch unet3|paper8]
 """
 from __future__ import annotations
 
@@ -24,7 +27,7 @@ import time
 
 import numpy as np
 
-from oracle import adam, unet
+from oracle import adam, unet, unet8
 from oracle import helmholtz as hz
 from synth import C_REF, H_10PPW, he_uniform, mixed_training_sample, rng_for
 
@@ -50,11 +53,11 @@ def lr_at(step: int, total: int, lr0: float = 1e-3, lr_min: float = 1e-5, restar
     return lr_min + 0.5 * (lr0 - lr_min) * (1.0 + math.cos(math.pi * k / span))
 
 
-def save(path, theta, specs, levels, base, in_ch, step, loss_hist, m=None, v=None):
+def save(path, theta, specs, levels, base, in_ch, step, loss_hist, m=None, v=None, arch="unet3"):
     tmp = path + ".tmp.npz"
     extra = {} if m is None else {"adam_m": m, "adam_v": v}
     np.savez(tmp, theta=np.asarray(theta, np.float32), levels=levels, base=base, in_ch=in_ch,
-             step=step, loss=np.asarray(loss_hist, np.float64), **extra)
+             step=step, loss=np.asarray(loss_hist, np.float64), arch=arch, **extra)
     os.replace(tmp, path)
 
 
@@ -72,10 +75,17 @@ def main():
     ap.add_argument("--save-every", type=int, default=100)
     ap.add_argument("--lr0", type=float, default=1e-3, help="peak learning rate of the cosine schedule")
     ap.add_argument("--restart", type=int, default=0, help="step at which the cosine schedule restarts")
+    ap.add_argument("--arch", default="unet3", choices=["unet3", "paper8"])
     args = ap.parse_args()
 
-    specs = unet.layer_specs(args.levels, args.base, args.in_ch)
-    theta = he_uniform(unet.init_shapes(specs), rng_for(42, 2, 0)).astype(np.float64)
+    if args.arch == "paper8":
+        net = unet8
+        specs = unet8.layer_specs(args.levels, args.base, args.in_ch)
+        theta = unet8.init_theta(specs, rng_for(42, 2, 0)).astype(np.float64)
+    else:
+        net = unet
+        specs = unet.layer_specs(args.levels, args.base, args.in_ch)
+        theta = he_uniform(unet.init_shapes(specs), rng_for(42, 2, 0)).astype(np.float64)
     m = np.zeros_like(theta)
     v = np.zeros_like(theta)
     start, hist = 0, []
@@ -88,7 +98,7 @@ def main():
     t0 = time.time()
     for step in range(start, args.steps):
         problems, rs = sample_batch(step, args.batch, args.nint)
-        loss, _, g = unet.loss_and_grad(theta.astype(np.float32), specs, problems, rs, dtype=np.float32)
+        loss, _, g = net.loss_and_grad(theta.astype(np.float32), specs, problems, rs, dtype=np.float32)
         theta, m, v = adam.adam_step(theta, g.astype(np.float64), m, v, step + 1,
                                      lr=lr_at(step, args.steps, args.lr0, restart=args.restart), clip=1.0)
         hist.append(loss)
@@ -97,9 +107,10 @@ def main():
                   f"lr {lr_at(step, args.steps, args.lr0, restart=args.restart):.2e} "
                   f"{(time.time() - t0) / (step + 1 - start):.2f} s/step", flush=True)
         if (step + 1) % args.save_every == 0 or step + 1 == args.steps:
-            save(args.out, theta, specs, args.levels, args.base, args.in_ch, step + 1, hist)
+            save(args.out, theta, specs, args.levels, args.base, args.in_ch, step + 1, hist, arch=args.arch)
             if args.ckpt:
-                save(args.ckpt, theta, specs, args.levels, args.base, args.in_ch, step + 1, hist, m, v)
+                save(args.ckpt, theta, specs, args.levels, args.base, args.in_ch, step + 1, hist, m, v,
+                     arch=args.arch)
 
 
 if __name__ == "__main__":

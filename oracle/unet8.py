@@ -95,6 +95,16 @@ def init_theta(specs, rng: np.random.Generator, slope: float = 0.25) -> np.ndarr
 
 # --------------------------------------------------------------------------- layers
 
+def _mix(M, x):
+    """sum_c M[o, c] x[b, c, h, w] -> [b, o, h, w] (a matrix product over the channel axis)."""
+    return np.moveaxis(np.tensordot(M, x, axes=([1], [1])), 0, 1)
+
+
+def _corr(g, x):
+    """sum_{b, h, w} g[b, o, h, w] x[b, c, h, w] -> [o, c]."""
+    return np.tensordot(g, x, axes=([0, 2, 3], [0, 2, 3]))
+
+
 def down(x, W, b):
     """8x8 stride-2 padding-3 convolution of x [B, C, H, W] (H, W even) -> [B, O, H/2, W/2]."""
     B, C, H, Wd = x.shape
@@ -104,9 +114,23 @@ def down(x, W, b):
     y = np.zeros((B, W.shape[0], Ho, Wo), x.dtype)
     for a in range(K8):
         for e in range(K8):
-            patch = xp[:, :, a:a + S8 * Ho:S8, e:e + S8 * Wo:S8]
-            y += np.einsum("oc,bchw->bohw", W[:, :, a, e], patch)
+            y += _mix(W[:, :, a, e], xp[:, :, a:a + S8 * Ho:S8, e:e + S8 * Wo:S8])
     return y + b[None, :, None, None]
+
+
+def down_backward(x, W, g):
+    """Reverse mode of down: (dx, dW, db) for the output gradient g [B, O, H/2, W/2]."""
+    B, C, H, Wd = x.shape
+    Ho, Wo = g.shape[2], g.shape[3]
+    xp = np.zeros((B, C, H + 2 * P8, Wd + 2 * P8), x.dtype)
+    xp[:, :, P8:P8 + H, P8:P8 + Wd] = x
+    dxp = np.zeros_like(xp)
+    dW = np.zeros_like(W)
+    for a in range(K8):
+        for e in range(K8):
+            dW[:, :, a, e] = _corr(g, xp[:, :, a:a + S8 * Ho:S8, e:e + S8 * Wo:S8])
+            dxp[:, :, a:a + S8 * Ho:S8, e:e + S8 * Wo:S8] += _mix(W[:, :, a, e].T, g)
+    return dxp[:, :, P8:P8 + H, P8:P8 + Wd], dW, g.sum(axis=(0, 2, 3))
 
 
 def up(x, W, b):
@@ -117,34 +141,107 @@ def up(x, W, b):
     full = np.zeros((B, W.shape[1], (H - 1) * S8 + K8, (Wd - 1) * S8 + K8), x.dtype)
     for a in range(K8):
         for e in range(K8):
-            full[:, :, a:a + S8 * H:S8, e:e + S8 * Wd:S8] += np.einsum("co,bchw->bohw", W[:, :, a, e], x)
+            full[:, :, a:a + S8 * H:S8, e:e + S8 * Wd:S8] += _mix(W[:, :, a, e].T, x)
     return full[:, :, P8:P8 + Ho, P8:P8 + Wo] + b[None, :, None, None]
 
 
+def up_backward(x, W, g):
+    """Reverse mode of up: (dx, dW, db) for the output gradient g [B, O, 2H, 2W]."""
+    B, C, H, Wd = x.shape
+    full = np.zeros((B, W.shape[1], (H - 1) * S8 + K8, (Wd - 1) * S8 + K8), x.dtype)
+    full[:, :, P8:P8 + g.shape[2], P8:P8 + g.shape[3]] = g
+    dx = np.zeros_like(x)
+    dW = np.zeros_like(W)
+    for a in range(K8):
+        for e in range(K8):
+            gs = full[:, :, a:a + S8 * H:S8, e:e + S8 * Wd:S8]
+            dx += _mix(W[:, :, a, e], gs)
+            dW[:, :, a, e] = _corr(x, gs)
+    return dx, dW, g.sum(axis=(0, 2, 3))
+
+
 def conv1(x, W, b):
-    return np.einsum("oc,bchw->bohw", W[:, :, 0, 0], x) + b[None, :, None, None]
+    return _mix(W[:, :, 0, 0], x) + b[None, :, None, None]
 
 
 def prelu(x, a):
     return np.where(x > 0, x, a * x)
 
 
-def forward(theta, specs, X, act_round=None):
+def prelu_backward(s, a, g):
+    """(ds, da) of y = prelu(s, a) for the output gradient g."""
+    neg = s <= 0
+    return np.where(neg, a * g, g), float(np.sum(np.where(neg, s * g, 0.0)))
+
+
+def forward(theta, specs, X, act_round=None, keep=False):
     """Network output [B, 2, Hp, Wp] for the packed input X (act_round: optional rounding of
-    every stored activation, as in unet.forward)."""
+    every stored activation, as in unet.forward). keep: also return the cache for backward."""
     rnd = act_round if act_round is not None else (lambda t: t)
     P = unpack(np.asarray(theta, dtype=X.dtype), specs)
     depth = sum(1 for s in specs if s[1] == "down")
+    cache = {}
     E = [rnd(X)]
     for l in range(1, depth + 1):
         W, b, a = P[f"down{l}"]
-        E.append(rnd(prelu(down(E[-1], W, b), a)))
+        s = down(E[-1], W, b)
+        cache[f"down{l}"] = (E[-1], s)
+        E.append(rnd(prelu(s, a)))
     W, b, a = P[f"up{depth - 1}"]
-    U = rnd(prelu(up(E[depth], W, b), a))
+    s = up(E[depth], W, b)
+    cache[f"up{depth - 1}"] = (E[depth], s)
+    U = rnd(prelu(s, a))
     for l in range(depth - 2, -1, -1):
         W, b, a = P[f"up{l}"]
-        U = rnd(prelu(up(np.concatenate([E[l + 1], U], axis=1), W, b), a))
-    return conv1(U, *P["head"][:2])
+        xin = np.concatenate([E[l + 1], U], axis=1)
+        s = up(xin, W, b)
+        cache[f"up{l}"] = (xin, s)
+        U = rnd(prelu(s, a))
+    cache["head"] = (U, None)
+    out = conv1(U, *P["head"][:2])
+    return (out, cache) if keep else out
+
+
+def backward(theta, specs, cache, gout):
+    """Gradient of sum(gout * forward(theta, X)) with respect to theta (flat, the layout of
+    unpack), from the cache of forward(keep=True)."""
+    P = unpack(np.asarray(theta, dtype=gout.dtype), specs)
+    depth = sum(1 for s in specs if s[1] == "down")
+    grads = {}
+    U = cache["head"][0]
+    Wh = P["head"][0]
+    grads["head"] = (_corr(gout, U)[:, :, None, None], gout.sum(axis=(0, 2, 3)), None)
+    gU = _mix(Wh[:, :, 0, 0].T, gout)
+    gE = {}
+    for l in range(0, depth):               # up0, up1, ..., up(depth-1)
+        W, b, a = P[f"up{l}"]
+        xin, s = cache[f"up{l}"]
+        gs, ga = prelu_backward(s, a, gU)
+        gx, gW, gb = up_backward(xin, W, gs)
+        grads[f"up{l}"] = (gW, gb, ga)
+        if l < depth - 1:                   # input concat[E_{l+1}, U_{l+1}]
+            ce = gx.shape[1] // 2
+            gE[l + 1] = gx[:, :ce]
+            gU = gx[:, ce:]
+        else:                               # the deepest takes E_depth alone
+            gE[depth] = gx
+    g = gE[depth]
+    for l in range(depth, 0, -1):           # down(depth), ..., down1
+        W, b, a = P[f"down{l}"]
+        xin, s = cache[f"down{l}"]
+        gs, ga = prelu_backward(s, a, g)
+        gx, gW, gb = down_backward(xin, W, gs)
+        grads[f"down{l}"] = (gW, gb, ga)
+        if l > 1:
+            g = gx + gE[l - 1]
+    parts = []
+    for name, kind, ci, co in specs:
+        gW, gb, ga = grads[name]
+        parts.append(np.asarray(gW).ravel())
+        parts.append(np.asarray(gb).ravel())
+        if kind != "conv1":
+            parts.append(np.array([ga]))
+    return np.concatenate(parts)
 
 
 def precond_apply(theta, specs, p: hz.Problem, v, dtype=np.float64, act_round=None):
@@ -156,3 +253,34 @@ def precond_apply(theta, specs, p: hz.Problem, v, dtype=np.float64, act_round=No
         return np.zeros((p.ny, p.nx), np.complex128)
     out = forward(np.asarray(theta, dtype=dtype), specs, X, act_round=act_round)
     return s * (out[0, 0, :p.ny, :p.nx].astype(np.float64) + 1j * out[0, 1, :p.ny, :p.nx].astype(np.float64))
+
+
+def loss_and_grad(theta, specs, problems, rs, squared=False, dtype=np.float64, need_grad=True):
+    """Batch-mean physics-informed loss (eq. (12); unsquared unless squared) and its gradient with
+    respect to theta for this network; problems share one grid size, rs [B, ny, nx] complex."""
+    B = len(problems)
+    in_ch = specs[0][2]
+    depth = sum(1 for s in specs if s[1] == "down")
+    theta = np.asarray(theta, dtype=dtype)
+    Xs, ss = zip(*(pack_input(rs[b], problems[b], in_ch, depth + 1, dtype) for b in range(B)))
+    out, cache = forward(theta, specs, np.concatenate(Xs), keep=True)
+    gout = np.zeros_like(out)
+    losses = np.empty(B)
+    for b in range(B):
+        p = problems[b]
+        z = ss[b] * (out[b, 0, :p.ny, :p.nx].astype(np.float64) + 1j * out[b, 1, :p.ny, :p.nx].astype(np.float64))
+        q = hz.op_apply(p, z) - rs[b]
+        nq, nr = np.linalg.norm(q), np.linalg.norm(rs[b])
+        if squared:
+            losses[b] = nq * nq / (nr * nr)
+            gq = 2.0 * q / (B * nr * nr)
+        else:
+            losses[b] = nq / nr
+            gq = q / (B * nq * nr) if nq > 0 else np.zeros_like(q)
+        gz = hz.op_adjoint(p, gq)
+        gout[b, 0, :p.ny, :p.nx] = ss[b] * gz.real
+        gout[b, 1, :p.ny, :p.nx] = ss[b] * gz.imag
+    loss = float(losses.mean())
+    if not need_grad:
+        return loss, losses, None
+    return loss, losses, backward(theta, specs, cache, gout.astype(dtype))

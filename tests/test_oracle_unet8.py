@@ -133,3 +133,74 @@ def test_precond_scale_equivariance_zero_and_padding():
     assert z.shape == (30, 30)
     assert np.allclose(unet8.precond_apply(theta, specs, P, 2.5 * v), 2.5 * z, rtol=1e-12, atol=1e-14)
     assert np.all(unet8.precond_apply(theta, specs, P, 0 * v) == 0)
+
+
+def test_backward_matches_torch_autograd():
+    # the reverse mode of the whole network against autograd over the independent torch statement,
+    # with a different PReLU slope of either sign in every layer
+    specs = unet8.layer_specs(3, 32, 5)
+    theta = unet8.init_theta(specs, np.random.default_rng(21)).astype(np.float64)
+    r = np.random.default_rng(22)
+    off = 0
+    for _, kind, ci, co in specs:
+        off += unet8.layer_len(kind, ci, co)
+        if kind != "conv1":
+            theta[off - 1] = r.uniform(-0.3, 0.6)
+    X = rand(2, 5, 32, 48, seed=23)
+    gout = rand(2, 2, 32, 48, seed=24)
+    out, cache = unet8.forward(theta, specs, X, keep=True)
+    g = unet8.backward(theta, specs, cache, gout)
+    th = torch.tensor(theta, requires_grad=True)
+
+    def torch_net(t):
+        P, o = {}, 0
+        for name, kind, ci, co in specs:
+            shp = unet8.weight_shape(kind, ci, co)
+            nw = int(np.prod(shp))
+            P[name] = (t[o:o + nw].reshape(shp), t[o + nw:o + nw + co],
+                       t[o + nw + co:o + nw + co + 1] if kind != "conv1" else None)
+            o += unet8.layer_len(kind, ci, co)
+        h = torch.from_numpy(X)
+        skips = [h]
+        for l in range(1, 4):
+            W, b, a = P[f"down{l}"]
+            h = F.prelu(F.conv2d(h, W, b, stride=2, padding=3), a)
+            skips.append(h)
+        W, b, a = P["up2"]
+        h = F.prelu(F.conv_transpose2d(h, W, b, stride=2, padding=3), a)
+        for l in (1, 0):
+            W, b, a = P[f"up{l}"]
+            h = F.prelu(F.conv_transpose2d(torch.cat([skips[l + 1], h], 1), W, b, stride=2, padding=3), a)
+        W, b, _ = P["head"]
+        return F.conv2d(h, W, b)
+
+    y = torch_net(th)
+    assert np.max(np.abs(y.detach().numpy() - out)) <= 1e-12 * np.abs(out).max()
+    (y * torch.from_numpy(gout)).sum().backward()
+    assert np.max(np.abs(th.grad.numpy() - g)) <= 1e-11 * np.max(np.abs(g))
+
+
+@pytest.mark.parametrize("squared", [False, True])
+def test_loss_gradient_finite_differences(squared):
+    # the physics-informed loss through A and this network: central differences along three random
+    # directions (FP64, 32 x 32 grid: 24 interior + 4 PML, depth 3)
+    specs = unet8.layer_specs(3, 32, 5)
+    theta = unet8.init_theta(specs, np.random.default_rng(25)).astype(np.float64)
+    probs, rs = [], []
+    for s in range(2):
+        c = skull_ring_velocity(32, 4, rng_for(9, 0, 40 + s), rings=1)
+        probs.append(hz.Problem(c, 4, H_10PPW, 1.0, 2.0, C_REF))
+        rs.append(box_smoothed_noise(32, np.random.default_rng(50 + s)))
+    rs = np.stack(rs)
+    loss, per, g = unet8.loss_and_grad(theta, specs, probs, rs, squared=squared)
+    assert np.isclose(loss, per.mean())
+    rng = np.random.default_rng(26)
+    for _ in range(3):
+        d = rng.standard_normal(theta.size)
+        d /= np.linalg.norm(d)
+        eps = 1e-6
+        lp = unet8.loss_and_grad(theta + eps * d, specs, probs, rs, squared=squared, need_grad=False)[0]
+        lm = unet8.loss_and_grad(theta - eps * d, specs, probs, rs, squared=squared, need_grad=False)[0]
+        fd = (lp - lm) / (2 * eps)
+        an = float(g @ d)
+        assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
