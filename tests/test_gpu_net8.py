@@ -1,6 +1,8 @@
 """GPU parity of the paper's own network (NO_ARCH_PAPER8: 8x8 stride-2 layers, PReLU; Table 2)
 against the oracle (oracle/unet8.py): each layer form in FP64, the whole preconditioner in FP64 /
 FP32 / BF16 on ragged grids, and an FP64 FGMRES history with it as the preconditioner."""
+import os
+
 import numpy as np
 import pytest
 
@@ -128,3 +130,50 @@ def test_paper_network_rejected_where_unsupported():
         hz.fgmres_batched([gp], [r[0]], net=net, m=5, maxit=5)
     with pytest.raises(ValueError):
         hz.Net(4, 16, 5, np.zeros(10, np.float32), kind="paper8")
+
+
+WEIGHTS8 = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2607_16906_amd", "weights", "paper8_d4_c32_in5.npz")
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS8), reason="oracle-trained weights of the paper's network missing")
+def test_trained_paper_network_fgmres_fp64_matches_oracle():
+    # with the weights the oracle trained for this network: FP64 FGMRES on a small grid, the whole
+    # residual history, iteration count and solution against the oracle
+    from paper_2607_16906_amd import hz
+    w = np.load(WEIGHTS8)
+    theta = w["theta"].astype(np.float32)
+    specs = unet8.layer_specs(4, 32, 5)
+    net = hz.Net(4, 32, 5, theta, kind="paper8")
+    nt, p = 40, 8
+    c = skull_ring_velocity(nt, p, rng_for(21, 0, 7), rings=1)
+    b = gaussian_sources(nt, p, rng_for(21, 1, 7))
+    op, gp = make_pair(c, p)
+    M = lambda v: unet8.precond_apply(theta.astype(np.float64), specs, op, v.reshape(nt, nt)).ravel()
+    A = lambda x: ohz.op_apply(op, x.reshape(nt, nt)).ravel()
+    ref = ofg.fgmres(A, M, b, m=30, tol=1e-8, maxit=300)
+    x, info = hz.fgmres(gp, to_dev(b, torch.complex128), net=net, m=30, tol=1e-8, maxit=300, krylov="c128",
+                        net_prec="fp64")
+    print(f"trained paper network, 40^2: oracle its {ref.its}, GPU its {info.its}")
+    assert ref.status == 0 and info.status == 0 and info.its == ref.its
+    h = np.array(ref.est_history)
+    d = np.abs(info.hist - h)
+    assert np.all(d <= 1e-10 * h + 1e-14), float(np.max(d / (1e-10 * h + 1e-14)))
+    assert rel(to_np(x), ref.x) <= 1e-8
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS8), reason="oracle-trained weights of the paper's network missing")
+def test_trained_paper_network_full_size_bf16_solve():
+    # the single-solve system (296^2) with the BF16 paper network: converged, and the true residual
+    # recomputed by the oracle's FP64 operator
+    from paper_2607_16906_amd import hz
+    from synth import H_10PPW, c2_system
+    w = np.load(WEIGHTS8)
+    net = hz.Net(4, 32, 5, w["theta"].astype(np.float32), kind="paper8")
+    s = c2_system(0)
+    op, gp = make_pair(s.c, s.npml)
+    x, info = hz.fgmres(gp, to_dev(s.b, torch.complex128), net=net, m=30, tol=1e-6, maxit=3000)
+    xr = to_np(x).reshape(s.nt, s.nt)
+    tr = np.linalg.norm(s.b - ohz.op_apply(op, xr)) / np.linalg.norm(s.b)
+    print(f"trained paper network, 296^2 BF16: its {info.its}, true relres {tr:.3e}")
+    assert info.status == 0 and tr <= 1e-6 and abs(tr - info.true_relres) <= 1e-9
