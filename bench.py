@@ -278,6 +278,18 @@ def bench_paper8(hz, torch, net3, reps=50):
     out["fgmres_true_relres"] = float(f"{info.true_relres:.3e}")
     if info.status == 0:
         out["solves_per_s"] = round(1.0 / dt, 3)
+    # at the training size (64^2 interior + 16 PML): iterations of both networks and of GMRES on
+    # five seeded systems of the single-solve kind
+    small = {"paper8": [], "unet3": [], "gmres": []}
+    for sid in range(5):
+        ss = c2_system(sid, nx=64, npml=16)
+        gs = hz.Problem(ss.c.astype(np.float32).ravel(), ss.nx, ss.nx, ss.npml, H_10PPW)
+        bs = torch.from_numpy(ss.b.ravel()).cuda()
+        for tag, nn in (("paper8", net8), ("unet3", net3), ("gmres", None)):
+            _, inf = hz.fgmres(gs, bs, net=nn, m=30, tol=1e-6, maxit=1000)
+            small[tag].append(inf.its if inf.status == 0 else -inf.its)
+    out["its_64_interior"] = small
+    out["its_64_interior_note"] = "FGMRES(30) to 1e-6, BF16 networks, 5 systems; negative: not converged"
     return out
 
 
