@@ -293,6 +293,49 @@ def bench_paper8(hz, torch, net3, reps=50):
     return out
 
 
+def bench_train_then_solve(hz, torch, S=4096, V=256, batch=32, epochs=30, nint=64, npml=16):
+    """The whole method on the GPU: train the 4-level / 32-channel network from the seeded initial
+    weights with the epoch-based loop (BF16, S samples of the D0-like mixture at 64^2 + 16 PML,
+    cosine 1e-3 -> 1e-5, clip 1, best epoch by validation loss), then solve the single-solve system
+    (296^2, FGMRES(30), tol 1e-6) preconditioned by the saved epoch's weights. These weights live
+    only in this run (the committed weights come from the oracle's training)."""
+    from synth import CFG_C3, COMP_WEIGHTS, H_10PPW, VAL_FIRST, c2_system, epoch_order, he_uniform, rng_for, \
+        training_set
+    from paper_2607_16906_amd.train import Trainer, resident_set
+    nt = nint + 2 * npml
+    t0 = time.perf_counter()
+    c, b = training_set(S, nt, npml)
+    vc, vb = training_set(V, nt, npml, first=VAL_FIRST)
+    probs, r = resident_set(c, b, nint, npml, H_10PPW)
+    vprobs, vr = resident_set(vc, vb, nint, npml, H_10PPW)
+    t_data = time.perf_counter() - t0
+    theta0 = he_uniform(hz.init_shapes(LEVELS, BASE, IN_CH), rng_for(CFG_C3, COMP_WEIGHTS, 0))
+    net = hz.Net(LEVELS, BASE, IN_CH, theta0)
+    tr = Trainer(net, probs, r, vprobs, vr, batch=batch, prec="bf16")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = tr.fit(theta0, [epoch_order(S, e) for e in range(epochs)])
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    net.set_weights(res.theta_best)
+    s = c2_system(0)
+    gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW)
+    bb = torch.from_numpy(s.b.ravel()).cuda()
+    hz.fgmres(gp, bb, net=net, m=M_RESTART, tol=TOL, maxit=M_RESTART)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = hz.fgmres(gp, bb, net=net, m=M_RESTART, tol=TOL, maxit=3000)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": f"train {epochs} epochs x {S} samples (+{V} validation) at {nint}^2 + {npml} PML, batch "
+                        f"{batch}, BF16, from seeded weights; then FGMRES(30) to 1e-6 on the 296^2 system",
+            "data_s": round(t_data, 2), "train_s": round(t_train, 2), "steps": len(res.train_loss),
+            "ms_per_step": round(res.step_ms, 3), "best_epoch": res.best_epoch,
+            "val_loss_first_best": [round(res.val_loss[0], 4), round(res.best_val, 4)],
+            "its": info.its, "converged": info.status == 0, "true_relres": float(f"{info.true_relres:.3e}"),
+            "solves_per_s": round(1.0 / dt, 3) if info.status == 0 else 0.0}
+
+
 def bench_batched(hz, torch, net, nsys=128, maxit=30):
     """Ragged batch: the 128 systems of the batched-serving mix (128..512 interior + 16..32 PML, each
     with its own velocity and sources), BF16 network, FGMRES(30), advanced together for one cycle
@@ -522,8 +565,8 @@ def main():
                     help="with --roofline-only: time this layer alone (for a profiler run of one kernel)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="with --roofline-only: also copy 512 MiB with a plain device copy (counter calibration)")
-    ap.add_argument("--only", choices=["training", "training_loop", "batched", "large", "restart", "spectral",
-                                       "appendix_b", "paper8"],
+    ap.add_argument("--only", choices=["training", "training_loop", "train_then_solve", "batched", "large",
+                                       "restart", "spectral", "appendix_b", "paper8"],
                     default=None,
                     help="run one extra section alone and print its JSON (for profiler runs)")
     args = ap.parse_args()
@@ -547,6 +590,8 @@ def main():
             res = bench_training(hz, torch, steps=2)
         elif args.only == "training_loop":
             res = bench_training_loop(hz, torch)
+        elif args.only == "train_then_solve":
+            res = bench_train_then_solve(hz, torch)
         else:
             net1 = hz.Net(LEVELS, BASE, IN_CH, theta)
             res = {"batched": bench_batched, "large": bench_large, "restart": bench_restart,
@@ -658,6 +703,7 @@ def main():
     if not args.no_extra:
         out["training"] = bench_training(hz, torch)
         out["training_loop"] = bench_training_loop(hz, torch)
+        out["train_then_solve"] = bench_train_then_solve(hz, torch)
         out["batched"] = bench_batched(hz, torch, net)
         out["large"] = bench_large(hz, torch, net)
         out["restart"] = bench_restart(hz, torch, net)
