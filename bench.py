@@ -36,6 +36,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "conv3_dominant_layer_296_bf16_tra
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2607_16906_amd", "csrc", f) for f in ("net_fwd.hip", "net_kernels.h")]
 
 
+def note(msg):
+    """One progress line on stderr per finished section (the JSON result goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_fingerprint():
     import hashlib
     h = hashlib.md5()
@@ -700,18 +705,24 @@ def main():
                     f"fp32_{big}_hbm_gbs": round(20 * big * big / (st_big * 1e-3) / 1e9, 1),
                     "hbm_frac": round(20 * big * big / (st_big * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)},
     }
+    note(f"single solve: {out['value']} solves/s BF16, {out['fp32_form']['value']} FP32 form")
     if not args.no_extra:
-        out["training"] = bench_training(hz, torch)
-        out["training_loop"] = bench_training_loop(hz, torch)
-        out["train_then_solve"] = bench_train_then_solve(hz, torch)
-        out["batched"] = bench_batched(hz, torch, net)
-        out["large"] = bench_large(hz, torch, net)
-        out["restart"] = bench_restart(hz, torch, net)
-        out["spectral"] = bench_spectral(hz, torch, net)
-        out["appendix_b"] = bench_appendix_b(hz, torch, net)
-        out["paper8"] = bench_paper8(hz, torch, net)
+        sections = [("training", lambda: bench_training(hz, torch)),
+                    ("training_loop", lambda: bench_training_loop(hz, torch)),
+                    ("train_then_solve", lambda: bench_train_then_solve(hz, torch)),
+                    ("batched", lambda: bench_batched(hz, torch, net)),
+                    ("large", lambda: bench_large(hz, torch, net)),
+                    ("restart", lambda: bench_restart(hz, torch, net)),
+                    ("spectral", lambda: bench_spectral(hz, torch, net)),
+                    ("appendix_b", lambda: bench_appendix_b(hz, torch, net)),
+                    ("paper8", lambda: bench_paper8(hz, torch, net))]
+        for name, fn in sections:
+            t0 = time.perf_counter()
+            out[name] = fn()
+            note(f"{name} done in {time.perf_counter() - t0:.1f} s")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(s, theta, its)
+        note("cpu_baseline done")
     print(json.dumps(out))
 
 

@@ -115,6 +115,112 @@ __global__ __launch_bounds__(KT) void k_stencil_dots(const C* __restrict__ z, St
 }
 
 constexpr int UPD_REG = 32;   // vectors held in registers by the single-pass first update
+constexpr int UPD_SPLIT4 = 24; // up to this many vectors pass 2 splits them over 4 wavefronts
+
+// Pass 2 of the orthogonalisation for FP32 vectors read as point pairs (16-byte aligned, even
+// stride), with V read once for any nv <= NW GMAX: the vectors are split over the NW wavefronts of
+// the block (wavefront q holds vectors [q G, q G + G), G = ceil(nv / NW), in registers). Per tile of
+// 64 pairs each wavefront forms its part of V h; the NW parts and w meet in LDS (double-buffered,
+// one barrier per tile); every wavefront forms the same w' = w - (sum of the parts in wavefront
+// order), wavefront 0 stores it, and each wavefront accumulates conj(V_i) w' for its own vectors,
+// reduced within the wavefront. Writes the same partial layout as k_update<float2, 1>.
+template <int GMAX, int NW>
+__global__ __launch_bounds__(NW * 64) void k_upd1_split(const float2* __restrict__ V, int64_t ldv, int nv,
+                                                   const double2* __restrict__ h, float2* __restrict__ w,
+                                                   int64_t n, int64_t per, double2* __restrict__ part, int ldp,
+                                                   const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const int64_t p0 = blockIdx.x * per, p1 = min(n, p0 + per);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), ln = threadIdx.x & 63;
+    const int G = (nv + NW - 1) / NW;
+    const int i0 = wv * G;
+    const int cnt = max(0, min(G, nv - i0));
+    __shared__ double4 sh[2][NW][64];
+    __shared__ float4 shw[2][64];
+    double ar[GMAX], ai[GMAX];
+#pragma unroll
+    for (int q = 0; q < GMAX; ++q) ar[q] = ai[q] = 0.0;
+    const int64_t len = p1 - p0;
+    const int64_t nunit = (len + 1) >> 1;   // pairs, the last one a single point when len is odd
+    int buf = 0;
+    for (int64_t k0 = 0; k0 < nunit; k0 += 64, buf ^= 1) {
+        const int64_t k = k0 + ln;
+        const bool valid = k < nunit;
+        const bool half = 2 * k + 1 == len;
+        const int64_t p = p0 + 2 * k;
+        float4 vr[GMAX];
+#pragma unroll
+        for (int q = 0; q < GMAX; ++q) {
+            vr[q] = float4{0.f, 0.f, 0.f, 0.f};
+            if (q < cnt && valid) {
+                const float2* src = V + (int64_t)(i0 + q) * ldv + p;
+                if (half) {
+                    const float2 t = src[0];
+                    vr[q] = float4{t.x, t.y, 0.f, 0.f};
+                } else {
+                    vr[q] = *(const float4*)src;
+                }
+            }
+        }
+        if (wv == 0) {
+            float4 a{0.f, 0.f, 0.f, 0.f};
+            if (valid) {
+                if (half) {
+                    const float2 t = w[p];
+                    a = float4{t.x, t.y, 0.f, 0.f};
+                } else {
+                    a = *(const float4*)(w + p);
+                }
+            }
+            shw[buf][ln] = a;
+        }
+        double sx = 0.0, sy = 0.0, tx = 0.0, ty = 0.0;
+#pragma unroll
+        for (int q = 0; q < GMAX; ++q)
+            if (q < cnt) {
+                const float4 v = vr[q];
+                const double2 hi = h[i0 + q];   // wavefront-uniform: scalar loads
+                sx += (double)v.x * hi.x - (double)v.y * hi.y;
+                sy += (double)v.x * hi.y + (double)v.y * hi.x;
+                tx += (double)v.z * hi.x - (double)v.w * hi.y;
+                ty += (double)v.z * hi.y + (double)v.w * hi.x;
+            }
+        sh[buf][wv][ln] = double4{sx, sy, tx, ty};
+        __syncthreads();
+        const float4 a = shw[buf][ln];
+        double ax = a.x, ay = a.y, bx = a.z, by = a.w;
+#pragma unroll
+        for (int r = 0; r < NW; ++r) {
+            const double4 s = sh[buf][r][ln];
+            ax -= s.x;
+            ay -= s.y;
+            bx -= s.z;
+            by -= s.w;
+        }
+        const float4 wp{(float)ax, (float)ay, half ? 0.f : (float)bx, half ? 0.f : (float)by};
+        if (wv == 0 && valid) {
+            if (half)
+                w[p] = float2{wp.x, wp.y};
+            else
+                *(float4*)(w + p) = wp;
+        }
+#pragma unroll
+        for (int q = 0; q < GMAX; ++q)
+            if (q < cnt) {
+                const float4 v = vr[q];
+                ar[q] += (double)v.x * wp.x + (double)v.y * wp.y + (double)v.z * wp.z + (double)v.w * wp.w;
+                ai[q] += (double)v.x * wp.y - (double)v.y * wp.x + (double)v.z * wp.w - (double)v.w * wp.z;
+            }
+    }
+    double2* mine = part + (int64_t)blockIdx.x * ldp + i0;
+#pragma unroll
+    for (int g0 = 0; g0 < GMAX; g0 += IC) {
+        if (g0 >= cnt) break;
+        double (&sr)[IC] = *reinterpret_cast<double (*)[IC]>(&ar[g0]);
+        double (&si)[IC] = *reinterpret_cast<double (*)[IC]>(&ai[g0]);
+        wave_store8(sr, si, mine + g0, cnt - g0);
+    }
+}
 
 template <typename C, int MODE>
 __global__ __launch_bounds__(KT) void k_update(const C* __restrict__ V, int64_t ldv, int nv,
@@ -498,7 +604,16 @@ int launch_update(bool c128, const void* V, int64_t ldv, int nv, const double2* 
         else if (mode == 1) HZ_UPD(double2, 1);
         else HZ_UPD(double2, 2);
     } else {
-        if (mode == 0) HZ_UPD(float2, 0);
+        // pass 2 with the vectors split over the wavefronts where that measured faster (short
+        // bases, and bases too long for k_update's single-pass register form)
+        const bool pairs = (ldv & 1) == 0 && ((((uintptr_t)V) | ((uintptr_t)w)) & 15) == 0;
+        if (mode == 1 && pairs && nv <= UPD_SPLIT4)
+            hipLaunchKernelGGL((k_upd1_split<8, 4>), dim3(sp.nblk), dim3(256), 0, s, (const float2*)V, ldv, nv, h,
+                               (float2*)w, n, sp.per_block, part, ldp, skip);
+        else if (mode == 1 && pairs && nv > UPD_REG && nv <= 64)
+            hipLaunchKernelGGL((k_upd1_split<8, 8>), dim3(sp.nblk), dim3(512), 0, s, (const float2*)V, ldv, nv, h,
+                               (float2*)w, n, sp.per_block, part, ldp, skip);
+        else if (mode == 0) HZ_UPD(float2, 0);
         else if (mode == 1) HZ_UPD(float2, 1);
         else HZ_UPD(float2, 2);
     }

@@ -129,7 +129,9 @@ __device__ __forceinline__ void stencil_tile_wide(const float2* __restrict__ u, 
         a1 = cadd(a1, cmul(w1, u0));
         a1 = cadd(a1, cmul(nj, C{nn.z, nn.w}));
         a1 = cadd(a1, cmul(sj, C{ss.z, ss.w}));
-        *(float4*)(y + p) = float4{a0.x, a0.y, a1.x, a1.y};
+        // streaming (non-temporal) store: this kernel never reads its output
+        typedef float f4v __attribute__((ext_vector_type(4)));
+        __builtin_nontemporal_store(f4v{a0.x, a0.y, a1.x, a1.y}, (f4v*)(y + p));
     }
 }
 

@@ -78,6 +78,27 @@ def test_gmres_fp32_krylov_reaches_tol():
     assert r <= 1e-6 and abs(r - info.true_relres) <= 1e-9
 
 
+@pytest.mark.parametrize("m", [24, 30, 48, 64])
+def test_fp32_krylov_long_basis_matches_oracle(m):
+    # FP32 basis on a grid of 120^2 nodes (57 vector blocks, the last one ragged), one cycle of up
+    # to 64 steps: every orthogonalisation form of the second pass runs (basis split over 4
+    # wavefronts up to 24 vectors, held in registers up to 32, split over 8 wavefronts up to 64).
+    # The residual estimate after every step, the cycle's true residual and its x follow the FP64
+    # oracle's within 1e-4 relative (FP32 vectors, FP64 sums and least squares).
+    from paper_2607_16906_amd import hz
+    c, b, p = small_system(nx=100, p=10, seed=2)
+    op, gp = make_pair(c, p)
+    ref = ofg.fgmres(oracle_A(op), lambda v: v, b, m=m, tol=1e-12, maxit=m)
+    x, info = hz.fgmres(gp, to_dev(b, torch.complex128), m=m, tol=1e-12, maxit=m, krylov="c64")
+    h = np.array(ref.est_history)
+    assert info.its == ref.its == m and info.status == ref.status == 1
+    d = np.abs(info.hist - h) / h
+    print(f"m {m}: max rel history difference {d.max():.2e}, x {rel(to_np(x), ref.x):.2e}")
+    assert np.all(d <= 1e-4), float(d.max())
+    assert abs(info.true_relres - ref.true_relres) <= 1e-4 * ref.true_relres
+    assert rel(to_np(x), ref.x) <= 1e-4
+
+
 @pytest.mark.parametrize("ortho", ["cgs2", "dcgs2"])
 def test_c1_fgmres_fp64_net_matches_oracle(ortho):
     # the plain-FP64 configuration: 64^2 + 8 PML, 2-level / 16-channel U-Net with seeded (untrained)
