@@ -117,6 +117,85 @@ __global__ __launch_bounds__(KT) void k_stencil_dots(const C* __restrict__ z, St
 constexpr int UPD_REG = 32;   // vectors held in registers by the single-pass first update
 constexpr int UPD_SPLIT4 = 24; // up to this many vectors pass 2 splits them over 4 wavefronts
 
+// w = A z and the pass-1 sums for FP32 vectors read as point pairs (even row length, 16-byte
+// aligned vectors, even stride), with the basis split over the NW wavefronts of the block
+// (wavefront q holds vectors [q G, q G + G), G = ceil(nv / NW) <= GMAX). Per tile of NW x 64 pairs
+// wavefront q evaluates the operator on pairs [64 q, 64 q + 64) of the tile (same term order as the
+// tiled stencil), stores them and puts them in LDS (double-buffered, one barrier per tile); then
+// each wavefront accumulates conj(V_i) w over the whole tile for its own vectors, reduced within
+// the wavefront. ||w||^2 is summed by the wavefront that evaluated each pair, then over the
+// wavefronts in order. Writes the same partial layout as k_stencil_dots<float2, false>.
+template <int GMAX, int NW>
+__global__ __launch_bounds__(NW * 64) void k_stencil_dots_split(const float2* __restrict__ z, StencilCoef sc,
+                                                                int nx, int ny, const float2* __restrict__ V,
+                                                                int64_t ldv, int nv, float2* __restrict__ w,
+                                                                int64_t n, int64_t per, double2* __restrict__ part,
+                                                                int ldp, const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    const int64_t p0 = blockIdx.x * per, p1 = min(n, p0 + per);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), ln = threadIdx.x & 63;
+    const int G = (nv + NW - 1) / NW;
+    const int i0 = wv * G;
+    const int cnt = max(0, min(G, nv - i0));
+    __shared__ float4 shw[2][NW][64];
+    __shared__ double red[NW];
+    double ar[GMAX], ai[GMAX];
+#pragma unroll
+    for (int q = 0; q < GMAX; ++q) ar[q] = ai[q] = 0.0;
+    double nacc = 0.0;
+    const int64_t npair = (p1 - p0) >> 1;   // p0 and p1 are even on this path
+    const int64_t q0 = p0 >> 1, hv = ldv >> 1;
+    const float4* __restrict__ V4 = (const float4*)V;
+    int buf = 0;
+    for (int64_t k0 = 0; k0 < npair; k0 += NW * 64, buf ^= 1) {
+        const int64_t k = k0 + wv * 64 + ln;
+        float4 a{0.f, 0.f, 0.f, 0.f};
+        if (k < npair) {
+            a = stencil_pair_value(z, (const float*)sc.k2, (const float2*)sc.E, (const float2*)sc.W,
+                                   (const float2*)sc.N, (const float2*)sc.S, (const float2*)sc.dx,
+                                   (const float2*)sc.dy, sc.conj_diag, nx, ny, p0 + 2 * k);
+            ((float4*)w)[q0 + k] = a;
+            nacc += (double)a.x * a.x + (double)a.y * a.y + (double)a.z * a.z + (double)a.w * a.w;
+        }
+        shw[buf][wv][ln] = a;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < NW; ++r) {
+            const int64_t kr = k0 + r * 64 + ln;
+            if (kr >= npair) break;
+            const float4 wp = shw[buf][r][ln];
+            float4 vr[GMAX];
+#pragma unroll
+            for (int q = 0; q < GMAX; ++q)
+                if (q < cnt) vr[q] = V4[(int64_t)(i0 + q) * hv + q0 + kr];
+#pragma unroll
+            for (int q = 0; q < GMAX; ++q)
+                if (q < cnt) {
+                    const float4 v = vr[q];
+                    ar[q] += (double)v.x * wp.x + (double)v.y * wp.y + (double)v.z * wp.z + (double)v.w * wp.w;
+                    ai[q] += (double)v.x * wp.y - (double)v.y * wp.x + (double)v.z * wp.w - (double)v.w * wp.z;
+                }
+        }
+    }
+    double2* mine = part + (int64_t)blockIdx.x * ldp;
+#pragma unroll
+    for (int g0 = 0; g0 < GMAX; g0 += IC) {
+        if (g0 >= cnt) break;
+        double (&sr)[IC] = *reinterpret_cast<double (*)[IC]>(&ar[g0]);
+        double (&si)[IC] = *reinterpret_cast<double (*)[IC]>(&ai[g0]);
+        wave_store8(sr, si, mine + i0 + g0, cnt - g0);
+    }
+    nacc = wave_sum(nacc);
+    if (ln == 0) red[wv] = nacc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int r = 0; r < NW; ++r) t += red[r];
+        mine[nv] = double2{t, 0.0};
+    }
+}
+
 // Pass 2 of the orthogonalisation for FP32 vectors read as point pairs (16-byte aligned, even
 // stride), with V read once for any nv <= NW GMAX: the vectors are split over the NW wavefronts of
 // the block (wavefront q holds vectors [q G, q G + G), G = ceil(nv / NW), in registers). Per tile of
@@ -457,9 +536,18 @@ int launch_stencil_dots(const hz_problem* p, bool c128, const void* z, const voi
 #define HZ_SD(C, TW, PR)                                                                                       \
     hipLaunchKernelGGL((k_stencil_dots<C, TW>), dim3(sp.nblk), dim3(KT), 0, s, (const C*)z, sc, p->nxt, p->nyt, \
                        (const C*)V, ldv, nv, (C*)w, p->n, sp.per_block, part, ldp, skip, PR)
+    const bool vpairs = (ldv & 1) == 0 && (((uintptr_t)V) & 15) == 0;
     if (c128) {
         if (two) HZ_SD(double2, true, 0);
         else HZ_SD(double2, false, 0);
+    } else if (!two && pairs && vpairs && nv <= 32) {
+        hipLaunchKernelGGL((k_stencil_dots_split<8, 4>), dim3(sp.nblk), dim3(256), 0, s, (const float2*)z, sc,
+                           p->nxt, p->nyt, (const float2*)V, ldv, nv, (float2*)w, p->n, sp.per_block, part, ldp,
+                           skip);
+    } else if (!two && pairs && vpairs && nv <= 64) {
+        hipLaunchKernelGGL((k_stencil_dots_split<8, 8>), dim3(sp.nblk), dim3(512), 0, s, (const float2*)z, sc,
+                           p->nxt, p->nyt, (const float2*)V, ldv, nv, (float2*)w, p->n, sp.per_block, part, ldp,
+                           skip);
     } else {
         if (two) HZ_SD(float2, true, pairs);
         else HZ_SD(float2, false, pairs);

@@ -139,12 +139,12 @@ __device__ __forceinline__ void stencil_tile_wide(const float2* __restrict__ u, 
 // nx even, u / y 16-byte aligned: the centre, north and south pairs are 16-byte loads, the west
 // and east neighbours 8-byte loads (zero outside the grid), the result one 16-byte store. Same
 // term order as stencil_tile.
-__device__ __forceinline__ void stencil_pair(const float2* __restrict__ u, float2* __restrict__ y,
-                                             const float* __restrict__ k2, const float2* __restrict__ cE,
-                                             const float2* __restrict__ cW, const float2* __restrict__ cN,
-                                             const float2* __restrict__ cS, const float2* __restrict__ dx,
-                                             const float2* __restrict__ dy, int conj_diag, int nx, int ny,
-                                             int64_t p) {
+__device__ __forceinline__ float4 stencil_pair_value(const float2* __restrict__ u,
+                                                     const float* __restrict__ k2, const float2* __restrict__ cE,
+                                                     const float2* __restrict__ cW, const float2* __restrict__ cN,
+                                                     const float2* __restrict__ cS, const float2* __restrict__ dx,
+                                                     const float2* __restrict__ dy, int conj_diag, int nx, int ny,
+                                                     int64_t p) {
     using C = float2;
     const int gj = (int)(p / nx), gi = (int)(p - (int64_t)gj * nx);
     const int64_t q = p >> 1, hq = nx >> 1;
@@ -174,7 +174,16 @@ __device__ __forceinline__ void stencil_pair(const float2* __restrict__ u, float
     a1 = cadd(a1, cmul(cW[gi + 1], u0));
     a1 = cadd(a1, cmul(nj, C{nn.z, nn.w}));
     a1 = cadd(a1, cmul(sj, C{ss.z, ss.w}));
-    ((float4*)y)[q] = float4{a0.x, a0.y, a1.x, a1.y};
+    return float4{a0.x, a0.y, a1.x, a1.y};
+}
+
+__device__ __forceinline__ void stencil_pair(const float2* __restrict__ u, float2* __restrict__ y,
+                                             const float* __restrict__ k2, const float2* __restrict__ cE,
+                                             const float2* __restrict__ cW, const float2* __restrict__ cN,
+                                             const float2* __restrict__ cS, const float2* __restrict__ dx,
+                                             const float2* __restrict__ dy, int conj_diag, int nx, int ny,
+                                             int64_t p) {
+    ((float4*)y)[p >> 1] = stencil_pair_value(u, k2, cE, cW, cN, cS, dx, dy, conj_diag, nx, ny, p);
 }
 
 }  // namespace hz
