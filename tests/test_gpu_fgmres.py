@@ -84,7 +84,8 @@ def test_fp32_krylov_long_basis_matches_oracle(m):
     # to 64 steps: every orthogonalisation form of the second pass runs (basis split over 4
     # wavefronts up to 24 vectors, held in registers up to 32, split over 8 wavefronts up to 64).
     # The residual estimate after every step, the cycle's true residual and its x follow the FP64
-    # oracle's within 1e-4 relative (FP32 vectors, FP64 sums and least squares).
+    # oracle's within 1e-5 relative (the FP32 bound for a matvec; FP32 vectors with FP64 sums and
+    # least squares stay near 1e-6).
     from paper_2607_16906_amd import hz
     c, b, p = small_system(nx=100, p=10, seed=2)
     op, gp = make_pair(c, p)
@@ -94,9 +95,9 @@ def test_fp32_krylov_long_basis_matches_oracle(m):
     assert info.its == ref.its == m and info.status == ref.status == 1
     d = np.abs(info.hist - h) / h
     print(f"m {m}: max rel history difference {d.max():.2e}, x {rel(to_np(x), ref.x):.2e}")
-    assert np.all(d <= 1e-4), float(d.max())
-    assert abs(info.true_relres - ref.true_relres) <= 1e-4 * ref.true_relres
-    assert rel(to_np(x), ref.x) <= 1e-4
+    assert np.all(d <= 1e-5), float(d.max())
+    assert abs(info.true_relres - ref.true_relres) <= 1e-5 * ref.true_relres
+    assert rel(to_np(x), ref.x) <= 1e-5
 
 
 @pytest.mark.parametrize("ortho", ["cgs2", "dcgs2"])
