@@ -145,7 +145,7 @@ def test_c5_fp32_krylov_cycle_full_size():
     # the basis split over 4 wavefronts (up to 24 / 32 vectors) and over 8 (33 to 50 vectors).
     # Against the FP64 oracle's GMRES cycle on the same system: the residual estimate after every
     # step within 1e-5 relative, and the cycle's true residual and x within 1e-5 (the FP32 bound
-    for a matvec; FP32 vectors with FP64 sums and least squares stay near 1e-6).
+    # for a matvec; FP32 vectors with FP64 sums and least squares stay near 1e-6).
     from paper_2607_16906_amd import hz
     from synth import c5_system
     s = c5_system(0)
