@@ -18,7 +18,8 @@
  *   - Every pointer named *_dev is device memory on the current HIP device.
  *     Host pointers are named *_host. The caller allocates and frees every
  *     input, output and workspace buffer; the library never frees caller
- *     memory. Handles own their own (immutable after creation) device data.
+ *     memory. Handles own their own (immutable after creation) device data;
+ *     a network handle also records the launch variants no_autotune chose (under a lock).
  *   - `stream` is a hipStream_t (NULL = the default stream). All calls are
  *     asynchronous on `stream` except fgmres_solve / fgmres_solve_batched,
  *     which synchronise `stream` once per restart cycle and return after
@@ -27,8 +28,9 @@
  *     record is filled) or a negative error code. Arguments are validated
  *     before any launch; on error nothing is launched and hz_last_error()
  *     (thread-local) describes the failure. No C++ exception crosses the ABI.
- *   - Handles are read-only after creation: concurrent calls on different
- *     streams with different workspaces are safe.
+ *   - Apart from those launch choices handles are read-only after creation:
+ *     concurrent calls on different streams with different workspaces are safe
+ *     (no_set_layer_variant and no_set_fused_upsampling excepted, see there).
  */
 #ifndef HZ_H
 #define HZ_H
@@ -250,8 +252,9 @@ typedef struct {
     int32_t ortho;        /* 0: CGS with one reorthogonalisation (three reductions per step);
                              1: delayed reorthogonalisation (one reduction per step: the step's
                              reduction also reorthogonalises and normalises the previous vector,
-                             whose network input scale comes from the Pythagorean norm); needs a
-                             network and fgmres_solve; same iterates in exact arithmetic */
+                             whose network input scale is its exact norm, summed from partials
+                             that the step's update pass leaves behind); needs a network and
+                             fgmres_solve; same iterates in exact arithmetic */
 } hz_opts;
 
 typedef struct {

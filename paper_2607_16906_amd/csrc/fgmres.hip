@@ -35,7 +35,7 @@ uint64_t next_handle_uid() {
 
 // Everything a captured cycle depends on. Zero-filled before use and compared bytewise.
 struct GraphKey {
-    uint64_t puid, nuid;
+    uint64_t puid, nuid, tgen;
     int32_t steps, fuse, m, maxit, krylov, net_prec, ortho, pad;
     double tol;
     const void* b;
@@ -316,6 +316,7 @@ static int solve_on(const hz_problem* p, const no_net* net, const hz_opts* o, co
             std::memset(&k, 0, sizeof k);
             k.puid = p->uid;
             k.nuid = net ? net->uid : 0;
+            k.tgen = net ? net->tune_gen.load() : 0;
             k.steps = steps;
             k.fuse = net ? net->fuse_up : -1;
             k.m = o->m;

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <array>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -61,6 +62,10 @@ struct no_net {
     std::mutex tune_mu;
     int fuse_up = 2;   // fused decoder convolution: 0 never, 1 where it applies, 2 where autotuned faster
     uint64_t uid = 0;  // handle identity (next_handle_uid)
+    // launch-choice generation: advanced whenever a variant is pinned, a size is newly tuned or the
+    // fused-upsampling mode changes, so that kept solver graphs recorded with older choices are
+    // not replayed
+    std::atomic<uint64_t> tune_gen{0};
 };
 
 namespace hz {

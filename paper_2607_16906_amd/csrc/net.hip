@@ -381,7 +381,10 @@ static int autotune_impl(const no_net* net, int Hp, int Wp, int batch, const Fwd
         }
         if (best_out) *best_out = best_ms / 10;
         std::lock_guard<std::mutex> g(mnet->tune_mu);
-        if (!mnet->tuned.count(key)) mnet->tuned[key] = best;
+        if (!mnet->tuned.count(key)) {
+            mnet->tuned[key] = best;
+            mnet->tune_gen.fetch_add(1);
+        }
         return HZ_OK;
     };
     // average time of the stand-alone transposed convolution, ms per launch
@@ -440,6 +443,7 @@ static int autotune_impl(const no_net* net, int Hp, int Wp, int batch, const Fwd
             if (rc == HZ_OK) {
                 std::lock_guard<std::mutex> g(mnet->tune_mu);
                 mnet->tuned[ukey].fuse = t_fused < 0.97f * (t_conv + t_up) ? 1 : 0;
+                mnet->tune_gen.fetch_add(1);
             }
         } else {
             rc = tune_layer(li + 1, (const T*)b.E[l], ce, (const T*)b.U[l], ce, (T*)b.T1d[l], nullptr, H, W);
@@ -695,6 +699,7 @@ extern "C" int no_set_layer_variant(const no_net* net, int layer, no_prec prec, 
     no_net* mnet = const_cast<no_net*>(net);
     std::lock_guard<std::mutex> g(mnet->tune_mu);
     mnet->tuned[{layer, H, W, batch, (int)prec}] = ConvCfg{tn, rows / 4, 1};
+    mnet->tune_gen.fetch_add(1);
     return HZ_OK;
 }
 
@@ -702,6 +707,7 @@ extern "C" int no_set_fused_upsampling(no_net* net, int mode) {
     clear_error();
     HZ_CHECK_ARG(net, "no_set_fused_upsampling: NULL network");
     HZ_CHECK_ARG(mode >= 0 && mode <= 2, "no_set_fused_upsampling: mode must be 0, 1 or 2");
+    if (net->fuse_up != mode) net->tune_gen.fetch_add(1);
     net->fuse_up = mode;
     return HZ_OK;
 }
