@@ -153,6 +153,24 @@ size_t no_workspace_size(const no_net* net, const hz_problem* p, no_prec prec);
 int no_precond_apply(const no_net* net, const hz_problem* p, no_prec prec, hz_dtype dtype,
                      const void* v_dev, void* z_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same z = N(v, c, sigma) as no_precond_apply, with
+ * the same kernels and result bits, but its scratch is a fixed library-owned array of
+ * NO_NOALLOC_SCRATCH_BYTES bytes per GPU (held until the process ends) instead of a caller
+ * workspace. Nothing is allocated: no hipMalloc / hipFree and no allocating library routine. The
+ * caller still passes v_dev and z_dev (n complex entries of type `dtype`).
+ * Every call on one GPU shares that GPU's array and leaves its contents behind, so calls that
+ * overlap on one GPU (different host threads, or different streams without ordering) race;
+ * serialise them. Nothing in the array needs to start at zero.
+ * Errors: HZ_ERR_ARG (NULL pointer, bad dtype or precision, v == z), HZ_ERR_WORKSPACE when the grid
+ * and precision need more scratch than the fixed size (no_workspace_size says how much; the
+ * 4-level / 32-channel network needs about 45 MB in BF16 and 90 MB in FP32 at 296^2 nodes, so
+ * BF16 fits up to about 500^2 nodes), HZ_ERR_HIP
+ * when the array's device address cannot be found; nothing is launched on error. */
+#define NO_NOALLOC_SCRATCH_BYTES (128ull << 20)
+int no_precond_apply_noalloc(const no_net* net, const hz_problem* p, no_prec prec, hz_dtype dtype,
+                             const void* v_dev, void* z_dev, void* stream);
+
 /* Time every launch variant (output-channel tile, pixel-tile height) of every 3x3 layer at
  * this problem's padded size and precision, on the forward workspace ws_dev
  * (no_workspace_size bytes), and keep the fastest in the network handle; later forward passes

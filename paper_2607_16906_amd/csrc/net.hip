@@ -10,6 +10,8 @@
 // with ReLU; a 1x1 head yields (Re, Im). The input field v is scaled by
 // s = ||v|| / sqrt(n) before the network and the output is multiplied by s.
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "krylov.h"
@@ -616,6 +618,61 @@ extern "C" int no_precond_apply(const no_net* net, const hz_problem* p, no_prec 
     HZ_CHECK_ARG(dtype == HZ_C64 || dtype == HZ_C128, "no_precond_apply: bad dtype");
     HZ_CHECK_ARG(v != z, "no_precond_apply: v and z must not overlap");
     return net_precond(net, p, prec, dtype == HZ_C128, v, z, ws, ws_bytes, nullptr, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------ allocation-free forward pass
+
+// Scratch memory of no_precond_apply_noalloc: one copy per GPU, held until the process ends. Host
+// code never passes the array's name to a kernel (on the host it is only a stand-in symbol); the
+// device address comes from hipGetSymbolAddress, once per device, and is kept in scratch_dev.
+static __device__ __align__(256) unsigned char scratch[NO_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_dev[SCRATCH_MAX_DEVICES] = {};
+
+// The current device's copy of `scratch` (looked up on the first call on that device).
+int scratch_for_current_device(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= SCRATCH_MAX_DEVICES) {
+        set_error("no_precond_apply_noalloc: no usable current device");
+        return HZ_ERR_HIP;
+    }
+    std::lock_guard<std::mutex> g(scratch_mu);
+    if (!scratch_dev[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            set_error("no_precond_apply_noalloc: hipGetSymbolAddress of the scratch array failed");
+            return HZ_ERR_HIP;
+        }
+        scratch_dev[dev] = ptr;
+    }
+    *out = scratch_dev[dev];
+    return HZ_OK;
+}
+}  // namespace
+
+extern "C" int no_precond_apply_noalloc(const no_net* net, const hz_problem* p, no_prec prec, hz_dtype dtype,
+                                        const void* v, void* z, void* stream) {
+    clear_error();
+    HZ_CHECK_ARG(net && p && v && z, "no_precond_apply_noalloc: NULL argument");
+    HZ_CHECK_ARG(dtype == HZ_C64 || dtype == HZ_C128, "no_precond_apply_noalloc: bad dtype");
+    HZ_CHECK_ARG(prec == NO_BF16 || prec == NO_FP32 || prec == NO_FP64, "no_precond_apply_noalloc: bad precision");
+    HZ_CHECK_ARG(v != z, "no_precond_apply_noalloc: v and z must not overlap");
+    int Hp, Wp;
+    net_padded_dims(net, p, &Hp, &Wp);
+    const size_t need = net_fwd_ws_bytes(net, Hp, Wp, 1, prec);
+    if (need > NO_NOALLOC_SCRATCH_BYTES) {
+        set_error("no_precond_apply_noalloc: this grid and precision need " + std::to_string(need) +
+                  " bytes of scratch, more than the fixed " + std::to_string((size_t)NO_NOALLOC_SCRATCH_BYTES) +
+                  " (use no_precond_apply with a caller workspace)");
+        return HZ_ERR_WORKSPACE;
+    }
+    void* ws = nullptr;
+    HZ_TRY(scratch_for_current_device(&ws));
+    return net_precond(net, p, prec, dtype == HZ_C128, v, z, ws, NO_NOALLOC_SCRATCH_BYTES, nullptr,
+                       (hipStream_t)stream);
 }
 
 extern "C" int no_layer_info(const no_net* net, int layer, int32_t* kind, int32_t* cin_p, int32_t* cout_p,

@@ -59,6 +59,7 @@ SIGNATURES = {
     "no_net_destroy": (_I, [_P]),
     "no_workspace_size": (_SZ, [_P, _P, _I]),
     "no_precond_apply": (_I, [_P, _P, _I, _I, _P, _P, _P, _SZ, _P]),
+    "no_precond_apply_noalloc": (_I, [_P, _P, _I, _I, _P, _P, _P]),
     "no_autotune": (_I, [_P, _P, _I, _P, _SZ, _P]),
     "no_layer_variant": (_I, [_P, _I, _I, _I, _I, _I, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)]),
     "no_set_layer_variant": (_I, [_P, _I, _I, _I, _I, _I, _I, _I]),
@@ -210,7 +211,16 @@ class Net:
         _check(lib.no_precond_apply(self.handle, problem.handle, PREC[prec], dt, _ptr(v), _ptr(z), _ptr(ws),
                                     ct.c_size_t(ws.numel()), _stream()), "no_precond_apply")
         return z
-
+    def apply_noalloc(self, problem: Problem, v, z, prec: str = "bf16"):
+        """z = N(v, c, sigma) into the caller's z with the library's fixed scratch
+        (no_precond_apply_noalloc): no device memory is allocated by this call."""
+        torch = _torch()
+        if not (v.is_contiguous() and z.is_contiguous()) or v.dtype != z.dtype or v.numel() != z.numel():
+            raise ValueError("v and z must be contiguous device vectors of one complex type and size")
+        dt = {torch.complex64: HZ_C64, torch.complex128: HZ_C128}[v.dtype]
+        _check(load_library().no_precond_apply_noalloc(self.handle, problem.handle, PREC[prec], dt, _ptr(v), _ptr(z),
+                                                       _stream()), "no_precond_apply_noalloc")
+        return z
 
     def autotune(self, problem: Problem, prec: str = "bf16"):
         """Pick the fastest launch variant of every 3x3 layer at this problem's size (no_autotune)."""
