@@ -105,7 +105,9 @@ def test_c1_fgmres_fp64_net_matches_oracle(ortho):
     # the plain-FP64 configuration: 64^2 + 8 PML, 2-level / 16-channel U-Net with seeded (untrained)
     # weights, m = 30, tol 1e-6, <= 300 its. The untrained network barely reduces the residual, and in
     # that stagnating regime rounding differences between two correct FP64 runs grow from cycle to
-    # cycle; what is fixed is the first cycle (1e-10) and the shape of the run.
+    # cycle (the oracle itself, with one input entry changed by one ulp, ends about 1e-3 apart in the
+    # final true residual: tests/test_oracle_parity_bars.py); what is fixed is the first cycle
+    # (1e-10), the shape of the run and the final true residual within 4e-3.
     from paper_2607_16906_amd import hz
     s = c1_system(0)
     op, gp = make_pair(s.c, s.npml)
@@ -120,8 +122,8 @@ def test_c1_fgmres_fp64_net_matches_oracle(ortho):
     h = np.array(ref.est_history)
     d = np.abs(info.hist[:30] - h[:30])
     assert np.all(d <= 1e-10 * h[:30] + 1e-14)
-    # later cycles agree only as two stagnating runs do (both stay near the starting residual)
-    assert abs(info.true_relres - ref.true_relres) <= 1e-2 * ref.true_relres
+    # later cycles agree only as two stagnating runs do (measured 1.5e-3 / 1.2e-3 for the two forms)
+    assert abs(info.true_relres - ref.true_relres) <= 4e-3 * ref.true_relres
     # within each cycle the estimate never increases
     for c0 in range(0, info.its, 30):
         assert np.all(np.diff(info.hist[c0:c0 + 30]) <= 1e-15)

@@ -1,8 +1,11 @@
 """Parity at the single-solve workload's full size (256^2 interior + 20 PML = 296^2 nodes, the
 trained 4-level / 32-channel network, the autotuned launch configuration the solver and the
-benchmark use), and the BF16-preconditioned FGMRES bar: true relative residual <= tol, iteration
-count within 2 of the FP64 oracle's on average over a set of seeded solves (each within
-max(2, 10 %), also on long solves)."""
+benchmark use), and the BF16-preconditioned FGMRES bar: true relative residual <= tol checked
+with the oracle's operator, and per solve an iteration count within 2 + s of the FP64 oracle's,
+where s = |its(oracle, activations rounded to BF16) - its(oracle)| is how far a rounding-level
+change of the preconditioner alone moves the oracle's own count on that system (the oracle counts
+of the larger systems are stored in tests/golden by scripts that call only the oracle)."""
+import json
 import os
 
 import numpy as np
@@ -18,6 +21,8 @@ from oracle import unet
 from synth import C_REF, H_10PPW, c2_system, gaussian_sources, rng_for, skull_ring_velocity
 
 from gpu_util import make_pair, rel, to_dev, to_np
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 WEIGHTS = os.path.join(os.path.dirname(__file__), "..", "paper_2607_16906_amd", "weights", "unet_l4_c32_in5.npz")
 SPECS = unet.layer_specs(4, 32, 5)
@@ -72,53 +77,111 @@ def test_c2_solve_full_size(c2, ortho):
     assert rr <= 1e-6 and abs(rr - info.true_relres) <= 1e-9
 
 
-def bf16_solve_pair(nx, p, seed, ortho="cgs2"):
-    """(oracle result, GPU info, true relative residual of the GPU x) of one BF16-preconditioned
-    solve: FP64 oracle FGMRES with the FP64 network on the BF16-rounded weights, GPU FGMRES with
-    the BF16 network and FP32 Krylov vectors (m = 30, tol = 1e-6)."""
+def bf16_iteration_bar(its_gpu, its_oracle, its_oracle_bf16_act):
+    """The per-solve bar: 2 iterations plus the oracle's own movement under BF16 activations."""
+    return abs(its_gpu - its_oracle) <= 2 + abs(its_oracle_bf16_act - its_oracle)
+
+
+def gpu_bf16_solve(c, p, b, ortho="cgs2", maxit=600):
+    """GPU FGMRES with the BF16 network and FP32 Krylov vectors (m = 30, tol = 1e-6): (info, true
+    relative residual of the returned x under the oracle's FP64 operator)."""
     from paper_2607_16906_amd import hz
-    nt = nx + 2 * p
-    c = skull_ring_velocity(nt, p, rng_for(14, 0, seed), rings=1 + seed % 3)
-    b = gaussian_sources(nt, p, rng_for(14, 1, seed))
     op, gp = make_pair(c, p)
     theta = np.load(WEIGHTS)["theta"].astype(np.float32)
-    th = bf16_round(theta)
-    M = lambda vv: unet.precond_apply(th, SPECS, op, vv.reshape(op.ny, op.nx)).ravel()
-    A = lambda xx: ohz.op_apply(op, xx.reshape(op.ny, op.nx)).ravel()
-    ref = ofg.fgmres(A, M, b.ravel(), m=30, tol=1e-6, maxit=400)
     net = hz.Net(4, 32, 5, theta)
-    x, info = hz.fgmres(gp, to_dev(b, torch.complex128), net=net, m=30, tol=1e-6, maxit=400, krylov="c64",
+    x, info = hz.fgmres(gp, to_dev(b, torch.complex128), net=net, m=30, tol=1e-6, maxit=maxit, krylov="c64",
                         net_prec="bf16", ortho=ortho)
+    A = lambda xx: ohz.op_apply(op, xx.reshape(op.ny, op.nx)).ravel()
     rr = np.linalg.norm(b.ravel() - A(to_np(x))) / np.linalg.norm(b)
-    print(f"nx {nx} seed {seed}: its GPU {info.its}, oracle {ref.its}, true relres {rr:.3e}")
-    return ref, info, rr
+    return info, rr
+
+
+def oracle_counts(c, p, b):
+    """FP64 oracle FGMRES counts on the BF16-rounded weights, activations exact and rounded to BF16."""
+    op, _ = make_pair(c, p)
+    th = bf16_round(np.load(WEIGHTS)["theta"].astype(np.float32))
+    A = lambda xx: ohz.op_apply(op, xx.reshape(op.ny, op.nx)).ravel()
+    out = []
+    for act in (None, unet.bf16_activation):
+        M = lambda vv: unet.precond_apply(th, SPECS, op, vv.reshape(op.ny, op.nx), act_round=act).ravel()
+        r = ofg.fgmres(A, M, b.ravel(), m=30, tol=1e-6, maxit=400)
+        assert r.status == 0
+        out.append(r.its)
+    return out
 
 
 @pytest.mark.parametrize("ortho", ["cgs2", "dcgs2"])
 def test_bf16_fgmres_iterations_match_oracle(ortho):
-    # 18 seeded solves of 30-60 iterations (12^2-20^2 interiors + 6 PML): every solve converges
-    # with true relative residual <= tol; the iteration count is within 2 of the oracle's on
-    # average and within max(2, 10 %) for each solve (rounding-level differences move single
-    # trajectories of this nonlinear iteration by a few steps; the FP64 network with FP64 Krylov
-    # vectors does so against the FP64 oracle as well)
-    diffs = []
+    # 18 seeded solves of 30-60 iterations (12^2-20^2 interiors + 6 PML), oracle counts computed here
+    worst = 0
     for nx in (12, 16, 20):
         for seed in range(6):
-            ref, info, rr = bf16_solve_pair(nx, 6, seed, ortho)
-            assert ref.status == 0 and info.status == 0 and rr <= 1e-6
-            assert abs(info.its - ref.its) <= max(2, ref.its // 10), (nx, seed, info.its, ref.its)
-            diffs.append(abs(info.its - ref.its))
-    print("mean |d its|", np.mean(diffs), "max", max(diffs))
-    assert np.mean(diffs) <= 2.0
+            nt = nx + 12
+            c = skull_ring_velocity(nt, 6, rng_for(14, 0, seed), rings=1 + seed % 3)
+            b = gaussian_sources(nt, 6, rng_for(14, 1, seed))
+            its, its_q = oracle_counts(c, 6, b)
+            info, rr = gpu_bf16_solve(c, 6, b, ortho, maxit=400)
+            print(f"nx {nx} seed {seed}: its GPU {info.its}, oracle {its} (BF16 activations {its_q}), "
+                  f"true relres {rr:.3e}")
+            assert info.status == 0 and rr <= 1e-6
+            assert bf16_iteration_bar(info.its, its, its_q), (nx, seed, info.its, its, its_q)
+            worst = max(worst, abs(info.its - its))
+    print("max |d its|", worst)
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2])
-def test_bf16_fgmres_long_solve_iterations(seed):
-    # 90-130 iterations (40^2 interior + 8 PML): count within max(2, 10 %) of the oracle's
-    ref, info, rr = bf16_solve_pair(40, 8, seed)
-    assert ref.status == 0 and info.status == 0
-    assert abs(info.its - ref.its) <= max(2, ref.its // 10)
-    assert rr <= 1e-6
+def _golden_systems():
+    with open(os.path.join(GOLDEN, "fgmres_counts.json")) as f:
+        return json.load(f)["systems"]
+
+
+@pytest.mark.parametrize("key", sorted(_golden_systems()))
+def test_bf16_fgmres_long_solve_iterations(key):
+    # 48-145 iterations (40^2 + 8 PML and 64^2 + 16 PML): the oracle's counts from the golden file
+    g = _golden_systems()[key]
+    nx, p, seed = g["nx"], g["npml"], g["seed"]
+    nt = nx + 2 * p
+    c = skull_ring_velocity(nt, p, rng_for(14, 0, seed), rings=1 + seed % 3)
+    b = gaussian_sources(nt, p, rng_for(14, 1, seed))
+    info, rr = gpu_bf16_solve(c, p, b)
+    print(f"{key}: its GPU {info.its}, oracle {g['its']} (BF16 activations {g['its_bf16_act']}), "
+          f"true relres {rr:.3e}")
+    assert info.status == 0 and rr <= 1e-6
+    assert bf16_iteration_bar(info.its, g["its"], g["its_bf16_act"])
+
+
+def test_c2_bf16_solve_against_golden_oracle():
+    # the benchmark's own solve (296^2, BF16 network, FP32 Krylov vectors, FGMRES(30), tol 1e-6)
+    # against the FP64 oracle's solve of the same system stored in tests/golden/c2_oracle.json
+    with open(os.path.join(GOLDEN, "c2_oracle.json")) as f:
+        runs = json.load(f)["runs"]
+    s = c2_system(0)
+    info, rr = gpu_bf16_solve(s.c, s.npml, s.b, maxit=3000)
+    ref, refq = runs["bf16_weights"], runs["bf16_weights_bf16_activations"]
+    print(f"296^2: its GPU {info.its}, oracle {ref['its']} (BF16 activations {refq['its']}), "
+          f"true relres {rr:.3e} (oracle {ref['true_relres']:.3e})")
+    assert info.status == 0 and rr <= 1e-6
+    assert bf16_iteration_bar(info.its, ref["its"], refq["its"])
+    h = np.array(ref["est_history"][:30])
+    print(f"first-cycle estimates: max relative difference {np.max(np.abs(info.hist[:30] - h) / h):.2e}")
+
+
+def test_c2_fp64_solve_against_golden_oracle():
+    # FP64 network and FP64 Krylov vectors on the float32 weights against the oracle's solve on the
+    # same weights: only the summation order differs; north-star bar +-2 on the count
+    from paper_2607_16906_amd import hz
+    with open(os.path.join(GOLDEN, "c2_oracle.json")) as f:
+        ref = json.load(f)["runs"]["fp32_weights"]
+    s = c2_system(0)
+    op, gp = make_pair(s.c, s.npml)
+    net = hz.Net(4, 32, 5, np.load(WEIGHTS)["theta"].astype(np.float32))
+    x, info = hz.fgmres(gp, to_dev(s.b, torch.complex128), net=net, m=30, tol=1e-6, maxit=3000, krylov="c128",
+                        net_prec="fp64")
+    h = np.array(ref["est_history"])
+    d = np.abs(info.hist[:30] - h[:30]) / h[:30]
+    print(f"296^2 FP64: its GPU {info.its}, oracle {ref['its']}, first-cycle history {d.max():.2e}")
+    assert info.status == 0 and info.true_relres <= 1e-6
+    assert abs(info.its - ref["its"]) <= 2
+    assert np.all(d <= 1e-10)
 
 
 def test_solves_independent_of_autotuning():

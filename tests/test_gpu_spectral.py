@@ -46,8 +46,8 @@ def test_spectral_apply_fp64_and_fp32(nt, p, adjoint):
     y64 = to_np(gp.apply(to_dev(u, torch.complex128), adjoint=adjoint)).reshape(nt, nt)
     assert rel(y64, ref) <= 1e-12
     y32 = to_np(gp.apply(to_dev(u, torch.complex64), adjoint=adjoint)).reshape(nt, nt)
-    # FP32 storage of u and of the per-axis matrices
-    assert rel(y32, ref) <= 2e-5
+    # FP32 storage of u and of the per-axis matrices (measured 1.5e-7 - 5.5e-7)
+    assert rel(y32, ref) <= 1e-5
 
 
 def test_spectral_full_size():
@@ -56,7 +56,7 @@ def test_spectral_full_size():
     u = rand_field((s.nt, s.nt), 5)
     ref = osp.op_apply(op, u)
     assert rel(to_np(gp.apply(to_dev(u, torch.complex128))).reshape(s.nt, s.nt), ref) <= 1e-12
-    assert rel(to_np(gp.apply(to_dev(u, torch.complex64))).reshape(s.nt, s.nt), ref) <= 2e-5
+    assert rel(to_np(gp.apply(to_dev(u, torch.complex64))).reshape(s.nt, s.nt), ref) <= 1e-5
 
 
 def test_spectral_gmres_fp64_matches_oracle():
