@@ -90,7 +90,42 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
     const int npa = (TH_ + 2) * (TW + 2) * vpp, npw = 9 * TN * vpp;
     uint4 ra[NPA], rw[NPW];
     const int ukn = UPCD > 0 ? up.cd / (4 * P::GW) : 0;   // MFMA steps of the transposed convolution
-    auto gload = [&](int k0) {
+    // Staging offsets of this thread, the same for every chunk up to the chunk's channel offset
+    // (computed once: index arithmetic per chunk would outweigh the chunk's matrix work). Patch
+    // vector i: LDS slot plds (or -1 when the thread has no vector i), source offsets poff0 /
+    // poff1 within the first / second input part (-1: outside the image, stored as zeros).
+    // Weight vector i: LDS slot wlds (-1: none) and offset woff in the packed weights.
+    int plds[NPA], wlds[NPW], woff[NPW];
+    int64_t poff0[NPA], poff1[NPA];
+#pragma unroll
+    for (int i = 0; i < NPA; ++i) {
+        const int v = threadIdx.x + i * CT;
+        plds[i] = -1;
+        poff0[i] = poff1[i] = -1;
+        if (v < npa) {
+            const int px = v / vpp, part = v - px * vpp;
+            const int py = px / (TW + 2), pxx = px - py * (TW + 2);
+            const int gy = ty0 + py - 1, gx = tx0 + pxx - 1;
+            plds[i] = px * PS + part * VE;
+            if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+                const int64_t pix = (int64_t)gy * W + gx;
+                poff0[i] = pix * c0 + part * VE;
+                poff1[i] = pix * c1 + part * VE;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NPW; ++i) {
+        const int v = threadIdx.x + i * CT;
+        wlds[i] = woff[i] = -1;
+        if (v < npw) {
+            const int row = v / vpp, part = v - row * vpp;
+            const int tap = row / TN, co = row - tap * TN;
+            wlds[i] = row * PS + part * VE;
+            woff[i] = (tap * cout_p + co0 + co) * cin_p + part * VE;
+        }
+    }
+    auto gload = [&](int k0, uint4 (&ra_)[NPA], uint4 (&rw_)[NPW]) {
         const bool uchunk = UPCD > 0 && k0 >= c0;
         if constexpr (UPCD > 0) {
             if (uchunk) {
@@ -111,53 +146,24 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
                     for (int r = 0; r < 4; ++r) rbt[mb][r] = ((const Acc*)up.bt)[k0 - c0 + mb * 16 + P::row_of(lg, r)];
             }
         }
+        // (the fused form stages only the first part from memory)
+        const bool first = UPCD > 0 || k0 < c0;
+        const T* pbase = first ? xs0 + k0 : xs1 + (k0 - c0);
 #pragma unroll
         for (int i = 0; i < NPA; ++i) {
-            const int v = threadIdx.x + i * CT;
-            uint4 val = uint4{0, 0, 0, 0};
-            if (v < npa && !uchunk) {
-                const int px = v / vpp, part = v - px * vpp;
-                const int py = px / (TW + 2), pxx = px - py * (TW + 2);
-                const int gy = ty0 + py - 1, gx = tx0 + pxx - 1;
-                if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-                    const int c = k0 + part * VE;
-                    const int64_t pix = (int64_t)gy * W + gx;
-                    // (the fused form stages only the first part from memory)
-                    const T* src = (UPCD > 0 || c < c0) ? xs0 + pix * c0 + c : xs1 + pix * c1 + (c - c0);
-                    val = *(const uint4*)src;
-                }
-            }
-            ra[i] = val;
+            const int64_t off = first ? poff0[i] : poff1[i];
+            ra_[i] = (off >= 0 && !uchunk) ? *(const uint4*)(pbase + off) : uint4{0, 0, 0, 0};
         }
 #pragma unroll
-        for (int i = 0; i < NPW; ++i) {
-            const int v = threadIdx.x + i * CT;
-            uint4 val = uint4{0, 0, 0, 0};
-            if (v < npw) {
-                const int row = v / vpp, part = v - row * vpp;
-                const int tap = row / TN, co = row - tap * TN;
-                val = *(const uint4*)(w + ((int64_t)tap * cout_p + co0 + co) * cin_p + k0 + part * VE);
-            }
-            rw[i] = val;
-        }
+        for (int i = 0; i < NPW; ++i) rw_[i] = woff[i] >= 0 ? *(const uint4*)(w + woff[i] + k0) : uint4{0, 0, 0, 0};
     };
-    auto lstore = [&](int k0) {
+    auto lstore = [&](int k0, const uint4 (&ra_)[NPA], const uint4 (&rw_)[NPW]) {
 #pragma unroll
-        for (int i = 0; i < NPA; ++i) {
-            const int v = threadIdx.x + i * CT;
-            if (v < npa && !(UPCD > 0 && k0 >= c0)) {
-                const int px = v / vpp, part = v - px * vpp;
-                *(uint4*)&patch[px * PS + part * VE] = ra[i];
-            }
-        }
+        for (int i = 0; i < NPA; ++i)
+            if (plds[i] >= 0 && !(UPCD > 0 && k0 >= c0)) *(uint4*)&patch[plds[i]] = ra_[i];
 #pragma unroll
-        for (int i = 0; i < NPW; ++i) {
-            const int v = threadIdx.x + i * CT;
-            if (v < npw) {
-                const int row = v / vpp, part = v - row * vpp;
-                *(uint4*)&wl[row * PS + part * VE] = rw[i];
-            }
-        }
+        for (int i = 0; i < NPW; ++i)
+            if (wlds[i] >= 0) *(uint4*)&wl[wlds[i]] = rw_[i];
     };
     const int hd = H / 2, wd = W / 2, dr0 = ty0 / 2 - 1, dc0 = tx0 / 2 - 1;
     if constexpr (UPCD > 0) {
@@ -177,10 +183,24 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
             rd[i] = val;
         }
     }
-    gload(kbeg);
-    for (int k0 = kbeg; k0 < kend; k0 += ck) {
+    // the epilogue's bias (and fused head weights), fetched with the first chunk
+    Acc bpre[NCB][4], hw0[NCB][4], hw1[NCB][4];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int co = co0 + cb * 16 + P::row_of(lg, r);
+            bpre[cb][r] = (bias && !splitp) ? bias[co] : Acc(0);
+            hw0[cb][r] = ex.head_w ? P::val(((const T*)ex.head_w)[co]) : Acc(0);
+            hw1[cb][r] = ex.head_w ? P::val(((const T*)ex.head_w)[cout_p + co]) : Acc(0);
+        }
+    const Acc hb0 = ex.head_w ? ((const Acc*)ex.head_b)[0] : Acc(0);
+    const Acc hb1 = ex.head_w ? ((const Acc*)ex.head_b)[1] : Acc(0);
+    // One chunk: stage the registers (ra_, rw_) in LDS, then refill them with chunk kpre (if any)
+    // while the matrix cores work on this one.
+    auto step = [&](int k0, uint4 (&ra_)[NPA], uint4 (&rw_)[NPW], int kpre) {
         __syncthreads();
-        lstore(k0);
+        lstore(k0, ra_, rw_);
         if constexpr (UPCD > 0) {
             if (k0 == kbeg) {
                 const int vpd = up.cd / VE;
@@ -234,7 +254,7 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
                 __syncthreads();
             }
         }
-        if (k0 + ck < kend) gload(k0 + ck);
+        if (kpre < kend) gload(kpre, ra_, rw_);
         if (ck == P::CK) {
             // full chunk: step st covers tap st / SPT and k-groups 4 (st mod SPT) + lg of it, all
             // offsets are compile-time after unrolling (the reads of the next steps can be issued
@@ -242,21 +262,32 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
             constexpr int SPT = P::CK / P::GW / 4;
             const T* pbase = &patch[((RPW * wv) * (TW + 2) + lr) * PS + lg * P::GW];
             const T* wbase = &wl[lr * PS + lg * P::GW];
+            // the wavefront's RPW + 2 patch rows at the 3 column offsets, read from LDS once and
+            // shared by the 3 row offsets dy of the window; the accumulation order is tap by tap,
+            // k-groups within a tap
+            Frag b[RPW + 2][3][SPT];
 #pragma unroll
-            for (int st = 0; st < 9 * SPT; ++st) {
-                const int tap = st / SPT, cgo = 4 * (st % SPT) * P::GW;
+            for (int ir = 0; ir < RPW + 2; ++ir)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                    for (int sg = 0; sg < SPT; ++sg)
+                        b[ir][dx][sg] = P::load(pbase + (ir * (TW + 2) + dx) * PS + 4 * sg * P::GW);
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
                 const int dy = tap / 3, dx = tap % 3;
-                Frag a[NCB], b[RPW];
 #pragma unroll
-                for (int pb = 0; pb < RPW; ++pb) b[pb] = P::load(pbase + ((pb + dy) * (TW + 2) + dx) * PS + cgo);
+                for (int sg = 0; sg < SPT; ++sg) {
+                    Frag a[NCB];
 #pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) a[cb] = P::load(wbase + (tap * TN + cb * 16) * PS + cgo);
+                    for (int cb = 0; cb < NCB; ++cb) a[cb] = P::load(wbase + (tap * TN + cb * 16) * PS + 4 * sg * P::GW);
 #pragma unroll
-                for (int pb = 0; pb < RPW; ++pb)
+                    for (int pb = 0; pb < RPW; ++pb)
 #pragma unroll
-                    for (int cb = 0; cb < NCB; ++cb) acc[pb][cb] = P::mma(a[cb], b[pb], acc[pb][cb]);
+                        for (int cb = 0; cb < NCB; ++cb) acc[pb][cb] = P::mma(a[cb], b[pb + dy][dx][sg], acc[pb][cb]);
+                }
             }
-            continue;
+            return;
         }
         for (int st = 0; st < steps; ++st) {
             const int gi = 4 * st + lg;
@@ -280,7 +311,9 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
 #pragma unroll
                 for (int cb = 0; cb < NCB; ++cb) acc[pb][cb] = P::mma(a[cb], b[pb], acc[pb][cb]);
         }
-    }
+    };
+    gload(kbeg, ra, rw);
+    for (int k0 = kbeg; k0 < kend; k0 += ck) step(k0, ra, rw, k0 + ck);
 
     const int gx = tx0 + lr;
     if (splitp) {
@@ -299,8 +332,6 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
         return;
     }
     if (ex.head_w) {   // fused 1x1 head over all cout_p = TN channels of the pixel
-        const T* wh = (const T*)ex.head_w;
-        const Acc* bh = (const Acc*)ex.head_b;
         Acc o0[RPW], o1[RPW];
 #pragma unroll
         for (int pb = 0; pb < RPW; ++pb) o0[pb] = o1[pb] = Acc(0);
@@ -308,8 +339,7 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
         for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int co = co0 + cb * 16 + P::row_of(lg, r);
-                const Acc w0 = P::val(wh[co]), w1 = P::val(wh[cout_p + co]), bc = bias ? bias[co] : Acc(0);
+                const Acc w0 = hw0[cb][r], w1 = hw1[cb][r], bc = bpre[cb][r];
 #pragma unroll
                 for (int pb = 0; pb < RPW; ++pb) {
                     Acc t = acc[pb][cb][r] + bc;
@@ -329,7 +359,7 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
             a1 += __shfl_xor(a1, 32, 64);
             const int gy = ty0 + RPW * wv + pb;
             if (lg == 0 && gy < ex.head_nyt && gx < ex.head_nxt) {
-                const double2 zv{sfac * (double)(bh[0] + a0), sfac * (double)(bh[1] + a1)};
+                const double2 zv{sfac * (double)(hb0 + a0), sfac * (double)(hb1 + a1)};
                 const int64_t zi = (int64_t)gy * ex.head_nxt + gx;
                 if (ex.head_c128) ((double2*)ex.head_z)[zi] = zv;
                 else ((float2*)ex.head_z)[zi] = from_d2<float2>(zv);
@@ -356,7 +386,7 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
         for (int pb = 0; pb < RPW; ++pb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                Acc t = acc[pb][cb][r] + (bias ? bias[co + P::row_of(lg, r)] : Acc(0));
+                Acc t = acc[pb][cb][r] + bpre[cb][r];
                 if (relu) t = t > Acc(0) ? t : Acc(0);
                 v[pb][r] = t;
             }
