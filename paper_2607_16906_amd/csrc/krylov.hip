@@ -131,7 +131,7 @@ __global__ __launch_bounds__(NW * 64) void k_stencil_dots_split(const float2* __
                                                                 int64_t ldv, int nv, float2* __restrict__ w,
                                                                 int64_t n, int64_t per, double2* __restrict__ part,
                                                                 int ldp, const int* __restrict__ skip) {
-    if (skip && *skip) return;
+    const int skipped = skip ? *skip : 0;   // tested once the first tile's loads are in flight
     const int64_t p0 = blockIdx.x * per, p1 = min(n, p0 + per);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), ln = threadIdx.x & 63;
     const int G = (nv + NW - 1) / NW;
@@ -150,10 +150,13 @@ __global__ __launch_bounds__(NW * 64) void k_stencil_dots_split(const float2* __
     for (int64_t k0 = 0; k0 < npair; k0 += NW * 64, buf ^= 1) {
         const int64_t k = k0 + wv * 64 + ln;
         float4 a{0.f, 0.f, 0.f, 0.f};
-        if (k < npair) {
+        if (k < npair)
             a = stencil_pair_value(z, (const float*)sc.k2, (const float2*)sc.E, (const float2*)sc.W,
                                    (const float2*)sc.N, (const float2*)sc.S, (const float2*)sc.dx,
                                    (const float2*)sc.dy, sc.conj_diag, nx, ny, p0 + 2 * k);
+        asm volatile("" ::: "memory");
+        if (k0 == 0 && skipped) return;   // uniform over the block; nothing written yet
+        if (k < npair) {
             ((float4*)w)[q0 + k] = a;
             nacc += (double)a.x * a.x + (double)a.y * a.y + (double)a.z * a.z + (double)a.w * a.w;
         }
@@ -208,7 +211,7 @@ __global__ __launch_bounds__(NW * 64) void k_upd1_split(const float2* __restrict
                                                    const double2* __restrict__ h, float2* __restrict__ w,
                                                    int64_t n, int64_t per, double2* __restrict__ part, int ldp,
                                                    const int* __restrict__ skip) {
-    if (skip && *skip) return;
+    const int skipped = skip ? *skip : 0;   // tested once the first tile's loads are in flight
     const int64_t p0 = blockIdx.x * per, p1 = min(n, p0 + per);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), ln = threadIdx.x & 63;
     const int G = (nv + NW - 1) / NW;
@@ -265,6 +268,7 @@ __global__ __launch_bounds__(NW * 64) void k_upd1_split(const float2* __restrict
                 ty += (double)v.z * hi.y + (double)v.w * hi.x;
             }
         sh[buf][wv][ln] = double4{sx, sy, tx, ty};
+        if (k0 == 0 && skipped) return;   // uniform over the block; nothing written yet
         __syncthreads();
         const float4 a = shw[buf][ln];
         double ax = a.x, ay = a.y, bx = a.z, by = a.w;
@@ -306,8 +310,16 @@ __global__ __launch_bounds__(KT) void k_update(const C* __restrict__ V, int64_t 
                                                const double2* __restrict__ h, C* __restrict__ w, int64_t n,
                                                int64_t per, double2* __restrict__ part, int ldp,
                                                const int* __restrict__ skip) {
-    if (skip && *skip) return;
     const int64_t p0 = blockIdx.x * per, p1 = min(n, p0 + per);
+    {
+        // the step-skip flag's load overlaps that of the block's first point of w (which
+        // brings its line into the cache for the loops below); nothing is written before the test
+        const int skipped = skip ? *skip : 0;
+        const int64_t pf = min(p0 + (int64_t)threadIdx.x, n - 1);
+        const C warm = w[pf];
+        asm volatile("" ::"v"(warm.x));
+        if (skipped) return;
+    }
     if (MODE == 1 && nv <= UPD_REG) {
         // single pass: the vectors read for the update of a point stay in registers for the sums
         // conj(V_i) w of the second Gram-Schmidt pass (V is read once)
@@ -366,6 +378,8 @@ __global__ __launch_bounds__(KT) void k_update(const C* __restrict__ V, int64_t 
         for (int64_t k = threadIdx.x; k < npair; k += KT) {
             const float4 a = w4[k];
             double ax = a.x, ay = a.y, bx = a.z, by = a.w;
+            // unrolled so that several basis loads are in flight (same order of the sums)
+#pragma unroll 8
             for (int i = 0; i < nv; ++i) {
                 const float4 v = ((const float4*)(V + (int64_t)i * ldv + p0))[k];
                 const double2 hi = h[i];
@@ -380,6 +394,7 @@ __global__ __launch_bounds__(KT) void k_update(const C* __restrict__ V, int64_t 
             const int64_t p = p1 - 1;
             const C wp = w[p];
             double ax = wp.x, ay = wp.y;
+#pragma unroll 8
             for (int i = 0; i < nv; ++i) {
                 const C v = V[(int64_t)i * ldv + p];
                 const double2 hi = h[i];
@@ -392,6 +407,7 @@ __global__ __launch_bounds__(KT) void k_update(const C* __restrict__ V, int64_t 
         for (int64_t p = p0 + threadIdx.x; p < p1; p += KT) {
             const C wp = w[p];
             double ax = wp.x, ay = wp.y;
+#pragma unroll 8
             for (int i = 0; i < nv; ++i) {
                 const C v = V[(int64_t)i * ldv + p];
                 const double2 hi = h[i];
@@ -410,9 +426,9 @@ __global__ __launch_bounds__(KT) void k_update(const C* __restrict__ V, int64_t 
 // one block per output value
 __global__ __launch_bounds__(KT) void k_finalize(const double2* __restrict__ part, int nblk, int ldp,
                                                  double2* __restrict__ out, const int* __restrict__ skip) {
-    if (skip && *skip) return;
+    const int skipped = skip ? *skip : 0;   // its load overlaps those of the partials
     const double2 v = block_sum_slot(part, nblk, ldp, blockIdx.x);
-    if (threadIdx.x == 0) out[blockIdx.x] = v;
+    if (threadIdx.x == 0 && !skipped) out[blockIdx.x] = v;
 }
 
 

@@ -326,6 +326,7 @@ __device__ __forceinline__ void norm_body(const C* __restrict__ w, int64_t p0, i
 __device__ inline double2 block_sum_slot(const double2* __restrict__ part, int nblk, int ldp, int i) {
     __shared__ double red[KT / 64][2];
     double a = 0, b = 0;
+#pragma unroll 4
     for (int q = threadIdx.x; q < nblk; q += KT) {
         const double2 v = part[(int64_t)q * ldp + i];
         a += v.x;
@@ -350,7 +351,8 @@ __device__ inline double2 block_sum_slot(const double2* __restrict__ part, int n
 __device__ inline double sum_parts(const double2* part, int nblk, int ldp, int slot) {
     const int ln = threadIdx.x & 63;
     double a = 0;
-    for (int q = ln; q < nblk; q += 64) a += part[(int64_t)q * ldp + slot].x;
+#pragma unroll 8
+    for (int q = ln; q < nblk; q += 64) a += part[(int64_t)q * ldp + slot].x;   // loads in flight together
     return wave_sum(a);
 }
 
@@ -481,7 +483,7 @@ __device__ inline void arnoldi_finish_body(SolveState* st, double2* __restrict__
                                            const double2* __restrict__ h1, const double2* __restrict__ h2,
                                            const double2* __restrict__ part, int nblk, int ldp, int j,
                                            double* __restrict__ hist) {
-    if (st->stop) return;
+    const int stopped = st->stop;   // tested after the loads below (they write LDS only)
     const double hn2 = sum_parts(part, nblk, ldp, 0);     // ||w||^2 after orthogonalisation
     // stage the column and the first AF_WIN rotations in LDS with one parallel pass
     __shared__ double2 hl[AF_WIN + 1], snl[AF_WIN];
@@ -496,7 +498,7 @@ __device__ inline void arnoldi_finish_body(SolveState* st, double2* __restrict__
         }
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
+    if (stopped || threadIdx.x != 0) return;
     const double wn0 = sqrt(h1[j + 1].x);
     const double hn = sqrt(hn2);
     auto hcol = [&](int i) {

@@ -42,8 +42,12 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
                                            typename P::T* __restrict__ y, int cout_p,
                                            typename P::T* __restrict__ ypool, int H, int W, int relu, int ck,
                                            const Conv3Out& ex, int bz, int co0, int ty0, int tx0, int kbeg, int kend,
-                                           typename P::Acc* __restrict__ splitp, UpIn up = UpIn()) {
+                                           typename P::Acc* __restrict__ splitp, UpIn up = UpIn(),
+                                           const int* __restrict__ skip = nullptr) {
     using T = typename P::T;
+    // the step-skip flag is read here but tested only once the first chunk's loads are in flight,
+    // so that its memory latency overlaps theirs (nothing is written before the test)
+    const int skipped = skip ? *skip : 0;
     using Acc = typename P::Acc;
     using AccV = typename P::AccV;
     using Frag = typename P::Frag;
@@ -313,6 +317,8 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
         }
     };
     gload(kbeg, ra, rw);
+    asm volatile("" ::: "memory");   // keep the loads above the test
+    if (skipped) return;             // uniform over the block
     for (int k0 = kbeg; k0 < kend; k0 += ck) step(k0, ra, rw, k0 + ck);
 
     const int gx = tx0 + lr;
@@ -471,7 +477,6 @@ __global__ __launch_bounds__(CT) void k_conv3(const typename P::T* __restrict__ 
                                               typename P::T* __restrict__ ypool, int H, int W, int relu, int ck,
                                               const int* __restrict__ skip, Conv3Out ex, int nsplit,
                                               typename P::Acc* __restrict__ splitp, int64_t sstride) {
-    if (skip && *skip) return;
     // logical order: channel block fastest, then K split, column tile, row tile, sample
     const int ncb_tot = cout_p / TN;
     const int nblk = gridDim.x * gridDim.y * gridDim.z;
@@ -489,7 +494,8 @@ __global__ __launch_bounds__(CT) void k_conv3(const typename P::T* __restrict__ 
     const int nch = cin_p / ck;
     const int kb = (nch * zs / nsplit) * ck, ke = (nch * (zs + 1) / nsplit) * ck;
     conv3_tile<P, TN, POOL, RPW>(x0, c0, x1, c1, w, bias, y, cout_p, ypool, H, W, relu, ck, ex, bz, co0,
-                                 tyi * 4 * RPW, txi * TW, kb, ke, splitp ? splitp + zs * sstride : nullptr);
+                                 tyi * 4 * RPW, txi * TW, kb, ke, splitp ? splitp + zs * sstride : nullptr, UpIn(),
+                                 skip);
 }
 
 // Decoder 3x3 convolution with the transposed convolution of the coarser level fused in (UpIn).
@@ -500,7 +506,6 @@ __global__ __launch_bounds__(CT) void k_conv3_up(const typename P::T* __restrict
                                                  const typename P::Acc* __restrict__ bias,
                                                  typename P::T* __restrict__ y, int cout_p, int H, int W,
                                                  const int* __restrict__ skip) {
-    if (skip && *skip) return;
     const int ncb_tot = cout_p / TN;
     const int nblk = gridDim.x * gridDim.y * gridDim.z;
     int v = xcd_linear(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nblk);
@@ -511,7 +516,7 @@ __global__ __launch_bounds__(CT) void k_conv3_up(const typename P::T* __restrict
     const int tyi = v % gridDim.y;
     const int bz = v / gridDim.y;
     conv3_tile<P, TN, false, RPW, UPCD>(x0, c0, nullptr, c1, w, bias, y, cout_p, nullptr, H, W, 1, P::CK, Conv3Out(),
-                                        bz, cbi * TN, tyi * 4 * RPW, txi * TW, 0, c0 + c1, nullptr, up);
+                                        bz, cbi * TN, tyi * 4 * RPW, txi * TW, 0, c0 + c1, nullptr, up, skip);
 }
 
 // Ragged batch: block b runs job jobs[b] = (system, tile, channel block) with the system's tensors.
@@ -543,11 +548,12 @@ __device__ __forceinline__ void convT2_tile(const typename P::T* __restrict__ x,
                                             const typename P::T* __restrict__ w,
                                             const typename P::Acc* __restrict__ bias,
                                             typename P::T* __restrict__ y, int cout_p, int H, int W, int ks, int bz,
-                                            int co0, int iy, int ix0) {
+                                            int co0, int iy, int ix0, const int* __restrict__ skip = nullptr) {
     using T = typename P::T;
     using Acc = typename P::Acc;
     using AccV = typename P::AccV;
     using Frag = typename P::Frag;
+    const int skipped = skip ? *skip : 0;   // tested once the first loads are in flight
     constexpr int KSM = convT2_ksmax<P>();
     constexpr int PS = KSM + 16 / (int)sizeof(T);
     constexpr int VE = 16 / sizeof(T);
@@ -613,6 +619,8 @@ __device__ __forceinline__ void convT2_tile(const typename P::T* __restrict__ x,
         }
     };
     gload(0);
+    asm volatile("" ::: "memory");
+    if (skipped) return;   // uniform over the block
     for (int k0 = 0; k0 < cin_p; k0 += ks) {
         __syncthreads();
         lstore();
@@ -670,7 +678,6 @@ __global__ __launch_bounds__(CT) void k_convT2(const typename P::T* __restrict__
                                                const typename P::Acc* __restrict__ bias,
                                                typename P::T* __restrict__ y, int cout_p, int H, int W, int ck,
                                                const int* __restrict__ skip) {
-    if (skip && *skip) return;
     const int ncb_tot = cout_p / TN;
     const int nblk = gridDim.x * gridDim.y * gridDim.z;
     int v = xcd_linear(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nblk);
@@ -680,7 +687,7 @@ __global__ __launch_bounds__(CT) void k_convT2(const typename P::T* __restrict__
     v /= gridDim.x;
     const int tyi = v % gridDim.y;
     const int bz = v / gridDim.y;
-    convT2_tile<P, TN>(x, cin_p, w, bias, y, cout_p, H, W, ck, bz, cbi * TN, tyi, txi * 64);
+    convT2_tile<P, TN>(x, cin_p, w, bias, y, cout_p, H, W, ck, bz, cbi * TN, tyi, txi * 64, skip);
 }
 
 template <class P, int TN>

@@ -13,31 +13,44 @@ inline int round16(int c) { return (c + 15) / 16 * 16; }
 
 // X[y][x][0..7] = [Re v / s, Im v / s, (c / c_ref, sigma_x, sigma_y), 0...] on the grid, 0 in the
 // padding, for padded pixel idx; is = 1 / s. vscale: v <- vscale v first (rounded to the vector
-// precision, stored back through vout).
+// precision, stored back through vout). skipped: every input is loaded first and nothing is
+// written (the caller's step-skip flag, whose load then overlaps these).
 template <class P, typename C>
 __device__ __forceinline__ void pack_pixel(const C* __restrict__ v, double is, const double* __restrict__ cnd,
                                            const double* __restrict__ sigx, const double* __restrict__ sigy, int nxt,
                                            int nyt, int Wp, int in_ch, typename P::T* __restrict__ X, int64_t idx,
-                                           const double* __restrict__ vscale, C* vout) {
+                                           const double* __restrict__ vscale, C* vout, int skipped = 0) {
     using T = typename P::T;
     const int yy = (int)(idx / Wp), xx = (int)(idx % Wp);
+    const bool on_grid = yy < nyt && xx < nxt;
+    const int64_t g = (int64_t)yy * nxt + xx;
+    C a{};
+    double f = 1.0, cn = 0.0, sx = 0.0, sy = 0.0;
+    if (on_grid) {
+        a = v[g];
+        if (vscale) f = *vscale;
+        if (in_ch == 5) {
+            cn = cnd[g];
+            sx = sigx[xx];
+            sy = sigy[yy];
+        }
+    }
+    asm volatile("" ::: "memory");   // the loads stay above the test
+    if (skipped) return;
     __attribute__((aligned(16))) T out[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) out[c] = P::cvt(0);
-    if (yy < nyt && xx < nxt) {
-        const int64_t g = (int64_t)yy * nxt + xx;
-        C a = v[g];
+    if (on_grid) {
         if (vscale) {
-            const double f = *vscale;
             a = from_d2<C>(double2{a.x * f, a.y * f});
             vout[g] = a;
         }
         out[0] = P::cvt((typename P::Acc)((double)a.x * is));
         out[1] = P::cvt((typename P::Acc)((double)a.y * is));
         if (in_ch == 5) {
-            out[2] = P::cvt((typename P::Acc)cnd[g]);
-            out[3] = P::cvt((typename P::Acc)sigx[xx]);
-            out[4] = P::cvt((typename P::Acc)sigy[yy]);
+            out[2] = P::cvt((typename P::Acc)cn);
+            out[3] = P::cvt((typename P::Acc)sx);
+            out[4] = P::cvt((typename P::Acc)sy);
         }
     }
     T* dst = X + idx * 8;   // 8 channels per pixel: 16 B (BF16) or whole 16-byte vectors
@@ -58,10 +71,11 @@ __global__ void k_pack(const C* __restrict__ v, double* __restrict__ sc, const d
                        int Wp, int in_ch, typename P::T* __restrict__ X, const int* __restrict__ skip,
                        double fixed_s = 0.0, const double* __restrict__ vscale = nullptr, C* vout = nullptr,
                        const double2* __restrict__ npart = nullptr, int nnp = 0, int ldp = 0) {
-    if (skip && *skip) return;
+    const int skipped = skip ? *skip : 0;   // tested after the pixel's loads (see pack_pixel)
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double is;
     if (npart) {
+        if (skipped) return;   // uniform over the block
         __shared__ double red[4];
         double a = 0;
         for (int q = threadIdx.x; q < nnp; q += blockDim.x) a += npart[(int64_t)q * ldp].x;
@@ -79,7 +93,7 @@ __global__ void k_pack(const C* __restrict__ v, double* __restrict__ sc, const d
         is = fixed_s > 0 ? 1.0 / fixed_s : sc[1];
     }
     if (idx >= (int64_t)Hp * Wp) return;
-    pack_pixel<P, C>(v, is, cnd, sigx, sigy, nxt, nyt, Wp, in_ch, X, idx, vscale, vout);
+    pack_pixel<P, C>(v, is, cnd, sigx, sigy, nxt, nyt, Wp, in_ch, X, idx, vscale, vout, skipped);
 }
 
 
