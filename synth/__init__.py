@@ -37,6 +37,7 @@ COMP_ORDER = 7          # the per-epoch visiting order of a fixed training set
 CFG_C1, CFG_C2, CFG_C3, CFG_C4, CFG_C5 = 1, 2, 3, 4, 5
 CFG_APPB = 8            # the second synthetic workload (simplified spherical-wave and seismic settings)
 CFG_TRAIN = 9           # epoch-based training on a fixed data set (Section 3.4)
+CFG_TABLE4 = 10         # the six training data sets D0-D5 of Section 3.2 (Table 4)
 VAL_FIRST = 10_000_000  # first stream index of validation samples (disjoint from training ones)
 
 
@@ -368,3 +369,62 @@ def epoch_order(count: int, epoch: int) -> np.ndarray:
     """The order in which epoch ``epoch`` visits a training set of ``count`` samples (a seeded
     permutation, drawn here so that the oracle and the GPU loop visit the same batches)."""
     return rng_for(CFG_TRAIN, COMP_ORDER, epoch).permutation(count)
+
+
+# --------------------------------------------------------------------------- Table 4 data sets
+
+# Section 3.2, Table 4: per data set, the source classes and the velocity classes with the
+# probabilities they are drawn with. The idealized-skull class is stood in for by skull rings.
+TABLE4 = {
+    "D0": ((("normal", "dirac", "dirac1", "dirac4"), (0.6, 0.3, 0.05, 0.05)), (("uniform", "skull"), (0.5, 0.5))),
+    "D1": ((("normal",), (1.0,)), (("uniform", "skull"), (0.5, 0.5))),
+    "D2": ((("normal", "dirac", "dirac1", "dirac4"), (0.6, 0.3, 0.05, 0.05)),
+           (("uniform", "skull", "rand_constant", "square"), (0.4, 0.4, 0.1, 0.1))),
+    "D3": ((("normal",), (1.0,)), (("uniform", "skull", "rand_constant", "square"), (0.4, 0.4, 0.1, 0.1))),
+    "D4": ((("normal",), (1.0,)), (("skull",), (1.0,))),
+    "D5": ((("normal",), (1.0,)), (("uniform",), (1.0,))),
+}
+
+
+def table4_classes(dataset: str, rng: np.random.Generator):
+    """(source class, velocity class) of one sample of data set D0..D5, drawn with Table 4's
+    probabilities (source first, then velocity, one uniform draw each)."""
+    (bk, bp), (ck, cp) = TABLE4[dataset]
+    ub, uc = rng.uniform(), rng.uniform()
+    b = bk[min(int(np.searchsorted(np.cumsum(bp), ub, side="right")), len(bk) - 1)]
+    c = ck[min(int(np.searchsorted(np.cumsum(cp), uc, side="right")), len(ck) - 1)]
+    return b, c
+
+
+def table4_sample(dataset: str, nt: int, npml: int, rng: np.random.Generator):
+    """One (velocity in m/s [nt, nt], source complex128 [nt, nt]) pair of data set D0..D5."""
+    bkind, ckind = table4_classes(dataset, rng)
+    if ckind == "uniform":
+        c = uniform_velocity(nt, rng)
+    elif ckind == "skull":
+        c = skull_ring_velocity(nt, npml, rng, rings=int(rng.integers(1, 4)))
+    elif ckind == "rand_constant":
+        c = rand_constant_velocity(nt, rng)
+    else:
+        c = square_velocity(nt)
+    if bkind == "normal":
+        b = normal_source(nt, rng)
+    elif bkind == "dirac":
+        b = dirac_source(nt, rng)
+    elif bkind == "dirac1":
+        b = dirac_source(nt, rng, centred=True)
+    else:
+        b = dirac4_source(nt)
+    return c, b
+
+
+def table4_set(dataset: str, count: int, nt: int, npml: int, *, first: int = 0):
+    """A fixed data set of ``count`` pairs of D0..D5 on one grid; sample i draws from stream
+    ``first + i`` of the data set (validation sets use ``first = VAL_FIRST``).
+    Returns (c [count, nt, nt] float64 in m/s, b [count, nt, nt] complex128)."""
+    k = int(dataset[1])
+    cs = np.empty((count, nt, nt), np.float64)
+    bs = np.empty((count, nt, nt), np.complex128)
+    for i in range(count):
+        cs[i], bs[i] = table4_sample(dataset, nt, npml, rng_for(CFG_TABLE4, k, first + i))
+    return cs, bs
