@@ -30,12 +30,13 @@ struct Layer {
 
 // 8x8 stride-2 padding-3 convolution (up = false: y is [Hin/2][Win/2]) or transposed convolution
 // (up = true: y is [2 Hin][2 Win]) of concat[x0, x1] (x1 = NULL and cat_cp = 0 without a second
-// part), + bias, then PReLU with slope bias[cout_p]; w packed [64 taps][cout_p][cin_p]; 32 output
-// channels (defined in net8.hip).
+// part), + bias, then PReLU with slope bias[cout_p]; w packed [64 taps][wcout][cin_p] (the 32
+// output channels are the first rows of each tap; wcout >= 32); 32 output channels; ypre (optional)
+// receives the pre-activation values (defined in net8.hip).
 template <class P>
 int launch_conv8(bool up, const typename P::T* x0, const typename P::T* x1, int cin_p, int cat_cp,
                  const typename P::T* w, const typename P::Acc* bias, typename P::T* y, int cout_p, int Hin, int Win,
-                 int batch, const int* skip, hipStream_t s);
+                 int batch, const int* skip, hipStream_t s, typename P::T* ypre = nullptr, int wcout = 32);
 
 }  // namespace hz
 

@@ -88,8 +88,8 @@ static bool build_layers(const no_arch* a, std::vector<Layer>& L, int64_t& npara
 
 // Repack one layer from the flat FP32 vector into [tap][cout_p][cin_p] (channels
 // padded with zeros) in BF16, FP32 and FP64, and its bias into FP32 and FP64.
-// The data-gradient packs hold the same values at [8 - tap][ci][co] (3x3) or [ab][ci][co]
-// (transposed convolutions).
+// The data-gradient packs hold the same values at [8 - tap][ci][co] (3x3) or [tap][ci][co]
+// (transposed 2x2 and the 8x8 layers).
 // One launch covers every layer: the blocks of layer l are [start[l], start[l + 1]).
 __global__ void k_repack(const float* __restrict__ theta, const Layer* __restrict__ layers,
                          const int64_t* __restrict__ start, int nl, bf16_t* __restrict__ wb,
@@ -132,7 +132,9 @@ __global__ void k_repack(const float* __restrict__ theta, const Layer* __restric
         wb[ly.pk_off + idx] = f2bf(v);
         wf[ly.pk_off + idx] = v;
         wd[ly.pk_off + idx] = (double)v;
-        if (ly.kind == L_CONV3 || ly.kind == L_CONVT2) {
+        if (ly.kind != L_CONV1) {
+            // data-gradient pack [tap][cin_p][cout_p]: flipped taps for the 3x3 layers; for the 8x8
+            // layers the same taps, which makes each one's data gradient the opposite 8x8 form
             const int tt = ly.kind == L_CONV3 ? 8 - tap : tap;
             const int64_t j = ((int64_t)tt * ly.cin_p + cis) * ly.cout_p + co;
             tb[ly.pk_off + j] = f2bf(v);

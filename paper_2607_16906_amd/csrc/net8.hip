@@ -32,7 +32,8 @@ template <class P, bool UP>
 __global__ __launch_bounds__(512) void k_conv8(
     const typename P::T* __restrict__ x0, const typename P::T* __restrict__ x1, int cin_p, int cat_cp,
     const typename P::T* __restrict__ w, const typename P::Acc* __restrict__ bias, typename P::T* __restrict__ y,
-    int Hin, int Win, int batch, int tiles, int ks, const int* __restrict__ skip) {
+    int Hin, int Win, int batch, int tiles, int ks, const int* __restrict__ skip, typename P::T* __restrict__ ypre,
+    int wcout) {
     using T = typename P::T;
     using Acc = typename P::Acc;
     using Frag = typename P::Frag;
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(512) void k_conv8(
             const bool ok = qv[t] && iy >= 0 && iy < Hin && ix >= 0 && ix < Win;
             bf[t] = ok ? P::load(src + ((int64_t)iy * Win + ix) * cstr + cc) : P::zero();
         }
-        const T* wt = w + ((int64_t)(a * 8 + e) * COUT + col) * cin_p + ci;
+        const T* wt = w + ((int64_t)(a * 8 + e) * wcout + col) * cin_p + ci;
 #pragma unroll
         for (int m = 0; m < 2; ++m) af[m] = P::load(wt + (int64_t)m * 16 * cin_p);
     };
@@ -155,16 +156,18 @@ __global__ __launch_bounds__(512) void k_conv8(
         if (!qv[t]) continue;
         const int oy = UP ? 2 * qy[t] + py : qy[t];
         const int ox = UP ? 2 * qx[t] + px : qx[t];
-        T* dst = y + (((int64_t)b * Ho + oy) * Wo + ox) * COUT;
+        const int64_t o = (((int64_t)b * Ho + oy) * Wo + ox) * COUT;
 #pragma unroll
         for (int m = 0; m < 2; ++m) {
-            Acc v[4];
+            Acc v[4], sv[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const Acc s = acc[m][t][r] + bias[m * 16 + P::row_of(g, r)];
+                sv[r] = s;
                 v[r] = s > 0 ? s : slope * s;
             }
-            store_rows<P>(dst + m * 16 + P::row_of(g, 0), v);
+            store_rows<P>(y + o + m * 16 + P::row_of(g, 0), v);
+            if (ypre) store_rows<P>(ypre + o + m * 16 + P::row_of(g, 0), sv);   // pre-activation (training)
         }
     }
 }
@@ -172,12 +175,12 @@ __global__ __launch_bounds__(512) void k_conv8(
 template <class P>
 int launch_conv8(bool up, const typename P::T* x0, const typename P::T* x1, int cin_p, int cat_cp,
                  const typename P::T* w, const typename P::Acc* bias, typename P::T* y, int cout_p, int Hin, int Win,
-                 int batch, const int* skip, hipStream_t s) {
+                 int batch, const int* skip, hipStream_t s, typename P::T* ypre, int wcout) {
     // shapes the kernel assumes: 32 output channels, input channels in whole K steps (a step of
     // 4 GW values may span several taps when cin_p < 4 GW), even input sides for the down form
     if (cout_p != 32 || cin_p < P::GW || cin_p % P::GW || cin_p > 64 || ((up ? 16 : 64) * cin_p) % (4 * P::GW) ||
         (cat_cp > 0 && (!x1 || cat_cp % P::GW || cat_cp >= cin_p)) || Hin < 1 || Win < 1 || batch < 1 ||
-        (!up && (Hin % 2 || Win % 2))) {
+        (!up && (Hin % 2 || Win % 2)) || wcout < 32) {
         set_error("conv8: unsupported layer shape");
         return HZ_ERR_ARG;
     }
@@ -195,19 +198,19 @@ int launch_conv8(bool up, const typename P::T* x0, const typename P::T* x1, int 
     const size_t shm = ks > 1 ? (size_t)nw * 16 * 64 * sizeof(typename P::Acc) : 0;
     if (up)
         hipLaunchKernelGGL((k_conv8<P, true>), dim3(grid), dim3(64 * nw), shm, s, x0, x1, cin_p, cat_cp, w, bias, y,
-                           Hin, Win, batch, tiles, ks, skip);
+                           Hin, Win, batch, tiles, ks, skip, ypre, wcout);
     else
         hipLaunchKernelGGL((k_conv8<P, false>), dim3(grid), dim3(64 * nw), shm, s, x0, x1, cin_p, cat_cp, w, bias, y,
-                           Hin, Win, batch, tiles, ks, skip);
+                           Hin, Win, batch, tiles, ks, skip, ypre, wcout);
     HZ_LAUNCH_CHECK();
     return HZ_OK;
 }
 
 template int launch_conv8<PolBF16>(bool, const bf16_t*, const bf16_t*, int, int, const bf16_t*, const float*, bf16_t*,
-                                   int, int, int, int, const int*, hipStream_t);
+                                   int, int, int, int, const int*, hipStream_t, bf16_t*, int);
 template int launch_conv8<PolF32>(bool, const float*, const float*, int, int, const float*, const float*, float*, int,
-                                  int, int, int, const int*, hipStream_t);
+                                  int, int, int, const int*, hipStream_t, float*, int);
 template int launch_conv8<PolF64>(bool, const double*, const double*, int, int, const double*, const double*, double*,
-                                  int, int, int, int, const int*, hipStream_t);
+                                  int, int, int, int, const int*, hipStream_t, double*, int);
 
 }  // namespace hz

@@ -1202,6 +1202,400 @@ static int loss_backward_impl(const no_net* net, int B, const hz_problem* const*
     return HZ_OK;
 }
 
+// ------------------------------------------------------------------ Table 2's network (FP32)
+//
+// Reverse mode of the 8x8 stride-2 layer set (Section 3.1, Table 2), in the paper's training
+// precision (FP32). With s the pre-activation of a layer and g the gradient of its PReLU output:
+//   PReLU:  gs = g (s > 0), alpha g (s <= 0); d alpha = sum_{s <= 0} s g; d b = sum gs;
+//   weights: d W[m][n][tap] = sum over the coarse pixels (i, j) of coarse[i][j][m] times
+//            fine[2i + a - 3][2j + e - 3][n] (tap = 8 a + e, fine values outside the grid are 0):
+//            a strided convolution has coarse = gs, fine = its input (m = out, n = in channel), a
+//            transposed one coarse = its input, fine = gs (m = in, n = out), matching the stored
+//            [out][in][8][8] and [in][out][8][8] orders;
+//   data:   the input gradient of a strided convolution is the transposed 8x8 form of gs with the
+//            data-gradient pack, that of a transposed convolution the strided form (both through
+//            k_conv8 with a linear epilogue: zero bias, slope 1);
+//   the decoder's concat input splits its gradient into the skip part (added to the encoder
+//   output's gradient) and the up part.
+// All sums over pixels run in fixed orders (per-block partials, then the blocks in order).
+
+constexpr int W8_CHUNKS = 16;    // pixel chunks of the 8x8 weight-gradient kernel
+constexpr int PR_BLOCKS = 256;   // blocks of the PReLU backward (partial rows)
+
+// In place: g <- gs = (g (+ g2)) * prelu'(s); part[blk][c] = sum gs (c < 32), part[blk][32] =
+// sum_{s <= 0} s (g (+ g2)). 32 channels per pixel; thread (lane l of 8, channel c) strides over
+// the block's pixels, then the 8 lanes are added in order.
+__global__ __launch_bounds__(TT) void k_prelu8_bwd(float* __restrict__ g, const float* __restrict__ g2,
+                                                   const float* __restrict__ spre, const float* __restrict__ bias,
+                                                   int64_t npx, int64_t per, float* __restrict__ part) {
+    const int c = threadIdx.x & 31, pl = threadIdx.x >> 5;
+    const float alpha = bias[32];
+    const int64_t p0 = (int64_t)blockIdx.x * per, p1 = min(npx, p0 + per);
+    float db = 0.f, da = 0.f;
+    for (int64_t p = p0 + pl; p < p1; p += 8) {
+        const int64_t i = p * 32 + c;
+        float v = g[i];
+        if (g2) v += g2[i];
+        const float sv = spre[i];
+        const float gs = sv > 0.f ? v : alpha * v;
+        if (!(sv > 0.f)) da += sv * v;
+        g[i] = gs;
+        db += gs;
+    }
+    __shared__ float rb[8][32], ra[TT];
+    rb[pl][c] = db;
+    ra[threadIdx.x] = da;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        float t = 0.f;
+        for (int l = 0; l < 8; ++l) t += rb[l][threadIdx.x];
+        part[(int64_t)blockIdx.x * 33 + threadIdx.x] = t;
+    }
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int k = 0; k < TT; ++k) t += ra[k];
+        part[(int64_t)blockIdx.x * 33 + 32] = t;
+    }
+}
+
+// grad[b_off + c] = sum_blk part[blk][c] (c < 32), grad[a_off] = sum_blk part[blk][32], in block
+// order.
+__global__ void k_prelu8_reduce(const float* __restrict__ part, int nblk, int64_t b_off, int64_t a_off,
+                                float* __restrict__ grad) {
+    const int c = threadIdx.x;
+    if (c > 32) return;
+    float t = 0.f;
+    for (int z = 0; z < nblk; ++z) t += part[(int64_t)z * 33 + c];
+    if (c < 32) grad[b_off + c] = t;
+    else grad[a_off] = t;
+}
+
+// Weight-gradient partials of one 8x8 layer on the matrix cores (v_mfma_f32_16x16x4_f32, 4 coarse
+// pixels per instruction): block (tap, 16-row block of m, chunk z); its 4 wavefronts take the
+// chunk's pixel quads round-robin, each for all n blocks, and are added in wavefront order.
+// coarse: [B][Hc][Wc][cms] (channels m0 .. of it from column cmo), fine: [B][2Hc][2Wc][cns] (N
+// channels used, N <= 32). part[z][(m * NP + n) * 64 + tap], NP = 32.
+__global__ __launch_bounds__(TT) void k_wgrad8(const float* __restrict__ coarse, int cms, int cmo,
+                                               const float* __restrict__ fine, int cns, int N, int Hc, int Wc, int B,
+                                               int64_t per, float* __restrict__ part, int mrows) {
+    const int tap = blockIdx.x, mb = blockIdx.y, z = blockIdx.z;
+    const int a = tap >> 3, e = tap & 7;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int m = mb * 16 + col;   // A row of this lane
+    const int64_t npx = (int64_t)B * Hc * Wc;
+    const int64_t p0 = (int64_t)z * per, p1 = min(npx, p0 + per);
+    const int Hf = 2 * Hc, Wf = 2 * Wc;
+    f32x4_t acc[2] = {f32x4_t{0.f, 0.f, 0.f, 0.f}, f32x4_t{0.f, 0.f, 0.f, 0.f}};
+    for (int64_t q = p0 + 4 * wv; q < p1; q += 16) {
+        const int64_t p = q + kq;
+        float av = 0.f, bv0 = 0.f, bv1 = 0.f;
+        if (p < p1) {
+            const int b = (int)(p / ((int64_t)Hc * Wc));
+            const int r = (int)(p - (int64_t)b * Hc * Wc);
+            const int i = r / Wc, j = r - (r / Wc) * Wc;
+            av = coarse[p * cms + cmo + m];
+            const int fy = 2 * i + a - 3, fx = 2 * j + e - 3;
+            if (fy >= 0 && fy < Hf && fx >= 0 && fx < Wf) {
+                const float* fr = fine + (((int64_t)b * Hf + fy) * Wf + fx) * cns;
+                if (col < N) bv0 = fr[col];
+                if (16 + col < N) bv1 = fr[16 + col];
+            }
+        }
+        acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv0, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv1, acc[1], 0, 0, 0);
+    }
+    __shared__ f32x4_t red[4][2][64];
+    red[wv][0][lane] = acc[0];
+    red[wv][1][lane] = acc[1];
+    __syncthreads();
+    if (wv != 0) return;
+    f32x4_t t0 = red[0][0][lane], t1 = red[0][1][lane];
+    for (int w = 1; w < 4; ++w) {
+        t0 += red[w][0][lane];
+        t1 += red[w][1][lane];
+    }
+    // D layout: lane l holds rows 4 (l / 16) + r (m) of column l % 16 (n)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int mm = mb * 16 + 4 * kq + r;
+        if (mm >= mrows) continue;
+        float* dst = part + (int64_t)z * mrows * 32 * 64;
+        if (col < N) dst[((int64_t)mm * 32 + col) * 64 + tap] = t0[r];
+        if (16 + col < N) dst[((int64_t)mm * 32 + 16 + col) * 64 + tap] = t1[r];
+    }
+}
+
+// grad[w_off + (m * Nl + n) * 64 + tap] = sum_z part[z][(m * 32 + n) * 64 + tap] (m < Ml, n < Nl),
+// chunks in order.
+__global__ void k_wgrad8_reduce(const float* __restrict__ part, int nchunk, int mrows, int Ml, int Nl, int64_t w_off,
+                                float* __restrict__ grad) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)Ml * Nl * 64) return;
+    const int tap = (int)(t % 64);
+    const int n = (int)((t / 64) % Nl);
+    const int m = (int)(t / (64 * Nl));
+    const int64_t slot = ((int64_t)m * 32 + n) * 64 + tap;
+    float a = 0.f;
+    for (int z = 0; z < nchunk; ++z) a += part[(int64_t)z * mrows * 32 * 64 + slot];
+    grad[w_off + t] = a;
+}
+
+// G(U0)[p][c] = g0 Wh[0][c] + g1 Wh[1][c] (the PReLU of the last up layer is handled by its own
+// backward step).
+__global__ void k_head8_dgrad(const float2* __restrict__ gz, const float* __restrict__ coef,
+                              const double* __restrict__ sc, const float* __restrict__ wh, int nxt, int nyt, int Hp,
+                              int Wp, int B, float* __restrict__ G) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t np = (int64_t)Hp * Wp;
+    if (idx >= np * B * 32) return;
+    const int c = (int)(idx % 32);
+    const int64_t pp = idx / 32;
+    const int b = (int)(pp / np);
+    const int64_t q = pp - (int64_t)b * np;
+    const float2 g = head_grad(gz, coef, sc, b, (int)(q / Wp), (int)(q % Wp), nxt, nyt);
+    G[idx] = g.x * wh[c] + g.y * wh[32 + c];
+}
+
+// linear epilogue of the data-gradient launches: zero bias, PReLU slope 1
+__global__ void k_linear_bias(float* b) {
+    if (threadIdx.x < 33) b[threadIdx.x] = threadIdx.x == 32 ? 1.f : 0.f;
+}
+
+struct Train8Bufs {
+    FwdBufs f;                      // X, E[1..L], U[0..L-1] (the forward's activations)
+    std::vector<float*> sE, sU;     // pre-activations
+    std::vector<float*> gE, gU;     // activation gradients
+    float* tmp;                     // data gradient of a strided convolution (finest level size)
+    float2 *z, *y, *gz;
+    double2* rpart;
+    double* ypart;
+    double *sc, *nr;
+    float* coef;
+    SampleProb* sprob;
+    float *wpart, *ppart, *lin;
+    size_t total;
+};
+
+static Train8Bufs train8_layout(const no_net* net, const hz_problem* p, int B, void* base, size_t cap) {
+    Train8Bufs t;
+    int Hp, Wp;
+    net_padded_dims(net, p, &Hp, &Wp);
+    t.f = fwd_layout<PolF32>(net, Hp, Wp, B, base, cap);
+    Carver c(base, cap);
+    c.off = t.f.total;
+    const int lv = net->a.levels;
+    t.sE.assign(lv + 1, nullptr);
+    t.gE.assign(lv + 1, nullptr);
+    t.sU.assign(lv, nullptr);
+    t.gU.assign(lv, nullptr);
+    for (int l = 1; l <= lv; ++l) {
+        const size_t px = (size_t)B * (Hp >> l) * (Wp >> l);
+        t.sE[l] = c.take<float>(px * 32);
+        t.gE[l] = c.take<float>(px * 32);
+    }
+    for (int l = 0; l < lv; ++l) {
+        const size_t px = (size_t)B * (Hp >> l) * (Wp >> l);
+        t.sU[l] = c.take<float>(px * 32);
+        t.gU[l] = c.take<float>(px * 32);
+    }
+    t.tmp = c.take<float>((size_t)B * (Hp >> 1) * (Wp >> 1) * 32);
+    const int64_t n = p->n;
+    t.z = c.take<float2>((size_t)B * n);
+    t.y = c.take<float2>((size_t)B * n);
+    t.gz = c.take<float2>((size_t)B * n);
+    Split sp = krylov_split(n);
+    t.rpart = c.take<double2>((size_t)B * sp.nblk);
+    t.ypart = c.take<double>((size_t)B * stencil_blocks(p));
+    t.sc = c.take<double>(2 * (size_t)B);
+    t.nr = c.take<double>(B);
+    t.coef = c.take<float>(B);
+    t.sprob = c.take<SampleProb>(B);
+    t.wpart = c.take<float>((size_t)W8_CHUNKS * 64 * 32 * 64);
+    const Layer& lh = net->layers.back();
+    t.ppart = c.take<float>(std::max<size_t>((size_t)PR_BLOCKS * 33, (size_t)WCHUNKS_MAX * (2 * lh.cin_p + 2)));
+    t.lin = c.take<float>(64);
+    t.total = c.off + 256;
+    return t;
+}
+
+// d W of one 8x8 layer into the flat gradient; coarse given as up to two channel parts of 32
+static int wgrad8(const Layer& ly, const float* c0p, const float* c1p, int cms0, int cms1, const float* fine, int cns,
+                  int N, int Hc, int Wc, int B, Train8Bufs& t, float* grad, int Ml, int Nl, hipStream_t s) {
+    const int64_t npx = (int64_t)B * Hc * Wc;
+    const int64_t per = ((npx + W8_CHUNKS - 1) / W8_CHUNKS + 15) / 16 * 16;
+    const int nchunk = (int)((npx + per - 1) / per);
+    const int mrows = Ml > 32 ? 64 : 32;
+    // first part: rows [0, 32) from c0p; second (concat): rows [32, 64) from c1p
+    hipLaunchKernelGGL(k_wgrad8, dim3(64, 2, nchunk), dim3(TT), 0, s, c0p, cms0, 0, fine, cns, N, Hc, Wc, B, per,
+                       t.wpart, mrows);
+    HZ_LAUNCH_CHECK();
+    if (c1p) {
+        hipLaunchKernelGGL(k_wgrad8, dim3(64, 2, nchunk), dim3(TT), 0, s, c1p, cms1, 0, fine, cns, N, Hc, Wc, B, per,
+                           t.wpart + (int64_t)32 * 32 * 64, mrows);
+        HZ_LAUNCH_CHECK();
+    }
+    const int64_t nout = (int64_t)Ml * Nl * 64;
+    hipLaunchKernelGGL(k_wgrad8_reduce, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, t.wpart, nchunk, mrows,
+                       Ml, Nl, ly.w_off, grad);
+    HZ_LAUNCH_CHECK();
+    return HZ_OK;
+}
+
+static int prelu8_bwd(const Layer& ly, const no_net* net, float* g, const float* g2, const float* spre, int64_t npx,
+                      Train8Bufs& t, float* grad, hipStream_t s) {
+    const int64_t per = (npx + PR_BLOCKS - 1) / PR_BLOCKS;
+    const int nblk = (int)((npx + per - 1) / per);
+    hipLaunchKernelGGL(k_prelu8_bwd, dim3(nblk), dim3(TT), 0, s, g, g2, spre, packed_b<PolF32>(net, ly), npx, per,
+                       t.ppart);
+    HZ_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_prelu8_reduce, dim3(1), dim3(64), 0, s, t.ppart, nblk, ly.b_off, ly.a_off, grad);
+    HZ_LAUNCH_CHECK();
+    return HZ_OK;
+}
+
+size_t train8_ws_bytes(const no_net* net, const hz_problem* p, int B) {
+    return train8_layout(net, p, B, nullptr, 0).total;
+}
+
+int loss_backward8(const no_net* net, int B, const hz_problem* const* probs, const float2* r, int squared,
+                   float* loss, float* per_sample, float* grad, void* ws, size_t ws_bytes, hipStream_t s) {
+    using P = PolF32;
+    const hz_problem* p0 = probs[0];
+    Train8Bufs t = train8_layout(net, p0, B, ws, ws_bytes);
+    if (t.total > ws_bytes) {
+        set_error("no_loss_backward: workspace too small");
+        return HZ_ERR_WORKSPACE;
+    }
+    int Hp, Wp;
+    net_padded_dims(net, p0, &Hp, &Wp);
+    const int64_t n = p0->n;
+    const int lv = net->a.levels;
+    const std::vector<Layer>& Ls = net->layers;
+    Split sp = krylov_split(n);
+    {
+        std::vector<SampleProb> hp(B);
+        for (int b = 0; b < B; ++b) {
+            const hz_problem* q = probs[b];
+            hp[b] = SampleProb{q->k2f, q->cnd, q->sigx, q->sigy, q->fE_f, q->fW_f, q->fN_f, q->fS_f,
+                               q->aE_f, q->aW_f, q->aN_f, q->aS_f, q->dx_f, q->dy_f};
+        }
+        HZ_HIP(hipMemcpyAsync(t.sprob, hp.data(), sizeof(SampleProb) * B, hipMemcpyHostToDevice, s));
+    }
+    hipLaunchKernelGGL(k_norm_batched, dim3(sp.nblk, B), dim3(KT), 0, s, r, n, sp.per_block, t.rpart, sp.nblk);
+    HZ_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sample_scales, dim3(B), dim3(64), 0, s, t.rpart, sp.nblk, n, t.sc, t.nr);
+    HZ_LAUNCH_CHECK();
+    const unsigned gp = (unsigned)(((int64_t)Hp * Wp + 255) / 256);
+    hipLaunchKernelGGL((k_pack_batched<P>), dim3(gp, B), dim3(256), 0, s, r, n, t.sc, t.sprob, p0->nxt, p0->nyt, Hp, Wp,
+                       net->a.in_ch, (float*)t.f.X);
+    HZ_LAUNCH_CHECK();
+    // forward, keeping the pre-activations
+    std::vector<int> dn(lv + 1), upl(lv);
+    {
+        int li = 0;
+        for (int l = 1; l <= lv; ++l) dn[l] = li++;
+        upl[lv - 1] = li++;
+        for (int l = lv - 2; l >= 0; --l) upl[l] = li++;
+    }
+    const float* in = (const float*)t.f.X;
+    for (int l = 1; l <= lv; ++l) {
+        const Layer& ly = Ls[dn[l]];
+        HZ_TRY(launch_conv8<P>(false, in, nullptr, ly.cin_p, 0, packed_w<P>(net, ly), packed_b<P>(net, ly),
+                               (float*)t.f.E[l], 32, Hp >> (l - 1), Wp >> (l - 1), B, nullptr, s, t.sE[l]));
+        in = (const float*)t.f.E[l];
+    }
+    {
+        const Layer& ly = Ls[upl[lv - 1]];
+        HZ_TRY(launch_conv8<P>(true, (const float*)t.f.E[lv], nullptr, ly.cin_p, 0, packed_w<P>(net, ly),
+                               packed_b<P>(net, ly), (float*)t.f.U[lv - 1], 32, Hp >> lv, Wp >> lv, B, nullptr, s,
+                               t.sU[lv - 1]));
+    }
+    for (int l = lv - 2; l >= 0; --l) {
+        const Layer& ly = Ls[upl[l]];
+        HZ_TRY(launch_conv8<P>(true, (const float*)t.f.E[l + 1], (const float*)t.f.U[l + 1], ly.cin_p, ly.cat_cp,
+                               packed_w<P>(net, ly), packed_b<P>(net, ly), (float*)t.f.U[l], 32, Hp >> (l + 1),
+                               Wp >> (l + 1), B, nullptr, s, t.sU[l]));
+    }
+    const Layer& lh = Ls.back();
+    const float* U0 = (const float*)t.f.U[0];
+    {
+        const int64_t tot = (int64_t)B * n;
+        hipLaunchKernelGGL(k_head_batched<P>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, U0, lh.cin_p,
+                           packed_w<P>(net, lh), packed_b<P>(net, lh), t.sc, p0->nxt, p0->nyt, Hp, Wp, B, t.z);
+        HZ_LAUNCH_CHECK();
+    }
+    const int nst = stencil_blocks(p0);
+    {
+        const dim3 g((p0->nxt + ST_TX - 1) / ST_TX, (p0->nyt + ST_TY - 1) / ST_TY, B);
+        hipLaunchKernelGGL(k_resid_batched, g, dim3(ST_THREADS), 0, s, t.z, r, t.y, n, t.sprob, p0->nxt, p0->nyt,
+                           t.ypart);
+        HZ_LAUNCH_CHECK();
+        if (grad) {
+            hipLaunchKernelGGL(k_adjoint_batched, g, dim3(ST_THREADS), 0, s, t.y, t.gz, n, t.sprob, p0->nxt,
+                               p0->nyt);
+            HZ_LAUNCH_CHECK();
+        }
+    }
+    hipLaunchKernelGGL(k_loss, dim3(1), dim3(1024), 0, s, t.ypart, nst, t.nr, B, squared, t.coef, loss, per_sample);
+    HZ_LAUNCH_CHECK();
+    if (!grad) return HZ_OK;
+
+    // ---- head
+    {
+        const int64_t tot = (int64_t)B * Hp * Wp * 32;
+        hipLaunchKernelGGL(k_head8_dgrad, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, t.gz, t.coef, t.sc,
+                           packed_w<P>(net, lh), p0->nxt, p0->nyt, Hp, Wp, B, t.gU[0]);
+        HZ_LAUNCH_CHECK();
+        const int64_t np = (int64_t)B * Hp * Wp;
+        const int64_t per = (np + WCHUNKS_MAX - 1) / WCHUNKS_MAX;
+        const int nchunk = (int)((np + per - 1) / per);
+        hipLaunchKernelGGL(k_head_wgrad<P>, dim3(nchunk), dim3(TT), 0, s, t.gz, t.coef, t.sc, U0, lh.cin_p, p0->nxt,
+                           p0->nyt, Hp, Wp, B, per, t.ppart);
+        HZ_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_head_reduce, dim3((unsigned)((lh.cout * lh.cin + 2 + 3) / 4)), dim3(256), 0, s, t.ppart,
+                           nchunk, lh.cin_p, lh, grad);
+        HZ_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_linear_bias, dim3(1), dim3(64), 0, s, t.lin);
+    HZ_LAUNCH_CHECK();
+    // ---- decoder, finest level first: gU[l] holds the gradient of U_l
+    for (int l = 0; l < lv; ++l) {
+        const Layer& ly = Ls[upl[l]];
+        const int Hc = Hp >> (l + 1), Wc = Wp >> (l + 1);   // the layer's input size
+        const int64_t npx = (int64_t)B * (Hp >> l) * (Wp >> l);
+        HZ_TRY(prelu8_bwd(ly, net, t.gU[l], nullptr, t.sU[l], npx, t, grad, s));
+        const float* gs = t.gU[l];
+        const bool cat = l < lv - 1;
+        // d W[c][o][tap]: coarse = the input (E_{l+1} | U_{l+1}), fine = gs
+        HZ_TRY(wgrad8(ly, (const float*)t.f.E[l + 1], cat ? (const float*)t.f.U[l + 1] : nullptr, 32, 32, gs, 32, 32,
+                      Hc, Wc, B, t, grad, ly.cin, ly.cout, s));
+        // input gradient: the strided form of gs with the data-gradient pack [tap][cin_p][32]
+        const float* wt = packed_wt<P>(net, ly);
+        HZ_TRY(launch_conv8<P>(false, gs, nullptr, 32, 0, wt, t.lin, t.gE[l + 1], 32, Hp >> l, Wp >> l, B, nullptr, s,
+                               nullptr, ly.cin_p));
+        if (cat)
+            HZ_TRY(launch_conv8<P>(false, gs, nullptr, 32, 0, wt + 32 * 32, t.lin, t.gU[l + 1], 32, Hp >> l, Wp >> l,
+                                   B, nullptr, s, nullptr, ly.cin_p));
+    }
+    // ---- encoder, deepest first: the gradient of E_l is gE[l] (+ the strided layer above's data
+    // gradient in tmp, for l < L)
+    for (int l = lv; l >= 1; --l) {
+        const Layer& ly = Ls[dn[l]];
+        const int64_t npx = (int64_t)B * (Hp >> l) * (Wp >> l);
+        HZ_TRY(prelu8_bwd(ly, net, t.gE[l], l < lv ? t.tmp : nullptr, t.sE[l], npx, t, grad, s));
+        const float* gs = t.gE[l];
+        const float* xin = l == 1 ? (const float*)t.f.X : (const float*)t.f.E[l - 1];
+        const int cs_in = l == 1 ? 8 : 32;
+        // d W[o][c][tap]: coarse = gs, fine = the input
+        HZ_TRY(wgrad8(ly, gs, nullptr, 32, 0, xin, cs_in, cs_in, Hp >> l, Wp >> l, B, t, grad, ly.cout, ly.cin, s));
+        if (l > 1)   // input gradient: the transposed form of gs with the data-gradient pack [tap][32][32]
+            HZ_TRY(launch_conv8<P>(true, gs, nullptr, 32, 0, packed_wt<P>(net, ly), t.lin, t.tmp, 32, Hp >> l,
+                                   Wp >> l, B, nullptr, s, nullptr, 32));
+    }
+    return HZ_OK;
+}
+
 // ------------------------------------------------------------------ Adam
 
 __global__ void k_sqnorm_part(const float* __restrict__ g, int64_t n, double* __restrict__ part) {
@@ -1247,7 +1641,8 @@ using namespace hz;
 extern "C" size_t no_train_workspace_size(const no_net* net, const hz_problem* p, int batch, no_prec prec,
                                           int recompute) {
     clear_error();
-    if (!net || !p || batch < 1 || net->a.kind != NO_ARCH_UNET3) return 0;
+    if (!net || !p || batch < 1) return 0;
+    if (net->a.kind == NO_ARCH_PAPER8) return prec == NO_FP32 && !recompute ? train8_ws_bytes(net, p, batch) : 0;
     if (prec == NO_BF16) return train_layout<PolBF16>(net, p, batch, nullptr, 0, recompute != 0).total;
     if (prec == NO_FP32) return train_layout<PolF32>(net, p, batch, nullptr, 0, recompute != 0).total;
     return 0;
@@ -1258,7 +1653,8 @@ extern "C" int no_loss_backward(const no_net* net, int batch, const hz_problem* 
                                 void* ws, size_t ws_bytes, void* stream) {
     clear_error();
     HZ_CHECK_ARG(net && problems && r && loss && ws, "no_loss_backward: NULL argument");
-    HZ_CHECK_ARG(net->a.kind == NO_ARCH_UNET3, "no_loss_backward: training needs the UNET3 network");
+    HZ_CHECK_ARG(net->a.kind == NO_ARCH_UNET3 || (prec == NO_FP32 && !recompute),
+                 "no_loss_backward: Table 2's network trains in FP32 without activation checkpointing");
     HZ_CHECK_ARG(batch >= 1 && batch <= 1024, "no_loss_backward: batch must be in [1, 1024]");
     HZ_CHECK_ARG(prec == NO_BF16 || prec == NO_FP32, "no_loss_backward: precision must be NO_BF16 or NO_FP32");
     for (int b = 0; b < batch; ++b) {
@@ -1269,6 +1665,8 @@ extern "C" int no_loss_backward(const no_net* net, int batch, const hz_problem* 
         HZ_CHECK_ARG(!is_spectral(problems[b]), "no_loss_backward: finite-difference problems only");
     }
     hipStream_t s = (hipStream_t)stream;
+    if (net->a.kind == NO_ARCH_PAPER8)
+        return loss_backward8(net, batch, problems, (const float2*)r, squared, loss, per_sample, grad, ws, ws_bytes, s);
     if (prec == NO_BF16)
         return loss_backward_impl<PolBF16>(net, batch, problems, (const float2*)r, squared, recompute != 0, loss,
                                            per_sample, grad, ws, ws_bytes, s);
