@@ -32,6 +32,7 @@ PEAK_HBM_GBS = 8000.0
 
 
 WEIGHTS8 = os.path.join(ROOT, "paper_2607_16906_amd", "weights", "paper8_d4_c32_in5.npz")
+WEIGHTS_L5 = os.path.join(ROOT, "paper_2607_16906_amd", "weights", "unet_l5_c32_in5.npz")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "conv3_dominant_layer_296_bf16_traffic.txt")
 GOLDEN_C2 = os.path.join(ROOT, "tests", "golden", "c2_oracle.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2607_16906_amd", "csrc", f) for f in ("net_fwd.hip", "net_kernels.h")]
@@ -125,14 +126,14 @@ def net_layers(levels, base, in_ch, Hp, Wp):
     return out
 
 
-def time_layers(net, Hp, Wp, reps, prec="bf16", only=-1):
+def time_layers(net, Hp, Wp, reps, prec="bf16", only=-1, levels=LEVELS):
     """Per-layer average launch time (ms) with HIP events on the current stream, each layer with the
     launch variant the autotuner chose for it (the one the solve uses)."""
     import torch
     elem = {"bf16": torch.int16, "fp32": torch.float32}[prec]
     ws = torch.empty(4 * Hp * Wp * 32 * 4 + 256, dtype=torch.uint8, device="cuda")
     res = []
-    for (i, kind, cin, cout, H, W) in net_layers(LEVELS, BASE, IN_CH, Hp, Wp):
+    for (i, kind, cin, cout, H, W) in net_layers(levels, BASE, IN_CH, Hp, Wp):
         if only >= 0 and i != only:
             continue
         _, cin_p, cout_p, cat_cp = net.layer_info(i)
@@ -273,7 +274,11 @@ def bench_paper8(hz, torch, net3, reps=50):
                 parts.append(np.array([0.25], np.float32))
         theta8 = np.concatenate(parts).astype(np.float32)
     net8 = hz.Net(4, 32, 5, theta8, kind="paper8")
-    s = c2_system(0)
+    if args.roofline_only and args.roofline_grid == "large":
+        from synth import c5_system
+        s = c5_system(0)
+    else:
+        s = c2_system(0)
     gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW)
     v = torch.from_numpy(s.b.ravel().astype(np.complex64)).cuda()
     Hp = (s.nt + 15) // 16 * 16
@@ -349,7 +354,11 @@ def bench_train_then_solve(hz, torch, S=4096, V=256, batch=32, epochs=30, nint=6
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     net.set_weights(res.theta_best)
-    s = c2_system(0)
+    if args.roofline_only and args.roofline_grid == "large":
+        from synth import c5_system
+        s = c5_system(0)
+    else:
+        s = c2_system(0)
     gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW)
     bb = torch.from_numpy(s.b.ravel()).cuda()
     hz.fgmres(gp, bb, net=net, m=M_RESTART, tol=TOL, maxit=M_RESTART)
@@ -488,7 +497,11 @@ def bench_restart(hz, torch, net, runs=RESTART_RUNS):
     (one-reduction) form, with FP32 or FP64 Krylov vectors. The one-reduction form is not run with
     FP32 vectors at m = 512: it loses orthogonality there and stalls near 4e-4."""
     from synth import H_10PPW, c2_system
-    s = c2_system(0)
+    if args.roofline_only and args.roofline_grid == "large":
+        from synth import c5_system
+        s = c5_system(0)
+    else:
+        s = c2_system(0)
     gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW)
     b = torch.from_numpy(s.b.ravel()).cuda()
     rows = []
@@ -509,38 +522,41 @@ def bench_restart(hz, torch, net, runs=RESTART_RUNS):
     return {"workload": "single solve, 256^2 interior + 20 PML, BF16 U-Net, tol 1e-6, FGMRES(m)", "runs": rows}
 
 
-def bench_large(hz, torch, net, maxit=100, m=50):
-    """Large single solve: 1024^2 interior + 32 PML (1088^2 nodes), FGMRES(50), BF16 network (the
-    trained 4-level network stands in for a 5-level one), FP32 Krylov vectors, bounded to maxit
-    iterations. Reports the network's rate at this size and the HBM rate of the Krylov phase
-    (stencil + Gram-Schmidt passes + Givens), whose basis (m + 1 vectors of 9.5 MB) no longer fits
-    in the caches."""
+def bench_large(hz, torch, net4, maxit=12000, m=50):
+    """Large single solve: 1024^2 interior + 32 PML (1088^2 nodes), FGMRES(50) to tol 1e-6 with the
+    5-level / 32-channel BF16 network trained at 128^2 + 16 PML and applied fully convolutionally,
+    FP32 Krylov vectors. Reports solves/s, the network's rate at this size, the HBM rate of the
+    Krylov phase (stencil + Gram-Schmidt passes + Givens; the basis of m + 1 vectors of 9.5 MB no
+    longer fits in the caches) and the checkpointed training step (loss and gradient) on 4 samples
+    at this size."""
+    from paper_2607_16906_amd.train import load_weights
     from synth import H_10PPW, c5_system
     s = c5_system(0)
     gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW)
     n = s.nt * s.nt
-    Hp = (s.nt + 7) // 8 * 8
+    net = hz.Net(5, BASE, IN_CH, load_weights(WEIGHTS_L5))
+    Hp = (s.nt + 15) // 16 * 16
     net.autotune(gp, "bf16")
-    layers = time_layers(net, Hp, Hp, reps=5)
+    layers = time_layers(net, Hp, Hp, reps=5, levels=5)
     net_ms = sum(r["ms"] for r in layers)
     net_flops = sum(r["flops"] for r in layers)
     dom = max(layers, key=lambda r: r["ms"])
     b = torch.from_numpy(s.b.ravel()).cuda()
     ws = torch.empty(hz.fgmres_workspace_bytes(gp, net, m, maxit, "c64", "bf16"), dtype=torch.uint8, device="cuda")
 
-    def solve(mode):
+    def solve(mode, cap):
         net.set_fused_upsampling(mode)
         hz.fgmres(gp, b, net=net, m=m, tol=1e-6, maxit=m, workspace=ws)   # warm-up (one cycle)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        x, info = hz.fgmres(gp, b, net=net, m=m, tol=1e-6, maxit=maxit, workspace=ws)
+        x, info = hz.fgmres(gp, b, net=net, m=m, tol=1e-6, maxit=cap, workspace=ws)
         torch.cuda.synchronize()
         return time.perf_counter() - t0, info
 
     # the phase split below subtracts the separately timed layers, so this solve runs them
-    # separately; the solve with the autotuned fused decoder form is timed beside it
-    dt, info = solve(0)
-    dt_f, info_f = solve(2)
+    # separately; a bounded solve with the autotuned fused decoder form is timed beside it
+    dt, info = solve(0, maxit)
+    dt_f, info_f = solve(2, 200)
     ms_it = dt / max(info.its, 1) * 1e3
     # algorithmic bytes of step j, the least the step needs: the matvec (20n), one read of the
     # basis for the projections and one for the update (16nj), w and the new vector (32n):
@@ -550,9 +566,26 @@ def bench_large(hz, torch, net, maxit=100, m=50):
     kbytes = sum(52 * n + 24 * n * (j + 1) for j in steps)
     abytes = sum(52 * n + 16 * n * j for j in steps)
     kry_s = max(dt - info.its * net_ms * 1e-3, 1e-9)
-    return {"workload": "single solve, 1024^2 interior + 32 PML (1088^2), FGMRES(50), BF16 4-level/32-ch U-Net, "
-                        f"FP32 Krylov, bounded to {maxit} iterations",
-            "nodes": n, "its": info.its, "true_relres": info.true_relres, "ms_per_it": round(ms_it, 3),
+    # checkpointed training step (loss + gradient, BF16, recompute) on 4 samples of this size
+    probs = [hz.Problem(c5_system(k).c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW) for k in range(4)]
+    from synth import box_smoothed_noise, rng_for
+    r = torch.from_numpy(np.stack([box_smoothed_noise(s.nt, rng_for(5, 3, k)).ravel() for k in range(4)])
+                         .astype(np.complex64)).cuda()
+    tws = torch.empty(hz.train_workspace_bytes(net, probs[0], 4, "bf16", recompute=True), dtype=torch.uint8,
+                      device="cuda")
+    hz.loss_backward(net, probs, r, prec="bf16", recompute=True, workspace=tws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        hz.loss_backward(net, probs, r, prec="bf16", recompute=True, workspace=tws)
+    torch.cuda.synchronize()
+    bwd_ms = (time.perf_counter() - t0) / 3 * 1e3
+    conv = info.status == 0 and info.true_relres <= 1e-6
+    return {"workload": "single solve, 1024^2 interior + 32 PML (1088^2), FGMRES(50) to tol 1e-6, BF16 5-level/32-ch "
+                        "U-Net trained at 128^2 + 16 PML, FP32 Krylov",
+            "nodes": n, "its": info.its, "converged": conv, "true_relres": info.true_relres,
+            "solves_per_s": round(1.0 / dt, 4) if conv else 0.0, "seconds": round(dt, 3),
+            "ms_per_it": round(ms_it, 3),
             "ms_per_it_fused_decoder": round(dt_f / max(info_f.its, 1) * 1e3, 3),
             "network_ms_per_apply": round(net_ms, 3), "network_tflops": round(net_flops / net_ms * 1e-9, 1),
             "network_mfma_frac": round(net_flops / net_ms * 1e-9 / PEAK_BF16_TFLOPS, 4),
@@ -562,7 +595,8 @@ def bench_large(hz, torch, net, maxit=100, m=50):
             "krylov_hbm_gbs": round(kbytes / kry_s / 1e9, 1),
             "krylov_hbm_frac": round(kbytes / kry_s / 1e9 / PEAK_HBM_GBS, 4),
             "krylov_algorithmic_hbm_gbs": round(abytes / kry_s / 1e9, 1),
-            "krylov_algorithmic_hbm_frac": round(abytes / kry_s / 1e9 / PEAK_HBM_GBS, 4)}
+            "krylov_algorithmic_hbm_frac": round(abytes / kry_s / 1e9 / PEAK_HBM_GBS, 4),
+            "training_step_4x1088_checkpointed_ms": round(bwd_ms, 2)}
 
 
 def cpu_baseline(system, theta, gpu_its, budget_s=20.0):
@@ -604,6 +638,8 @@ def main():
     ap.add_argument("--roofline-only", action="store_true", help="only the per-layer roofline timing")
     ap.add_argument("--roofline-layer", type=int, default=-1,
                     help="with --roofline-only: time this layer alone (for a profiler run of one kernel)")
+    ap.add_argument("--roofline-grid", choices=["single", "large"], default="single",
+                    help="with --roofline-only: the single-solve grid (296^2) or the large solve's (1088^2)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="with --roofline-only: also copy 512 MiB with a plain device copy (counter calibration)")
     ap.add_argument("--only", choices=["training", "training_loop", "train_then_solve", "batched", "large",
@@ -640,7 +676,11 @@ def main():
                    "paper8": bench_paper8}[args.only](hz, torch, net1)
         print(json.dumps({args.only: res}))
         return
-    s = c2_system(0)
+    if args.roofline_only and args.roofline_grid == "large":
+        from synth import c5_system
+        s = c5_system(0)
+    else:
+        s = c2_system(0)
     gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW)
     net = hz.Net(LEVELS, BASE, IN_CH, theta)
     Hp = Wp = (s.nt + 7) // 8 * 8

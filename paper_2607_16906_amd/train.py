@@ -165,3 +165,85 @@ def resident_set(c, b, nint: int, npml: int, h: float):
     probs = [hz.Problem(ci.astype(np.float32).ravel(), nint, nint, npml, h) for ci in c]
     r = torch.from_numpy(np.ascontiguousarray(b.reshape(len(b), -1)).astype(np.complex64)).to("cuda")
     return probs, r
+
+
+def save_weights(path, theta, *, levels, base, in_ch, dataset, nint, npml, epochs, best_epoch, best_val, steps,
+                 bf16=False):
+    """Write a parameter file: float32 theta (or, bf16=True, its BF16 rounding as 16-bit patterns,
+    half the size, for networks that only run with BF16 operands) and the training record."""
+    th = np.asarray(theta, np.float32)
+    rec = dict(levels=levels, base=base, in_ch=in_ch, dataset=dataset, nint=nint, npml=npml, epochs=epochs,
+               best_epoch=best_epoch, best_val=best_val, step=steps)
+    if bf16:
+        u = th.view(np.uint32).astype(np.uint64)
+        u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+        np.savez(path, theta_bf16=u, **rec)
+    else:
+        np.savez(path, theta=th, **rec)
+
+
+def load_weights(path):
+    """theta (float32) of a parameter file written by save_weights (or by the oracle's trainer)."""
+    w = np.load(path)
+    if "theta" in w:
+        return w["theta"].astype(np.float32)
+    return (w["theta_bf16"].astype(np.uint32) << 16).view(np.float32)
+
+
+def main():
+    """Train a 3x3 U-Net on one of the Table 4 data sets on the GPU and write its parameter file.
+
+    Usage: python -m paper_2607_16906_amd.train --out FILE [--dataset D0] [--levels 5] [--base 32]
+           [--nint 128] [--npml 16] [--count 4096] [--val 256] [--epochs 24] [--batch 32]
+           [--prec fp32] [--bf16-file]
+    """
+    import argparse
+    import time
+
+    import torch
+
+    from synth import (CFG_TABLE4, COMP_ORDER, COMP_WEIGHTS, H_10PPW, VAL_FIRST, he_uniform, rng_for,
+                       table4_set, training_set)
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--dataset", default="D0", choices=[f"D{k}" for k in range(6)] + ["mix"],
+                    help="a Table 4 data set, or 'mix': the D0-like mixture with smooth source classes "
+                         "(Gaussian blobs, box-smoothed noise) beside the paper's ones")
+    ap.add_argument("--levels", type=int, default=5)
+    ap.add_argument("--base", type=int, default=32)
+    ap.add_argument("--nint", type=int, default=128)
+    ap.add_argument("--npml", type=int, default=16)
+    ap.add_argument("--count", type=int, default=4096)
+    ap.add_argument("--val", type=int, default=256)
+    ap.add_argument("--epochs", type=int, default=24)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--bf16-file", action="store_true", help="store the BF16 rounding of the weights")
+    a = ap.parse_args()
+    torch.cuda.set_device(0)
+    nt = a.nint + 2 * a.npml
+    t0 = time.time()
+    if a.dataset == "mix":
+        c, b = training_set(a.count, nt, a.npml)
+        cv, bv = training_set(a.val, nt, a.npml, first=VAL_FIRST)
+    else:
+        c, b = table4_set(a.dataset, a.count, nt, a.npml)
+        cv, bv = table4_set(a.dataset, a.val, nt, a.npml, first=VAL_FIRST)
+    probs, r = resident_set(c, b, a.nint, a.npml, H_10PPW)
+    vprobs, vr = resident_set(cv, bv, a.nint, a.npml, H_10PPW)
+    print(f"data set {a.dataset}: {a.count} + {a.val} samples on {nt}^2 in {time.time() - t0:.1f} s", flush=True)
+    theta0 = he_uniform(hz.init_shapes(a.levels, a.base, 5), rng_for(CFG_TABLE4, COMP_WEIGHTS, a.levels))
+    net = hz.Net(a.levels, a.base, 5, theta0)
+    tr = Trainer(net, probs, r, vprobs, vr, batch=a.batch, prec=a.prec)
+    orders = [rng_for(CFG_TABLE4, COMP_ORDER, e).permutation(a.count) for e in range(a.epochs)]
+    res = tr.fit(theta0, orders, log=lambda msg: print(msg, flush=True))
+    steps = a.epochs * ((a.count + a.batch - 1) // a.batch)
+    print(f"best epoch {res.best_epoch} val {res.best_val:.4f}; {steps} steps, {res.step_ms:.2f} ms per step",
+          flush=True)
+    save_weights(a.out, res.theta_best.cpu().numpy(), levels=a.levels, base=a.base, in_ch=5, dataset=a.dataset,
+                 nint=a.nint, npml=a.npml, epochs=a.epochs, best_epoch=res.best_epoch, best_val=res.best_val,
+                 steps=steps, bf16=a.bf16_file)
+
+
+if __name__ == "__main__":
+    main()

@@ -226,3 +226,25 @@ def test_c5_fp32_krylov_cycle_full_size():
     assert np.all(d <= 1e-5), float(d.max())
     assert abs(info.true_relres - ref.true_relres) <= 1e-5 * ref.true_relres
     assert xr <= 1e-5
+
+
+WEIGHTS_L5 = os.path.join(os.path.dirname(__file__), "..", "paper_2607_16906_amd", "weights", "unet_l5_c32_in5.npz")
+
+
+@pytest.mark.skipif(not os.path.exists(WEIGHTS_L5), reason="5-level network weights missing")
+def test_c5_bf16_solve_to_tol():
+    # the large configuration as stated: 1088^2 nodes, the 5-level / 32-channel network trained at
+    # 128^2 + 16 PML and applied at full resolution in BF16, FP32 Krylov vectors, FGMRES(50) to
+    # 1e-6; the true residual of the returned x recomputed with the oracle's FP64 operator
+    from paper_2607_16906_amd import hz
+    from paper_2607_16906_amd.train import load_weights
+    from synth import c5_system
+    s = c5_system(0)
+    op, gp = make_pair(s.c, s.npml)
+    net = hz.Net(5, 32, 5, load_weights(WEIGHTS_L5))
+    x, info = hz.fgmres(gp, to_dev(s.b, torch.complex128), net=net, m=50, tol=1e-6, maxit=12000, krylov="c64",
+                        net_prec="bf16")
+    xs = to_np(x).reshape(op.ny, op.nx)
+    rr = np.linalg.norm(s.b.reshape(op.ny, op.nx) - ohz.op_apply(op, xs)) / np.linalg.norm(s.b)
+    print(f"1088^2, 5-level network: its {info.its}, true relres {rr:.3e} (reported {info.true_relres:.3e})")
+    assert info.status == 0 and rr <= 1e-6 and abs(rr - info.true_relres) <= 1e-9
