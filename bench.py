@@ -676,23 +676,31 @@ def main():
                    "paper8": bench_paper8}[args.only](hz, torch, net1)
         print(json.dumps({args.only: res}))
         return
+    levels = LEVELS
     if args.roofline_only and args.roofline_grid == "large":
+        # the large system with the 5-level network its solve uses
         from synth import c5_system
         s = c5_system(0)
+        from paper_2607_16906_amd.train import load_weights
+        levels = 5
+        net = hz.Net(5, BASE, IN_CH, load_weights(WEIGHTS_L5))
     else:
         s = c2_system(0)
+        net = hz.Net(LEVELS, BASE, IN_CH, theta)
     gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW)
-    net = hz.Net(LEVELS, BASE, IN_CH, theta)
-    Hp = Wp = (s.nt + 7) // 8 * 8
+    q = 1 << (levels - 1)
+    Hp = Wp = (s.nt + q - 1) // q * q
     net.autotune(gp, "bf16")
-    net.autotune(gp, "fp32")
+    if levels == LEVELS:
+        net.autotune(gp, "fp32")
 
     if args.roofline_only and args.roofline_variant:
         # pin the launch variant (the profiler runs must time the launch the solve uses)
         tn, rows = (int(t) for t in args.roofline_variant.split(","))
-        lay = [r for r in net_layers(LEVELS, BASE, IN_CH, Hp, Wp) if r[0] == args.roofline_layer][0]
+        lay = [r for r in net_layers(levels, BASE, IN_CH, Hp, Wp) if r[0] == args.roofline_layer][0]
         net.set_layer_variant(args.roofline_layer, lay[4], lay[5], tn, rows)
-    layers = time_layers(net, Hp, Wp, reps=50, only=args.roofline_layer if args.roofline_only else -1)
+    layers = time_layers(net, Hp, Wp, reps=50, only=args.roofline_layer if args.roofline_only else -1,
+                         levels=levels)
     dom = max(layers, key=lambda r: r["ms"])
     tn, rows = net.layer_variant(dom["layer"], dom["H"], dom["W"]) if dom["kind"] == 0 else (0, 0)
     variant = f"tn{tn} rows{rows}"

@@ -17,6 +17,7 @@ With --arch paper8 it trains Table 2's own layer set (oracle/unet8.py: --levels 
 
 Usage: python -m oracle.train_weights --out FILE [--steps N] [--batch B] [--levels L]
        [--base C] [--resume CKPT] [--ckpt CKPT] [--lr0 LR] [--restart STEP] [--arch unet3|paper8]
+       [--dataset mix|D0..D5]
 """
 from __future__ import annotations
 
@@ -29,17 +30,21 @@ import numpy as np
 
 from oracle import adam, unet, unet8
 from oracle import helmholtz as hz
-from synth import C_REF, H_10PPW, he_uniform, mixed_training_sample, rng_for
+from synth import C_REF, H_10PPW, he_uniform, mixed_training_sample, rng_for, table4_sample
 
 
-def sample_batch(step: int, batch: int, nint: int):
-    """One batch: a PML width drawn per batch, a (velocity, source) pair per sample."""
+def sample_batch(step: int, batch: int, nint: int, dataset: str = "mix"):
+    """One batch: a PML width drawn per batch, a (velocity, source) pair per sample, from the
+    D0-like mixture ("mix") or one of the data sets D0..D5 of Section 3.2 (Table 4)."""
     r = rng_for(42, 5, step)
     p = int(r.integers(12, 21))
     nt = nint + 2 * p
     problems, rs = [], []
     for s in range(batch):
-        c, b = mixed_training_sample(nt, p, rng_for(42, 6, step * batch + s))
+        if dataset == "mix":
+            c, b = mixed_training_sample(nt, p, rng_for(42, 6, step * batch + s))
+        else:
+            c, b = table4_sample(dataset, nt, p, rng_for(42, 10 + int(dataset[1]), step * batch + s))
         problems.append(hz.Problem(c, p, H_10PPW, 1.0, 2.0, C_REF))
         rs.append(b)
     return problems, np.stack(rs)
@@ -76,6 +81,8 @@ def main():
     ap.add_argument("--lr0", type=float, default=1e-3, help="peak learning rate of the cosine schedule")
     ap.add_argument("--restart", type=int, default=0, help="step at which the cosine schedule restarts")
     ap.add_argument("--arch", default="unet3", choices=["unet3", "paper8"])
+    ap.add_argument("--dataset", default="mix", choices=["mix"] + [f"D{k}" for k in range(6)],
+                    help="the D0-like mixture or a Table 4 data set")
     args = ap.parse_args()
 
     if args.arch == "paper8":
@@ -97,7 +104,7 @@ def main():
         print(f"resumed at step {start}", flush=True)
     t0 = time.time()
     for step in range(start, args.steps):
-        problems, rs = sample_batch(step, args.batch, args.nint)
+        problems, rs = sample_batch(step, args.batch, args.nint, args.dataset)
         loss, _, g = net.loss_and_grad(theta.astype(np.float32), specs, problems, rs, dtype=np.float32)
         theta, m, v = adam.adam_step(theta, g.astype(np.float64), m, v, step + 1,
                                      lr=lr_at(step, args.steps, args.lr0, restart=args.restart), clip=1.0)
