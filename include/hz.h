@@ -171,8 +171,9 @@ int no_precond_apply(const no_net* net, const hz_problem* p, no_prec prec, hz_dt
 int no_precond_apply_noalloc(const no_net* net, const hz_problem* p, no_prec prec, hz_dtype dtype,
                              const void* v_dev, void* z_dev, void* stream);
 
-/* Time every launch variant (output-channel tile, pixel-tile height) of every 3x3 layer at
- * this problem's padded size and precision, on the forward workspace ws_dev
+/* Time every launch variant (output-channel tile, pixel-tile height, input-channel chunks per
+ * LDS stage) of every 3x3 layer at this problem's padded size and precision, on the forward
+ * workspace ws_dev
  * (no_workspace_size bytes), and keep the fastest in the network handle; later forward passes
  * at that size use it. The variants accumulate every output in the same order, so the choice
  * never changes a result bit. fgmres_solve calls it on its first use of a size.
@@ -181,17 +182,27 @@ int no_autotune(const no_net* net, const hz_problem* p, no_prec prec, void* ws_d
                 void* stream);
 
 /* Launch variant used for 3x3 layer `layer` at (batch, H, W, prec): output-channel tile *tn
- * (16, 32 or 64; 0 = the built-in choice) and pixel-tile height *rows (8 or 16), as no_autotune
- * chose it or no_set_layer_variant pinned it. Errors: NULL pointer, not a 3x3 layer. */
+ * (16, 32 or 64; 0 = the built-in choice), pixel-tile height *rows (8 or 16), input-channel
+ * chunks per LDS stage *stages (1, 2 or 4: one global-load latency per stage) and pixel tiles per
+ * workgroup *tiles (1; or 2 and more for the weight-stationary form, which keeps the weights of
+ * its output channels in LDS across that many tiles; there *stages counts the tiles whose
+ * patch loads are in flight together, 2 to 4), as no_autotune chose it or no_set_layer_variant
+ * pinned it. Errors: NULL pointer, not a 3x3 layer. */
 int no_layer_variant(const no_net* net, int layer, no_prec prec, int batch, int H, int W, int32_t* tn,
-                     int32_t* rows);
+                     int32_t* rows, int32_t* stages, int32_t* tiles);
 
-/* Pin the launch variant of 3x3 layer `layer` at (batch, H, W, prec) to (tn, rows), as if
- * no_autotune had chosen it (a later no_autotune of that size keeps it). Every variant gives
- * the same result bits; this fixes the launch for profiling and measurement. Errors: not a 3x3
- * layer, tn not in {16, 32, 64} or not dividing the stored output channels, rows not 8 or 16.
+/* Pin the launch variant of 3x3 layer `layer` at (batch, H, W, prec) to (tn, rows, stages,
+ * tiles), as if no_autotune had chosen it (a later no_autotune of that size keeps it). Every
+ * variant gives the same result bits; this fixes the launch for profiling and measurement.
+ * Errors: not a 3x3 layer, tn not in {16, 32, 64} or not dividing the stored output channels,
+ * rows not 8 or 16, stages not 1, or 2 / 4 for BF16 where that many chunk buffers fit in the
+ * 160 KB of LDS of a workgroup (4 with tn 16, or tn 32 and 8 rows), tiles not 1, or 2..64 for
+ * BF16 where the layer's input is at most 4 whole chunks of 32 channels per part and the weights
+ * and patches of all chunks fit in the LDS (then stages 2 or 3, or 4 with at most 2 chunks; 2
+ * with 16 rows).
  * Thread-safe. */
-int no_set_layer_variant(const no_net* net, int layer, no_prec prec, int batch, int H, int W, int tn, int rows);
+int no_set_layer_variant(const no_net* net, int layer, no_prec prec, int batch, int H, int W, int tn, int rows,
+                         int stages, int tiles);
 
 /* Choose how no_precond_apply and fgmres_solve run a decoder level with BF16 activations
  * whose coarser tensor has at most 128 channels: the fused form computes the 2x2 stride-2
@@ -275,12 +286,28 @@ typedef struct {
                              fgmres_solve; same iterates in exact arithmetic */
 } hz_opts;
 
+/* Phases of a solve timed into hz_info.phase_ms (milliseconds; Section 4 reports the
+ * elapsed time of a solve, ET): */
+enum {
+    HZ_PHASE_SETUP = 0,   /* GPU time from the start of the solve to the first basis vector: the
+                             network's launch-variant trials on the first call at a grid size,
+                             ||b||, the FP64 residual b - A x0 and v_1 */
+    HZ_PHASE_CYCLES = 1,  /* GPU time of the restart cycles (network, matvec, Gram-Schmidt and
+                             Hessenberg steps, cycle end with the FP64 true residual) */
+    HZ_PHASE_BUILD = 2,   /* host time spent capturing and instantiating cycle graphs (zero when
+                             every cycle replays a kept graph) */
+    HZ_PHASE_TOTAL = 3,   /* host wall time of the whole call */
+    HZ_NPHASE = 4
+};
+
 typedef struct {
     int32_t status;       /* HZ_OK, HZ_NOT_CONVERGED, HZ_ERR_BREAKDOWN or HZ_ERR_NONFINITE */
     int32_t its;          /* preconditioner applications (Arnoldi steps) */
     int32_t cycles;       /* restart cycles started */
     double est_relres;    /* last Givens estimate |g_{j+1}| / ||b|| */
     double true_relres;   /* FP64 ||b - A x|| / ||b|| of the returned x */
+    double phase_ms[HZ_NPHASE];   /* phase times (HZ_PHASE_*); the batched solve writes the
+                                     batch's times into every record */
 } hz_info;
 
 /* Workspace bytes for fgmres_solve. */

@@ -602,8 +602,11 @@ static int solve_batched(int nsys, const hz_problem* const* probs, const no_net*
     int rc = HZ_OK;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    PhaseTimer pt;
     do {
-        if (hipEventRecord(ev, user) != hipSuccess || hipStreamWaitEvent(s, ev, 0) != hipSuccess) {
+        if ((rc = pt.create()) != HZ_OK) break;
+        if (hipEventRecord(ev, user) != hipSuccess || hipStreamWaitEvent(s, ev, 0) != hipSuccess ||
+            hipEventRecord(pt.ev[0], s) != hipSuccess) {
             rc = HZ_ERR_HIP;
             break;
         }
@@ -630,7 +633,11 @@ static int solve_batched(int nsys, const hz_problem* const* probs, const no_net*
                     return HZ_ERR_HIP;
             return hipStreamSynchronize(s) == hipSuccess ? HZ_OK : HZ_ERR_HIP;
         };
-        if ((rc = read_states()) != HZ_OK) break;
+        if (hipEventRecord(pt.ev[1], s) != hipSuccess) {
+            rc = HZ_ERR_HIP;
+            break;
+        }
+        if ((rc = read_states()) != HZ_OK || (rc = pt.add(HZ_PHASE_SETUP)) != HZ_OK) break;
         for (int i = 0; i < nsys; ++i)
             if (hs[i].bnorm == 0.0 && !(hs[i].flags & FL_NONFINITE))
                 if (hipMemsetAsync(B.S[i].d.x, 0, sizeof(double2) * B.S[i].n, s) != hipSuccess) rc = HZ_ERR_HIP;
@@ -655,6 +662,7 @@ static int solve_batched(int nsys, const hz_problem* const* probs, const no_net*
                 tables_dirty = true;
             }
             if (tables_dirty || steps != graph_steps || !exec) {
+                const auto t0 = std::chrono::steady_clock::now();
                 if (exec) (void)hipGraphExecDestroy(exec);
                 if (graph) (void)hipGraphDestroy(graph);
                 exec = nullptr;
@@ -673,12 +681,15 @@ static int solve_batched(int nsys, const hz_problem* const* probs, const no_net*
                 }
                 graph_steps = steps;
                 tables_dirty = false;
+                pt.ms[HZ_PHASE_BUILD] +=
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             }
-            if (hipGraphLaunch(exec, s) != hipSuccess) {
+            if (hipEventRecord(pt.ev[0], s) != hipSuccess || hipGraphLaunch(exec, s) != hipSuccess ||
+                hipEventRecord(pt.ev[1], s) != hipSuccess) {
                 rc = HZ_ERR_HIP;
                 break;
             }
-            if ((rc = read_states()) != HZ_OK) break;
+            if ((rc = read_states()) != HZ_OK || (rc = pt.add(HZ_PHASE_CYCLES)) != HZ_OK) break;
         }
         if (rc != HZ_OK) break;
         for (int i = 0; i < nsys; ++i) {
@@ -688,6 +699,7 @@ static int solve_batched(int nsys, const hz_problem* const* probs, const no_net*
             f.cycles = q.cycles;
             f.est_relres = q.est;
             f.true_relres = q.true_rel;
+            for (int k = 0; k < HZ_PHASE_TOTAL; ++k) f.phase_ms[k] = pt.ms[k];
             if (q.flags & FL_NONFINITE) f.status = HZ_ERR_NONFINITE;
             else if (q.flags & FL_CONVERGED) f.status = HZ_OK;
             else if (q.flags & FL_BREAKDOWN) f.status = HZ_ERR_BREAKDOWN;
@@ -744,20 +756,28 @@ extern "C" int fgmres_solve_batched(int nsys, const hz_problem* const* probs, co
                                     const void* const* b, void* const* x, void* ws, size_t ws_bytes, hz_info* info,
                                     void* stream) {
     clear_error();
+    const auto t_call = std::chrono::steady_clock::now();
     HZ_TRY(check_batch(nsys, probs, net, o));
     HZ_CHECK_ARG(b && x && ws && info, "fgmres_solve_batched: NULL argument");
     for (int s = 0; s < nsys; ++s) HZ_CHECK_ARG(b[s] && x[s], "fgmres_solve_batched: NULL vector");
+    for (int s = 0; s < nsys; ++s) std::memset(info[s].phase_ms, 0, sizeof info[s].phase_ms);
     hipStream_t st = (hipStream_t)stream;
     const bool c128 = o->krylov == HZ_C128;
+    int rc;
     switch (net ? o->net_prec : NO_FP32) {
         case NO_BF16:
-            return c128 ? solve_batched<PolBF16, double2>(nsys, probs, net, o, b, x, ws, ws_bytes, info, st)
-                        : solve_batched<PolBF16, float2>(nsys, probs, net, o, b, x, ws, ws_bytes, info, st);
+            rc = c128 ? solve_batched<PolBF16, double2>(nsys, probs, net, o, b, x, ws, ws_bytes, info, st)
+                      : solve_batched<PolBF16, float2>(nsys, probs, net, o, b, x, ws, ws_bytes, info, st);
+            break;
         case NO_FP32:
-            return c128 ? solve_batched<PolF32, double2>(nsys, probs, net, o, b, x, ws, ws_bytes, info, st)
-                        : solve_batched<PolF32, float2>(nsys, probs, net, o, b, x, ws, ws_bytes, info, st);
+            rc = c128 ? solve_batched<PolF32, double2>(nsys, probs, net, o, b, x, ws, ws_bytes, info, st)
+                      : solve_batched<PolF32, float2>(nsys, probs, net, o, b, x, ws, ws_bytes, info, st);
+            break;
         default:
-            return c128 ? solve_batched<PolF64, double2>(nsys, probs, net, o, b, x, ws, ws_bytes, info, st)
-                        : solve_batched<PolF64, float2>(nsys, probs, net, o, b, x, ws, ws_bytes, info, st);
+            rc = c128 ? solve_batched<PolF64, double2>(nsys, probs, net, o, b, x, ws, ws_bytes, info, st)
+                      : solve_batched<PolF64, float2>(nsys, probs, net, o, b, x, ws, ws_bytes, info, st);
     }
+    const double total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_call).count();
+    for (int s = 0; s < nsys; ++s) info[s].phase_ms[HZ_PHASE_TOTAL] = total;
+    return rc;
 }

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <chrono>
 #include <string>
 
 #include "hz.h"
@@ -121,5 +122,26 @@ __device__ inline float wave_sum(float v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+
+// GPU time between two events on the solve's stream, summed per phase.
+struct PhaseTimer {
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    double ms[HZ_NPHASE] = {0, 0, 0, 0};
+    int create() {
+        for (auto& e : ev) HZ_HIP(hipEventCreate(&e));
+        return HZ_OK;
+    }
+    // after a synchronisation of the stream: adds the time from ev[0] to ev[1]
+    int add(int phase) {
+        float t = 0.f;
+        HZ_HIP(hipEventElapsedTime(&t, ev[0], ev[1]));
+        ms[phase] += t;
+        return HZ_OK;
+    }
+    ~PhaseTimer() {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
 
 }  // namespace hz

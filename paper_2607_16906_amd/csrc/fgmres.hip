@@ -16,6 +16,7 @@
 // coefficients are seen; it is dropped when its problem or network is destroyed.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -292,6 +293,9 @@ static int solve_on(const hz_problem* p, const no_net* net, const hz_opts* o, co
     Split sp = krylov_split(n);
     const int nres = stencil_blocks(p);
 
+    PhaseTimer pt;
+    HZ_TRY(pt.create());
+    HZ_HIP(hipEventRecord(pt.ev[0], s));
     // pick the fastest launch variant of every network layer at this size (first call only)
     if (net) HZ_TRY(net_autotune(net, p, o->net_prec, L.net_ws, L.net_ws_bytes, s));
     // ||b||, then the first true residual and v_1
@@ -301,9 +305,11 @@ static int solve_on(const hz_problem* p, const no_net* net, const hz_opts* o, co
     HZ_TRY(launch_cycle_start(kb, L.rpart, nres, s));
     HZ_TRY(launch_cast_scale(c128, L.r64, L.V, n, kb.st, s));
 
+    HZ_HIP(hipEventRecord(pt.ev[1], s));
     SolveState hs{};
     HZ_HIP(hipMemcpyAsync(&hs, kb.st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
     HZ_HIP(hipStreamSynchronize(s));
+    HZ_TRY(pt.add(HZ_PHASE_SETUP));
     if (hs.bnorm == 0.0 && !(hs.flags & FL_NONFINITE)) HZ_HIP(hipMemsetAsync(x, 0, sizeof(double2) * n, s));
     int graph_steps = -1;
     while (!(hs.flags & (FL_CONVERGED | FL_NONFINITE | FL_BREAKDOWN)) && hs.its < o->maxit) {
@@ -330,6 +336,7 @@ static int solve_on(const hz_problem* p, const no_net* net, const hz_opts* o, co
             k.ws = L.kb.st;   // the workspace base (the layout's first buffer)
             k.ws_len = L.total;
             if (!graph_acquire(k, gu)) {
+                const auto t0 = std::chrono::steady_clock::now();
                 HZ_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
                 const int crc = o->ortho == 1 ? cycle_launches_lag(p, net, o, L, kb, b, x, steps, s)
                                               : cycle_launches(p, net, o, L, kb, b, x, steps, s);
@@ -338,13 +345,19 @@ static int solve_on(const hz_problem* p, const no_net* net, const hz_opts* o, co
                 HZ_HIP(e);
                 HZ_HIP(hipGraphInstantiate(&gu.e, gu.g, nullptr, nullptr, 0));
                 graph_keep(k, gu);
+                pt.ms[HZ_PHASE_BUILD] +=
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             }
             graph_steps = steps;
         }
+        HZ_HIP(hipEventRecord(pt.ev[0], s));
         HZ_HIP(hipGraphLaunch(gu.e, s));
+        HZ_HIP(hipEventRecord(pt.ev[1], s));
         HZ_HIP(hipMemcpyAsync(&hs, kb.st, sizeof(SolveState), hipMemcpyDeviceToHost, s));
         HZ_HIP(hipStreamSynchronize(s));
+        HZ_TRY(pt.add(HZ_PHASE_CYCLES));
     }
+    for (int i = 0; i < HZ_PHASE_TOTAL; ++i) info->phase_ms[i] = pt.ms[i];
     if (o->hist_host && o->hist_len > 0) {
         const int cnt = std::min(std::min(hs.its, o->hist_len), kb.hist_cap);
         if (cnt > 0) {
@@ -385,7 +398,9 @@ extern "C" size_t fgmres_workspace_size(const hz_problem* p, const no_net* net, 
 extern "C" int fgmres_solve(const hz_problem* p, const no_net* net, const hz_opts* o, const void* b_dev,
                             void* x_dev, void* ws, size_t ws_bytes, hz_info* info, void* stream) {
     clear_error();
+    const auto t_call = std::chrono::steady_clock::now();
     HZ_CHECK_ARG(p && b_dev && x_dev && ws && info, "fgmres_solve: NULL argument");
+    std::memset(info->phase_ms, 0, sizeof info->phase_ms);
     HZ_TRY(check_opts(o, net, p));
     FgmresLayout L = fgmres_layout(p, net, o, ws, ws_bytes);
     if (L.total > ws_bytes) {
@@ -412,6 +427,8 @@ extern "C" int fgmres_solve(const hz_problem* p, const no_net* net, const hz_opt
     }
     (void)hipEventDestroy(ev);
     (void)hipStreamDestroy(s);
+    info->phase_ms[HZ_PHASE_TOTAL] =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_call).count();
     return rc;
 }
 

@@ -223,7 +223,9 @@ __global__ __launch_bounds__(NW * 64) void k_upd1_split(const float2* __restrict
 #pragma unroll
     for (int q = 0; q < GMAX; ++q) ar[q] = ai[q] = 0.0;
     const int64_t len = p1 - p0;
-    const int64_t nunit = (len + 1) >> 1;   // pairs, the last one a single point when len is odd
+    // pairs, the last one a single point when len is odd (an odd-length vector in a basis of even
+    // stride; the solver's bases have stride n, and an odd n takes k_update instead)
+    const int64_t nunit = (len + 1) >> 1;
     int buf = 0;
     for (int64_t k0 = 0; k0 < nunit; k0 += 64, buf ^= 1) {
         const int64_t k = k0 + ln;

@@ -113,3 +113,9 @@ def test_batched_bitwise_reproducible():
     xb, ib = hz.fgmres_batched(ps, bs, net=net, m=20, tol=1e-6, maxit=300, krylov="c64", net_prec="bf16")
     for a, b, i, j in zip(xa, xb, ia, ib):
         assert i.its == j.its and torch.equal(a, b)
+    # the batch's phase times are written into every record, the GPU phases inside the wall time
+    ph = ia[0].phase_ms
+    print(f"batch phases {ph}")
+    assert all(i.phase_ms == ph for i in ia)
+    assert ph["setup"] > 0 and ph["cycles"] > 0 and ph["build"] > 0
+    assert ph["setup"] + ph["cycles"] + ph["build"] <= ph["total"] + 1e-3

@@ -204,8 +204,9 @@ def test_solves_independent_of_autotuning():
 
 def test_c5_fp32_krylov_cycle_full_size():
     # the large single solve's Krylov configuration at its full size (1088^2 nodes, FP32 basis,
-    # restart length 50): one cycle runs the stencil with the first sums and the second pass with
-    # the basis split over 4 wavefronts (up to 24 / 32 vectors) and over 8 (33 to 50 vectors).
+    # restart length 50): one cycle runs the stencil with the first sums and all three forms of the
+    # second pass: the basis split over 4 wavefronts (up to 24 vectors), k_update's register form
+    # (25 to 32 vectors) and the basis split over 8 wavefronts (33 to 50 vectors).
     # Against the FP64 oracle's GMRES cycle on the same system: the residual estimate after every
     # step within 1e-5 relative, and the cycle's true residual and x within 1e-5 (the FP32 bound
     # for a matvec; FP32 vectors with FP64 sums and least squares stay near 1e-6).
