@@ -31,7 +31,7 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 
 
-WEIGHTS8 = os.path.join(ROOT, "paper_2607_16906_amd", "weights", "paper8_d4_c32_in5.npz")
+WEIGHTS8 = os.path.join(ROOT, "paper_2607_16906_amd", "weights", "paper8_d4_c32_in5_D0.npz")
 WEIGHTS_L5 = os.path.join(ROOT, "paper_2607_16906_amd", "weights", "unet_l5_c32_in5.npz")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "conv3_dominant_layer_296_bf16_traffic.txt")
 GOLDEN_C2 = os.path.join(ROOT, "tests", "golden", "c2_oracle.json")
@@ -258,32 +258,25 @@ def paper8_flops(depth, ch, in_ch, Hp, Wp):
 def bench_paper8(hz, torch, net3, reps=50):
     """The paper's own layer set (Table 2: depth 4, 32 channels, 8x8 stride-2, PReLU) as the
     preconditioner on the single-solve system (296^2): one application in BF16 and FP32 against the
-    3x3 network's, and FGMRES with it (m = 30, tol 1e-6) with the weights the oracle trained for it
-    (seeded He-uniform weights with slopes 0.25 when that file is absent)."""
-    from synth import H_10PPW, c2_system, he_uniform, rng_for
+    3x3 network's, and FGMRES with it (m = 30, tol 1e-6) with the weights the library's epoch loop
+    trained for it on data set D0 (Table 4) at 128^2 + 16 PML (seeded He-uniform weights with
+    slopes 0.25 when that file is absent)."""
+    from paper_2607_16906_amd.train import init_theta_paper8
+    from synth import H_10PPW, c2_system, rng_for
     trained = os.path.exists(WEIGHTS8)
     if trained:
         w8 = np.load(WEIGHTS8)
         theta8 = w8["theta"].astype(np.float32)
     else:
-        rng = rng_for(21, 2, 0)
-        parts = []
-        for i, shp in enumerate(hz.init_shapes_paper8(4, 32, 5)):
-            parts.append(he_uniform([shp], rng))
-            if i < 8:
-                parts.append(np.array([0.25], np.float32))
-        theta8 = np.concatenate(parts).astype(np.float32)
+        theta8 = init_theta_paper8(4, 32, 5, rng_for(21, 2, 0))
     net8 = hz.Net(4, 32, 5, theta8, kind="paper8")
-    if args.roofline_only and args.roofline_grid == "large":
-        from synth import c5_system
-        s = c5_system(0)
-    else:
-        s = c2_system(0)
+    s = c2_system(0)
     gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW)
     v = torch.from_numpy(s.b.ravel().astype(np.complex64)).cuda()
     Hp = (s.nt + 15) // 16 * 16
     out = {"workload": "one application on 296^2 (padded to 304^2); FGMRES(30) to 1e-6 on the single-solve system",
-           "weights": f"oracle-trained, {int(w8['step'])} steps" if trained else "seeded (untrained)",
+           "weights": (f"trained on the GPU on D0, {int(w8['epochs'])} epochs of {int(w8['step'])} steps, "
+                       f"validation loss {float(w8['best_val']):.4f}") if trained else "seeded (untrained)",
            "params": net8.nparam, "gflop_per_apply": round(paper8_flops(4, 32, 5, Hp, Hp) * 1e-9, 3)}
     for tag, net in (("paper8", net8), ("unet3", net3)):
         for prec in ("bf16", "fp32"):
@@ -302,18 +295,20 @@ def bench_paper8(hz, torch, net3, reps=50):
                 out[f"{tag}_{prec}_tflops"] = round(paper8_flops(4, 32, 5, Hp, Hp) / (ms * 1e-3) * 1e-12, 1)
     b = torch.from_numpy(s.b.ravel()).cuda()
     maxit = 3000 if trained else 60
-    hz.fgmres(gp, b, net=net8, m=30, tol=1e-6, maxit=30)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, info = hz.fgmres(gp, b, net=net8, m=30, tol=1e-6, maxit=maxit)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    out["fgmres_ms_per_it"] = round(dt * 1e3 / max(info.its, 1), 3)
-    out["fgmres_its"] = info.its
-    out["fgmres_converged"] = info.status == 0
-    out["fgmres_true_relres"] = float(f"{info.true_relres:.3e}")
-    if info.status == 0:
-        out["solves_per_s"] = round(1.0 / dt, 3)
+    for prec in ("bf16", "fp32"):
+        sfx = "" if prec == "bf16" else "_fp32_net"
+        hz.fgmres(gp, b, net=net8, m=30, tol=1e-6, maxit=30, net_prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = hz.fgmres(gp, b, net=net8, m=30, tol=1e-6, maxit=maxit, net_prec=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out["fgmres_ms_per_it" + sfx] = round(dt * 1e3 / max(info.its, 1), 3)
+        out["fgmres_its" + sfx] = info.its
+        out["fgmres_converged" + sfx] = info.status == 0
+        out["fgmres_true_relres" + sfx] = float(f"{info.true_relres:.3e}")
+        if info.status == 0:
+            out["solves_per_s" + sfx] = round(1.0 / dt, 3)
     # at the training size (64^2 interior + 16 PML): iterations of both networks and of GMRES on
     # five seeded systems of the single-solve kind
     small = {"paper8": [], "unet3": [], "gmres": []}
@@ -325,7 +320,17 @@ def bench_paper8(hz, torch, net3, reps=50):
             _, inf = hz.fgmres(gs, bs, net=nn, m=30, tol=1e-6, maxit=1000)
             small[tag].append(inf.its if inf.status == 0 else -inf.its)
     out["its_64_interior"] = small
-    out["its_64_interior_note"] = "FGMRES(30) to 1e-6, BF16 networks, 5 systems; negative: not converged"
+    # at the paper network's training size (128^2 interior + 16 PML)
+    mid = {"paper8": [], "unet3": []}
+    for sid in range(2):
+        ss = c2_system(sid, nx=128, npml=16)
+        gs = hz.Problem(ss.c.astype(np.float32).ravel(), ss.nx, ss.nx, ss.npml, H_10PPW)
+        bs = torch.from_numpy(ss.b.ravel()).cuda()
+        for tag, nn in (("paper8", net8), ("unet3", net3)):
+            _, inf = hz.fgmres(gs, bs, net=nn, m=30, tol=1e-6, maxit=2000)
+            mid[tag].append(inf.its if inf.status == 0 else -inf.its)
+    out["its_128_interior"] = mid
+    out["its_64_interior_note"] = "FGMRES(30) to 1e-6, BF16 networks; negative: not converged"
     return out
 
 
@@ -354,11 +359,7 @@ def bench_train_then_solve(hz, torch, S=4096, V=256, batch=32, epochs=30, nint=6
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     net.set_weights(res.theta_best)
-    if args.roofline_only and args.roofline_grid == "large":
-        from synth import c5_system
-        s = c5_system(0)
-    else:
-        s = c2_system(0)
+    s = c2_system(0)
     gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW)
     bb = torch.from_numpy(s.b.ravel()).cuda()
     hz.fgmres(gp, bb, net=net, m=M_RESTART, tol=TOL, maxit=M_RESTART)
@@ -497,11 +498,7 @@ def bench_restart(hz, torch, net, runs=RESTART_RUNS):
     (one-reduction) form, with FP32 or FP64 Krylov vectors. The one-reduction form is not run with
     FP32 vectors at m = 512: it loses orthogonality there and stalls near 4e-4."""
     from synth import H_10PPW, c2_system
-    if args.roofline_only and args.roofline_grid == "large":
-        from synth import c5_system
-        s = c5_system(0)
-    else:
-        s = c2_system(0)
+    s = c2_system(0)
     gp = hz.Problem(s.c.astype(np.float32).ravel(), s.nx, s.nx, s.npml, H_10PPW)
     b = torch.from_numpy(s.b.ravel()).cuda()
     rows = []
@@ -634,7 +631,8 @@ def main():
     ap.add_argument("--fp32-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the training and batched sections")
-    ap.add_argument("--roofline-variant", default="", help="with --roofline-only: pin the layer's launch variant 'tn,rows'")
+    ap.add_argument("--roofline-variant", default="",
+                    help="with --roofline-only: pin the layer's launch variant 'tn,rows[,stages[,tiles]]'")
     ap.add_argument("--roofline-only", action="store_true", help="only the per-layer roofline timing")
     ap.add_argument("--roofline-layer", type=int, default=-1,
                     help="with --roofline-only: time this layer alone (for a profiler run of one kernel)")
@@ -696,14 +694,15 @@ def main():
 
     if args.roofline_only and args.roofline_variant:
         # pin the launch variant (the profiler runs must time the launch the solve uses)
-        tn, rows = (int(t) for t in args.roofline_variant.split(","))
+        vv = [int(t) for t in args.roofline_variant.split(",")]
+        tn, rows, stages, tiles = vv[0], vv[1], (vv[2] if len(vv) > 2 else 1), (vv[3] if len(vv) > 3 else 1)
         lay = [r for r in net_layers(levels, BASE, IN_CH, Hp, Wp) if r[0] == args.roofline_layer][0]
-        net.set_layer_variant(args.roofline_layer, lay[4], lay[5], tn, rows)
+        net.set_layer_variant(args.roofline_layer, lay[4], lay[5], tn, rows, stages, tiles)
     layers = time_layers(net, Hp, Wp, reps=50, only=args.roofline_layer if args.roofline_only else -1,
                          levels=levels)
     dom = max(layers, key=lambda r: r["ms"])
-    tn, rows = net.layer_variant(dom["layer"], dom["H"], dom["W"]) if dom["kind"] == 0 else (0, 0)
-    variant = f"tn{tn} rows{rows}"
+    tn, rows, stages, tiles = net.layer_variant(dom["layer"], dom["H"], dom["W"]) if dom["kind"] == 0 else (0, 0, 1, 1)
+    variant = f"tn{tn} rows{rows}" + (f" stages{stages}" if stages > 1 else "") + (f" tiles{tiles}" if tiles > 1 else "")
     achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
     net_ms = sum(r["ms"] for r in layers)
     net_flops = sum(r["flops"] for r in layers)
@@ -775,6 +774,7 @@ def main():
                    "weights_step": int(w["step"])},
         "solve": {"its": its, "cycles": infos[-1].cycles, "true_relres": infos[-1].true_relres,
                   "converged": ok, "us_per_it": round(ms_step * 1e3 / max(its, 1), 1),
+                  "phase_ms": {k: round(v, 3) for k, v in infos[-1].phase_ms.items()},
                   "vs_oracle": oracle_comparison(its, infos[-1].true_relres, "bf16_weights")},
         "fp32_form": {"value": round(1e3 / ms32, 4) if i32.status == 0 else 0.0, "unit": "solves/s",
                       "ms_per_solve": round(ms32, 3), "its": i32.its, "true_relres": i32.true_relres,

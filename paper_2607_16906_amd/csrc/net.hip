@@ -352,35 +352,53 @@ static int autotune_impl(const no_net* net, int Hp, int Wp, int batch, const Fwd
         ConvCfg best;
         float best_ms = 1e30f;
         const int chunks = (c0 + c1) / std::max(1, std::min(P::CK, c1 > 0 ? std::min(c0, c1) : c0 + c1));
+        // candidates: (channel tile, rows per wavefront) with 1 / 2 / 4 chunks per LDS stage, and the
+        // weight-stationary form with 2 ... 16 tiles per block where it applies
+        std::vector<ConvCfg> cands;
         for (int tn : {16, 32, 64}) {
             if (ly.cout_p % tn) continue;
             for (int rpw : {2, 4}) {
-                for (int ks : {1}) {
-                    if (ks > 1 && (ks > chunks || (size_t)ks * H * W * ly.cout_p > b.split_elems)) continue;
-                    ConvCfg cfg{tn, rpw, ks};
-                    auto run = [&]() {
-                        if (up)
-                            return launch_conv3_up<P>(x0, c0, *up, c1, packed_w<P>(net, ly), packed_b<P>(net, ly),
-                                                      y, ly.cout_p, H, W, batch, nullptr, s, cfg);
-                        return launch_conv3<P>(x0, c0, x1, c1, packed_w<P>(net, ly), packed_b<P>(net, ly), y,
-                                               ly.cout_p, pool, H, W, batch, true, nullptr, s, Conv3Out(), cfg,
-                                               (Acc*)b.splitbuf);
-                    };
-                    HZ_TRY(run());
-                    HZ_TRY(hold());
-                    HZ_HIP(hipEventRecord(e0, s));
-                    for (int r = 0; r < 10; ++r) HZ_TRY(run());
-                    HZ_HIP(hipEventRecord(e1, s));
-                    HZ_HIP(hipEventSynchronize(e1));
-                    float ms = 0;
-                    HZ_HIP(hipEventElapsedTime(&ms, e0, e1));
-                    // a later candidate replaces the current best only when clearly faster (3 %),
-                    // so that timing noise does not flip the choice between near-equal variants
-                    if (ms < 0.97f * best_ms) {
-                        best_ms = ms;
-                        best = cfg;
-                    }
+                for (int ns : {1, 2, 4}) {
+                    // chunks per LDS stage: only where there are that many chunks (the plain form)
+                    if (ns > 1 && (up || ns > chunks || !conv3_stages_ok<P>(tn, rpw, ns))) continue;
+                    ConvCfg cfg{tn, rpw, 1};
+                    cfg.ns = ns;
+                    cands.push_back(cfg);
                 }
+                if (!up && conv3_ws_ok<P>(tn, rpw, c0, c1, ly.cout_p))
+                    for (const auto& tp : {std::array<int, 2>{4, 2}, {8, 3}, {16, 3}, {16, 4}, {32, 4}}) {
+                        // (tiles per block, tiles of loads in flight; 4 only with at most 2 chunks;
+                        // 16-row tiles with 2)
+                        if ((tp[1] == 4 && c0 + c1 > 2 * P::CK) || (rpw == 4 && tp[1] > 2)) continue;
+                        ConvCfg cfg{tn, rpw, 1};
+                        cfg.tpb = tp[0];
+                        cfg.ns = tp[1];
+                        cands.push_back(cfg);
+                    }
+            }
+        }
+        for (const ConvCfg& cfg : cands) {
+            auto run = [&]() {
+                if (up)
+                    return launch_conv3_up<P>(x0, c0, *up, c1, packed_w<P>(net, ly), packed_b<P>(net, ly),
+                                              y, ly.cout_p, H, W, batch, nullptr, s, cfg);
+                return launch_conv3<P>(x0, c0, x1, c1, packed_w<P>(net, ly), packed_b<P>(net, ly), y,
+                                       ly.cout_p, pool, H, W, batch, true, nullptr, s, Conv3Out(), cfg,
+                                       (Acc*)b.splitbuf);
+            };
+            HZ_TRY(run());
+            HZ_TRY(hold());
+            HZ_HIP(hipEventRecord(e0, s));
+            for (int r = 0; r < 10; ++r) HZ_TRY(run());
+            HZ_HIP(hipEventRecord(e1, s));
+            HZ_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            HZ_HIP(hipEventElapsedTime(&ms, e0, e1));
+            // a later candidate replaces the current best only when clearly faster (3 %),
+            // so that timing noise does not flip the choice between near-equal variants
+            if (ms < 0.97f * best_ms) {
+                best_ms = ms;
+                best = cfg;
             }
         }
         if (best_out) *best_out = best_ms / 10;
@@ -734,19 +752,21 @@ extern "C" int no_layer_forward(const no_net* net, int layer, no_prec prec, int 
 }
 
 extern "C" int no_layer_variant(const no_net* net, int layer, no_prec prec, int batch, int H, int W, int32_t* tn,
-                                int32_t* rows) {
+                                int32_t* rows, int32_t* stages, int32_t* tiles) {
     clear_error();
-    HZ_CHECK_ARG(net && tn && rows, "no_layer_variant: NULL argument");
+    HZ_CHECK_ARG(net && tn && rows && stages && tiles, "no_layer_variant: NULL argument");
     HZ_CHECK_ARG(layer >= 0 && layer < (int)net->layers.size() && net->layers[layer].kind == L_CONV3,
                  "no_layer_variant: not a 3x3 layer");
     const ConvCfg c = net_cfg(net, layer, H, W, batch, prec);
     *tn = c.tn;
     *rows = 4 * (c.rpw == 4 ? 4 : 2);
+    *stages = c.ns;
+    *tiles = c.tpb > 1 ? c.tpb : 1;
     return HZ_OK;
 }
 
 extern "C" int no_set_layer_variant(const no_net* net, int layer, no_prec prec, int batch, int H, int W, int tn,
-                                    int rows) {
+                                    int rows, int stages, int tiles) {
     clear_error();
     HZ_CHECK_ARG(net, "no_set_layer_variant: NULL network");
     HZ_CHECK_ARG(layer >= 0 && layer < (int)net->layers.size() && net->layers[layer].kind == L_CONV3,
@@ -754,10 +774,27 @@ extern "C" int no_set_layer_variant(const no_net* net, int layer, no_prec prec, 
     HZ_CHECK_ARG(prec == NO_BF16 || prec == NO_FP32 || prec == NO_FP64, "no_set_layer_variant: bad precision");
     HZ_CHECK_ARG((tn == 16 || tn == 32 || tn == 64) && net->layers[layer].cout_p % tn == 0 && (rows == 8 || rows == 16),
                  "no_set_layer_variant: tn must be 16, 32 or 64 and divide the output channels, rows 8 or 16");
+    const int rpw = rows / 4;
+    const Layer& ly = net->layers[layer];
+    const int c0 = ly.cat_cp > 0 ? ly.cat_cp : ly.cin_p, c1 = ly.cat_cp > 0 ? ly.cin_p - ly.cat_cp : 0;
+    if (tiles > 1) {
+        HZ_CHECK_ARG(tiles <= 64 && prec == NO_BF16 && conv3_ws_ok<PolBF16>(tn, rpw, c0, c1, ly.cout_p) &&
+                         stages >= 2 && stages <= (rpw == 4 ? 2 : c0 + c1 <= 2 * PolBF16::CK ? 4 : 3),
+                     "no_set_layer_variant: tiles must be 1, or 2..64 for the weight-stationary BF16 form (at most "
+                     "4 input chunks, LDS within 160 KB) with 2 or 3 tiles of loads in flight (4 with at most 2 "
+                     "chunks)");
+    } else {
+        const bool st_ok = prec == NO_BF16 ? conv3_stages_ok<PolBF16>(tn, rpw, stages) : stages == 1;
+        HZ_CHECK_ARG(st_ok && tiles == 1,
+                     "no_set_layer_variant: stages must be 1, or 2 / 4 in BF16 where the stages fit in the LDS");
+    }
     HZ_CHECK_ARG(batch >= 1 && H >= 1 && W >= 1, "no_set_layer_variant: bad size");
     no_net* mnet = const_cast<no_net*>(net);
     std::lock_guard<std::mutex> g(mnet->tune_mu);
-    mnet->tuned[{layer, H, W, batch, (int)prec}] = ConvCfg{tn, rows / 4, 1};
+    ConvCfg c{tn, rpw, 1};
+    c.ns = stages;
+    c.tpb = tiles > 1 ? tiles : 0;
+    mnet->tuned[{layer, H, W, batch, (int)prec}] = c;
     mnet->tune_gen.fetch_add(1);
     return HZ_OK;
 }

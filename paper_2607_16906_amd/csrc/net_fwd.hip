@@ -22,11 +22,55 @@ __device__ __forceinline__ int xcd_linear(int p, int n) {
 template <class P>
 constexpr int pix_stride() { return P::CK + 16 / (int)sizeof(typename P::T); }   // +16 B against bank conflicts
 
+// The matrix-core work of one full input-channel chunk (P::CK channels) staged in LDS: patch
+// pst ((4 RPW + 2) x 18 pixels, pixel stride pix_stride) and weights wst (9 taps x TN rows, same
+// stride), accumulated into acc[pixel row][channel block] of the wavefront's RPW rows. Step st
+// covers tap st / SPT and k-groups 4 (st mod SPT) + lg of it; all offsets are compile-time after
+// unrolling (the reads of the next steps can be issued while the matrix cores work). The
+// wavefront's RPW + 2 patch rows at the 3 column offsets are read from LDS once and shared by the
+// 3 row offsets dy of the window; the accumulation order is tap by tap, k-groups within a tap.
+template <class P, int TN, int RPW>
+__device__ __forceinline__ void conv3_chunk_mma(typename P::AccV (&acc)[RPW][TN / 16], const typename P::T* pst,
+                                                const typename P::T* wst, int wv, int lr, int lg) {
+    using T = typename P::T;
+    using Frag = typename P::Frag;
+    constexpr int PS = pix_stride<P>();
+    constexpr int NCB = TN / 16;
+    constexpr int SPT = P::CK / P::GW / 4;
+    const T* pbase = pst + ((RPW * wv) * (TW + 2) + lr) * PS + lg * P::GW;
+    const T* wbase = wst + lr * PS + lg * P::GW;
+    Frag b[RPW + 2][3][SPT];
+#pragma unroll
+    for (int ir = 0; ir < RPW + 2; ++ir)
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+            for (int sg = 0; sg < SPT; ++sg)
+                b[ir][dx][sg] = P::load(pbase + (ir * (TW + 2) + dx) * PS + 4 * sg * P::GW);
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3, dx = tap % 3;
+#pragma unroll
+        for (int sg = 0; sg < SPT; ++sg) {
+            Frag a[NCB];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) a[cb] = P::load(wbase + (tap * TN + cb * 16) * PS + 4 * sg * P::GW);
+#pragma unroll
+            for (int pb = 0; pb < RPW; ++pb)
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) acc[pb][cb] = P::mma(a[cb], b[pb + dy][dx][sg], acc[pb][cb]);
+        }
+    }
+}
+
 // One block's tile: output channels [co0, co0 + TN) of the (4 RPW) x 16 pixel tile at (ty0, tx0)
 // of sample bz, over the input-channel chunks [kbeg, kend). Each wavefront owns RPW rows of the
-// tile. The next chunk's patch and weights are loaded into registers while the matrix cores work
-// on the current chunk (register double buffering). With splitp set, the raw accumulators are
-// written to splitp[[bz][pixel][channel]] (no bias or activation) for a later split-K reduction.
+// tile. NS chunks form one stage: their patches and weights sit in NS LDS buffers, and the next
+// stage's NS chunks are loaded into registers while the matrix cores work on the current stage
+// (register double buffering), so that one global-load latency is paid per NS chunks. The chunks
+// of a stage are computed one after the other in the order of NS = 1, so every NS gives the same
+// result bits. With splitp set, the raw accumulators are written to splitp[[bz][pixel][channel]]
+// (no bias or activation) for a later split-K reduction.
 //
 // UPCD > 0 (fused upsampling, see UpIn): the channels from c0 on are U, computed per chunk from the
 // coarse patch d[ty0/2 - 1 .. ty0/2 + 2 RPW][tx0/2 - 1 .. tx0/2 + 8] (staged once in LDS, all
@@ -34,7 +78,7 @@ constexpr int pix_stride() { return P::CK + 16 / (int)sizeof(typename P::T); }  
 // every coarse pixel of the patch, with the same MFMA steps (input channels in groups of 4 GW, in
 // order) as the stand-alone transposed convolution, adds the bias, rounds to the activation type
 // and writes the values that land in the (4 RPW + 2) x 18 patch (zero outside the image).
-template <class P, int TN, bool POOL, int RPW, int UPCD = 0>
+template <class P, int TN, bool POOL, int RPW, int UPCD = 0, int NS = 1>
 __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0, int c0,
                                            const typename P::T* __restrict__ x1, int c1,
                                            const typename P::T* __restrict__ w,
@@ -58,8 +102,10 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
     constexpr int VPP_MAX = P::CK / VE;
     constexpr int NPA = ((TH_ + 2) * (TW + 2) * VPP_MAX + CT - 1) / CT;   // patch vectors per thread
     constexpr int NPW = (9 * TN * VPP_MAX + CT - 1) / CT;                 // weight vectors per thread
-    __shared__ __attribute__((aligned(16))) T patch[(TH_ + 2) * (TW + 2) * PS];
-    __shared__ __attribute__((aligned(16))) T wl[9 * TN * PS];
+    static_assert(NS == 1 || UPCD == 0, "multi-chunk stages are for the plain convolution");
+    constexpr int PSZ = (TH_ + 2) * (TW + 2) * PS, WSZ = 9 * TN * PS;   // one chunk's patch / weights
+    __shared__ __attribute__((aligned(16))) T patch[NS * PSZ];
+    __shared__ __attribute__((aligned(16))) T wl[NS * WSZ];
     // fused upsampling: coarse patch geometry, LDS and per-lane fragments
     constexpr int DR = TH_ / 2 + 2, DC = TW / 2 + 2, NDP = DR * DC;   // coarse patch pixels
     constexpr int NDB = (NDP + 15) / 16;                               // their 16-pixel MFMA blocks
@@ -92,7 +138,7 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
     const int groups = 9 * cpg;
     const int steps = (groups + 3) / 4;
     const int npa = (TH_ + 2) * (TW + 2) * vpp, npw = 9 * TN * vpp;
-    uint4 ra[NPA], rw[NPW];
+    uint4 ra[NS][NPA], rw[NS][NPW];
     const int ukn = UPCD > 0 ? up.cd / (4 * P::GW) : 0;   // MFMA steps of the transposed convolution
     // Staging offsets of this thread, the same for every chunk up to the chunk's channel offset
     // (computed once: index arithmetic per chunk would outweigh the chunk's matrix work). Patch
@@ -161,13 +207,13 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
 #pragma unroll
         for (int i = 0; i < NPW; ++i) rw_[i] = woff[i] >= 0 ? *(const uint4*)(w + woff[i] + k0) : uint4{0, 0, 0, 0};
     };
-    auto lstore = [&](int k0, const uint4 (&ra_)[NPA], const uint4 (&rw_)[NPW]) {
+    auto lstore = [&](int k0, int st, const uint4 (&ra_)[NPA], const uint4 (&rw_)[NPW]) {
 #pragma unroll
         for (int i = 0; i < NPA; ++i)
-            if (plds[i] >= 0 && !(UPCD > 0 && k0 >= c0)) *(uint4*)&patch[plds[i]] = ra_[i];
+            if (plds[i] >= 0 && !(UPCD > 0 && k0 >= c0)) *(uint4*)&patch[st * PSZ + plds[i]] = ra_[i];
 #pragma unroll
         for (int i = 0; i < NPW; ++i)
-            if (wlds[i] >= 0) *(uint4*)&wl[wlds[i]] = rw_[i];
+            if (wlds[i] >= 0) *(uint4*)&wl[st * WSZ + wlds[i]] = rw_[i];
     };
     const int hd = H / 2, wd = W / 2, dr0 = ty0 / 2 - 1, dc0 = tx0 / 2 - 1;
     if constexpr (UPCD > 0) {
@@ -200,11 +246,42 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
         }
     const Acc hb0 = ex.head_w ? ((const Acc*)ex.head_b)[0] : Acc(0);
     const Acc hb1 = ex.head_w ? ((const Acc*)ex.head_b)[1] : Acc(0);
-    // One chunk: stage the registers (ra_, rw_) in LDS, then refill them with chunk kpre (if any)
-    // while the matrix cores work on this one.
-    auto step = [&](int k0, uint4 (&ra_)[NPA], uint4 (&rw_)[NPW], int kpre) {
+    // The matrix-core work of the chunk held in LDS stage stg.
+    auto compute = [&](int stg) {
+        if (ck == P::CK) {
+            conv3_chunk_mma<P, TN, RPW>(acc, &patch[stg * PSZ], &wl[stg * WSZ], wv, lr, lg);
+            return;
+        }
+        for (int sp = 0; sp < steps; ++sp) {
+            const int gi = 4 * sp + lg;
+            Frag a[NCB], b[RPW];
+            if (gi < groups) {
+                const int tap = gi / cpg, cg = gi - tap * cpg;
+                const int dy = tap / 3, dx = tap - 3 * (tap / 3);
+#pragma unroll
+                for (int pb = 0; pb < RPW; ++pb)
+                    b[pb] = P::load(&patch[stg * PSZ + ((RPW * wv + pb + dy) * (TW + 2) + lr + dx) * PS + cg * P::GW]);
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) a[cb] = P::load(&wl[stg * WSZ + (tap * TN + cb * 16 + lr) * PS + cg * P::GW]);
+            } else {
+#pragma unroll
+                for (int pb = 0; pb < RPW; ++pb) b[pb] = P::zero();
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) a[cb] = P::zero();
+            }
+#pragma unroll
+            for (int pb = 0; pb < RPW; ++pb)
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) acc[pb][cb] = P::mma(a[cb], b[pb], acc[pb][cb]);
+        }
+    };
+    // One stage (chunks k0, k0 + ck, ... below kend, at most NS): put the registers in LDS, then
+    // refill them with the stage from kpre on (if any) while the matrix cores work on this one.
+    auto step = [&](int k0, int kpre) {
         __syncthreads();
-        lstore(k0, ra_, rw_);
+#pragma unroll
+        for (int st = 0; st < NS; ++st)
+            if (k0 + st * ck < kend) lstore(k0 + st * ck, st, ra[st], rw[st]);
         if constexpr (UPCD > 0) {
             if (k0 == kbeg) {
                 const int vpd = up.cd / VE;
@@ -258,68 +335,21 @@ __device__ __forceinline__ void conv3_tile(const typename P::T* __restrict__ x0,
                 __syncthreads();
             }
         }
-        if (kpre < kend) gload(kpre, ra_, rw_);
-        if (ck == P::CK) {
-            // full chunk: step st covers tap st / SPT and k-groups 4 (st mod SPT) + lg of it, all
-            // offsets are compile-time after unrolling (the reads of the next steps can be issued
-            // while the matrix cores work)
-            constexpr int SPT = P::CK / P::GW / 4;
-            const T* pbase = &patch[((RPW * wv) * (TW + 2) + lr) * PS + lg * P::GW];
-            const T* wbase = &wl[lr * PS + lg * P::GW];
-            // the wavefront's RPW + 2 patch rows at the 3 column offsets, read from LDS once and
-            // shared by the 3 row offsets dy of the window; the accumulation order is tap by tap,
-            // k-groups within a tap
-            Frag b[RPW + 2][3][SPT];
 #pragma unroll
-            for (int ir = 0; ir < RPW + 2; ++ir)
+        for (int st = 0; st < NS; ++st)
+            if (kpre + st * ck < kend) gload(kpre + st * ck, ra[st], rw[st]);
 #pragma unroll
-                for (int dx = 0; dx < 3; ++dx)
-#pragma unroll
-                    for (int sg = 0; sg < SPT; ++sg)
-                        b[ir][dx][sg] = P::load(pbase + (ir * (TW + 2) + dx) * PS + 4 * sg * P::GW);
-#pragma unroll
-            for (int tap = 0; tap < 9; ++tap) {
-                const int dy = tap / 3, dx = tap % 3;
-#pragma unroll
-                for (int sg = 0; sg < SPT; ++sg) {
-                    Frag a[NCB];
-#pragma unroll
-                    for (int cb = 0; cb < NCB; ++cb) a[cb] = P::load(wbase + (tap * TN + cb * 16) * PS + 4 * sg * P::GW);
-#pragma unroll
-                    for (int pb = 0; pb < RPW; ++pb)
-#pragma unroll
-                        for (int cb = 0; cb < NCB; ++cb) acc[pb][cb] = P::mma(a[cb], b[pb + dy][dx][sg], acc[pb][cb]);
-                }
-            }
-            return;
-        }
-        for (int st = 0; st < steps; ++st) {
-            const int gi = 4 * st + lg;
-            Frag a[NCB], b[RPW];
-            if (gi < groups) {
-                const int tap = gi / cpg, cg = gi - tap * cpg;
-                const int dy = tap / 3, dx = tap - 3 * (tap / 3);
-#pragma unroll
-                for (int pb = 0; pb < RPW; ++pb)
-                    b[pb] = P::load(&patch[((RPW * wv + pb + dy) * (TW + 2) + lr + dx) * PS + cg * P::GW]);
-#pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) a[cb] = P::load(&wl[(tap * TN + cb * 16 + lr) * PS + cg * P::GW]);
-            } else {
-#pragma unroll
-                for (int pb = 0; pb < RPW; ++pb) b[pb] = P::zero();
-#pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) a[cb] = P::zero();
-            }
-#pragma unroll
-            for (int pb = 0; pb < RPW; ++pb)
-#pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) acc[pb][cb] = P::mma(a[cb], b[pb], acc[pb][cb]);
-        }
+        for (int st = 0; st < NS; ++st)
+            if (k0 + st * ck < kend) compute(st);
     };
-    gload(kbeg, ra, rw);
+    gload(kbeg, ra[0], rw[0]);
+#pragma unroll
+    for (int st = 1; st < NS; ++st)
+        if (kbeg + st * ck < kend) gload(kbeg + st * ck, ra[st], rw[st]);
     asm volatile("" ::: "memory");   // keep the loads above the test
     if (skipped) return;             // uniform over the block
-    for (int k0 = kbeg; k0 < kend; k0 += ck) step(k0, ra, rw, k0 + ck);
+    for (int k0 = kbeg; k0 < kend; k0 += NS * ck) step(k0, k0 + NS * ck);
+
 
     const int gx = tx0 + lr;
     if (splitp) {
@@ -468,7 +498,7 @@ __global__ void k_splitk_epilogue(const typename P::Acc* __restrict__ part, int 
 }
 
 // grid: x = column tiles, y = row tiles, z = (sample, channel block, K split)
-template <class P, int TN, bool POOL, int RPW>
+template <class P, int TN, bool POOL, int RPW, int NS = 1>
 __global__ __launch_bounds__(CT) void k_conv3(const typename P::T* __restrict__ x0, int c0,
                                               const typename P::T* __restrict__ x1, int c1,
                                               const typename P::T* __restrict__ w,
@@ -493,9 +523,231 @@ __global__ __launch_bounds__(CT) void k_conv3(const typename P::T* __restrict__ 
     const int cin_p = c0 + c1;
     const int nch = cin_p / ck;
     const int kb = (nch * zs / nsplit) * ck, ke = (nch * (zs + 1) / nsplit) * ck;
-    conv3_tile<P, TN, POOL, RPW>(x0, c0, x1, c1, w, bias, y, cout_p, ypool, H, W, relu, ck, ex, bz, co0,
+    conv3_tile<P, TN, POOL, RPW, 0, NS>(x0, c0, x1, c1, w, bias, y, cout_p, ypool, H, W, relu, ck, ex, bz, co0,
                                  tyi * 4 * RPW, txi * TW, kb, ke, splitp ? splitp + zs * sstride : nullptr, UpIn(),
                                  skip);
+}
+
+// Weight-stationary 3x3 convolution for layers with few input channels on large grids, with
+// loader and compute wavefronts. A block of 8 wavefronts keeps the weights of its TN output
+// channels for all WCH chunks (9 x TN x cin_p, the whole input) in LDS, loaded once, and runs tpb
+// consecutive pixel tiles with them (row-major tile order of the sample). Wavefronts 4-7 only
+// load: they hold the patches (all chunks) of the next K tiles in K register sets and move one
+// tile per step into a double-buffered LDS patch; wavefronts 0-3 only compute and store: per step
+// they run the matrix cores on the tile staged in the previous step and write its outputs. Each
+// wavefront's memory counter then tracks loads only or stores only, so a loader waits for its
+// oldest tile alone while K - 1 tiles of loads stay in flight. One barrier per step. Every output
+// is accumulated chunk by chunk and tap by tap as in conv3_tile (same result bits as the other
+// variants). Plain epilogue: bias, ReLU, optional 2 x 2 average pool.
+// grid: x = tile groups, y = channel blocks, z = samples.
+constexpr int WS_THREADS = 2 * CT;
+template <class P, int TN, bool POOL, int RPW, int WCH, int K>
+__global__ __launch_bounds__(WS_THREADS) void k_conv3_ws(const typename P::T* __restrict__ x0, int c0,
+                                                         const typename P::T* __restrict__ x1, int c1,
+                                                         const typename P::T* __restrict__ w,
+                                                         const typename P::Acc* __restrict__ bias,
+                                                         typename P::T* __restrict__ y, int cout_p,
+                                                         typename P::T* __restrict__ ypool, int H, int W, int relu,
+                                                         int tpb, const int* __restrict__ skip) {
+    using T = typename P::T;
+    using Acc = typename P::Acc;
+    using AccV = typename P::AccV;
+    const int skipped = skip ? *skip : 0;   // tested once the first loads are in flight
+    constexpr int TH_ = 4 * RPW;
+    constexpr int PS = pix_stride<P>();
+    constexpr int VE = 16 / sizeof(T);
+    constexpr int NCB = TN / 16;
+    constexpr int VPP = P::CK / VE;
+    constexpr int PSZ = (TH_ + 2) * (TW + 2) * PS, WSZ = 9 * TN * PS;
+    constexpr int NPV = (TH_ + 2) * (TW + 2) * VPP;       // patch vectors per chunk
+    constexpr int NPA = (NPV + CT - 1) / CT;              // per loader thread
+    constexpr int NPW = (9 * TN * VPP + WS_THREADS - 1) / WS_THREADS;   // weight vectors per thread
+    __shared__ __attribute__((aligned(16))) T patch[2 * WCH * PSZ];
+    __shared__ __attribute__((aligned(16))) T wl[WCH * WSZ];
+
+    // logical order: channel block fastest, then tile group, then sample
+    const int ncb_tot = gridDim.y;
+    const int ngrp = gridDim.x;
+    const int nblk = gridDim.x * gridDim.y * gridDim.z;
+    int v = xcd_linear(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nblk);
+    const int cbi = v % ncb_tot;
+    v /= ncb_tot;
+    const int grp = v % ngrp;
+    const int bz = v / ngrp;
+    const int co0 = cbi * TN;
+    const int cin_p = c0 + c1;
+    const int nch = cin_p / P::CK;   // <= WCH (checked on the host)
+    const int ntx = (W + TW - 1) / TW;
+    const int t_beg = grp * tpb, t_end = min(ntx * ((H + TH_ - 1) / TH_), t_beg + tpb);
+    const int64_t plane = (int64_t)H * W;
+    const T* xs0 = x0 + (int64_t)bz * plane * c0;
+    const T* xs1 = x1 ? x1 + (int64_t)bz * plane * c1 : nullptr;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool loader = wv >= 4;
+    const int lt = threadIdx.x - CT;   // loader thread index (loaders only)
+    const int lr = lane & 15, lg = lane >> 4;
+
+    // weights of all chunks (every wavefront): into registers together, then into LDS
+    {
+        uint4 rw[WCH][NPW];
+#pragma unroll
+        for (int c = 0; c < WCH; ++c)
+#pragma unroll
+            for (int i = 0; i < NPW; ++i) {
+                const int vv = threadIdx.x + i * WS_THREADS;
+                rw[c][i] = uint4{0, 0, 0, 0};
+                if (c < nch && vv < 9 * TN * VPP) {
+                    const int row = vv / VPP, part = vv - row * VPP;
+                    const int tap = row / TN, co = row - tap * TN;
+                    rw[c][i] = *(const uint4*)(w + (int64_t)(tap * cout_p + co0 + co) * cin_p + c * P::CK + part * VE);
+                }
+            }
+#pragma unroll
+        for (int c = 0; c < WCH; ++c)
+#pragma unroll
+            for (int i = 0; i < NPW; ++i) {
+                const int vv = threadIdx.x + i * WS_THREADS;
+                if (c < nch && vv < 9 * TN * VPP) {
+                    const int row = vv / VPP, part = vv - row * VPP;
+                    *(uint4*)&wl[c * WSZ + row * PS + part * VE] = rw[c][i];
+                }
+            }
+    }
+    // loader: the patches of all chunks of tile t into ra_. Every lane loads unconditionally (from
+    // pixel 0 where its pixel is outside the image), so that the number of loads in flight does not
+    // depend on the data; ok_ marks the vectors inside, and lstore writes zeros for the others.
+    auto gload = [&](int t, uint4 (&ra_)[WCH][NPA], uint32_t& ok_) {
+        const int ty0 = (t / ntx) * TH_, tx0 = (t % ntx) * TW;
+        ok_ = 0;
+#pragma unroll
+        for (int i = 0; i < NPA; ++i) {
+            const int vv = min(lt + i * CT, NPV - 1);
+            const int px = vv / VPP;
+            const int part = vv - px * VPP;
+            const int py = px / (TW + 2), pxx = px - py * (TW + 2);
+            const int gy = ty0 + py - 1, gx = tx0 + pxx - 1;
+            const bool in = gy >= 0 && gy < H && gx >= 0 && gx < W;
+            const int64_t pix = in ? (int64_t)gy * W + gx : 0;
+            ok_ |= (in ? 1u : 0u) << i;
+#pragma unroll
+            for (int c = 0; c < WCH; ++c) {
+                const int k0 = c * P::CK;
+                const T* src = k0 < c0 ? xs0 + pix * c0 + k0 : xs1 + pix * c1 + (k0 - c0);
+                ra_[c][i] = *(const uint4*)(src + part * VE);
+            }
+        }
+    };
+    // loader: a register set into LDS patch buffer b
+    auto lstore = [&](int b, const uint4 (&ra_)[WCH][NPA], uint32_t ok_) {
+#pragma unroll
+        for (int i = 0; i < NPA; ++i) {
+            const int vv = lt + i * CT;
+            if (vv < NPV) {
+                const int px = vv / VPP, part = vv - px * VPP;
+                const bool in = (ok_ >> i) & 1u;
+#pragma unroll
+                for (int c = 0; c < WCH; ++c)
+                    *(uint4*)&patch[(b * WCH + c) * PSZ + px * PS + part * VE] = in ? ra_[c][i] : uint4{0, 0, 0, 0};
+            }
+        }
+    };
+    // loader set u holds tile t_beg + u + K j for j = 0, 1, ...
+    uint4 ra[K][WCH][NPA];
+    uint32_t ok[K];
+    if (loader) {
+#pragma unroll
+        for (int u = 0; u < K; ++u) gload(min(t_beg + u, t_end - 1), ra[u], ok[u]);
+    }
+    asm volatile("" ::: "memory");       // keep the loads above the test
+    if (skipped) return;                 // uniform over the block
+    if (loader) lstore(0, ra[0], ok[0]);   // tile t_beg into buffer 0
+    __syncthreads();
+
+    // compute wavefronts: tile t from LDS buffer b, outputs to memory
+    Acc bpre[NCB][4];
+    auto compute = [&](int t, int b) {
+        AccV acc[RPW][NCB];
+#pragma unroll
+        for (int pb = 0; pb < RPW; ++pb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[pb][cb][r] = 0;
+#pragma unroll
+        for (int c = 0; c < WCH; ++c)
+            if (c < nch) conv3_chunk_mma<P, TN, RPW>(acc, &patch[(b * WCH + c) * PSZ], &wl[c * WSZ], wv, lr, lg);
+        // register r of a lane holds output channel co0 + 16 cb + row_of(lg, r) of pixel
+        // (ty0 + RPW wv + pb, tx0 + lr)
+        const int ty0 = (t / ntx) * TH_, tx0 = (t % ntx) * TW;
+        const int gx = tx0 + lr;
+        T* ys = y + (int64_t)bz * plane * cout_p;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const int co = co0 + cb * 16;
+            Acc vv[RPW][4];
+#pragma unroll
+            for (int pb = 0; pb < RPW; ++pb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    Acc q = acc[pb][cb][r] + bpre[cb][r];
+                    if (relu) q = q > Acc(0) ? q : Acc(0);
+                    vv[pb][r] = q;
+                }
+#pragma unroll
+            for (int pb = 0; pb < RPW; ++pb) {
+                const int gy = ty0 + RPW * wv + pb;
+                if (gy < H && gx < W) store_rows<P>(ys + ((int64_t)gy * W + gx) * cout_p + co + P::row_of(lg, 0), vv[pb]);
+            }
+            if (POOL) {
+                T* ps = ypool + (int64_t)bz * (plane / 4) * cout_p;
+#pragma unroll
+                for (int pp = 0; pp < RPW; pp += 2) {
+                    Acc q[4];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        Acc sm = vv[pp][r] + vv[pp + 1][r];
+                        sm += __shfl_xor(sm, 1, 64);
+                        q[r] = Acc(0.25) * sm;
+                    }
+                    const int gy = ty0 + RPW * wv + pp;
+                    if ((lr & 1) == 0 && gy < H && gx < W)
+                        store_rows<P>(ps + ((int64_t)(gy / 2) * (W / 2) + gx / 2) * cout_p + co + P::row_of(lg, 0), q);
+                }
+            }
+        }
+    };
+    // Step i (tile t = t_beg + i), one barrier each: the compute wavefronts work on buffer i % 2
+    // while the loaders move tile t + 1 (register set (i + 1) % K) into buffer (i + 1) % 2 and
+    // refill set i % K with tile t + K. The two roles run separate loops with the same number of
+    // barriers (the role is uniform per wavefront), so that each role's code holds only its own
+    // kind of memory operation and its waits count only those.
+    if (loader) {
+        for (int t0 = t_beg; t0 < t_end; t0 += K) {
+#pragma unroll
+            for (int u = 0; u < K; ++u) {
+                const int t = t0 + u;
+                if (t < t_end) {
+                    const int b = (t - t_beg) & 1;
+                    if (t + 1 < t_end) lstore(b ^ 1, ra[(u + 1) % K], ok[(u + 1) % K]);
+                    // (past the group's last tile the set reloads that tile: the same number of
+                    // loads on every path)
+                    gload(min(t + K, t_end - 1), ra[u], ok[u]);
+                    __syncthreads();
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) bpre[cb][r] = bias[co0 + cb * 16 + P::row_of(lg, r)];
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the bias is in registers before the loop
+        for (int t = t_beg; t < t_end; ++t) {
+            compute(t, (t - t_beg) & 1);
+            __syncthreads();
+        }
+    }
 }
 
 // Decoder 3x3 convolution with the transposed convolution of the coarser level fused in (UpIn).
@@ -742,6 +994,49 @@ int launch_conv3(const typename P::T* x0, int c0, const typename P::T* x1, int c
         return HZ_ERR_ARG;
     }
     const int rpw = cfg.rpw == 4 ? 4 : 2;
+    if (cfg.tpb > 1 && !ex.head_w && !ex.split && !ex.mask0_ && !ex.mask1_ && bias &&
+        conv3_ws_ok<P>(cfg.tn, rpw, c0, c1, cout_p)) {
+        // weight-stationary form: all weights of the block's channels in LDS, cfg.tpb tiles per block
+        const int tn = cfg.tn, th = 4 * rpw;
+        const int ntiles = ((W + TW - 1) / TW) * ((H + th - 1) / th);
+        const int ngrp = (ntiles + cfg.tpb - 1) / cfg.tpb;
+        const int nch = cin_p / P::CK;
+        dim3 grid(ngrp, cout_p / tn, batch);
+#define HZ_WS1(TNV, PL, R, WC, KV)                                                                           \
+    hipLaunchKernelGGL((k_conv3_ws<P, TNV, PL, R, WC, KV>), grid, dim3(WS_THREADS), 0, s, x0, c0, x1, c1, w, bias, \
+                       y, cout_p, ypool, H, W, relu ? 1 : 0, cfg.tpb, skip)
+#define HZ_WS(TNV, PL, R, WC)                                             \
+    if constexpr (R == 2) {                                               \
+        if (cfg.ns >= 4 && WC <= 2) { HZ_WS1(TNV, PL, R, WC, 4); }        \
+        else if (cfg.ns == 3) { HZ_WS1(TNV, PL, R, WC, 3); }              \
+        else { HZ_WS1(TNV, PL, R, WC, 2); }                               \
+    } else {                                                              \
+        HZ_WS1(TNV, PL, R, WC, 2);                                        \
+    }
+#define HZ_WSW(TNV, PL, R)                                                                        \
+    if (nch == 1) {                                                                                \
+        if constexpr (conv3_ws_lds<P>(TNV, R, 1) <= 160 * 1024) { HZ_WS(TNV, PL, R, 1); }          \
+    } else if (nch == 2) {                                                                         \
+        if constexpr (conv3_ws_lds<P>(TNV, R, 2) <= 160 * 1024) { HZ_WS(TNV, PL, R, 2); }          \
+    } else if constexpr (conv3_ws_lds<P>(TNV, R, 4) <= 160 * 1024) { HZ_WS(TNV, PL, R, 4); }
+#define HZ_WST(PL, R)                        \
+    if (tn == 64) { HZ_WSW(64, PL, R) }      \
+    else if (tn == 32) { HZ_WSW(32, PL, R) } \
+    else { HZ_WSW(16, PL, R) }
+        if constexpr (std::is_same<P, PolBF16>::value) {
+            if (ypool) {
+                if (rpw == 4) { HZ_WST(true, 4) } else { HZ_WST(true, 2) }
+            } else {
+                if (rpw == 4) { HZ_WST(false, 4) } else { HZ_WST(false, 2) }
+            }
+        }
+#undef HZ_WST
+#undef HZ_WSW
+#undef HZ_WS
+#undef HZ_WS1
+        HZ_LAUNCH_CHECK();
+        return HZ_OK;
+    }
     int ksplit = cfg.ksplit < 1 ? 1 : cfg.ksplit;
     if (ksplit > cin_p / ck) ksplit = cin_p / ck;
     if (ksplit > 1 && (!splitbuf || ex.split || ex.mask0_ || ex.mask1_)) ksplit = 1;
@@ -774,19 +1069,32 @@ int launch_conv3(const typename P::T* x0, int c0, const typename P::T* x1, int c
     const int64_t sstride = (int64_t)batch * H * W * cout_p;
     typename P::Acc* sp = ksplit > 1 ? splitbuf : nullptr;
     const bool kpool = ypool && ksplit == 1;
-#define HZ_C3(TNV, PL, R)                                                                                  \
-    hipLaunchKernelGGL((k_conv3<P, TNV, PL, R>), grid, dim3(CT), 0, s, x0, c0, x1, c1, w, bias, y, cout_p, \
+    // chunks per LDS stage: BF16 only, where the stage fits in LDS (conv3_stages_ok)
+    int ns = cfg.ns;
+    if (!conv3_stages_ok<P>(tn, rpw, ns) || ex.head_w) ns = 1;
+#define HZ_C3(TNV, PL, R, NSV)                                                                                  \
+    hipLaunchKernelGGL((k_conv3<P, TNV, PL, R, NSV>), grid, dim3(CT), 0, s, x0, c0, x1, c1, w, bias, y, cout_p, \
                        kpool ? ypool : nullptr, H, W, relu ? 1 : 0, ck, skip, ex, ksplit, sp, sstride)
+#define HZ_C3N(TNV, PL, R)                                                    \
+    if constexpr (std::is_same<P, PolBF16>::value) {                          \
+        if (ns == 2) HZ_C3(TNV, PL, R, 2);                                    \
+        else if (ns == 4) {                                                   \
+            if constexpr (conv3_stages_ok<P>(TNV, R, 4)) HZ_C3(TNV, PL, R, 4); \
+        } else HZ_C3(TNV, PL, R, 1);                                          \
+    } else {                                                                  \
+        HZ_C3(TNV, PL, R, 1);                                                 \
+    }
 #define HZ_C3T(PL, R)                       \
-    if (tn == 64) HZ_C3(64, PL, R);         \
-    else if (tn == 32) HZ_C3(32, PL, R);    \
-    else HZ_C3(16, PL, R);
+    if (tn == 64) { HZ_C3N(64, PL, R) }     \
+    else if (tn == 32) { HZ_C3N(32, PL, R) } \
+    else { HZ_C3N(16, PL, R) }
     if (kpool) {
         if (rpw == 4) { HZ_C3T(true, 4) } else { HZ_C3T(true, 2) }
     } else {
         if (rpw == 4) { HZ_C3T(false, 4) } else { HZ_C3T(false, 2) }
     }
 #undef HZ_C3T
+#undef HZ_C3N
 #undef HZ_C3
     HZ_LAUNCH_CHECK();
     if (ksplit > 1) {

@@ -10,6 +10,8 @@
 // ReLU and can also write the 2 x 2 average pool of the result.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace hz {
@@ -134,7 +136,44 @@ struct ConvCfg {
     int rpw = 2;
     int ksplit = 1;
     int fuse = 0;   // decoder layer: take the fused form (transposed convolution inside, UpIn)
+    int ns = 1;     // input-channel chunks per LDS stage (1, 2 or 4; BF16 only, same result bits)
+    int tpb = 0;    // > 1: weight-stationary form with tpb pixel tiles per block (BF16, conv3_ws_ok);
+                    // ns is then the number of tiles whose loads are in flight (2, 3 or 4)
 };
+
+// LDS bytes of the weight-stationary 3x3 form: the weights of wch chunks and two patch buffers of
+// wch chunks each.
+template <class P>
+constexpr int conv3_ws_lds(int tn, int rpw, int wch) {
+    const int ps = P::CK + 16 / (int)sizeof(typename P::T);
+    return wch * (2 * (4 * rpw + 2) * 18 * ps + 9 * tn * ps) * (int)sizeof(typename P::T);
+}
+
+// Whether the weight-stationary form applies: BF16, channel tile tn in {16, 32, 64} dividing
+// cout_p, both input parts whole chunks of P::CK channels, 1, 2 or 4 chunks, and the LDS of all
+// chunk buffers within 160 KB.
+template <class P>
+constexpr bool conv3_ws_ok(int tn, int rpw, int c0, int c1, int cout_p) {
+    if (!std::is_same<P, PolBF16>::value) return false;
+    if (tn != 16 && tn != 32 && tn != 64) return false;
+    if (cout_p % tn || c0 % P::CK || c1 % P::CK || c0 + c1 == 0) return false;
+    const int nch = (c0 + c1) / P::CK;
+    if (nch != 1 && nch != 2 && nch != 4) return false;
+    return conv3_ws_lds<P>(tn, rpw, nch) <= 160 * 1024;
+}
+
+// Whether a 3x3 launch with channel tile tn, rows per wavefront rpw and ns chunks per LDS stage
+// exists: ns = 1 always; ns = 2 for BF16; ns = 4 for BF16 where the four stages fit in the LDS
+// (160 KB per workgroup).
+template <class P>
+constexpr bool conv3_stages_ok(int tn, int rpw, int ns) {
+    if (ns == 1) return true;
+    if (ns != 2 && ns != 4) return false;
+    if (!std::is_same<P, PolBF16>::value) return false;
+    const int ps = P::CK + 8;   // BF16 pixel stride (elements)
+    const int bytes = ((4 * rpw + 2) * 18 * ps + 9 * tn * ps) * 2;
+    return ns * bytes <= 160 * 1024;
+}
 
 // Second input part of a decoder 3x3 convolution given as the 2x2 stride-2 transposed
 // convolution of a coarser tensor, computed inside each block and never stored:

@@ -40,9 +40,14 @@ class HzOpts(ct.Structure):
                 ("ortho", ct.c_int32)]
 
 
+HZ_NPHASE = 4
+PHASES = ("setup", "cycles", "build", "total")   # HZ_PHASE_* order
+
+
 class HzInfo(ct.Structure):
     _fields_ = [("status", ct.c_int32), ("its", ct.c_int32), ("cycles", ct.c_int32),
-                ("est_relres", ct.c_double), ("true_relres", ct.c_double)]
+                ("est_relres", ct.c_double), ("true_relres", ct.c_double),
+                ("phase_ms", ct.c_double * HZ_NPHASE)]
 
 
 _P, _I, _SZ, _F = ct.c_void_p, ct.c_int, ct.c_size_t, ct.c_float
@@ -61,8 +66,9 @@ SIGNATURES = {
     "no_precond_apply": (_I, [_P, _P, _I, _I, _P, _P, _P, _SZ, _P]),
     "no_precond_apply_noalloc": (_I, [_P, _P, _I, _I, _P, _P, _P]),
     "no_autotune": (_I, [_P, _P, _I, _P, _SZ, _P]),
-    "no_layer_variant": (_I, [_P, _I, _I, _I, _I, _I, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)]),
-    "no_set_layer_variant": (_I, [_P, _I, _I, _I, _I, _I, _I, _I]),
+    "no_layer_variant": (_I, [_P, _I, _I, _I, _I, _I, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32),
+                              ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32)]),
+    "no_set_layer_variant": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I, _I]),
     "no_set_fused_upsampling": (_I, [_P, _I]),
     "no_layer_info": (_I, [_P, _I, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32),
                            ct.POINTER(ct.c_int32)]),
@@ -230,16 +236,17 @@ class Net:
                "no_autotune")
 
     def layer_variant(self, layer: int, H: int, W: int, prec: str = "bf16", batch: int = 1):
-        """(tn, rows) launch variant of a 3x3 layer at this size (no_layer_variant)."""
-        tn, rows = ct.c_int32(), ct.c_int32()
+        """(tn, rows, stages, tiles) launch variant of a 3x3 layer at this size (no_layer_variant)."""
+        tn, rows, st, tl = ct.c_int32(), ct.c_int32(), ct.c_int32(), ct.c_int32()
         _check(load_library().no_layer_variant(self.handle, layer, PREC[prec], batch, H, W, ct.byref(tn),
-                                               ct.byref(rows)), "no_layer_variant")
-        return tn.value, rows.value
+                                               ct.byref(rows), ct.byref(st), ct.byref(tl)), "no_layer_variant")
+        return tn.value, rows.value, st.value, tl.value
 
-    def set_layer_variant(self, layer: int, H: int, W: int, tn: int, rows: int, prec: str = "bf16", batch: int = 1):
+    def set_layer_variant(self, layer: int, H: int, W: int, tn: int, rows: int, stages: int = 1, tiles: int = 1,
+                          prec: str = "bf16", batch: int = 1):
         """Pin the launch variant of a 3x3 layer at this size (no_set_layer_variant)."""
-        _check(load_library().no_set_layer_variant(self.handle, layer, PREC[prec], batch, H, W, tn, rows),
-               "no_set_layer_variant")
+        _check(load_library().no_set_layer_variant(self.handle, layer, PREC[prec], batch, H, W, tn, rows, stages,
+                                                   tiles), "no_set_layer_variant")
 
     def set_fused_upsampling(self, mode: int):
         """BF16 decoder: transposed convolution inside the next 3x3 layer: 0 never, 1 always,
@@ -374,6 +381,11 @@ class SolveInfo:
     est_relres: float
     true_relres: float
     hist: np.ndarray
+    phase_ms: dict = None   # {"setup", "cycles", "build", "total"} in milliseconds
+
+
+def _phases(info) -> dict:
+    return {k: float(info.phase_ms[i]) for i, k in enumerate(PHASES)}
 
 
 ORTHO = {"cgs2": 0, "dcgs2": 1}
@@ -415,7 +427,8 @@ def fgmres(problem: Problem, b, x0=None, *, net: Net | None = None, m: int = 30,
                           ct.byref(info), _stream())
     if rc in (HZ_ERR_ARG, HZ_ERR_HIP, HZ_ERR_WORKSPACE):
         _check(rc, "fgmres_solve")
-    return x, SolveInfo(info.status, info.its, info.cycles, info.est_relres, info.true_relres, hist[:info.its].copy())
+    return x, SolveInfo(info.status, info.its, info.cycles, info.est_relres, info.true_relres, hist[:info.its].copy(),
+                        _phases(info))
 
 
 def fgmres_batched(problems, bs, x0s=None, *, net: Net | None = None, m: int = 30, tol: float = 1e-6,
@@ -443,7 +456,8 @@ def fgmres_batched(problems, bs, x0s=None, *, net: Net | None = None, m: int = 3
                                   _stream())
     if rc in (HZ_ERR_ARG, HZ_ERR_HIP, HZ_ERR_WORKSPACE):
         _check(rc, "fgmres_solve_batched")
-    return xs, [SolveInfo(i.status, i.its, i.cycles, i.est_relres, i.true_relres, np.zeros(0)) for i in infos]
+    return xs, [SolveInfo(i.status, i.its, i.cycles, i.est_relres, i.true_relres, np.zeros(0), _phases(i))
+                for i in infos]
 
 
 def fgmres_batched_workspace_bytes(problems, net: Net | None, m: int, maxit: int, krylov: str = "c64",

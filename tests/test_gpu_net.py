@@ -113,13 +113,84 @@ def test_pinned_layer_variants_identical_bits():
                 H = Hp >> level[i]
                 tn = tn0 if specs[i][3] % tn0 == 0 else 16
                 net.set_layer_variant(i, H, H, tn, rows, prec=prec)
-                assert net.layer_variant(i, H, H, prec=prec) == (tn, rows)
+                assert net.layer_variant(i, H, H, prec=prec) == (tn, rows, 1, 1)
             outs.append(net.apply(gp, vd, prec=prec))
         assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
     with pytest.raises(hz.HzError):
         net.set_layer_variant(convs[0], Hp, Hp, 24, 8)
     with pytest.raises(hz.HzError):
         net.set_layer_variant(len(specs) - 1, Hp, Hp, 16, 8)   # the head is not a 3x3 layer
+    with pytest.raises(hz.HzError):
+        net.set_layer_variant(convs[0], Hp, Hp, 16, 8, stages=2, prec="fp32")   # BF16 only
+    with pytest.raises(hz.HzError):
+        net.set_layer_variant(convs[0], Hp, Hp, 16, 8, stages=3)
+    i32 = next(i for i in convs if specs[i][3] % 32 == 0)
+    with pytest.raises(hz.HzError):   # four stages of 32-channel, 16-row tiles do not fit in the LDS
+        net.set_layer_variant(i32, Hp >> level[i32], Hp >> level[i32], 32, 16, stages=4)
+
+
+@pytest.mark.parametrize("levels,base,nx,p", [(4, 32, 64, 8), (2, 96, 40, 8)])
+def test_staged_chunks_identical_bits(levels, base, nx, p):
+    # several input-channel chunks per LDS stage (one global-load latency per stage) compute the
+    # chunks in the same order: BF16 outputs bit-identical to one chunk per stage, with chunk
+    # counts that stages do not divide (96 / 192 channels: 3 or 6 chunks of 32; the decoder's two
+    # input parts) and every channel tile and tile height
+    from paper_2607_16906_amd import hz
+    op, gp, specs, theta, net, v = setup(levels, base, 5, nx, p, seed=8)
+    q = 1 << (levels - 1)
+    Hp = (op.ny + q - 1) // q * q
+    convs = [i for i, s in enumerate(specs) if s[1] == "conv3"]
+    level = {i: int(s[0][3]) for i, s in enumerate(specs) if s[0][:3] in ("enc", "dec")}
+    vd = to_dev(v, torch.complex64)
+    net.set_fused_upsampling(0)
+
+    used = [0]
+
+    def run(tn0, rows, stages, tiles=1, inflight=1):
+        nws = 0
+        for i in convs:
+            H = Hp >> level[i]
+            tn = tn0 if specs[i][3] % tn0 == 0 else 16
+            st, tl = stages, tiles
+            if tl > 1:
+                st = inflight
+                while True:
+                    try:
+                        net.set_layer_variant(i, H, H, tn, rows, st, tl)
+                        nws += 1
+                        break
+                    except hz.HzError:
+                        if st == 2:
+                            tl = 1
+                            break
+                        st -= 1
+                if tl == 1:
+                    st = stages
+            if tl == 1:
+                while st > 1:
+                    try:
+                        net.set_layer_variant(i, H, H, tn, rows, st)
+                        break
+                    except hz.HzError:
+                        st //= 2
+                if st == 1:
+                    net.set_layer_variant(i, H, H, tn, rows, 1)
+            assert net.layer_variant(i, H, H) == (tn, rows, st, tl)
+        used[0] += nws
+        return net.apply(gp, vd, prec="bf16")
+
+    ref = run(16, 8, 1)
+    for tn0, rows, stages in ((16, 8, 2), (16, 8, 4), (32, 8, 4), (16, 16, 4), (64, 16, 2), (32, 16, 2), (64, 8, 2)):
+        out = run(tn0, rows, stages)
+        assert torch.equal(out, ref), (tn0, rows, stages)
+    # the weight-stationary form (all weights of the block's channels in LDS, several pixel tiles
+    # per block; tile counts that do not divide the grid's tiles) where the layer qualifies
+    for tn0, rows, tiles, inflight in ((16, 8, 2, 2), (32, 8, 3, 2), (64, 16, 4, 3), (32, 16, 7, 3), (16, 8, 64, 4),
+                                       (32, 8, 8, 4), (16, 16, 5, 2), (32, 8, 1000, 4)):
+        out = run(tn0, rows, 1, tiles, inflight)
+        assert torch.equal(out, ref), (tn0, rows, tiles, inflight)
+    # (the 96-channel network has 3 or 6 chunks per layer: no layer takes that form)
+    assert used[0] > 0 or base == 96
 
 
 @pytest.mark.parametrize("levels,base,nx,p", [(4, 32, 256, 20), (4, 32, 30, 6), (3, 64, 44, 10), (4, 32, 100, 14)])
