@@ -168,12 +168,12 @@ def resident_set(c, b, nint: int, npml: int, h: float):
 
 
 def save_weights(path, theta, *, levels, base, in_ch, dataset, nint, npml, epochs, best_epoch, best_val, steps,
-                 bf16=False):
+                 bf16=False, arch="unet3"):
     """Write a parameter file: float32 theta (or, bf16=True, its BF16 rounding as 16-bit patterns,
     half the size, for networks that only run with BF16 operands) and the training record."""
     th = np.asarray(theta, np.float32)
     rec = dict(levels=levels, base=base, in_ch=in_ch, dataset=dataset, nint=nint, npml=npml, epochs=epochs,
-               best_epoch=best_epoch, best_val=best_val, step=steps)
+               best_epoch=best_epoch, best_val=best_val, step=steps, arch=arch)
     if bf16:
         u = th.view(np.uint32).astype(np.uint64)
         u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
@@ -190,11 +190,26 @@ def load_weights(path):
     return (w["theta_bf16"].astype(np.uint32) << 16).view(np.float32)
 
 
-def main():
-    """Train a 3x3 U-Net on one of the Table 4 data sets on the GPU and write its parameter file.
+def init_theta_paper8(depth: int, ch: int, in_ch: int, rng, slope: float = 0.25) -> np.ndarray:
+    """Seeded He-uniform weights and biases of Table 2's network (hz.init_shapes_paper8 order), each
+    layer but the 1x1 head followed by its PReLU slope (0.25, the usual PReLU initial value)."""
+    from synth import he_uniform
+    shapes = hz.init_shapes_paper8(depth, ch, in_ch)
+    parts = []
+    for i, sh in enumerate(shapes):
+        parts.append(he_uniform([sh], rng))
+        if i + 1 < len(shapes):
+            parts.append(np.array([slope], np.float32))
+    return np.concatenate(parts).astype(np.float32)
 
-    Usage: python -m paper_2607_16906_amd.train --out FILE [--dataset D0] [--levels 5] [--base 32]
-           [--nint 128] [--npml 16] [--count 4096] [--val 256] [--epochs 24] [--batch 32]
+
+def main():
+    """Train a network on one of the Table 4 data sets on the GPU and write its parameter file:
+    the 3x3 U-Net (--arch unet3; --levels, --base) or Table 2's 8x8 stride-2 network with PReLU
+    (--arch paper8; --levels is its depth, --base its channels per layer; FP32, as Section 3.4).
+
+    Usage: python -m paper_2607_16906_amd.train --out FILE [--arch unet3] [--dataset D0] [--levels 5]
+           [--base 32] [--nint 128] [--npml 16] [--count 4096] [--val 256] [--epochs 24] [--batch 32]
            [--prec fp32] [--bf16-file]
     """
     import argparse
@@ -206,6 +221,7 @@ def main():
                        table4_set, training_set)
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
+    ap.add_argument("--arch", default="unet3", choices=["unet3", "paper8"])
     ap.add_argument("--dataset", default="D0", choices=[f"D{k}" for k in range(6)] + ["mix"],
                     help="a Table 4 data set, or 'mix': the D0-like mixture with smooth source classes "
                          "(Gaussian blobs, box-smoothed noise) beside the paper's ones")
@@ -220,6 +236,8 @@ def main():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--bf16-file", action="store_true", help="store the BF16 rounding of the weights")
     a = ap.parse_args()
+    if a.arch == "paper8" and a.prec != "fp32":
+        ap.error("the paper8 network trains in FP32")
     torch.cuda.set_device(0)
     nt = a.nint + 2 * a.npml
     t0 = time.time()
@@ -232,8 +250,11 @@ def main():
     probs, r = resident_set(c, b, a.nint, a.npml, H_10PPW)
     vprobs, vr = resident_set(cv, bv, a.nint, a.npml, H_10PPW)
     print(f"data set {a.dataset}: {a.count} + {a.val} samples on {nt}^2 in {time.time() - t0:.1f} s", flush=True)
-    theta0 = he_uniform(hz.init_shapes(a.levels, a.base, 5), rng_for(CFG_TABLE4, COMP_WEIGHTS, a.levels))
-    net = hz.Net(a.levels, a.base, 5, theta0)
+    if a.arch == "paper8":
+        theta0 = init_theta_paper8(a.levels, a.base, 5, rng_for(CFG_TABLE4, COMP_WEIGHTS, 100 + a.levels))
+    else:
+        theta0 = he_uniform(hz.init_shapes(a.levels, a.base, 5), rng_for(CFG_TABLE4, COMP_WEIGHTS, a.levels))
+    net = hz.Net(a.levels, a.base, 5, theta0, kind=a.arch)
     tr = Trainer(net, probs, r, vprobs, vr, batch=a.batch, prec=a.prec)
     orders = [rng_for(CFG_TABLE4, COMP_ORDER, e).permutation(a.count) for e in range(a.epochs)]
     res = tr.fit(theta0, orders, log=lambda msg: print(msg, flush=True))
@@ -242,7 +263,7 @@ def main():
           flush=True)
     save_weights(a.out, res.theta_best.cpu().numpy(), levels=a.levels, base=a.base, in_ch=5, dataset=a.dataset,
                  nint=a.nint, npml=a.npml, epochs=a.epochs, best_epoch=res.best_epoch, best_val=res.best_val,
-                 steps=steps, bf16=a.bf16_file)
+                 steps=steps, bf16=a.bf16_file, arch=a.arch)
 
 
 if __name__ == "__main__":
