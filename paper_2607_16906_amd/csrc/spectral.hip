@@ -7,9 +7,9 @@
 // stretching G = diag(1 / gamma), gamma = 1 + i sigma / omega at the nodes, the operator is
 //     A u = u Mx^T + My u + k^2 u,   M = G D G D   (u as an [ny][nx] matrix),
 // and A^H w = w conj(Mx) + My^H w + k^2 w. The library forms Mx and My once per problem
-// (FP64 and FP32), so that one launch applies A: for the small grids of this method (N <= a few
-// thousand) the dense per-axis contraction costs 8 N FLOP per node and reads the grid once,
-// with no temporaries and no FFT passes.
+// (FP64 and FP32), so that one launch applies A: for the grids of this method (N up to a few
+// thousand) the two per-axis contractions are dense complex GEMMs of 8 N FLOP per node each, run
+// on the matrix cores, with no temporaries and no FFT passes.
 #include "problem.h"
 
 namespace hz {
@@ -60,239 +60,188 @@ __global__ void k_spec_mmat(double2* __restrict__ Md, float2* __restrict__ Mf, c
     Mf[(int64_t)j * n + l] = float2{(float)m.x, (float)m.y};
 }
 
-constexpr int SP_K = 32;    // contraction chunk and tile width (x)
-constexpr int SP_Y = 8;     // tile height (y)
+// Matrix-core form. The two per-axis contractions are complex GEMMs, each taken as four real
+// 16 x 16 x 4 MFMA products per k-step (re += a.re b.re - a.im b.im, im += a.re b.im + a.im b.re,
+// the negated a.im staged beside a.im). A block of 8 wavefronts owns a 32 x 32 output tile:
+// wavefronts 0-3 form the x part sum_k u[y][k] Mx'[x][k] of one 16 x 16 quarter each, wavefronts
+// 4-7 the y part sum_k My'[y][k] u[k][x] of the same quarters, both over chunks of SPK k values
+// staged together in LDS (the next chunk's values in registers meanwhile). The y part is then
+// added to the x part (in that order) and the epilogue adds k^2 u; for RESID it forms
+// r = b - A u with the tile's ||r||^2 in part[tile]. Mx' = Mx and My' = My, or for ADJ
+// Mx'[x][k] = conj(Mx[k][x]) and My'[y][k] = conj(My[k][y]). FP32 takes v_mfma_f32_16x16x4_f32,
+// FP64 v_mfma_f64_16x16x4_f64.
+constexpr int SPT = 32;     // output tile edge
+constexpr int SPK = 16;     // k values per chunk
+constexpr int SPW = 512;    // threads per block
 
-// One SP_Y x SP_K output tile (rows y0.., columns x0..) per block of 256 threads, one output per
-// thread: acc = sum_k u[y][k] Mx'[x][k] + sum_k My'[y][k] u[k][x], with Mx'[x][k] = Mx[x][k] and
-// My'[y][k] = My[y][k] (ADJ: conj(Mx[k][x]), conj(My[k][y])), the x part's chunks first, then the
-// y part's, each chunk staged in LDS while the next one is loaded into registers. Then
-// y = acc + k^2 u, or for RESID r = b - (acc + k^2 u) with the tile's ||r||^2 in part[tile].
-// Small tiles keep many blocks in flight: the grids of this method are a few hundred nodes wide.
+template <typename T>
+struct SpecMma;
+template <>
+struct SpecMma<float> {
+    typedef __attribute__((ext_vector_type(4))) float V;
+    __device__ static V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row_of(int lg, int r) { return 4 * lg + r; }
+};
+template <>
+struct SpecMma<double> {
+    typedef __attribute__((ext_vector_type(4))) double V;
+    __device__ static V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row_of(int lg, int r) { return lg + 4 * r; }
+};
+
 template <typename C, bool ADJ, bool RESID>
-__global__ __launch_bounds__(256) void k_spectral(const C* __restrict__ u, C* __restrict__ y, const C* __restrict__ b,
+__global__ __launch_bounds__(SPW) void k_spectral(const C* __restrict__ u, C* __restrict__ y, const C* __restrict__ b,
                                                   const C* __restrict__ Mx, const C* __restrict__ My,
                                                   const decltype(C{}.x)* __restrict__ k2, int nx, int ny,
                                                   double* __restrict__ part, const int* __restrict__ skip) {
     using T = decltype(C{}.x);
+    using M = SpecMma<T>;
+    using V = typename M::V;
     if (skip && *skip) return;
-    __shared__ C sa[SP_Y][SP_K + 1];     // x part: u rows; y part: My' rows
-    __shared__ C sb[SP_K][SP_K + 1];     // x part: Mx' rows (sb[x][k]); y part: u (sb[k][x])
-    const int tx = threadIdx.x & (SP_K - 1), ty = threadIdx.x / SP_K;
-    const int x0 = blockIdx.x * SP_K, y0 = blockIdx.y * SP_Y;
-    T ar = 0, ai = 0;
-    auto mat = [&](const C* M, int n, int r, int k) -> C {   // M'[r][k]
-        if (ADJ) {
-            const C v = M[(int64_t)k * n + r];
-            return C{v.x, -v.y};
-        }
-        return M[(int64_t)r * n + k];
-    };
-    constexpr int PB = SP_K * SP_K / 256;    // sb elements per thread (sa: one)
-    const int ncx = (nx + SP_K - 1) / SP_K, ncy = (ny + SP_K - 1) / SP_K;
-    const int nch = ncx + ncy;
-    C ra, rb[PB];
+    // [row][k] operands (u rows for x, My' rows for y) and [k][col] operands (Mx' for x, u for y),
+    // as real and imaginary planes, one padding element per row
+    __shared__ T sa[2][2][SPT][SPK + 1];   // [part][re/im][row][k]
+    __shared__ T sb[2][2][SPK][SPT + 1];   // [part][re/im][k][col]
+    __shared__ V sy[4][2][64];            // y-part accumulators handed to the x-part wavefronts
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int prt = wv >> 2;              // 0: x part, 1: y part
+    const int q = wv & 3;                 // output quarter: rows 16 (q / 2), columns 16 (q % 2)
+    const int lr = lane & 15, lg = lane >> 4;
+    const int x0 = blockIdx.x * SPT, y0 = blockIdx.y * SPT;
+    const int nch = (max(nx, ny) + SPK - 1) / SPK;
+    // staging: each thread moves one [row][k] and one [k][col] element of each part per chunk
+    // (1024 + 1024 elements, 512 threads, two of each kind per thread)
+    C ra[2][2], rb[2][2];
     auto gload = [&](int ch) {
-        const bool xp = ch < ncx;
-        const int k0 = (xp ? ch : ch - ncx) * SP_K;
-        {
-            const int gy = y0 + ty, gk = k0 + tx;
-            if (xp) ra = (gy < ny && gk < nx) ? u[(int64_t)gy * nx + gk] : C{0, 0};
-            else ra = (gy < ny && gk < ny) ? mat(My, ny, gy, gk) : C{0, 0};
-        }
+        const int k0 = ch * SPK;
 #pragma unroll
-        for (int i = 0; i < PB; ++i) {
-            const int e = threadIdx.x + 256 * i;
-            const int r = e / SP_K, cc = e % SP_K;
-            if (xp) {
-                const int gx = x0 + r, gk = k0 + cc;
-                rb[i] = (gx < nx && gk < nx) ? mat(Mx, nx, gx, gk) : C{0, 0};
-            } else {
-                const int gk = k0 + r, gx = x0 + cc;
-                rb[i] = (gk < ny && gx < nx) ? u[(int64_t)gk * nx + gx] : C{0, 0};
-            }
-        }
-    };
-    gload(0);
-    for (int ch = 0; ch < nch; ++ch) {
-        __syncthreads();
-        sa[ty][tx] = ra;
-#pragma unroll
-        for (int i = 0; i < PB; ++i) {
-            const int e = threadIdx.x + 256 * i;
-            sb[e / SP_K][e % SP_K] = rb[i];
-        }
-        __syncthreads();
-        if (ch + 1 < nch) gload(ch + 1);
-        if (ch < ncx) {
-#pragma unroll 8
-            for (int kk = 0; kk < SP_K; ++kk) {
-                const C a = sa[ty][kk], m = sb[tx][kk];
-                ar += a.x * m.x - a.y * m.y;
-                ai += a.x * m.y + a.y * m.x;
-            }
-        } else {
-#pragma unroll 8
-            for (int kk = 0; kk < SP_K; ++kk) {
-                const C m = sa[ty][kk], v = sb[kk][tx];
-                ar += m.x * v.x - m.y * v.y;
-                ai += m.x * v.y + m.y * v.x;
-            }
-        }
-    }
-    double nrm = 0.0;
-    const int gy = y0 + ty, gx = x0 + tx;
-    if (gy < ny && gx < nx) {
-        const int64_t q = (int64_t)gy * nx + gx;
-        const C uq = u[q];
-        const T kk = k2[q];
-        T vr = ar + kk * uq.x, vi = ai + kk * uq.y;
-        if (RESID) {
-            vr = b[q].x - vr;
-            vi = b[q].y - vi;
-            nrm = (double)vr * vr + (double)vi * vi;
-        }
-        y[q] = C{vr, vi};
-    }
-    if (RESID) {
-        __shared__ double red[4];
-        double t = nrm;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
-        __syncthreads();
-        if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-    }
-}
-
-constexpr int SP_B = 32;    // tile edge of the register-tiled form for large grids
-
-// Large grids: one 32 x 32 tile per block, 2 x 2 outputs per thread (each LDS value feeds two
-// products), the same chunk sequence and prefetch as k_spectral and the same summation order.
-template <typename C, bool ADJ, bool RESID>
-__global__ __launch_bounds__(256) void k_spectral_big(const C* __restrict__ u, C* __restrict__ y,
-                                                      const C* __restrict__ b, const C* __restrict__ Mx,
-                                                      const C* __restrict__ My,
-                                                      const decltype(C{}.x)* __restrict__ k2, int nx, int ny,
-                                                      double* __restrict__ part, const int* __restrict__ skip) {
-    using T = decltype(C{}.x);
-    if (skip && *skip) return;
-    __shared__ C sa[SP_B][SP_B + 1];
-    __shared__ C sb[SP_B][SP_B + 1];
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int x0 = blockIdx.x * SP_B, y0 = blockIdx.y * SP_B;
-    T ar[2][2], ai[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) ar[a][c] = ai[a][c] = T(0);
-    auto mat = [&](const C* M, int n, int r, int k) -> C {   // M'[r][k]
-        if (ADJ) {
-            const C v = M[(int64_t)k * n + r];
-            return C{v.x, -v.y};
-        }
-        return M[(int64_t)r * n + k];
-    };
-    constexpr int PER = SP_B * SP_B / 256;
-    const int ncx = (nx + SP_B - 1) / SP_B, ncy = (ny + SP_B - 1) / SP_B;
-    const int nch = ncx + ncy;
-    C ra[PER], rb[PER];
-    auto gload = [&](int ch) {
-        const bool xp = ch < ncx;
-        const int k0 = (xp ? ch : ch - ncx) * SP_B;
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int e = threadIdx.x + 256 * i;
-            const int r = e / SP_B, kk = e % SP_B;
-            if (xp) {
-                const int gy = y0 + r, gx = x0 + r, gk = k0 + kk;
-                ra[i] = (gy < ny && gk < nx) ? u[(int64_t)gy * nx + gk] : C{0, 0};
-                rb[i] = (gx < nx && gk < nx) ? mat(Mx, nx, gx, gk) : C{0, 0};
-            } else {
+        for (int i = 0; i < 2; ++i) {
+            const int e = threadIdx.x + SPW * i;          // 0 .. 1023
+            const int pp = e >> 9, f = e & 511;           // part, element of the 32 x 16 / 16 x 32 tile
+            if (pp == 0) {
+                // x part: a = u[y0 + r][k0 + kk] (k fastest); b = Mx'[x0 + c][k0 + kk]
+                const int r = f / SPK, kk = f % SPK;
                 const int gy = y0 + r, gk = k0 + kk;
-                ra[i] = (gy < ny && gk < ny) ? mat(My, ny, gy, gk) : C{0, 0};
-                const int gk2 = k0 + r, gx = x0 + kk;
-                rb[i] = (gk2 < ny && gx < nx) ? u[(int64_t)gk2 * nx + gx] : C{0, 0};
+                ra[i][0] = (gy < ny && gk < nx) ? u[(int64_t)gy * nx + gk] : C{0, 0};
+                if (ADJ) {   // conj(Mx[k][x]): x fastest
+                    const int kr = f / SPT, c = f % SPT;
+                    const int gx = x0 + c, gk2 = k0 + kr;
+                    const C v = (gx < nx && gk2 < nx) ? Mx[(int64_t)gk2 * nx + gx] : C{0, 0};
+                    rb[i][0] = C{v.x, -v.y};
+                } else {     // Mx[x][k]: k fastest
+                    const int c = f / SPK, kk2 = f % SPK;
+                    const int gx = x0 + c, gk2 = k0 + kk2;
+                    rb[i][0] = (gx < nx && gk2 < nx) ? Mx[(int64_t)gx * nx + gk2] : C{0, 0};
+                }
+            } else {
+                // y part: a = My'[y0 + r][k0 + kk]; b = u[k0 + kk][x0 + c] (x fastest)
+                if (ADJ) {   // conj(My[k][y]): y fastest
+                    const int kk = f / SPT, r = f % SPT;
+                    const int gy = y0 + r, gk = k0 + kk;
+                    const C v = (gy < ny && gk < ny) ? My[(int64_t)gk * ny + gy] : C{0, 0};
+                    ra[i][1] = C{v.x, -v.y};
+                } else {     // My[y][k]: k fastest
+                    const int r = f / SPK, kk = f % SPK;
+                    const int gy = y0 + r, gk = k0 + kk;
+                    ra[i][1] = (gy < ny && gk < ny) ? My[(int64_t)gy * ny + gk] : C{0, 0};
+                }
+                const int kr = f / SPT, c = f % SPT;
+                const int gk2 = k0 + kr, gx = x0 + c;
+                rb[i][1] = (gk2 < ny && gx < nx) ? u[(int64_t)gk2 * nx + gx] : C{0, 0};
             }
         }
     };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int e = threadIdx.x + SPW * i;
+            const int pp = e >> 9, f = e & 511;
+            if (pp == 0) {
+                const int r = f / SPK, kk = f % SPK;
+                sa[0][0][r][kk] = ra[i][0].x;
+                sa[0][1][r][kk] = ra[i][0].y;
+                int kr, c;
+                if (ADJ) { kr = f / SPT; c = f % SPT; } else { c = f / SPK; kr = f % SPK; }
+                sb[0][0][kr][c] = rb[i][0].x;
+                sb[0][1][kr][c] = rb[i][0].y;
+            } else {
+                int r, kk;
+                if (ADJ) { kk = f / SPT; r = f % SPT; } else { r = f / SPK; kk = f % SPK; }
+                sa[1][0][r][kk] = ra[i][1].x;
+                sa[1][1][r][kk] = ra[i][1].y;
+                const int kr = f / SPT, c = f % SPT;
+                sb[1][0][kr][c] = rb[i][1].x;
+                sb[1][1][kr][c] = rb[i][1].y;
+            }
+        }
+    };
+    V are, aim;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) are[r] = aim[r] = T(0);
+    const int ar0 = 16 * (q >> 1), bc0 = 16 * (q & 1);
     gload(0);
     for (int ch = 0; ch < nch; ++ch) {
         __syncthreads();
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int e = threadIdx.x + 256 * i;
-            sa[e / SP_B][e % SP_B] = ra[i];
-            sb[e / SP_B][e % SP_B] = rb[i];
-        }
+        lstore();
         __syncthreads();
         if (ch + 1 < nch) gload(ch + 1);
-        if (ch < ncx) {
-#pragma unroll 8
-            for (int kk = 0; kk < SP_B; ++kk) {
-                const C uu[2] = {sa[ty][kk], sa[ty + 16][kk]};
-                const C mm[2] = {sb[tx][kk], sb[tx + 16][kk]};
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        ar[a][c] += uu[a].x * mm[c].x - uu[a].y * mm[c].y;
-                        ai[a][c] += uu[a].x * mm[c].y + uu[a].y * mm[c].x;
-                    }
-            }
-        } else {
-#pragma unroll 8
-            for (int kk = 0; kk < SP_B; ++kk) {
-                const C mm[2] = {sa[ty][kk], sa[ty + 16][kk]};
-                const C vv[2] = {sb[kk][tx], sb[kk][tx + 16]};
-#pragma unroll
-                for (int a = 0; a < 2; ++a)
-#pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-                        ar[a][c] += mm[a].x * vv[c].x - mm[a].y * vv[c].y;
-                        ai[a][c] += mm[a].x * vv[c].y + mm[a].y * vv[c].x;
-                    }
-            }
+        for (int st = 0; st < SPK / 4; ++st) {
+            const int kk = 4 * st + lg;
+            const T a_re = sa[prt][0][ar0 + lr][kk], a_im = sa[prt][1][ar0 + lr][kk];
+            const T b_re = sb[prt][0][kk][bc0 + lr], b_im = sb[prt][1][kk][bc0 + lr];
+            are = M::mma(a_re, b_re, are);
+            are = M::mma(-a_im, b_im, are);
+            aim = M::mma(a_re, b_im, aim);
+            aim = M::mma(a_im, b_re, aim);
         }
     }
+    // y part into LDS, then the x-part wavefronts add it and finish
+    if (prt == 1) {
+        sy[q][0][lane] = are;
+        sy[q][1][lane] = aim;
+    }
+    __syncthreads();
     double nrm = 0.0;
+    if (prt == 0) {
+        const V yre = sy[q][0][lane], yim = sy[q][1][lane];
+        const int gx = x0 + bc0 + lr;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int gy = y0 + ty + 16 * a, gx = x0 + tx + 16 * c;
+        for (int r = 0; r < 4; ++r) {
+            const int gy = y0 + ar0 + M::row_of(lg, r);
             if (gy < ny && gx < nx) {
-                const int64_t q = (int64_t)gy * nx + gx;
-                const C uq = u[q];
-                const T kk = k2[q];
-                T vr = ar[a][c] + kk * uq.x, vi = ai[a][c] + kk * uq.y;
+                const int64_t idx = (int64_t)gy * nx + gx;
+                const C uq = u[idx];
+                const T kq = k2[idx];
+                T vr = (are[r] + yre[r]) + kq * uq.x, vi = (aim[r] + yim[r]) + kq * uq.y;
                 if (RESID) {
-                    vr = b[q].x - vr;
-                    vi = b[q].y - vi;
+                    vr = b[idx].x - vr;
+                    vi = b[idx].y - vi;
                     nrm += (double)vr * vr + (double)vi * vi;
                 }
-                y[q] = C{vr, vi};
+                y[idx] = C{vr, vi};
             }
         }
+    }
     if (RESID) {
-        __shared__ double red[4];
+        __shared__ double red[SPW / 64];
         double t = nrm;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+        if (lane == 0) red[wv] = t;
         __syncthreads();
-        if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+        if (threadIdx.x == 0) {
+            double acc = 0.0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) acc += red[w];   // the x-part wavefronts hold the values
+            part[blockIdx.y * gridDim.x + blockIdx.x] = acc;
+        }
     }
-}
-
-// the register-tiled form once the small tiles would exceed about 4 blocks per CU
-static bool spectral_big(const hz_problem* p) {
-    return (int64_t)((p->nxt + SP_K - 1) / SP_K) * ((p->nyt + SP_Y - 1) / SP_Y) > 1024;
 }
 
 static dim3 spectral_grid(const hz_problem* p) {
-    if (spectral_big(p)) return dim3((p->nxt + SP_B - 1) / SP_B, (p->nyt + SP_B - 1) / SP_B);
-    return dim3((p->nxt + SP_K - 1) / SP_K, (p->nyt + SP_Y - 1) / SP_Y);
+    return dim3((p->nxt + SPT - 1) / SPT, (p->nyt + SPT - 1) / SPT);
 }
 
 int spectral_blocks(const hz_problem* p) {
@@ -315,15 +264,9 @@ int spectral_setup(hz_problem* p, hipStream_t s) {
 int launch_spectral(const hz_problem* p, bool fp64, bool adjoint, const void* x, void* y, hipStream_t s,
                     const int* skip) {
     const dim3 grid = spectral_grid(p);
-#define HZ_SP(C, A, MX, MY, K2)                                                                                \
-    if (spectral_big(p))                                                                                       \
-        hipLaunchKernelGGL((k_spectral_big<C, A, false>), grid, dim3(256), 0, s, (const C*)x, (C*)y,             \
-                           (const C*)nullptr, (const C*)MX, (const C*)MY, K2, p->nxt, p->nyt, (double*)nullptr, \
-                           skip);                                                                              \
-    else                                                                                                       \
-        hipLaunchKernelGGL((k_spectral<C, A, false>), grid, dim3(256), 0, s, (const C*)x, (C*)y,                 \
-                           (const C*)nullptr, (const C*)MX, (const C*)MY, K2, p->nxt, p->nyt, (double*)nullptr, \
-                           skip)
+#define HZ_SP(C, A, MX, MY, K2)                                                                                  \
+    hipLaunchKernelGGL((k_spectral<C, A, false>), grid, dim3(SPW), 0, s, (const C*)x, (C*)y, (const C*)nullptr, \
+                       (const C*)MX, (const C*)MY, K2, p->nxt, p->nyt, (double*)nullptr, skip)
     if (fp64) {
         if (adjoint) HZ_SP(double2, true, p->Mx_d, p->My_d, p->k2d);
         else HZ_SP(double2, false, p->Mx_d, p->My_d, p->k2d);
@@ -338,12 +281,8 @@ int launch_spectral(const hz_problem* p, bool fp64, bool adjoint, const void* x,
 
 int launch_spectral_resid64(const hz_problem* p, const double2* b, const double2* x, double2* r, double* part,
                             const int* skip, hipStream_t s) {
-    if (spectral_big(p))
-        hipLaunchKernelGGL((k_spectral_big<double2, false, true>), spectral_grid(p), dim3(256), 0, s, x, r, b,
-                           (const double2*)p->Mx_d, (const double2*)p->My_d, p->k2d, p->nxt, p->nyt, part, skip);
-    else
-        hipLaunchKernelGGL((k_spectral<double2, false, true>), spectral_grid(p), dim3(256), 0, s, x, r, b,
-                           (const double2*)p->Mx_d, (const double2*)p->My_d, p->k2d, p->nxt, p->nyt, part, skip);
+    hipLaunchKernelGGL((k_spectral<double2, false, true>), spectral_grid(p), dim3(SPW), 0, s, x, r, b,
+                       (const double2*)p->Mx_d, (const double2*)p->My_d, p->k2d, p->nxt, p->nyt, part, skip);
     HZ_LAUNCH_CHECK();
     return HZ_OK;
 }
