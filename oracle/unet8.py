@@ -255,9 +255,13 @@ def precond_apply(theta, specs, p: hz.Problem, v, dtype=np.float64, act_round=No
     return s * (out[0, 0, :p.ny, :p.nx].astype(np.float64) + 1j * out[0, 1, :p.ny, :p.nx].astype(np.float64))
 
 
-def loss_and_grad(theta, specs, problems, rs, squared=False, dtype=np.float64, need_grad=True):
+def loss_and_grad(theta, specs, problems, rs, squared=False, dtype=np.float64, need_grad=True, ops=None):
     """Batch-mean physics-informed loss (eq. (12); unsquared unless squared) and its gradient with
-    respect to theta for this network; problems share one grid size, rs [B, ny, nx] complex."""
+    respect to theta for this network; problems share one grid size, rs [B, ny, nx] complex.
+    ops: the operator module (op_apply, op_adjoint): helmholtz (the default, the finite-difference
+    stencil) or spectral (the Fourier-differentiation form of Section 2.1).
+    """
+    ops = hz if ops is None else ops
     B = len(problems)
     in_ch = specs[0][2]
     depth = sum(1 for s in specs if s[1] == "down")
@@ -269,7 +273,7 @@ def loss_and_grad(theta, specs, problems, rs, squared=False, dtype=np.float64, n
     for b in range(B):
         p = problems[b]
         z = ss[b] * (out[b, 0, :p.ny, :p.nx].astype(np.float64) + 1j * out[b, 1, :p.ny, :p.nx].astype(np.float64))
-        q = hz.op_apply(p, z) - rs[b]
+        q = ops.op_apply(p, z) - rs[b]
         nq, nr = np.linalg.norm(q), np.linalg.norm(rs[b])
         if squared:
             losses[b] = nq * nq / (nr * nr)
@@ -277,7 +281,7 @@ def loss_and_grad(theta, specs, problems, rs, squared=False, dtype=np.float64, n
         else:
             losses[b] = nq / nr
             gq = q / (B * nq * nr) if nq > 0 else np.zeros_like(q)
-        gz = hz.op_adjoint(p, gq)
+        gz = ops.op_adjoint(p, gq)
         gout[b, 0, :p.ny, :p.nx] = ss[b] * gz.real
         gout[b, 1, :p.ny, :p.nx] = ss[b] * gz.imag
     loss = float(losses.mean())

@@ -52,6 +52,9 @@ int spectral_setup(hz_problem* p, hipStream_t s);
 int spectral_blocks(const hz_problem* p);
 int launch_spectral(const hz_problem* p, bool fp64, bool adjoint, const void* x, void* y, hipStream_t s,
                     const int* skip = nullptr);
+// FP32 form of the residual with partials (the training loss on the spectral operator)
+int launch_spectral_resid32(const hz_problem* p, const float2* b, const float2* x, float2* r, double* part,
+                            const int* skip, hipStream_t s);
 int launch_spectral_resid64(const hz_problem* p, const double2* b, const double2* x, double2* r, double* part,
                             const int* skip, hipStream_t s);
 // y = b - A x in FP32 (float2 [n]) with one ||y||^2 partial (FP64) per block.

@@ -279,6 +279,14 @@ int launch_spectral(const hz_problem* p, bool fp64, bool adjoint, const void* x,
     return HZ_OK;
 }
 
+int launch_spectral_resid32(const hz_problem* p, const float2* b, const float2* x, float2* r, double* part,
+                            const int* skip, hipStream_t s) {
+    hipLaunchKernelGGL((k_spectral<float2, false, true>), spectral_grid(p), dim3(SPW), 0, s, x, r, b,
+                       (const float2*)p->Mx_f, (const float2*)p->My_f, p->k2f, p->nxt, p->nyt, part, skip);
+    HZ_LAUNCH_CHECK();
+    return HZ_OK;
+}
+
 int launch_spectral_resid64(const hz_problem* p, const double2* b, const double2* x, double2* r, double* part,
                             const int* skip, hipStream_t s) {
     hipLaunchKernelGGL((k_spectral<double2, false, true>), spectral_grid(p), dim3(SPW), 0, s, x, r, b,

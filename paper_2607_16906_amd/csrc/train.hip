@@ -1047,6 +1047,32 @@ __global__ __launch_bounds__(ST_THREADS) void k_adjoint_batched(const float2* __
                                   blockIdx.x * ST_TX, blockIdx.y * ST_TY);
 }
 
+// y_b = r_b - A_b z_b with ||y_b||^2 partials (stencil_blocks of them per sample) and, with grad,
+// g_b = A_b^H y_b, for a batch on one grid: the finite-difference stencil in one launch per
+// pass, or the Fourier-differentiation operator (Section 2.1) one sample at a time.
+static int batch_resid_adjoint(int B, const hz_problem* const* probs, const float2* z, const float2* r, float2* y,
+                               float2* gz, double* ypart, const SampleProb* sprob, bool grad, hipStream_t s) {
+    const hz_problem* p0 = probs[0];
+    const int64_t n = p0->n;
+    if (is_spectral(p0)) {
+        const int nst = stencil_blocks(p0);
+        for (int b = 0; b < B; ++b)
+            HZ_TRY(launch_spectral_resid32(probs[b], r + b * n, z + b * n, y + b * n, ypart + (int64_t)b * nst,
+                                           nullptr, s));
+        if (grad)
+            for (int b = 0; b < B; ++b) HZ_TRY(launch_spectral(probs[b], false, true, y + b * n, gz + b * n, s, nullptr));
+        return HZ_OK;
+    }
+    const dim3 g((p0->nxt + ST_TX - 1) / ST_TX, (p0->nyt + ST_TY - 1) / ST_TY, B);
+    hipLaunchKernelGGL(k_resid_batched, g, dim3(ST_THREADS), 0, s, z, r, y, n, sprob, p0->nxt, p0->nyt, ypart);
+    HZ_LAUNCH_CHECK();
+    if (grad) {
+        hipLaunchKernelGGL(k_adjoint_batched, g, dim3(ST_THREADS), 0, s, y, gz, n, sprob, p0->nxt, p0->nyt);
+        HZ_LAUNCH_CHECK();
+    }
+    return HZ_OK;
+}
+
 // ------------------------------------------------------------------ loss + backward
 
 template <class P>
@@ -1100,17 +1126,7 @@ static int loss_backward_impl(const no_net* net, int B, const hz_problem* const*
     }
     // y_b = r_b - A_b z_b with ||y_b||^2 partials, then A_b^H y_b
     const int nst = stencil_blocks(p0);
-    {
-        const dim3 g((p0->nxt + ST_TX - 1) / ST_TX, (p0->nyt + ST_TY - 1) / ST_TY, B);
-        hipLaunchKernelGGL(k_resid_batched, g, dim3(ST_THREADS), 0, s, t.z, r, t.y, n, t.sprob, p0->nxt, p0->nyt,
-                           t.ypart);
-        HZ_LAUNCH_CHECK();
-        if (grad) {
-            hipLaunchKernelGGL(k_adjoint_batched, g, dim3(ST_THREADS), 0, s, t.y, t.gz, n, t.sprob, p0->nxt,
-                               p0->nyt);
-            HZ_LAUNCH_CHECK();
-        }
-    }
+    HZ_TRY(batch_resid_adjoint(B, probs, t.z, r, t.y, t.gz, t.ypart, t.sprob, grad != nullptr, s));
     hipLaunchKernelGGL(k_loss, dim3(1), dim3(1024), 0, s, t.ypart, nst, t.nr, B, squared, t.coef, loss, per_sample);
     HZ_LAUNCH_CHECK();
     if (!grad) return HZ_OK;  // loss only (validation): no reverse pass
@@ -1526,17 +1542,7 @@ int loss_backward8(const no_net* net, int B, const hz_problem* const* probs, con
         HZ_LAUNCH_CHECK();
     }
     const int nst = stencil_blocks(p0);
-    {
-        const dim3 g((p0->nxt + ST_TX - 1) / ST_TX, (p0->nyt + ST_TY - 1) / ST_TY, B);
-        hipLaunchKernelGGL(k_resid_batched, g, dim3(ST_THREADS), 0, s, t.z, r, t.y, n, t.sprob, p0->nxt, p0->nyt,
-                           t.ypart);
-        HZ_LAUNCH_CHECK();
-        if (grad) {
-            hipLaunchKernelGGL(k_adjoint_batched, g, dim3(ST_THREADS), 0, s, t.y, t.gz, n, t.sprob, p0->nxt,
-                               p0->nyt);
-            HZ_LAUNCH_CHECK();
-        }
-    }
+    HZ_TRY(batch_resid_adjoint(B, probs, t.z, r, t.y, t.gz, t.ypart, t.sprob, grad != nullptr, s));
     hipLaunchKernelGGL(k_loss, dim3(1), dim3(1024), 0, s, t.ypart, nst, t.nr, B, squared, t.coef, loss, per_sample);
     HZ_LAUNCH_CHECK();
     if (!grad) return HZ_OK;
@@ -1662,7 +1668,8 @@ extern "C" int no_loss_backward(const no_net* net, int batch, const hz_problem* 
         HZ_CHECK_ARG(problems[b]->nxt == problems[0]->nxt && problems[b]->nyt == problems[0]->nyt &&
                          problems[b]->g.npml == problems[0]->g.npml,
                      "no_loss_backward: every problem of a batch must have the same grid and PML");
-        HZ_CHECK_ARG(!is_spectral(problems[b]), "no_loss_backward: finite-difference problems only");
+        HZ_CHECK_ARG(is_spectral(problems[b]) == is_spectral(problems[0]),
+                     "no_loss_backward: every problem of a batch must have the same discretization");
     }
     hipStream_t s = (hipStream_t)stream;
     if (net->a.kind == NO_ARCH_PAPER8)

@@ -158,22 +158,23 @@ class Trainer:
         return res
 
 
-def resident_set(c, b, nint: int, npml: int, h: float):
+def resident_set(c, b, nint: int, npml: int, h: float, disc: str = "fd"):
     """Upload a data set: velocities c [S, nt, nt] (m/s) and sources b [S, nt, nt] (complex) to one
-    hz.Problem per sample and one [S, n] complex64 device tensor."""
+    hz.Problem per sample (discretization disc: "fd" or "spectral") and one [S, n] complex64
+    device tensor."""
     torch = hz._torch()
-    probs = [hz.Problem(ci.astype(np.float32).ravel(), nint, nint, npml, h) for ci in c]
+    probs = [hz.Problem(ci.astype(np.float32).ravel(), nint, nint, npml, h, disc=disc) for ci in c]
     r = torch.from_numpy(np.ascontiguousarray(b.reshape(len(b), -1)).astype(np.complex64)).to("cuda")
     return probs, r
 
 
 def save_weights(path, theta, *, levels, base, in_ch, dataset, nint, npml, epochs, best_epoch, best_val, steps,
-                 bf16=False, arch="unet3"):
+                 bf16=False, arch="unet3", disc="fd"):
     """Write a parameter file: float32 theta (or, bf16=True, its BF16 rounding as 16-bit patterns,
     half the size, for networks that only run with BF16 operands) and the training record."""
     th = np.asarray(theta, np.float32)
     rec = dict(levels=levels, base=base, in_ch=in_ch, dataset=dataset, nint=nint, npml=npml, epochs=epochs,
-               best_epoch=best_epoch, best_val=best_val, step=steps, arch=arch)
+               best_epoch=best_epoch, best_val=best_val, step=steps, arch=arch, disc=disc)
     if bf16:
         u = th.view(np.uint32).astype(np.uint64)
         u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
@@ -210,7 +211,7 @@ def main():
 
     Usage: python -m paper_2607_16906_amd.train --out FILE [--arch unet3] [--dataset D0] [--levels 5]
            [--base 32] [--nint 128] [--npml 16] [--count 4096] [--val 256] [--epochs 24] [--batch 32]
-           [--prec fp32] [--bf16-file]
+           [--prec fp32] [--bf16-file] [--disc fd|spectral]
     """
     import argparse
     import time
@@ -235,6 +236,8 @@ def main():
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--bf16-file", action="store_true", help="store the BF16 rounding of the weights")
+    ap.add_argument("--disc", default="fd", choices=["fd", "spectral"],
+                    help="operator of the loss: finite differences or Fourier differentiation (Section 2.1)")
     a = ap.parse_args()
     if a.arch == "paper8" and a.prec != "fp32":
         ap.error("the paper8 network trains in FP32")
@@ -247,8 +250,8 @@ def main():
     else:
         c, b = table4_set(a.dataset, a.count, nt, a.npml)
         cv, bv = table4_set(a.dataset, a.val, nt, a.npml, first=VAL_FIRST)
-    probs, r = resident_set(c, b, a.nint, a.npml, H_10PPW)
-    vprobs, vr = resident_set(cv, bv, a.nint, a.npml, H_10PPW)
+    probs, r = resident_set(c, b, a.nint, a.npml, H_10PPW, a.disc)
+    vprobs, vr = resident_set(cv, bv, a.nint, a.npml, H_10PPW, a.disc)
     print(f"data set {a.dataset}: {a.count} + {a.val} samples on {nt}^2 in {time.time() - t0:.1f} s", flush=True)
     if a.arch == "paper8":
         theta0 = init_theta_paper8(a.levels, a.base, 5, rng_for(CFG_TABLE4, COMP_WEIGHTS, 100 + a.levels))
@@ -263,7 +266,7 @@ def main():
           flush=True)
     save_weights(a.out, res.theta_best.cpu().numpy(), levels=a.levels, base=a.base, in_ch=5, dataset=a.dataset,
                  nint=a.nint, npml=a.npml, epochs=a.epochs, best_epoch=res.best_epoch, best_val=res.best_val,
-                 steps=steps, bf16=a.bf16_file, arch=a.arch)
+                 steps=steps, bf16=a.bf16_file, arch=a.arch, disc=a.disc)
 
 
 if __name__ == "__main__":

@@ -1,7 +1,7 @@
 """GPU parity of the Fourier-differentiation operator (the paper's discretization) against the
 oracle's FFT form: FP64 and FP32 forward and adjoint applies on even and odd grids with ragged
-tiles, the full single-solve size, FP64 GMRES / FGMRES histories on it, and the paths that take
-the finite-difference operator only."""
+tiles, the full single-solve size, FP64 GMRES / FGMRES histories on it, the training loss and its
+gradient through this operator, and the paths that take the finite-difference operator only."""
 import os
 
 import numpy as np
@@ -108,9 +108,58 @@ def test_spectral_rejected_where_unsupported():
         net = hz.Net(4, 32, 5, theta)
         with pytest.raises(hz.HzError):
             hz.fgmres(gp, b, net=net, m=5, tol=1e-6, maxit=10, ortho="dcgs2")
+        # one batch holds one discretization
+        from gpu_util import make_pair
+        _, gfd = make_pair(c, p)
         with pytest.raises(hz.HzError):
-            hz.loss_backward(net, [gp], to_dev(np.ones(gp.n), torch.complex64), prec="fp32")
+            hz.loss_backward(net, [gp, gfd], to_dev(np.ones((2, gp.n)), torch.complex64), prec="fp32")
     with pytest.raises(hz.HzError):
         hz.fgmres_batched([gp], [b], m=5, tol=1e-6, maxit=10)
     with pytest.raises(KeyError):
         hz.Problem(np.full(20 * 20, 1500.0, np.float32), 20, 20, 0, H_10PPW, disc="bogus")
+
+
+@pytest.mark.parametrize("squared", [False, True])
+def test_spectral_loss_gradient_matches_oracle(squared):
+    # eq. (12) on the Fourier-differentiation operator: FP32 loss, per-sample losses and gradient
+    # (reverse mode through its adjoint and the U-Net) against the oracle's FP64 ones
+    from synth import box_smoothed_noise, he_uniform
+    from paper_2607_16906_amd import hz
+    nt, p, B = 32, 4, 2
+    pairs = [spectral_pair(skull_ring_velocity(nt, p, rng_for(33, 0, b), rings=1 + b), p) for b in range(B)]
+    rs = np.stack([box_smoothed_noise(nt, rng_for(33, 3, b)) for b in range(B)])
+    specs = unet.layer_specs(3, 8, 5)
+    theta = he_uniform(unet.init_shapes(specs), rng_for(33, 2, 0))
+    net = hz.Net(3, 8, 5, theta)
+    loss, per, g = hz.loss_backward(net, [gp for _, gp in pairs], to_dev(rs.astype(np.complex64), torch.complex64),
+                                    squared=squared, prec="fp32")
+    rr = rs.astype(np.complex64).astype(np.complex128)
+    rl, rp, rg = unet.loss_and_grad(theta.astype(np.float64), specs, [op for op, _ in pairs], rr, squared=squared,
+                                    ops=osp)
+    loss, per, g = to_np(loss)[0], to_np(per), to_np(g)
+    err = np.linalg.norm(g - rg) / np.linalg.norm(rg)
+    print(f"spectral loss {loss:.6f} (oracle {rl:.6f}), gradient rel err {err:.2e}")
+    assert abs(loss - rl) <= 1e-5 * rl and np.max(np.abs(per - rp) / rp) <= 1e-5
+    assert err <= 1e-4
+
+
+def test_spectral_training_epochs_lower_loss():
+    # the epoch loop trains a network against the Fourier-differentiation operator
+    from synth import he_uniform
+    from paper_2607_16906_amd import hz
+    from paper_2607_16906_amd.train import Trainer
+    nt, p = 32, 4
+    def sys(i):
+        _, gp = spectral_pair(skull_ring_velocity(nt, p, rng_for(34, 0, i), rings=1), p)
+        return gp, gaussian_sources(nt, p, rng_for(34, 1, i))
+    tr_set = [sys(i) for i in range(32)]
+    va_set = [sys(100 + i) for i in range(8)]
+    r = to_dev(np.stack([b for _, b in tr_set]).astype(np.complex64), torch.complex64).reshape(32, -1)
+    vr = to_dev(np.stack([b for _, b in va_set]).astype(np.complex64), torch.complex64).reshape(8, -1)
+    theta = he_uniform(unet.init_shapes(unet.layer_specs(3, 8, 5)), rng_for(34, 2, 0))
+    net = hz.Net(3, 8, 5, theta)
+    tr = Trainer(net, [g for g, _ in tr_set], r, [g for g, _ in va_set], vr, batch=8, prec="fp32")
+    v0 = tr.validation_loss()
+    res = tr.fit(theta, [np.random.default_rng(e).permutation(32) for e in range(6)], lr0=1e-3, lr_min=1e-4)
+    print(f"spectral training: validation loss {v0:.4f} -> {res.best_val:.4f} (epoch {res.best_epoch})")
+    assert np.all(np.isfinite(res.train_loss)) and res.best_val < v0

@@ -189,15 +189,15 @@ def test_precond_scale_equivariance_and_zero():
     assert np.all(unet.precond_apply(theta, specs, P, 0 * v) == 0)
 
 
-def fd_check(specs, theta, problems, rs, squared, ndir=3, eps=1e-6, seed=0):
-    loss, _, g = unet.loss_and_grad(theta, specs, problems, rs, squared=squared)
+def fd_check(specs, theta, problems, rs, squared, ndir=3, eps=1e-6, seed=0, ops=None):
+    loss, _, g = unet.loss_and_grad(theta, specs, problems, rs, squared=squared, ops=ops)
     rng = np.random.default_rng(seed)
     errs = []
     for _ in range(ndir):
         d = rng.standard_normal(theta.size)
         d /= np.linalg.norm(d)
-        lp = unet.loss_and_grad(theta + eps * d, specs, problems, rs, squared=squared, need_grad=False)[0]
-        lm = unet.loss_and_grad(theta - eps * d, specs, problems, rs, squared=squared, need_grad=False)[0]
+        lp = unet.loss_and_grad(theta + eps * d, specs, problems, rs, squared=squared, need_grad=False, ops=ops)[0]
+        lm = unet.loss_and_grad(theta - eps * d, specs, problems, rs, squared=squared, need_grad=False, ops=ops)[0]
         fd = (lp - lm) / (2 * eps)
         an = float(g @ d)
         errs.append(abs(fd - an) / max(abs(an), 1e-12))
@@ -212,6 +212,21 @@ def test_gradient_finite_differences_32grid_8ch(squared):
     problems = [small_problem(s, nx=24, p=4) for s in range(2)]
     rs = np.stack([box_smoothed_noise(32, np.random.default_rng(20 + s)) for s in range(2)])
     assert fd_check(specs, theta, problems, rs, squared) < 1e-6
+
+
+@pytest.mark.parametrize("squared", [False, True])
+def test_gradient_finite_differences_spectral_operator(squared):
+    # the loss on the Fourier-differentiation operator (Section 2.1): its gradient, through that
+    # operator's adjoint, against central differences; and the operator really is the other one
+    from oracle import spectral
+    specs = unet.layer_specs(3, 8, 5)
+    theta = he_uniform(unet.init_shapes(specs), np.random.default_rng(12)).astype(np.float64)
+    problems = [small_problem(s, nx=24, p=4) for s in range(2)]
+    rs = np.stack([box_smoothed_noise(32, np.random.default_rng(30 + s)) for s in range(2)])
+    assert fd_check(specs, theta, problems, rs, squared, ops=spectral) < 1e-6
+    l_fd = unet.loss_and_grad(theta, specs, problems, rs, squared=squared, need_grad=False)[0]
+    l_sp = unet.loss_and_grad(theta, specs, problems, rs, squared=squared, need_grad=False, ops=spectral)[0]
+    assert abs(l_fd - l_sp) > 1e-3 * l_fd
 
 
 def test_gradient_matches_torch_autograd():
