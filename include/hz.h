@@ -244,7 +244,9 @@ size_t no_train_workspace_size(const no_net* net, const hz_problem* p, int batch
 /* Physics-informed loss and its gradient (eq. (10)-(12)) for a batch of residuals:
  * per sample q_b = A_b N(r_b) - r_b and l_b = ||q_b|| / ||r_b|| (squared != 0:
  * ||q_b||^2 / ||r_b||^2); loss = mean_b l_b. Reverse mode through A^H and the
- * U-Net. problems: `batch` handles of one grid size; r_dev: [batch][n] complex64;
+ * U-Net. problems: `batch` handles of one grid size and one discretization (the five-point
+ * stencil, or the Fourier-differentiation operator of Section 2.1 with its adjoint); r_dev:
+ * [batch][n] complex64;
  * loss_dev: 1 float (written); per_sample_dev: `batch` floats or NULL;
  * grad_dev: no_param_count floats (overwritten with d loss / d theta), or NULL to evaluate the
  * loss alone (a validation pass: the forward pass and the residuals, no reverse pass).
