@@ -638,6 +638,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp32-steps", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--large-maxit", type=int, default=12000,
+                    help="with --only large: cap on the large solve's iterations (a bounded run for the profiler)")
     ap.add_argument("--no-extra", action="store_true", help="skip the training and batched sections")
     ap.add_argument("--roofline-variant", default="",
                     help="with --roofline-only: pin the layer's launch variant 'tn,rows[,stages[,tiles]]'")
@@ -677,9 +679,11 @@ def main():
             res = bench_train_then_solve(hz, torch)
         else:
             net1 = hz.Net(LEVELS, BASE, IN_CH, theta)
-            res = {"batched": bench_batched, "large": bench_large, "restart": bench_restart,
-                   "spectral": bench_spectral, "appendix_b": bench_appendix_b,
-                   "paper8": bench_paper8}[args.only](hz, torch, net1)
+            if args.only == "large":
+                res = bench_large(hz, torch, net1, maxit=args.large_maxit)
+            else:
+                res = {"batched": bench_batched, "restart": bench_restart, "spectral": bench_spectral,
+                       "appendix_b": bench_appendix_b, "paper8": bench_paper8}[args.only](hz, torch, net1)
         print(json.dumps({args.only: res}))
         return
     levels = LEVELS
