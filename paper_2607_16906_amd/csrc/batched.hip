@@ -324,6 +324,15 @@ static void layer_levels(const no_net* net, std::vector<int>& lvl, std::vector<i
     lvl.push_back(0); role.push_back(5);           // head
 }
 
+// whether the 1x1 head runs in the epilogue of the last 3x3 layer (a decoder's second layer whose
+// 16, 32 or 64 output channels one block covers)
+static bool head_fused(const no_net* net) {
+    const int nl = (int)net->layers.size();
+    if (net->a.levels < 2 || nl < 2) return false;
+    const int cp = net->layers[nl - 2].cout_p;
+    return (cp == 16 || cp == 32 || cp == 64) && net->layers[nl - 1].cin_p == cp;
+}
+
 template <class P>
 struct BatchPlan {
     std::vector<SysLayout> S;
@@ -466,7 +475,8 @@ static void build_tables(const BatchPlan<P>& B, const no_net* net, const std::ve
             const int H = B.S[s].Hp >> l, W = B.S[s].Wp >> l;
             tiles += convT ? (int64_t)H * ((W + 63) / 64) : (int64_t)((W + 15) / 16) * ((H + 7) / 8);
         }
-        const int tn = convT ? convT2_batch_tn(ly.cout_p) : conv3_batch_tn(ly.cout_p, tiles);
+        const bool fhead = li == nl - 2 && head_fused(net);
+        const int tn = convT ? convT2_batch_tn(ly.cout_p) : fhead ? ly.cout_p : conv3_batch_tn(ly.cout_p, tiles);
         h.tn[li] = tn;
         for (int s = 0; s < nsys; ++s) {
             const FwdBufs& fb = B.S[s].fb;
@@ -482,6 +492,15 @@ static void build_tables(const BatchPlan<P>& B, const no_net* net, const std::ve
                 case 2: io.x0 = l == lv - 1 ? fb.E[l] : fb.D[l]; io.y = fb.U[l - 1]; break;
                 case 3: io.x0 = fb.E[l]; io.x1 = fb.U[l]; io.y = fb.T1d[l]; break;
                 case 4: io.x0 = fb.T1d[l]; io.y = fb.D[l]; break;
+            }
+            if (fhead) {
+                const KDesc& d = B.S[s].d;
+                io.y = nullptr;
+                io.z = d.Z;
+                io.zld = d.n;
+                io.nxt = d.nxt;
+                io.nyt = d.nyt;
+                io.sc = d.sc;
             }
         }
         // channel blocks of one tile are neighbours in the job order (the kernel maps each XCD
@@ -533,10 +552,16 @@ static int net_step(const BatchPlan<P>& B, const HostTables<P>& h, const no_net*
     std::vector<int> lvl, role;
     layer_levels(net, lvl, role);
     const int nl = (int)net->layers.size();
+    const bool fhead = head_fused(net);
+    const Layer& lh = net->layers.back();
     for (int li = 0; li < nl - 1; ++li) {
         const Layer& ly = net->layers[li];
         const int nj = (int)h.cjobs[li].size();
-        if (role[li] == 2) {
+        if (fhead && li == nl - 2) {
+            HZ_TRY(launch_conv3_jobs_head<P>(t.cjobs[li], nj, t.io[li], packed_w<P>(net, ly), packed_b<P>(net, ly),
+                                             ly.cin_p, 0, ly.cout_p, packed_w<P>(net, lh), packed_b<P>(net, lh), col,
+                                             std::is_same<C, double2>::value, s));
+        } else if (role[li] == 2) {
             HZ_TRY(launch_convT2_jobs<P>(t.cjobs[li], nj, t.io[li], packed_w<P>(net, ly), packed_b<P>(net, ly), ly.cin_p,
                                          ly.cout_p, h.tn[li], s));
         } else {
@@ -546,10 +571,11 @@ static int net_step(const BatchPlan<P>& B, const HostTables<P>& h, const no_net*
                                         ly.cin_p - c1, c1, ly.cout_p, h.tn[li], pool, s));
         }
     }
-    const Layer& lh = net->layers.back();
-    hipLaunchKernelGGL((kb_head<P, C>), dim3(nv), dim3(KT), 0, s, t.vjobs, t.kd, col, packed_w<P>(net, lh),
-                       packed_b<P>(net, lh), lh.cin_p);
-    HZ_LAUNCH_CHECK();
+    if (!fhead) {
+        hipLaunchKernelGGL((kb_head<P, C>), dim3(nv), dim3(KT), 0, s, t.vjobs, t.kd, col, packed_w<P>(net, lh),
+                           packed_b<P>(net, lh), lh.cin_p);
+        HZ_LAUNCH_CHECK();
+    }
     return HZ_OK;
 }
 

@@ -785,6 +785,31 @@ __global__ __launch_bounds__(CT) void k_conv3_jobs(const TileJob* __restrict__ j
                                0, jb.c0, jb.ty0, jb.tx0, 0, c0 + c1, nullptr);
 }
 
+// Last 3x3 layer of a ragged batch with the 1x1 head in its epilogue: TN == cout_p, so one
+// block holds every output channel of its pixels; z gets column col of the system's vectors.
+template <class P, int TN>
+__global__ __launch_bounds__(CT) void k_conv3_jobs_head(const TileJob* __restrict__ jobs,
+                                                        const LayerIO* __restrict__ io,
+                                                        const typename P::T* __restrict__ w,
+                                                        const typename P::Acc* __restrict__ bias, int c0, int c1,
+                                                        int ck, const typename P::T* __restrict__ head_w,
+                                                        const typename P::Acc* __restrict__ head_b, int col,
+                                                        int c128) {
+    const TileJob jb = jobs[xcd_linear(blockIdx.x, gridDim.x)];
+    const LayerIO d = io[jb.sys];
+    if (d.stop && *d.stop) return;
+    Conv3Out ex;
+    ex.head_w = head_w;
+    ex.head_b = head_b;
+    ex.head_c128 = c128;
+    ex.head_z = c128 ? (void*)((double2*)d.z + (int64_t)col * d.zld) : (void*)((float2*)d.z + (int64_t)col * d.zld);
+    ex.head_nxt = d.nxt;
+    ex.head_nyt = d.nyt;
+    ex.head_sc = d.sc;
+    conv3_tile<P, TN, false, 2>((const typename P::T*)d.x0, c0, (const typename P::T*)d.x1, c1, w, bias, nullptr,
+                                TN, nullptr, d.H, d.W, 1, ck, ex, 0, 0, jb.ty0, jb.tx0, 0, c0 + c1, nullptr);
+}
+
 // 2x2 stride-2 transposed convolution: a GEMM per input pixel with M = 4 x
 // output channels (tap a, b and channel), N = 16 input pixels per wave, K = input
 // channels. Block: 64 input pixels of one row (4 waves x 16) and TN channels.
@@ -1208,6 +1233,27 @@ int launch_conv3_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const t
 }
 
 template <class P>
+int launch_conv3_jobs_head(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
+                           const typename P::Acc* bias, int c0, int c1, int cout_p, const typename P::T* head_w,
+                           const typename P::Acc* head_b, int col, bool c128, hipStream_t s) {
+    if (njobs <= 0) return HZ_OK;
+    const int ck = chunk_for<P>(c0 + c1, c0, c1);
+#define HZ_C3H(TNV)                                                                                      \
+    hipLaunchKernelGGL((k_conv3_jobs_head<P, TNV>), dim3(njobs), dim3(CT), 0, s, jobs, io, w, bias, c0, c1, ck, \
+                       head_w, head_b, col, c128 ? 1 : 0)
+    if (cout_p == 64) HZ_C3H(64);
+    else if (cout_p == 32) HZ_C3H(32);
+    else if (cout_p == 16) HZ_C3H(16);
+    else {
+        set_error("conv3 jobs: fused head needs 16, 32 or 64 channels");
+        return HZ_ERR_ARG;
+    }
+#undef HZ_C3H
+    HZ_LAUNCH_CHECK();
+    return HZ_OK;
+}
+
+template <class P>
 int launch_convT2_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
                        const typename P::Acc* bias, int cin_p, int cout_p, int tn, hipStream_t s) {
     if (njobs <= 0) return HZ_OK;
@@ -1232,6 +1278,8 @@ int launch_convT2_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const 
                                   const int*, hipStream_t);                                                    \
     template int launch_conv3_jobs<P>(const TileJob*, int, const LayerIO*, const P::T*, const P::Acc*, int, int, \
                                       int, int, bool, hipStream_t);                                            \
+    template int launch_conv3_jobs_head<P>(const TileJob*, int, const LayerIO*, const P::T*, const P::Acc*, int,   \
+                                           int, int, const P::T*, const P::Acc*, int, bool, hipStream_t);       \
     template int launch_convT2_jobs<P>(const TileJob*, int, const LayerIO*, const P::T*, const P::Acc*, int, int, \
                                        int, hipStream_t);                                                      \
     template int conv_chunk<P>(int, int, int);                                                                 \

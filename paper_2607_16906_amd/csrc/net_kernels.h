@@ -104,6 +104,12 @@ struct LayerIO {
     void* ypool;
     int H, W;
     const int* stop;   // the system's stop flag (the block returns when it is set)
+    // fused 1x1 head (last 3x3 layer only): column col of z, i.e. z + col * zld, of nyt x nxt
+    // points, scaled by sc[0]; element type float2 or double2 as the launch says
+    void* z;
+    int64_t zld;
+    int nxt, nyt;
+    const double* sc;
 };
 
 // Optional extras of a 3x3 convolution launch: a split of the output channels into two
@@ -197,6 +203,12 @@ int launch_conv3(const typename P::T* x0, int c0, const typename P::T* x1, int c
 template <class P>
 int launch_conv3_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
                       const typename P::Acc* bias, int c0, int c1, int cout_p, int tn, bool pool, hipStream_t s);
+// The same with the 1x1 output head fused into the epilogue (cout_p 16, 32 or 64, one job per
+// pixel tile): writes column col of each system's z (LayerIO head fields) instead of y.
+template <class P>
+int launch_conv3_jobs_head(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
+                           const typename P::Acc* bias, int c0, int c1, int cout_p, const typename P::T* head_w,
+                           const typename P::Acc* head_b, int col, bool c128, hipStream_t s);
 template <class P>
 int launch_convT2_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
                        const typename P::Acc* bias, int cin_p, int cout_p, int tn, hipStream_t s);
