@@ -402,13 +402,25 @@ def bench_batched(hz, torch, net, nsys=128, maxit=MAXIT):
     steps = max(i.its for i in infos)
     its = np.array([i.its for i in infos])
     conv = sum(1 for i in infos if i.status == 0 and i.true_relres <= TOL)
+    # lower bound on the whole solve: every system's network FLOPs at the BF16 matrix peak plus its
+    # algorithmic Krylov bytes (52n + 16nj at step j of a cycle) at the HBM peak
+    q = 1 << (LEVELS - 1)
+    net_fl = kry_b = 0.0
+    for inf, p, (nx, pml) in zip(infos, probs, sizes):
+        Hp = (nx + 2 * pml + q - 1) // q * q
+        fl = sum(layer_flops(kind, ci, co, H, W) for (_, kind, ci, co, H, W) in net_layers(LEVELS, BASE, IN_CH, Hp, Hp))
+        net_fl += inf.its * (fl + 2.0 * Hp * Hp * 2 * BASE)
+        kry_b += sum(52.0 * p.n + 16.0 * p.n * (k % M_RESTART) for k in range(inf.its))
+    bound_s = net_fl / (PEAK_BF16_TFLOPS * 1e12) + kry_b / (PEAK_HBM_GBS * 1e9)
     return {"workload": f"{nsys} systems of the batched-serving mix, BF16 U-Net, FP32 Krylov, FGMRES(30), tol 1e-6",
             "nodes_total": int(sum(p.n for p in probs)), "seconds": round(dt, 3),
             "converged": conv, "solves_per_s": round(conv / dt, 3),
             "its_min_median_max": [int(its.min()), int(np.median(its)), int(its.max())],
             "ms_per_step": round(dt / steps * 1e3, 2),
             "node_iterations_per_s": round(node_its / dt, 1),
-            "max_true_relres": max(i.true_relres for i in infos)}
+            "max_true_relres": max(i.true_relres for i in infos),
+            "network_tflop": round(net_fl * 1e-12, 2), "krylov_algorithmic_gb": round(kry_b * 1e-9, 1),
+            "bound_s": round(bound_s, 3), "combined_frac": round(bound_s / dt, 4)}
 
 
 def bench_spectral(hz, torch, net):

@@ -436,8 +436,39 @@ struct HostTables {
     std::vector<TileJob> vjobs, stjobs, pjobs;
     std::vector<std::vector<LayerIO>> io;
     std::vector<std::vector<TileJob>> cjobs;
-    std::vector<int> tn;
+    std::vector<int> tn, rpw;
+    std::vector<char> ws;   // 3x3 layer in the weight-stationary form
 };
+
+// Launch form of a 3x3 layer over a ragged batch with `tiles` 16 x 16 pixel tiles in all: in BF16
+// the weight-stationary form with 32-channel blocks where it applies (layers of at most two input
+// chunks), with enough tiles per block to pipeline them and enough blocks to fill the GPU, else
+// 16 x 16 tiles with 32-channel blocks; FP32 / FP64 keep 8 x 16 tiles (conv3_batch_tn).
+template <class P>
+static void batch_conv3_form(const Layer& ly, int c1, int64_t tiles16, int64_t tiles8, bool head, int& tn, int& rpw,
+                             int& tpb) {
+    tpb = 0;
+    if (std::is_same<P, PolBF16>::value && ly.cout_p % 32 == 0) {
+        const int64_t ncb = ly.cout_p / WSJ_TN;
+        if (ws_jobs_ok<P>(ly.cin_p - c1, c1, ly.cout_p) && (!head || ly.cout_p == WSJ_TN)) {
+            int t = 32;
+            while (t > 4 && (tiles16 + t - 1) / t * ncb < 1024) t /= 2;
+            if ((tiles16 + t - 1) / t * ncb >= 256) {
+                tn = WSJ_TN;
+                rpw = WSJ_RPW;
+                tpb = t;
+                return;
+            }
+        }
+        if (!head && tiles16 * (ly.cout_p / 32) >= 512) {
+            tn = 32;
+            rpw = 4;
+            return;
+        }
+    }
+    tn = head ? ly.cout_p : conv3_batch_tn(ly.cout_p, tiles8);
+    rpw = 2;
+}
 
 template <class P>
 static void build_tables(const BatchPlan<P>& B, const no_net* net, const std::vector<int>& active, HostTables<P>& h) {
@@ -466,18 +497,25 @@ static void build_tables(const BatchPlan<P>& B, const no_net* net, const std::ve
     h.io.assign(nl, std::vector<LayerIO>(nsys));
     h.cjobs.assign(nl, {});
     h.tn.assign(nl, 16);
+    h.rpw.assign(nl, 2);
+    h.ws.assign(nl, 0);
     for (int li = 0; li < nl - 1; ++li) {
         const Layer& ly = net->layers[li];
         const int l = lvl[li];
         const bool convT = role[li] == 2;
-        int64_t tiles = 0;
+        int64_t tiles = 0, tiles16 = 0;
         for (int s : active) {
             const int H = B.S[s].Hp >> l, W = B.S[s].Wp >> l;
             tiles += convT ? (int64_t)H * ((W + 63) / 64) : (int64_t)((W + 15) / 16) * ((H + 7) / 8);
+            tiles16 += (int64_t)((W + 15) / 16) * ((H + 15) / 16);
         }
         const bool fhead = li == nl - 2 && head_fused(net);
-        const int tn = convT ? convT2_batch_tn(ly.cout_p) : fhead ? ly.cout_p : conv3_batch_tn(ly.cout_p, tiles);
+        int tn = 16, rpw = 2, tpb = 0;
+        if (convT) tn = convT2_batch_tn(ly.cout_p);
+        else batch_conv3_form<P>(ly, ly.cat_cp ? ly.cin_p - ly.cat_cp : 0, tiles16, tiles, fhead, tn, rpw, tpb);
         h.tn[li] = tn;
+        h.rpw[li] = rpw;
+        h.ws[li] = tpb > 0;
         for (int s = 0; s < nsys; ++s) {
             const FwdBufs& fb = B.S[s].fb;
             LayerIO& io = h.io[li][s];
@@ -511,8 +549,13 @@ static void build_tables(const BatchPlan<P>& B, const no_net* net, const std::ve
                 for (int iy = 0; iy < H; ++iy)
                     for (int ix = 0; ix < W; ix += 64)
                         for (int co = 0; co < ly.cout_p; co += tn) h.cjobs[li].push_back(TileJob{s, co, iy, ix});
+            } else if (tpb > 0) {   // (sys, first channel, first tile, end tile), tiles of 4 rpw x 16
+                const int nt = ((W + 15) / 16) * ((H + 4 * rpw - 1) / (4 * rpw));
+                for (int t0 = 0; t0 < nt; t0 += tpb)
+                    for (int co = 0; co < ly.cout_p; co += tn)
+                        h.cjobs[li].push_back(TileJob{s, co, t0, std::min(nt, t0 + tpb)});
             } else {
-                for (int ty = 0; ty < H; ty += 8)
+                for (int ty = 0; ty < H; ty += 4 * rpw)
                     for (int tx = 0; tx < W; tx += 16)
                         for (int co = 0; co < ly.cout_p; co += tn) h.cjobs[li].push_back(TileJob{s, co, ty, tx});
             }
@@ -557,7 +600,15 @@ static int net_step(const BatchPlan<P>& B, const HostTables<P>& h, const no_net*
     for (int li = 0; li < nl - 1; ++li) {
         const Layer& ly = net->layers[li];
         const int nj = (int)h.cjobs[li].size();
-        if (fhead && li == nl - 2) {
+        const bool hd = fhead && li == nl - 2;
+        if (h.ws[li]) {
+            const int c1 = ly.cat_cp ? ly.cin_p - ly.cat_cp : 0;
+            const bool pool = role[li] == 1 && lvl[li] + 1 < net->a.levels;
+            HZ_TRY(launch_conv3_ws_jobs<P>(t.cjobs[li], nj, t.io[li], packed_w<P>(net, ly), packed_b<P>(net, ly),
+                                           ly.cin_p - c1, c1, ly.cout_p, pool, hd ? packed_w<P>(net, lh) : nullptr,
+                                           hd ? packed_b<P>(net, lh) : nullptr, col, std::is_same<C, double2>::value,
+                                           s));
+        } else if (hd) {
             HZ_TRY(launch_conv3_jobs_head<P>(t.cjobs[li], nj, t.io[li], packed_w<P>(net, ly), packed_b<P>(net, ly),
                                              ly.cin_p, 0, ly.cout_p, packed_w<P>(net, lh), packed_b<P>(net, lh), col,
                                              std::is_same<C, double2>::value, s));
@@ -568,7 +619,7 @@ static int net_step(const BatchPlan<P>& B, const HostTables<P>& h, const no_net*
             const int c1 = ly.cat_cp ? ly.cin_p - ly.cat_cp : 0;
             const bool pool = role[li] == 1 && lvl[li] + 1 < net->a.levels;
             HZ_TRY(launch_conv3_jobs<P>(t.cjobs[li], nj, t.io[li], packed_w<P>(net, ly), packed_b<P>(net, ly),
-                                        ly.cin_p - c1, c1, ly.cout_p, h.tn[li], pool, s));
+                                        ly.cin_p - c1, c1, ly.cout_p, h.tn[li], h.rpw[li], pool, s));
         }
     }
     if (!fhead) {

@@ -539,20 +539,22 @@ __global__ __launch_bounds__(CT) void k_conv3(const typename P::T* __restrict__ 
 // oldest tile alone while K - 1 tiles of loads stay in flight. One barrier per step. Every output
 // is accumulated chunk by chunk and tap by tap as in conv3_tile (same result bits as the other
 // variants). Plain epilogue: bias, ReLU, optional 2 x 2 average pool.
-// grid: x = tile groups, y = channel blocks, z = samples.
+// With HEAD (TN == cout_p) the epilogue is the fused 1x1 head of conv3_tile instead (ex.head_*).
 constexpr int WS_THREADS = 2 * CT;
-template <class P, int TN, bool POOL, int RPW, int WCH, int K>
-__global__ __launch_bounds__(WS_THREADS) void k_conv3_ws(const typename P::T* __restrict__ x0, int c0,
-                                                         const typename P::T* __restrict__ x1, int c1,
-                                                         const typename P::T* __restrict__ w,
-                                                         const typename P::Acc* __restrict__ bias,
-                                                         typename P::T* __restrict__ y, int cout_p,
-                                                         typename P::T* __restrict__ ypool, int H, int W, int relu,
-                                                         int tpb, const int* __restrict__ skip) {
+// One block: output channels [co0, co0 + TN) of tiles [t_beg, t_end) of one sample (xs0, xs1, ys,
+// yps already point at the sample; tiles row-major over the image, TW wide and 4 RPW high).
+template <class P, int TN, bool POOL, int RPW, int WCH, int K, bool HEAD>
+__device__ __forceinline__ void conv3_ws_body(const typename P::T* __restrict__ xs0, int c0,
+                                              const typename P::T* __restrict__ xs1, int c1,
+                                              const typename P::T* __restrict__ w,
+                                              const typename P::Acc* __restrict__ bias,
+                                              typename P::T* __restrict__ ys, int cout_p,
+                                              typename P::T* __restrict__ yps, int H, int W, int relu, int co0,
+                                              int t_beg, int t_end, int skipped, const Conv3Out& ex) {
     using T = typename P::T;
     using Acc = typename P::Acc;
     using AccV = typename P::AccV;
-    const int skipped = skip ? *skip : 0;   // tested once the first loads are in flight
+    static_assert(!HEAD || !POOL, "the fused head has no pooled output");
     constexpr int TH_ = 4 * RPW;
     constexpr int PS = pix_stride<P>();
     constexpr int VE = 16 / sizeof(T);
@@ -565,23 +567,9 @@ __global__ __launch_bounds__(WS_THREADS) void k_conv3_ws(const typename P::T* __
     __shared__ __attribute__((aligned(16))) T patch[2 * WCH * PSZ];
     __shared__ __attribute__((aligned(16))) T wl[WCH * WSZ];
 
-    // logical order: channel block fastest, then tile group, then sample
-    const int ncb_tot = gridDim.y;
-    const int ngrp = gridDim.x;
-    const int nblk = gridDim.x * gridDim.y * gridDim.z;
-    int v = xcd_linear(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nblk);
-    const int cbi = v % ncb_tot;
-    v /= ncb_tot;
-    const int grp = v % ngrp;
-    const int bz = v / ngrp;
-    const int co0 = cbi * TN;
     const int cin_p = c0 + c1;
     const int nch = cin_p / P::CK;   // <= WCH (checked on the host)
     const int ntx = (W + TW - 1) / TW;
-    const int t_beg = grp * tpb, t_end = min(ntx * ((H + TH_ - 1) / TH_), t_beg + tpb);
-    const int64_t plane = (int64_t)H * W;
-    const T* xs0 = x0 + (int64_t)bz * plane * c0;
-    const T* xs1 = x1 ? x1 + (int64_t)bz * plane * c1 : nullptr;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const bool loader = wv >= 4;
@@ -665,7 +653,8 @@ __global__ __launch_bounds__(WS_THREADS) void k_conv3_ws(const typename P::T* __
     __syncthreads();
 
     // compute wavefronts: tile t from LDS buffer b, outputs to memory
-    Acc bpre[NCB][4];
+    Acc bpre[NCB][4], hw0[NCB][4], hw1[NCB][4];
+    Acc hb0 = Acc(0), hb1 = Acc(0);
     auto compute = [&](int t, int b) {
         AccV acc[RPW][NCB];
 #pragma unroll
@@ -681,7 +670,42 @@ __global__ __launch_bounds__(WS_THREADS) void k_conv3_ws(const typename P::T* __
         // (ty0 + RPW wv + pb, tx0 + lr)
         const int ty0 = (t / ntx) * TH_, tx0 = (t % ntx) * TW;
         const int gx = tx0 + lr;
-        T* ys = y + (int64_t)bz * plane * cout_p;
+        if constexpr (HEAD) {   // as conv3_tile's fused head: rounded activations, then the 1x1 head
+            Acc o0[RPW], o1[RPW];
+#pragma unroll
+            for (int pb = 0; pb < RPW; ++pb) o0[pb] = o1[pb] = Acc(0);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const Acc w0 = hw0[cb][r], w1 = hw1[cb][r], bc = bpre[cb][r];
+#pragma unroll
+                    for (int pb = 0; pb < RPW; ++pb) {
+                        Acc q = acc[pb][cb][r] + bc;
+                        if (relu) q = q > Acc(0) ? q : Acc(0);
+                        q = P::val(P::cvt(q));
+                        o0[pb] += q * w0;
+                        o1[pb] += q * w1;
+                    }
+                }
+            const double sfac = ex.head_fixed_s > 0 ? ex.head_fixed_s : ex.head_sc[0];
+#pragma unroll
+            for (int pb = 0; pb < RPW; ++pb) {
+                Acc a0 = o0[pb], a1 = o1[pb];
+                a0 += __shfl_xor(a0, 16, 64);
+                a1 += __shfl_xor(a1, 16, 64);
+                a0 += __shfl_xor(a0, 32, 64);
+                a1 += __shfl_xor(a1, 32, 64);
+                const int gy = ty0 + RPW * wv + pb;
+                if (lg == 0 && gy < ex.head_nyt && gx < ex.head_nxt) {
+                    const double2 zv{sfac * (double)(hb0 + a0), sfac * (double)(hb1 + a1)};
+                    const int64_t zi = (int64_t)gy * ex.head_nxt + gx;
+                    if (ex.head_c128) ((double2*)ex.head_z)[zi] = zv;
+                    else ((float2*)ex.head_z)[zi] = from_d2<float2>(zv);
+                }
+            }
+            return;
+        }
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
             const int co = co0 + cb * 16;
@@ -700,7 +724,7 @@ __global__ __launch_bounds__(WS_THREADS) void k_conv3_ws(const typename P::T* __
                 if (gy < H && gx < W) store_rows<P>(ys + ((int64_t)gy * W + gx) * cout_p + co + P::row_of(lg, 0), vv[pb]);
             }
             if (POOL) {
-                T* ps = ypool + (int64_t)bz * (plane / 4) * cout_p;
+                T* ps = yps;
 #pragma unroll
                 for (int pp = 0; pp < RPW; pp += 2) {
                     Acc q[4];
@@ -741,13 +765,81 @@ __global__ __launch_bounds__(WS_THREADS) void k_conv3_ws(const typename P::T* __
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) bpre[cb][r] = bias[co0 + cb * 16 + P::row_of(lg, r)];
-        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the bias is in registers before the loop
+            for (int r = 0; r < 4; ++r) {
+                const int co = co0 + cb * 16 + P::row_of(lg, r);
+                bpre[cb][r] = bias[co];
+                if constexpr (HEAD) {
+                    hw0[cb][r] = P::val(((const T*)ex.head_w)[co]);
+                    hw1[cb][r] = P::val(((const T*)ex.head_w)[cout_p + co]);
+                }
+            }
+        if constexpr (HEAD) {
+            hb0 = ((const Acc*)ex.head_b)[0];
+            hb1 = ((const Acc*)ex.head_b)[1];
+        }
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): bias (and head) in registers before the loop
         for (int t = t_beg; t < t_end; ++t) {
             compute(t, (t - t_beg) & 1);
             __syncthreads();
         }
     }
+}
+
+// grid: x = tile groups (tpb tiles each), y = channel blocks, z = samples; logical block order:
+// channel block fastest, then tile group, then sample.
+template <class P, int TN, bool POOL, int RPW, int WCH, int K>
+__global__ __launch_bounds__(WS_THREADS) void k_conv3_ws(const typename P::T* __restrict__ x0, int c0,
+                                                         const typename P::T* __restrict__ x1, int c1,
+                                                         const typename P::T* __restrict__ w,
+                                                         const typename P::Acc* __restrict__ bias,
+                                                         typename P::T* __restrict__ y, int cout_p,
+                                                         typename P::T* __restrict__ ypool, int H, int W, int relu,
+                                                         int tpb, const int* __restrict__ skip) {
+    const int skipped = skip ? *skip : 0;   // tested once the first loads are in flight
+    const int ncb_tot = gridDim.y;
+    const int ngrp = gridDim.x;
+    const int nblk = gridDim.x * gridDim.y * gridDim.z;
+    int v = xcd_linear(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nblk);
+    const int cbi = v % ncb_tot;
+    v /= ncb_tot;
+    const int grp = v % ngrp;
+    const int bz = v / ngrp;
+    const int ntiles = ((W + TW - 1) / TW) * ((H + 4 * RPW - 1) / (4 * RPW));
+    const int t_beg = grp * tpb, t_end = min(ntiles, t_beg + tpb);
+    const int64_t plane = (int64_t)H * W;
+    conv3_ws_body<P, TN, POOL, RPW, WCH, K, false>(
+        x0 + (int64_t)bz * plane * c0, c0, x1 ? x1 + (int64_t)bz * plane * c1 : nullptr, c1, w, bias,
+        y + (int64_t)bz * plane * cout_p, cout_p, POOL ? ypool + (int64_t)bz * (plane / 4) * cout_p : nullptr, H, W,
+        relu, cbi * TN, t_beg, t_end, skipped, Conv3Out());
+}
+
+// Ragged batch, weight-stationary form: job = (system, first output channel, first tile, end
+// tile) in the fields (sys, c0, ty0, tx0); with HEAD the fused 1x1 head writes column col of the
+// system's z (LayerIO head fields) instead of y.
+template <class P, int TN, bool POOL, int RPW, int WCH, int K, bool HEAD>
+__global__ __launch_bounds__(WS_THREADS) void k_conv3_ws_jobs(const TileJob* __restrict__ jobs,
+                                                              const LayerIO* __restrict__ io,
+                                                              const typename P::T* __restrict__ w,
+                                                              const typename P::Acc* __restrict__ bias, int c0, int c1,
+                                                              int cout_p, const typename P::T* __restrict__ head_w,
+                                                              const typename P::Acc* __restrict__ head_b, int col,
+                                                              int c128) {
+    const TileJob jb = jobs[xcd_linear(blockIdx.x, gridDim.x)];
+    const LayerIO d = io[jb.sys];
+    if (d.stop && *d.stop) return;
+    Conv3Out ex;
+    if constexpr (HEAD) {
+        ex.head_w = head_w;
+        ex.head_b = head_b;
+        ex.head_c128 = c128;
+        ex.head_z = c128 ? (void*)((double2*)d.z + (int64_t)col * d.zld) : (void*)((float2*)d.z + (int64_t)col * d.zld);
+        ex.head_nxt = d.nxt;
+        ex.head_nyt = d.nyt;
+        ex.head_sc = d.sc;
+    }
+    conv3_ws_body<P, TN, POOL, RPW, WCH, K, HEAD>((const typename P::T*)d.x0, c0, (const typename P::T*)d.x1, c1, w,
+                                                  bias, (typename P::T*)d.y, cout_p, (typename P::T*)d.ypool, d.H,
+                                                  d.W, 1, jb.c0, jb.ty0, jb.tx0, 0, ex);
 }
 
 // Decoder 3x3 convolution with the transposed convolution of the coarser level fused in (UpIn).
@@ -772,7 +864,7 @@ __global__ __launch_bounds__(CT) void k_conv3_up(const typename P::T* __restrict
 }
 
 // Ragged batch: block b runs job jobs[b] = (system, tile, channel block) with the system's tensors.
-template <class P, int TN, bool POOL>
+template <class P, int TN, bool POOL, int RPW>
 __global__ __launch_bounds__(CT) void k_conv3_jobs(const TileJob* __restrict__ jobs, const LayerIO* __restrict__ io,
                                                    const typename P::T* __restrict__ w,
                                                    const typename P::Acc* __restrict__ bias, int c0, int c1,
@@ -780,7 +872,7 @@ __global__ __launch_bounds__(CT) void k_conv3_jobs(const TileJob* __restrict__ j
     const TileJob jb = jobs[xcd_linear(blockIdx.x, gridDim.x)];
     const LayerIO d = io[jb.sys];
     if (d.stop && *d.stop) return;
-    conv3_tile<P, TN, POOL, 2>((const typename P::T*)d.x0, c0, (const typename P::T*)d.x1, c1, w, bias,
+    conv3_tile<P, TN, POOL, RPW>((const typename P::T*)d.x0, c0, (const typename P::T*)d.x1, c1, w, bias,
                                (typename P::T*)d.y, cout_p, (typename P::T*)d.ypool, d.H, d.W, relu, ck, Conv3Out(),
                                0, jb.c0, jb.ty0, jb.tx0, 0, c0 + c1, nullptr);
 }
@@ -1212,20 +1304,33 @@ int conv_chunk(int cin_p, int c0, int c1) { return chunk_for<P>(cin_p, c0, c1); 
 
 template <class P>
 int launch_conv3_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
-                      const typename P::Acc* bias, int c0, int c1, int cout_p, int tn, bool pool, hipStream_t s) {
+                      const typename P::Acc* bias, int c0, int c1, int cout_p, int tn, int rpw, bool pool,
+                      hipStream_t s) {
     if (njobs <= 0) return HZ_OK;
     const int ck = chunk_for<P>(c0 + c1, c0, c1);
-#define HZ_C3J(TNV, PL)                                                                                         \
-    hipLaunchKernelGGL((k_conv3_jobs<P, TNV, PL>), dim3(njobs), dim3(CT), 0, s, jobs, io, w, bias, c0, c1, cout_p, \
+#define HZ_C3J(TNV, PL, R)                                                                                         \
+    hipLaunchKernelGGL((k_conv3_jobs<P, TNV, PL, R>), dim3(njobs), dim3(CT), 0, s, jobs, io, w, bias, c0, c1, cout_p, \
                        1, ck)
-    if (pool) {
-        if (tn == 64) HZ_C3J(64, true);
-        else if (tn == 32) HZ_C3J(32, true);
-        else HZ_C3J(16, true);
+    if (rpw == 4) {
+        if constexpr (std::is_same<P, PolBF16>::value) {
+            if (tn != 32) {
+                set_error("conv3 jobs: 16-row tiles use 32-channel blocks");
+                return HZ_ERR_ARG;
+            }
+            if (pool) HZ_C3J(32, true, 4);
+            else HZ_C3J(32, false, 4);
+        } else {
+            set_error("conv3 jobs: 16-row tiles are BF16 only");
+            return HZ_ERR_ARG;
+        }
+    } else if (pool) {
+        if (tn == 64) HZ_C3J(64, true, 2);
+        else if (tn == 32) HZ_C3J(32, true, 2);
+        else HZ_C3J(16, true, 2);
     } else {
-        if (tn == 64) HZ_C3J(64, false);
-        else if (tn == 32) HZ_C3J(32, false);
-        else HZ_C3J(16, false);
+        if (tn == 64) HZ_C3J(64, false, 2);
+        else if (tn == 32) HZ_C3J(32, false, 2);
+        else HZ_C3J(16, false, 2);
     }
 #undef HZ_C3J
     HZ_LAUNCH_CHECK();
@@ -1254,6 +1359,40 @@ int launch_conv3_jobs_head(const TileJob* jobs, int njobs, const LayerIO* io, co
 }
 
 template <class P>
+int launch_conv3_ws_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
+                         const typename P::Acc* bias, int c0, int c1, int cout_p, bool pool,
+                         const typename P::T* head_w, const typename P::Acc* head_b, int col, bool c128,
+                         hipStream_t s) {
+    if (njobs <= 0) return HZ_OK;
+    if constexpr (std::is_same<P, PolBF16>::value) {
+        const int nch = (c0 + c1) / P::CK;
+        if (!ws_jobs_ok<P>(c0, c1, cout_p) || (head_w && (pool || cout_p != WSJ_TN))) {
+            set_error("conv3 jobs: the weight-stationary form needs BF16, 32-channel blocks, 1 or 2 input chunks");
+            return HZ_ERR_ARG;
+        }
+#define HZ_WSJ(PL, WC, HD)                                                                                      \
+    hipLaunchKernelGGL((k_conv3_ws_jobs<P, WSJ_TN, PL, WSJ_RPW, WC, 2, HD>), dim3(njobs), dim3(WS_THREADS), 0, s, \
+                       jobs, io, w, bias, c0, c1, cout_p, head_w, head_b, col, c128 ? 1 : 0)
+        if (head_w) {
+            if (nch == 1) HZ_WSJ(false, 1, true);
+            else HZ_WSJ(false, 2, true);
+        } else if (pool) {
+            if (nch == 1) HZ_WSJ(true, 1, false);
+            else HZ_WSJ(true, 2, false);
+        } else {
+            if (nch == 1) HZ_WSJ(false, 1, false);
+            else HZ_WSJ(false, 2, false);
+        }
+#undef HZ_WSJ
+        HZ_LAUNCH_CHECK();
+        return HZ_OK;
+    } else {
+        set_error("conv3 jobs: the weight-stationary form is BF16 only");
+        return HZ_ERR_ARG;
+    }
+}
+
+template <class P>
 int launch_convT2_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
                        const typename P::Acc* bias, int cin_p, int cout_p, int tn, hipStream_t s) {
     if (njobs <= 0) return HZ_OK;
@@ -1277,9 +1416,11 @@ int launch_convT2_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const 
     template int launch_convT2<P>(const P::T*, int, const P::T*, const P::Acc*, P::T*, int, int, int, int,       \
                                   const int*, hipStream_t);                                                    \
     template int launch_conv3_jobs<P>(const TileJob*, int, const LayerIO*, const P::T*, const P::Acc*, int, int, \
-                                      int, int, bool, hipStream_t);                                            \
+                                      int, int, int, bool, hipStream_t);                                       \
     template int launch_conv3_jobs_head<P>(const TileJob*, int, const LayerIO*, const P::T*, const P::Acc*, int,   \
                                            int, int, const P::T*, const P::Acc*, int, bool, hipStream_t);       \
+    template int launch_conv3_ws_jobs<P>(const TileJob*, int, const LayerIO*, const P::T*, const P::Acc*, int, int, \
+                                         int, bool, const P::T*, const P::Acc*, int, bool, hipStream_t);        \
     template int launch_convT2_jobs<P>(const TileJob*, int, const LayerIO*, const P::T*, const P::Acc*, int, int, \
                                        int, hipStream_t);                                                      \
     template int conv_chunk<P>(int, int, int);                                                                 \

@@ -199,16 +199,31 @@ int launch_conv3(const typename P::T* x0, int c0, const typename P::T* x1, int c
                  const typename P::Acc* bias, typename P::T* y, int cout_p, typename P::T* ypool, int H, int W,
                  int batch, bool relu, const int* skip, hipStream_t s, Conv3Out ex = Conv3Out(),
                  ConvCfg cfg = ConvCfg(), typename P::Acc* splitbuf = nullptr);
-// Ragged-batch versions: one launch over a job table.
+// Ragged-batch versions: one launch over a job table (3x3: tiles of 4 rpw rows x 16 columns, rpw 2,
+// or 4 with tn 32 in BF16).
 template <class P>
 int launch_conv3_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
-                      const typename P::Acc* bias, int c0, int c1, int cout_p, int tn, bool pool, hipStream_t s);
+                      const typename P::Acc* bias, int c0, int c1, int cout_p, int tn, int rpw, bool pool,
+                      hipStream_t s);
 // The same with the 1x1 output head fused into the epilogue (cout_p 16, 32 or 64, one job per
 // pixel tile): writes column col of each system's z (LayerIO head fields) instead of y.
 template <class P>
 int launch_conv3_jobs_head(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
                            const typename P::Acc* bias, int c0, int c1, int cout_p, const typename P::T* head_w,
                            const typename P::Acc* head_b, int col, bool c128, hipStream_t s);
+// Weight-stationary form over a job table (BF16; WSJ_TN output channels and 4 WSJ_RPW pixel rows
+// per tile; job = (sys, first output channel, first tile, end tile) with tiles row-major over the
+// system's image); with head_w the fused 1x1 head as in launch_conv3_jobs_head (cout_p == WSJ_TN).
+constexpr int WSJ_TN = 32, WSJ_RPW = 4;
+template <class P>
+constexpr bool ws_jobs_ok(int c0, int c1, int cout_p) {
+    return conv3_ws_ok<P>(WSJ_TN, WSJ_RPW, c0, c1, cout_p) && c0 + c1 <= 2 * P::CK;
+}
+template <class P>
+int launch_conv3_ws_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
+                         const typename P::Acc* bias, int c0, int c1, int cout_p, bool pool,
+                         const typename P::T* head_w, const typename P::Acc* head_b, int col, bool c128,
+                         hipStream_t s);
 template <class P>
 int launch_convT2_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
                        const typename P::Acc* bias, int cin_p, int cout_p, int tn, hipStream_t s);
