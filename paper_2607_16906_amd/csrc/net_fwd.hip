@@ -63,6 +63,38 @@ __device__ __forceinline__ void conv3_chunk_mma(typename P::AccV (&acc)[RPW][TN 
     }
 }
 
+// The MFMA steps of an input of one k-group (P::GW channels) per tap held in LDS as conv3_chunk_mma's
+// layout: step s takes taps 4 s .. 4 s + 3 (lane group lg: tap 4 s + lg, zero past the ninth), the
+// same steps and operands as conv3_tile with a chunk of P::GW channels.
+template <class P, int TN, int RPW>
+__device__ __forceinline__ void conv3_group_mma(typename P::AccV (&acc)[RPW][TN / 16], const typename P::T* pst,
+                                                const typename P::T* wst, int wv, int lr, int lg) {
+    using Frag = typename P::Frag;
+    constexpr int PS = pix_stride<P>();
+    constexpr int NCB = TN / 16;
+#pragma unroll
+    for (int sp = 0; sp < 3; ++sp) {
+        const int tap = 4 * sp + lg;
+        Frag a[NCB], b[RPW];
+        if (tap < 9) {
+            const int dy = tap / 3, dx = tap - 3 * (tap / 3);
+#pragma unroll
+            for (int pb = 0; pb < RPW; ++pb) b[pb] = P::load(pst + ((RPW * wv + pb + dy) * (TW + 2) + lr + dx) * PS);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) a[cb] = P::load(wst + (tap * TN + cb * 16 + lr) * PS);
+        } else {
+#pragma unroll
+            for (int pb = 0; pb < RPW; ++pb) b[pb] = P::zero();
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) a[cb] = P::zero();
+        }
+#pragma unroll
+        for (int pb = 0; pb < RPW; ++pb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[pb][cb] = P::mma(a[cb], b[pb], acc[pb][cb]);
+    }
+}
+
 // One block's tile: output channels [co0, co0 + TN) of the (4 RPW) x 16 pixel tile at (ty0, tx0)
 // of sample bz, over the input-channel chunks [kbeg, kend). Each wavefront owns RPW rows of the
 // tile. NS chunks form one stage: their patches and weights sit in NS LDS buffers, and the next
@@ -543,7 +575,7 @@ __global__ __launch_bounds__(CT) void k_conv3(const typename P::T* __restrict__ 
 constexpr int WS_THREADS = 2 * CT;
 // One block: output channels [co0, co0 + TN) of tiles [t_beg, t_end) of one sample (xs0, xs1, ys,
 // yps already point at the sample; tiles row-major over the image, TW wide and 4 RPW high).
-template <class P, int TN, bool POOL, int RPW, int WCH, int K, bool HEAD>
+template <class P, int TN, bool POOL, int RPW, int WCH, int K, bool HEAD, bool SMALL = false>
 __device__ __forceinline__ void conv3_ws_body(const typename P::T* __restrict__ xs0, int c0,
                                               const typename P::T* __restrict__ xs1, int c1,
                                               const typename P::T* __restrict__ w,
@@ -555,11 +587,12 @@ __device__ __forceinline__ void conv3_ws_body(const typename P::T* __restrict__ 
     using Acc = typename P::Acc;
     using AccV = typename P::AccV;
     static_assert(!HEAD || !POOL, "the fused head has no pooled output");
+    static_assert(!SMALL || WCH == 1, "an input of one k-group per tap is one chunk");
     constexpr int TH_ = 4 * RPW;
     constexpr int PS = pix_stride<P>();
     constexpr int VE = 16 / sizeof(T);
     constexpr int NCB = TN / 16;
-    constexpr int VPP = P::CK / VE;
+    constexpr int VPP = SMALL ? 1 : P::CK / VE;           // vectors per pixel of a chunk
     constexpr int PSZ = (TH_ + 2) * (TW + 2) * PS, WSZ = 9 * TN * PS;
     constexpr int NPV = (TH_ + 2) * (TW + 2) * VPP;       // patch vectors per chunk
     constexpr int NPA = (NPV + CT - 1) / CT;              // per loader thread
@@ -568,7 +601,7 @@ __device__ __forceinline__ void conv3_ws_body(const typename P::T* __restrict__ 
     __shared__ __attribute__((aligned(16))) T wl[WCH * WSZ];
 
     const int cin_p = c0 + c1;
-    const int nch = cin_p / P::CK;   // <= WCH (checked on the host)
+    const int nch = SMALL ? 1 : cin_p / P::CK;   // <= WCH (checked on the host)
     const int ntx = (W + TW - 1) / TW;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -665,7 +698,10 @@ __device__ __forceinline__ void conv3_ws_body(const typename P::T* __restrict__ 
                 for (int r = 0; r < 4; ++r) acc[pb][cb][r] = 0;
 #pragma unroll
         for (int c = 0; c < WCH; ++c)
-            if (c < nch) conv3_chunk_mma<P, TN, RPW>(acc, &patch[(b * WCH + c) * PSZ], &wl[c * WSZ], wv, lr, lg);
+            if (c < nch) {
+                if constexpr (SMALL) conv3_group_mma<P, TN, RPW>(acc, &patch[(b * WCH + c) * PSZ], &wl[c * WSZ], wv, lr, lg);
+                else conv3_chunk_mma<P, TN, RPW>(acc, &patch[(b * WCH + c) * PSZ], &wl[c * WSZ], wv, lr, lg);
+            }
         // register r of a lane holds output channel co0 + 16 cb + row_of(lg, r) of pixel
         // (ty0 + RPW wv + pb, tx0 + lr)
         const int ty0 = (t / ntx) * TH_, tx0 = (t % ntx) * TW;
@@ -813,10 +849,36 @@ __global__ __launch_bounds__(WS_THREADS) void k_conv3_ws(const typename P::T* __
         relu, cbi * TN, t_beg, t_end, skipped, Conv3Out());
 }
 
+// The same for an input of one k-group per tap (conv3_ws_small): no pooled output.
+template <class P, int TN, int RPW, int K>
+__global__ __launch_bounds__(WS_THREADS) void k_conv3_ws8(const typename P::T* __restrict__ x0, int c0,
+                                                          const typename P::T* __restrict__ w,
+                                                          const typename P::Acc* __restrict__ bias,
+                                                          typename P::T* __restrict__ y, int cout_p, int H, int W,
+                                                          int relu, int tpb, const int* __restrict__ skip) {
+    const int skipped = skip ? *skip : 0;   // tested once the first loads are in flight
+    const int ncb_tot = gridDim.y;
+    const int ngrp = gridDim.x;
+    const int nblk = gridDim.x * gridDim.y * gridDim.z;
+    int v = xcd_linear(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nblk);
+    const int cbi = v % ncb_tot;
+    v /= ncb_tot;
+    const int grp = v % ngrp;
+    const int bz = v / ngrp;
+    const int ntiles = ((W + TW - 1) / TW) * ((H + 4 * RPW - 1) / (4 * RPW));
+    const int t_beg = grp * tpb, t_end = min(ntiles, t_beg + tpb);
+    const int64_t plane = (int64_t)H * W;
+    const typename P::T* xs = x0 + (int64_t)bz * plane * c0;
+    // (the second input part is empty; xs stands in for its pointer, which is never read)
+    conv3_ws_body<P, TN, false, RPW, 1, K, false, true>(xs, c0, xs, 0, w, bias,
+                                                        y + (int64_t)bz * plane * cout_p, cout_p, nullptr, H, W, relu,
+                                                        cbi * TN, t_beg, t_end, skipped, Conv3Out());
+}
+
 // Ragged batch, weight-stationary form: job = (system, first output channel, first tile, end
 // tile) in the fields (sys, c0, ty0, tx0); with HEAD the fused 1x1 head writes column col of the
 // system's z (LayerIO head fields) instead of y.
-template <class P, int TN, bool POOL, int RPW, int WCH, int K, bool HEAD>
+template <class P, int TN, bool POOL, int RPW, int WCH, int K, bool HEAD, bool SMALL>
 __global__ __launch_bounds__(WS_THREADS) void k_conv3_ws_jobs(const TileJob* __restrict__ jobs,
                                                               const LayerIO* __restrict__ io,
                                                               const typename P::T* __restrict__ w,
@@ -837,7 +899,7 @@ __global__ __launch_bounds__(WS_THREADS) void k_conv3_ws_jobs(const TileJob* __r
         ex.head_nyt = d.nyt;
         ex.head_sc = d.sc;
     }
-    conv3_ws_body<P, TN, POOL, RPW, WCH, K, HEAD>((const typename P::T*)d.x0, c0, (const typename P::T*)d.x1, c1, w,
+    conv3_ws_body<P, TN, POOL, RPW, WCH, K, HEAD, SMALL>((const typename P::T*)d.x0, c0, (const typename P::T*)d.x1, c1, w,
                                                   bias, (typename P::T*)d.y, cout_p, (typename P::T*)d.ypool, d.H,
                                                   d.W, 1, jb.c0, jb.ty0, jb.tx0, 0, ex);
 }
@@ -1119,6 +1181,35 @@ int launch_conv3(const typename P::T* x0, int c0, const typename P::T* x1, int c
         const int ngrp = (ntiles + cfg.tpb - 1) / cfg.tpb;
         const int nch = cin_p / P::CK;
         dim3 grid(ngrp, cout_p / tn, batch);
+        if (conv3_ws_small<P>(c0, c1)) {
+            if (ypool) {
+                set_error("conv3: the weight-stationary form of a one-k-group input has no pooled output");
+                return HZ_ERR_ARG;
+            }
+            if constexpr (std::is_same<P, PolBF16>::value) {
+#define HZ_WS8(TNV, R, KV)                                                                                     \
+    hipLaunchKernelGGL((k_conv3_ws8<P, TNV, R, KV>), grid, dim3(WS_THREADS), 0, s, x0, c0, w, bias, y, cout_p, H, W, \
+                       relu ? 1 : 0, cfg.tpb, skip)
+#define HZ_WS8K(TNV, R)                                     \
+    if constexpr (R == 2) {                                 \
+        if (cfg.ns >= 4) { HZ_WS8(TNV, R, 4); }             \
+        else if (cfg.ns == 3) { HZ_WS8(TNV, R, 3); }        \
+        else { HZ_WS8(TNV, R, 2); }                         \
+    } else {                                                \
+        HZ_WS8(TNV, R, 2);                                  \
+    }
+#define HZ_WS8T(R)                             \
+    if (tn == 64) { HZ_WS8K(64, R) }           \
+    else if (tn == 32) { HZ_WS8K(32, R) }      \
+    else { HZ_WS8K(16, R) }
+                if (rpw == 4) { HZ_WS8T(4) } else { HZ_WS8T(2) }
+#undef HZ_WS8T
+#undef HZ_WS8K
+#undef HZ_WS8
+            }
+            HZ_LAUNCH_CHECK();
+            return HZ_OK;
+        }
 #define HZ_WS1(TNV, PL, R, WC, KV)                                                                           \
     hipLaunchKernelGGL((k_conv3_ws<P, TNV, PL, R, WC, KV>), grid, dim3(WS_THREADS), 0, s, x0, c0, x1, c1, w, bias, \
                        y, cout_p, ypool, H, W, relu ? 1 : 0, cfg.tpb, skip)
@@ -1370,18 +1461,24 @@ int launch_conv3_ws_jobs(const TileJob* jobs, int njobs, const LayerIO* io, cons
             set_error("conv3 jobs: the weight-stationary form needs BF16, 32-channel blocks, 1 or 2 input chunks");
             return HZ_ERR_ARG;
         }
-#define HZ_WSJ(PL, WC, HD)                                                                                      \
-    hipLaunchKernelGGL((k_conv3_ws_jobs<P, WSJ_TN, PL, WSJ_RPW, WC, 2, HD>), dim3(njobs), dim3(WS_THREADS), 0, s, \
-                       jobs, io, w, bias, c0, c1, cout_p, head_w, head_b, col, c128 ? 1 : 0)
-        if (head_w) {
-            if (nch == 1) HZ_WSJ(false, 1, true);
-            else HZ_WSJ(false, 2, true);
+#define HZ_WSJ(PL, WC, HD, SM)                                                                                  \
+    hipLaunchKernelGGL((k_conv3_ws_jobs<P, WSJ_TN, PL, WSJ_RPW, WC, 2, HD, SM>), dim3(njobs), dim3(WS_THREADS), 0, \
+                       s, jobs, io, w, bias, c0, c1, cout_p, head_w, head_b, col, c128 ? 1 : 0)
+        if (conv3_ws_small<P>(c0, c1)) {
+            if (head_w || pool) {
+                set_error("conv3 jobs: an input of one k-group per tap has no fused head or pooling here");
+                return HZ_ERR_ARG;
+            }
+            HZ_WSJ(false, 1, false, true);
+        } else if (head_w) {
+            if (nch == 1) HZ_WSJ(false, 1, true, false);
+            else HZ_WSJ(false, 2, true, false);
         } else if (pool) {
-            if (nch == 1) HZ_WSJ(true, 1, false);
-            else HZ_WSJ(true, 2, false);
+            if (nch == 1) HZ_WSJ(true, 1, false, false);
+            else HZ_WSJ(true, 2, false, false);
         } else {
-            if (nch == 1) HZ_WSJ(false, 1, false);
-            else HZ_WSJ(false, 2, false);
+            if (nch == 1) HZ_WSJ(false, 1, false, false);
+            else HZ_WSJ(false, 2, false, false);
         }
 #undef HZ_WSJ
         HZ_LAUNCH_CHECK();

@@ -155,14 +155,23 @@ constexpr int conv3_ws_lds(int tn, int rpw, int wch) {
     return wch * (2 * (4 * rpw + 2) * 18 * ps + 9 * tn * ps) * (int)sizeof(typename P::T);
 }
 
+// An input of one k-group (P::GW channels) per tap, as the first layer's: the weight-stationary
+// form then stages one k-group per pixel and runs conv3_tile's grouped-tap steps.
+template <class P>
+constexpr bool conv3_ws_small(int c0, int c1) {
+    return c1 == 0 && c0 == P::GW;
+}
+
 // Whether the weight-stationary form applies: BF16, channel tile tn in {16, 32, 64} dividing
-// cout_p, both input parts whole chunks of P::CK channels, 1, 2 or 4 chunks, and the LDS of all
-// chunk buffers within 160 KB.
+// cout_p, both input parts whole chunks of P::CK channels (1, 2 or 4 chunks) or an input of one
+// k-group per tap (conv3_ws_small), and the LDS of all chunk buffers within 160 KB.
 template <class P>
 constexpr bool conv3_ws_ok(int tn, int rpw, int c0, int c1, int cout_p) {
     if (!std::is_same<P, PolBF16>::value) return false;
     if (tn != 16 && tn != 32 && tn != 64) return false;
-    if (cout_p % tn || c0 % P::CK || c1 % P::CK || c0 + c1 == 0) return false;
+    if (cout_p % tn) return false;
+    if (conv3_ws_small<P>(c0, c1)) return conv3_ws_lds<P>(tn, rpw, 1) <= 160 * 1024;
+    if (c0 % P::CK || c1 % P::CK || c0 + c1 == 0) return false;
     const int nch = (c0 + c1) / P::CK;
     if (nch != 1 && nch != 2 && nch != 4) return false;
     return conv3_ws_lds<P>(tn, rpw, nch) <= 160 * 1024;
@@ -211,8 +220,8 @@ template <class P>
 int launch_conv3_jobs_head(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
                            const typename P::Acc* bias, int c0, int c1, int cout_p, const typename P::T* head_w,
                            const typename P::Acc* head_b, int col, bool c128, hipStream_t s);
-// Weight-stationary form over a job table (BF16; WSJ_TN output channels and 4 WSJ_RPW pixel rows
-// per tile; job = (sys, first output channel, first tile, end tile) with tiles row-major over the
+// Weight-stationary form over a job table (BF16, inputs of one or two chunks or of one k-group per
+// tap; WSJ_TN output channels and 4 WSJ_RPW pixel rows per tile; job = (sys, first output channel, first tile, end tile) with tiles row-major over the
 // system's image); with head_w the fused 1x1 head as in launch_conv3_jobs_head (cout_p == WSJ_TN).
 constexpr int WSJ_TN = 32, WSJ_RPW = 4;
 template <class P>
