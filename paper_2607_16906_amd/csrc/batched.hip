@@ -437,7 +437,7 @@ struct HostTables {
     std::vector<std::vector<LayerIO>> io;
     std::vector<std::vector<TileJob>> cjobs;
     std::vector<int> tn, rpw;
-    std::vector<char> ws;   // 3x3 layer in the weight-stationary form
+    std::vector<char> ws;   // layer in the weight-stationary form
 };
 
 // Launch form of a 3x3 layer over a ragged batch with `tiles` 16 x 16 pixel tiles in all: in BF16
@@ -511,8 +511,19 @@ static void build_tables(const BatchPlan<P>& B, const no_net* net, const std::ve
         }
         const bool fhead = li == nl - 2 && head_fused(net);
         int tn = 16, rpw = 2, tpb = 0;
-        if (convT) tn = convT2_batch_tn(ly.cout_p);
-        else batch_conv3_form<P>(ly, ly.cat_cp ? ly.cin_p - ly.cat_cp : 0, tiles16, tiles, fhead, tn, rpw, tpb);
+        if (convT) {
+            tn = convT2_batch_tn(ly.cout_p);
+            // weight-stationary form where the input channels fit one stage: 4-32 row segments per
+            // job, while that still gives at least 256 jobs
+            if (convT2_ws_ok<P>(ly.cin_p, ly.cout_p, tn)) {
+                const int64_t ncb = ly.cout_p / tn;
+                int t = 32;
+                while (t > 4 && (tiles + t - 1) / t * ncb < 1024) t /= 2;
+                if ((tiles + t - 1) / t * ncb >= 256) tpb = t;
+            }
+        } else {
+            batch_conv3_form<P>(ly, ly.cat_cp ? ly.cin_p - ly.cat_cp : 0, tiles16, tiles, fhead, tn, rpw, tpb);
+        }
         h.tn[li] = tn;
         h.rpw[li] = rpw;
         h.ws[li] = tpb > 0;
@@ -545,7 +556,12 @@ static void build_tables(const BatchPlan<P>& B, const no_net* net, const std::ve
         // to a contiguous range of jobs, so they share the tile's input in one L2)
         for (int s : active) {
             const int H = B.S[s].Hp >> l, W = B.S[s].Wp >> l;
-            if (convT) {
+            if (convT && tpb > 0) {   // (sys, first channel, first segment, end segment)
+                const int nt = H * ((W + 63) / 64);
+                for (int t0 = 0; t0 < nt; t0 += tpb)
+                    for (int co = 0; co < ly.cout_p; co += tn)
+                        h.cjobs[li].push_back(TileJob{s, co, t0, std::min(nt, t0 + tpb)});
+            } else if (convT) {
                 for (int iy = 0; iy < H; ++iy)
                     for (int ix = 0; ix < W; ix += 64)
                         for (int co = 0; co < ly.cout_p; co += tn) h.cjobs[li].push_back(TileJob{s, co, iy, ix});
@@ -601,7 +617,10 @@ static int net_step(const BatchPlan<P>& B, const HostTables<P>& h, const no_net*
         const Layer& ly = net->layers[li];
         const int nj = (int)h.cjobs[li].size();
         const bool hd = fhead && li == nl - 2;
-        if (h.ws[li]) {
+        if (role[li] == 2 && h.ws[li]) {
+            HZ_TRY(launch_convT2_ws_jobs<P>(t.cjobs[li], nj, t.io[li], packed_w<P>(net, ly), packed_b<P>(net, ly),
+                                            ly.cin_p, ly.cout_p, h.tn[li], s));
+        } else if (h.ws[li]) {
             const int c1 = ly.cat_cp ? ly.cin_p - ly.cat_cp : 0;
             const bool pool = role[li] == 1 && lvl[li] + 1 < net->a.levels;
             HZ_TRY(launch_conv3_ws_jobs<P>(t.cjobs[li], nj, t.io[li], packed_w<P>(net, ly), packed_b<P>(net, ly),

@@ -1133,6 +1133,164 @@ __global__ __launch_bounds__(CT) void k_convT2_jobs(const TileJob* __restrict__ 
                        jb.ty0, jb.tx0);
 }
 
+// Ragged batch, transposed convolution with every input channel in one stage (cin_p a multiple of
+// 4 GW, at most 4 CK): a block keeps the weights of its TN output channels in LDS and runs the
+// 64-pixel input row segments [t_beg, t_end) of one system (segment t: input row t / nseg, columns
+// 64 (t % nseg) ..), job = (system, first output channel, t_beg, t_end) in (sys, c0, ty0, tx0).
+// As in conv3_ws_body, wavefronts 4-7 only load (K register sets, one segment per step into a
+// double-buffered LDS patch) and wavefronts 0-3 only run the matrix cores and store, one barrier
+// per step; the MFMA steps and the epilogue are convT2_tile's (the same result bits).
+template <class P, int TN, int K>
+__global__ __launch_bounds__(WS_THREADS) void k_convT2_ws_jobs(const TileJob* __restrict__ jobs,
+                                                               const LayerIO* __restrict__ io,
+                                                               const typename P::T* __restrict__ w,
+                                                               const typename P::Acc* __restrict__ bias, int cin_p,
+                                                               int cout_p) {
+    using T = typename P::T;
+    using Acc = typename P::Acc;
+    using AccV = typename P::AccV;
+    using Frag = typename P::Frag;
+    constexpr int KSM = convT2_ksmax<P>();
+    constexpr int PS = KSM + 16 / (int)sizeof(T);
+    constexpr int VE = 16 / sizeof(T);
+    constexpr int NCB = TN / 16;
+    constexpr int NXA = (64 * KSM / VE + CT - 1) / CT;                    // per loader thread
+    constexpr int NWV = (4 * TN * KSM / VE + WS_THREADS - 1) / WS_THREADS;   // per thread
+    __shared__ __attribute__((aligned(16))) T xin[2 * 64 * PS];
+    __shared__ __attribute__((aligned(16))) T wl[4 * TN * PS];
+    const TileJob jb = jobs[xcd_linear(blockIdx.x, gridDim.x)];
+    const LayerIO d = io[jb.sys];
+    if (d.stop && *d.stop) return;
+    const T* xs = (const T*)d.x0;
+    T* ys = (T*)d.y;
+    const int W = d.W;
+    const int co0 = jb.c0, t_beg = jb.ty0, t_end = jb.tx0;
+    const int nseg = (W + 63) / 64;
+    const int vpp = cin_p / VE;
+    const int nxv = 64 * vpp, nwv = 4 * TN * vpp;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool loader = wv >= 4;
+    const int lt = threadIdx.x - CT;
+    const int lr = lane & 15, lg = lane >> 4;
+    {   // the block's weights (every wavefront): [4 parities][TN][cin_p] into LDS rows
+        uint4 rw[NWV];
+#pragma unroll
+        for (int i = 0; i < NWV; ++i) {
+            const int v = threadIdx.x + i * WS_THREADS;
+            rw[i] = uint4{0, 0, 0, 0};
+            if (v < nwv) {
+                const int row = v / vpp, part = v - row * vpp;
+                const int ab = row / TN, co = row - ab * TN;
+                rw[i] = *(const uint4*)(w + ((int64_t)ab * cout_p + co0 + co) * cin_p + part * VE);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NWV; ++i) {
+            const int v = threadIdx.x + i * WS_THREADS;
+            if (v < nwv) {
+                const int row = v / vpp, part = v - row * vpp;
+                *(uint4*)&wl[row * PS + part * VE] = rw[i];
+            }
+        }
+    }
+    // loader: segment t into ra_, every lane loading (from pixel 0 of the row where its pixel is
+    // past the row's end; ok_ marks the others), so that the loads in flight do not depend on data
+    auto gload = [&](int t, uint4 (&ra_)[NXA], uint32_t& ok_) {
+        const int iy = t / nseg, ix0 = (t - iy * nseg) * 64;
+        ok_ = 0;
+#pragma unroll
+        for (int i = 0; i < NXA; ++i) {
+            const int vv = min(lt + i * CT, nxv - 1);
+            const int px = vv / vpp, part = vv - px * vpp;
+            const int gx = ix0 + px;
+            const bool in = gx < W;
+            ok_ |= (in ? 1u : 0u) << i;
+            ra_[i] = *(const uint4*)(xs + ((int64_t)iy * W + (in ? gx : 0)) * cin_p + part * VE);
+        }
+    };
+    auto lstore = [&](int b, const uint4 (&ra_)[NXA], uint32_t ok_) {
+#pragma unroll
+        for (int i = 0; i < NXA; ++i) {
+            const int vv = lt + i * CT;
+            if (vv < nxv) {
+                const int px = vv / vpp, part = vv - px * vpp;
+                *(uint4*)&xin[b * 64 * PS + px * PS + part * VE] = ((ok_ >> i) & 1u) ? ra_[i] : uint4{0, 0, 0, 0};
+            }
+        }
+    };
+    uint4 ra[K][NXA];
+    uint32_t ok[K];
+    if (loader) {
+#pragma unroll
+        for (int u = 0; u < K; ++u) gload(min(t_beg + u, t_end - 1), ra[u], ok[u]);
+        lstore(0, ra[0], ok[0]);
+    }
+    __syncthreads();
+    Acc bpre[NCB][4];
+    auto compute = [&](int t, int b) {
+        AccV acc[4][NCB];
+#pragma unroll
+        for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[ab][cb][r] = 0;
+        const T* xb = &xin[b * 64 * PS + (wv * 16 + lr) * PS + lg * P::GW];
+        const T* wb = &wl[lr * PS + lg * P::GW];
+#pragma unroll
+        for (int st = 0; st < KSM / P::GW / 4; ++st) {
+            if (4 * st * P::GW >= cin_p) break;
+            const Frag bx = P::load(xb + 4 * st * P::GW);
+#pragma unroll
+            for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb)
+                    acc[ab][cb] = P::mma(P::load(wb + (ab * TN + cb * 16) * PS + 4 * st * P::GW), bx, acc[ab][cb]);
+        }
+        const int iy = t / nseg, ix0 = (t - iy * nseg) * 64;
+        const int gx = ix0 + wv * 16 + lr;
+        if (gx >= W) return;
+#pragma unroll
+        for (int ab = 0; ab < 4; ++ab) {
+            const int oy = 2 * iy + (ab >> 1), ox = 2 * gx + (ab & 1);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                T* dst = ys + ((int64_t)oy * (2 * W) + ox) * cout_p + co0 + cb * 16;
+                Acc tv[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) tv[r] = acc[ab][cb][r] + bpre[cb][r];
+                store_rows<P>(dst + P::row_of(lg, 0), tv);
+            }
+        }
+    };
+    // the two roles run separate loops with one barrier per step (as conv3_ws_body)
+    if (loader) {
+        for (int t0 = t_beg; t0 < t_end; t0 += K) {
+#pragma unroll
+            for (int u = 0; u < K; ++u) {
+                const int t = t0 + u;
+                if (t < t_end) {
+                    const int b = (t - t_beg) & 1;
+                    if (t + 1 < t_end) lstore(b ^ 1, ra[(u + 1) % K], ok[(u + 1) % K]);
+                    gload(min(t + K, t_end - 1), ra[u], ok[u]);
+                    __syncthreads();
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) bpre[cb][r] = bias[co0 + cb * 16 + P::row_of(lg, r)];
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the bias is in registers before the loop
+        for (int t = t_beg; t < t_end; ++t) {
+            compute(t, (t - t_beg) & 1);
+            __syncthreads();
+        }
+    }
+}
+
 static int pick_tn(int cout_p) { return cout_p % 64 == 0 ? 64 : (cout_p % 32 == 0 ? 32 : 16); }
 
 int conv3_batch_tn(int cout_p, int64_t tiles) {
@@ -1140,7 +1298,13 @@ int conv3_batch_tn(int cout_p, int64_t tiles) {
     while (tn > 16 && tiles * (cout_p / tn) < 512) tn /= 2;
     return tn;
 }
-int convT2_batch_tn(int cout_p) { return cout_p % 32 == 0 ? 32 : 16; }
+// 16-channel blocks (every padded channel count is a multiple of 16): the kernel runs one tile per
+// block with one load stage, and the 16-channel form's registers and LDS let 4 blocks share a CU
+// instead of 2, hiding more of each block's load latency (faster on the serving mix, where the
+// transposed layers are bound by that latency rather than by the bytes they move)
+int convT2_batch_tn(int /*cout_p*/) {
+    return 16;
+}
 
 template <class P>
 static int convT2_stage(int cin_p) {
@@ -1490,6 +1654,29 @@ int launch_conv3_ws_jobs(const TileJob* jobs, int njobs, const LayerIO* io, cons
 }
 
 template <class P>
+int launch_convT2_ws_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
+                          const typename P::Acc* bias, int cin_p, int cout_p, int tn, hipStream_t s) {
+    if (njobs <= 0) return HZ_OK;
+    if constexpr (std::is_same<P, PolBF16>::value) {
+        if (!convT2_ws_ok<P>(cin_p, cout_p, tn)) {
+            set_error("convT2 jobs: the weight-stationary form needs BF16 and one stage of input channels");
+            return HZ_ERR_ARG;
+        }
+        if (tn == 32)
+            hipLaunchKernelGGL((k_convT2_ws_jobs<P, 32, 2>), dim3(njobs), dim3(WS_THREADS), 0, s, jobs, io, w, bias,
+                               cin_p, cout_p);
+        else
+            hipLaunchKernelGGL((k_convT2_ws_jobs<P, 16, 2>), dim3(njobs), dim3(WS_THREADS), 0, s, jobs, io, w, bias,
+                               cin_p, cout_p);
+        HZ_LAUNCH_CHECK();
+        return HZ_OK;
+    } else {
+        set_error("convT2 jobs: the weight-stationary form is BF16 only");
+        return HZ_ERR_ARG;
+    }
+}
+
+template <class P>
 int launch_convT2_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
                        const typename P::Acc* bias, int cin_p, int cout_p, int tn, hipStream_t s) {
     if (njobs <= 0) return HZ_OK;
@@ -1520,6 +1707,8 @@ int launch_convT2_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const 
                                          int, bool, const P::T*, const P::Acc*, int, bool, hipStream_t);        \
     template int launch_convT2_jobs<P>(const TileJob*, int, const LayerIO*, const P::T*, const P::Acc*, int, int, \
                                        int, hipStream_t);                                                      \
+    template int launch_convT2_ws_jobs<P>(const TileJob*, int, const LayerIO*, const P::T*, const P::Acc*, int,    \
+                                          int, int, hipStream_t);                                              \
     template int conv_chunk<P>(int, int, int);                                                                 \
     template bool conv3_up_ok<P>(int, int, int, int, int);                                                     \
     template int launch_conv3_up<P>(const P::T*, int, UpIn, int, const P::T*, const P::Acc*, P::T*, int, int, int, \
