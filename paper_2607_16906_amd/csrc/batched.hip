@@ -117,17 +117,7 @@ __global__ __launch_bounds__(KT) void kb_update(const TileJob* __restrict__ jobs
     const C* V = (const C*)d.V;
     C* w = (C*)d.V + (int64_t)nv * d.n;
     const double2* h = MODE == 1 ? d.h1 : d.h2;
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += KT) {
-        const C wp = w[p];
-        double ax = wp.x, ay = wp.y;
-        for (int i = 0; i < nv; ++i) {
-            const C v = V[(int64_t)i * d.n + p];
-            const double2 hi = h[i];
-            ax -= (double)v.x * hi.x - (double)v.y * hi.y;
-            ay -= (double)v.x * hi.y + (double)v.y * hi.x;
-        }
-        w[p] = from_d2<C>(double2{ax, ay});
-    }
+    update_body(V, d.n, nv, h, w, p0, p1);
     __syncthreads();   // the sweeps below may read points written by other threads of the block
     double2* mine = d.part + (int64_t)jb.c0 * d.ldp;
     if (MODE == 1) dots_body(V, d.n, nv, (const C*)w, p0, p1, mine);

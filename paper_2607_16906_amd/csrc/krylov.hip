@@ -373,52 +373,7 @@ __global__ __launch_bounds__(KT) void k_update(const C* __restrict__ V, int64_t 
         }
         return;
     }
-    if (pair_ok<C>(V, w, ldv, p0)) {
-        // two points per lane, 16-byte loads and stores
-        float4* __restrict__ w4 = (float4*)(w + p0);
-        const int64_t npair = (p1 - p0) >> 1;
-        for (int64_t k = threadIdx.x; k < npair; k += KT) {
-            const float4 a = w4[k];
-            double ax = a.x, ay = a.y, bx = a.z, by = a.w;
-            // unrolled so that several basis loads are in flight (same order of the sums)
-#pragma unroll 8
-            for (int i = 0; i < nv; ++i) {
-                const float4 v = ((const float4*)(V + (int64_t)i * ldv + p0))[k];
-                const double2 hi = h[i];
-                ax -= (double)v.x * hi.x - (double)v.y * hi.y;
-                ay -= (double)v.x * hi.y + (double)v.y * hi.x;
-                bx -= (double)v.z * hi.x - (double)v.w * hi.y;
-                by -= (double)v.z * hi.y + (double)v.w * hi.x;
-            }
-            w4[k] = float4{(float)ax, (float)ay, (float)bx, (float)by};
-        }
-        if (((p1 - p0) & 1) && threadIdx.x == KT - 1) {
-            const int64_t p = p1 - 1;
-            const C wp = w[p];
-            double ax = wp.x, ay = wp.y;
-#pragma unroll 8
-            for (int i = 0; i < nv; ++i) {
-                const C v = V[(int64_t)i * ldv + p];
-                const double2 hi = h[i];
-                ax -= (double)v.x * hi.x - (double)v.y * hi.y;
-                ay -= (double)v.x * hi.y + (double)v.y * hi.x;
-            }
-            w[p] = from_d2<C>(double2{ax, ay});
-        }
-    } else {
-        for (int64_t p = p0 + threadIdx.x; p < p1; p += KT) {
-            const C wp = w[p];
-            double ax = wp.x, ay = wp.y;
-#pragma unroll 8
-            for (int i = 0; i < nv; ++i) {
-                const C v = V[(int64_t)i * ldv + p];
-                const double2 hi = h[i];
-                ax -= (double)v.x * hi.x - (double)v.y * hi.y;
-                ay -= (double)v.x * hi.y + (double)v.y * hi.x;
-            }
-            w[p] = from_d2<C>(double2{ax, ay});
-        }
-    }
+    update_body(V, ldv, nv, h, w, p0, p1);
     __syncthreads();   // the sweeps below may read points written by other threads of the block
     double2* mine = part + (int64_t)blockIdx.x * ldp;
     if (MODE == 1) dots_body(V, ldv, nv, w, p0, p1, mine);

@@ -199,6 +199,60 @@ __device__ __forceinline__ void dots_body_waves(const C* __restrict__ V, int64_t
     }
 }
 
+// w -= sum_i V_i h_i (i in order) over points [p0, p1) of one KT-thread block: two points per lane
+// with 16-byte loads and stores where the vectors allow it (pair_ok), else one; the basis loads of
+// several i are in flight together.
+template <typename C>
+__device__ __forceinline__ void update_body(const C* __restrict__ V, int64_t ldv, int nv, const double2* __restrict__ h,
+                                            C* __restrict__ w, int64_t p0, int64_t p1) {
+    if (pair_ok<C>(V, w, ldv, p0)) {
+        // two points per lane, 16-byte loads and stores
+        float4* __restrict__ w4 = (float4*)(w + p0);
+        const int64_t npair = (p1 - p0) >> 1;
+        for (int64_t k = threadIdx.x; k < npair; k += KT) {
+            const float4 a = w4[k];
+            double ax = a.x, ay = a.y, bx = a.z, by = a.w;
+            // unrolled so that several basis loads are in flight (same order of the sums)
+#pragma unroll 8
+            for (int i = 0; i < nv; ++i) {
+                const float4 v = ((const float4*)(V + (int64_t)i * ldv + p0))[k];
+                const double2 hi = h[i];
+                ax -= (double)v.x * hi.x - (double)v.y * hi.y;
+                ay -= (double)v.x * hi.y + (double)v.y * hi.x;
+                bx -= (double)v.z * hi.x - (double)v.w * hi.y;
+                by -= (double)v.z * hi.y + (double)v.w * hi.x;
+            }
+            w4[k] = float4{(float)ax, (float)ay, (float)bx, (float)by};
+        }
+        if (((p1 - p0) & 1) && threadIdx.x == KT - 1) {
+            const int64_t p = p1 - 1;
+            const C wp = w[p];
+            double ax = wp.x, ay = wp.y;
+#pragma unroll 8
+            for (int i = 0; i < nv; ++i) {
+                const C v = V[(int64_t)i * ldv + p];
+                const double2 hi = h[i];
+                ax -= (double)v.x * hi.x - (double)v.y * hi.y;
+                ay -= (double)v.x * hi.y + (double)v.y * hi.x;
+            }
+            w[p] = from_d2<C>(double2{ax, ay});
+        }
+    } else {
+        for (int64_t p = p0 + threadIdx.x; p < p1; p += KT) {
+            const C wp = w[p];
+            double ax = wp.x, ay = wp.y;
+#pragma unroll 8
+            for (int i = 0; i < nv; ++i) {
+                const C v = V[(int64_t)i * ldv + p];
+                const double2 hi = h[i];
+                ax -= (double)v.x * hi.x - (double)v.y * hi.y;
+                ay -= (double)v.x * hi.y + (double)v.y * hi.x;
+            }
+            w[p] = from_d2<C>(double2{ax, ay});
+        }
+    }
+}
+
 template <typename C>
 __device__ __forceinline__ void dots_body(const C* __restrict__ V, int64_t ldv, int nv, const C* __restrict__ w,
                                  int64_t p0, int64_t p1, double2* __restrict__ part) {
