@@ -1134,13 +1134,13 @@ __global__ __launch_bounds__(CT) void k_convT2_jobs(const TileJob* __restrict__ 
 }
 
 // Ragged batch, transposed convolution with every input channel in one stage (cin_p a multiple of
-// 4 GW, at most KSM): a block keeps the weights of its TN output channels in LDS and runs the
+// 4 GW, at most 4 CK): a block keeps the weights of its TN output channels in LDS and runs the
 // 64-pixel input row segments [t_beg, t_end) of one system (segment t: input row t / nseg, columns
 // 64 (t % nseg) ..), job = (system, first output channel, t_beg, t_end) in (sys, c0, ty0, tx0).
 // As in conv3_ws_body, wavefronts 4-7 only load (K register sets, one segment per step into a
 // double-buffered LDS patch) and wavefronts 0-3 only run the matrix cores and store, one barrier
 // per step; the MFMA steps and the epilogue are convT2_tile's (the same result bits).
-template <class P, int TN, int K, int KSM>
+template <class P, int TN, int K>
 __global__ __launch_bounds__(WS_THREADS) void k_convT2_ws_jobs(const TileJob* __restrict__ jobs,
                                                                const LayerIO* __restrict__ io,
                                                                const typename P::T* __restrict__ w,
@@ -1150,6 +1150,7 @@ __global__ __launch_bounds__(WS_THREADS) void k_convT2_ws_jobs(const TileJob* __
     using Acc = typename P::Acc;
     using AccV = typename P::AccV;
     using Frag = typename P::Frag;
+    constexpr int KSM = convT2_ksmax<P>();
     constexpr int PS = KSM + 16 / (int)sizeof(T);
     constexpr int VE = 16 / sizeof(T);
     constexpr int NCB = TN / 16;
@@ -1661,16 +1662,12 @@ int launch_convT2_ws_jobs(const TileJob* jobs, int njobs, const LayerIO* io, con
             set_error("convT2 jobs: the weight-stationary form needs BF16 and one stage of input channels");
             return HZ_ERR_ARG;
         }
-        // (the stage sizes: 4 CK channels, or 8 CK with 16-channel blocks)
-        if (cin_p > 4 * P::CK)
-            hipLaunchKernelGGL((k_convT2_ws_jobs<P, 16, 2, 8 * P::CK>), dim3(njobs), dim3(WS_THREADS), 0, s, jobs, io,
-                               w, bias, cin_p, cout_p);
-        else if (tn == 32)
-            hipLaunchKernelGGL((k_convT2_ws_jobs<P, 32, 2, 4 * P::CK>), dim3(njobs), dim3(WS_THREADS), 0, s, jobs, io,
-                               w, bias, cin_p, cout_p);
+        if (tn == 32)
+            hipLaunchKernelGGL((k_convT2_ws_jobs<P, 32, 2>), dim3(njobs), dim3(WS_THREADS), 0, s, jobs, io, w, bias,
+                               cin_p, cout_p);
         else
-            hipLaunchKernelGGL((k_convT2_ws_jobs<P, 16, 2, 4 * P::CK>), dim3(njobs), dim3(WS_THREADS), 0, s, jobs, io,
-                               w, bias, cin_p, cout_p);
+            hipLaunchKernelGGL((k_convT2_ws_jobs<P, 16, 2>), dim3(njobs), dim3(WS_THREADS), 0, s, jobs, io, w, bias,
+                               cin_p, cout_p);
         HZ_LAUNCH_CHECK();
         return HZ_OK;
     } else {

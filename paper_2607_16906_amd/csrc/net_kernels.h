@@ -237,13 +237,12 @@ template <class P>
 int launch_convT2_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
                        const typename P::Acc* bias, int cin_p, int cout_p, int tn, hipStream_t s);
 // Weight-stationary transposed convolution over a job table (BF16, every input channel in one
-// stage: up to 4 CK, or 8 CK with tn 16): job = (sys, first output channel, first 64-pixel input
-// row segment, end segment), the segments of a system row-major (ceil(W / 64) per input row);
-// tn 16 or 32.
+// stage): job = (sys, first output channel, first 64-pixel input row segment, end segment), the
+// segments of a system row-major (ceil(W / 64) per input row); tn 16 or 32.
 template <class P>
 constexpr bool convT2_ws_ok(int cin_p, int cout_p, int tn) {
     return std::is_same<P, PolBF16>::value && (tn == 16 || tn == 32) && cout_p % tn == 0 &&
-           cin_p % (4 * P::GW) == 0 && cin_p > 0 && (cin_p <= 4 * P::CK || (tn == 16 && cin_p <= 8 * P::CK));
+           cin_p % (4 * P::GW) == 0 && cin_p > 0 && cin_p <= 4 * P::CK;
 }
 template <class P>
 int launch_convT2_ws_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
