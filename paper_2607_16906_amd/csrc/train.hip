@@ -290,6 +290,21 @@ __global__ __launch_bounds__(TT) void k_wgrad3(const typename P::T* __restrict__
     if (blockIdx.x == 0 && tci == 0) partb[(int64_t)z * cout_p + co] = accb;
 }
 
+// 8 x 8 transpose of 16-bit elements: r[p] holds elements 0..7 of row p; o[k] receives element k
+// of rows 0..7 (row p in its element p)
+__device__ __forceinline__ void wg_transpose8(const uint4 (&r)[8], uint4 (&o)[8]) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        uint32_t wv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t a = (&r[2 * j].x)[k >> 1], c = (&r[2 * j + 1].x)[k >> 1];
+            wv[j] = (k & 1) ? ((a >> 16) | (c & 0xffff0000u)) : ((a & 0xffffu) | (c << 16));
+        }
+        o[k] = uint4{wv[0], wv[1], wv[2], wv[3]};
+    }
+}
+
 // 3x3 on the matrix cores (BF16 operands, FP32 accumulation): for every tap (dy, dx),
 // dW[co][ci][tap] = sum_p G[p][co] X[p + (dy - 1, dx - 1)][ci] is a product with the pixels as
 // the reduction index. Block: 32 output x 32 input channels over its chunk of 8 x 16 pixel
@@ -323,45 +338,79 @@ __global__ __launch_bounds__(TT) void k_wgrad3_mfma(const bf16_t* __restrict__ G
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[t][r] = 0.f;
     float accb = 0.f;                            // bias: thread sums 16 pixels of channel threadIdx.x / 8
-    const int t_end = min(ntiles, (z + 1) * tpc);
-    for (int tile = z * tpc; tile < t_end; ++tile) {
+    const int t_beg = z * tpc, t_end = min(ntiles, (z + 1) * tpc);
+    // G tile (128 pixels x 32 channels) and the three shifted copies of the input patch, staged
+    // transposed by units of 8 pixels x 8 channels: a thread loads a unit's 8 pixel vectors into
+    // registers (the next tile's while the matrix cores work on this one), transposes them
+    // (wg_transpose8) and writes 8 channel rows of 8 pixels as 16-byte stores (the same LDS
+    // contents as element-wise transposing stores). Units [0, 64): G; [64, 304): the X copies.
+    constexpr int NU = 16 * 4 + 3 * 10 * 2 * 4;
+    constexpr int UPT = (NU + TT - 1) / TT;
+    uint4 rg[UPT][8];
+    auto gload = [&](int tile) {
         const int b = tile / per_img, r = tile - b * per_img;
         const int ty0 = (r / tx_n) * 8, tx0 = (r % tx_n) * 16;
-        __syncthreads();
-        // G tile: 128 pixels x 32 channels, 4 vectors of 8 channels per pixel
-        for (int v = threadIdx.x; v < 128 * 4; v += TT) {
-            const int px = v >> 2, part8 = v & 3;
-            const int gy = ty0 + (px >> 4), gx = tx0 + (px & 15);
-            const int co = co0 + part8 * 8;
-            uint4 val = uint4{0, 0, 0, 0};
-            if (gy < H && gx < W && co < cout_p)
-                val = *(const uint4*)(G + ((int64_t)b * plane + (int64_t)gy * W + gx) * cout_p + co);
-            const bf16_t* e = (const bf16_t*)&val;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) gt[(part8 * 8 + k) * WG_GS + px] = e[k];
-        }
-        // input patch: 10 x 18 pixels x 32 channels; copy dx holds column c + dx at column c
-        for (int v = threadIdx.x; v < 180 * 4; v += TT) {
-            const int px = v >> 2, part8 = v & 3;
-            const int py = px / 18, pc = px - py * 18;
-            const int gy = ty0 + py - 1, gx = tx0 + pc - 1;
-            const int ci = ci0 + part8 * 8;
-            uint4 val = uint4{0, 0, 0, 0};
-            if (gy >= 0 && gy < H && gx >= 0 && gx < W && ci < cin_p) {
-                const int64_t pix = (int64_t)b * plane + (int64_t)gy * W + gx;
-                val = *(const uint4*)(ci < c0 ? x0 + pix * c0 + ci : x1 + pix * c1 + (ci - c0));
-            }
-            const bf16_t* e = (const bf16_t*)&val;
+        for (int i = 0; i < UPT; ++i) {
+            const int u = threadIdx.x + i * TT;
+            if (u >= NU) break;
+            const int part8 = u & 3;
+            if (u < 16 * 4) {   // G: pixels 8 pg .. 8 pg + 7 of the tile (row pg / 2, columns 8 (pg % 2) ..)
+                const int pg = u >> 2;
+                const int gy = ty0 + (pg >> 1), gx0 = tx0 + 8 * (pg & 1);
+                const int co = co0 + part8 * 8;
 #pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const int c = pc - dx;
-                if (c >= 0 && c < 16) {
+                for (int k = 0; k < 8; ++k) {
+                    rg[i][k] = uint4{0, 0, 0, 0};
+                    if (gy < H && gx0 + k < W && co < cout_p)
+                        rg[i][k] = *(const uint4*)(G + ((int64_t)b * plane + (int64_t)gy * W + gx0 + k) * cout_p + co);
+                }
+            } else {            // X copy dx, patch row py, columns 8 hc .. 8 hc + 7 of the copy
+                const int q = (u - 16 * 4) >> 2;
+                const int dx = q / 20, py = (q % 20) >> 1, hc = q & 1;
+                const int gy = ty0 + py - 1, gx0 = tx0 + 8 * hc + dx - 1;
+                const int ci = ci0 + part8 * 8;
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) xt[(dx * WG_CI + part8 * 8 + k) * WG_XS + py * 16 + c] = e[k];
+                for (int k = 0; k < 8; ++k) {
+                    const int gx = gx0 + k;
+                    rg[i][k] = uint4{0, 0, 0, 0};
+                    if (gy >= 0 && gy < H && gx >= 0 && gx < W && ci < cin_p) {
+                        const int64_t pix = (int64_t)b * plane + (int64_t)gy * W + gx;
+                        rg[i][k] = *(const uint4*)(ci < c0 ? x0 + pix * c0 + ci : x1 + pix * c1 + (ci - c0));
+                    }
                 }
             }
         }
+    };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int i = 0; i < UPT; ++i) {
+            const int u = threadIdx.x + i * TT;
+            if (u >= NU) break;
+            const int part8 = u & 3;
+            bf16_t* dst;
+            int stride;
+            if (u < 16 * 4) {
+                dst = &gt[(part8 * 8) * WG_GS + 8 * (u >> 2)];
+                stride = WG_GS;
+            } else {
+                const int q = (u - 16 * 4) >> 2;
+                const int dx = q / 20, py = (q % 20) >> 1, hc = q & 1;
+                dst = &xt[(dx * WG_CI + part8 * 8) * WG_XS + py * 16 + 8 * hc];
+                stride = WG_XS;
+            }
+            uint4 o[8];
+            wg_transpose8(rg[i], o);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) *(uint4*)(dst + k * stride) = o[k];
+        }
+    };
+    if (t_beg < t_end) gload(t_beg);
+    for (int tile = t_beg; tile < t_end; ++tile) {
+        __syncthreads();   // the previous tile's reads of the LDS are done
+        lstore();
         __syncthreads();
+        if (tile + 1 < t_end) gload(tile + 1);
         if (blockIdx.x == 0) {
             const int co = threadIdx.x >> 3, seg = threadIdx.x & 7;
 #pragma unroll
