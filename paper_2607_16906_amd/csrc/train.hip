@@ -632,37 +632,67 @@ __global__ __launch_bounds__(TT) void k_wgradT_mfma(const bf16_t* __restrict__ G
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[t][r] = 0.f;
     float accb = 0.f;
-    const int t_end = min(ntiles, (z + 1) * tpc);
-    for (int tile = z * tpc; tile < t_end; ++tile) {
+    const int t_beg = z * tpc, t_end = min(ntiles, (z + 1) * tpc);
+    // G at the 4 fine pixels (parity ab) of each of the 128 coarse pixels, and x, staged transposed
+    // by units of 8 coarse pixels x 8 channels as in k_wgrad3_mfma (register transposes, 16-byte
+    // LDS stores, the next tile's loads in flight). Units [0, 256): G (ab, pixel group, part);
+    // [256, 320): x.
+    constexpr int NU = 4 * 16 * 4 + 16 * 4;
+    constexpr int UPT = (NU + TT - 1) / TT;
+    uint4 rg[UPT][8];
+    auto gload = [&](int tile) {
         const int b = tile / per_img, r = tile - b * per_img;
         const int ty0 = (r / tx_n) * 8, tx0 = (r % tx_n) * 16;
-        __syncthreads();
-        // G at the 4 fine pixels of each of the 128 coarse pixels, 4 vectors of 8 channels each
-        for (int v = threadIdx.x; v < 128 * 4 * 4; v += TT) {
-            const int part8 = v & 3, ab = (v >> 2) & 3, px = v >> 4;
-            const int iy = ty0 + (px >> 4), ix = tx0 + (px & 15);
-            const int co = co0 + part8 * 8;
-            uint4 val = uint4{0, 0, 0, 0};
-            if (iy < H && ix < W && co < cout_p) {
-                const int oy = 2 * iy + (ab >> 1), ox = 2 * ix + (ab & 1);
-                val = *(const uint4*)(G + ((int64_t)b * 4 * plane + (int64_t)oy * 2 * W + ox) * cout_p + co);
+#pragma unroll
+        for (int i = 0; i < UPT; ++i) {
+            const int u = threadIdx.x + i * TT;
+            if (u >= NU) break;
+            const int part8 = u & 3;
+            const int pg = (u >> 2) & 15;
+            const int iy = ty0 + (pg >> 1), ix0 = tx0 + 8 * (pg & 1);
+            if (u < 4 * 16 * 4) {
+                const int ab = u >> 6;
+                const int co = co0 + part8 * 8;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    rg[i][k] = uint4{0, 0, 0, 0};
+                    if (iy < H && ix0 + k < W && co < cout_p) {
+                        const int oy = 2 * iy + (ab >> 1), ox = 2 * (ix0 + k) + (ab & 1);
+                        rg[i][k] = *(const uint4*)(G + ((int64_t)b * 4 * plane + (int64_t)oy * 2 * W + ox) * cout_p + co);
+                    }
+                }
+            } else {
+                const int ci = ci0 + part8 * 8;
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    rg[i][k] = uint4{0, 0, 0, 0};
+                    if (iy < H && ix0 + k < W && ci < cin_p)
+                        rg[i][k] = *(const uint4*)(x + ((int64_t)b * plane + (int64_t)iy * W + ix0 + k) * cin_p + ci);
+                }
             }
-            const bf16_t* e = (const bf16_t*)&val;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) gt[(ab * WG_CO + part8 * 8 + k) * WG_GS + px] = e[k];
         }
-        for (int v = threadIdx.x; v < 128 * 4; v += TT) {
-            const int part8 = v & 3, px = v >> 2;
-            const int iy = ty0 + (px >> 4), ix = tx0 + (px & 15);
-            const int ci = ci0 + part8 * 8;
-            uint4 val = uint4{0, 0, 0, 0};
-            if (iy < H && ix < W && ci < cin_p)
-                val = *(const uint4*)(x + ((int64_t)b * plane + (int64_t)iy * W + ix) * cin_p + ci);
-            const bf16_t* e = (const bf16_t*)&val;
+    };
+    auto lstore = [&]() {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) xt[(part8 * 8 + k) * WG_GS + px] = e[k];
+        for (int i = 0; i < UPT; ++i) {
+            const int u = threadIdx.x + i * TT;
+            if (u >= NU) break;
+            const int part8 = u & 3;
+            const int pg = (u >> 2) & 15;
+            bf16_t* dst = u < 4 * 16 * 4 ? &gt[((u >> 6) * WG_CO + part8 * 8) * WG_GS + 8 * pg]
+                                         : &xt[(part8 * 8) * WG_GS + 8 * pg];
+            uint4 o[8];
+            wg_transpose8(rg[i], o);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) *(uint4*)(dst + k * WG_GS) = o[k];
         }
+    };
+    if (t_beg < t_end) gload(t_beg);
+    for (int tile = t_beg; tile < t_end; ++tile) {
+        __syncthreads();   // the previous tile's reads of the LDS are done
+        lstore();
         __syncthreads();
+        if (tile + 1 < t_end) gload(tile + 1);
         if (blockIdx.x == 0) {
             const int co = threadIdx.x >> 3, seg = threadIdx.x & 7;
 #pragma unroll
