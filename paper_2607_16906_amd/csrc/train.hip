@@ -340,69 +340,66 @@ __global__ __launch_bounds__(TT) void k_wgrad3_mfma(const bf16_t* __restrict__ G
     float accb = 0.f;                            // bias: thread sums 16 pixels of channel threadIdx.x / 8
     const int t_beg = z * tpc, t_end = min(ntiles, (z + 1) * tpc);
     // G tile (128 pixels x 32 channels) and the three shifted copies of the input patch, staged
-    // transposed by units of 8 pixels x 8 channels: a thread loads a unit's 8 pixel vectors into
-    // registers (the next tile's while the matrix cores work on this one), transposes them
-    // (wg_transpose8) and writes 8 channel rows of 8 pixels as 16-byte stores (the same LDS
-    // contents as element-wise transposing stores). Units [0, 64): G; [64, 304): the X copies.
-    constexpr int NU = 16 * 4 + 3 * 10 * 2 * 4;
-    constexpr int UPT = (NU + TT - 1) / TT;
-    uint4 rg[UPT][8];
+    // transposed: a thread loads its unit's pixel vectors into registers (the next tile's while the
+    // matrix cores work on this one), transposes 8 pixels x 8 channels at a time (wg_transpose8)
+    // and writes 8 channel rows of 8 pixels as 16-byte stores (the same LDS contents as
+    // element-wise transposing stores). Units [0, 64): G, 8 pixels; [64, 144): 10 pixels of one
+    // patch row (columns 8 h .. 8 h + 9), from which the three copies take their 8-pixel windows.
+    constexpr int NU = 16 * 4 + 10 * 2 * 4;
+    static_assert(NU <= TT, "one unit per thread");
+    uint4 rg[10];
     auto gload = [&](int tile) {
         const int b = tile / per_img, r = tile - b * per_img;
         const int ty0 = (r / tx_n) * 8, tx0 = (r % tx_n) * 16;
+        const int u = threadIdx.x;
+        if (u >= NU) return;
+        const int part8 = u & 3;
+        if (u < 16 * 4) {   // G: pixels 8 pg .. 8 pg + 7 of the tile (row pg / 2, columns 8 (pg % 2) ..)
+            const int pg = u >> 2;
+            const int gy = ty0 + (pg >> 1), gx0 = tx0 + 8 * (pg & 1);
+            const int co = co0 + part8 * 8;
 #pragma unroll
-        for (int i = 0; i < UPT; ++i) {
-            const int u = threadIdx.x + i * TT;
-            if (u >= NU) break;
-            const int part8 = u & 3;
-            if (u < 16 * 4) {   // G: pixels 8 pg .. 8 pg + 7 of the tile (row pg / 2, columns 8 (pg % 2) ..)
-                const int pg = u >> 2;
-                const int gy = ty0 + (pg >> 1), gx0 = tx0 + 8 * (pg & 1);
-                const int co = co0 + part8 * 8;
+            for (int k = 0; k < 8; ++k) {
+                rg[k] = uint4{0, 0, 0, 0};
+                if (gy < H && gx0 + k < W && co < cout_p)
+                    rg[k] = *(const uint4*)(G + ((int64_t)b * plane + (int64_t)gy * W + gx0 + k) * cout_p + co);
+            }
+        } else {            // X: patch row py, patch columns 8 h .. 8 h + 9
+            const int q = u - 16 * 4;
+            const int h = (q >> 2) & 1, py = q >> 3;
+            const int gy = ty0 + py - 1, gx0 = tx0 + 8 * h - 1;
+            const int ci = ci0 + part8 * 8;
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    rg[i][k] = uint4{0, 0, 0, 0};
-                    if (gy < H && gx0 + k < W && co < cout_p)
-                        rg[i][k] = *(const uint4*)(G + ((int64_t)b * plane + (int64_t)gy * W + gx0 + k) * cout_p + co);
-                }
-            } else {            // X copy dx, patch row py, columns 8 hc .. 8 hc + 7 of the copy
-                const int q = (u - 16 * 4) >> 2;
-                const int dx = q / 20, py = (q % 20) >> 1, hc = q & 1;
-                const int gy = ty0 + py - 1, gx0 = tx0 + 8 * hc + dx - 1;
-                const int ci = ci0 + part8 * 8;
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const int gx = gx0 + k;
-                    rg[i][k] = uint4{0, 0, 0, 0};
-                    if (gy >= 0 && gy < H && gx >= 0 && gx < W && ci < cin_p) {
-                        const int64_t pix = (int64_t)b * plane + (int64_t)gy * W + gx;
-                        rg[i][k] = *(const uint4*)(ci < c0 ? x0 + pix * c0 + ci : x1 + pix * c1 + (ci - c0));
-                    }
+            for (int k = 0; k < 10; ++k) {
+                const int gx = gx0 + k;
+                rg[k] = uint4{0, 0, 0, 0};
+                if (gy >= 0 && gy < H && gx >= 0 && gx < W && ci < cin_p) {
+                    const int64_t pix = (int64_t)b * plane + (int64_t)gy * W + gx;
+                    rg[k] = *(const uint4*)(ci < c0 ? x0 + pix * c0 + ci : x1 + pix * c1 + (ci - c0));
                 }
             }
         }
     };
+    auto put = [&](bf16_t* dst, int stride, int off) {   // the 8 pixels rg[off ..] transposed to dst
+        uint4 w8[8], o[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) w8[k] = rg[off + k];
+        wg_transpose8(w8, o);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) *(uint4*)(dst + k * stride) = o[k];
+    };
     auto lstore = [&]() {
+        const int u = threadIdx.x;
+        if (u >= NU) return;
+        const int part8 = u & 3;
+        if (u < 16 * 4) {
+            put(&gt[(part8 * 8) * WG_GS + 8 * (u >> 2)], WG_GS, 0);
+        } else {            // copy dx, columns 8 h .. 8 h + 7 hold patch columns 8 h + dx ..
+            const int q = u - 16 * 4;
+            const int h = (q >> 2) & 1, py = q >> 3;
 #pragma unroll
-        for (int i = 0; i < UPT; ++i) {
-            const int u = threadIdx.x + i * TT;
-            if (u >= NU) break;
-            const int part8 = u & 3;
-            bf16_t* dst;
-            int stride;
-            if (u < 16 * 4) {
-                dst = &gt[(part8 * 8) * WG_GS + 8 * (u >> 2)];
-                stride = WG_GS;
-            } else {
-                const int q = (u - 16 * 4) >> 2;
-                const int dx = q / 20, py = (q % 20) >> 1, hc = q & 1;
-                dst = &xt[(dx * WG_CI + part8 * 8) * WG_XS + py * 16 + 8 * hc];
-                stride = WG_XS;
-            }
-            uint4 o[8];
-            wg_transpose8(rg[i], o);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) *(uint4*)(dst + k * stride) = o[k];
+            for (int dx = 0; dx < 3; ++dx)
+                put(&xt[(dx * WG_CI + part8 * 8) * WG_XS + py * 16 + 8 * h], WG_XS, dx);
         }
     };
     if (t_beg < t_end) gload(t_beg);
