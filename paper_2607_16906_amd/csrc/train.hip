@@ -982,10 +982,12 @@ static int wgrad_conv3(const Layer& ly, const typename P::T* G, const typename P
     const int ntiles = ((W + 15) / 16) * ((H + 7) / 8) * B;
     int nchunk;
     if constexpr (std::is_same<P, PolBF16>::value || std::is_same<P, PolF32>::value) {
-        // matrix-core form: about 1024 blocks, as many chunks as the partial buffer holds
+        // matrix-core form: about 1024 blocks (512 in BF16, whose blocks prefetch their next tile),
+        // as many chunks as the partial buffer holds
         const int ctiles = ((ly.cin_p + WG_CI - 1) / WG_CI) * ((ly.cout_p + WG_CO - 1) / WG_CO);
         const size_t per_chunk = (size_t)9 * ly.cout_p * ly.cin_p;
-        int want = std::min(512, std::max(1, (1024 + ctiles - 1) / ctiles));
+        const int nb = std::is_same<P, PolBF16>::value ? 512 : 1024;
+        int want = std::min(512, std::max(1, (nb + ctiles - 1) / ctiles));
         want = (int)std::min<size_t>((size_t)want, t.wcap / per_chunk);
         want = std::min(want, (int)std::min<size_t>((size_t)WCHUNKS_MAX, t.bcap / (size_t)ly.cout_p));
         const int tpc = (ntiles + want - 1) / want;
