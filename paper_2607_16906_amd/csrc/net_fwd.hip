@@ -1133,19 +1133,18 @@ __global__ __launch_bounds__(CT) void k_convT2_jobs(const TileJob* __restrict__ 
                        jb.ty0, jb.tx0);
 }
 
-// Ragged batch, transposed convolution with every input channel in one stage (cin_p a multiple of
-// 4 GW, at most 4 CK): a block keeps the weights of its TN output channels in LDS and runs the
-// 64-pixel input row segments [t_beg, t_end) of one system (segment t: input row t / nseg, columns
-// 64 (t % nseg) ..), job = (system, first output channel, t_beg, t_end) in (sys, c0, ty0, tx0).
-// As in conv3_ws_body, wavefronts 4-7 only load (K register sets, one segment per step into a
-// double-buffered LDS patch) and wavefronts 0-3 only run the matrix cores and store, one barrier
-// per step; the MFMA steps and the epilogue are convT2_tile's (the same result bits).
+// Transposed convolution with every input channel in one stage (cin_p a multiple of 4 GW, at
+// most 4 CK), weight-stationary: a block keeps the weights of its TN output channels in LDS and
+// runs the 64-pixel input row segments [t_beg, t_end) of one sample (segment t: input row
+// t / nseg, columns 64 (t % nseg) ..; xs and ys at the sample). As in conv3_ws_body, wavefronts
+// 4-7 only load (K register sets, one segment per step into a double-buffered LDS patch) and
+// wavefronts 0-3 only run the matrix cores and store, one barrier per step; the MFMA steps and
+// the epilogue are convT2_tile's (the same result bits).
 template <class P, int TN, int K>
-__global__ __launch_bounds__(WS_THREADS) void k_convT2_ws_jobs(const TileJob* __restrict__ jobs,
-                                                               const LayerIO* __restrict__ io,
-                                                               const typename P::T* __restrict__ w,
-                                                               const typename P::Acc* __restrict__ bias, int cin_p,
-                                                               int cout_p) {
+__device__ __forceinline__ void convT2_ws_body(const typename P::T* __restrict__ xs, typename P::T* __restrict__ ys,
+                                               const typename P::T* __restrict__ w,
+                                               const typename P::Acc* __restrict__ bias, int cin_p, int cout_p,
+                                               int W, int co0, int t_beg, int t_end) {
     using T = typename P::T;
     using Acc = typename P::Acc;
     using AccV = typename P::AccV;
@@ -1158,13 +1157,6 @@ __global__ __launch_bounds__(WS_THREADS) void k_convT2_ws_jobs(const TileJob* __
     constexpr int NWV = (4 * TN * KSM / VE + WS_THREADS - 1) / WS_THREADS;   // per thread
     __shared__ __attribute__((aligned(16))) T xin[2 * 64 * PS];
     __shared__ __attribute__((aligned(16))) T wl[4 * TN * PS];
-    const TileJob jb = jobs[xcd_linear(blockIdx.x, gridDim.x)];
-    const LayerIO d = io[jb.sys];
-    if (d.stop && *d.stop) return;
-    const T* xs = (const T*)d.x0;
-    T* ys = (T*)d.y;
-    const int W = d.W;
-    const int co0 = jb.c0, t_beg = jb.ty0, t_end = jb.tx0;
     const int nseg = (W + 63) / 64;
     const int vpp = cin_p / VE;
     const int nxv = 64 * vpp, nwv = 4 * TN * vpp;
@@ -1289,6 +1281,44 @@ __global__ __launch_bounds__(WS_THREADS) void k_convT2_ws_jobs(const TileJob* __
             __syncthreads();
         }
     }
+}
+
+// Ragged batch: job = (system, first output channel, t_beg, t_end) in (sys, c0, ty0, tx0).
+template <class P, int TN, int K>
+__global__ __launch_bounds__(WS_THREADS) void k_convT2_ws_jobs(const TileJob* __restrict__ jobs,
+                                                               const LayerIO* __restrict__ io,
+                                                               const typename P::T* __restrict__ w,
+                                                               const typename P::Acc* __restrict__ bias, int cin_p,
+                                                               int cout_p) {
+    const TileJob jb = jobs[xcd_linear(blockIdx.x, gridDim.x)];
+    const LayerIO d = io[jb.sys];
+    if (d.stop && *d.stop) return;
+    convT2_ws_body<P, TN, K>((const typename P::T*)d.x0, (typename P::T*)d.y, w, bias, cin_p, cout_p, d.W, jb.c0,
+                             jb.ty0, jb.tx0);
+}
+
+// grid: x = segment groups (tpb segments each), y = channel blocks, z = samples; logical block
+// order: channel block fastest, then segment group, then sample.
+template <class P, int TN, int K>
+__global__ __launch_bounds__(WS_THREADS) void k_convT2_ws(const typename P::T* __restrict__ x, int cin_p,
+                                                          const typename P::T* __restrict__ w,
+                                                          const typename P::Acc* __restrict__ bias,
+                                                          typename P::T* __restrict__ y, int cout_p, int H, int W,
+                                                          int tpb, const int* __restrict__ skip) {
+    if (skip && *skip) return;   // uniform over the grid
+    const int ncb_tot = gridDim.y;
+    const int ngrp = gridDim.x;
+    const int nblk = gridDim.x * gridDim.y * gridDim.z;
+    int v = xcd_linear(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nblk);
+    const int cbi = v % ncb_tot;
+    v /= ncb_tot;
+    const int grp = v % ngrp;
+    const int bz = v / ngrp;
+    const int nt = H * ((W + 63) / 64);
+    const int t_beg = grp * tpb, t_end = min(nt, t_beg + tpb);
+    const int64_t plane = (int64_t)H * W;
+    convT2_ws_body<P, TN, K>(x + (int64_t)bz * plane * cin_p, y + (int64_t)bz * plane * 4 * cout_p, w, bias, cin_p,
+                             cout_p, W, cbi * TN, t_beg, t_end);
 }
 
 static int pick_tn(int cout_p) { return cout_p % 64 == 0 ? 64 : (cout_p % 32 == 0 ? 32 : 16); }
@@ -1543,6 +1573,23 @@ int launch_convT2(const typename P::T* x, int cin_p, const typename P::T* w, con
     if (cout_p % 16 || ck < VE || cin_p % ck || ck % VE) {
         set_error("convT2: unsupported channel combination");
         return HZ_ERR_ARG;
+    }
+    if constexpr (std::is_same<P, PolBF16>::value) {
+        // the weight-stationary form (16-channel blocks, 4-32 row segments per block) where the input
+        // channels fit one stage and it gives at least 256 blocks (the same result bits)
+        if (convT2_ws_ok<P>(cin_p, cout_p, 16)) {
+            const int nt = H * ((W + 63) / 64);
+            const int64_t ncb = cout_p / 16;
+            int tpb = 32;
+            while (tpb > 4 && (int64_t)((nt + tpb - 1) / tpb) * ncb * batch < 1024) tpb /= 2;
+            if ((int64_t)((nt + tpb - 1) / tpb) * ncb * batch >= 256) {
+                dim3 g((nt + tpb - 1) / tpb, (unsigned)ncb, batch);
+                hipLaunchKernelGGL((k_convT2_ws<P, 16, 2>), g, dim3(WS_THREADS), 0, s, x, cin_p, w, bias, y, cout_p, H,
+                                   W, tpb, skip);
+                HZ_LAUNCH_CHECK();
+                return HZ_OK;
+            }
+        }
     }
     const int tn = cout_p % 32 == 0 ? 32 : 16;
     dim3 grid((W + 63) / 64, H, (cout_p / tn) * batch);
