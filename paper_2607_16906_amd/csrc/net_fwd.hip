@@ -575,7 +575,7 @@ __global__ __launch_bounds__(CT) void k_conv3(const typename P::T* __restrict__ 
 constexpr int WS_THREADS = 2 * CT;
 // One block: output channels [co0, co0 + TN) of tiles [t_beg, t_end) of one sample (xs0, xs1, ys,
 // yps already point at the sample; tiles row-major over the image, TW wide and 4 RPW high).
-template <class P, int TN, bool POOL, int RPW, int WCH, int K, bool HEAD, bool SMALL = false>
+template <class P, int TN, bool POOL, int RPW, int WCH, int K, bool HEAD, bool SMALL = false, bool MASKED = false>
 __device__ __forceinline__ void conv3_ws_body(const typename P::T* __restrict__ xs0, int c0,
                                               const typename P::T* __restrict__ xs1, int c1,
                                               const typename P::T* __restrict__ w,
@@ -588,6 +588,11 @@ __device__ __forceinline__ void conv3_ws_body(const typename P::T* __restrict__ 
     using AccV = typename P::AccV;
     static_assert(!HEAD || !POOL, "the fused head has no pooled output");
     static_assert(!SMALL || WCH == 1, "an input of one k-group per tap is one chunk");
+    // MASKED: conv3_tile's split / masked epilogue (ex.split, ex.y1_, ex.mask0_, ex.mask1_, already
+    // at the sample) and an optional bias, for the data gradient of training (BF16: a lane's 4
+    // registers are 4 consecutive channels, whose mask entries are one 8-byte load)
+    static_assert(!MASKED || (!HEAD && !POOL && std::is_same<P, PolBF16>::value),
+                  "the masked epilogue: BF16, no head or pooled output");
     constexpr int TH_ = 4 * RPW;
     constexpr int PS = pix_stride<P>();
     constexpr int VE = 16 / sizeof(T);
@@ -689,6 +694,26 @@ __device__ __forceinline__ void conv3_ws_body(const typename P::T* __restrict__ 
     Acc bpre[NCB][4], hw0[NCB][4], hw1[NCB][4];
     Acc hb0 = Acc(0), hb1 = Acc(0);
     auto compute = [&](int t, int b) {
+        // (MASKED) the mask entries of this tile's outputs, loaded before the matrix-core work
+        uint2 mk[MASKED ? RPW : 1][MASKED ? NCB : 1];
+        if constexpr (MASKED) {
+            const int split = ex.split > 0 ? ex.split : cout_p;
+            const bool second = co0 >= split;
+            const int cst = second ? cout_p - split : split;
+            const T* ms = (const T*)(second ? ex.mask1_ : ex.mask0_);
+            const int cbase = second ? co0 - split : co0;
+            const int ty0m = (t / ntx) * TH_, gxm = (t % ntx) * TW + lr;
+#pragma unroll
+            for (int pb = 0; pb < RPW; ++pb)
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) {
+                    const int gy = ty0m + RPW * wv + pb;
+                    mk[pb][cb] = uint2{0x3f803f80u, 0x3f803f80u};   // 1.0 in every entry: kept
+                    if (ms && gy < H && gxm < W)
+                        mk[pb][cb] = *(const uint2*)(ms + ((int64_t)gy * W + gxm) * cst + cbase + cb * 16 +
+                                                     P::row_of(lg, 0));
+                }
+        }
         AccV acc[RPW][NCB];
 #pragma unroll
         for (int pb = 0; pb < RPW; ++pb)
@@ -738,6 +763,35 @@ __device__ __forceinline__ void conv3_ws_body(const typename P::T* __restrict__ 
                     const int64_t zi = (int64_t)gy * ex.head_nxt + gx;
                     if (ex.head_c128) ((double2*)ex.head_z)[zi] = zv;
                     else ((float2*)ex.head_z)[zi] = from_d2<float2>(zv);
+                }
+            }
+            return;
+        }
+        if constexpr (MASKED) {   // as conv3_tile's epilogue with an output split and masks
+            const int split = ex.split > 0 ? ex.split : cout_p;
+            const bool second = co0 >= split;
+            const int cst = second ? cout_p - split : split;   // channels per pixel of this output
+            T* yb = second ? (T*)ex.y1_ : ys;
+            const int cbase = second ? co0 - split : co0;
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const int cl = cbase + cb * 16;
+#pragma unroll
+                for (int pb = 0; pb < RPW; ++pb) {
+                    const int gy = ty0 + RPW * wv + pb;
+                    if (gy < H && gx < W) {
+                        const int64_t off = ((int64_t)gy * W + gx) * cst + cl;
+                        Acc q[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            q[r] = acc[pb][cb][r] + bpre[cb][r];
+                            if (relu) q[r] = q[r] > Acc(0) ? q[r] : Acc(0);
+                            const uint32_t mw = r < 2 ? mk[pb][cb].x : mk[pb][cb].y;
+                            const T m = (T)((mw >> (16 * (r & 1))) & 0xffffu);
+                            if (!(P::val(m) > Acc(0))) q[r] = Acc(0);
+                        }
+                        store_rows<P>(yb + off + P::row_of(lg, 0), q);
+                    }
                 }
             }
             return;
@@ -803,7 +857,8 @@ __device__ __forceinline__ void conv3_ws_body(const typename P::T* __restrict__ 
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int co = co0 + cb * 16 + P::row_of(lg, r);
-                bpre[cb][r] = bias[co];
+                if constexpr (MASKED) bpre[cb][r] = bias ? bias[co] : Acc(0);
+                else bpre[cb][r] = bias[co];
                 if constexpr (HEAD) {
                     hw0[cb][r] = P::val(((const T*)ex.head_w)[co]);
                     hw1[cb][r] = P::val(((const T*)ex.head_w)[cout_p + co]);
@@ -873,6 +928,40 @@ __global__ __launch_bounds__(WS_THREADS) void k_conv3_ws8(const typename P::T* _
     conv3_ws_body<P, TN, false, RPW, 1, K, false, true>(xs, c0, xs, 0, w, bias,
                                                         y + (int64_t)bz * plane * cout_p, cout_p, nullptr, H, W, relu,
                                                         cbi * TN, t_beg, t_end, skipped, Conv3Out());
+}
+
+// The data gradient of training in the weight-stationary form (one input x0 of c0 channels, no
+// bias or activation): output channels below split go to y0 (split per pixel), the others to y1;
+// an entry whose mask entry (mask0 / mask1, the same layouts) is <= 0 is zero.
+template <class P, int TN, int RPW, int WCH, int K>
+__global__ __launch_bounds__(WS_THREADS) void k_conv3_ws_dgrad(const typename P::T* __restrict__ x0, int c0,
+                                                               const typename P::T* __restrict__ w,
+                                                               typename P::T* __restrict__ y0, int cout_p, int H, int W,
+                                                               int tpb, int split, typename P::T* __restrict__ y1,
+                                                               const typename P::T* __restrict__ mask0,
+                                                               const typename P::T* __restrict__ mask1) {
+    const int ncb_tot = gridDim.y;
+    const int ngrp = gridDim.x;
+    const int nblk = gridDim.x * gridDim.y * gridDim.z;
+    int v = xcd_linear(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nblk);
+    const int cbi = v % ncb_tot;
+    v /= ncb_tot;
+    const int grp = v % ngrp;
+    const int bz = v / ngrp;
+    const int ntiles = ((W + TW - 1) / TW) * ((H + 4 * RPW - 1) / (4 * RPW));
+    const int t_beg = grp * tpb, t_end = min(ntiles, t_beg + tpb);
+    const int64_t plane = (int64_t)H * W;
+    const int s0 = split > 0 ? split : cout_p, s1 = cout_p - s0;
+    Conv3Out ex;
+    ex.split = split;
+    ex.y1_ = y1 ? y1 + (int64_t)bz * plane * s1 : nullptr;
+    ex.mask0_ = mask0 ? mask0 + (int64_t)bz * plane * s0 : nullptr;
+    ex.mask1_ = mask1 ? mask1 + (int64_t)bz * plane * s1 : nullptr;
+    const typename P::T* xs = x0 + (int64_t)bz * plane * c0;
+    // (no second input part; xs stands in for its pointer, which is never read)
+    conv3_ws_body<P, TN, false, RPW, WCH, K, false, false, true>(xs, c0, xs, 0, w, nullptr,
+                                                                 y0 + (int64_t)bz * plane * s0, cout_p, nullptr, H,
+                                                                 W, 0, cbi * TN, t_beg, t_end, 0, ex);
 }
 
 // Ragged batch, weight-stationary form: job = (system, first output channel, first tile, end
@@ -1724,6 +1813,34 @@ int launch_convT2_ws_jobs(const TileJob* jobs, int njobs, const LayerIO* io, con
 }
 
 template <class P>
+int launch_conv3_ws_dgrad(const typename P::T* x0, int c0, const typename P::T* w, typename P::T* y0, int cout_p,
+                          int H, int W, int batch, int split, typename P::T* y1, const typename P::T* mask0,
+                          const typename P::T* mask1, hipStream_t s) {
+    if constexpr (std::is_same<P, PolBF16>::value) {
+        if (!conv3_ws_dgrad_ok<P>(c0, cout_p, split)) {
+            set_error("conv3: the weight-stationary data gradient needs BF16, 1 or 2 input chunks and 32-channel parts");
+            return HZ_ERR_ARG;
+        }
+        const int ntiles = ((W + TW - 1) / TW) * ((H + 15) / 16);
+        const int ncb = cout_p / WSJ_TN;
+        int tpb = 32;
+        while (tpb > 4 && (int64_t)((ntiles + tpb - 1) / tpb) * ncb * batch < 1024) tpb /= 2;
+        dim3 grid((ntiles + tpb - 1) / tpb, ncb, batch);
+        if (c0 == P::CK)
+            hipLaunchKernelGGL((k_conv3_ws_dgrad<P, WSJ_TN, WSJ_RPW, 1, 2>), grid, dim3(WS_THREADS), 0, s, x0, c0, w, y0,
+                               cout_p, H, W, tpb, split, y1, mask0, mask1);
+        else
+            hipLaunchKernelGGL((k_conv3_ws_dgrad<P, WSJ_TN, WSJ_RPW, 2, 2>), grid, dim3(WS_THREADS), 0, s, x0, c0, w, y0,
+                               cout_p, H, W, tpb, split, y1, mask0, mask1);
+        HZ_LAUNCH_CHECK();
+        return HZ_OK;
+    } else {
+        set_error("conv3: the weight-stationary data gradient is BF16 only");
+        return HZ_ERR_ARG;
+    }
+}
+
+template <class P>
 int launch_convT2_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
                        const typename P::Acc* bias, int cin_p, int cout_p, int tn, hipStream_t s) {
     if (njobs <= 0) return HZ_OK;
@@ -1752,6 +1869,8 @@ int launch_convT2_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const 
                                            int, int, const P::T*, const P::Acc*, int, bool, hipStream_t);       \
     template int launch_conv3_ws_jobs<P>(const TileJob*, int, const LayerIO*, const P::T*, const P::Acc*, int, int, \
                                          int, bool, const P::T*, const P::Acc*, int, bool, hipStream_t);        \
+    template int launch_conv3_ws_dgrad<P>(const P::T*, int, const P::T*, P::T*, int, int, int, int, int, P::T*,   \
+                                          const P::T*, const P::T*, hipStream_t);                               \
     template int launch_convT2_jobs<P>(const TileJob*, int, const LayerIO*, const P::T*, const P::Acc*, int, int, \
                                        int, hipStream_t);                                                      \
     template int launch_convT2_ws_jobs<P>(const TileJob*, int, const LayerIO*, const P::T*, const P::Acc*, int,    \

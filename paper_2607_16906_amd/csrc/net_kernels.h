@@ -228,6 +228,18 @@ template <class P>
 constexpr bool ws_jobs_ok(int c0, int c1, int cout_p) {
     return conv3_ws_ok<P>(WSJ_TN, WSJ_RPW, c0, c1, cout_p) && c0 + c1 <= 2 * P::CK;
 }
+// The data gradient of training (split output, masks, no bias) in the weight-stationary form:
+// BF16, an input of 1 or 2 chunks, WSJ_TN-channel blocks that both output parts divide, 16 x 16
+// tiles; y0 / y1 / masks as Conv3Out's split and masks, samples along grid z.
+template <class P>
+constexpr bool conv3_ws_dgrad_ok(int c0, int cout_p, int split) {
+    return conv3_ws_ok<P>(WSJ_TN, WSJ_RPW, c0, 0, cout_p) && c0 <= 2 * P::CK && split % WSJ_TN == 0 &&
+           (cout_p - split) % WSJ_TN == 0;
+}
+template <class P>
+int launch_conv3_ws_dgrad(const typename P::T* x0, int c0, const typename P::T* w, typename P::T* y0, int cout_p,
+                          int H, int W, int batch, int split, typename P::T* y1, const typename P::T* mask0,
+                          const typename P::T* mask1, hipStream_t s);
 template <class P>
 int launch_conv3_ws_jobs(const TileJob* jobs, int njobs, const LayerIO* io, const typename P::T* w,
                          const typename P::Acc* bias, int c0, int c1, int cout_p, bool pool,

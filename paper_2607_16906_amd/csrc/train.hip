@@ -1056,7 +1056,11 @@ static int dgrad_conv3(const no_net* net, const Layer& ly, const typename P::T* 
     ex.y1_ = y1;
     ex.mask0_ = mask0;
     ex.mask1_ = mask1;
-    // output channels of the data gradient = stored input channels of the layer
+    // output channels of the data gradient = stored input channels of the layer; BF16 layers whose
+    // gradient has 1 or 2 chunks take the weight-stationary form (the same result bits)
+    if (conv3_ws_dgrad_ok<P>(ly.cout_p, ly.cin_p, ly.cat_cp))
+        return launch_conv3_ws_dgrad<P>(G, ly.cout_p, packed_wt<P>(net, ly), y0, ly.cin_p, H, W, B, ly.cat_cp, y1,
+                                        mask0, mask1, s);
     return launch_conv3<P>(G, ly.cout_p, nullptr, 0, packed_wt<P>(net, ly), nullptr, y0, ly.cin_p, nullptr, H, W, B,
                            false, nullptr, s, ex);
 }
