@@ -840,15 +840,32 @@ __global__ __launch_bounds__(TT) void k_convT2_dgrad(const typename P::T* __rest
     const int ix = ix0 + wv * 16 + lr;
     if (ix >= W) return;
     const int64_t pix = (int64_t)bz * plane + (int64_t)iy * W + ix;
+    if constexpr (std::is_same<P, PolBF16>::value) {
+        // a lane's 4 registers are 4 consecutive channels: one 8-byte mask load and one store
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
+        for (int cb = 0; cb < NCB; ++cb) {
+            const int64_t o = pix * cin_p + ci0 + cb * 16 + P::row_of(lg, 0);
+            const uint2 mk = *(const uint2*)(xmask + o);
+            typename P::Acc v[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int ci = ci0 + cb * 16 + P::row_of(lg, r);
-            typename P::Acc v = acc[cb][r];
-            if (!(P::val(xmask[pix * cin_p + ci]) > typename P::Acc(0))) v = 0;
-            gx[pix * cin_p + ci] = P::cvt(v);
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t mw = r < 2 ? mk.x : mk.y;
+                const T m = (T)((mw >> (16 * (r & 1))) & 0xffffu);
+                v[r] = P::val(m) > typename P::Acc(0) ? acc[cb][r] : typename P::Acc(0);
+            }
+            store_rows<P>(gx + o, v);
         }
+    } else {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int ci = ci0 + cb * 16 + P::row_of(lg, r);
+                typename P::Acc v = acc[cb][r];
+                if (!(P::val(xmask[pix * cin_p + ci]) > typename P::Acc(0))) v = 0;
+                gx[pix * cin_p + ci] = P::cvt(v);
+            }
+    }
 }
 
 // G(enc_{l-1}b) = (skip + unpool(dP) / 4) masked by E > 0, in place in skip. E, skip: [B][H][W][c];
