@@ -413,17 +413,22 @@ __global__ __launch_bounds__(TT) void k_wgrad3_mfma(const bf16_t* __restrict__ G
 #pragma unroll
             for (int k = 0; k < 16; ++k) accb += bf2f(gt[co * WG_GS + seg * 16 + k]);
         }
-        // 4 reduction steps of 32 pixels (tile rows 2s, 2s + 1)
+        // 4 reduction steps of 32 pixels (step s: tile rows 2s, 2s + 1), every tap's accumulator
+        // taking the steps in order. The input fragment of step s and row offset dy starts at patch
+        // row 2s + dy: per column offset dx, the 9 distinct fragments are read once for all steps.
+        bf16x8_t a[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int row = 2 * s + (kg >> 1), col = 8 * (kg & 1);
-            const bf16x8_t a = PolBF16::load(&gt[(cob * 16 + lr) * WG_GS + 32 * s + 8 * kg]);
+        for (int s = 0; s < 4; ++s) a[s] = PolBF16::load(&gt[(cob * 16 + lr) * WG_GS + 32 * s + 8 * kg]);
 #pragma unroll
-            for (int t = 0; t < 9; ++t) {
-                const int dy = t / 3, dx = t % 3;
-                const bf16x8_t bb = PolBF16::load(&xt[(dx * WG_CI + cib * 16 + lr) * WG_XS + (row + dy) * 16 + col]);
-                acc[t] = PolBF16::mma(a, bb, acc[t]);
-            }
+        for (int dx = 0; dx < 3; ++dx) {
+            bf16x8_t bq[9];
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+                bq[q] = PolBF16::load(&xt[(dx * WG_CI + cib * 16 + lr) * WG_XS + (q + (kg >> 1)) * 16 + 8 * (kg & 1)]);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy) acc[dy * 3 + dx] = PolBF16::mma(a[s], bq[2 * s + dy], acc[dy * 3 + dx]);
         }
     }
     // lane holds D[co = co0 + 16 cob + 4 kg + r][ci = ci0 + 16 cib + lr] of every tap
