@@ -483,41 +483,69 @@ __global__ __launch_bounds__(TT) void k_wgrad3_mfma_f32(const float* __restrict_
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[t][r] = 0.f;
     float accb = 0.f;
-    const int t_end = min(ntiles, (z + 1) * tpc);
-    for (int tile = z * tpc; tile < t_end; ++tile) {
+    const int t_beg = z * tpc, t_end = min(ntiles, (z + 1) * tpc);
+    // G tile (128 pixels x 32 channels) and input patch (10 x 18 pixels x 32 channels) as vectors
+    // of 4 channels: a thread's vectors of the next tile are loaded into registers while the
+    // matrix cores work on this one, then written transposed (one value per LDS row)
+    constexpr int NGV = (128 * 8 + TT - 1) / TT, NXV = (180 * 8 + TT - 1) / TT;
+    float4 rgv[NGV], rxv[NXV];
+    auto gload = [&](int tile) {
         const int b = tile / per_img, r = tile - b * per_img;
         const int ty0 = (r / tx_n) * 8, tx0 = (r % tx_n) * 16;
-        __syncthreads();
-        // G tile: 128 pixels x 32 channels, 8 vectors of 4 channels per pixel
-        for (int v = threadIdx.x; v < 128 * 8; v += TT) {
+#pragma unroll
+        for (int i = 0; i < NGV; ++i) {
+            const int v = threadIdx.x + i * TT;
             const int px = v >> 3, part4 = v & 7;
             const int gy = ty0 + (px >> 4), gx = tx0 + (px & 15);
             const int co = co0 + part4 * 4;
-            float4 val = float4{0.f, 0.f, 0.f, 0.f};
-            if (gy < H && gx < W && co < cout_p)
-                val = *(const float4*)(G + ((int64_t)b * plane + (int64_t)gy * W + gx) * cout_p + co);
-            gt[(part4 * 4 + 0) * WF_GS + px] = val.x;
-            gt[(part4 * 4 + 1) * WF_GS + px] = val.y;
-            gt[(part4 * 4 + 2) * WF_GS + px] = val.z;
-            gt[(part4 * 4 + 3) * WF_GS + px] = val.w;
+            rgv[i] = float4{0.f, 0.f, 0.f, 0.f};
+            if (v < 128 * 8 && gy < H && gx < W && co < cout_p)
+                rgv[i] = *(const float4*)(G + ((int64_t)b * plane + (int64_t)gy * W + gx) * cout_p + co);
         }
-        // input patch: 10 x 18 pixels x 32 channels
-        for (int v = threadIdx.x; v < 180 * 8; v += TT) {
+#pragma unroll
+        for (int i = 0; i < NXV; ++i) {
+            const int v = threadIdx.x + i * TT;
             const int px = v >> 3, part4 = v & 7;
             const int py = px / 18, pc = px - py * 18;
             const int gy = ty0 + py - 1, gx = tx0 + pc - 1;
             const int ci = ci0 + part4 * 4;
-            float4 val = float4{0.f, 0.f, 0.f, 0.f};
-            if (gy >= 0 && gy < H && gx >= 0 && gx < W && ci < cin_p) {
+            rxv[i] = float4{0.f, 0.f, 0.f, 0.f};
+            if (v < 180 * 8 && gy >= 0 && gy < H && gx >= 0 && gx < W && ci < cin_p) {
                 const int64_t pix = (int64_t)b * plane + (int64_t)gy * W + gx;
-                val = *(const float4*)(ci < c0 ? x0 + pix * c0 + ci : x1 + pix * c1 + (ci - c0));
+                rxv[i] = *(const float4*)(ci < c0 ? x0 + pix * c0 + ci : x1 + pix * c1 + (ci - c0));
             }
-            xt[(part4 * 4 + 0) * WF_XS + px] = val.x;
-            xt[(part4 * 4 + 1) * WF_XS + px] = val.y;
-            xt[(part4 * 4 + 2) * WF_XS + px] = val.z;
-            xt[(part4 * 4 + 3) * WF_XS + px] = val.w;
         }
+    };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int i = 0; i < NGV; ++i) {
+            const int v = threadIdx.x + i * TT;
+            if (v < 128 * 8) {
+                const int px = v >> 3, part4 = v & 7;
+                gt[(part4 * 4 + 0) * WF_GS + px] = rgv[i].x;
+                gt[(part4 * 4 + 1) * WF_GS + px] = rgv[i].y;
+                gt[(part4 * 4 + 2) * WF_GS + px] = rgv[i].z;
+                gt[(part4 * 4 + 3) * WF_GS + px] = rgv[i].w;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < NXV; ++i) {
+            const int v = threadIdx.x + i * TT;
+            if (v < 180 * 8) {
+                const int px = v >> 3, part4 = v & 7;
+                xt[(part4 * 4 + 0) * WF_XS + px] = rxv[i].x;
+                xt[(part4 * 4 + 1) * WF_XS + px] = rxv[i].y;
+                xt[(part4 * 4 + 2) * WF_XS + px] = rxv[i].z;
+                xt[(part4 * 4 + 3) * WF_XS + px] = rxv[i].w;
+            }
+        }
+    };
+    if (t_beg < t_end) gload(t_beg);
+    for (int tile = t_beg; tile < t_end; ++tile) {
+        __syncthreads();   // the previous tile's reads of the LDS are done
+        lstore();
         __syncthreads();
+        if (tile + 1 < t_end) gload(tile + 1);
         if (blockIdx.x == 0) {
             const int co = threadIdx.x >> 3, seg = threadIdx.x & 7;
 #pragma unroll
